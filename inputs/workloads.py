@@ -1,0 +1,159 @@
+"""Initial states of the workloads, built from the counter-based generator.
+
+Recipes (stated once here and repeated in the design notes):
+
+* Game of Life: W x H torus, cell index y*W + x, a cell starts alive iff its
+  uniform draw is below the density (0.25).
+* n-body: N bodies, radius sqrt(u1) and angle 2*pi*u2 (uniform in the unit
+  disk), mass uniform in [0.5, 1.5], velocity zero.
+* spring mesh: W x H jittered grid with spacing h = 1/W centred on the
+  origin, jitter uniform in +-0.3 h per coordinate; springs to the right
+  neighbour, to the neighbour below and along one random diagonal of every
+  grid cell; stiffness 10**U(2, 4); rest length = initial distance; node mass
+  1; initial velocity N(0, 0.01**2) per component.
+* batched meshes: node counts log-uniform in [1e3, 6.4e4], W = round(sqrt(n)),
+  H = ceil(n / W), each mesh built as above with its own seed.
+
+Everything is produced in float64 and rounded to float32 where the simulated
+state is float32; both the oracle and the GPU receive the rounded values.
+"""
+
+import math
+
+import numpy as np
+
+from .rng import GAMMA, MASK64, _mix_int, config_seed, normal, uniform
+
+MAX_DEGREE = 8
+
+
+def gol_init(W: int, H: int, seed: int | None = None, density: float = 0.25) -> np.ndarray:
+    """uint8 array of W*H initial cell states (1 = alive), index y*W + x."""
+    if seed is None:
+        seed = config_seed(1)
+    u = uniform(seed, 0, np.arange(W * H))
+    return (u < density).astype(np.uint8)
+
+
+def nbody_init(N: int, seed: int | None = None) -> dict:
+    """Positions uniform in the unit disk, masses in [0.5, 1.5], zero velocity (float32)."""
+    if seed is None:
+        seed = config_seed(2)
+    ids = np.arange(N)
+    r = np.sqrt(uniform(seed, 0, ids))
+    th = 2.0 * np.pi * uniform(seed, 1, ids)
+    m = 0.5 + uniform(seed, 2, ids)
+    f32 = np.float32
+    return {
+        "x": (r * np.cos(th)).astype(f32),
+        "y": (r * np.sin(th)).astype(f32),
+        "vx": np.zeros(N, f32),
+        "vy": np.zeros(N, f32),
+        "m": m.astype(f32),
+    }
+
+
+def spring_mesh(W: int, H: int, seed: int | None = None, jitter: float = 0.3,
+                v_sigma: float = 0.01, id_offset: int = 0, spring_offset: int = 0) -> dict:
+    """Jittered planar grid mesh with one random diagonal per cell.
+
+    Returned arrays (float32 state, int32 topology):
+      x, y, vx, vy, m          per node (node id = j*W + i + id_offset)
+      a, b, k, L0              per spring (spring id = position + spring_offset)
+      adj (N, 8), adj_is_b     per node: spring ids in ascending order, -1 = empty
+      slot_a, slot_b           per spring: its slot in the adjacency of a / b
+    Node and spring ids inside the arrays are local (0-based); the offsets are
+    returned for callers that concatenate several meshes.
+    """
+    if seed is None:
+        seed = config_seed(3)
+    N = W * H
+    ids = np.arange(N, dtype=np.int64)
+    i = ids % W
+    j = ids // W
+    h = 1.0 / W
+    jx = (2.0 * uniform(seed, 0, ids) - 1.0) * jitter
+    jy = (2.0 * uniform(seed, 1, ids) - 1.0) * jitter
+    x = ((i + 0.5 + jx) * h - 0.5 * W * h).astype(np.float32)
+    y = ((j + 0.5 + jy) * h - 0.5 * H * h).astype(np.float32)
+
+    has_r = i + 1 < W
+    has_d = j + 1 < H
+    has_g = has_r & has_d
+    coin = uniform(seed, 2, ids) < 0.5
+    a = np.stack([ids, ids, np.where(coin, ids, ids + 1)], axis=1)
+    b = np.stack([ids + 1, ids + W, np.where(coin, ids + W + 1, ids + W)], axis=1)
+    valid = np.stack([has_r, has_d, has_g], axis=1)
+    a = a[valid]
+    b = b[valid]
+    S = a.shape[0]
+    sid = np.arange(S, dtype=np.int64)
+
+    k = (10.0 ** (2.0 + 2.0 * uniform(seed, 3, sid))).astype(np.float32)
+    dx = x[b].astype(np.float64) - x[a].astype(np.float64)
+    dy = y[b].astype(np.float64) - y[a].astype(np.float64)
+    L0 = np.sqrt(dx * dx + dy * dy).astype(np.float32)
+
+    node = np.concatenate([a, b])
+    spr = np.concatenate([sid, sid])
+    isb = np.concatenate([np.zeros(S, np.uint8), np.ones(S, np.uint8)])
+    order = np.lexsort((spr, node))
+    node_s, spr_s, isb_s = node[order], spr[order], isb[order]
+    first = np.searchsorted(node_s, node_s, side="left")
+    rank = np.arange(node_s.shape[0]) - first
+    if N and rank.max(initial=0) >= MAX_DEGREE:
+        raise ValueError("node degree above 8")
+    adj = np.full((N, MAX_DEGREE), -1, dtype=np.int32)
+    adj_is_b = np.zeros((N, MAX_DEGREE), dtype=np.uint8)
+    adj[node_s, rank] = spr_s
+    adj_is_b[node_s, rank] = isb_s
+    slot_a = np.empty(S, np.int32)
+    slot_b = np.empty(S, np.int32)
+    sel = isb_s == 0
+    slot_a[spr_s[sel]] = rank[sel]
+    slot_b[spr_s[~sel]] = rank[~sel]
+
+    vx = (v_sigma * normal(seed, 4, ids)).astype(np.float32)
+    vy = (v_sigma * normal(seed, 5, ids)).astype(np.float32)
+    return {
+        "W": W, "H": H, "N": N, "S": S, "h": h,
+        "id_offset": id_offset, "spring_offset": spring_offset,
+        "x": x, "y": y, "vx": vx, "vy": vy, "m": np.ones(N, np.float32),
+        "a": a.astype(np.int32), "b": b.astype(np.int32), "k": k, "L0": L0,
+        "adj": adj, "adj_is_b": adj_is_b, "slot_a": slot_a, "slot_b": slot_b,
+    }
+
+
+def struct_seed(base: int, s: int) -> int:
+    return _mix_int((base + GAMMA * (s + 1)) & MASK64)
+
+
+def batched_sizes(n_struct: int = 256, seed: int | None = None,
+                  lo: float = 1e3, hi: float = 6.4e4) -> list:
+    """(W, H) of each structure: n log-uniform in [lo, hi], W = round(sqrt(n)), H = ceil(n/W)."""
+    if seed is None:
+        seed = config_seed(4)
+    u = uniform(seed, 0, np.arange(n_struct))
+    n = np.rint(np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))).astype(np.int64)
+    out = []
+    for nn in n:
+        W = int(round(math.sqrt(int(nn))))
+        H = int(math.ceil(int(nn) / W))
+        out.append((W, H))
+    return out
+
+
+def batched_meshes(n_struct: int = 256, seed: int | None = None,
+                   lo: float = 1e3, hi: float = 6.4e4) -> list:
+    """List of independent meshes with global id offsets (nodes and springs)."""
+    if seed is None:
+        seed = config_seed(4)
+    meshes = []
+    noff = 0
+    soff = 0
+    for s, (W, H) in enumerate(batched_sizes(n_struct, seed, lo, hi)):
+        m = spring_mesh(W, H, struct_seed(seed, s), id_offset=noff, spring_offset=soff)
+        meshes.append(m)
+        noff += m["N"]
+        soff += m["S"]
+    return meshes

@@ -1,0 +1,15 @@
+"""CPU oracle of SMMO execution.  TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports, links or runs it.
+"""
+
+from .oracle import (  # noqa: F401
+    build,
+    GolWorld,
+    nbody_steps,
+    nbody_force_at,
+    spring_steps,
+    spring_breaks,
+)

@@ -1,0 +1,180 @@
+"""ctypes wrapper of the C oracle (smmo_oracle.c).  TEST INFRASTRUCTURE ONLY.
+
+Each function names the thesis passage that its C counterpart follows; the
+C file carries the full statement of the semantics.
+"""
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "smmo_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build() -> str:
+    """Compile the oracle with gcc (always recompiles).  Returns the library path."""
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            lib = C.CDLL(_LIB)
+            P = C.c_void_p
+            LL = C.c_longlong
+            D = C.c_double
+            lib.orc_gol_create.restype = P
+            lib.orc_gol_create.argtypes = [C.c_int, C.c_int, P]
+            lib.orc_gol_step.restype = C.c_int
+            lib.orc_gol_step.argtypes = [P, C.c_int]
+            lib.orc_gol_read.restype = LL
+            lib.orc_gol_read.argtypes = [P, P, P, P]
+            lib.orc_gol_error.restype = C.c_int
+            lib.orc_gol_error.argtypes = [P]
+            lib.orc_gol_free.restype = None
+            lib.orc_gol_free.argtypes = [P]
+            lib.orc_nbody_steps.restype = C.c_int
+            lib.orc_nbody_steps.argtypes = [LL, P, P, P, P, P, P, P, D, D, D, C.c_int, P, P]
+            lib.orc_nbody_force_at.restype = C.c_int
+            lib.orc_nbody_force_at.argtypes = [LL, P, P, P, D, D, P, LL, P, P, P, P]
+            lib.orc_spring_steps.restype = LL
+            lib.orc_spring_steps.argtypes = [LL, P, P, P, P, P, P, P, LL, P, P, P, P, P, P,
+                                             P, P, P, D, C.c_float, C.c_int, P, P, P, P, P]
+            lib.orc_spring_breaks.restype = C.c_int
+            lib.orc_spring_breaks.argtypes = [D, D, D, D, D, C.c_float]
+            _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64).copy()
+
+
+class GolWorld:
+    """Game of Life in SMMO form on a W x H torus (thesis Ch.7 "gol", rule B3/S23)."""
+
+    def __init__(self, W: int, H: int, init):
+        self.lib = _load()
+        self.W, self.H = W, H
+        init = np.ascontiguousarray(init, dtype=np.uint8).reshape(-1)
+        assert init.size == W * H
+        self._init = init
+        self.h = self.lib.orc_gol_create(W, H, _p(init))
+        if not self.h:
+            raise ValueError("bad grid")
+
+    def step(self, n: int = 1):
+        err = self.lib.orc_gol_step(self.h, n)
+        if err:
+            raise RuntimeError("oracle gol error %d" % err)
+
+    def read(self):
+        """(state u8[W*H], count i32[W*H], sorted cell indices of Alive objects)."""
+        nc = self.W * self.H
+        st = np.empty(nc, np.uint8)
+        ct = np.empty(nc, np.int32)
+        al = np.empty(nc, np.int32)
+        n = self.lib.orc_gol_read(self.h, _p(st), _p(ct), _p(al))
+        if self.lib.orc_gol_error(self.h):
+            raise RuntimeError("oracle gol error %d" % self.lib.orc_gol_error(self.h))
+        return st, ct, al[:n].copy()
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.orc_gol_free(self.h)
+            self.h = None
+
+
+def nbody_steps(x, y, vx, vy, m, G, eps, dt, steps=1):
+    """Thesis Ch.7 "nbody": `steps` x {compute_force (device_do), update}, float64.
+
+    Returns dict of x, y, vx, vy, fx, fy and the force conditioning scales
+    sfx, sfy = sum_j |term_ij| of the last force evaluation.
+    """
+    lib = _load()
+    x, y, vx, vy, m = (_f64(a) for a in (x, y, vx, vy, m))
+    n = x.size
+    fx, fy, sfx, sfy = (np.zeros(n) for _ in range(4))
+    rc = lib.orc_nbody_steps(n, _p(x), _p(y), _p(vx), _p(vy), _p(fx), _p(fy), _p(m),
+                             float(G), float(eps), float(dt), int(steps), _p(sfx), _p(sfy))
+    if rc:
+        raise RuntimeError("oracle nbody error %d" % rc)
+    return dict(x=x, y=y, vx=vx, vy=vy, fx=fx, fy=fy, sfx=sfx, sfy=sfy)
+
+
+def nbody_force_at(x, y, m, G, eps, idx):
+    """compute_force of the bodies `idx` only: (fx, fy, sfx, sfy), float64."""
+    lib = _load()
+    x, y, m = (_f64(a) for a in (x, y, m))
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    k = idx.size
+    fx, fy, sfx, sfy = (np.zeros(k) for _ in range(4))
+    rc = lib.orc_nbody_force_at(x.size, _p(x), _p(y), _p(m), float(G), float(eps),
+                                _p(idx), k, _p(fx), _p(fy), _p(sfx), _p(sfy))
+    if rc:
+        raise RuntimeError("oracle nbody error %d" % rc)
+    return fx, fy, sfx, sfy
+
+
+def spring_steps(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1,
+                 alive=None, fx=None, fy=None):
+    """Thesis Ch.7 "structure" compute steps: `steps` x {Spring::compute_force,
+    Node::update} in float64 with the float32 break decision.
+
+    `mesh` holds x, y, vx, vy, m, adj, adj_is_b, a, b, k, L0, slot_a, slot_b
+    (ids local to the arrays).  Returns a new dict with the updated state, the
+    spring forces fx, fy, the alive flags, the number of springs broken and
+    the conditioning scales sf (per spring), svx, svy, sx, sy (per node).
+    """
+    lib = _load()
+    N = int(np.asarray(mesh["x"]).size)
+    S = int(np.asarray(mesh["a"]).size)
+    x, y, vx, vy, m = (_f64(mesh[k]) for k in ("x", "y", "vx", "vy", "m"))
+    adj = np.ascontiguousarray(mesh["adj"], dtype=np.int32).reshape(N, 8).copy()
+    adjb = np.ascontiguousarray(mesh["adj_is_b"], dtype=np.uint8).reshape(N, 8)
+    a = np.ascontiguousarray(mesh["a"], dtype=np.int32)
+    b = np.ascontiguousarray(mesh["b"], dtype=np.int32)
+    kk = _f64(mesh["k"])
+    L0 = _f64(mesh["L0"])
+    sa = np.ascontiguousarray(mesh["slot_a"], dtype=np.int32)
+    sb = np.ascontiguousarray(mesh["slot_b"], dtype=np.int32)
+    al = (np.ones(S, np.uint8) if alive is None else np.ascontiguousarray(alive, dtype=np.uint8).copy())
+    fxo = np.zeros(S) if fx is None else _f64(fx)
+    fyo = np.zeros(S) if fy is None else _f64(fy)
+    sf = np.zeros(S)
+    svx, svy, sx, sy = (np.zeros(N) for _ in range(4))
+    nb = lib.orc_spring_steps(N, _p(x), _p(y), _p(vx), _p(vy), _p(m), _p(adj), _p(adjb),
+                              S, _p(a), _p(b), _p(kk), _p(L0), _p(sa), _p(sb), _p(al),
+                              _p(fxo), _p(fyo), float(dt), float(thresh), int(steps),
+                              _p(sf), _p(svx), _p(svy), _p(sx), _p(sy))
+    if nb < 0:
+        raise RuntimeError("oracle spring error %d" % nb)
+    out = dict(mesh)
+    out.update(x=x, y=y, vx=vx, vy=vy, adj=adj, alive=al, fx=fxo, fy=fyo, nbroken=int(nb),
+               sf=sf, svx=svx, svy=svy, sx=sx, sy=sy)
+    return out
+
+
+def spring_breaks(xa, ya, xb, yb, L0, thresh=0.3) -> bool:
+    """The float32 break decision of one spring."""
+    return bool(_load().orc_spring_breaks(float(xa), float(ya), float(xb), float(yb),
+                                          float(L0), float(thresh)))

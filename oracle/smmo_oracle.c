@@ -1,0 +1,540 @@
+/*
+ * CPU oracle of SMMO execution.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded C; float64 arithmetic; array-of-structs object
+ * stores.  Only the test suite, the smoke check and the bench's CPU-baseline
+ * leg load this library.  It shares no code, header, table or helper with the
+ * HIP library, and it never calls it.
+ *
+ * Semantics followed (Springer, "Memory-Efficient Object-Oriented Programming
+ * on GPUs"):
+ *   - Single-Method Multiple-Objects, Ch.3 sec.3.2.1 "Definition and Runtime
+ *     Semantics": a parallel do-all runs a method once for every object of a
+ *     class that exists when the operation starts; objects created during it
+ *     are not visited; the order is unspecified; a method may delete only its
+ *     own object (as its last statement) or objects of other classes.
+ *   - DynaSOAr interface, Ch.5 sec.5.1.1: parallel_new constructs n objects,
+ *     passing the index 0..n-1 to the constructor; device_do is a sequential
+ *     loop over all objects of a class inside one method execution.
+ * A do-all here takes a snapshot of the live object ids and calls the method
+ * on each id in ascending order, one after the other.  Every method below
+ * reads only fields that the same do-all does not write (or its own
+ * object's), so this sequential loop is one valid schedule of the parallel
+ * operation.
+ *
+ * Parity pins (what checks this file against something other than itself)
+ * are in tests/test_oracle_*.py.  Block and slot placement is not modelled:
+ * the oracle keeps live sets only, and results are compared through key
+ * fields (cell index, node id, spring id).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Object store: one per class.  Objects have ids; destroyed ids are reused.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    size_t size;          /* bytes per object */
+    size_t n;             /* ids handed out so far (high-water mark) */
+    size_t cap;
+    unsigned char *data;
+    unsigned char *live;
+    size_t *freelist;
+    size_t nfree;
+    size_t nlive;
+} ostore;
+
+static int os_init(ostore *s, size_t size, size_t cap)
+{
+    memset(s, 0, sizeof *s);
+    s->size = size;
+    s->cap = cap ? cap : 16;
+    s->data = calloc(s->cap, size);
+    s->live = calloc(s->cap, 1);
+    s->freelist = malloc(s->cap * sizeof(size_t));
+    return (s->data && s->live && s->freelist) ? 0 : -1;
+}
+
+static void os_free(ostore *s)
+{
+    free(s->data);
+    free(s->live);
+    free(s->freelist);
+    memset(s, 0, sizeof *s);
+}
+
+static void *os_at(const ostore *s, size_t id) { return s->data + id * s->size; }
+
+/* new: reuse the most recently freed id, else the next unused one */
+static long long os_new(ostore *s)
+{
+    size_t id;
+    if (s->nfree) {
+        id = s->freelist[--s->nfree];
+    } else {
+        if (s->n == s->cap) {
+            size_t nc = s->cap * 2;
+            unsigned char *d = realloc(s->data, nc * s->size);
+            unsigned char *l = realloc(s->live, nc);
+            size_t *f = realloc(s->freelist, nc * sizeof(size_t));
+            if (!d || !l || !f) return -1;
+            s->data = d; s->live = l; s->freelist = f;
+            memset(s->live + s->cap, 0, nc - s->cap);
+            s->cap = nc;
+        }
+        id = s->n++;
+    }
+    memset(os_at(s, id), 0, s->size);
+    s->live[id] = 1;
+    s->nlive++;
+    return (long long)id;
+}
+
+/* destroy: deleting a dead object is a usage error; report it */
+static int os_destroy(ostore *s, size_t id)
+{
+    if (id >= s->n || !s->live[id]) return -1;
+    s->live[id] = 0;
+    s->freelist[s->nfree++] = id;
+    s->nlive--;
+    return 0;
+}
+
+/* the set of objects a do-all visits: those alive when it starts */
+static size_t os_snapshot(const ostore *s, size_t *ids)
+{
+    size_t k = 0;
+    for (size_t i = 0; i < s->n; i++)
+        if (s->live[i]) ids[k++] = i;
+    return k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Game of Life in SMMO form (thesis Ch.7 "gol"; rule B3/S23 as stated       */
+/* there: a live cell stays alive with two or three live neighbours, a dead  */
+/* cell becomes alive with exactly three).                                   */
+/*                                                                           */
+/* Classes: Cell {state u8, count i32, cell_id i32}, one per grid cell and   */
+/* never destroyed; Alive {cell_id i32}, one per live cell, created on birth */
+/* and destroyed on death (the thesis attaches an Alive agent to every live  */
+/* cell).  Grid: W x H torus, cell index y*W + x.                             */
+/* One generation = three do-alls:                                            */
+/*   Cell::count  - number of live cells among the 8 torus neighbours        */
+/*   Alive::death - if its cell's count is not 2 or 3: cell state = 0,        */
+/*                  delete this                                               */
+/*   Cell::birth  - if state == 0 and count == 3: state = 1, new Alive        */
+/* ------------------------------------------------------------------------ */
+typedef struct { uint8_t state; int32_t count; int32_t cell_id; } gol_cell;
+typedef struct { int32_t cell_id; } gol_alive;
+
+typedef struct {
+    int W, H;
+    ostore cell, alive;
+    size_t *cells;   /* cell index -> Cell object id (the thesis's Cell::cells array) */
+    size_t *snap;
+    int err;
+} gol_world;
+
+static void gol_cell_count(gol_world *w, gol_cell *c)
+{
+    int x = c->cell_id % w->W, y = c->cell_id / w->W, n = 0;
+    for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++) {
+            if (!dx && !dy) continue;
+            int nx = (x + dx + w->W) % w->W, ny = (y + dy + w->H) % w->H;
+            const gol_cell *o = os_at(&w->cell, w->cells[(size_t)ny * w->W + nx]);
+            n += o->state;
+        }
+    c->count = n;
+}
+
+static void gol_alive_death(gol_world *w, size_t self)
+{
+    gol_alive *a = os_at(&w->alive, self);
+    gol_cell *c = os_at(&w->cell, w->cells[a->cell_id]);
+    if (c->count != 2 && c->count != 3) {
+        c->state = 0;
+        if (os_destroy(&w->alive, self)) w->err = 1;   /* last statement: delete this */
+    }
+}
+
+static void gol_cell_birth(gol_world *w, gol_cell *c)
+{
+    if (c->state == 0 && c->count == 3) {
+        c->state = 1;
+        long long id = os_new(&w->alive);
+        if (id < 0) { w->err = 2; return; }
+        ((gol_alive *)os_at(&w->alive, (size_t)id))->cell_id = c->cell_id;
+    }
+}
+
+void *orc_gol_create(int W, int H, const uint8_t *init)
+{
+    if (W <= 0 || H <= 0) return NULL;
+    gol_world *w = calloc(1, sizeof *w);
+    size_t nc = (size_t)W * H;
+    w->W = W; w->H = H;
+    w->cells = malloc(nc * sizeof(size_t));
+    w->snap = malloc(nc * sizeof(size_t));
+    if (os_init(&w->cell, sizeof(gol_cell), nc) || os_init(&w->alive, sizeof(gol_alive), nc)) return NULL;
+    /* parallel_new<Cell>(W*H): constructor(index) */
+    for (size_t i = 0; i < nc; i++) {
+        long long id = os_new(&w->cell);
+        gol_cell *c = os_at(&w->cell, (size_t)id);
+        c->state = init[i] ? 1 : 0;
+        c->count = 0;
+        c->cell_id = (int32_t)i;
+        w->cells[i] = (size_t)id;
+    }
+    /* one Alive per initially live cell, in ascending cell index */
+    for (size_t i = 0; i < nc; i++)
+        if (init[i]) {
+            long long id = os_new(&w->alive);
+            ((gol_alive *)os_at(&w->alive, (size_t)id))->cell_id = (int32_t)i;
+        }
+    return w;
+}
+
+int orc_gol_step(void *wp, int steps)
+{
+    gol_world *w = wp;
+    for (int s = 0; s < steps; s++) {
+        size_t k = os_snapshot(&w->cell, w->snap);
+        for (size_t i = 0; i < k; i++) gol_cell_count(w, os_at(&w->cell, w->snap[i]));
+        k = os_snapshot(&w->alive, w->snap);
+        for (size_t i = 0; i < k; i++) gol_alive_death(w, w->snap[i]);
+        k = os_snapshot(&w->cell, w->snap);
+        for (size_t i = 0; i < k; i++) gol_cell_birth(w, os_at(&w->cell, w->snap[i]));
+    }
+    return w->err;
+}
+
+/* state and count per cell index; sorted cell indices of the live Alive objects */
+long long orc_gol_read(void *wp, uint8_t *state, int32_t *count, int32_t *alive_cells)
+{
+    gol_world *w = wp;
+    size_t nc = (size_t)w->W * w->H;
+    for (size_t i = 0; i < nc; i++) {
+        const gol_cell *c = os_at(&w->cell, w->cells[i]);
+        if (state) state[i] = c->state;
+        if (count) count[i] = c->count;
+    }
+    long long n = 0;
+    if (alive_cells) {
+        /* counting sort over cell indices gives the canonical (ascending) set */
+        unsigned char *mark = calloc(nc, 1);
+        for (size_t i = 0; i < w->alive.n; i++)
+            if (w->alive.live[i]) {
+                int32_t cid = ((gol_alive *)os_at(&w->alive, i))->cell_id;
+                if (mark[cid]) w->err = 3;   /* two Alive objects on one cell */
+                mark[cid] = 1;
+            }
+        for (size_t i = 0; i < nc; i++)
+            if (mark[i]) alive_cells[n++] = (int32_t)i;
+        free(mark);
+    } else {
+        n = (long long)w->alive.nlive;
+    }
+    return n;
+}
+
+int orc_gol_error(void *wp) { return ((gol_world *)wp)->err; }
+
+void orc_gol_free(void *wp)
+{
+    gol_world *w = wp;
+    if (!w) return;
+    os_free(&w->cell);
+    os_free(&w->alive);
+    free(w->cells);
+    free(w->snap);
+    free(w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* n-body (thesis Ch.7 "nbody"): class Body {x, y, vx, vy, fx, fy, m}.        */
+/*   Body::compute_force: f = 0, then a device_do over all bodies adds the   */
+/*     gravitational pull of every other body j:                             */
+/*       f += G m_i m_j (x_j - x_i) / (|x_j - x_i|^2 + eps^2)^(3/2)            */
+/*     (Newton's law F = G m1 m2 / r^2 along the connecting line; eps is a    */
+/*     Plummer softening length, eps = 0 gives the thesis's unsoftened law).  */
+/*   Body::update: v += f / m * dt, then x += v * dt with the new v (the      */
+/*     thesis's time step: velocity first, position from the new velocity).  */
+/* The thesis's wall bounce is not part of this method set.                  */
+/* ------------------------------------------------------------------------ */
+typedef struct { double x, y, vx, vy, fx, fy, m, sx, sy; } nb_body;
+
+/* device_do<Body>(&Body::apply_force) seen from body `self` */
+static void nb_force(const ostore *st, const size_t *all, size_t nall, size_t self,
+                     double G, double eps2)
+{
+    nb_body *b = os_at(st, self);
+    double fx = 0, fy = 0, sx = 0, sy = 0;
+    for (size_t t = 0; t < nall; t++) {
+        if (all[t] == self) continue;   /* the thesis skips other == this */
+        const nb_body *o = os_at(st, all[t]);
+        double dx = o->x - b->x, dy = o->y - b->y;
+        double r2 = dx * dx + dy * dy + eps2;
+        double c = G * b->m * o->m / (r2 * sqrt(r2));
+        fx += c * dx;
+        fy += c * dy;
+        sx += fabs(c * dx);
+        sy += fabs(c * dy);
+    }
+    b->fx = fx; b->fy = fy; b->sx = sx; b->sy = sy;
+}
+
+static void nb_update(nb_body *b, double dt)
+{
+    b->vx += b->fx / b->m * dt;
+    b->vy += b->fy / b->m * dt;
+    b->x += b->vx * dt;
+    b->y += b->vy * dt;
+}
+
+/*
+ * `steps` iterations of {compute_force, update} on n bodies, arrays updated in
+ * place.  sfx/sfy (may be NULL) receive sum_j |term_ij| per component of the
+ * last force evaluation: the conditioning scale used by the parity tolerance.
+ */
+int orc_nbody_steps(long long n, double *x, double *y, double *vx, double *vy,
+                    double *fx, double *fy, const double *m, double G, double eps,
+                    double dt, int steps, double *sfx, double *sfy)
+{
+    ostore st;
+    if (n < 0 || os_init(&st, sizeof(nb_body), (size_t)(n ? n : 1))) return -1;
+    size_t *snap = malloc((size_t)(n ? n : 1) * sizeof(size_t));
+    for (long long i = 0; i < n; i++) {   /* parallel_new<Body>(n) */
+        nb_body *b = os_at(&st, (size_t)os_new(&st));
+        b->x = x[i]; b->y = y[i]; b->vx = vx[i]; b->vy = vy[i]; b->m = m[i];
+    }
+    for (int s = 0; s < steps; s++) {
+        size_t k = os_snapshot(&st, snap);
+        for (size_t i = 0; i < k; i++) nb_force(&st, snap, k, snap[i], G, eps * eps);
+        k = os_snapshot(&st, snap);
+        for (size_t i = 0; i < k; i++) nb_update(os_at(&st, snap[i]), dt);
+    }
+    for (long long i = 0; i < n; i++) {   /* ids equal the construction index */
+        const nb_body *b = os_at(&st, (size_t)i);
+        x[i] = b->x; y[i] = b->y; vx[i] = b->vx; vy[i] = b->vy;
+        if (fx) fx[i] = b->fx;
+        if (fy) fy[i] = b->fy;
+        if (sfx) sfx[i] = b->sx;
+        if (sfy) sfy[i] = b->sy;
+    }
+    free(snap);
+    os_free(&st);
+    return 0;
+}
+
+/* compute_force for selected bodies only (the device_do of those bodies) */
+int orc_nbody_force_at(long long n, const double *x, const double *y, const double *m,
+                       double G, double eps, const long long *idx, long long nidx,
+                       double *fx, double *fy, double *sfx, double *sfy)
+{
+    ostore st;
+    if (n < 0 || os_init(&st, sizeof(nb_body), (size_t)(n ? n : 1))) return -1;
+    size_t *snap = malloc((size_t)(n ? n : 1) * sizeof(size_t));
+    for (long long i = 0; i < n; i++) {
+        nb_body *b = os_at(&st, (size_t)os_new(&st));
+        b->x = x[i]; b->y = y[i]; b->m = m[i];
+    }
+    size_t k = os_snapshot(&st, snap);
+    for (long long t = 0; t < nidx; t++) {
+        if (idx[t] < 0 || idx[t] >= n) { free(snap); os_free(&st); return -2; }
+        nb_force(&st, snap, k, (size_t)idx[t], G, eps * eps);
+        const nb_body *b = os_at(&st, (size_t)idx[t]);
+        fx[t] = b->fx; fy[t] = b->fy;
+        if (sfx) sfx[t] = b->sx;
+        if (sfy) sfy[t] = b->sy;
+    }
+    free(snap);
+    os_free(&st);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spring-mass mesh (thesis Ch.7 "structure", its compute steps):           */
+/*   Spring::compute_force - Hooke's law F = k * dx on the spring's two     */
+/*     endpoints; a spring stretched past its limit breaks: it unlinks      */
+/*     itself from both nodes and deletes itself.                            */
+/*   Node::update - sum the forces of the attached springs, then            */
+/*     accelerate and move as in nbody (v += F/m dt, x += v dt).             */
+/* Readings where the thesis leaves the details open (listed in the design   */
+/* notes): the spring pulls and pushes (two-sided Hooke's law on the length  */
+/* change l - L0), the force on endpoint a is k (l - L0) d / l with          */
+/* d = x_b - x_a and the force on b is its negative; a spring breaks when    */
+/* its strain (l - L0) / L0 exceeds a threshold, and it then exerts no force */
+/* in that step.  The break decision is integer-valued, so it is taken in    */
+/* float32, in the same operation order as the GPU kernel:                   */
+/*   dx = xb - xa; dy = yb - ya; l2 = fma(dx, dx, dy*dy); l = sqrt(l2);       */
+/*   strain = (l - L0) / L0;  break iff strain > threshold                   */
+/* with every operation rounded to float32.  Forces and the update are float64. */
+/* Nodes keep up to 8 spring slots; a break empties the two slots (the       */
+/* spring remembers its slot index in each node); Node::update sums the      */
+/* occupied slots in slot order.                                             */
+/* ------------------------------------------------------------------------ */
+#define SP_DEG 8
+
+typedef struct {
+    double x, y, vx, vy, m;
+    long long adj[SP_DEG];     /* spring object id, -1 = empty slot */
+    uint8_t adjb[SP_DEG];      /* 1 if this node is the spring's endpoint b */
+    double svx, svy, sx, sy;   /* conditioning scales of the last update */
+} sp_node;
+
+typedef struct {
+    long long a, b;            /* node object ids */
+    double k, L0, fx, fy, sf;
+    int32_t sa, sb;            /* slot of this spring in a.adj / b.adj */
+} sp_spring;
+
+typedef struct {
+    ostore node, spring;
+    size_t *snap;
+    float thresh;
+    double dt;
+    long long nbroken;
+    int err;
+} sp_world;
+
+/* the float32 break decision (see above) */
+static int sp_breaks(double xa, double ya, double xb, double yb, double L0, float thresh)
+{
+    float dx = (float)xb - (float)xa;
+    float dy = (float)yb - (float)ya;
+    float dy2 = dy * dy;
+    float l2 = fmaf(dx, dx, dy2);
+    float l = sqrtf(l2);
+    float L0f = (float)L0;
+    float strain = (l - L0f) / L0f;
+    return strain > thresh;
+}
+
+static void sp_spring_force(sp_world *w, size_t self)
+{
+    sp_spring *s = os_at(&w->spring, self);
+    sp_node *a = os_at(&w->node, (size_t)s->a);
+    sp_node *b = os_at(&w->node, (size_t)s->b);
+    if (sp_breaks(a->x, a->y, b->x, b->y, s->L0, w->thresh)) {
+        if (a->adj[s->sa] != (long long)self || b->adj[s->sb] != (long long)self) w->err = 4;
+        a->adj[s->sa] = -1;
+        b->adj[s->sb] = -1;
+        s->fx = s->fy = s->sf = 0;
+        w->nbroken++;
+        if (os_destroy(&w->spring, self)) w->err = 5;   /* last statement: delete this */
+        return;
+    }
+    double dx = b->x - a->x, dy = b->y - a->y;
+    double l = sqrt(dx * dx + dy * dy);
+    double c = s->k * (l - s->L0) / l;
+    s->fx = c * dx;
+    s->fy = c * dy;
+    s->sf = s->k * (l + s->L0);    /* scale of the float32 rounding error of f */
+}
+
+static void sp_node_update(sp_world *w, sp_node *n)
+{
+    double Fx = 0, Fy = 0, SF = 0;
+    for (int q = 0; q < SP_DEG; q++) {
+        if (n->adj[q] < 0) continue;
+        const sp_spring *s = os_at(&w->spring, (size_t)n->adj[q]);
+        double sg = n->adjb[q] ? -1.0 : 1.0;
+        Fx += sg * s->fx;
+        Fy += sg * s->fy;
+        SF += s->sf;
+    }
+    n->svx = fabs(n->vx) + w->dt * SF / n->m;
+    n->svy = fabs(n->vy) + w->dt * SF / n->m;
+    n->sx = fabs(n->x) + w->dt * n->svx;
+    n->sy = fabs(n->y) + w->dt * n->svy;
+    n->vx += Fx / n->m * w->dt;
+    n->vy += Fy / n->m * w->dt;
+    n->x += n->vx * w->dt;
+    n->y += n->vy * w->dt;
+}
+
+/*
+ * `steps` iterations of {Spring::compute_force, Node::update} on a mesh given
+ * by arrays indexed by node id (N) and spring id (S); updated in place.
+ *   adj:   N*8 spring ids (-1 empty), adjb: N*8 endpoint-b flags
+ *   alive: S flags (0 = spring already broken; such ids must not be in adj)
+ * Optional outputs (NULL to skip), all of the last step:
+ *   sf (S)               scale of each spring force
+ *   svx, svy, sx, sy (N) scales of the node velocity and position updates
+ * Returns the number of springs broken, or a negative error code.
+ */
+long long orc_spring_steps(long long N, double *x, double *y, double *vx, double *vy,
+                           const double *m, int32_t *adj, const uint8_t *adjb,
+                           long long S, const int32_t *a, const int32_t *b,
+                           const double *k, const double *L0,
+                           const int32_t *slot_a, const int32_t *slot_b,
+                           uint8_t *alive, double *fx, double *fy,
+                           double dt, float thresh, int steps,
+                           double *sf, double *svx, double *svy, double *sx, double *sy)
+{
+    sp_world w;
+    memset(&w, 0, sizeof w);
+    w.dt = dt;
+    w.thresh = thresh;
+    if (N < 0 || S < 0) return -1;
+    if (os_init(&w.node, sizeof(sp_node), (size_t)(N ? N : 1)) ||
+        os_init(&w.spring, sizeof(sp_spring), (size_t)(S ? S : 1))) return -1;
+    size_t big = (size_t)(N > S ? N : S);
+    w.snap = malloc((big ? big : 1) * sizeof(size_t));
+    for (long long i = 0; i < N; i++) {      /* parallel_new<Node>(N) */
+        sp_node *n = os_at(&w.node, (size_t)os_new(&w.node));
+        n->x = x[i]; n->y = y[i]; n->vx = vx[i]; n->vy = vy[i]; n->m = m[i];
+        for (int q = 0; q < SP_DEG; q++) {
+            n->adj[q] = adj[i * SP_DEG + q];
+            n->adjb[q] = adjb[i * SP_DEG + q];
+        }
+    }
+    for (long long i = 0; i < S; i++) {      /* parallel_new<Spring>(S) */
+        sp_spring *s = os_at(&w.spring, (size_t)os_new(&w.spring));
+        s->a = a[i]; s->b = b[i]; s->k = k[i]; s->L0 = L0[i];
+        s->sa = slot_a[i]; s->sb = slot_b[i];
+        s->fx = fx ? fx[i] : 0; s->fy = fy ? fy[i] : 0;
+    }
+    for (long long i = 0; i < S; i++)        /* springs broken before this call */
+        if (!alive[i]) os_destroy(&w.spring, (size_t)i);
+    for (long long i = 0; i < N; i++)
+        for (int q = 0; q < SP_DEG; q++) {
+            long long sid = adj[i * SP_DEG + q];
+            if (sid >= S || (sid >= 0 && !alive[sid])) w.err = 6;
+        }
+    for (int st = 0; st < steps && !w.err; st++) {
+        size_t kk = os_snapshot(&w.spring, w.snap);
+        for (size_t i = 0; i < kk; i++) sp_spring_force(&w, w.snap[i]);
+        kk = os_snapshot(&w.node, w.snap);
+        for (size_t i = 0; i < kk; i++) sp_node_update(&w, os_at(&w.node, w.snap[i]));
+    }
+    for (long long i = 0; i < N; i++) {
+        const sp_node *n = os_at(&w.node, (size_t)i);
+        x[i] = n->x; y[i] = n->y; vx[i] = n->vx; vy[i] = n->vy;
+        for (int q = 0; q < SP_DEG; q++) adj[i * SP_DEG + q] = (int32_t)n->adj[q];
+        if (svx) svx[i] = n->svx;
+        if (svy) svy[i] = n->svy;
+        if (sx) sx[i] = n->sx;
+        if (sy) sy[i] = n->sy;
+    }
+    for (long long i = 0; i < S; i++) {
+        const sp_spring *s = os_at(&w.spring, (size_t)i);
+        alive[i] = w.spring.live[i];
+        if (fx) fx[i] = s->fx;
+        if (fy) fy[i] = s->fy;
+        if (sf) sf[i] = s->sf;
+    }
+    free(w.snap);
+    os_free(&w.node);
+    os_free(&w.spring);
+    return w.err ? -(long long)w.err - 10 : w.nbroken;
+}
+
+/* the float32 break decision alone, for tests of its edge cases */
+int orc_spring_breaks(double xa, double ya, double xb, double yb, double L0, float thresh)
+{
+    return sp_breaks(xa, ya, xb, yb, L0, thresh);
+}

@@ -1,0 +1,160 @@
+"""Pins of the spring-mass oracle (thesis Ch.7 "structure", its compute steps:
+Hooke's law F = k dx per spring, then the nbody-style node update; springs
+break past a strain limit).
+
+Pinned by: a hand-computed single step; the exact solution of symplectic
+Euler on a harmonic oscillator (two nodes, one spring); the exactly
+conserved modified energy of symplectic Euler on a linear (collinear) chain;
+momentum conservation and bounded energy on a 2-D mesh; the break rule; and
+batched runs equal to separate runs.
+"""
+
+import math
+
+import numpy as np
+
+from inputs import spring_mesh
+from oracle import spring_breaks, spring_steps
+
+
+def line_mesh(xs, ks, L0s, vs=None):
+    """Nodes on the x axis joined in order by springs (node i -> spring i-1, i)."""
+    n = len(xs)
+    S = n - 1
+    adj = -np.ones((n, 8), np.int32)
+    adjb = np.zeros((n, 8), np.uint8)
+    slot_a = np.zeros(S, np.int32)
+    slot_b = np.zeros(S, np.int32)
+    fill = [0] * n
+    for s in range(S):
+        for node, isb in ((s, 0), (s + 1, 1)):
+            q = fill[node]
+            adj[node, q] = s
+            adjb[node, q] = isb
+            (slot_b if isb else slot_a)[s] = q
+            fill[node] += 1
+    return dict(x=np.array(xs, float), y=np.zeros(n), vx=np.zeros(n) if vs is None else np.array(vs, float),
+                vy=np.zeros(n), m=np.ones(n), adj=adj, adj_is_b=adjb,
+                a=np.arange(S, dtype=np.int32), b=np.arange(1, n, dtype=np.int32),
+                k=np.array(ks, float), L0=np.array(L0s, float), slot_a=slot_a, slot_b=slot_b)
+
+
+def test_hand_computed_step():
+    # nodes at 0 and 1.5, k = 2, L0 = 1: force on a = 2 * 0.5 = 1 towards b
+    r = spring_steps(line_mesh([0.0, 1.5], [2.0], [1.0]), dt=0.5, thresh=1.0)
+    assert r["fx"].tolist() == [1.0] and r["fy"].tolist() == [0.0]
+    assert r["vx"].tolist() == [0.5, -0.5]
+    assert r["x"].tolist() == [0.25, 1.25]
+
+
+def test_two_node_oscillator_matches_discrete_closed_form():
+    # separation s = L0 + 2u; each node: u'' = -(2k/m) u.  Symplectic Euler on
+    # u'' = -w^2 u has the exact solution u_n = A cos(n th) + B sin(n th) with
+    # cos th = 1 - w^2 dt^2 / 2.
+    k, L0, u0, dt, n = 50.0, 1.0, 0.05, 1e-3, 3000
+    w2 = 2 * k
+    r = spring_steps(line_mesh([-(L0 / 2 + u0), L0 / 2 + u0], [k], [L0]), dt=dt, thresh=1.0, steps=n)
+    # map: v' = v - w2 dt u, u' = u + dt v'.  With u_0 = u0, v_0 = 0:
+    th = math.acos(1 - w2 * dt * dt / 2)
+    u1 = u0 + dt * (0 - w2 * dt * u0)
+    A = u0
+    B = (u1 - A * math.cos(th)) / math.sin(th)
+    u_n = A * math.cos(n * th) + B * math.sin(n * th)
+    assert abs((r["x"][1] - L0 / 2) - u_n) < 1e-12
+    assert abs((-r["x"][0] - L0 / 2) - u_n) < 1e-12
+
+
+def test_linear_chain_conserves_modified_energy():
+    # collinear chain, no breaking: forces are linear in the displacements, and
+    # symplectic Euler conserves H = 1/2 v.v + 1/2 u.K u - dt/2 v.K u exactly.
+    rng = np.random.default_rng(7)
+    n = 12
+    L0 = 1.0 + 0.2 * rng.random(n - 1)
+    ks = 10 + 90 * rng.random(n - 1)
+    rest = np.concatenate([[0.0], np.cumsum(L0)])
+    u = 0.02 * rng.standard_normal(n)
+    v = 0.1 * rng.standard_normal(n)
+    K = np.zeros((n, n))
+    for s in range(n - 1):
+        K[s, s] += ks[s]; K[s + 1, s + 1] += ks[s]
+        K[s, s + 1] -= ks[s]; K[s + 1, s] -= ks[s]
+    dt = 2e-3
+
+    def H(u, v):
+        return 0.5 * v @ v + 0.5 * u @ K @ u - 0.5 * dt * v @ K @ u
+
+    H0 = H(u, v)
+    mesh = line_mesh(rest + u, ks, L0, v)
+    r = spring_steps(mesh, dt=dt, thresh=1.0, steps=5000)
+    H1 = H(r["x"] - rest, r["vx"])
+    assert abs(H1 - H0) <= 1e-12 * abs(H0)
+    assert r["nbroken"] == 0
+
+
+def _energy(r):
+    alive = r["alive"].astype(bool)
+    a, b = r["a"][alive], r["b"][alive]
+    l = np.hypot(r["x"][b] - r["x"][a], r["y"][b] - r["y"][a])
+    pe = 0.5 * np.sum(r["k"][alive] * (l - r["L0"][alive]) ** 2)
+    ke = 0.5 * np.sum(r["m"] * (r["vx"] ** 2 + r["vy"] ** 2))
+    return ke + pe
+
+
+def test_mesh_momentum_conserved_and_energy_bounded():
+    mesh = spring_mesh(12, 10, seed=11)
+    mesh = {k: (v.astype(np.float64) if isinstance(v, np.ndarray) and v.dtype == np.float32 else v)
+            for k, v in mesh.items()}
+    p0 = np.array([mesh["vx"].sum(), mesh["vy"].sum()])
+    E0 = _energy(dict(mesh, alive=np.ones(mesh["S"], np.uint8)))
+    state = mesh
+    es = []
+    for _ in range(20):
+        state = spring_steps(state, dt=1e-5, thresh=1e30, steps=500,
+                             alive=state.get("alive"), fx=state.get("fx"), fy=state.get("fy"))
+        es.append(_energy(state))
+    p1 = np.array([state["vx"].sum(), state["vy"].sum()])
+    assert np.all(np.abs(p1 - p0) <= 1e-12 * np.sum(np.abs(state["vx"]) + np.abs(state["vy"])))
+    assert max(abs(e - E0) for e in es) <= 1e-3 * E0
+    assert state["nbroken"] == 0
+
+
+def test_initial_strain_is_zero():
+    m = spring_mesh(30, 20, seed=5)
+    l = np.hypot(m["x"][m["b"]].astype(float) - m["x"][m["a"]], m["y"][m["b"]].astype(float) - m["y"][m["a"]])
+    assert np.max(np.abs(l - m["L0"]) / m["L0"]) < 1e-6
+    r = spring_steps(m, dt=1e-5, steps=1)
+    assert r["nbroken"] == 0
+
+
+def test_break_rule():
+    # strain 0.31 breaks (both slots emptied, no force), 0.29 does not
+    m = line_mesh([0.0, 1.31, 2.60], [5.0, 5.0], [1.0, 1.0])
+    r = spring_steps(m, dt=1e-3, thresh=0.3)
+    assert r["alive"].tolist() == [0, 1]
+    assert r["adj"][0].tolist() == [-1] * 8
+    assert r["adj"][1].tolist() == [-1, 1] + [-1] * 6
+    assert r["nbroken"] == 1
+    # node 0 felt nothing; node 2 was pulled towards node 1 by 5 * 0.29
+    assert r["vx"][0] == 0.0
+    assert abs(r["vx"][2] - (-5 * 0.29 * 1e-3)) < 1e-12
+    assert spring_breaks(0, 0, 1.31, 0, 1.0) and not spring_breaks(0, 0, 1.29, 0, 1.0)
+    assert spring_breaks(0, 0, 0, 1.31, 1.0) and not spring_breaks(0, 0, 0, 0.5, 1.0)
+
+
+def test_batched_equals_separate():
+    m1 = spring_mesh(9, 7, seed=1)
+    m2 = spring_mesh(6, 11, seed=2)
+    cat = {}
+    for key in ("x", "y", "vx", "vy", "m", "k", "L0", "slot_a", "slot_b", "adj_is_b"):
+        cat[key] = np.concatenate([m1[key], m2[key]])
+    cat["a"] = np.concatenate([m1["a"], m2["a"] + m1["N"]])
+    cat["b"] = np.concatenate([m1["b"], m2["b"] + m1["N"]])
+    adj2 = np.where(m2["adj"] >= 0, m2["adj"] + m1["S"], -1)
+    cat["adj"] = np.concatenate([m1["adj"], adj2])
+    r = spring_steps(cat, dt=1e-4, thresh=0.05, steps=300)
+    r1 = spring_steps(m1, dt=1e-4, thresh=0.05, steps=300)
+    r2 = spring_steps(m2, dt=1e-4, thresh=0.05, steps=300)
+    for key in ("x", "y", "vx", "vy"):
+        assert np.array_equal(r[key], np.concatenate([r1[key], r2[key]]))
+    assert np.array_equal(r["alive"], np.concatenate([r1["alive"], r2["alive"]]))
+    assert r["nbroken"] == r1["nbroken"] + r2["nbroken"]
