@@ -1,0 +1,257 @@
+/*
+ * smmo.h - C ABI of libsmmo, Single-Method Multiple-Objects execution on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Programming model (Springer, "Memory-Efficient Object-Oriented Programming
+ * on GPUs", Ch.3 sec.3.2.1 "Definition and Runtime Semantics" and Ch.5
+ * sec.5.1.1 "Programming Interface"): objects of user-defined classes live on
+ * a device heap; parallel_do runs one method on every object of a class that
+ * exists when the operation starts; methods may create objects of any class
+ * (the new objects are not visited by the running operation) and may delete
+ * their own object as their last action, or objects of other classes.
+ *
+ * Storage (Ch.5 sec.5.2 "Architecture Overview"): the heap is divided into M
+ * blocks of equal size.  A block holds up to 64 objects of one class in
+ * structure-of-arrays layout: one contiguous 64-entry array per field (per
+ * inner-array element), so the 64 lanes of a wavefront touch one contiguous
+ * run of memory per field.  Every class gets capacity 64 (the thesis gives
+ * capacity 64 to the smallest class, sec.5.2.2 "Block Capacity"; a wavefront
+ * is 64 lanes wide on CDNA).  Block states and free space are indexed by
+ * hierarchical bitmaps (sec.5.3.1).
+ *
+ * Conventions for every call:
+ *   - The return value is an smmo_status: SMMO_OK or a negative error code.
+ *     smmo_last_error() gives a text description of the last error raised on
+ *     the calling host thread.
+ *   - Argument errors are detected on the host before anything is enqueued;
+ *     nothing is enqueued when a call fails.
+ *   - Device-side errors (heap exhausted during an allocation, a handle that
+ *     does not name a live object of the class, a retry loop that exceeded
+ *     its bound) set an error word on the device.  Every later kernel on the
+ *     heap sees the word and does nothing; the next smmo_sync() or
+ *     smmo_heap_stats() returns it (SMMO_ENOMEM or SMMO_EDEVICE).
+ *   - "stream" is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work and return without waiting, except smmo_sync(), smmo_heap_stats(),
+ *     smmo_check_invariants() and smmo_heap_free(), which wait.  All calls on
+ *     one heap must be ordered on the host and on the device (one stream, or
+ *     streams joined by events); two calls on one heap that run at the same
+ *     time on the device race.
+ *   - Device pointers are addresses in device memory of the GPU the heap is
+ *     on.  The caller owns every buffer it passes and keeps it alive until the
+ *     work that uses it has completed.  libsmmo allocates no device memory:
+ *     the heap and all of its internal arrays are carved out of the buffer
+ *     given to smmo_alloc_heap().
+ *   - Handles are 32-bit: (block index << 6) | slot.  SMMO_NULL names no
+ *     object.  Handles of live objects are < 2^31, so the top bit is free for
+ *     the caller to use as a flag in handle-valued fields.
+ */
+#ifndef SMMO_H
+#define SMMO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t smmo_status;
+#define SMMO_OK 0
+#define SMMO_EINVAL (-1)        /* bad argument                                */
+#define SMMO_ENOMEM (-2)        /* heap exhausted / buffer too small           */
+#define SMMO_ESTATE (-3)        /* call not allowed in the current state       */
+#define SMMO_EHIP (-4)          /* a HIP runtime call failed                   */
+#define SMMO_EDEVICE (-5)       /* device-side error (see smmo_sync)           */
+#define SMMO_EUNSUPPORTED (-6)  /* feature or method not available             */
+
+typedef uint32_t smmo_handle;
+#define SMMO_NULL 0xFFFFFFFFu
+
+typedef void *smmo_stream;      /* a hipStream_t */
+
+/* field element types */
+#define SMMO_U8 1
+#define SMMO_I32 2
+#define SMMO_U32 3
+#define SMMO_F32 4
+#define SMMO_HANDLE 5           /* uint32 handle (or handle with flag bit 31) */
+
+#define SMMO_MAX_CLASSES 16
+#define SMMO_MAX_FIELDS 32      /* per class, counting every inner-array element */
+#define SMMO_BLOCK_CAPACITY 64
+
+typedef struct smmo_schema smmo_schema;
+typedef struct smmo_heap smmo_heap;
+
+/* One field of a class.  count > 1 declares an inner array of `count`
+ * elements stored as `count` separate 64-entry SOA arrays ("SOA with full
+ * inlining" of inner arrays, Ch.4 sec.4.3.1), so that element q of 64
+ * objects is one contiguous run. */
+typedef struct {
+    const char *name;           /* unique within the class, <= 31 chars */
+    int32_t dtype;              /* SMMO_U8 .. SMMO_HANDLE */
+    uint32_t count;             /* inner-array length, >= 1 */
+} smmo_field_desc;
+
+/* Heap configuration (smmo_config_default() fills the defaults). */
+typedef struct {
+    uint32_t lookup_retries;    /* active-block lookups before the slow path
+                                   (Ch.5 sec.5.3.2 "Lookup Retry"); default 5 */
+    uint32_t rotation;          /* 1: rotate bitmap containers before
+                                   find-first-set ("Bitmap Rotation"); default 1 */
+    uint32_t coalescing;        /* 1: one leader lane allocates for all lanes of a
+                                   wavefront ("Allocation Request Coalescing");
+                                   0: every lane allocates on its own; default 1 */
+    uint32_t bulk_ordered;      /* 1: smmo_parallel_new claims free blocks in
+                                   ascending order and fills them densely;
+                                   0: every object goes through the device
+                                   allocator; default 1 */
+    uint32_t spin_limit;        /* bound on every retry loop; exceeding it sets
+                                   SMMO_EDEVICE instead of hanging; default 1<<22 */
+    uint32_t grid_waves;        /* wavefronts per method launch (0 = automatic) */
+    uint32_t reserved[10];
+} smmo_config;
+
+typedef struct {
+    uint64_t live_objects[SMMO_MAX_CLASSES];
+    uint64_t blocks[SMMO_MAX_CLASSES];       /* allocated blocks per class */
+    uint64_t free_blocks;
+    uint64_t total_blocks;                   /* M */
+    double fragmentation;                    /* unused slots / slots of allocated
+                                                blocks (Ch.5 sec.5.6.3, "F") */
+    int32_t device_error;                    /* SMMO_OK, SMMO_ENOMEM or SMMO_EDEVICE */
+    uint32_t block_bytes;
+    uint64_t slow_paths;                     /* blocks initialized by device new */
+    uint64_t alloc_retries;                  /* failed reservations, all retried */
+} smmo_stats;
+
+typedef struct {
+    uint64_t hierarchy_violations;   /* summary bit != OR of its container  */
+    uint64_t state_violations;       /* block not exactly one of free / allocated[type] */
+    uint64_t active_violations;      /* active[C] set <=> allocated[C] and not full */
+    uint64_t type_violations;        /* allocated[C] set but block type != C */
+    uint64_t empty_allocated;        /* allocated blocks with no object */
+} smmo_invariants;
+
+/* A field initializer for smmo_parallel_new: `values` is a device pointer to
+ * n * count elements of the field's type, object i's elements at
+ * [i*count, (i+1)*count).  Fields without an initializer are zero-filled. */
+typedef struct {
+    uint32_t field_id;
+    const void *values;
+} smmo_field_init;
+
+/* ---- configuration and schema ------------------------------------------ */
+
+void smmo_config_default(smmo_config *cfg);
+
+/* Creates an empty schema.  *out receives it; free with smmo_schema_free(). */
+smmo_status smmo_schema_create(smmo_schema **out);
+smmo_status smmo_schema_free(smmo_schema *s);
+
+/* Declares a class (the thesis declares classes and field types at compile
+ * time, Ch.5 sec.5.1.1 "Data Layout DSL"; here at run time).  Fields are laid
+ * out in the given order.  *class_id receives 0, 1, ... in definition order.
+ * Fails with SMMO_ESTATE once a heap was created from the schema, SMMO_EINVAL
+ * for duplicate or empty names, bad types, count 0, or more than
+ * SMMO_MAX_FIELDS arrays, SMMO_ENOMEM for more than SMMO_MAX_CLASSES classes. */
+smmo_status smmo_define_class(smmo_schema *s, const char *name,
+                              const smmo_field_desc *fields, uint32_t nfields,
+                              uint32_t *class_id);
+
+/* Looks up a field of a class by name; *field_id is its index in the
+ * class's field list. */
+smmo_status smmo_field_id(const smmo_schema *s, uint32_t class_id, const char *name,
+                          uint32_t *field_id);
+
+/* Bytes of one block (the largest class's 64-object data segment), and the
+ * device buffer size smmo_alloc_heap() needs for a heap of `blocks` blocks. */
+smmo_status smmo_block_bytes(const smmo_schema *s, uint32_t *block_bytes);
+smmo_status smmo_heap_bytes(const smmo_schema *s, uint64_t blocks, uint64_t *bytes);
+
+/* ---- heap -------------------------------------------------------------- */
+
+/* Creates a heap in the caller's device buffer `dev_buf` of `bytes` bytes
+ * (256-byte aligned).  M, the number of blocks, is the largest count whose
+ * arrays and blocks fit; at most 2^25 - 2.  Enqueues the initialization (all
+ * blocks free, Ch.5 sec.5.2.4 "Block Bitmaps") on `stream`.  The schema is
+ * frozen.  cfg may be NULL for the defaults.  The buffer must stay allocated
+ * until smmo_heap_free().  SMMO_ENOMEM if not even one block fits. */
+smmo_status smmo_alloc_heap(smmo_schema *s, void *dev_buf, size_t bytes,
+                            const smmo_config *cfg, smmo_stream stream, smmo_heap **out);
+
+/* Waits for the heap's work and releases host-side state (not dev_buf). */
+smmo_status smmo_heap_free(smmo_heap *h);
+
+/* ---- SMMO operations ---------------------------------------------------- */
+
+/* parallel_new (Ch.5 sec.5.1.1): creates n objects of class `class_id`.
+ * Object i takes its field values from the initializers (element i), other
+ * fields are zero.  If out_handles (device, n entries) is not NULL,
+ * out_handles[i] receives object i's handle.  n = 0 is a no-op.  The host
+ * rejects n > 64 * M with SMMO_ENOMEM; if the free blocks do not suffice the
+ * device sets SMMO_ENOMEM (bulk_ordered: nothing is created; otherwise the
+ * objects that found room exist and the others' handles are SMMO_NULL). */
+smmo_status smmo_parallel_new(smmo_heap *h, uint32_t class_id, uint32_t n,
+                              const smmo_field_init *init, uint32_t ninit,
+                              uint32_t *out_handles, smmo_stream stream);
+
+/* parallel_do (Ch.3 sec.3.2.1; Ch.5 sec.5.2.7): runs method `method_id` once
+ * on every object of class `class_id` alive when the launch starts.  `args`
+ * points to the method's argument struct (host memory, copied before return;
+ * smmo_methods.h), args_bytes its size.  The method must accept the class:
+ * each method names the fields it needs (by name and type) and fails with
+ * SMMO_EINVAL if the class lacks one. */
+smmo_status smmo_parallel_do(smmo_heap *h, uint32_t class_id, uint32_t method_id,
+                             const void *args, size_t args_bytes, smmo_stream stream);
+
+/* destroy (Ch.5 sec.5.1.1; deallocation as in sec.5.2.6 and sec.5.4): deletes
+ * the n objects whose handles are in the device array `handles`.  Each must
+ * be a live object of class `class_id` and appear once; a handle that is not
+ * sets SMMO_EDEVICE and is skipped.  Empty blocks return to the free state. */
+smmo_status smmo_destroy(smmo_heap *h, uint32_t class_id, const uint32_t *handles,
+                         uint32_t n, smmo_stream stream);
+
+/* Copies fields of all live objects of a class into dense device arrays.
+ * out_ptrs[j] (host array of nfields device pointers) receives field
+ * field_ids[j]: capacity * count elements of the field's type.  out_handles
+ * (device, may be NULL) receives the handles.  *out_count (device uint32)
+ * receives the number of live objects; objects beyond `capacity` are not
+ * written.  The order is unspecified (block by block). */
+smmo_status smmo_gather_soa(smmo_heap *h, uint32_t class_id, const uint32_t *field_ids,
+                            uint32_t nfields, void *const *out_ptrs, uint32_t *out_handles,
+                            uint32_t capacity, uint32_t *out_count, smmo_stream stream);
+
+/* ---- synchronization, statistics, diagnostics --------------------------- */
+
+/* Waits for all work enqueued on the heap and returns the device error word
+ * (SMMO_OK, SMMO_ENOMEM or SMMO_EDEVICE). */
+smmo_status smmo_sync(smmo_heap *h);
+
+/* Waits, then fills *st (live objects and blocks per class, fragmentation,
+ * the device error word).  Returns SMMO_OK even if device_error is set. */
+smmo_status smmo_heap_stats(smmo_heap *h, smmo_stats *st);
+
+/* Waits, then checks the block-state invariants that hold whenever no kernel
+ * runs on the heap: bitmap hierarchy consistency (Ch.5 sec.5.4.5 "container
+ * consistency"), free XOR allocated, active <=> allocated and not full. */
+smmo_status smmo_check_invariants(smmo_heap *h, smmo_invariants *inv);
+
+/* Resets the device error word (after the caller has handled it). */
+smmo_status smmo_clear_error(smmo_heap *h, smmo_stream stream);
+
+/* Number of blocks M and block size of a heap. */
+smmo_status smmo_heap_info(const smmo_heap *h, uint64_t *blocks, uint32_t *block_bytes);
+
+/* Method id of a method compiled into the library (names in smmo_methods.h),
+ * SMMO_EINVAL if unknown. */
+smmo_status smmo_method_id(const char *name, uint32_t *method_id);
+
+/* Copies the last error message of the calling host thread (NUL-terminated,
+ * truncated to n bytes). */
+smmo_status smmo_last_error(char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMMO_H */

@@ -1,0 +1,104 @@
+/*
+ * smmo_methods.h - methods compiled into libsmmo and their argument structs.
+ *
+ * A C ABI cannot take device lambdas or member-function pointers, so the
+ * methods that smmo_parallel_do() can run are compiled into the library and
+ * named by id (smmo_method_id(name)).  Each method states the class it runs
+ * on and the fields it needs by name and type; smmo_parallel_do() resolves
+ * them in the class's layout and returns SMMO_EINVAL if one is missing.
+ * Argument structs are passed by host pointer and size and copied at launch.
+ */
+#ifndef SMMO_METHODS_H
+#define SMMO_METHODS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- Game of Life in SMMO form (thesis Ch.7 "gol", rule B3/S23) --------
+ * Cell  {state: U8, count: I32, cell_id: I32}   one per cell, never deleted
+ * Alive {cell_id: I32}                          one per live cell
+ * "gol.cell_count"  on Cell : count = live cells among the 8 torus neighbours
+ * "gol.alive_death" on Alive: if its cell's count is not 2 or 3, set the cell
+ *                             dead and delete this Alive object
+ * "gol.cell_birth"  on Cell : if dead and count == 3, set alive and create an
+ *                             Alive object for the cell
+ * cells[i] is the handle of the Cell with cell_id i (the thesis keeps Cell
+ * pointers in a global array); the grid is width x height, index y*width+x. */
+typedef struct {
+    uint32_t cell_class;
+    uint32_t alive_class;
+    const uint32_t *cells;      /* device, width*height handles */
+    int32_t width;
+    int32_t height;
+} smmo_gol_args;
+
+/* ---- n-body (thesis Ch.7 "nbody") ----------------------------------------
+ * Body {pos_x, pos_y, vel_x, vel_y, force_x, force_y, mass: F32}
+ * "nbody.force"  : force = sum over all other bodies j (a device_do over the
+ *                  class) of G m m_j (x_j - x) / (|x_j - x|^2 + eps^2)^(3/2)
+ * "nbody.update" : vel += force / mass * dt; pos += vel * dt               */
+typedef struct {
+    float G;
+    float eps;
+    float dt;
+    uint32_t reserved;
+} smmo_nbody_args;
+
+/* ---- spring-mass mesh (thesis Ch.7 "structure", compute steps) -----------
+ * Node   {x, y, vx, vy, m: F32, adj: HANDLE x 8}
+ *        adj[q] = spring handle | (1 << 31 if this node is the spring's
+ *        endpoint b), SMMO_NULL for an empty slot
+ * Spring {a, b: HANDLE (nodes), k, L0, fx, fy: F32, slot_a, slot_b: U8}
+ *        slot_a / slot_b: index of this spring in a.adj / b.adj
+ * "spring.force"       on Spring: d = x_b - x_a, l = |d|; if
+ *        (l - L0) / L0 > strain_limit the spring empties its two adjacency
+ *        slots and deletes itself; otherwise (fx, fy) = k (l - L0) d / l,
+ *        the force on a (b receives the negative).
+ * "spring.node_update" on Node: F = sum over occupied slots, in slot order,
+ *        of +-(fx, fy); v += F / m * dt; x += v * dt.
+ * "spring.link"        on Spring: writes the spring's handle into a.adj[slot_a]
+ *        and (handle | 1 << 31) into b.adj[slot_b]; builds the topology after
+ *        parallel_new of the nodes (adj empty) and the springs.               */
+typedef struct {
+    uint32_t node_class;
+    uint32_t spring_class;
+    float dt;
+    float strain_limit;
+} smmo_spring_args;
+
+/* ---- test methods ---------------------------------------------------------
+ * "test.axpy"      on any class with F32 field "x": x = a * x + b
+ * "test.destroy_if" on any class with I32 field "key": delete this object if
+ *                   key mod `mod` == `rem` (mod > 0)
+ * "test.spawn"     on any class with I32 field "key": an object whose key
+ *                   mod `mod` == `rem` creates `copies` objects of class
+ *                   target_class (which must have an I32 field "key") with
+ *                   key = key * key_mul + key_add + c, c = 0 .. copies-1.
+ *                   target_class may be the running class: the new objects
+ *                   are not visited by the same launch.                     */
+typedef struct {
+    float a;
+    float b;
+} smmo_axpy_args;
+
+typedef struct {
+    int32_t mod;
+    int32_t rem;
+} smmo_destroy_if_args;
+
+typedef struct {
+    uint32_t target_class;
+    int32_t mod;
+    int32_t rem;
+    uint32_t copies;            /* 0 .. 8 */
+    int32_t key_mul;
+    int32_t key_add;
+} smmo_spawn_args;
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMMO_METHODS_H */

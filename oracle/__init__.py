@@ -10,6 +10,7 @@ from .oracle import (  # noqa: F401
     GolWorld,
     nbody_steps,
     nbody_force_at,
+    nbody_update,
     spring_steps,
     spring_breaks,
 )

@@ -50,6 +50,8 @@ def _load():
             lib.orc_gol_free.argtypes = [P]
             lib.orc_nbody_steps.restype = C.c_int
             lib.orc_nbody_steps.argtypes = [LL, P, P, P, P, P, P, P, D, D, D, C.c_int, P, P]
+            lib.orc_nbody_update.restype = C.c_int
+            lib.orc_nbody_update.argtypes = [LL, P, P, P, P, P, P, P, D]
             lib.orc_nbody_force_at.restype = C.c_int
             lib.orc_nbody_force_at.argtypes = [LL, P, P, P, D, D, P, LL, P, P, P, P]
             lib.orc_spring_steps.restype = LL
@@ -119,6 +121,16 @@ def nbody_steps(x, y, vx, vy, m, G, eps, dt, steps=1):
     if rc:
         raise RuntimeError("oracle nbody error %d" % rc)
     return dict(x=x, y=y, vx=vx, vy=vy, fx=fx, fy=fy, sfx=sfx, sfy=sfy)
+
+
+def nbody_update(x, y, vx, vy, fx, fy, m, dt):
+    """Body::update alone from given forces: v += f/m dt, x += v dt (float64)."""
+    lib = _load()
+    x, y, vx, vy, fx, fy, m = (_f64(a) for a in (x, y, vx, vy, fx, fy, m))
+    rc = lib.orc_nbody_update(x.size, _p(x), _p(y), _p(vx), _p(vy), _p(fx), _p(fy), _p(m), float(dt))
+    if rc:
+        raise RuntimeError("oracle nbody error %d" % rc)
+    return dict(x=x, y=y, vx=vx, vy=vy)
 
 
 def nbody_force_at(x, y, m, G, eps, idx):

@@ -329,6 +329,29 @@ int orc_nbody_steps(long long n, double *x, double *y, double *vx, double *vy,
     return 0;
 }
 
+/* Body::update alone, from given forces (arrays updated in place) */
+int orc_nbody_update(long long n, double *x, double *y, double *vx, double *vy,
+                     const double *fx, const double *fy, const double *m, double dt)
+{
+    ostore st;
+    if (n < 0 || os_init(&st, sizeof(nb_body), (size_t)(n ? n : 1))) return -1;
+    size_t *snap = malloc((size_t)(n ? n : 1) * sizeof(size_t));
+    for (long long i = 0; i < n; i++) {
+        nb_body *b = os_at(&st, (size_t)os_new(&st));
+        b->x = x[i]; b->y = y[i]; b->vx = vx[i]; b->vy = vy[i];
+        b->fx = fx[i]; b->fy = fy[i]; b->m = m[i];
+    }
+    size_t k = os_snapshot(&st, snap);
+    for (size_t i = 0; i < k; i++) nb_update(os_at(&st, snap[i]), dt);
+    for (long long i = 0; i < n; i++) {
+        const nb_body *b = os_at(&st, (size_t)i);
+        x[i] = b->x; y[i] = b->y; vx[i] = b->vx; vy[i] = b->vy;
+    }
+    free(snap);
+    os_free(&st);
+    return 0;
+}
+
 /* compute_force for selected bodies only (the device_do of those bodies) */
 int orc_nbody_force_at(long long n, const double *x, const double *y, const double *m,
                        double G, double eps, const long long *idx, long long nidx,

@@ -1,0 +1,638 @@
+// Methods that smmo_parallel_do() can run (argument structs and field
+// contracts in include/smmo_methods.h).
+//
+// Every method kernel walks the class's block list R (built by the
+// enumeration pre-pass) with one wavefront per block and one lane per slot,
+// the thread assignment of DynaSOAr's parallel_do with N_T = 64 (Ch.5
+// sec.5.2.7): lane s handles slot s, so each field access of a wavefront is
+// one contiguous 64-entry run.  The launch is a fixed grid that strides over
+// R, whose length is read on the device, so step loops need no host
+// read-back.  Work-groups are renumbered so that each of the eight XCDs
+// (each with its own L2) walks a contiguous stretch of R.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "../../include/smmo_methods.h"
+#include "smmo_device.hpp"
+#include "smmo_host.hpp"
+
+using namespace smmo;
+
+namespace {
+
+// Work-group g runs on XCD g % 8; give XCD x the contiguous range of logical
+// work-group numbers [start(x), start(x) + count(x)).
+__device__ __forceinline__ uint32_t xcd_logical_wg()
+{
+    const uint32_t G = gridDim.x, g = blockIdx.x;
+    const uint32_t x = g & 7u, k = g >> 3, per = G >> 3, rem = G & 7u;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Calls f(bid, bitmap) for every block of class `cls` in R, one wavefront per
+// block.  A block that was freed (or freed and re-used by another class)
+// since R was built has a different type and is skipped, so R may be a
+// superset of the class's blocks.  bitmap = the iteration bitmap (snapshot of
+// the allocation bitmap taken by the enumeration) or the allocation bitmap,
+// which is the same as long as the method creates no object of its own class.
+template <class F>
+__device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, bool snapshot, F &&f)
+{
+    const uint32_t r = __builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_RFINAL + cls));
+    const uint32_t *R = h.R + (uint64_t)cls * h.M;
+    const uint32_t wpg = blockDim.x >> 6;
+    const uint32_t nw = gridDim.x * wpg;
+    for (uint32_t i = xcd_logical_wg() * wpg + (threadIdx.x >> 6); i < r; i += nw) {
+        const uint32_t bid = __builtin_amdgcn_readfirstlane(R[i]);
+        if (__builtin_amdgcn_readfirstlane(ald32(h.type + bid)) != cls) continue;
+        const uint64_t bm = uniform64(snapshot ? h.iter_bm[bid] : ald(h.alloc_bm + bid));
+        f(bid, bm);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T *farr(const HeapView &h, uint32_t bid, uint32_t off)
+{
+    return reinterpret_cast<T *>(h.block(bid) + off);
+}
+
+template <class T>
+__device__ __forceinline__ T &fref(const HeapView &h, uint32_t handle, uint32_t off)
+{
+    return reinterpret_cast<T *>(h.block(handle >> 6) + off)[handle & 63];
+}
+
+smmo_status launched(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SMMO_OK : hip_fail(e, what);
+}
+
+#define BIND(cls, name, dt, cnt, off, stride)                                              \
+    do {                                                                                   \
+        smmo_status _s = bind_field(h->schema, (cls), (name), (dt), (cnt), (off), (stride)); \
+        if (_s) return _s;                                                                 \
+    } while (0)
+
+// ======================================================= Game of Life =====
+struct GolK {
+    uint32_t cell_cls, alive_cls;
+    const uint32_t *cells;
+    int32_t W, H;
+    uint32_t c_state, c_count, c_id;   // Cell field offsets
+    uint32_t a_id;                     // Alive field offset
+};
+
+// Cell::count - live cells among the 8 neighbours on the torus
+__global__ __launch_bounds__(256) void k_gol_count(HeapView h, GolK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if (!((bm >> s) & 1)) return;
+        const int32_t id = farr<int32_t>(h, bid, p.c_id)[s];
+        const int32_t x = id % p.W, y = id / p.W;
+        int32_t n = 0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int32_t ny = (y + dy + p.H) % p.H;
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy) continue;
+                const int32_t nx = (x + dx + p.W) % p.W;
+                const uint32_t hc = p.cells[ny * p.W + nx];
+                n += fref<uint8_t>(h, hc, p.c_state);
+            }
+        }
+        farr<int32_t>(h, bid, p.c_count)[s] = n;
+    });
+}
+
+// Alive::death - if the cell's count is not 2 or 3: cell dies, delete this
+__global__ __launch_bounds__(256) void k_gol_death(HeapView h, GolK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.alive_cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        bool die = false;
+        if ((bm >> s) & 1) {
+            const int32_t cid = farr<int32_t>(h, bid, p.a_id)[s];
+            const uint32_t hc = p.cells[cid];
+            const int32_t n = fref<int32_t>(h, hc, p.c_count);
+            if (n != 2 && n != 3) {
+                fref<uint8_t>(h, hc, p.c_state) = 0;
+                die = true;
+            }
+        }
+        wave_release_own_block(h, p.alive_cls, bid, __ballot(die));
+    });
+}
+
+// Cell::birth - if dead with exactly three live neighbours: becomes alive and
+// gets a new Alive object
+__global__ __launch_bounds__(256) void k_gol_birth(HeapView h, GolK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        bool born = false;
+        int32_t id = 0;
+        if ((bm >> s) & 1) {
+            uint8_t &st = farr<uint8_t>(h, bid, p.c_state)[s];
+            if (st == 0 && farr<int32_t>(h, bid, p.c_count)[s] == 3) {
+                st = 1;
+                born = true;
+                id = farr<int32_t>(h, bid, p.c_id)[s];
+            }
+        }
+        const uint32_t a = wave_allocate(h, p.alive_cls, born);
+        if (born && a != kNull) fref<int32_t>(h, a, p.a_id) = id;
+    });
+}
+
+smmo_status bind_gol(smmo_heap *h, const smmo_gol_args &a, GolK &k)
+{
+    if (a.cell_class >= h->schema->nclasses || a.alive_class >= h->schema->nclasses ||
+        a.cell_class == a.alive_class)
+        return fail(SMMO_EINVAL, "gol: bad class ids");
+    if (!a.cells || a.width <= 0 || a.height <= 0) return fail(SMMO_EINVAL, "gol: bad grid");
+    k.cell_cls = a.cell_class;
+    k.alive_cls = a.alive_class;
+    k.cells = a.cells;
+    k.W = a.width;
+    k.H = a.height;
+    BIND(a.cell_class, "state", SMMO_U8, 1, &k.c_state, nullptr);
+    BIND(a.cell_class, "count", SMMO_I32, 1, &k.c_count, nullptr);
+    BIND(a.cell_class, "cell_id", SMMO_I32, 1, &k.c_id, nullptr);
+    BIND(a.alive_class, "cell_id", SMMO_I32, 1, &k.a_id, nullptr);
+    return SMMO_OK;
+}
+
+template <int Which>
+smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_gol_args a;
+    memcpy(&a, args, sizeof a);
+    GolK k;
+    smmo_status s = bind_gol(h, a, k);
+    if (s) return s;
+    const uint32_t want = Which == 1 ? a.alive_class : a.cell_class;
+    if (cls != want) return fail(SMMO_EINVAL, "gol: method runs on a different class");
+    if ((s = ensure_enumerated(h, cls, false, st))) return s;
+    const uint32_t grid = method_grid(h, cls);
+    if (Which == 0) hipLaunchKernelGGL(k_gol_count, dim3(grid), dim3(256), 0, st, h->v, k);
+    if (Which == 1) hipLaunchKernelGGL(k_gol_death, dim3(grid), dim3(256), 0, st, h->v, k);
+    if (Which == 2) hipLaunchKernelGGL(k_gol_birth, dim3(grid), dim3(256), 0, st, h->v, k);
+    if ((s = launched("gol kernel"))) return s;
+    if (Which == 2) note_allocation(h, a.alive_class, 64ull * h->v.M);
+    return SMMO_OK;
+}
+
+// ============================================================= n-body =====
+struct NbodyK {
+    uint32_t cls;
+    uint32_t o_x, o_y, o_vx, o_vy, o_fx, o_fy, o_m;
+    float G, eps2, dt;
+};
+
+// Body::compute_force with device_do over all bodies (Ch.7 "nbody").  A
+// work-group owns one block of 64 bodies i (one per lane in every wave);
+// its four wavefronts split the other bodies j block-wise (wave w takes
+// every fourth block of R), stage each j-block in LDS and read it back as
+// broadcasts.  Each wave sums one j-block (64 terms) into a fresh float32
+// partial and adds the partial to its running sum with Kahan compensation;
+// the four running sums are combined in wave order.  The thesis leaves this
+// shared-memory tiling as future work (its "Further Optimizations").
+template <bool kGuard>
+__global__ __launch_bounds__(256) void k_nbody_force(HeapView h, NbodyK p)
+{
+    __shared__ float4 tile[4][64];
+    __shared__ float2 red[4][64];
+    if (heap_failed(h)) return;
+    const uint32_t r = __builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_RFINAL + p.cls));
+    const uint32_t *R = h.R + (uint64_t)p.cls * h.M;
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (uint32_t ib = xcd_logical_wg(); ib < r; ib += gridDim.x) {
+        const uint32_t bid = R[ib];
+        if (ald32(h.type + bid) != p.cls) continue;     // same for the whole work-group
+        const uint64_t bmi = ald(h.alloc_bm + bid);
+        const float xi = farr<float>(h, bid, p.o_x)[lane];
+        const float yi = farr<float>(h, bid, p.o_y)[lane];
+        float ax = 0.f, ay = 0.f, cx = 0.f, cy = 0.f;
+        for (uint32_t j0 = 0; j0 < r; j0 += 4) {
+            const uint32_t jt = j0 + w;
+            if (jt >= r) break;                          // wave-uniform
+            const uint32_t jb = __builtin_amdgcn_readfirstlane(R[jt]);
+            if (__builtin_amdgcn_readfirstlane(ald32(h.type + jb)) != p.cls) continue;
+            const uint64_t bmj = uniform64(ald(h.alloc_bm + jb));
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if ((bmj >> lane) & 1)
+                v = make_float4(farr<float>(h, jb, p.o_x)[lane], farr<float>(h, jb, p.o_y)[lane],
+                                farr<float>(h, jb, p.o_m)[lane], 0.f);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            tile[w][lane] = v;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            float tx = 0.f, ty = 0.f;
+#pragma unroll 8
+            for (int j = 0; j < 64; ++j) {
+                const float4 q = tile[w][j];
+                const float dx = q.x - xi, dy = q.y - yi;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, p.eps2));
+                float inv = __frsqrt_rn(r2);
+                if (kGuard) inv = r2 > 0.f ? inv : 0.f;
+                const float sc = q.z * inv * (inv * inv);
+                tx = fmaf(dx, sc, tx);
+                ty = fmaf(dy, sc, ty);
+            }
+            float yx = tx - cx, t = ax + yx;
+            cx = (t - ax) - yx;
+            ax = t;
+            float yy = ty - cy;
+            t = ay + yy;
+            cy = (t - ay) - yy;
+            ay = t;
+        }
+        red[w][lane] = make_float2(ax, ay);
+        __syncthreads();
+        if (w == 0 && ((bmi >> lane) & 1)) {
+            float sx = 0.f, sy = 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sx += red[k][lane].x;
+                sy += red[k][lane].y;
+            }
+            const float gm = p.G * farr<float>(h, bid, p.o_m)[lane];
+            farr<float>(h, bid, p.o_fx)[lane] = gm * sx;
+            farr<float>(h, bid, p.o_fy)[lane] = gm * sy;
+        }
+        __syncthreads();
+    }
+}
+
+// Body::update - v += f / m dt; x += v dt (velocity first)
+__global__ __launch_bounds__(256) void k_nbody_update(HeapView h, NbodyK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if (!((bm >> s) & 1)) return;
+        const float m = farr<float>(h, bid, p.o_m)[s];
+        float vx = farr<float>(h, bid, p.o_vx)[s], vy = farr<float>(h, bid, p.o_vy)[s];
+        vx += farr<float>(h, bid, p.o_fx)[s] / m * p.dt;
+        vy += farr<float>(h, bid, p.o_fy)[s] / m * p.dt;
+        farr<float>(h, bid, p.o_vx)[s] = vx;
+        farr<float>(h, bid, p.o_vy)[s] = vy;
+        farr<float>(h, bid, p.o_x)[s] += vx * p.dt;
+        farr<float>(h, bid, p.o_y)[s] += vy * p.dt;
+    });
+}
+
+smmo_status bind_nbody(smmo_heap *h, uint32_t cls, const smmo_nbody_args &a, NbodyK &k)
+{
+    if (!(a.eps >= 0.f) || !(a.dt == a.dt) || !(a.G == a.G)) return fail(SMMO_EINVAL, "nbody: bad parameters");
+    k.cls = cls;
+    BIND(cls, "pos_x", SMMO_F32, 1, &k.o_x, nullptr);
+    BIND(cls, "pos_y", SMMO_F32, 1, &k.o_y, nullptr);
+    BIND(cls, "vel_x", SMMO_F32, 1, &k.o_vx, nullptr);
+    BIND(cls, "vel_y", SMMO_F32, 1, &k.o_vy, nullptr);
+    BIND(cls, "force_x", SMMO_F32, 1, &k.o_fx, nullptr);
+    BIND(cls, "force_y", SMMO_F32, 1, &k.o_fy, nullptr);
+    BIND(cls, "mass", SMMO_F32, 1, &k.o_m, nullptr);
+    k.G = a.G;
+    k.eps2 = a.eps * a.eps;
+    k.dt = a.dt;
+    return SMMO_OK;
+}
+
+smmo_status launch_nbody_force(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_nbody_args a;
+    memcpy(&a, args, sizeof a);
+    NbodyK k;
+    smmo_status s = bind_nbody(h, cls, a, k);
+    if (s) return s;
+    if ((s = ensure_enumerated(h, cls, false, st))) return s;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, h->ub_blocks[cls]), 8192);
+    if (k.eps2 > 0.f)
+        hipLaunchKernelGGL(k_nbody_force<false>, dim3(grid), dim3(256), 0, st, h->v, k);
+    else
+        hipLaunchKernelGGL(k_nbody_force<true>, dim3(grid), dim3(256), 0, st, h->v, k);
+    return launched("k_nbody_force");
+}
+
+smmo_status launch_nbody_update(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_nbody_args a;
+    memcpy(&a, args, sizeof a);
+    NbodyK k;
+    smmo_status s = bind_nbody(h, cls, a, k);
+    if (s) return s;
+    if ((s = ensure_enumerated(h, cls, false, st))) return s;
+    hipLaunchKernelGGL(k_nbody_update, dim3(method_grid(h, cls)), dim3(256), 0, st, h->v, k);
+    return launched("k_nbody_update");
+}
+
+// ======================================================== spring-mass =====
+struct SpringK {
+    uint32_t node_cls, spring_cls;
+    uint32_t s_a, s_b, s_k, s_L0, s_fx, s_fy, s_sa, s_sb;      // Spring fields
+    uint32_t n_x, n_y, n_vx, n_vy, n_m, n_adj, n_adj_stride;   // Node fields
+    float dt, limit;
+};
+
+// The break decision is integer-valued, so it is evaluated in float32 with a
+// fixed operation order (no contraction): dx, dy; l2 = fma(dx, dx, dy*dy);
+// l = sqrt(l2) (correctly rounded); strain = (l - L0) / L0 (correctly rounded).
+__device__ __forceinline__ bool spring_breaks(float dx, float dy, float L0, float limit, float &l)
+{
+#pragma clang fp contract(off)
+    const float dy2 = dy * dy;
+    const float l2 = __builtin_fmaf(dx, dx, dy2);
+    l = __builtin_sqrtf(l2);
+    const float strain = (l - L0) / L0;
+    return strain > limit;
+}
+
+// Spring::compute_force (Ch.7 "structure"): Hooke's law on the length change;
+// a spring strained past the limit empties its two adjacency slots and
+// deletes itself (the thesis's remove_spring followed by destroy).
+__global__ __launch_bounds__(256) void k_spring_force(HeapView h, SpringK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        bool brk = false;
+        if ((bm >> s) & 1) {
+            const uint32_t a = farr<uint32_t>(h, bid, p.s_a)[s];
+            const uint32_t b = farr<uint32_t>(h, bid, p.s_b)[s];
+            const float k = farr<float>(h, bid, p.s_k)[s];
+            const float L0 = farr<float>(h, bid, p.s_L0)[s];
+            const float xa = fref<float>(h, a, p.n_x), ya = fref<float>(h, a, p.n_y);
+            const float xb = fref<float>(h, b, p.n_x), yb = fref<float>(h, b, p.n_y);
+            const float dx = xb - xa, dy = yb - ya;
+            float l;
+            brk = spring_breaks(dx, dy, L0, p.limit, l);
+            if (brk) {
+                const uint32_t qa = farr<uint8_t>(h, bid, p.s_sa)[s];
+                const uint32_t qb = farr<uint8_t>(h, bid, p.s_sb)[s];
+                fref<uint32_t>(h, a, p.n_adj + qa * p.n_adj_stride) = kNull;
+                fref<uint32_t>(h, b, p.n_adj + qb * p.n_adj_stride) = kNull;
+            } else {
+                const float c = k * (l - L0) / l;
+                farr<float>(h, bid, p.s_fx)[s] = c * dx;
+                farr<float>(h, bid, p.s_fy)[s] = c * dy;
+            }
+        }
+        wave_release_own_block(h, p.spring_cls, bid, __ballot(brk));
+    });
+}
+
+// Node::update: sum the attached springs' forces in slot order (+f if this
+// node is endpoint a, -f if b), then v += F/m dt, x += v dt.
+__global__ __launch_bounds__(256) void k_spring_node(HeapView h, SpringK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if (!((bm >> s) & 1)) return;
+        uint32_t e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = farr<uint32_t>(h, bid, p.n_adj + q * p.n_adj_stride)[s];
+        float Fx = 0.f, Fy = 0.f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (e[q] == kNull) continue;
+            const uint32_t sh = e[q] & 0x7FFFFFFFu;
+            const float fx = fref<float>(h, sh, p.s_fx), fy = fref<float>(h, sh, p.s_fy);
+            if (e[q] >> 31) {
+                Fx -= fx;
+                Fy -= fy;
+            } else {
+                Fx += fx;
+                Fy += fy;
+            }
+        }
+        const float m = farr<float>(h, bid, p.n_m)[s];
+        float vx = farr<float>(h, bid, p.n_vx)[s], vy = farr<float>(h, bid, p.n_vy)[s];
+        vx += Fx / m * p.dt;
+        vy += Fy / m * p.dt;
+        farr<float>(h, bid, p.n_vx)[s] = vx;
+        farr<float>(h, bid, p.n_vy)[s] = vy;
+        farr<float>(h, bid, p.n_x)[s] += vx * p.dt;
+        farr<float>(h, bid, p.n_y)[s] += vy * p.dt;
+    });
+}
+
+// Spring::link: registers the spring in its two nodes' adjacency slots
+// (slot_a of a, slot_b of b, the latter flagged as endpoint b).  Builds a
+// mesh's topology on the device after parallel_new of nodes and springs;
+// every (node, slot) pair belongs to one spring, so the writes never collide.
+__global__ __launch_bounds__(256) void k_spring_link(HeapView h, SpringK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if (!((bm >> s) & 1)) return;
+        const uint32_t self = (bid << 6) | s;
+        const uint32_t a = farr<uint32_t>(h, bid, p.s_a)[s];
+        const uint32_t b = farr<uint32_t>(h, bid, p.s_b)[s];
+        const uint32_t qa = farr<uint8_t>(h, bid, p.s_sa)[s];
+        const uint32_t qb = farr<uint8_t>(h, bid, p.s_sb)[s];
+        if (qa >= 8 || qb >= 8) {
+            raise_error(h, ERR_BADHANDLE);
+            return;
+        }
+        fref<uint32_t>(h, a, p.n_adj + qa * p.n_adj_stride) = self;
+        fref<uint32_t>(h, b, p.n_adj + qb * p.n_adj_stride) = self | 0x80000000u;
+    });
+}
+
+smmo_status bind_spring(smmo_heap *h, const smmo_spring_args &a, SpringK &k)
+{
+    const uint32_t nc = h->schema->nclasses;
+    if (a.node_class >= nc || a.spring_class >= nc || a.node_class == a.spring_class)
+        return fail(SMMO_EINVAL, "spring: bad class ids");
+    if (!(a.dt == a.dt) || !(a.strain_limit == a.strain_limit)) return fail(SMMO_EINVAL, "spring: NaN parameter");
+    k.node_cls = a.node_class;
+    k.spring_cls = a.spring_class;
+    BIND(a.spring_class, "a", SMMO_HANDLE, 1, &k.s_a, nullptr);
+    BIND(a.spring_class, "b", SMMO_HANDLE, 1, &k.s_b, nullptr);
+    BIND(a.spring_class, "k", SMMO_F32, 1, &k.s_k, nullptr);
+    BIND(a.spring_class, "L0", SMMO_F32, 1, &k.s_L0, nullptr);
+    BIND(a.spring_class, "fx", SMMO_F32, 1, &k.s_fx, nullptr);
+    BIND(a.spring_class, "fy", SMMO_F32, 1, &k.s_fy, nullptr);
+    BIND(a.spring_class, "slot_a", SMMO_U8, 1, &k.s_sa, nullptr);
+    BIND(a.spring_class, "slot_b", SMMO_U8, 1, &k.s_sb, nullptr);
+    BIND(a.node_class, "x", SMMO_F32, 1, &k.n_x, nullptr);
+    BIND(a.node_class, "y", SMMO_F32, 1, &k.n_y, nullptr);
+    BIND(a.node_class, "vx", SMMO_F32, 1, &k.n_vx, nullptr);
+    BIND(a.node_class, "vy", SMMO_F32, 1, &k.n_vy, nullptr);
+    BIND(a.node_class, "m", SMMO_F32, 1, &k.n_m, nullptr);
+    BIND(a.node_class, "adj", SMMO_HANDLE, 8, &k.n_adj, &k.n_adj_stride);
+    k.dt = a.dt;
+    k.limit = a.strain_limit;
+    return SMMO_OK;
+}
+
+template <int Which>
+smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_spring_args a;
+    memcpy(&a, args, sizeof a);
+    SpringK k;
+    smmo_status s = bind_spring(h, a, k);
+    if (s) return s;
+    if (cls != (Which == 1 ? a.node_class : a.spring_class))
+        return fail(SMMO_EINVAL, "spring: method runs on a different class");
+    if ((s = ensure_enumerated(h, cls, false, st))) return s;
+    const uint32_t grid = method_grid(h, cls);
+    if (Which == 0) hipLaunchKernelGGL(k_spring_force, dim3(grid), dim3(256), 0, st, h->v, k);
+    if (Which == 1) hipLaunchKernelGGL(k_spring_node, dim3(grid), dim3(256), 0, st, h->v, k);
+    if (Which == 2) hipLaunchKernelGGL(k_spring_link, dim3(grid), dim3(256), 0, st, h->v, k);
+    return launched("spring kernel");
+}
+
+// ======================================================= test methods =====
+struct AxpyK {
+    uint32_t cls, o_x;
+    float a, b;
+};
+
+__global__ __launch_bounds__(256) void k_axpy(HeapView h, AxpyK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if ((bm >> s) & 1) {
+            float &x = farr<float>(h, bid, p.o_x)[s];
+            x = p.a * x + p.b;
+        }
+    });
+}
+
+smmo_status launch_axpy(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_axpy_args a;
+    memcpy(&a, args, sizeof a);
+    AxpyK k{cls, 0, a.a, a.b};
+    BIND(cls, "x", SMMO_F32, 1, &k.o_x, nullptr);
+    smmo_status s = ensure_enumerated(h, cls, false, st);
+    if (s) return s;
+    hipLaunchKernelGGL(k_axpy, dim3(method_grid(h, cls)), dim3(256), 0, st, h->v, k);
+    return launched("k_axpy");
+}
+
+struct DestroyIfK {
+    uint32_t cls, o_key;
+    int32_t mod, rem;
+};
+
+__global__ __launch_bounds__(256) void k_destroy_if(HeapView h, DestroyIfK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        bool d = false;
+        if ((bm >> s) & 1) {
+            const int32_t key = farr<int32_t>(h, bid, p.o_key)[s];
+            int32_t m = key % p.mod;
+            if (m < 0) m += p.mod;
+            d = m == p.rem;
+        }
+        wave_release_own_block(h, p.cls, bid, __ballot(d));
+    });
+}
+
+smmo_status launch_destroy_if(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_destroy_if_args a;
+    memcpy(&a, args, sizeof a);
+    if (a.mod <= 0) return fail(SMMO_EINVAL, "destroy_if: mod must be > 0");
+    DestroyIfK k{cls, 0, a.mod, a.rem};
+    BIND(cls, "key", SMMO_I32, 1, &k.o_key, nullptr);
+    smmo_status s = ensure_enumerated(h, cls, false, st);
+    if (s) return s;
+    hipLaunchKernelGGL(k_destroy_if, dim3(method_grid(h, cls)), dim3(256), 0, st, h->v, k);
+    return launched("k_destroy_if");
+}
+
+struct SpawnK {
+    uint32_t cls, target, o_key, t_key;
+    int32_t mod, rem, mul, add;
+    uint32_t copies, snapshot;
+};
+
+__global__ __launch_bounds__(256) void k_spawn(HeapView h, SpawnK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, p.snapshot != 0, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        bool sp = false;
+        int32_t key = 0;
+        if ((bm >> s) & 1) {
+            key = farr<int32_t>(h, bid, p.o_key)[s];
+            int32_t m = key % p.mod;
+            if (m < 0) m += p.mod;
+            sp = m == p.rem;
+        }
+        for (uint32_t c = 0; c < p.copies; ++c) {
+            const uint32_t nh = wave_allocate(h, p.target, sp);
+            if (sp && nh != kNull) fref<int32_t>(h, nh, p.t_key) = key * p.mul + p.add + (int32_t)c;
+        }
+    });
+}
+
+smmo_status launch_spawn(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_spawn_args a;
+    memcpy(&a, args, sizeof a);
+    if (a.mod <= 0 || a.copies > 8 || a.target_class >= h->schema->nclasses)
+        return fail(SMMO_EINVAL, "spawn: bad arguments");
+    SpawnK k{cls, a.target_class, 0, 0, a.mod, a.rem, a.key_mul, a.key_add, a.copies,
+             a.target_class == cls ? 1u : 0u};
+    BIND(cls, "key", SMMO_I32, 1, &k.o_key, nullptr);
+    BIND(a.target_class, "key", SMMO_I32, 1, &k.t_key, nullptr);
+    smmo_status s = ensure_enumerated(h, cls, k.snapshot != 0, st);
+    if (s) return s;
+    hipLaunchKernelGGL(k_spawn, dim3(method_grid(h, cls)), dim3(256), 0, st, h->v, k);
+    if ((s = launched("k_spawn"))) return s;
+    note_allocation(h, a.target_class, 64ull * h->v.M);
+    return SMMO_OK;
+}
+
+const MethodEntry kMethods[] = {
+    {"gol.cell_count", sizeof(smmo_gol_args), launch_gol<0>},
+    {"gol.alive_death", sizeof(smmo_gol_args), launch_gol<1>},
+    {"gol.cell_birth", sizeof(smmo_gol_args), launch_gol<2>},
+    {"nbody.force", sizeof(smmo_nbody_args), launch_nbody_force},
+    {"nbody.update", sizeof(smmo_nbody_args), launch_nbody_update},
+    {"spring.force", sizeof(smmo_spring_args), launch_spring<0>},
+    {"spring.node_update", sizeof(smmo_spring_args), launch_spring<1>},
+    {"spring.link", sizeof(smmo_spring_args), launch_spring<2>},
+    {"test.axpy", sizeof(smmo_axpy_args), launch_axpy},
+    {"test.destroy_if", sizeof(smmo_destroy_if_args), launch_destroy_if},
+    {"test.spawn", sizeof(smmo_spawn_args), launch_spawn},
+};
+
+} // namespace
+
+namespace smmo {
+const MethodEntry *method_table(uint32_t *count)
+{
+    *count = (uint32_t)(sizeof(kMethods) / sizeof(kMethods[0]));
+    return kMethods;
+}
+} // namespace smmo

@@ -1,0 +1,457 @@
+// Device side of the SMMO heap: hierarchical bitmaps, block slot reservation
+// and release, block invalidation, and wavefront-aggregated allocation and
+// deallocation.  Follows the DynaSOAr allocator (Springer, Ch.5 sec.5.2 and
+// sec.5.3, correctness argument in sec.5.4), re-expressed for CDNA wave64:
+//   - a block holds 64 objects, so its 64-bit allocation bitmap is exactly a
+//     wavefront ballot; one wavefront processes one block, one lane per slot;
+//   - the leader of an aggregated allocation is the lowest requesting lane,
+//     results are broadcast by readlane and ranks come from the ballot;
+//   - CDNA has no independent thread scheduling, so every retrying bitmap
+//     update runs in a converged loop in which each lane tries each of its
+//     pending updates once per iteration (the deadlock-free deallocation of
+//     sec.5.4.4, applied to every multi-lane bitmap update);
+//   - every retry loop is bounded; exceeding the bound raises a device error
+//     instead of hanging the GPU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "smmo_layout.hpp"
+
+namespace smmo {
+
+// ---------------------------------------------------------------- atomics --
+// Bitmap words and block headers are shared mutable state; all accesses go
+// through agent-scope atomics so that they bypass the non-coherent per-CU
+// vector L1.
+__device__ __forceinline__ uint64_t ald(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ald32(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t aor(uint64_t *p, uint64_t v)
+{
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t aand(uint64_t *p, uint64_t v)
+{
+    return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// allocation-bitmap updates order the block type (published before the
+// bitmap is reset, Alg. initialize_block) against slot reservation
+__device__ __forceinline__ uint64_t aor_ar(uint64_t *p, uint64_t v)
+{
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t aand_ar(uint64_t *p, uint64_t v)
+{
+    return __hip_atomic_fetch_and(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void raise_error(const HeapView &h, uint32_t bits)
+{
+    __hip_atomic_fetch_or(h.ctrl + CTRL_ERR, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void count_event(const HeapView &h, uint32_t word)
+{
+    __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(h.ctrl + word), 1ull,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool heap_failed(const HeapView &h)
+{
+    return ald32(h.ctrl + CTRL_ERR) != 0;
+}
+
+// ------------------------------------------------------------ bit helpers --
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t rotr64(uint64_t x, uint32_t r)
+{
+    r &= 63;
+    return r ? (x >> r) | (x << (64 - r)) : x;
+}
+
+// index of the n-th (0-based) set bit of b, or 64 if b has fewer bits
+// (Alg. nth_set_bit: clear the lowest set bit n times, then find first set)
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t b, uint32_t n)
+{
+    for (uint32_t i = 0; i < n && b; ++i) b &= b - 1;
+    return b ? (uint32_t)(__ffsll((unsigned long long)b) - 1) : 64u;
+}
+
+// the lowest n set bits of b
+__device__ __forceinline__ uint64_t lowest_bits(uint64_t b, uint32_t n)
+{
+    if ((uint32_t)__popcll(b) <= n) return b;
+    uint32_t p = nth_set_bit(b, n);   // first bit not taken
+    return b & ((1ull << p) - 1);
+}
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t global_wave_id()
+{
+    return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+}
+
+// ---------------------------------------------------- hierarchical bitmap --
+// A bitmap of M bits is a stack of levels; level l+1 has one bit per 64-bit
+// container of level l, set iff that container is non-zero ("container
+// consistency", sec.5.3.1).  Levels are only eventually consistent while
+// kernels run; they are consistent whenever no kernel runs on the heap.
+
+// One pending switch of a bit: dir +1 = set (0 -> 1), -1 = clear (1 -> 0).
+// A successful switch that sets the first bit of a container, or clears its
+// last bit, continues as the same switch one level up (Alg. try_clear).
+struct BitOp {
+    uint32_t pos;
+    uint16_t bmid;
+    int8_t lvl;
+    int8_t dir;
+};
+
+constexpr int kMaxOps = 6;
+
+struct OpQueue {
+    BitOp op[kMaxOps];
+    __device__ __forceinline__ void reset()
+    {
+#pragma unroll
+        for (int i = 0; i < kMaxOps; ++i) op[i].dir = 0;
+    }
+    __device__ __forceinline__ bool push(uint32_t bmid, uint32_t pos, int dir)
+    {
+#pragma unroll
+        for (int i = 0; i < kMaxOps; ++i)
+            if (op[i].dir == 0) {
+                op[i].pos = pos;
+                op[i].bmid = (uint16_t)bmid;
+                op[i].lvl = 0;
+                op[i].dir = (int8_t)dir;
+                return true;
+            }
+        return false;
+    }
+    __device__ __forceinline__ bool pending() const
+    {
+        bool p = false;
+#pragma unroll
+        for (int i = 0; i < kMaxOps; ++i) p |= op[i].dir != 0;
+        return p;
+    }
+};
+
+// One attempt of a pending switch.  A failed attempt (the bit already has the
+// target value: another thread's opposite switch is still on its way) leaves
+// the op pending; the caller retries it later.
+__device__ __forceinline__ void bitop_try(const HeapView &h, BitOp &o)
+{
+    uint64_t *w = h.bm_word(o.bmid, (uint32_t)o.lvl, o.pos >> 6);
+    const uint64_t bit = 1ull << (o.pos & 63);
+    if (o.dir > 0) {
+        const uint64_t prev = aor(w, bit);
+        if (prev & bit) return;
+        if (prev == 0 && (uint32_t)o.lvl + 1 < h.nlev) {
+            o.lvl++;
+            o.pos >>= 6;
+            return;
+        }
+        o.dir = 0;
+    } else {
+        const uint64_t prev = aand(w, ~bit);
+        if (!(prev & bit)) return;
+        if (prev == bit && (uint32_t)o.lvl + 1 < h.nlev) {
+            o.lvl++;
+            o.pos >>= 6;
+            return;
+        }
+        o.dir = 0;
+    }
+}
+
+// Converged completion of every lane's pending switches.  All lanes of the
+// wavefront that may hold pending switches must call this together; each
+// iteration every lane tries each of its pending switches once, so a switch
+// that waits for another lane's switch cannot block it.
+__device__ __forceinline__ void run_ops_wave(const HeapView &h, OpQueue &q)
+{
+    for (uint32_t it = 0;; ++it) {
+        bool pend = false;
+#pragma unroll
+        for (int i = 0; i < kMaxOps; ++i)
+            if (q.op[i].dir) {
+                bitop_try(h, q.op[i]);
+                pend |= q.op[i].dir != 0;
+            }
+        if (__ballot(pend) == 0) break;
+        if (it >= h.spin_limit) {
+            if (pend) raise_error(h, ERR_SPIN);
+            break;
+        }
+    }
+}
+
+// The same for a single lane running alone (the allocation leader: no other
+// lane of its wavefront holds pending switches while it runs).
+__device__ __forceinline__ void run_ops_lane(const HeapView &h, OpQueue &q)
+{
+    for (uint32_t it = 0; q.pending(); ++it) {
+        if (it >= h.spin_limit) {
+            raise_error(h, ERR_SPIN);
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < kMaxOps; ++i)
+            if (q.op[i].dir) bitop_try(h, q.op[i]);
+    }
+}
+
+__device__ __forceinline__ void switch_bit_lane(const HeapView &h, uint32_t bmid, uint32_t pos, int dir)
+{
+    OpQueue q;
+    q.reset();
+    q.push(bmid, pos, dir);
+    run_ops_lane(h, q);
+}
+
+// Alg. try_find_set: top-down descent, at each level the first set bit of
+// the container after rotating it by a seed-dependent amount ("Bitmap
+// Rotation", sec.5.3.2).  May fail spuriously while levels are inconsistent.
+__device__ __forceinline__ int64_t find_set(const HeapView &h, uint32_t bmid, uint32_t seed)
+{
+    uint32_t idx = 0;
+    for (int lvl = (int)h.nlev - 1; lvl >= 0; --lvl) {
+        const uint64_t c = ald(h.bm_word(bmid, (uint32_t)lvl, idx));
+        if (!c) return -1;
+        const uint32_t r = h.rotation ? (hash32(seed + 0x9E3779B9u * (uint32_t)(lvl + 1)) & 63u) : 0u;
+        const uint32_t b = ((uint32_t)(__ffsll((unsigned long long)rotr64(c, r)) - 1) + r) & 63u;
+        idx = idx * 64u + b;
+    }
+    return (int64_t)idx;
+}
+
+// Bitmap::clear() on the free-block bitmap: find a set bit and switch it off;
+// retry the search if another thread switched it first.  Returns -1 when no
+// free block is found (the thesis spins forever here; we report exhaustion).
+__device__ __forceinline__ int64_t claim_free_block(const HeapView &h, uint32_t seed)
+{
+    for (uint32_t t = 0; t < 4096u; ++t) {
+        const int64_t b = find_set(h, BM_FREE, seed + t * 0x632BE5ABu);
+        if (b < 0) {
+            // spurious failures happen while another thread is between two
+            // levels; give it time, then conclude the heap is exhausted
+            if (t >= 256u) return -1;
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        uint64_t *w = h.bm_word(BM_FREE, 0, (uint32_t)b >> 6);
+        const uint64_t bit = 1ull << (b & 63);
+        const uint64_t prev = aand(w, ~bit);
+        if (!(prev & bit)) continue;           // someone else took it
+        if (prev == bit && h.nlev > 1) {        // cleared the container's last bit
+            OpQueue q;
+            q.reset();
+            q.op[0] = BitOp{(uint32_t)b >> 6, (uint16_t)BM_FREE, 1, -1};
+            run_ops_lane(h, q);
+        }
+        return b;
+    }
+    raise_error(h, ERR_SPIN);
+    return -1;
+}
+
+// Alg. initialize_block: publish the type, then reset the allocation bitmap
+// (every class has capacity 64, so no tail bits are pre-set).
+__device__ __forceinline__ void initialize_block(const HeapView &h, uint32_t bid, uint32_t cls)
+{
+    __hip_atomic_store(h.type + bid, cls, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(h.alloc_bm + bid, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block::reserve, extended to up to n slots at once (reserve_multiple):
+// returns the mask of slots this call switched 0 -> 1 (0 = block full or
+// invalidated) and whether this call made the block full.
+__device__ __forceinline__ uint64_t reserve_slots(const HeapView &h, uint32_t bid, uint32_t n,
+                                                  bool &filled)
+{
+    uint64_t *p = h.alloc_bm + bid;
+    uint64_t cur = ald(p);
+    filled = false;
+    for (int it = 0; it < 64; ++it) {
+        const uint64_t want = lowest_bits(~cur, n);
+        if (!want) return 0;
+        const uint64_t prev = aor_ar(p, want);
+        const uint64_t got = want & ~prev;
+        if (got) {
+            filled = (prev | want) == ~0ull;
+            return got;
+        }
+        cur = prev | want;   // all wanted slots were taken meanwhile; look again
+    }
+    return 0;
+}
+
+// Alg. invalidate: try to switch all 64 slots to 1 so that no reservation can
+// succeed; on success the block is empty and can be freed; if some slot was
+// reserved meanwhile, roll back (and owe the deferred active-bit clear when a
+// concurrent release saw the block as full).  Bitmap switches are queued,
+// not performed, so that the caller can complete them in a converged loop.
+// Returns true if the block was invalidated.
+__device__ __forceinline__ bool invalidate_block(const HeapView &h, uint32_t bid, OpQueue &q)
+{
+    uint64_t *p = h.alloc_bm + bid;
+    for (int attempt = 0; attempt < kMaxOps - 3; ++attempt) {
+        const uint64_t before = aor_ar(p, ~0ull);
+        if (before == ~0ull) return false;
+        const uint32_t t = ald32(h.type + bid);
+        if (before == 0) {
+            // The block is ours and empty.  Retire its type before it is
+            // marked free, so a stale block list sees it as not of class t.
+            __hip_atomic_store(h.type + bid, kNull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            q.push(bm_active(t), bid, -1);
+            q.push(bm_alloc(t), bid, -1);
+            q.push(BM_FREE, bid, +1);
+            return true;
+        }
+        const uint64_t before_rb = aand_ar(p, before);
+        if (before_rb != ~0ull) q.push(bm_active(t), bid, -1);
+        if ((before_rb & before) != 0) return false;
+        // empty again: retry the invalidation
+    }
+    return false;
+}
+
+// Block::deallocate for a set of slots of one block, with the block-state
+// consequences of Alg. deallocate: the release that frees the first slot of a
+// full block re-activates it; the release that empties it invalidates it.
+// Switches are queued into q.
+__device__ __forceinline__ void release_slots(const HeapView &h, uint32_t cls, uint32_t bid,
+                                              uint64_t mask, OpQueue &q)
+{
+    const uint64_t prev = aand_ar(h.alloc_bm + bid, ~mask);
+    if ((prev & mask) != mask) {
+        raise_error(h, ERR_BADHANDLE);   // releasing a free slot
+        return;
+    }
+    if (prev == ~0ull) q.push(bm_active(cls), bid, +1);
+    if ((prev & ~mask) == 0) invalidate_block(h, bid, q);
+}
+
+// ------------------------------------------------------------- allocation --
+// The leader's part of Alg. allocate with request coalescing: find an active
+// block of the class (lookup retry with rotation), else initialize a free
+// block (slow path); reserve up to n slots; deactivate the block if this
+// filled it; roll back if the block's type changed meanwhile.
+__device__ __forceinline__ uint32_t leader_allocate(const HeapView &h, uint32_t cls, uint32_t n,
+                                                    uint64_t &got, uint32_t seed)
+{
+    got = 0;
+    for (uint32_t attempt = 0; attempt < h.spin_limit; ++attempt) {
+        int64_t bid = -1;
+        for (uint32_t t = 0; t < h.retries && bid < 0; ++t)
+            bid = find_set(h, bm_active(cls), hash32(seed + attempt * 977u + t * 131u));
+        if (bid < 0) {
+            bid = claim_free_block(h, hash32(seed ^ (attempt * 0x27d4eb2fu)));
+            if (bid < 0) {
+                raise_error(h, ERR_NOMEM);
+                return kNoBlock;
+            }
+            initialize_block(h, (uint32_t)bid, cls);
+            switch_bit_lane(h, bm_alloc(cls), (uint32_t)bid, +1);
+            switch_bit_lane(h, bm_active(cls), (uint32_t)bid, +1);
+            count_event(h, CTRL_SLOW);
+        }
+        bool filled;
+        const uint64_t g = reserve_slots(h, (uint32_t)bid, n, filled);
+        if (g) {
+            const uint32_t t = __hip_atomic_load(h.type + bid, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (filled) switch_bit_lane(h, bm_active(t), (uint32_t)bid, -1);
+            if (t == cls) {
+                got = g;
+                return (uint32_t)bid;
+            }
+            OpQueue q;                     // block re-typed meanwhile: roll back
+            q.reset();
+            release_slots(h, t, (uint32_t)bid, g, q);
+            run_ops_lane(h, q);
+        }
+        count_event(h, CTRL_RETRY);
+    }
+    raise_error(h, ERR_SPIN);
+    return kNoBlock;
+}
+
+// Allocation of one object of class `cls` for every lane with want = true.
+// Must be called by all lanes of the wavefront together (converged).  With
+// coalescing the lowest requesting lane allocates for all requesting lanes;
+// each lane takes the slot whose rank among the reserved slots equals its
+// rank among the requesting lanes.  Returns the handle, or SMMO_NULL when
+// want is false or the heap is exhausted.
+__device__ __forceinline__ uint32_t wave_allocate(const HeapView &h, uint32_t cls, bool want)
+{
+    uint32_t result = kNull;
+    uint64_t pending = __ballot(want);
+    const uint32_t lane = lane_id();
+    const uint32_t seed = hash32(global_wave_id() * 0x9E3779B1u + 0x51ED27u);
+    for (uint32_t round = 0; pending; ++round) {
+        const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)pending) - 1);
+        const uint32_t n = h.coalescing ? (uint32_t)__popcll(pending) : 1u;
+        uint32_t bid = kNoBlock;
+        uint64_t got = 0;
+        if (lane == leader) bid = leader_allocate(h, cls, n, got, seed + round * 0x85ebca6bu);
+        bid = __shfl(bid, (int)leader);
+        const uint32_t glo = __shfl((uint32_t)got, (int)leader);
+        const uint32_t ghi = __shfl((uint32_t)(got >> 32), (int)leader);
+        got = ((uint64_t)ghi << 32) | glo;
+        if (bid == kNoBlock) break;
+        const uint32_t k = (uint32_t)__popcll(got);
+        if ((pending >> lane) & 1) {
+            const uint32_t rank = (uint32_t)__popcll(pending & ((1ull << lane) - 1));
+            if (rank < k) result = (bid << 6) | nth_set_bit(got, rank);
+        }
+        pending &= ~lowest_bits(pending, k);
+    }
+    return result;
+}
+
+// Deallocation of arbitrary handles of class `cls` (one per lane with want).
+// Converged call.  Handles must name live objects of the class.
+__device__ __forceinline__ void wave_deallocate(const HeapView &h, uint32_t cls, uint32_t handle,
+                                                bool want)
+{
+    OpQueue q;
+    q.reset();
+    if (want) release_slots(h, cls, handle >> 6, 1ull << (handle & 63), q);
+    run_ops_wave(h, q);
+}
+
+// Deallocation of objects that delete themselves inside a method: the
+// wavefront processes one block, so all its releases go to that block and
+// are combined into one atomic (the multi-slot release of sec.5.3.2).
+// Converged call; `mask` is the ballot of the lanes deleting their object.
+__device__ __forceinline__ void wave_release_own_block(const HeapView &h, uint32_t cls, uint32_t bid,
+                                                       uint64_t mask)
+{
+    if (!mask) return;
+    OpQueue q;
+    q.reset();
+    const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)mask) - 1);
+    if (lane_id() == leader) release_slots(h, cls, bid, mask, q);
+    run_ops_wave(h, q);
+}
+
+} // namespace smmo

@@ -1,0 +1,83 @@
+// Host-side state of schemas and heaps, shared by the library's translation
+// units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/smmo.h"
+#include "smmo_layout.hpp"
+
+struct smmo_field_info {
+    char name[32];
+    int32_t dtype;
+    uint32_t count;
+    uint32_t size;       // bytes per element
+    uint32_t offset;     // byte offset of element 0's 64-entry array in a block
+    uint32_t stride;     // bytes from one inner element's array to the next
+};
+
+struct smmo_class_info {
+    char name[32];
+    uint32_t nfields;
+    uint32_t narrays;
+    smmo_field_info f[SMMO_MAX_FIELDS];
+    uint32_t data_bytes;
+};
+
+struct smmo_schema {
+    uint32_t nclasses = 0;
+    smmo_class_info c[SMMO_MAX_CLASSES];
+    bool frozen = false;
+};
+
+enum RState : int { R_DIRTY = 0, R_VALID = 1 };
+
+struct smmo_heap {
+    smmo_schema *schema = nullptr;
+    smmo::HeapView v{};
+    void *base = nullptr;
+    size_t bytes = 0;
+    smmo_config cfg{};
+    hipStream_t last = nullptr;
+    int device = 0;
+    uint64_t *host_ctrl = nullptr;     // pinned copy target for control words
+    int rstate[SMMO_MAX_CLASSES] = {};
+    uint64_t ub_blocks[SMMO_MAX_CLASSES] = {};   // upper bound of blocks per class
+    uint32_t cu_count = 256;
+};
+
+namespace smmo {
+
+// sets the calling thread's last-error text and returns `st`
+smmo_status fail(smmo_status st, const std::string &msg);
+smmo_status hip_fail(hipError_t e, const char *what);
+
+uint32_t dtype_size(int32_t dtype);
+
+// field lookup by name with the expected type and inner-array length
+// (count 0 = any); on success fills offset / stride of the field
+smmo_status bind_field(const smmo_schema *s, uint32_t cls, const char *name, int32_t dtype,
+                       uint32_t count, uint32_t *offset, uint32_t *stride);
+
+// block list of a class for the next launch: rebuilds it if it is stale;
+// snapshot = copy allocation bitmaps to iteration bitmaps on the way
+smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st);
+
+// launch width for a method over class cls: work-groups of 256 threads
+uint32_t method_grid(const smmo_heap *h, uint32_t cls);
+
+// bookkeeping after a launch that creates objects of class cls
+void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects);
+
+struct MethodEntry {
+    const char *name;
+    size_t args_bytes;
+    smmo_status (*launch)(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+};
+
+const MethodEntry *method_table(uint32_t *count);
+
+} // namespace smmo

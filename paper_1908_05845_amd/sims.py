@@ -1,0 +1,224 @@
+"""Workload drivers on the SMMO heap: Game of Life, n-body and spring meshes.
+
+Each driver builds a heap, creates its objects with smmo_parallel_new from
+dense arrays (as produced by the ``inputs`` package), runs steps as
+sequences of smmo_parallel_do, and reads canonical state back with
+smmo_gather_soa (ordered by the objects' key fields, since slot placement is
+not part of the result).  Everything runs through libsmmo.
+"""
+
+import numpy as np
+
+from . import smmo
+
+GOL_CLASSES = {
+    "Cell": [("state", "u8", 1), ("count", "i32", 1), ("cell_id", "i32", 1)],
+    "Alive": [("cell_id", "i32", 1)],
+}
+
+NBODY_CLASSES = {
+    "Body": [("pos_x", "f32", 1), ("pos_y", "f32", 1), ("vel_x", "f32", 1), ("vel_y", "f32", 1),
+             ("force_x", "f32", 1), ("force_y", "f32", 1), ("mass", "f32", 1), ("id", "i32", 1)],
+}
+
+SPRING_CLASSES = {
+    "Node": [("x", "f32", 1), ("y", "f32", 1), ("vx", "f32", 1), ("vy", "f32", 1), ("m", "f32", 1),
+             ("adj", "handle", 8), ("id", "i32", 1)],
+    "Spring": [("a", "handle", 1), ("b", "handle", 1), ("k", "f32", 1), ("L0", "f32", 1),
+               ("fx", "f32", 1), ("fy", "f32", 1), ("slot_a", "u8", 1), ("slot_b", "u8", 1),
+               ("id", "i32", 1)],
+}
+
+
+def _blocks(n: int) -> int:
+    return (n + 63) // 64
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+class GolSim:
+    """Game of Life in SMMO form on a W x H torus (Cell + Alive classes)."""
+
+    def __init__(self, W: int, H: int, init, cfg=None, extra_blocks: int = 16):
+        import torch
+
+        self.W, self.H = W, H
+        n = W * H
+        self.heap = smmo.Heap(GOL_CLASSES, blocks=3 * _blocks(n) + extra_blocks, cfg=cfg)
+        dev = self.heap.buf.device
+        init = np.ascontiguousarray(init, dtype=np.uint8).reshape(-1)
+        ids = torch.arange(n, dtype=torch.int32, device=dev)
+        self.cells = self.heap.new("Cell", n, state=torch.from_numpy(init).to(dev), cell_id=ids).clone()
+        live = torch.from_numpy(np.flatnonzero(init).astype(np.int32)).to(dev)
+        if live.numel():
+            self.heap.new("Alive", live.numel(), cell_id=live)
+        self.args = smmo.smmo_gol_args(self.heap.cls["Cell"], self.heap.cls["Alive"],
+                                       self.cells.data_ptr(), W, H)
+        self.m_count = smmo.smmo_method_id("gol.cell_count")
+        self.m_death = smmo.smmo_method_id("gol.alive_death")
+        self.m_birth = smmo.smmo_method_id("gol.cell_birth")
+
+    def step(self, n: int = 1, stream=None):
+        h, c, a = self.heap.h, self.heap.cls["Cell"], self.heap.cls["Alive"]
+        for _ in range(n):
+            smmo.smmo_parallel_do(h, c, self.m_count, self.args, stream)
+            smmo.smmo_parallel_do(h, a, self.m_death, self.args, stream)
+            smmo.smmo_parallel_do(h, c, self.m_birth, self.args, stream)
+
+    def read(self):
+        """(state u8[W*H], count i32[W*H], sorted cell ids of Alive objects)."""
+        g = self.heap.gather("Cell", ["state", "count", "cell_id"])
+        nc = self.W * self.H
+        cid = _np(g["cell_id"])
+        state = np.zeros(nc, np.uint8)
+        count = np.zeros(nc, np.int32)
+        state[cid] = _np(g["state"])
+        count[cid] = _np(g["count"])
+        a = self.heap.gather("Alive", ["cell_id"])
+        return state, count, np.sort(_np(a["cell_id"]))
+
+
+class NbodySim:
+    """All-pairs n-body (class Body) with Plummer softening."""
+
+    def __init__(self, state: dict, G: float, eps: float, dt: float, cfg=None, extra_blocks: int = 8):
+        import torch
+
+        n = int(np.asarray(state["x"]).size)
+        self.n = n
+        self.heap = smmo.Heap(NBODY_CLASSES, blocks=_blocks(n) + extra_blocks, cfg=cfg)
+        dev = self.heap.buf.device
+
+        def t(a):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+        self.handles = self.heap.new("Body", n, pos_x=t(state["x"]), pos_y=t(state["y"]),
+                                     vel_x=t(state["vx"]), vel_y=t(state["vy"]), mass=t(state["m"]),
+                                     id=torch.arange(n, dtype=torch.int32, device=dev)).clone()
+        self.args = smmo.smmo_nbody_args(G, eps, dt, 0)
+        self.m_force = smmo.smmo_method_id("nbody.force")
+        self.m_update = smmo.smmo_method_id("nbody.update")
+        self.cls = self.heap.cls["Body"]
+
+    def force(self, stream=None):
+        smmo.smmo_parallel_do(self.heap.h, self.cls, self.m_force, self.args, stream)
+
+    def update(self, stream=None):
+        smmo.smmo_parallel_do(self.heap.h, self.cls, self.m_update, self.args, stream)
+
+    def step(self, n: int = 1, stream=None):
+        for _ in range(n):
+            self.force(stream)
+            self.update(stream)
+
+    def read(self):
+        g = self.heap.gather("Body")
+        order = np.argsort(_np(g["id"]))
+        out = {}
+        for key, f in (("x", "pos_x"), ("y", "pos_y"), ("vx", "vel_x"), ("vy", "vel_y"),
+                       ("fx", "force_x"), ("fy", "force_y"), ("m", "mass")):
+            out[key] = _np(g[f])[order]
+        out["id"] = _np(g["id"])[order]
+        return out
+
+
+class SpringSim:
+    """Spring-mass mesh (classes Node and Spring) built from a mesh dict.
+
+    The mesh dict has the arrays of ``inputs.spring_mesh`` (ids local to the
+    arrays).  Springs with alive == 0 (if an 'alive' array is given) are not
+    created.  Node adjacency is built on the device by spring.link.
+    """
+
+    def __init__(self, mesh: dict, dt: float, strain_limit: float = 0.3, cfg=None, extra_blocks: int = 16,
+                 blocks: int | None = None):
+        import torch
+
+        N = int(np.asarray(mesh["x"]).size)
+        S_all = int(np.asarray(mesh["a"]).size)
+        alive = np.ones(S_all, bool) if mesh.get("alive") is None else np.asarray(mesh["alive"]).astype(bool)
+        sid = np.flatnonzero(alive).astype(np.int32)
+        S = sid.size
+        self.N, self.S_all = N, S_all
+        if blocks is None:
+            blocks = _blocks(N) + _blocks(S) + extra_blocks
+        self.heap = smmo.Heap(SPRING_CLASSES, blocks=blocks, cfg=cfg)
+        dev = self.heap.buf.device
+
+        def f32(a):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+        def i32(a):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+
+        null_adj = torch.full((N * 8,), -1, dtype=torch.int32, device=dev)
+        self.node_h = self.heap.new("Node", N, x=f32(mesh["x"]), y=f32(mesh["y"]), vx=f32(mesh["vx"]),
+                                    vy=f32(mesh["vy"]), m=f32(mesh["m"]), adj=null_adj,
+                                    id=torch.arange(N, dtype=torch.int32, device=dev)).clone()
+        a_idx = i32(np.asarray(mesh["a"])[sid]).long()
+        b_idx = i32(np.asarray(mesh["b"])[sid]).long()
+        fx = mesh.get("fx")
+        fy = mesh.get("fy")
+        kw = {}
+        if fx is not None:
+            kw["fx"] = f32(np.asarray(fx)[sid])
+            kw["fy"] = f32(np.asarray(fy)[sid])
+        if S:
+            self.spring_h = self.heap.new(
+                "Spring", S, a=self.node_h[a_idx], b=self.node_h[b_idx], k=f32(np.asarray(mesh["k"])[sid]),
+                L0=f32(np.asarray(mesh["L0"])[sid]),
+                slot_a=torch.from_numpy(np.asarray(mesh["slot_a"])[sid].astype(np.uint8)).to(dev),
+                slot_b=torch.from_numpy(np.asarray(mesh["slot_b"])[sid].astype(np.uint8)).to(dev),
+                id=i32(sid), **kw).clone()
+        self.args = smmo.smmo_spring_args(self.heap.cls["Node"], self.heap.cls["Spring"], dt, strain_limit)
+        self.m_force = smmo.smmo_method_id("spring.force")
+        self.m_node = smmo.smmo_method_id("spring.node_update")
+        self.m_link = smmo.smmo_method_id("spring.link")
+        if S:
+            smmo.smmo_parallel_do(self.heap.h, self.heap.cls["Spring"], self.m_link, self.args)
+
+    def spring_force(self, stream=None):
+        smmo.smmo_parallel_do(self.heap.h, self.heap.cls["Spring"], self.m_force, self.args, stream)
+
+    def node_update(self, stream=None):
+        smmo.smmo_parallel_do(self.heap.h, self.heap.cls["Node"], self.m_node, self.args, stream)
+
+    def step(self, n: int = 1, stream=None):
+        for _ in range(n):
+            self.spring_force(stream)
+            self.node_update(stream)
+
+    def read(self):
+        """Canonical state: node arrays by node id, spring arrays by spring id
+        (alive flags for springs; adjacency as spring ids, -1 empty)."""
+        gs = self.heap.gather("Spring", ["id", "fx", "fy", "a", "b"])
+        gn = self.heap.gather("Node", ["id", "x", "y", "vx", "vy", "m", "adj"])
+        S = self.S_all
+        sid = _np(gs["id"])
+        sh = _np(gs["handle"]).astype(np.int64)
+        alive = np.zeros(S, np.uint8)
+        alive[sid] = 1
+        fx = np.zeros(S, np.float32)
+        fy = np.zeros(S, np.float32)
+        fx[sid] = _np(gs["fx"])
+        fy[sid] = _np(gs["fy"])
+        hs = np.argsort(sh)
+        sh_sorted, sid_sorted = sh[hs], sid[hs]
+        nid = _np(gn["id"])
+        order = np.argsort(nid)
+        out = {"alive": alive, "fx": fx, "fy": fy}
+        for key in ("x", "y", "vx", "vy", "m"):
+            out[key] = _np(gn[key])[order]
+        raw = _np(gn["adj"]).reshape(-1, 8)[order].astype(np.int64) & 0xFFFFFFFF
+        used = raw != 0xFFFFFFFF
+        hh = raw & 0x7FFFFFFF
+        pos = np.clip(np.searchsorted(sh_sorted, hh), 0, max(sh_sorted.size - 1, 0))
+        found = (sh_sorted[pos] == hh) if sh_sorted.size else np.zeros(raw.shape, bool)
+        # -1 empty slot; -2 a handle that names no live spring (an error)
+        adj = np.where(used, np.where(found, sid_sorted[pos] if sid_sorted.size else -2, -2), -1)
+        out["adj"] = adj.astype(np.int32)
+        out["adj_is_b"] = np.where(used, raw >> 31, 0).astype(np.uint8)
+        out["node_handles_by_id"] = _np(gn["handle"])[order]
+        return out

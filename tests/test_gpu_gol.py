@@ -1,0 +1,69 @@
+"""GPU parity of Game of Life in SMMO form against the oracle: bit-exact cell
+states, neighbour counts and the canonical Alive set after every generation
+(objects are created on birth and deleted on death by the device allocator)."""
+
+import numpy as np
+import pytest
+
+from inputs import gol_init
+from oracle import GolWorld
+from paper_1908_05845_amd import smmo
+from paper_1908_05845_amd.sims import GolSim
+
+pytestmark = pytest.mark.gpu
+
+
+def compare_run(W, H, init, steps, cfg=None, every=1):
+    sim = GolSim(W, H, init, cfg=cfg)
+    ref = GolWorld(W, H, init)
+    for s in range(1, steps + 1):
+        sim.step(1)
+        ref.step(1)
+        if s % every == 0 or s == steps:
+            gs, gc, ga = sim.read()
+            rs, rc, ra = ref.read()
+            assert np.array_equal(gs, rs), ("state", s)
+            assert np.array_equal(gc, rc), ("count", s)
+            assert np.array_equal(ga, ra), ("alive set", s)
+    inv = sim.heap.invariants()
+    assert inv.hierarchy_violations == 0 and inv.state_violations == 0
+    assert inv.active_violations == 0 and inv.type_violations == 0 and inv.empty_allocated == 0
+    st = sim.heap.stats()
+    assert st.live_objects[sim.heap.cls["Alive"]] == ref.read()[2].size
+    return sim
+
+
+def test_config_256_torus_100_steps_bit_exact(dev):
+    print("gol 256x256 x 100", flush=True)
+    compare_run(256, 256, gol_init(256, 256), 100)
+
+
+@pytest.mark.parametrize("W,H", [(37, 23), (8, 8), (1, 1), (3, 70), (64, 1), (100, 65)])
+def test_ragged_tori(dev, W, H):
+    print("gol %dx%d" % (W, H), flush=True)
+    rng = np.random.default_rng(W * 1000 + H)
+    compare_run(W, H, (rng.random(W * H) < 0.3).astype(np.uint8), 30)
+
+
+def test_glider_on_torus(dev):
+    g = np.zeros((16, 16), np.uint8)
+    for (x, y) in [(1, 0), (2, 1), (0, 2), (1, 2), (2, 2)]:
+        g[y, x] = 1
+    sim = compare_run(16, 16, g.reshape(-1), 64, every=4)
+    st, _, _ = sim.read()
+    assert np.array_equal(st.reshape(16, 16), g)
+
+
+def test_empty_and_full_boards(dev):
+    compare_run(20, 20, np.zeros(400, np.uint8), 3)
+    compare_run(20, 20, np.ones(400, np.uint8), 3)
+
+
+@pytest.mark.parametrize("variant", [dict(rotation=0), dict(coalescing=0), dict(lookup_retries=1),
+                                     dict(bulk_ordered=0)])
+def test_allocator_variants_same_result(dev, variant):
+    print("gol variant", variant, flush=True)
+    c = smmo.smmo_config_default()
+    for k, v in variant.items():
+        setattr(c, k, v)
+    compare_run(128, 96, gol_init(128, 96, seed=77), 40, cfg=c, every=5)

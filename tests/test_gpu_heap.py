@@ -1,0 +1,278 @@
+"""GPU tests of the heap itself: creation, gather, do-all, self-deletion,
+host destroy, device allocation (coalesced or not, rotated or not), the
+iteration snapshot, heap exhaustion, and the block-state invariants after
+every operation.  Results are checked against a plain Python model of the
+live set (the SMMO semantics), never against the GPU itself."""
+
+import numpy as np
+import pytest
+
+from paper_1908_05845_amd import smmo
+
+pytestmark = pytest.mark.gpu
+
+ALL = {
+    "A": [("x", "f32", 1), ("key", "i32", 1), ("tag", "u8", 1), ("h", "handle", 1), ("arr", "u32", 3)],
+    "B": [("key", "i32", 1), ("x", "f32", 1)],
+}
+
+
+def clean(heap):
+    inv = heap.invariants()
+    bad = {f: getattr(inv, f) for f in ("hierarchy_violations", "state_violations", "active_violations",
+                                        "type_violations", "empty_allocated")}
+    assert all(v == 0 for v in bad.values()), bad
+
+
+def keys_of(heap, cls="A"):
+    g = heap.gather(cls, ["key"])
+    return np.sort(g["key"].cpu().numpy())
+
+
+def cfg(**kw):
+    c = smmo.smmo_config_default()
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1000, 4097])
+def test_new_gather_roundtrip(dev, n):
+    import torch
+
+    print("roundtrip n=%d" % n, flush=True)
+    heap = smmo.Heap(ALL, blocks=200)
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n).astype(np.float32)
+    key = np.arange(n, dtype=np.int32)
+    tag = rng.integers(0, 256, n).astype(np.uint8)
+    hh = rng.integers(0, 2 ** 31, n).astype(np.int64).astype(np.int32)
+    arr = rng.integers(0, 2 ** 31, 3 * n).astype(np.int32)
+    t = lambda a: torch.from_numpy(a).to(dev)
+    hd = heap.new("A", n, x=t(x), key=t(key), tag=t(tag), h=t(hh), arr=t(arr))
+    g = heap.gather("A")
+    assert g["count"] == n
+    o = np.argsort(g["key"].cpu().numpy())
+    assert np.array_equal(g["key"].cpu().numpy()[o], key)
+    assert np.array_equal(g["x"].cpu().numpy()[o], x)
+    assert np.array_equal(g["tag"].cpu().numpy()[o], tag)
+    assert np.array_equal(g["h"].cpu().numpy()[o], hh)
+    assert np.array_equal(g["arr"].cpu().numpy()[o].reshape(-1), arr)
+    hs = hd.cpu().numpy()
+    assert len(set(hs.tolist())) == n
+    assert set(hs.tolist()) == set(g["handle"].cpu().numpy().tolist())
+    # handle of object i is the one reported for key i
+    assert np.array_equal(g["handle"].cpu().numpy()[o], hs)
+    st = heap.stats()
+    assert st.live_objects[0] == n and st.blocks[0] == (n + 63) // 64
+    clean(heap)
+    heap.close()
+
+
+def test_axpy_visits_every_live_object_once(dev):
+    import torch
+
+    heap = smmo.Heap(ALL, blocks=64)
+    n = 1500
+    x = torch.arange(n, dtype=torch.float32, device=dev)
+    heap.new("A", n, x=x, key=torch.arange(n, dtype=torch.int32, device=dev))
+    heap.do("A", "test.axpy", smmo.smmo_axpy_args(2.0, 1.0))
+    heap.do("A", "test.axpy", smmo.smmo_axpy_args(1.0, -3.0))
+    g = heap.gather("A", ["x", "key"])
+    o = np.argsort(g["key"].cpu().numpy())
+    assert np.array_equal(g["x"].cpu().numpy()[o], 2.0 * np.arange(n, dtype=np.float32) - 2.0)
+    # a class with no objects: the do-all is a no-op
+    heap.do("B", "test.axpy", smmo.smmo_axpy_args(2.0, 1.0))
+    heap.sync()
+    clean(heap)
+
+
+def test_self_deletion_frees_empty_blocks(dev):
+    import torch
+
+    heap = smmo.Heap(ALL, blocks=64)
+    n = 2048
+    heap.new("A", n, key=torch.arange(n, dtype=torch.int32, device=dev))
+    model = np.arange(n)
+    for mod, rem in ((3, 1), (5, 0), (2, 0), (7, 3)):
+        heap.do("A", "test.destroy_if", smmo.smmo_destroy_if_args(mod, rem))
+        model = model[model % mod != rem]
+        assert np.array_equal(keys_of(heap), model)
+        clean(heap)
+    st = heap.stats()
+    assert st.live_objects[0] == model.size
+    # delete everything: all blocks return to the free state
+    heap.do("A", "test.destroy_if", smmo.smmo_destroy_if_args(1, 0))
+    st = heap.stats()
+    assert st.live_objects[0] == 0 and st.blocks[0] == 0 and st.free_blocks == heap.blocks
+    clean(heap)
+    heap.do("A", "test.axpy", smmo.smmo_axpy_args(1.0, 1.0))   # stale block list, nothing to visit
+    heap.sync()
+
+
+def test_host_destroy_and_bad_handles(dev):
+    import torch
+
+    heap = smmo.Heap(ALL, blocks=64)
+    n = 1000
+    hd = heap.new("A", n, key=torch.arange(n, dtype=torch.int32, device=dev))
+    rng = np.random.default_rng(1)
+    pick = rng.choice(n, 600, replace=False)
+    heap.destroy("A", hd[torch.from_numpy(pick).to(dev)])
+    model = np.setdiff1d(np.arange(n), pick)
+    assert np.array_equal(keys_of(heap), model)
+    clean(heap)
+    # destroying one of them again is an error reported by the next sync
+    heap.destroy("A", hd[torch.from_numpy(pick[:1]).to(dev)])
+    with pytest.raises(smmo.SmmoError) as e:
+        heap.sync()
+    assert e.value.status == smmo.SMMO_EDEVICE
+    smmo.smmo_clear_error(heap.h)
+    heap.sync()
+    # a handle of the wrong class is rejected too
+    hb = heap.new("B", 10, key=torch.arange(10, dtype=torch.int32, device=dev))
+    heap.destroy("A", hb[:1])
+    with pytest.raises(smmo.SmmoError):
+        heap.sync()
+    smmo.smmo_clear_error(heap.h)
+    assert np.array_equal(keys_of(heap), model)
+    assert keys_of(heap, "B").size == 10
+    clean(heap)
+
+
+@pytest.mark.parametrize("variant", [
+    dict(),
+    dict(rotation=0),
+    dict(coalescing=0),
+    dict(lookup_retries=1, rotation=0),
+])
+def test_device_allocator_parallel_new(dev, variant):
+    import torch
+
+    print("device new", variant, flush=True)
+    heap = smmo.Heap(ALL, blocks=2500, cfg=cfg(bulk_ordered=0, **variant))
+    n = 100_000
+    hd = heap.new("A", n, key=torch.arange(n, dtype=torch.int32, device=dev))
+    heap.sync()
+    hs = hd.cpu().numpy()
+    assert (hs != -1).all() and len(set(hs.tolist())) == n
+    assert np.array_equal(keys_of(heap), np.arange(n))
+    st = heap.stats()
+    assert st.live_objects[0] == n
+    assert st.blocks[0] >= (n + 63) // 64
+    clean(heap)
+
+
+def test_spawn_into_own_class_is_not_visited(dev):
+    import torch
+
+    heap = smmo.Heap(ALL, blocks=256)
+    n = 1000
+    heap.new("A", n, key=torch.arange(n, dtype=torch.int32, device=dev))
+    # keys 3k spawn two objects with keys 3*key + c, c = 0, 1; key 3*key is
+    # again divisible by 3, so a visit of a new object would spawn more
+    heap.do("A", "test.spawn", smmo.smmo_spawn_args(heap.cls["A"], 3, 0, 2, 3, 0))
+    base = np.arange(n)
+    sel = base[base % 3 == 0]
+    model = np.sort(np.concatenate([base, 3 * sel, 3 * sel + 1]))
+    assert np.array_equal(keys_of(heap), model)
+    clean(heap)
+
+
+def test_churn_against_live_set_model(dev):
+    import torch
+
+    for variant in (dict(), dict(rotation=0, lookup_retries=1), dict(coalescing=0)):
+        print("churn", variant, flush=True)
+        heap = smmo.Heap(ALL, blocks=600, cfg=cfg(**variant))
+        n = 3000
+        heap.new("A", n, key=torch.arange(n, dtype=torch.int32, device=dev))
+        model = np.arange(n, dtype=np.int64)
+        rng = np.random.default_rng(2)
+        for rnd in range(12):
+            mod = int(rng.integers(2, 6))
+            rem = int(rng.integers(0, mod))
+            heap.do("A", "test.destroy_if", smmo.smmo_destroy_if_args(mod, rem))
+            model = model[model % mod != rem]
+            mod2 = int(rng.integers(2, 5))
+            rem2 = int(rng.integers(0, mod2))
+            copies = int(rng.integers(1, 3))
+            add = int(rng.integers(0, 1000))
+            sel = model[model % mod2 == rem2]
+            if model.size + copies * sel.size < 20000:    # stay well inside the heap
+                heap.do("A", "test.spawn", smmo.smmo_spawn_args(heap.cls["A"], mod2, rem2, copies, 1, add))
+                new = [sel + add + c for c in range(copies)]
+                model = np.sort(np.concatenate([model] + new))
+            assert np.array_equal(keys_of(heap), model), (variant, rnd)
+            clean(heap)
+        heap.close()
+
+
+def test_cross_class_allocation(dev):
+    import torch
+
+    heap = smmo.Heap(ALL, blocks=256)
+    n = 640
+    heap.new("A", n, key=torch.arange(n, dtype=torch.int32, device=dev))
+    heap.do("A", "test.spawn", smmo.smmo_spawn_args(heap.cls["B"], 1, 0, 3, 10, 0))
+    kb = keys_of(heap, "B")
+    assert np.array_equal(kb, np.sort(np.concatenate([10 * np.arange(n) + c for c in range(3)])))
+    assert keys_of(heap, "A").size == n
+    clean(heap)
+
+
+def test_bulk_oom_creates_nothing(dev):
+    import torch
+
+    heap = smmo.Heap(ALL, blocks=10)
+    n = 11 * 64
+    heap.new("A", n, key=torch.arange(n, dtype=torch.int32, device=dev))
+    with pytest.raises(smmo.SmmoError) as e:
+        heap.sync()
+    assert e.value.status == smmo.SMMO_ENOMEM
+    smmo.smmo_clear_error(heap.h)
+    assert heap.stats().live_objects[0] == 0
+    clean(heap)
+    # exactly full is fine
+    heap.new("A", 10 * 64, key=torch.arange(640, dtype=torch.int32, device=dev))
+    heap.sync()
+    assert heap.stats().free_blocks == 0
+    clean(heap)
+    # the host rejects more objects than slots outright
+    with pytest.raises(smmo.SmmoError) as e:
+        heap.new("A", 10 * 64 + 1)
+    assert e.value.status == smmo.SMMO_ENOMEM
+
+
+def test_device_oom_is_reported_not_hung(dev):
+    import torch
+
+    heap = smmo.Heap(ALL, blocks=20)
+    n = 64 * 10
+    heap.new("A", n, key=torch.arange(n, dtype=torch.int32, device=dev))
+    heap.do("A", "test.spawn", smmo.smmo_spawn_args(heap.cls["B"], 1, 0, 4, 1, 0))
+    with pytest.raises(smmo.SmmoError) as e:
+        heap.sync()
+    assert e.value.status in (smmo.SMMO_ENOMEM, smmo.SMMO_EDEVICE)
+    smmo.smmo_clear_error(heap.h)
+    st = heap.stats()
+    assert st.free_blocks == 0 and 0 < st.live_objects[1] <= 64 * 10
+    assert st.live_objects[0] == n
+    clean(heap)
+
+
+def test_gather_capacity_and_bad_method_binding(dev):
+    import torch
+
+    heap = smmo.Heap(ALL, blocks=64)
+    heap.new("A", 300, key=torch.arange(300, dtype=torch.int32, device=dev))
+    g = heap.gather("A", ["key"], capacity=100)
+    assert g["count"] == 300 and g["key"].numel() == 100
+    assert len(set(g["key"].cpu().numpy().tolist())) == 100
+    # class B has no "key"-less problem but lacks the spring fields
+    with pytest.raises(smmo.SmmoError) as e:
+        heap.do("B", "spring.force", smmo.smmo_spring_args(0, 1, 1e-3, 0.3))
+    assert e.value.status == smmo.SMMO_EINVAL
+    with pytest.raises(smmo.SmmoError):
+        smmo.smmo_parallel_do(heap.h, heap.cls["A"], smmo.smmo_method_id("test.axpy"),
+                              smmo.smmo_destroy_if_args(1, 0))   # wrong argument struct size

@@ -1,0 +1,105 @@
+"""GPU parity of the spring-mass mesh (thesis Ch.7 "structure", compute
+steps) against the float64 oracle.
+
+Per checked step k the GPU's float32 state (positions, velocities, live
+springs, adjacency) is read back; the oracle takes those values and runs
+one step.  Topology is integer work and must match exactly: the set of live
+springs and every adjacency slot (the break decision is taken in float32 on
+both sides, in the same operation order).  Float results must match within
+1e-5 of their conditioning scale (spring force: k (l + L0); node velocity
+and position: |v| + dt S_F / m and |x| + dt S_v, S_F = sum of the scales of
+the attached springs).
+"""
+
+import numpy as np
+import pytest
+
+from inputs import spring_mesh
+from oracle import spring_steps
+from paper_1908_05845_amd.sims import SpringSim
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+TOPO = ("a", "b", "k", "L0", "slot_a", "slot_b")
+
+
+def state_dict(mesh, st):
+    d = {k: mesh[k] for k in TOPO}
+    for k in ("x", "y", "vx", "vy", "m", "adj", "adj_is_b", "alive", "fx", "fy"):
+        d[k] = st[k]
+    return d
+
+
+def check_step(sim, mesh, dt, limit):
+    st = sim.read()
+    assert (st["adj"] != -2).all(), "adjacency names a dead spring"
+    ref = spring_steps(state_dict(mesh, st), dt, limit, 1, alive=st["alive"], fx=st["fx"], fy=st["fy"])
+    sim.step(1)
+    s1 = sim.read()
+    assert np.array_equal(s1["alive"], ref["alive"]), int(np.sum(s1["alive"] != ref["alive"]))
+    assert np.array_equal(s1["adj"], ref["adj"])
+    assert np.array_equal(s1["adj_is_b"][s1["adj"] >= 0], np.asarray(mesh["adj_is_b"])[s1["adj"] >= 0])
+    al = ref["alive"].astype(bool)
+    for key in ("fx", "fy"):
+        err = np.abs(s1[key][al] - ref[key][al])
+        assert np.all(err <= TOL * ref["sf"][al]), (key, float(np.max(err / ref["sf"][al])))
+    for key, sc in (("vx", "svx"), ("vy", "svy"), ("x", "sx"), ("y", "sy")):
+        err = np.abs(s1[key] - ref[key])
+        assert np.all(err <= TOL * ref[sc]), (key, float(np.max(err / ref[sc])))
+    return ref["nbroken"]
+
+
+def test_small_mesh_with_breaking_every_step(dev):
+    print("spring 40x30 breaking", flush=True)
+    mesh = spring_mesh(40, 30, seed=21, v_sigma=1.0)
+    dt, limit = 1e-4, 0.3
+    sim = SpringSim(mesh, dt, limit)
+    broken = 0
+    for _ in range(150):
+        broken += check_step(sim, mesh, dt, limit)
+    assert broken > 20, broken       # the run exercises destruction
+    inv = sim.heap.invariants()
+    assert inv.hierarchy_violations == 0 and inv.state_violations == 0 and inv.active_violations == 0
+    assert inv.type_violations == 0 and inv.empty_allocated == 0
+
+
+@pytest.mark.parametrize("W,H", [(1, 2), (2, 2), (9, 7), (65, 3)])
+def test_ragged_meshes(dev, W, H):
+    print("spring %dx%d" % (W, H), flush=True)
+    mesh = spring_mesh(W, H, seed=W * 7 + H, v_sigma=2.0)
+    sim = SpringSim(mesh, 1e-4, 0.05)
+    for _ in range(40):
+        check_step(sim, mesh, 1e-4, 0.05)
+
+
+def test_everything_breaks(dev):
+    mesh = spring_mesh(12, 12, seed=3, v_sigma=20.0)
+    sim = SpringSim(mesh, 1e-3, 0.01)
+    for _ in range(30):
+        check_step(sim, mesh, 1e-3, 0.01)
+    st = sim.heap.stats()
+    spr = sim.heap.cls["Spring"]
+    assert st.live_objects[spr] == int(sim.read()["alive"].sum())
+
+
+def test_config_1000x1000_checked_steps(dev):
+    print("spring 1000x1000", flush=True)
+    mesh = spring_mesh(1000, 1000)
+    assert mesh["N"] == 1_000_000 and mesh["S"] == 2_996_001
+    dt, limit = 1e-5, 0.3
+    sim = SpringSim(mesh, dt, limit)
+    checks = (0, 1, 10, 1000, 3000, 9999)
+    step = 0
+    broken = 0
+    while step <= checks[-1]:
+        if step in checks:
+            print("  check step", step, flush=True)
+            broken += check_step(sim, mesh, dt, limit)
+        else:
+            sim.step(1)
+        step += 1
+    print("  springs broken at checked steps:", broken, flush=True)
+    st = sim.read()
+    n_alive = int(st["alive"].sum())
+    assert sim.heap.stats().live_objects[sim.heap.cls["Spring"]] == n_alive

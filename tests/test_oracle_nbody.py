@@ -10,7 +10,7 @@ import math
 
 import numpy as np
 
-from oracle import nbody_force_at, nbody_steps
+from oracle import nbody_force_at, nbody_steps, nbody_update
 
 
 def test_single_body_feels_no_force():
@@ -102,3 +102,17 @@ def test_sampled_force_equals_full_step_force():
     fx, fy, sx, sy = nbody_force_at(x, y, m, 1.0 / n, 1e-3, idx)
     assert np.array_equal(fx, r["fx"][idx]) and np.array_equal(fy, r["fy"][idx])
     assert np.all(sx >= np.abs(fx)) and np.all(sy >= np.abs(fy))
+
+
+def test_update_alone_matches_full_step():
+    rng = np.random.default_rng(6)
+    n = 50
+    x, y, m = rng.random(n), rng.random(n), 0.5 + rng.random(n)
+    vx, vy = 0.1 * rng.standard_normal(n), 0.1 * rng.standard_normal(n)
+    full = nbody_steps(x, y, vx, vy, m, G=0.3, eps=1e-2, dt=1e-3)
+    up = nbody_update(x, y, vx, vy, full["fx"], full["fy"], m, dt=1e-3)
+    for k in ("x", "y", "vx", "vy"):
+        assert np.array_equal(up[k], full[k])
+    # worked example: f = 2, m = 4, dt = 0.5 -> v = 0.25, x = 1 + 0.125
+    r = nbody_update([1.0], [0.0], [0.0], [0.0], [2.0], [0.0], [4.0], dt=0.5)
+    assert r["vx"][0] == 0.25 and r["x"][0] == 1.125
