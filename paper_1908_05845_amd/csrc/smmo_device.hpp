@@ -249,15 +249,19 @@ __device__ __forceinline__ int64_t find_set(const HeapView &h, uint32_t bmid, ui
 // free block is found (the thesis spins forever here; we report exhaustion).
 __device__ __forceinline__ int64_t claim_free_block(const HeapView &h, uint32_t seed)
 {
-    for (uint32_t t = 0; t < 4096u; ++t) {
+    uint32_t misses = 0;
+    for (uint32_t t = 0; t < h.spin_limit; ++t) {
         const int64_t b = find_set(h, BM_FREE, seed + t * 0x632BE5ABu);
         if (b < 0) {
-            // spurious failures happen while another thread is between two
-            // levels; give it time, then conclude the heap is exhausted
-            if (t >= 256u) return -1;
-            __builtin_amdgcn_s_sleep(2);
+            // A search can miss while another thread is between two levels
+            // of the hierarchy; only a run of consecutive misses means the
+            // heap is exhausted.  Races lost to other claimers (below) are
+            // progress of others and do not count.
+            if (++misses > 128u) return -1;
+            __builtin_amdgcn_s_sleep(4);
             continue;
         }
+        misses = 0;
         uint64_t *w = h.bm_word(BM_FREE, 0, (uint32_t)b >> 6);
         const uint64_t bit = 1ull << (b & 63);
         const uint64_t prev = aand(w, ~bit);

@@ -197,7 +197,7 @@ class SpringSim:
         gn = self.heap.gather("Node", ["id", "x", "y", "vx", "vy", "m", "adj"])
         S = self.S_all
         sid = _np(gs["id"])
-        sh = _np(gs["handle"]).astype(np.int64)
+        sh = _np(gs["_handle"]).astype(np.int64)
         alive = np.zeros(S, np.uint8)
         alive[sid] = 1
         fx = np.zeros(S, np.float32)
@@ -220,5 +220,5 @@ class SpringSim:
         adj = np.where(used, np.where(found, sid_sorted[pos] if sid_sorted.size else -2, -2), -1)
         out["adj"] = adj.astype(np.int32)
         out["adj_is_b"] = np.where(used, raw >> 31, 0).astype(np.uint8)
-        out["node_handles_by_id"] = _np(gn["handle"])[order]
+        out["node_handles_by_id"] = _np(gn["_handle"])[order]
         return out

@@ -382,7 +382,10 @@ class Heap:
         self._keep = [handles]
 
     def gather(self, cname: str, names=None, capacity: int | None = None, stream=None):
-        """Dense copies of fields of the live objects (+ 'handle'), synchronizing."""
+        """Dense copies of fields of the live objects, synchronizing.
+
+        Returns {field: tensor, '_handle': handles, '_count': number of live
+        objects (may exceed capacity)}."""
         t = self.torch
         if names is None:
             names = list(self.fields[cname].keys())
@@ -399,11 +402,11 @@ class Heap:
         self.sync()
         n = int(self._count.item())
         k = min(n, capacity)
-        res = {"handle": hd[:k]}
+        res = {"_handle": hd[:k]}
         for fname, o in zip(names, outs):
             cnt = self.fields[cname][fname][2]
             res[fname] = o[: k * cnt].reshape(k, cnt) if cnt > 1 else o[:k]
-        res["count"] = n
+        res["_count"] = n
         return res
 
     def sync(self):
