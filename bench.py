@@ -1,0 +1,340 @@
+"""Benchmark of SMMO execution on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload spring|gol|nbody]
+
+Default workload: the spring-mass structure of 1,000,000 nodes and 2,996,001
+springs (1000 x 1000 jittered grid, stiffness log-uniform in [1e2, 1e4],
+rest length = initial distance, float32, dt 1e-5, springs deleted past
+strain 0.3).  One step = one pass of the hot path over the whole mesh:
+parallel_do(Spring, spring.force) (Hooke force, breaking springs delete
+themselves) and parallel_do(Node, spring.node_update).  The default run is
+the workload's 10,000 steps after W warm-up steps, all inputs resident in
+HBM before the timed region.
+
+Prints one JSON line: object-method updates per second (live objects
+processed by the do-alls, summed over launches, per second), the dominant
+kernel's roofline (algorithmic bytes per launch / HIP-event-timed launch
+duration, against 8 TB/s), and the CPU oracle timed on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "object-method updates/sec + HBM GB/s % peak; batched & adjoint vs plain"
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
+COUNTERS_FILE = os.path.join(HERE, "profiles", "spring_counters.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", choices=["spring", "gol", "nbody"], default="spring")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-steps", type=int, default=200,
+                    help="steps timed per kernel with HIP events for the roofline")
+    ap.add_argument("--cpu-steps", type=int, default=None)
+    return ap.parse_args()
+
+
+def events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_1908_05845_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(fn.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, launches_bytes):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if there is none for this kernel or the sources changed since."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_hash") != kernel_source_hash():
+        return None
+    k = c.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+# ------------------------------------------------------------------ spring --
+def bench_spring(args, torch):
+    import numpy as np
+
+    from inputs import spring_mesh
+    from paper_1908_05845_amd import smmo
+    from paper_1908_05845_amd.sims import SpringSim
+
+    W = H = 1000
+    dt, limit = 1e-5, 0.3
+    steps = 10_000 if args.steps is None else args.steps
+    warmup = 20 if args.warmup is None else args.warmup
+    mesh = spring_mesh(W, H)
+    sim = SpringSim(mesh, dt, limit)
+    heap = sim.heap
+    lib = smmo.load_library()
+    stream = torch.cuda.current_stream().cuda_stream
+    hp, cs, cn = heap.h, heap.cls["Spring"], heap.cls["Node"]
+    mf, mn = sim.m_force, sim.m_node
+    argp = smmo.C.byref(sim.args)
+    asz = smmo.C.sizeof(sim.args)
+
+    def step():
+        lib.smmo_parallel_do(hp, cs, mf, argp, asz, stream)
+        lib.smmo_parallel_do(hp, cn, mn, argp, asz, stream)
+
+    for _ in range(warmup):
+        step()
+    heap.sync()
+    st0 = heap.stats()
+    live0 = (st0.live_objects[cs], st0.live_objects[cn])
+
+    torch.cuda.synchronize()
+    e0, e1 = events(torch, 2)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    heap.sync()
+    st1 = heap.stats()
+    live1 = (st1.live_objects[cs], st1.live_objects[cn])
+    # live objects processed per step: springs alive at the start of each
+    # force pass (breaks during the run counted at the mean) plus all nodes
+    springs_mean = 0.5 * (live0[0] + live1[0])
+    updates = steps * (springs_mean + live0[1])
+
+    # per-kernel durations with HIP events on the launch stream
+    ks = args.kernel_steps
+    ev = events(torch, 3 * ks)
+    torch.cuda.synchronize()
+    for i in range(ks):
+        ev[3 * i].record()
+        lib.smmo_parallel_do(hp, cs, mf, argp, asz, stream)
+        ev[3 * i + 1].record()
+        lib.smmo_parallel_do(hp, cn, mn, argp, asz, stream)
+        ev[3 * i + 2].record()
+    torch.cuda.synchronize()
+    heap.sync()
+    t_force = sum(ev[3 * i].elapsed_time(ev[3 * i + 1]) for i in range(ks)) / ks * 1e-3
+    t_node = sum(ev[3 * i + 1].elapsed_time(ev[3 * i + 2]) for i in range(ks)) / ks * 1e-3
+    st2 = heap.stats()
+    S = 0.5 * (live1[0] + st2.live_objects[cs])
+    N = live0[1]
+    # algorithmic bytes (design minimum, each byte once):
+    #   spring.force per live spring: a, b, k, L0 (16) + x, y of both nodes
+    #     (16) + fx, fy written (8) = 40 B
+    #   spring.node_update per node: adjacency (32) + x, y, vx, vy, m (20) +
+    #     x, y, vx, vy written (16) = 68 B, plus fx, fy (8) per attached spring
+    bytes_force = 40.0 * S
+    bytes_node = 68.0 * N + 16.0 * S
+    kernels = {
+        "spring.force": {"avg_us": t_force * 1e6, "bytes": bytes_force,
+                         "gbs": bytes_force / t_force / 1e9},
+        "spring.node_update": {"avg_us": t_node * 1e6, "bytes": bytes_node,
+                               "gbs": bytes_node / t_node / 1e9},
+    }
+    dom = "spring.force" if t_force >= t_node else "spring.node_update"
+    kd = kernels[dom]
+    traffic = traffic_for(dom, kd["bytes"])
+    step_bytes = bytes_force + bytes_node
+    res = {
+        "value": updates / (ms * 1e-3),
+        "unit": "updates/s",
+        "ms_per_step": ms / steps,
+        "dtype": "f32",
+        "config": {"workload": "spring-mass structure, 1000x1000 jittered grid: 1,000,000 Node and "
+                               "2,996,001 Spring objects, dt 1e-5, strain limit 0.3",
+                   "nodes": int(N), "springs_at_start": int(live0[0]), "springs_at_end": int(live1[0]),
+                   "steps_total_incl_warmup": warmup + steps, "heap_blocks": heap.blocks,
+                   "block_bytes": heap.block_bytes},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": kd["bytes"], "avg_launch_us": kd["avg_us"]},
+        "step_hbm": {"algorithmic_bytes": step_bytes, "gbs": step_bytes / (ms * 1e-3 / steps) / 1e9,
+                     "frac": step_bytes / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS},
+        "kernels": kernels,
+        "host_wall_s": wall,
+        "device_error": st2.device_error,
+    }
+
+    def cpu_leg():
+        from oracle import spring_steps
+
+        k = args.cpu_steps or 50
+        t = time.perf_counter()
+        r = spring_steps(mesh, dt, limit, k)
+        el = time.perf_counter() - t
+        objs = k * (mesh["N"] + 0.5 * (mesh["S"] + int(r["alive"].sum())))
+        return {"value": objs / el, "unit": "updates/s", "cores": 1, "kind": "oracle",
+                "sample": "first %d steps of the same 1000x1000 mesh from its initial state, one "
+                          "call of the float64 oracle (load, steps, unload), %.1f s" % (k, el)}
+
+    return res, cpu_leg, steps, warmup
+
+
+# --------------------------------------------------------------------- gol --
+def bench_gol(args, torch):
+    from inputs import gol_init
+    from paper_1908_05845_amd.sims import GolSim
+
+    W = H = 256
+    steps = 100 if args.steps is None else args.steps
+    warmup = 5 if args.warmup is None else args.warmup
+    init = gol_init(W, H)
+    sim = GolSim(W, H, init)
+    for _ in range(warmup):
+        sim.step(1)
+    sim.heap.sync()
+    cls_a = sim.heap.cls["Alive"]
+    alive_before = sim.heap.stats().live_objects[cls_a]
+    torch.cuda.synchronize()
+    e0, e1 = events(torch, 2)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sim.heap.sync()
+    alive_after = sim.heap.stats().live_objects[cls_a]
+    updates = steps * (2 * W * H + 0.5 * (alive_before + alive_after))
+    res = {"value": updates / (ms * 1e-3), "unit": "updates/s", "ms_per_step": ms / steps, "dtype": "u8/i32",
+           "config": {"workload": "Game of Life in SMMO form, 256x256 torus, 25% initial density"},
+           "roofline": None}
+
+    def cpu_leg():
+        from oracle import GolWorld
+
+        w = GolWorld(W, H, init)
+        t = time.perf_counter()
+        w.step(steps)
+        el = time.perf_counter() - t
+        return {"value": updates / el, "unit": "updates/s", "cores": 1, "kind": "oracle",
+                "sample": "%d generations from the initial state, %.2f s" % (steps, el)}
+
+    return res, cpu_leg, steps, warmup
+
+
+# ------------------------------------------------------------------- nbody --
+def bench_nbody(args, torch):
+    from inputs import nbody_init
+    from paper_1908_05845_amd.sims import NbodySim
+
+    n = 65536
+    G, eps, dt = 1.0 / n, 1e-3, 1e-4
+    steps = 50 if args.steps is None else args.steps
+    warmup = 2 if args.warmup is None else args.warmup
+    st = nbody_init(n)
+    sim = NbodySim(st, G, eps, dt)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    ev = events(torch, 3 * steps)
+    for i in range(steps):
+        ev[3 * i].record()
+        sim.force()
+        ev[3 * i + 1].record()
+        sim.update()
+        ev[3 * i + 2].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[-1])
+    tf = sum(ev[3 * i].elapsed_time(ev[3 * i + 1]) for i in range(steps)) / steps * 1e-3
+    pairs = float(n) * n
+    flop = 20.0 * pairs
+    res = {"value": steps * 2 * n / (ms * 1e-3), "unit": "updates/s", "ms_per_step": ms / steps, "dtype": "f32",
+           "config": {"workload": "n-body, 65,536 bodies, all pairs, softening 1e-3, dt 1e-4"},
+           "roofline": {"bound": "alu", "kernel": "nbody.force", "achieved": flop / tf / 1e12,
+                        "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": flop / tf / 1e12 / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                        "pairs_per_s": pairs / tf, "avg_launch_us": tf * 1e6}}
+
+    def cpu_leg():
+        from oracle import nbody_force_at
+
+        import numpy as np
+        k = 2048
+        t = time.perf_counter()
+        nbody_force_at(st["x"], st["y"], st["m"], G, eps, np.arange(k))
+        el = time.perf_counter() - t
+        return {"value": k / el * 2, "unit": "updates/s", "cores": 1, "kind": "oracle",
+                "sample": "compute_force of %d of the 65,536 bodies (all pairs), %.1f s" % (k, el)}
+
+    return res, cpu_leg, steps, warmup
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_1908_05845_amd import smmo
+
+    smmo.load_library()
+    fn = {"spring": bench_spring, "gol": bench_gol, "nbody": bench_nbody}[args.workload]
+    res, cpu_leg, steps, warmup = fn(args, torch)
+    cpu = None if args.no_cpu_baseline else cpu_leg()
+    if cpu is not None:
+        cpu["cpu_model"] = _cpu_model()
+        cpu["host_nproc"] = os.cpu_count()
+    line = {
+        "metric": METRIC,
+        "value": res["value"],
+        "unit": res["unit"],
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": res["dtype"],
+        "data": "synthetic",
+        "config": res["config"],
+        "roofline": res["roofline"],
+        "cpu_baseline": cpu,
+    }
+    for k in ("step_hbm", "kernels", "device_error"):
+        if k in res:
+            line[k] = res[k]
+    print(json.dumps(line), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()
