@@ -39,9 +39,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["spring", "gol", "nbody"], default="spring")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-steps", type=int, default=200,
+    ap.add_argument("--kernel-steps", type=int, default=50,
                     help="steps timed per kernel with HIP events for the roofline")
     ap.add_argument("--cpu-steps", type=int, default=None)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with three plain 512 MiB device copies (reference for rocprofv3 byte counters)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarize two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this bench into "
+                         "profiles/spring_counters.json and print a text summary; needs no GPU")
+    ap.add_argument("--graph-steps", type=int, default=50,
+                    help="steps per captured HIP graph in the timed region (0 = eager launches)")
     return ap.parse_args()
 
 
@@ -97,26 +104,89 @@ def bench_spring(args, torch):
     argp = smmo.C.byref(sim.args)
     asz = smmo.C.sizeof(sim.args)
 
-    def step():
-        lib.smmo_parallel_do(hp, cs, mf, argp, asz, stream)
-        lib.smmo_parallel_do(hp, cn, mn, argp, asz, stream)
+    def step(st=stream):
+        lib.smmo_parallel_do(hp, cs, mf, argp, asz, st)
+        lib.smmo_parallel_do(hp, cn, mn, argp, asz, st)
 
     for _ in range(warmup):
         step()
     heap.sync()
+    # eager reference: host-launched steps (reported, not the value)
+    eager_n = min(1000, steps)
+    torch.cuda.synchronize()
+    ee = events(torch, 2)
+    t0 = time.perf_counter()
+    ee[0].record()
+    for _ in range(eager_n):
+        step()
+    ee[1].record()
+    torch.cuda.synchronize()
+    eager_wall = time.perf_counter() - t0
+    eager_ms = ee[0].elapsed_time(ee[1]) / max(eager_n, 1)
+    warmup += eager_n
+    # the timed region replays a HIP graph of G steps: the method kernels read
+    # the block lists and their lengths on the device, so a captured step is
+    # the same work as a launched one, without the host launch cost
+    G = args.graph_steps
+    graph = None
+    if G > 0:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            cap = torch.cuda.current_stream().cuda_stream
+            for _ in range(G):
+                step(cap)
+        step()          # one launched step: the heap's last stream is ours again
+        warmup += 1
+        torch.cuda.synchronize()
+    heap.sync()
     st0 = heap.stats()
     live0 = (st0.live_objects[cs], st0.live_objects[cn])
 
-    torch.cuda.synchronize()
-    e0, e1 = events(torch, 2)
-    t0 = time.perf_counter()
-    e0.record()
-    for _ in range(steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
+    # kernel timing: `ks` back-to-back launches of each kernel between two HIP
+    # events on the launch stream, at mid-run (between the two timed halves).
+    # Repeated force passes are idempotent and the node passes run with dt = 0,
+    # so the simulation state is unchanged.
+    ks = args.kernel_steps
+    frozen = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit)
+    fp = smmo.C.byref(frozen)
+
+    def kernel_pass():
+        ev = events(torch, 3)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(ks):
+            lib.smmo_parallel_do(hp, cs, mf, fp, asz, stream)
+        ev[1].record()
+        for _ in range(ks):
+            lib.smmo_parallel_do(hp, cn, mn, fp, asz, stream)
+        ev[2].record()
+        torch.cuda.synchronize()
+        st = heap.stats()
+        return (ev[0].elapsed_time(ev[1]) / ks * 1e-3, ev[1].elapsed_time(ev[2]) / ks * 1e-3,
+                st.live_objects[cs])
+
+    half = steps // 2
+    ms = 0.0
+    wall = 0.0
+    for part, n in enumerate((half, steps - half)):
+        torch.cuda.synchronize()
+        e0, e1 = events(torch, 2)
+        t0 = time.perf_counter()
+        e0.record()
+        if graph is not None:
+            for _ in range(n // G):
+                graph.replay()
+            for _ in range(n % G):
+                step()
+        else:
+            for _ in range(n):
+                step()
+        e1.record()
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        ms += e0.elapsed_time(e1)
+        if part == 0:
+            t_force, t_node, s_mid = kernel_pass()
     heap.sync()
     st1 = heap.stats()
     live1 = (st1.live_objects[cs], st1.live_objects[cn])
@@ -124,23 +194,8 @@ def bench_spring(args, torch):
     # force pass (breaks during the run counted at the mean) plus all nodes
     springs_mean = 0.5 * (live0[0] + live1[0])
     updates = steps * (springs_mean + live0[1])
-
-    # per-kernel durations with HIP events on the launch stream
-    ks = args.kernel_steps
-    ev = events(torch, 3 * ks)
-    torch.cuda.synchronize()
-    for i in range(ks):
-        ev[3 * i].record()
-        lib.smmo_parallel_do(hp, cs, mf, argp, asz, stream)
-        ev[3 * i + 1].record()
-        lib.smmo_parallel_do(hp, cn, mn, argp, asz, stream)
-        ev[3 * i + 2].record()
-    torch.cuda.synchronize()
-    heap.sync()
-    t_force = sum(ev[3 * i].elapsed_time(ev[3 * i + 1]) for i in range(ks)) / ks * 1e-3
-    t_node = sum(ev[3 * i + 1].elapsed_time(ev[3 * i + 2]) for i in range(ks)) / ks * 1e-3
-    st2 = heap.stats()
-    S = 0.5 * (live1[0] + st2.live_objects[cs])
+    st2 = st1
+    S = float(s_mid)
     N = live0[1]
     # algorithmic bytes (design minimum, each byte once):
     #   spring.force per live spring: a, b, k, L0 (16) + x, y of both nodes
@@ -175,7 +230,9 @@ def bench_spring(args, torch):
         "step_hbm": {"algorithmic_bytes": step_bytes, "gbs": step_bytes / (ms * 1e-3 / steps) / 1e9,
                      "frac": step_bytes / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS},
         "kernels": kernels,
-        "host_wall_s": wall,
+        "launch": {"mode": "hip graph of %d steps" % G if graph is not None else "eager",
+                   "timed_host_wall_s": wall, "eager_ms_per_step": eager_ms,
+                   "eager_host_ms_per_step": eager_wall / max(eager_n, 1) * 1e3},
         "device_error": st2.device_error,
     }
 
@@ -282,8 +339,73 @@ def bench_nbody(args, torch):
     return res, cpu_leg, steps, warmup
 
 
+COPY_BYTES = 512 << 20
+KERNEL_KEYS = {"spring.force": "k_spring_force", "spring.node_update": "k_spring_node"}
+
+
+def calibrate_copy(torch):
+    """Three plain device-to-device copies of COPY_BYTES (reads and writes
+    COPY_BYTES each): the reference that scales rocprofv3 byte counters."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def _read_counter_csv(d):
+    import csv
+    import glob
+
+    rows = []
+    for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(fn) as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def summarize_counters(fetch_dir, write_dir):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the spring kernels,
+    scaled by the ratio of true to counted bytes of the calibration copy."""
+    out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES, "kernels": {}}
+    lines = []
+    factor = {}
+    per = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _read_counter_csv(d) if r.get("Counter_Name") == counter]
+        if not rows:
+            raise SystemExit("no %s rows under %s" % (counter, d))
+        copies = [r for r in rows if "copy" in r["Kernel_Name"].lower()]
+        big = max(int(r["Grid_Size"]) for r in copies)
+        cal = [float(r["Counter_Value"]) * 1024.0 for r in copies if int(r["Grid_Size"]) == big]
+        factor[counter] = COPY_BYTES / (sum(cal) / len(cal))
+        for name, key in KERNEL_KEYS.items():
+            vals = [float(r["Counter_Value"]) * 1024.0 for r in rows if key in r["Kernel_Name"]]
+            per.setdefault(name, {})[counter] = (sum(vals) / len(vals), len(vals))
+    for name, d in per.items():
+        fetch = d["FETCH_SIZE"][0] * factor["FETCH_SIZE"]
+        write = d["WRITE_SIZE"][0] * factor["WRITE_SIZE"]
+        out["kernels"][name] = {"fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+                                "hbm_bytes_per_launch": fetch + write, "dispatches": d["FETCH_SIZE"][1]}
+        lines.append("| %s | %d | %.1f MB | %.1f MB | %.1f MB |" % (
+            name, d["FETCH_SIZE"][1], fetch / 1e6, write / 1e6, (fetch + write) / 1e6))
+    out["copy_factor"] = factor
+    path = os.path.join(HERE, "profiles", "spring_counters.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("copy calibration factor (true bytes / counted bytes): FETCH %.4f  WRITE %.4f"
+          % (factor["FETCH_SIZE"], factor["WRITE_SIZE"]))
+    print("| kernel | dispatches | FETCH (scaled) | WRITE (scaled) | HBM bytes / launch |")
+    print("|---|---|---|---|---|")
+    print("\n".join(lines))
+    print("written", path)
+
+
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)"
               % args.gpus, file=sys.stderr)
@@ -319,10 +441,12 @@ def main():
         "roofline": res["roofline"],
         "cpu_baseline": cpu,
     }
-    for k in ("step_hbm", "kernels", "device_error"):
+    for k in ("step_hbm", "kernels", "launch", "device_error"):
         if k in res:
             line[k] = res[k]
     print(json.dumps(line), flush=True)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
 
 
 def _cpu_model():

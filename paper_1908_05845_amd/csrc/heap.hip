@@ -593,7 +593,7 @@ smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStre
 
 uint32_t method_grid(const smmo_heap *h, uint32_t cls)
 {
-    uint64_t waves = h->cfg.grid_waves ? h->cfg.grid_waves : 16ull * h->cu_count;
+    uint64_t waves = h->cfg.grid_waves ? h->cfg.grid_waves : 64ull * h->cu_count;
     waves = std::min<uint64_t>(waves, std::max<uint64_t>(1, h->ub_blocks[cls]));
     return (uint32_t)((waves + 3) / 4);
 }

@@ -45,6 +45,9 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // superset of the class's blocks.  bitmap = the iteration bitmap (snapshot of
 // the allocation bitmap taken by the enumeration) or the allocation bitmap,
 // which is the same as long as the method creates no object of its own class.
+// Within one launch a block's type and (outside snapshot mode) its bitmap
+// change only through the wavefront that processes it, so plain loads are
+// enough.  The next R entry is fetched one iteration ahead.
 template <class F>
 __device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, bool snapshot, F &&f)
 {
@@ -52,11 +55,18 @@ __device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, 
     const uint32_t *R = h.R + (uint64_t)cls * h.M;
     const uint32_t wpg = blockDim.x >> 6;
     const uint32_t nw = gridDim.x * wpg;
-    for (uint32_t i = xcd_logical_wg() * wpg + (threadIdx.x >> 6); i < r; i += nw) {
-        const uint32_t bid = __builtin_amdgcn_readfirstlane(R[i]);
-        if (__builtin_amdgcn_readfirstlane(ald32(h.type + bid)) != cls) continue;
-        const uint64_t bm = uniform64(snapshot ? h.iter_bm[bid] : ald(h.alloc_bm + bid));
-        f(bid, bm);
+    uint32_t i = xcd_logical_wg() * wpg + (threadIdx.x >> 6);
+    if (i >= r) return;
+    uint32_t bid = __builtin_amdgcn_readfirstlane(R[i]);
+    for (;;) {
+        const uint32_t in = i + nw;
+        const uint32_t bnext = __builtin_amdgcn_readfirstlane(in < r ? R[in] : 0u);
+        const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
+        const uint64_t bm = uniform64(snapshot ? h.iter_bm[bid] : h.alloc_bm[bid]);
+        if (t == cls) f(bid, bm);
+        if (in >= r) break;
+        i = in;
+        bid = bnext;
     }
 }
 
@@ -76,6 +86,31 @@ smmo_status launched(const char *what)
 {
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SMMO_OK : hip_fail(e, what);
+}
+
+// Kernel parameters for (method tag, class, argument struct), bound by
+// `bind` on the first launch and taken from the heap's cache afterwards.
+template <class K, class A, class Bind>
+smmo_status cached_bind(smmo_heap *h, const void *tag, uint32_t cls, const A &a, K &k, Bind &&bind)
+{
+    static_assert(sizeof(A) <= sizeof(smmo_bind_slot::args) && sizeof(K) <= sizeof(smmo_bind_slot::k),
+                  "bind cache slot too small");
+    for (smmo_bind_slot &sl : h->bind_cache)
+        if (sl.method == tag && sl.cls == cls && sl.nargs == sizeof(A) && sl.nk == sizeof(K) &&
+            memcmp(sl.args, &a, sizeof(A)) == 0) {
+            memcpy(&k, sl.k, sizeof(K));
+            return SMMO_OK;
+        }
+    smmo_status s = bind();
+    if (s) return s;
+    smmo_bind_slot &sl = h->bind_cache[h->bind_next++ % (sizeof(h->bind_cache) / sizeof(h->bind_cache[0]))];
+    sl.method = tag;
+    sl.cls = cls;
+    sl.nargs = sizeof(A);
+    sl.nk = sizeof(K);
+    memcpy(sl.args, &a, sizeof(A));
+    memcpy(sl.k, &k, sizeof(K));
+    return SMMO_OK;
 }
 
 #define BIND(cls, name, dt, cnt, off, stride)                                              \
@@ -184,7 +219,8 @@ smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     smmo_gol_args a;
     memcpy(&a, args, sizeof a);
     GolK k;
-    smmo_status s = bind_gol(h, a, k);
+    smmo_status s = cached_bind(h, (const void *)&launch_gol<Which>, cls, a, k,
+                                [&] { return bind_gol(h, a, k); });
     if (s) return s;
     const uint32_t want = Which == 1 ? a.alive_class : a.cell_class;
     if (cls != want) return fail(SMMO_EINVAL, "gol: method runs on a different class");
@@ -322,7 +358,8 @@ smmo_status launch_nbody_force(smmo_heap *h, uint32_t cls, const void *args, hip
     smmo_nbody_args a;
     memcpy(&a, args, sizeof a);
     NbodyK k;
-    smmo_status s = bind_nbody(h, cls, a, k);
+    smmo_status s = cached_bind(h, (const void *)&launch_nbody_force, cls, a, k,
+                                [&] { return bind_nbody(h, cls, a, k); });
     if (s) return s;
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     const uint32_t grid = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(1, h->ub_blocks[cls]), 8192);
@@ -338,7 +375,8 @@ smmo_status launch_nbody_update(smmo_heap *h, uint32_t cls, const void *args, hi
     smmo_nbody_args a;
     memcpy(&a, args, sizeof a);
     NbodyK k;
-    smmo_status s = bind_nbody(h, cls, a, k);
+    smmo_status s = cached_bind(h, (const void *)&launch_nbody_update, cls, a, k,
+                                [&] { return bind_nbody(h, cls, a, k); });
     if (s) return s;
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     hipLaunchKernelGGL(k_nbody_update, dim3(method_grid(h, cls)), dim3(256), 0, st, h->v, k);
@@ -374,27 +412,37 @@ __global__ __launch_bounds__(256) void k_spring_force(HeapView h, SpringK p)
     if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
-        bool brk = false;
-        if ((bm >> s) & 1) {
-            const uint32_t a = farr<uint32_t>(h, bid, p.s_a)[s];
-            const uint32_t b = farr<uint32_t>(h, bid, p.s_b)[s];
-            const float k = farr<float>(h, bid, p.s_k)[s];
-            const float L0 = farr<float>(h, bid, p.s_L0)[s];
-            const float xa = fref<float>(h, a, p.n_x), ya = fref<float>(h, a, p.n_y);
-            const float xb = fref<float>(h, b, p.n_x), yb = fref<float>(h, b, p.n_y);
-            const float dx = xb - xa, dy = yb - ya;
-            float l;
-            brk = spring_breaks(dx, dy, L0, p.limit, l);
-            if (brk) {
-                const uint32_t qa = farr<uint8_t>(h, bid, p.s_sa)[s];
-                const uint32_t qb = farr<uint8_t>(h, bid, p.s_sb)[s];
-                fref<uint32_t>(h, a, p.n_adj + qa * p.n_adj_stride) = kNull;
-                fref<uint32_t>(h, b, p.n_adj + qb * p.n_adj_stride) = kNull;
-            } else {
-                const float c = k * (l - L0) / l;
-                farr<float>(h, bid, p.s_fx)[s] = c * dx;
-                farr<float>(h, bid, p.s_fy)[s] = c * dy;
-            }
+        const bool live = (bm >> s) & 1;
+        // the block's own fields for all 64 slots (one contiguous run each);
+        // gathers through the node handles only for live slots
+        const uint32_t a = farr<uint32_t>(h, bid, p.s_a)[s];
+        const uint32_t b = farr<uint32_t>(h, bid, p.s_b)[s];
+        const float k = farr<float>(h, bid, p.s_k)[s];
+        const float L0 = farr<float>(h, bid, p.s_L0)[s];
+        float xa = 0.f, ya = 0.f, xb = 0.f, yb = 0.f;
+        if (live) {
+            xa = fref<float>(h, a, p.n_x);
+            ya = fref<float>(h, a, p.n_y);
+            xb = fref<float>(h, b, p.n_x);
+            yb = fref<float>(h, b, p.n_y);
+        }
+        const float dx = xb - xa, dy = yb - ya;
+        float l;
+        const bool brk = live && spring_breaks(dx, dy, L0, p.limit, l);
+        float fx = 0.f, fy = 0.f;
+        if (live && !brk) {
+            const float c = k * (l - L0) / l;
+            fx = c * dx;
+            fy = c * dy;
+        }
+        // full-width stores: dead and broken slots get 0, never read
+        farr<float>(h, bid, p.s_fx)[s] = fx;
+        farr<float>(h, bid, p.s_fy)[s] = fy;
+        if (brk) {
+            const uint32_t qa = farr<uint8_t>(h, bid, p.s_sa)[s];
+            const uint32_t qb = farr<uint8_t>(h, bid, p.s_sb)[s];
+            fref<uint32_t>(h, a, p.n_adj + qa * p.n_adj_stride) = kNull;
+            fref<uint32_t>(h, b, p.n_adj + qb * p.n_adj_stride) = kNull;
         }
         wave_release_own_block(h, p.spring_cls, bid, __ballot(brk));
     });
@@ -407,32 +455,45 @@ __global__ __launch_bounds__(256) void k_spring_node(HeapView h, SpringK p)
     if (heap_failed(h)) return;
     for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
-        if (!((bm >> s) & 1)) return;
+        const bool live = (bm >> s) & 1;
         uint32_t e[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) e[q] = farr<uint32_t>(h, bid, p.n_adj + q * p.n_adj_stride)[s];
+        const float m = farr<float>(h, bid, p.n_m)[s];
+        float x = farr<float>(h, bid, p.n_x)[s], y = farr<float>(h, bid, p.n_y)[s];
+        float vx = farr<float>(h, bid, p.n_vx)[s], vy = farr<float>(h, bid, p.n_vy)[s];
+        float gx[8], gy[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            gx[q] = 0.f;
+            gy[q] = 0.f;
+            if (live && e[q] != kNull) {
+                const uint32_t sh = e[q] & 0x7FFFFFFFu;
+                gx[q] = fref<float>(h, sh, p.s_fx);
+                gy[q] = fref<float>(h, sh, p.s_fy);
+            }
+        }
         float Fx = 0.f, Fy = 0.f;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             if (e[q] == kNull) continue;
-            const uint32_t sh = e[q] & 0x7FFFFFFFu;
-            const float fx = fref<float>(h, sh, p.s_fx), fy = fref<float>(h, sh, p.s_fy);
             if (e[q] >> 31) {
-                Fx -= fx;
-                Fy -= fy;
+                Fx -= gx[q];
+                Fy -= gy[q];
             } else {
-                Fx += fx;
-                Fy += fy;
+                Fx += gx[q];
+                Fy += gy[q];
             }
         }
-        const float m = farr<float>(h, bid, p.n_m)[s];
-        float vx = farr<float>(h, bid, p.n_vx)[s], vy = farr<float>(h, bid, p.n_vy)[s];
+        if (!live) return;
         vx += Fx / m * p.dt;
         vy += Fy / m * p.dt;
+        x += vx * p.dt;
+        y += vy * p.dt;
         farr<float>(h, bid, p.n_vx)[s] = vx;
         farr<float>(h, bid, p.n_vy)[s] = vy;
-        farr<float>(h, bid, p.n_x)[s] += vx * p.dt;
-        farr<float>(h, bid, p.n_y)[s] += vy * p.dt;
+        farr<float>(h, bid, p.n_x)[s] = x;
+        farr<float>(h, bid, p.n_y)[s] = y;
     });
 }
 
@@ -493,7 +554,8 @@ smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStrea
     smmo_spring_args a;
     memcpy(&a, args, sizeof a);
     SpringK k;
-    smmo_status s = bind_spring(h, a, k);
+    smmo_status s = cached_bind(h, (const void *)&launch_spring<Which>, cls, a, k,
+                                [&] { return bind_spring(h, a, k); });
     if (s) return s;
     if (cls != (Which == 1 ? a.node_class : a.spring_class))
         return fail(SMMO_EINVAL, "spring: method runs on a different class");

@@ -35,6 +35,18 @@ struct smmo_schema {
 
 enum RState : int { R_DIRTY = 0, R_VALID = 1 };
 
+// A method launch resolves its fields by name; the schema is frozen once a
+// heap exists, so the resolved kernel parameters are cached per
+// (method, class, argument bytes) to keep the host cost of a launch low.
+struct smmo_bind_slot {
+    const void *method = nullptr;
+    uint32_t cls = 0;
+    uint32_t nargs = 0;
+    uint32_t nk = 0;
+    alignas(8) unsigned char args[64];
+    alignas(8) unsigned char k[256];
+};
+
 struct smmo_heap {
     smmo_schema *schema = nullptr;
     smmo::HeapView v{};
@@ -47,6 +59,8 @@ struct smmo_heap {
     int rstate[SMMO_MAX_CLASSES] = {};
     uint64_t ub_blocks[SMMO_MAX_CLASSES] = {};   // upper bound of blocks per class
     uint32_t cu_count = 256;
+    smmo_bind_slot bind_cache[16];
+    uint32_t bind_next = 0;
 };
 
 namespace smmo {
