@@ -12,5 +12,6 @@ from .oracle import (  # noqa: F401
     nbody_force_at,
     nbody_update,
     spring_steps,
+    spring_adjoint,
     spring_breaks,
 )

@@ -57,6 +57,9 @@ def _load():
             lib.orc_spring_steps.restype = LL
             lib.orc_spring_steps.argtypes = [LL, P, P, P, P, P, P, P, LL, P, P, P, P, P, P,
                                              P, P, P, D, C.c_float, C.c_int, P, P, P, P, P]
+            lib.orc_spring_adjoint.restype = C.c_int
+            lib.orc_spring_adjoint.argtypes = [LL, P, P, P, P, P, P, P, LL, P, P, P, P, P, P, P, P,
+                                               D, C.c_int, C.c_int, P, P, P, P, P, P, P, P]
             lib.orc_spring_breaks.restype = C.c_int
             lib.orc_spring_breaks.argtypes = [D, D, D, D, D, C.c_float]
             _lib = lib
@@ -190,3 +193,34 @@ def spring_breaks(xa, ya, xb, yb, L0, thresh=0.3) -> bool:
     """The float32 break decision of one spring."""
     return bool(_load().orc_spring_breaks(float(xa), float(ya), float(xb), float(yb),
                                           float(L0), float(thresh)))
+
+
+def spring_adjoint(mesh: dict, dt: float, steps: int, every: int = 20, xhat=None, yhat=None):
+    """Reverse-mode gradients of L = 1/2 |x_T - xhat|^2 through `steps`
+    spring-mesh steps with breaking off (float64), checkpointing (x, v) every
+    `every` steps.  xhat defaults to the initial positions.  Returns dict with
+    loss, gk (dL/dk), gvx, gvy (dL/dv0), gx, gy (dL/dx0), xT, yT."""
+    lib = _load()
+    N = int(np.asarray(mesh["x"]).size)
+    S = int(np.asarray(mesh["a"]).size)
+    x, y, vx, vy, m = (_f64(mesh[k]) for k in ("x", "y", "vx", "vy", "m"))
+    adj = np.ascontiguousarray(mesh["adj"], dtype=np.int32).reshape(N, 8)
+    adjb = np.ascontiguousarray(mesh["adj_is_b"], dtype=np.uint8).reshape(N, 8)
+    a = np.ascontiguousarray(mesh["a"], dtype=np.int32)
+    b = np.ascontiguousarray(mesh["b"], dtype=np.int32)
+    kk = _f64(mesh["k"])
+    L0 = _f64(mesh["L0"])
+    sa = np.ascontiguousarray(mesh["slot_a"], dtype=np.int32)
+    sb = np.ascontiguousarray(mesh["slot_b"], dtype=np.int32)
+    xh = x.copy() if xhat is None else _f64(xhat)
+    yh = y.copy() if yhat is None else _f64(yhat)
+    gk = np.zeros(S)
+    gvx, gvy, gx, gy, xT, yT = (np.zeros(N) for _ in range(6))
+    loss = C.c_double()
+    rc = lib.orc_spring_adjoint(N, _p(x), _p(y), _p(vx), _p(vy), _p(m), _p(adj), _p(adjb), S, _p(a),
+                                _p(b), _p(kk), _p(L0), _p(sa), _p(sb), _p(xh), _p(yh), float(dt),
+                                int(steps), int(every), _p(gk), _p(gvx), _p(gvy), _p(gx), _p(gy),
+                                _p(xT), _p(yT), C.byref(loss))
+    if rc:
+        raise RuntimeError("oracle adjoint error %d" % rc)
+    return dict(loss=loss.value, gk=gk, gvx=gvx, gvy=gvy, gx=gx, gy=gy, xT=xT, yT=yT)

@@ -561,3 +561,172 @@ int orc_spring_breaks(double xa, double ya, double xb, double yb, double L0, flo
 {
     return sp_breaks(xa, ya, xb, yb, L0, thresh);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Differentiable spring mesh (reverse mode through the compute steps above,  */
+/* topology fixed: no spring breaks).  Not in the thesis; it is the reverse   */
+/* of one step                                                               */
+/*   v_{n+1} = v_n + dt M^-1 f(x_n; k),   x_{n+1} = x_n + dt v_{n+1}          */
+/* for the loss L = 1/2 sum_i |x_i(T) - xhat_i|^2.  With adjoints lx = dL/dx, */
+/* lv = dL/dv, starting from lx_T = x_T - xhat, lv_T = 0, step n (T-1 .. 0):  */
+/*   mu = lv_{n+1} + dt lx_{n+1};  w = M^-1 mu;  lv_n = mu                     */
+/*   per spring (a, b) at positions x_n: d = x_b - x_a, l = |d|, u = d / l,   */
+/*     g = w_a - w_b,  K g = k ((1 - L0/l) g + (L0/l) u (u . g)),             */
+/*     dL/dk += dt (l - L0) (u . g);   lx_a -= dt K g;  lx_b += dt K g        */
+/*   lx_n = lx_{n+1} + (those spring terms)                                  */
+/* Positions x_n are recomputed per segment from (x, v) checkpoints taken    */
+/* every `every` steps of the forward pass.  Each reverse step is three       */
+/* do-alls: Node (mu, w, lv), Spring (K g, dL/dk), Node (sum of spring terms  */
+/* in slot order).                                                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double lx, ly, lvx, lvy, wx, wy;
+} adj_node;
+
+typedef struct {
+    double cx, cy, gk;
+} adj_spring;
+
+static void adj_node_mu(sp_world *w, adj_node *an, const sp_node *n)
+{
+    (void)w;
+    double mux = an->lvx + w->dt * an->lx, muy = an->lvy + w->dt * an->ly;
+    an->wx = mux / n->m;
+    an->wy = muy / n->m;
+    an->lvx = mux;
+    an->lvy = muy;
+}
+
+static void adj_spring_jg(sp_world *w, size_t self, const double *px, const double *py,
+                          const adj_node *an, adj_spring *as)
+{
+    const sp_spring *s = os_at(&w->spring, self);
+    double dx = px[s->b] - px[s->a], dy = py[s->b] - py[s->a];
+    double l = sqrt(dx * dx + dy * dy);
+    double ux = dx / l, uy = dy / l;
+    double gx = an[s->a].wx - an[s->b].wx, gy = an[s->a].wy - an[s->b].wy;
+    double ug = ux * gx + uy * gy;
+    double kgx = s->k * ((1.0 - s->L0 / l) * gx + (s->L0 / l) * ux * ug);
+    double kgy = s->k * ((1.0 - s->L0 / l) * gy + (s->L0 / l) * uy * ug);
+    as[self].cx = w->dt * kgx;
+    as[self].cy = w->dt * kgy;
+    as[self].gk += w->dt * (l - s->L0) * ug;
+}
+
+static void adj_node_sum(sp_world *w, size_t self, adj_node *an, const adj_spring *as)
+{
+    const sp_node *n = os_at(&w->node, self);
+    for (int q = 0; q < SP_DEG; q++) {
+        if (n->adj[q] < 0) continue;
+        const adj_spring *c = &as[n->adj[q]];
+        if (n->adjb[q]) { an[self].lx += c->cx; an[self].ly += c->cy; }
+        else { an[self].lx -= c->cx; an[self].ly -= c->cy; }
+    }
+}
+
+/*
+ * Forward T steps from (x, y, vx, vy) with breaking off, then the reverse
+ * sweep.  Outputs (NULL to skip): gk (S), gvx, gvy, gx, gy (N) = dL/dk,
+ * dL/dv0, dL/dx0; xT, yT (N) final positions; *loss.  `every` = checkpoint
+ * interval (1..T).  Returns 0, or a negative error code.
+ */
+int orc_spring_adjoint(long long N, const double *x, const double *y, const double *vx,
+                       const double *vy, const double *m, const int32_t *adj, const uint8_t *adjb,
+                       long long S, const int32_t *a, const int32_t *b, const double *k,
+                       const double *L0, const int32_t *slot_a, const int32_t *slot_b,
+                       const double *xhat, const double *yhat, double dt, int T, int every,
+                       double *gk, double *gvx, double *gvy, double *gx, double *gy,
+                       double *xT, double *yT, double *loss)
+{
+    if (N < 0 || S < 0 || T < 0 || every < 1) return -1;
+    sp_world w;
+    memset(&w, 0, sizeof w);
+    w.dt = dt;
+    w.thresh = INFINITY;
+    if (os_init(&w.node, sizeof(sp_node), (size_t)(N ? N : 1)) ||
+        os_init(&w.spring, sizeof(sp_spring), (size_t)(S ? S : 1))) return -1;
+    size_t big = (size_t)(N > S ? N : S);
+    w.snap = malloc((big ? big : 1) * sizeof(size_t));
+    for (long long i = 0; i < N; i++) {
+        sp_node *n = os_at(&w.node, (size_t)os_new(&w.node));
+        n->x = x[i]; n->y = y[i]; n->vx = vx[i]; n->vy = vy[i]; n->m = m[i];
+        for (int q = 0; q < SP_DEG; q++) { n->adj[q] = adj[i * SP_DEG + q]; n->adjb[q] = adjb[i * SP_DEG + q]; }
+    }
+    for (long long i = 0; i < S; i++) {
+        sp_spring *s = os_at(&w.spring, (size_t)os_new(&w.spring));
+        s->a = a[i]; s->b = b[i]; s->k = k[i]; s->L0 = L0[i]; s->sa = slot_a[i]; s->sb = slot_b[i];
+    }
+    int nck = (T + every - 1) / every + 1;
+    double *ck = malloc((size_t)nck * 4 * (size_t)(N ? N : 1) * sizeof(double));
+    double *tx = malloc((size_t)every * (size_t)(N ? N : 1) * sizeof(double));
+    double *ty = malloc((size_t)every * (size_t)(N ? N : 1) * sizeof(double));
+    adj_node *an = calloc((size_t)(N ? N : 1), sizeof(adj_node));
+    adj_spring *as = calloc((size_t)(S ? S : 1), sizeof(adj_spring));
+    if (!ck || !tx || !ty || !an || !as) return -1;
+
+    /* forward, checkpoint (x, v) at steps 0, every, 2 every, ... */
+    for (int n = 0; n < T; n++) {
+        if (n % every == 0) {
+            double *c = ck + (size_t)(n / every) * 4 * N;
+            for (long long i = 0; i < N; i++) {
+                const sp_node *p = os_at(&w.node, (size_t)i);
+                c[i] = p->x; c[N + i] = p->y; c[2 * N + i] = p->vx; c[3 * N + i] = p->vy;
+            }
+        }
+        size_t kk = os_snapshot(&w.spring, w.snap);
+        for (size_t i = 0; i < kk; i++) sp_spring_force(&w, w.snap[i]);
+        kk = os_snapshot(&w.node, w.snap);
+        for (size_t i = 0; i < kk; i++) sp_node_update(&w, os_at(&w.node, w.snap[i]));
+    }
+    if (w.nbroken) w.err = 7;
+    double L = 0;
+    for (long long i = 0; i < N; i++) {
+        const sp_node *p = os_at(&w.node, (size_t)i);
+        double ex = p->x - xhat[i], ey = p->y - yhat[i];
+        L += 0.5 * (ex * ex + ey * ey);
+        an[i].lx = ex; an[i].ly = ey; an[i].lvx = 0; an[i].lvy = 0;
+        if (xT) xT[i] = p->x;
+        if (yT) yT[i] = p->y;
+    }
+    /* reverse, segment by segment */
+    for (int seg = (T - 1) / every; seg >= 0 && T > 0; seg--) {
+        int n0 = seg * every, n1 = n0 + every < T ? n0 + every : T;
+        const double *c = ck + (size_t)seg * 4 * N;
+        for (long long i = 0; i < N; i++) {
+            sp_node *p = os_at(&w.node, (size_t)i);
+            p->x = c[i]; p->y = c[N + i]; p->vx = c[2 * N + i]; p->vy = c[3 * N + i];
+        }
+        for (int n = n0; n < n1; n++) {       /* recompute the segment's positions */
+            double *px = tx + (size_t)(n - n0) * N, *py = ty + (size_t)(n - n0) * N;
+            for (long long i = 0; i < N; i++) {
+                const sp_node *p = os_at(&w.node, (size_t)i);
+                px[i] = p->x; py[i] = p->y;
+            }
+            size_t kk = os_snapshot(&w.spring, w.snap);
+            for (size_t i = 0; i < kk; i++) sp_spring_force(&w, w.snap[i]);
+            kk = os_snapshot(&w.node, w.snap);
+            for (size_t i = 0; i < kk; i++) sp_node_update(&w, os_at(&w.node, w.snap[i]));
+        }
+        for (int n = n1 - 1; n >= n0; n--) {
+            const double *px = tx + (size_t)(n - n0) * N, *py = ty + (size_t)(n - n0) * N;
+            size_t kk = os_snapshot(&w.node, w.snap);
+            for (size_t i = 0; i < kk; i++) adj_node_mu(&w, &an[w.snap[i]], os_at(&w.node, w.snap[i]));
+            kk = os_snapshot(&w.spring, w.snap);
+            for (size_t i = 0; i < kk; i++) adj_spring_jg(&w, w.snap[i], px, py, an, as);
+            kk = os_snapshot(&w.node, w.snap);
+            for (size_t i = 0; i < kk; i++) adj_node_sum(&w, w.snap[i], an, as);
+        }
+    }
+    for (long long i = 0; i < S; i++) if (gk) gk[i] = as[i].gk;
+    for (long long i = 0; i < N; i++) {
+        if (gvx) gvx[i] = an[i].lvx;
+        if (gvy) gvy[i] = an[i].lvy;
+        if (gx) gx[i] = an[i].lx;
+        if (gy) gy[i] = an[i].ly;
+    }
+    if (loss) *loss = L;
+    free(ck); free(tx); free(ty); free(an); free(as); free(w.snap);
+    os_free(&w.node);
+    os_free(&w.spring);
+    return w.err ? -(int)w.err - 10 : 0;
+}
