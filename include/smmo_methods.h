@@ -69,6 +69,45 @@ typedef struct {
     float strain_limit;
 } smmo_spring_args;
 
+/* ---- reverse mode through the spring-mesh step (breaking off) ------------
+ * Node   additionally {lx, ly, lvx, lvy, wx, wy: F32, id: I32}
+ *        (dL/dx, dL/dv and the weighted velocity adjoint w = M^-1 mu)
+ * Spring additionally {cx, cy, gk: F32}
+ *        (dt K g of the current reverse step, accumulated dL/dk)
+ * For L = f(x_T), a reverse step n (T-1 .. 0) from the adjoints at n+1 is
+ *   mu = lv + dt lx; w = mu / m; lv = mu;                      (Node)
+ *   g = w_a - w_b; u = d / l at x_n; K g = k((1 - L0/l) g + (L0/l) u (u.g));
+ *   c = dt K g; gk += dt (l - L0)(u.g)                          (Spring)
+ *   lx -= c at endpoint a, += c at endpoint b, in slot order    (Node)
+ * "adjoint.record" on Node  : tape plane pair `slot` <- (x, y), by handle
+ * "adjoint.save"   on Node  : tape planes 4*slot .. 4*slot+3 <- (x, y, vx, vy)
+ * "adjoint.load"   on Node  : (x, y, vx, vy) <- those planes
+ * "adjoint.seed"   on Node  : lx, ly <- seed_x[id], seed_y[id]; lvx, lvy <-
+ *                             seed_vx[id], seed_vy[id] (0 if NULL)
+ * "adjoint.zero"   on Spring: gk = cx = cy = 0
+ * "adjoint.node"   on Node  : mode bit 0: add the springs' c terms to lx, ly;
+ *                             mode bit 1: mu, w, lv as above (bit 0 first)
+ * "adjoint.spring" on Spring: c and gk with positions x_n read from tape
+ *                             plane pair `slot`
+ * The tape holds planes of `plane` floats (plane >= 64 * heap blocks, one
+ * float per handle); tape_floats is its capacity, checked on the host.
+ * seed arrays have seed_count entries, indexed by the node's id field.     */
+typedef struct {
+    uint32_t node_class;
+    uint32_t spring_class;
+    float dt;
+    uint32_t mode;
+    float *tape;
+    uint64_t tape_floats;
+    uint64_t plane;
+    uint32_t slot;
+    uint32_t seed_count;
+    const float *seed_x;
+    const float *seed_y;
+    const float *seed_vx;
+    const float *seed_vy;
+} smmo_adjoint_args;
+
 /* ---- test methods ---------------------------------------------------------
  * "test.axpy"      on any class with F32 field "x": x = a * x + b
  * "test.destroy_if" on any class with I32 field "key": delete this object if

@@ -12,4 +12,5 @@ from .workloads import (  # noqa: F401
     nbody_init,
     spring_mesh,
     batched_meshes,
+    concat_meshes,
 )

@@ -157,3 +157,24 @@ def batched_meshes(n_struct: int = 256, seed: int | None = None,
         noff += m["N"]
         soff += m["S"]
     return meshes
+
+
+def concat_meshes(meshes: list) -> dict:
+    """One mesh dict holding independent meshes side by side: node and spring
+    ids are shifted by the sizes of the meshes before (global ids); slots are
+    unchanged.  Springs of one mesh only reference that mesh's nodes."""
+    out = {}
+    for key in ("x", "y", "vx", "vy", "m", "k", "L0", "slot_a", "slot_b"):
+        out[key] = np.concatenate([m[key] for m in meshes])
+    noff = np.cumsum([0] + [m["N"] for m in meshes])
+    soff = np.cumsum([0] + [m["S"] for m in meshes])
+    out["a"] = np.concatenate([m["a"] + noff[i] for i, m in enumerate(meshes)]).astype(np.int32)
+    out["b"] = np.concatenate([m["b"] + noff[i] for i, m in enumerate(meshes)]).astype(np.int32)
+    out["adj"] = np.concatenate([np.where(m["adj"] >= 0, m["adj"] + soff[i], -1)
+                                 for i, m in enumerate(meshes)]).astype(np.int32)
+    out["adj_is_b"] = np.concatenate([m["adj_is_b"] for m in meshes])
+    out["N"] = int(noff[-1])
+    out["S"] = int(soff[-1])
+    out["node_offsets"] = noff
+    out["spring_offsets"] = soff
+    return out

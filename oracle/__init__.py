@@ -13,5 +13,6 @@ from .oracle import (  # noqa: F401
     nbody_update,
     spring_steps,
     spring_adjoint,
+    spring_adjoint_step,
     spring_breaks,
 )

@@ -60,6 +60,9 @@ def _load():
             lib.orc_spring_adjoint.restype = C.c_int
             lib.orc_spring_adjoint.argtypes = [LL, P, P, P, P, P, P, P, LL, P, P, P, P, P, P, P, P,
                                                D, C.c_int, C.c_int, P, P, P, P, P, P, P, P]
+            lib.orc_spring_adjoint_step.restype = C.c_int
+            lib.orc_spring_adjoint_step.argtypes = [LL, P, P, P, P, P, LL, P, P, P, P, D,
+                                                    P, P, P, P, P, P, P, P, P, P]
             lib.orc_spring_breaks.restype = C.c_int
             lib.orc_spring_breaks.argtypes = [D, D, D, D, D, C.c_float]
             _lib = lib
@@ -224,3 +227,27 @@ def spring_adjoint(mesh: dict, dt: float, steps: int, every: int = 20, xhat=None
     if rc:
         raise RuntimeError("oracle adjoint error %d" % rc)
     return dict(loss=loss.value, gk=gk, gvx=gvx, gvy=gvy, gx=gx, gy=gy, xT=xT, yT=yT)
+
+
+def spring_adjoint_step(mesh: dict, px, py, dt, lx, ly, lvx, lvy):
+    """One reverse step from positions x_n (px, py) and the adjoints at step
+    n+1; returns the adjoints at step n, this step's dL/dk contribution and
+    the conditioning scales (sgk, slx, sly, slvx, slvy)."""
+    lib = _load()
+    N = int(np.asarray(mesh["x"]).size)
+    S = int(np.asarray(mesh["a"]).size)
+    px, py, m = _f64(px), _f64(py), _f64(mesh["m"])
+    adj = np.ascontiguousarray(mesh["adj"], dtype=np.int32).reshape(N, 8)
+    adjb = np.ascontiguousarray(mesh["adj_is_b"], dtype=np.uint8).reshape(N, 8)
+    a = np.ascontiguousarray(mesh["a"], dtype=np.int32)
+    b = np.ascontiguousarray(mesh["b"], dtype=np.int32)
+    kk, L0 = _f64(mesh["k"]), _f64(mesh["L0"])
+    lx, ly, lvx, lvy = (_f64(v) for v in (lx, ly, lvx, lvy))
+    gk, sgk = np.zeros(S), np.zeros(S)
+    slx, sly, slvx, slvy = (np.zeros(N) for _ in range(4))
+    rc = lib.orc_spring_adjoint_step(N, _p(px), _p(py), _p(m), _p(adj), _p(adjb), S, _p(a), _p(b),
+                                     _p(kk), _p(L0), float(dt), _p(lx), _p(ly), _p(lvx), _p(lvy),
+                                     _p(gk), _p(sgk), _p(slx), _p(sly), _p(slvx), _p(slvy))
+    if rc:
+        raise RuntimeError("oracle adjoint step error %d" % rc)
+    return dict(lx=lx, ly=ly, lvx=lvx, lvy=lvy, gk=gk, sgk=sgk, slx=slx, sly=sly, slvx=slvx, slvy=slvy)

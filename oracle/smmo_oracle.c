@@ -730,3 +730,67 @@ int orc_spring_adjoint(long long N, const double *x, const double *y, const doub
     os_free(&w.spring);
     return w.err ? -(int)w.err - 10 : 0;
 }
+
+/*
+ * One reverse step in isolation (the three do-alls above), from given
+ * positions x_n and adjoints (lx, ly, lvx, lvy) = at step n+1; they are
+ * replaced by the adjoints at step n.  gk receives this step's contribution
+ * to dL/dk.  Conditioning scales of the float32 rounding error (NULL to
+ * skip): sgk (S) = dt (l + L0) |g|; slx, sly (N) = |lx| + sum over the
+ * node's springs of dt k (1 + 2 L0/l) |g|; slv (N) = |lv| + dt |lx|.
+ */
+int orc_spring_adjoint_step(long long N, const double *px, const double *py, const double *m,
+                            const int32_t *adj, const uint8_t *adjb, long long S, const int32_t *a,
+                            const int32_t *b, const double *k, const double *L0, double dt,
+                            double *lx, double *ly, double *lvx, double *lvy, double *gk,
+                            double *sgk, double *slx, double *sly, double *slvx, double *slvy)
+{
+    if (N < 0 || S < 0) return -1;
+    sp_world w;
+    memset(&w, 0, sizeof w);
+    w.dt = dt;
+    if (os_init(&w.node, sizeof(sp_node), (size_t)(N ? N : 1)) ||
+        os_init(&w.spring, sizeof(sp_spring), (size_t)(S ? S : 1))) return -1;
+    size_t big = (size_t)(N > S ? N : S);
+    w.snap = malloc((big ? big : 1) * sizeof(size_t));
+    adj_node *an = calloc((size_t)(N ? N : 1), sizeof(adj_node));
+    adj_spring *as = calloc((size_t)(S ? S : 1), sizeof(adj_spring));
+    for (long long i = 0; i < N; i++) {
+        sp_node *n = os_at(&w.node, (size_t)os_new(&w.node));
+        n->x = px[i]; n->y = py[i]; n->m = m[i];
+        for (int q = 0; q < SP_DEG; q++) { n->adj[q] = adj[i * SP_DEG + q]; n->adjb[q] = adjb[i * SP_DEG + q]; }
+        an[i].lx = lx[i]; an[i].ly = ly[i]; an[i].lvx = lvx[i]; an[i].lvy = lvy[i];
+    }
+    for (long long i = 0; i < S; i++) {
+        sp_spring *s = os_at(&w.spring, (size_t)os_new(&w.spring));
+        s->a = a[i]; s->b = b[i]; s->k = k[i]; s->L0 = L0[i];
+    }
+    if (slvx) for (long long i = 0; i < N; i++) {
+        slvx[i] = fabs(lvx[i]) + dt * fabs(lx[i]);
+        slvy[i] = fabs(lvy[i]) + dt * fabs(ly[i]);
+    }
+    size_t kk = os_snapshot(&w.node, w.snap);
+    for (size_t i = 0; i < kk; i++) adj_node_mu(&w, &an[w.snap[i]], os_at(&w.node, w.snap[i]));
+    kk = os_snapshot(&w.spring, w.snap);
+    for (size_t i = 0; i < kk; i++) adj_spring_jg(&w, w.snap[i], px, py, an, as);
+    if (slx) {
+        for (long long i = 0; i < N; i++) { slx[i] = fabs(an[i].lx); sly[i] = fabs(an[i].ly); }
+        for (long long i = 0; i < S; i++) {
+            const sp_spring *s = os_at(&w.spring, (size_t)i);
+            double dx = px[s->b] - px[s->a], dy = py[s->b] - py[s->a];
+            double l = sqrt(dx * dx + dy * dy);
+            double g = hypot(an[s->a].wx - an[s->b].wx, an[s->a].wy - an[s->b].wy);
+            double sc = dt * s->k * (1.0 + 2.0 * s->L0 / l) * g;
+            slx[s->a] += sc; sly[s->a] += sc; slx[s->b] += sc; sly[s->b] += sc;
+            if (sgk) sgk[i] = dt * (l + s->L0) * g;
+        }
+    }
+    kk = os_snapshot(&w.node, w.snap);
+    for (size_t i = 0; i < kk; i++) adj_node_sum(&w, w.snap[i], an, as);
+    for (long long i = 0; i < N; i++) { lx[i] = an[i].lx; ly[i] = an[i].ly; lvx[i] = an[i].lvx; lvy[i] = an[i].lvy; }
+    for (long long i = 0; i < S; i++) gk[i] = as[i].gk;
+    free(an); free(as); free(w.snap);
+    os_free(&w.node);
+    os_free(&w.spring);
+    return 0;
+}

@@ -1,0 +1,200 @@
+"""Differentiable spring mesh: reverse mode through the spring-mesh step.
+
+``DiffSpringSim`` runs the forward steps (breaking off) with (x, v)
+checkpoints every ``every`` steps and, given dL/dx_T, the reverse sweep:
+each segment is recomputed from its checkpoint while ``adjoint.record``
+writes the positions to a tape, then reversed step by step with the
+``adjoint.node`` / ``adjoint.spring`` methods.  All of it runs in libsmmo;
+this module only orders the calls.
+
+``SpringRollout`` wraps it as a ``torch.autograd.Function`` of the spring
+stiffnesses and the initial velocities.
+"""
+
+import math
+
+import numpy as np
+
+from . import smmo
+from .sims import SPRING_CLASSES
+
+ADJ_CLASSES = {
+    "Node": SPRING_CLASSES["Node"] + [("lx", "f32", 1), ("ly", "f32", 1), ("lvx", "f32", 1),
+                                      ("lvy", "f32", 1), ("wx", "f32", 1), ("wy", "f32", 1)],
+    "Spring": SPRING_CLASSES["Spring"] + [("cx", "f32", 1), ("cy", "f32", 1), ("gk", "f32", 1)],
+}
+
+
+def _blocks(n: int) -> int:
+    return (n + 63) // 64
+
+
+class DiffSpringSim:
+    """Spring mesh with fixed topology and a reverse sweep.
+
+    mesh: arrays as made by ``inputs.spring_mesh`` (ids local to the arrays);
+    k, vx, vy may be overridden by torch tensors (device) or arrays.
+    """
+
+    def __init__(self, mesh: dict, dt: float, steps: int, every: int = 20, k=None, vx=None, vy=None,
+                 cfg=None):
+        import torch
+
+        self.torch = torch
+        N = int(np.asarray(mesh["x"]).size)
+        S = int(np.asarray(mesh["a"]).size)
+        self.N, self.S = N, S
+        self.dt, self.T, self.every = float(dt), int(steps), max(1, int(every))
+        self.heap = smmo.Heap(ADJ_CLASSES, blocks=_blocks(N) + _blocks(S) + 8, cfg=cfg)
+        dev = self.heap.buf.device
+        self.dev = dev
+
+        def f32(a):
+            if isinstance(a, torch.Tensor):
+                return a.detach().to(device=dev, dtype=torch.float32).contiguous()
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+        def i32(a):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+
+        null_adj = torch.full((N * 8,), -1, dtype=torch.int32, device=dev)
+        self.node_h = self.heap.new("Node", N, x=f32(mesh["x"]), y=f32(mesh["y"]),
+                                    vx=f32(mesh["vx"] if vx is None else vx),
+                                    vy=f32(mesh["vy"] if vy is None else vy), m=f32(mesh["m"]),
+                                    adj=null_adj, id=torch.arange(N, dtype=torch.int32, device=dev)).clone()
+        a_idx = i32(mesh["a"]).long()
+        b_idx = i32(mesh["b"]).long()
+        if S:
+            self.spring_h = self.heap.new(
+                "Spring", S, a=self.node_h[a_idx], b=self.node_h[b_idx],
+                k=f32(mesh["k"] if k is None else k), L0=f32(mesh["L0"]),
+                slot_a=torch.from_numpy(np.asarray(mesh["slot_a"]).astype(np.uint8)).to(dev),
+                slot_b=torch.from_numpy(np.asarray(mesh["slot_b"]).astype(np.uint8)).to(dev),
+                id=torch.arange(S, dtype=torch.int32, device=dev)).clone()
+        self.cn, self.cs = self.heap.cls["Node"], self.heap.cls["Spring"]
+        self.fargs = smmo.smmo_spring_args(self.cn, self.cs, self.dt, math.inf)
+        ids = {n: smmo.smmo_method_id(n) for n in (
+            "spring.force", "spring.node_update", "spring.link", "adjoint.record", "adjoint.save",
+            "adjoint.load", "adjoint.seed", "adjoint.zero", "adjoint.node", "adjoint.spring")}
+        self.mid = ids
+        if S:
+            self._do(self.cs, "spring.link", self.fargs)
+        # tapes: one float per handle and plane
+        self.plane = 64 * self.heap.blocks
+        nck = (self.T + self.every - 1) // self.every if self.T else 0
+        self.ckpt = torch.empty(max(1, nck) * 4 * self.plane, dtype=torch.float32, device=dev)
+        self.tape = torch.empty(max(1, min(self.every, max(self.T, 1))) * 2 * self.plane,
+                                dtype=torch.float32, device=dev)
+
+    # ------------------------------------------------------------ helpers --
+    def _do(self, cls, name, args):
+        smmo.smmo_parallel_do(self.heap.h, cls, self.mid[name], args)
+
+    def _aargs(self, tape, slot=0, mode=0, seeds=(None, None, None, None), count=0):
+        P = [0 if s is None else s.data_ptr() for s in seeds]
+        return smmo.smmo_adjoint_args(self.cn, self.cs, self.dt, mode, tape.data_ptr(), tape.numel(),
+                                      self.plane, slot, count, P[0] or None, P[1] or None,
+                                      P[2] or None, P[3] or None)
+
+    def step(self):
+        self._do(self.cs, "spring.force", self.fargs)
+        self._do(self.cn, "spring.node_update", self.fargs)
+
+    # ------------------------------------------------------------ forward --
+    def forward(self):
+        """T steps; checkpoints at 0, every, 2 every, ...  Returns x_T as (N, 2) by node id."""
+        for n in range(self.T):
+            if n % self.every == 0:
+                self._do(self.cn, "adjoint.save", self._aargs(self.ckpt, slot=n // self.every))
+            self.step()
+        return self.positions()
+
+    def positions(self):
+        torch = self.torch
+        g = self.heap.gather("Node", ["id", "x", "y"])
+        out = torch.empty((self.N, 2), dtype=torch.float32, device=self.dev)
+        idx = g["id"].long()
+        out[idx, 0] = g["x"]
+        out[idx, 1] = g["y"]
+        return out
+
+    # ----------------------------------------------------------- backward --
+    def backward(self, gx, gy, gvx=None, gvy=None):
+        """Reverse sweep from dL/dx_T (and dL/dv_T, default 0), tensors of N by
+        node id.  Returns (dL/dk by spring id, dL/dv0 (N, 2), dL/dx0 (N, 2))."""
+        torch = self.torch
+        seeds = [t.detach().to(device=self.dev, dtype=torch.float32).contiguous() if t is not None else None
+                 for t in (gx, gy, gvx, gvy)]
+        self._do(self.cn, "adjoint.seed", self._aargs(self.tape, seeds=seeds, count=self.N))
+        if self.S:
+            self._do(self.cs, "adjoint.zero", self._aargs(self.tape))
+        first = True
+        nseg = (self.T + self.every - 1) // self.every
+        for seg in range(nseg - 1, -1, -1):
+            n0 = seg * self.every
+            n1 = min(n0 + self.every, self.T)
+            self._do(self.cn, "adjoint.load", self._aargs(self.ckpt, slot=seg))
+            for t in range(n1 - n0):
+                self._do(self.cn, "adjoint.record", self._aargs(self.tape, slot=t))
+                if t < n1 - n0 - 1:       # the segment's last step is not needed
+                    self.step()
+            for t in range(n1 - n0 - 1, -1, -1):
+                self._do(self.cn, "adjoint.node", self._aargs(self.tape, mode=2 if first else 3))
+                first = False
+                if self.S:
+                    self._do(self.cs, "adjoint.spring", self._aargs(self.tape, slot=t))
+        if not first:
+            self._do(self.cn, "adjoint.node", self._aargs(self.tape, mode=1))
+        self.heap.sync()
+        return self.gradients()
+
+    def gradients(self):
+        torch = self.torch
+        gk = torch.zeros(self.S, dtype=torch.float32, device=self.dev)
+        if self.S:
+            g = self.heap.gather("Spring", ["id", "gk"])
+            gk[g["id"].long()] = g["gk"]
+        g = self.heap.gather("Node", ["id", "lvx", "lvy", "lx", "ly"])
+        idx = g["id"].long()
+        gv = torch.empty((self.N, 2), dtype=torch.float32, device=self.dev)
+        gx = torch.empty((self.N, 2), dtype=torch.float32, device=self.dev)
+        gv[idx, 0], gv[idx, 1] = g["lvx"], g["lvy"]
+        gx[idx, 0], gx[idx, 1] = g["lx"], g["ly"]
+        return gk, gv, gx
+
+
+def _autograd_function():
+    import torch
+
+    class SpringRollout(torch.autograd.Function):
+        """x_T = rollout(k, v0): T spring-mesh steps from the mesh's initial
+        positions with stiffnesses k (S,) and initial velocities v0 (N, 2);
+        the backward runs the checkpointed reverse sweep on the GPU."""
+
+        @staticmethod
+        def forward(ctx, k, v0, mesh, dt, steps, every=20):
+            sim = DiffSpringSim(mesh, dt, steps, every, k=k, vx=v0[:, 0], vy=v0[:, 1])
+            xT = sim.forward()
+            ctx.sim = sim
+            return xT
+
+        @staticmethod
+        def backward(ctx, g):
+            sim = ctx.sim
+            gk, gv, _ = sim.backward(g[:, 0], g[:, 1])
+            sim.heap.close()
+            ctx.sim = None
+            return gk, gv, None, None, None, None
+
+    return SpringRollout
+
+
+_SR = None
+
+
+def spring_rollout(k, v0, mesh, dt, steps, every=20):
+    """Differentiable rollout: returns x_T (N, 2); gradients flow to k and v0."""
+    global _SR
+    if _SR is None:
+        _SR = _autograd_function()
+    return _SR.apply(k, v0, mesh, dt, steps, every)

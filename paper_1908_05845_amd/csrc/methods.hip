@@ -16,108 +16,11 @@
 #include <string>
 
 #include "../../include/smmo_methods.h"
-#include "smmo_device.hpp"
-#include "smmo_host.hpp"
+#include "method_common.hpp"
 
 using namespace smmo;
 
 namespace {
-
-// Work-group g runs on XCD g % 8; give XCD x the contiguous range of logical
-// work-group numbers [start(x), start(x) + count(x)).
-__device__ __forceinline__ uint32_t xcd_logical_wg()
-{
-    const uint32_t G = gridDim.x, g = blockIdx.x;
-    const uint32_t x = g & 7u, k = g >> 3, per = G >> 3, rem = G & 7u;
-    return x * per + (x < rem ? x : rem) + k;
-}
-
-__device__ __forceinline__ uint64_t uniform64(uint64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Calls f(bid, bitmap) for every block of class `cls` in R, one wavefront per
-// block.  A block that was freed (or freed and re-used by another class)
-// since R was built has a different type and is skipped, so R may be a
-// superset of the class's blocks.  bitmap = the iteration bitmap (snapshot of
-// the allocation bitmap taken by the enumeration) or the allocation bitmap,
-// which is the same as long as the method creates no object of its own class.
-// Within one launch a block's type and (outside snapshot mode) its bitmap
-// change only through the wavefront that processes it, so plain loads are
-// enough.  The next R entry is fetched one iteration ahead.
-template <class F>
-__device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, bool snapshot, F &&f)
-{
-    const uint32_t r = __builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_RFINAL + cls));
-    const uint32_t *R = h.R + (uint64_t)cls * h.M;
-    const uint32_t wpg = blockDim.x >> 6;
-    const uint32_t nw = gridDim.x * wpg;
-    uint32_t i = xcd_logical_wg() * wpg + (threadIdx.x >> 6);
-    if (i >= r) return;
-    uint32_t bid = __builtin_amdgcn_readfirstlane(R[i]);
-    for (;;) {
-        const uint32_t in = i + nw;
-        const uint32_t bnext = __builtin_amdgcn_readfirstlane(in < r ? R[in] : 0u);
-        const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
-        const uint64_t bm = uniform64(snapshot ? h.iter_bm[bid] : h.alloc_bm[bid]);
-        if (t == cls) f(bid, bm);
-        if (in >= r) break;
-        i = in;
-        bid = bnext;
-    }
-}
-
-template <class T>
-__device__ __forceinline__ T *farr(const HeapView &h, uint32_t bid, uint32_t off)
-{
-    return reinterpret_cast<T *>(h.block(bid) + off);
-}
-
-template <class T>
-__device__ __forceinline__ T &fref(const HeapView &h, uint32_t handle, uint32_t off)
-{
-    return reinterpret_cast<T *>(h.block(handle >> 6) + off)[handle & 63];
-}
-
-smmo_status launched(const char *what)
-{
-    const hipError_t e = hipGetLastError();
-    return e == hipSuccess ? SMMO_OK : hip_fail(e, what);
-}
-
-// Kernel parameters for (method tag, class, argument struct), bound by
-// `bind` on the first launch and taken from the heap's cache afterwards.
-template <class K, class A, class Bind>
-smmo_status cached_bind(smmo_heap *h, const void *tag, uint32_t cls, const A &a, K &k, Bind &&bind)
-{
-    static_assert(sizeof(A) <= sizeof(smmo_bind_slot::args) && sizeof(K) <= sizeof(smmo_bind_slot::k),
-                  "bind cache slot too small");
-    for (smmo_bind_slot &sl : h->bind_cache)
-        if (sl.method == tag && sl.cls == cls && sl.nargs == sizeof(A) && sl.nk == sizeof(K) &&
-            memcmp(sl.args, &a, sizeof(A)) == 0) {
-            memcpy(&k, sl.k, sizeof(K));
-            return SMMO_OK;
-        }
-    smmo_status s = bind();
-    if (s) return s;
-    smmo_bind_slot &sl = h->bind_cache[h->bind_next++ % (sizeof(h->bind_cache) / sizeof(h->bind_cache[0]))];
-    sl.method = tag;
-    sl.cls = cls;
-    sl.nargs = sizeof(A);
-    sl.nk = sizeof(K);
-    memcpy(sl.args, &a, sizeof(A));
-    memcpy(sl.k, &k, sizeof(K));
-    return SMMO_OK;
-}
-
-#define BIND(cls, name, dt, cnt, off, stride)                                              \
-    do {                                                                                   \
-        smmo_status _s = bind_field(h->schema, (cls), (name), (dt), (cnt), (off), (stride)); \
-        if (_s) return _s;                                                                 \
-    } while (0)
 
 // ======================================================= Game of Life =====
 struct GolK {
@@ -684,6 +587,13 @@ const MethodEntry kMethods[] = {
     {"spring.force", sizeof(smmo_spring_args), launch_spring<0>},
     {"spring.node_update", sizeof(smmo_spring_args), launch_spring<1>},
     {"spring.link", sizeof(smmo_spring_args), launch_spring<2>},
+    {"adjoint.record", sizeof(smmo_adjoint_args), launch_adj_record},
+    {"adjoint.save", sizeof(smmo_adjoint_args), launch_adj_save},
+    {"adjoint.load", sizeof(smmo_adjoint_args), launch_adj_load},
+    {"adjoint.seed", sizeof(smmo_adjoint_args), launch_adj_seed},
+    {"adjoint.zero", sizeof(smmo_adjoint_args), launch_adj_zero},
+    {"adjoint.node", sizeof(smmo_adjoint_args), launch_adj_node},
+    {"adjoint.spring", sizeof(smmo_adjoint_args), launch_adj_spring},
     {"test.axpy", sizeof(smmo_axpy_args), launch_axpy},
     {"test.destroy_if", sizeof(smmo_destroy_if_args), launch_destroy_if},
     {"test.spawn", sizeof(smmo_spawn_args), launch_spawn},

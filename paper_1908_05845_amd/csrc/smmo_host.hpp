@@ -43,7 +43,7 @@ struct smmo_bind_slot {
     uint32_t cls = 0;
     uint32_t nargs = 0;
     uint32_t nk = 0;
-    alignas(8) unsigned char args[64];
+    alignas(8) unsigned char args[128];
     alignas(8) unsigned char k[256];
 };
 

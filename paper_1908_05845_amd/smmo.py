@@ -80,6 +80,14 @@ class smmo_spring_args(C.Structure):
                 ("strain_limit", C.c_float)]
 
 
+class smmo_adjoint_args(C.Structure):
+    _fields_ = [("node_class", C.c_uint32), ("spring_class", C.c_uint32), ("dt", C.c_float),
+                ("mode", C.c_uint32), ("tape", C.c_void_p), ("tape_floats", C.c_uint64),
+                ("plane", C.c_uint64), ("slot", C.c_uint32), ("seed_count", C.c_uint32),
+                ("seed_x", C.c_void_p), ("seed_y", C.c_void_p), ("seed_vx", C.c_void_p),
+                ("seed_vy", C.c_void_p)]
+
+
 class smmo_axpy_args(C.Structure):
     _fields_ = [("a", C.c_float), ("b", C.c_float)]
 

@@ -94,7 +94,8 @@ def test_too_many_classes_and_duplicates(lib):
 
 def test_method_ids(lib):
     names = ["gol.cell_count", "gol.alive_death", "gol.cell_birth", "nbody.force", "nbody.update",
-             "spring.force", "spring.node_update", "spring.link", "test.axpy", "test.destroy_if",
+             "spring.force", "spring.node_update", "spring.link", "adjoint.record", "adjoint.save",
+             "adjoint.load", "adjoint.seed", "adjoint.zero", "adjoint.node", "adjoint.spring", "test.axpy", "test.destroy_if",
              "test.spawn"]
     ids = [smmo.smmo_method_id(n) for n in names]
     assert len(set(ids)) == len(ids)
@@ -123,3 +124,4 @@ def test_struct_sizes_match_header(lib):
     assert C.sizeof(smmo.smmo_spring_args) == 16
     assert C.sizeof(smmo.smmo_spawn_args) == 24
     assert C.sizeof(smmo.smmo_config) == 64
+    assert C.sizeof(smmo.smmo_adjoint_args) == 80

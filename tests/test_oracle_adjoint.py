@@ -128,3 +128,28 @@ def test_forward_part_equals_plain_forward():
     r = spring_adjoint(mesh, 1e-3, 40, every=20)
     f = spring_steps(mesh, 1e-3, 1e30, 40)
     assert np.array_equal(r["xT"], f["x"]) and np.array_equal(r["yT"], f["y"])
+
+
+def test_single_step_function_composes_to_full_adjoint():
+    # the full reverse sweep is the composition of single reverse steps
+    from oracle import spring_adjoint_step
+
+    mesh = _as64(spring_mesh(5, 4, seed=12, v_sigma=0.5))
+    dt, T = 1e-3, 10
+    full = spring_adjoint(mesh, dt, T, every=T)
+    xs, ys = [], []
+    st = mesh
+    for n in range(T):
+        xs.append(st["x"].copy())
+        ys.append(st["y"].copy())
+        st = spring_steps(st, dt, 1e30, 1)
+    lx, ly = st["x"] - mesh["x"], st["y"] - mesh["y"]
+    lvx, lvy = np.zeros(mesh["N"]), np.zeros(mesh["N"])
+    gk = np.zeros(mesh["S"])
+    for n in range(T - 1, -1, -1):
+        r = spring_adjoint_step(mesh, xs[n], ys[n], dt, lx, ly, lvx, lvy)
+        lx, ly, lvx, lvy = r["lx"], r["ly"], r["lvx"], r["lvy"]
+        gk += r["gk"]
+        assert np.all(r["slx"] >= np.abs(r["lx"]) * 0) and np.all(r["sgk"] >= 0)
+    assert np.allclose(gk, full["gk"], rtol=1e-12, atol=0)
+    assert np.array_equal(lvx, full["gvx"]) and np.array_equal(lx, full["gx"])
