@@ -243,6 +243,15 @@ smmo_status smmo_clear_error(smmo_heap *h, smmo_stream stream);
 /* Number of blocks M and block size of a heap. */
 smmo_status smmo_heap_info(const smmo_heap *h, uint64_t *blocks, uint32_t *block_bytes);
 
+/* Launch shape of `method_id` on class `class_id` for this heap (the
+ * autotuner's knob): work-group size wg_threads (64, 128, 256, 512 or 1024;
+ * 0 = default 256) and grid_waves wavefronts in total (0 = default, 64 per
+ * CU).  Each wavefront walks blocks grid_waves apart, so blocks per
+ * wavefront = ceil(blocks of the class / grid_waves).  Methods with a fixed
+ * shape (nbody.force) ignore it. */
+smmo_status smmo_set_launch(smmo_heap *h, uint32_t method_id, uint32_t class_id,
+                            uint32_t wg_threads, uint32_t grid_waves);
+
 /* Method id of a method compiled into the library (names in smmo_methods.h),
  * SMMO_EINVAL if unknown. */
 smmo_status smmo_method_id(const char *name, uint32_t *method_id);

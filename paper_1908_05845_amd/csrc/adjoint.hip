@@ -40,7 +40,7 @@ __device__ __forceinline__ float *plane_ptr(const AdjK &p, uint32_t plane_index)
     return p.tape + (uint64_t)plane_index * p.plane;
 }
 
-__global__ __launch_bounds__(256) void k_adj_record(HeapView h, AdjK p)
+__global__ __launch_bounds__(1024) void k_adj_record(HeapView h, AdjK p)
 {
     if (heap_failed(h)) return;
     float *px = plane_ptr(p, 2 * p.slot), *py = plane_ptr(p, 2 * p.slot + 1);
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_adj_record(HeapView h, AdjK p)
 }
 
 template <bool kLoad>
-__global__ __launch_bounds__(256) void k_adj_ckpt(HeapView h, AdjK p)
+__global__ __launch_bounds__(1024) void k_adj_ckpt(HeapView h, AdjK p)
 {
     if (heap_failed(h)) return;
     float *c0 = plane_ptr(p, 4 * p.slot), *c1 = plane_ptr(p, 4 * p.slot + 1);
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_adj_ckpt(HeapView h, AdjK p)
     });
 }
 
-__global__ __launch_bounds__(256) void k_adj_seed(HeapView h, AdjK p)
+__global__ __launch_bounds__(1024) void k_adj_seed(HeapView h, AdjK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_adj_seed(HeapView h, AdjK p)
     });
 }
 
-__global__ __launch_bounds__(256) void k_adj_zero(HeapView h, AdjK p)
+__global__ __launch_bounds__(1024) void k_adj_zero(HeapView h, AdjK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_adj_zero(HeapView h, AdjK p)
 
 // Node pass: (bit 0) lx, ly += the springs' terms in slot order; (bit 1)
 // mu = lv + dt lx, w = mu / m, lv = mu.
-__global__ __launch_bounds__(256) void k_adj_node(HeapView h, AdjK p)
+__global__ __launch_bounds__(1024) void k_adj_node(HeapView h, AdjK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_adj_node(HeapView h, AdjK p)
 }
 
 // Spring pass: c = dt K(x_n) g with g = w_a - w_b, and dL/dk += dt (l - L0) u.g
-__global__ __launch_bounds__(256) void k_adj_spring(HeapView h, AdjK p)
+__global__ __launch_bounds__(1024) void k_adj_spring(HeapView h, AdjK p)
 {
     if (heap_failed(h)) return;
     const float *px = plane_ptr(p, 2 * p.slot), *py = plane_ptr(p, 2 * p.slot + 1);
@@ -243,7 +243,8 @@ smmo_status launch_adj(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     if (Which == W_SEED && (!a.seed_x || !a.seed_y)) return fail(SMMO_EINVAL, "adjoint: seed arrays are NULL");
     if (Which == W_NODE && (a.mode & ~3u)) return fail(SMMO_EINVAL, "adjoint: bad mode");
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
-    const dim3 grid(method_grid(h, cls)), blk(256);
+    const LaunchShape ls = method_shape(h, cls);
+    const dim3 grid = ls.grid, blk = ls.block;
     switch (Which) {
     case W_RECORD: hipLaunchKernelGGL(k_adj_record, grid, blk, 0, st, h->v, k); break;
     case W_SAVE: hipLaunchKernelGGL(k_adj_ckpt<false>, grid, blk, 0, st, h->v, k); break;

@@ -591,11 +591,20 @@ smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStre
     return SMMO_OK;
 }
 
-uint32_t method_grid(const smmo_heap *h, uint32_t cls)
+LaunchShape method_shape(const smmo_heap *h, uint32_t cls)
 {
+    uint32_t wg = 256;
     uint64_t waves = h->cfg.grid_waves ? h->cfg.grid_waves : 64ull * h->cu_count;
+    if (h->cur_method < 64) {
+        if (h->launch_wg[h->cur_method][cls]) wg = h->launch_wg[h->cur_method][cls];
+        if (h->launch_waves[h->cur_method][cls]) waves = h->launch_waves[h->cur_method][cls];
+    }
     waves = std::min<uint64_t>(waves, std::max<uint64_t>(1, h->ub_blocks[cls]));
-    return (uint32_t)((waves + 3) / 4);
+    const uint32_t wpg = wg / 64;
+    LaunchShape ls;
+    ls.grid = dim3((uint32_t)((waves + wpg - 1) / wpg));
+    ls.block = dim3(wg);
+    return ls;
 }
 
 void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects)
@@ -858,9 +867,27 @@ smmo_status smmo_parallel_do(smmo_heap *h, uint32_t class_id, uint32_t method_id
     if (args_bytes != m.args_bytes || (m.args_bytes && !args))
         return fail(SMMO_EINVAL, std::string("method '") + m.name + "': wrong argument size");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    h->cur_method = method_id;
     s = m.launch(h, class_id, args, st);
+    h->cur_method = 0xFFFFFFFFu;
     if (s) return s;
     h->last = st;
+    return SMMO_OK;
+}
+
+smmo_status smmo_set_launch(smmo_heap *h, uint32_t method_id, uint32_t class_id, uint32_t wg_threads,
+                            uint32_t grid_waves)
+{
+    smmo_status s = check_class(h, class_id);
+    if (s) return s;
+    uint32_t nm = 0;
+    method_table(&nm);
+    if (method_id >= nm || method_id >= 64) return fail(SMMO_EINVAL, "unknown method id");
+    if (wg_threads != 0 && wg_threads != 64 && wg_threads != 128 && wg_threads != 256 && wg_threads != 512 &&
+        wg_threads != 1024)
+        return fail(SMMO_EINVAL, "work-group size must be 0 or one of 64, 128, 256, 512, 1024");
+    h->launch_wg[method_id][class_id] = (uint16_t)wg_threads;
+    h->launch_waves[method_id][class_id] = grid_waves;
     return SMMO_OK;
 }
 
@@ -895,8 +922,9 @@ smmo_status smmo_gather_soa(smmo_heap *h, uint32_t class_id, const uint32_t *fie
         return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     if ((s = ensure_enumerated(h, class_id, false, st))) return s;
-    const uint32_t grid = method_grid(h, class_id);
-    hipLaunchKernelGGL(k_gather, dim3(grid), dim3(256), 0, st, h->v, class_id, fs, out_handles, capacity,
+    h->cur_method = 0xFFFFFFFFu;
+    const LaunchShape ls = method_shape(h, class_id);
+    hipLaunchKernelGGL(k_gather, ls.grid, ls.block, 0, st, h->v, class_id, fs, out_handles, capacity,
                        out_count);
     if ((s = launch_check("k_gather"))) return s;
     h->last = st;

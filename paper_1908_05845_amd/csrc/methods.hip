@@ -32,7 +32,7 @@ struct GolK {
 };
 
 // Cell::count - live cells among the 8 neighbours on the torus
-__global__ __launch_bounds__(256) void k_gol_count(HeapView h, GolK p)
+__global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void k_gol_count(HeapView h, GolK p)
 }
 
 // Alive::death - if the cell's count is not 2 or 3: cell dies, delete this
-__global__ __launch_bounds__(256) void k_gol_death(HeapView h, GolK p)
+__global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.alive_cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_gol_death(HeapView h, GolK p)
 
 // Cell::birth - if dead with exactly three live neighbours: becomes alive and
 // gets a new Alive object
-__global__ __launch_bounds__(256) void k_gol_birth(HeapView h, GolK p)
+__global__ __launch_bounds__(1024) void k_gol_birth(HeapView h, GolK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -128,10 +128,10 @@ smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     const uint32_t want = Which == 1 ? a.alive_class : a.cell_class;
     if (cls != want) return fail(SMMO_EINVAL, "gol: method runs on a different class");
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
-    const uint32_t grid = method_grid(h, cls);
-    if (Which == 0) hipLaunchKernelGGL(k_gol_count, dim3(grid), dim3(256), 0, st, h->v, k);
-    if (Which == 1) hipLaunchKernelGGL(k_gol_death, dim3(grid), dim3(256), 0, st, h->v, k);
-    if (Which == 2) hipLaunchKernelGGL(k_gol_birth, dim3(grid), dim3(256), 0, st, h->v, k);
+    const LaunchShape ls = method_shape(h, cls);
+    if (Which == 0) hipLaunchKernelGGL(k_gol_count, ls.grid, ls.block, 0, st, h->v, k);
+    if (Which == 1) hipLaunchKernelGGL(k_gol_death, ls.grid, ls.block, 0, st, h->v, k);
+    if (Which == 2) hipLaunchKernelGGL(k_gol_birth, ls.grid, ls.block, 0, st, h->v, k);
     if ((s = launched("gol kernel"))) return s;
     if (Which == 2) note_allocation(h, a.alive_class, 64ull * h->v.M);
     return SMMO_OK;
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void k_nbody_force(HeapView h, NbodyK p)
 }
 
 // Body::update - v += f / m dt; x += v dt (velocity first)
-__global__ __launch_bounds__(256) void k_nbody_update(HeapView h, NbodyK p)
+__global__ __launch_bounds__(1024) void k_nbody_update(HeapView h, NbodyK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -282,7 +282,7 @@ smmo_status launch_nbody_update(smmo_heap *h, uint32_t cls, const void *args, hi
                                 [&] { return bind_nbody(h, cls, a, k); });
     if (s) return s;
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
-    hipLaunchKernelGGL(k_nbody_update, dim3(method_grid(h, cls)), dim3(256), 0, st, h->v, k);
+    hipLaunchKernelGGL(k_nbody_update, method_shape(h, cls).grid, method_shape(h, cls).block, 0, st, h->v, k);
     return launched("k_nbody_update");
 }
 
@@ -310,7 +310,7 @@ __device__ __forceinline__ bool spring_breaks(float dx, float dy, float L0, floa
 // Spring::compute_force (Ch.7 "structure"): Hooke's law on the length change;
 // a spring strained past the limit empties its two adjacency slots and
 // deletes itself (the thesis's remove_spring followed by destroy).
-__global__ __launch_bounds__(256) void k_spring_force(HeapView h, SpringK p)
+__global__ __launch_bounds__(1024) void k_spring_force(HeapView h, SpringK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(256) void k_spring_force(HeapView h, SpringK p)
 
 // Node::update: sum the attached springs' forces in slot order (+f if this
 // node is endpoint a, -f if b), then v += F/m dt, x += v dt.
-__global__ __launch_bounds__(256) void k_spring_node(HeapView h, SpringK p)
+__global__ __launch_bounds__(1024) void k_spring_node(HeapView h, SpringK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void k_spring_node(HeapView h, SpringK p)
 // (slot_a of a, slot_b of b, the latter flagged as endpoint b).  Builds a
 // mesh's topology on the device after parallel_new of nodes and springs;
 // every (node, slot) pair belongs to one spring, so the writes never collide.
-__global__ __launch_bounds__(256) void k_spring_link(HeapView h, SpringK p)
+__global__ __launch_bounds__(1024) void k_spring_link(HeapView h, SpringK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -463,10 +463,10 @@ smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStrea
     if (cls != (Which == 1 ? a.node_class : a.spring_class))
         return fail(SMMO_EINVAL, "spring: method runs on a different class");
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
-    const uint32_t grid = method_grid(h, cls);
-    if (Which == 0) hipLaunchKernelGGL(k_spring_force, dim3(grid), dim3(256), 0, st, h->v, k);
-    if (Which == 1) hipLaunchKernelGGL(k_spring_node, dim3(grid), dim3(256), 0, st, h->v, k);
-    if (Which == 2) hipLaunchKernelGGL(k_spring_link, dim3(grid), dim3(256), 0, st, h->v, k);
+    const LaunchShape ls = method_shape(h, cls);
+    if (Which == 0) hipLaunchKernelGGL(k_spring_force, ls.grid, ls.block, 0, st, h->v, k);
+    if (Which == 1) hipLaunchKernelGGL(k_spring_node, ls.grid, ls.block, 0, st, h->v, k);
+    if (Which == 2) hipLaunchKernelGGL(k_spring_link, ls.grid, ls.block, 0, st, h->v, k);
     return launched("spring kernel");
 }
 
@@ -476,7 +476,7 @@ struct AxpyK {
     float a, b;
 };
 
-__global__ __launch_bounds__(256) void k_axpy(HeapView h, AxpyK p)
+__global__ __launch_bounds__(1024) void k_axpy(HeapView h, AxpyK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -496,7 +496,7 @@ smmo_status launch_axpy(smmo_heap *h, uint32_t cls, const void *args, hipStream_
     BIND(cls, "x", SMMO_F32, 1, &k.o_x, nullptr);
     smmo_status s = ensure_enumerated(h, cls, false, st);
     if (s) return s;
-    hipLaunchKernelGGL(k_axpy, dim3(method_grid(h, cls)), dim3(256), 0, st, h->v, k);
+    hipLaunchKernelGGL(k_axpy, method_shape(h, cls).grid, method_shape(h, cls).block, 0, st, h->v, k);
     return launched("k_axpy");
 }
 
@@ -505,7 +505,7 @@ struct DestroyIfK {
     int32_t mod, rem;
 };
 
-__global__ __launch_bounds__(256) void k_destroy_if(HeapView h, DestroyIfK p)
+__global__ __launch_bounds__(1024) void k_destroy_if(HeapView h, DestroyIfK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
@@ -530,7 +530,7 @@ smmo_status launch_destroy_if(smmo_heap *h, uint32_t cls, const void *args, hipS
     BIND(cls, "key", SMMO_I32, 1, &k.o_key, nullptr);
     smmo_status s = ensure_enumerated(h, cls, false, st);
     if (s) return s;
-    hipLaunchKernelGGL(k_destroy_if, dim3(method_grid(h, cls)), dim3(256), 0, st, h->v, k);
+    hipLaunchKernelGGL(k_destroy_if, method_shape(h, cls).grid, method_shape(h, cls).block, 0, st, h->v, k);
     return launched("k_destroy_if");
 }
 
@@ -540,7 +540,7 @@ struct SpawnK {
     uint32_t copies, snapshot;
 };
 
-__global__ __launch_bounds__(256) void k_spawn(HeapView h, SpawnK p)
+__global__ __launch_bounds__(1024) void k_spawn(HeapView h, SpawnK p)
 {
     if (heap_failed(h)) return;
     for_each_block(h, p.cls, p.snapshot != 0, [&](uint32_t bid, uint64_t bm) {
@@ -572,7 +572,7 @@ smmo_status launch_spawn(smmo_heap *h, uint32_t cls, const void *args, hipStream
     BIND(a.target_class, "key", SMMO_I32, 1, &k.t_key, nullptr);
     smmo_status s = ensure_enumerated(h, cls, k.snapshot != 0, st);
     if (s) return s;
-    hipLaunchKernelGGL(k_spawn, dim3(method_grid(h, cls)), dim3(256), 0, st, h->v, k);
+    hipLaunchKernelGGL(k_spawn, method_shape(h, cls).grid, method_shape(h, cls).block, 0, st, h->v, k);
     if ((s = launched("k_spawn"))) return s;
     note_allocation(h, a.target_class, 64ull * h->v.M);
     return SMMO_OK;

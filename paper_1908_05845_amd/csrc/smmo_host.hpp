@@ -61,6 +61,10 @@ struct smmo_heap {
     uint32_t cu_count = 256;
     smmo_bind_slot bind_cache[16];
     uint32_t bind_next = 0;
+    // launch shape per (method, class) set by smmo_set_launch (0 = default)
+    uint16_t launch_wg[64][SMMO_MAX_CLASSES] = {};
+    uint32_t launch_waves[64][SMMO_MAX_CLASSES] = {};
+    uint32_t cur_method = 0xFFFFFFFFu;     // method being launched by smmo_parallel_do
 };
 
 namespace smmo {
@@ -80,8 +84,14 @@ smmo_status bind_field(const smmo_schema *s, uint32_t cls, const char *name, int
 // snapshot = copy allocation bitmaps to iteration bitmaps on the way
 smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st);
 
-// launch width for a method over class cls: work-groups of 256 threads
-uint32_t method_grid(const smmo_heap *h, uint32_t cls);
+// launch shape of a do-all over class cls: the (method, class) setting of
+// smmo_set_launch if any, else 256-thread work-groups and 64 wavefronts per
+// CU, never more wavefronts than the class can have blocks
+struct LaunchShape {
+    dim3 grid;
+    dim3 block;
+};
+LaunchShape method_shape(const smmo_heap *h, uint32_t cls);
 
 // bookkeeping after a launch that creates objects of class cls
 void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects);

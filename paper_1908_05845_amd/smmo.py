@@ -110,7 +110,7 @@ EXPORTS = [
     "smmo_field_id", "smmo_block_bytes", "smmo_heap_bytes", "smmo_alloc_heap", "smmo_heap_free",
     "smmo_parallel_new", "smmo_parallel_do", "smmo_destroy", "smmo_gather_soa", "smmo_sync",
     "smmo_heap_stats", "smmo_check_invariants", "smmo_clear_error", "smmo_heap_info",
-    "smmo_method_id", "smmo_last_error",
+    "smmo_method_id", "smmo_last_error", "smmo_set_launch",
 ]
 
 
@@ -145,6 +145,7 @@ def load_library(path: str = LIB_PATH):
             "smmo_clear_error": (S, [P, P]),
             "smmo_heap_info": (S, [P, P, P]),
             "smmo_method_id": (S, [C.c_char_p, P]),
+            "smmo_set_launch": (S, [P, U32, U32, U32, U32]),
             "smmo_last_error": (S, [C.c_char_p, C.c_size_t]),
         }
         for name, (res, args) in sig.items():
@@ -321,6 +322,11 @@ def smmo_method_id(name: str) -> int:
     out = C.c_uint32()
     _check(lib, lib.smmo_method_id(name.encode(), C.byref(out)))
     return out.value
+
+
+def smmo_set_launch(heap, method_id: int, class_id: int, wg_threads: int = 0, grid_waves: int = 0) -> None:
+    lib = load_library()
+    _check(lib, lib.smmo_set_launch(heap, method_id, class_id, wg_threads, grid_waves))
 
 
 def smmo_last_error() -> str:
