@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarize two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this bench into "
                          "profiles/spring_counters.json and print a text summary; needs no GPU")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and adjoint measurements")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="compare rocprofv3 --kernel-trace durations of a run of this bench with the "
+                         "per-kernel times it printed (BENCH_JSON: its output line); needs no GPU")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="steps per captured HIP graph in the timed region (0 = eager launches)")
     return ap.parse_args()
@@ -104,13 +110,36 @@ def bench_spring(args, torch):
     argp = smmo.C.byref(sim.args)
     asz = smmo.C.sizeof(sim.args)
 
+    # dispatches of each kernel issued so far (graph replays included), so
+    # that a rocprofv3 trace of this run can be cut at the same launches
+    count = {"spring.force": 0, "spring.node_update": 0}
+
     def step(st=stream):
         lib.smmo_parallel_do(hp, cs, mf, argp, asz, st)
         lib.smmo_parallel_do(hp, cn, mn, argp, asz, st)
 
+    def counted(n):
+        count["spring.force"] += n
+        count["spring.node_update"] += n
+
     for _ in range(warmup):
         step()
+    counted(warmup)
     heap.sync()
+    frozen0 = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit)
+    tuned = None
+    if not args.no_autotune:
+        from paper_1908_05845_amd import autotune
+
+        # force passes are idempotent; node passes with dt = 0 leave the state
+        tf = autotune.tune(heap, "spring.force", "Spring", sim.args, repeat=10)
+        tn = autotune.tune(heap, "spring.node_update", "Node", frozen0, repeat=10)
+        for t in (tf, tn):
+            t.pop("tried")
+        tuned = {"spring.force": tf, "spring.node_update": tn}
+        n_tries = len(autotune.DEFAULT_WG) * len(autotune.DEFAULT_WAVES_PER_CU) * 12
+        count["spring.force"] += n_tries
+        count["spring.node_update"] += n_tries
     # eager reference: host-launched steps (reported, not the value)
     eager_n = min(1000, steps)
     torch.cuda.synchronize()
@@ -119,6 +148,7 @@ def bench_spring(args, torch):
     ee[0].record()
     for _ in range(eager_n):
         step()
+    counted(eager_n)
     ee[1].record()
     torch.cuda.synchronize()
     eager_wall = time.perf_counter() - t0
@@ -136,6 +166,7 @@ def bench_spring(args, torch):
             for _ in range(G):
                 step(cap)
         step()          # one launched step: the heap's last stream is ours again
+        counted(1)
         warmup += 1
         torch.cuda.synchronize()
     heap.sync()
@@ -150,8 +181,13 @@ def bench_spring(args, torch):
     frozen = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit)
     fp = smmo.C.byref(frozen)
 
+    window = {}
+
     def kernel_pass():
         ev = events(torch, 3)
+        for k in count:
+            window[k] = [count[k], count[k] + ks]
+            count[k] += ks
         torch.cuda.synchronize()
         ev[0].record()
         for _ in range(ks):
@@ -182,6 +218,7 @@ def bench_spring(args, torch):
             for _ in range(n):
                 step()
         e1.record()
+        counted(n)
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
         ms += e0.elapsed_time(e1)
@@ -230,6 +267,9 @@ def bench_spring(args, torch):
         "step_hbm": {"algorithmic_bytes": step_bytes, "gbs": step_bytes / (ms * 1e-3 / steps) / 1e9,
                      "frac": step_bytes / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS},
         "kernels": kernels,
+        "autotune": tuned,
+        "trace_window": {"note": "per-kernel dispatch index range of the timing pass (0-based, "
+                                 "graph replays included)", **window},
         "launch": {"mode": "hip graph of %d steps" % G if graph is not None else "eager",
                    "timed_host_wall_s": wall, "eager_ms_per_step": eager_ms,
                    "eager_host_ms_per_step": eager_wall / max(eager_n, 1) * 1e3},
@@ -249,6 +289,93 @@ def bench_spring(args, torch):
                           "call of the float64 oracle (load, steps, unload), %.1f s" % (k, el)}
 
     return res, cpu_leg, steps, warmup
+
+
+def measure_batched(torch, plain_updates_per_s):
+    """256 independent meshes (node counts log-uniform in [1e3, 6.4e4]) in one
+    heap; the 1,000-step loop captured in one HIP graph and replayed once."""
+    from inputs import batched_meshes, concat_meshes
+    from paper_1908_05845_amd.sims import SpringSim
+
+    mesh = concat_meshes(batched_meshes(256))
+    dt, limit, T = 1e-5, 0.3, 1000
+    sim = SpringSim(mesh, dt, limit)
+    heap = sim.heap
+    sim.step(5)
+    heap.sync()
+    st0 = heap.stats()
+    s0 = st0.live_objects[heap.cls["Spring"]]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cap = torch.cuda.current_stream()
+        for _ in range(T):
+            sim.step(1, stream=cap)
+    sim.step(1)
+    torch.cuda.synchronize()
+    e0, e1 = events(torch, 2)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    heap.sync()
+    st1 = heap.stats()
+    s1 = st1.live_objects[heap.cls["Spring"]]
+    n = st1.live_objects[heap.cls["Node"]]
+    ups = T * (n + 0.5 * (s0 + s1)) / (ms * 1e-3)
+    step_bytes = 68.0 * n + 56.0 * 0.5 * (s0 + s1)
+    res = {"workload": "256 spring meshes in one heap, node counts log-uniform in [1e3, 6.4e4]",
+           "nodes": int(n), "springs_at_start": int(s0), "springs_at_end": int(s1), "steps": T,
+           "launch": "one HIP graph of %d steps (%d kernel launches)" % (T, 2 * T),
+           "ms_per_step": ms / T, "updates_per_s": ups, "vs_plain": ups / plain_updates_per_s,
+           "step_hbm_gbs": step_bytes / (ms * 1e-3 / T) / 1e9,
+           "device_error": st1.device_error}
+    heap.close()
+    return res
+
+
+def measure_adjoint(torch, plain_updates_per_s):
+    """316 x 317 mesh (100,172 nodes), breaking off, 200 steps forward with a
+    checkpoint every 20 steps, then the reverse sweep (segment recompute
+    included) for L = 1/2 |x_T - x_0|^2."""
+    import numpy as np
+
+    from inputs import config_seed, spring_mesh
+    from paper_1908_05845_amd.adjoint import DiffSpringSim
+
+    mesh = spring_mesh(316, 317, seed=config_seed(5))
+    dt, T, every = 1e-5, 200, 20
+    sim = DiffSpringSim(mesh, dt, T, every)
+    x0 = torch.from_numpy(np.stack([mesh["x"], mesh["y"]], 1)).to(sim.dev)
+    # one untimed pass first (module loads, block lists)
+    sim.forward()
+    sim.backward(torch.zeros(sim.N, device=sim.dev), torch.zeros(sim.N, device=sim.dev))
+    sim2 = DiffSpringSim(mesh, dt, T, every)
+    torch.cuda.synchronize()
+    e = events(torch, 3)
+    t0 = time.perf_counter()
+    e[0].record()
+    xT = sim2.forward()
+    e[1].record()
+    g = xT - x0
+    gk, gv, _ = sim2.backward(g[:, 0], g[:, 1])
+    e[2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd = e[0].elapsed_time(e[1])
+    bwd = e[1].elapsed_time(e[2])
+    per_step = sim2.N + sim2.S
+    res = {"workload": "316x317 spring mesh, 100,172 nodes, %d springs, breaking off, dt 1e-5" % sim2.S,
+           "steps": T, "checkpoint_every": every, "forward_ms": fwd, "backward_ms": bwd,
+           "backward_over_forward": bwd / fwd,
+           "forward_updates_per_s": T * per_step / (fwd * 1e-3),
+           "backward_updates_per_s": T * per_step / (bwd * 1e-3),
+           "backward_vs_plain_updates_per_s": T * per_step / (bwd * 1e-3) / plain_updates_per_s,
+           "loss": float(0.5 * (g ** 2).sum().item()), "grad_k_norm": float(gk.norm().item()),
+           "grad_v0_norm": float(gv.norm().item()), "host_wall_s": wall}
+    sim.heap.close()
+    sim2.heap.close()
+    return res
 
 
 # --------------------------------------------------------------------- gol --
@@ -401,8 +528,37 @@ def summarize_counters(fetch_dir, write_dir):
     print("written", path)
 
 
+def summarize_trace(trace_dir, bench_json):
+    """Average kernel durations from a rocprofv3 kernel trace: over the bench's
+    timing-pass window (the same dispatches its HIP events timed) and over
+    the whole run, next to the bench's own figures."""
+    import csv
+    import glob
+
+    with open(bench_json) as f:
+        line = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    rows = []
+    for fn in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(fn) as f:
+            rows.extend(csv.DictReader(f))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    print("| kernel | dispatches | window | rocprofv3 avg in window (us) | bench HIP-event avg (us) "
+          "| rocprofv3 avg whole run (us) |")
+    print("|---|---|---|---|---|---|")
+    for name, key in KERNEL_KEYS.items():
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3 for r in rows if key in r["Kernel_Name"]]
+        lo, hi = line["trace_window"][name]
+        win = d[lo:hi]
+        print("| %s | %d | [%d, %d) | %.2f | %.2f | %.2f |" % (
+            name, len(d), lo, hi, sum(win) / max(len(win), 1), line["kernels"][name]["avg_us"],
+            sum(d) / max(len(d), 1)))
+
+
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
         return
@@ -420,6 +576,10 @@ def main():
     smmo.load_library()
     fn = {"spring": bench_spring, "gol": bench_gol, "nbody": bench_nbody}[args.workload]
     res, cpu_leg, steps, warmup = fn(args, torch)
+    extras = {}
+    if args.workload == "spring" and not args.no_extras:
+        extras["batched"] = measure_batched(torch, res["value"])
+        extras["adjoint"] = measure_adjoint(torch, res["value"])
     cpu = None if args.no_cpu_baseline else cpu_leg()
     if cpu is not None:
         cpu["cpu_model"] = _cpu_model()
@@ -441,9 +601,10 @@ def main():
         "roofline": res["roofline"],
         "cpu_baseline": cpu,
     }
-    for k in ("step_hbm", "kernels", "launch", "device_error"):
+    for k in ("step_hbm", "kernels", "autotune", "launch", "trace_window", "device_error"):
         if k in res:
             line[k] = res[k]
+    line.update(extras)
     print(json.dumps(line), flush=True)
     if args.calibrate_copy:
         calibrate_copy(torch)
