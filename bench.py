@@ -378,6 +378,76 @@ def measure_adjoint(torch, plain_updates_per_s):
     return res
 
 
+def measure_gol_extra(torch):
+    """Game of Life, 256 x 256 torus, 25 % start: 100 generations captured in
+    one HIP graph (three do-alls per generation plus the Alive block-list
+    pass).  Births are device allocations, deaths device deletions."""
+    from inputs import gol_init
+    from paper_1908_05845_amd.sims import GolSim
+
+    W = H = 256
+    sim = GolSim(W, H, gol_init(W, H))
+    heap = sim.heap
+    sim.step(2)
+    heap.sync()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cap = torch.cuda.current_stream()
+        sim.step(100, stream=cap)
+    sim.step(1)
+    heap.sync()
+    st0 = heap.stats()
+    e0, e1 = events(torch, 2)
+    torch.cuda.synchronize()
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st1 = heap.stats()
+    ca = heap.cls["Alive"]
+    news = st1.device_news - st0.device_news
+    dels = st1.device_deletes - st0.device_deletes
+    alive = 0.5 * (st0.live_objects[ca] + st1.live_objects[ca])
+    res = {"workload": "Game of Life in SMMO form, 256x256 torus, 25% start, 100 generations",
+           "launch": "one HIP graph of 100 generations", "us_per_generation": ms * 1e3 / 100,
+           "updates_per_s": 100 * (2 * W * H + alive) / (ms * 1e-3),
+           "births_per_s": news / (ms * 1e-3), "deaths_per_s": dels / (ms * 1e-3),
+           "births": int(news), "deaths": int(dels), "alive_mean": alive,
+           "fragmentation_end": st1.fragmentation, "device_error": st1.device_error}
+    heap.close()
+    return res
+
+
+def measure_nbody_extra(torch):
+    """n-body, 65,536 bodies, 50 steps: device_do over all pairs (FP32 VALU bound)."""
+    from inputs import nbody_init
+    from paper_1908_05845_amd.sims import NbodySim
+
+    n = 65536
+    sim = NbodySim(nbody_init(n), 1.0 / n, 1e-3, 1e-4)
+    sim.step(1)
+    torch.cuda.synchronize()
+    e = events(torch, 3)
+    e[0].record()
+    for _ in range(10):
+        sim.force()
+    e[1].record()
+    sim.step(49)
+    e[2].record()
+    torch.cuda.synchronize()
+    tf = e[0].elapsed_time(e[1]) / 10 * 1e-3
+    ms = e[1].elapsed_time(e[2]) / 49
+    pairs = float(n) * n
+    res = {"workload": "n-body, 65,536 bodies, all pairs, softening 1e-3, dt 1e-4",
+           "ms_per_step": ms, "force_us": tf * 1e6, "pairs_per_s": pairs / tf,
+           "tflops_20_per_pair": 20 * pairs / tf / 1e12,
+           "frac_fp32_peak": 20 * pairs / tf / 1e12 / FP32_VALU_PEAK_TFLOPS,
+           "frac_fp32_nonpacked_peak": 20 * pairs / tf / 1e12 / (FP32_VALU_PEAK_TFLOPS / 2)}
+    sim.heap.close()
+    return res
+
+
 # --------------------------------------------------------------------- gol --
 def bench_gol(args, torch):
     from inputs import gol_init
@@ -580,6 +650,8 @@ def main():
     if args.workload == "spring" and not args.no_extras:
         extras["batched"] = measure_batched(torch, res["value"])
         extras["adjoint"] = measure_adjoint(torch, res["value"])
+        extras["gol"] = measure_gol_extra(torch)
+        extras["nbody"] = measure_nbody_extra(torch)
     cpu = None if args.no_cpu_baseline else cpu_leg()
     if cpu is not None:
         cpu["cpu_model"] = _cpu_model()

@@ -123,6 +123,10 @@ typedef struct {
     uint32_t block_bytes;
     uint64_t slow_paths;                     /* blocks initialized by device new */
     uint64_t alloc_retries;                  /* failed reservations, all retried */
+    uint64_t device_news;                    /* objects created by device allocation
+                                                (methods, non-ordered parallel_new) */
+    uint64_t device_deletes;                 /* objects released by device
+                                                deallocation (methods, smmo_destroy) */
 } smmo_stats;
 
 typedef struct {

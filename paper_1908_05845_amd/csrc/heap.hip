@@ -960,6 +960,8 @@ smmo_status smmo_heap_stats(smmo_heap *h, smmo_stats *out)
     out->block_bytes = (uint32_t)h->v.block_bytes;
     out->slow_paths = *reinterpret_cast<const uint64_t *>(w + CTRL_SLOW);
     out->alloc_retries = *reinterpret_cast<const uint64_t *>(w + CTRL_RETRY);
+    out->device_news = *reinterpret_cast<const uint64_t *>(w + CTRL_NEWS);
+    out->device_deletes = *reinterpret_cast<const uint64_t *>(w + CTRL_DELS);
     const uint32_t err = w[CTRL_ERR];
     out->device_error = err == 0 ? SMMO_OK : (err == ERR_NOMEM ? SMMO_ENOMEM : SMMO_EDEVICE);
     return SMMO_OK;

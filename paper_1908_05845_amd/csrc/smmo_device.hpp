@@ -63,6 +63,12 @@ __device__ __forceinline__ void count_event(const HeapView &h, uint32_t word)
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ void count_events(const HeapView &h, uint32_t word, uint64_t n)
+{
+    __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(h.ctrl + word), (unsigned long long)n,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ bool heap_failed(const HeapView &h)
 {
     return ald32(h.ctrl + CTRL_ERR) != 0;
@@ -351,6 +357,7 @@ __device__ __forceinline__ void release_slots(const HeapView &h, uint32_t cls, u
         raise_error(h, ERR_BADHANDLE);   // releasing a free slot
         return;
     }
+    count_events(h, CTRL_DELS, (uint64_t)__popcll(mask));
     if (prev == ~0ull) q.push(bm_active(cls), bid, +1);
     if ((prev & ~mask) == 0) invalidate_block(h, bid, q);
 }
@@ -386,6 +393,7 @@ __device__ __forceinline__ uint32_t leader_allocate(const HeapView &h, uint32_t 
             if (filled) switch_bit_lane(h, bm_active(t), (uint32_t)bid, -1);
             if (t == cls) {
                 got = g;
+                count_events(h, CTRL_NEWS, (uint64_t)__popcll(g));
                 return (uint32_t)bid;
             }
             OpQueue q;                     // block re-typed meanwhile: roll back

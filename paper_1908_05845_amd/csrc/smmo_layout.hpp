@@ -56,6 +56,8 @@ enum : uint32_t {
     CTRL_RETRY = 4,       // u64: failed slot reservations (retried)
     CTRL_GCOUNT = 8,      // gather: running output count
     CTRL_GDONE = 9,       // gather: finished wavefronts
+    CTRL_NEWS = 10,       // u64: objects created by device allocation
+    CTRL_DELS = 12,       // u64: objects released by device deallocation
     CTRL_RCOUNT = 16,     // [class] enumeration: running length of R
     CTRL_RDONE = 32,      // [class] enumeration: finished wavefronts
     CTRL_RFINAL = 48,     // [class] length of R after the last enumeration
