@@ -572,9 +572,11 @@ def summarize_counters(fetch_dir, write_dir):
         rows = [r for r in _read_counter_csv(d) if r.get("Counter_Name") == counter]
         if not rows:
             raise SystemExit("no %s rows under %s" % (counter, d))
-        copies = [r for r in rows if "copy" in r["Kernel_Name"].lower()]
-        big = max(int(r["Grid_Size"]) for r in copies)
-        cal = [float(r["Counter_Value"]) * 1024.0 for r in copies if int(r["Grid_Size"]) == big]
+        # the calibration copies are the last three copy dispatches of the run
+        # (earlier copies are host uploads and small staging transfers)
+        copies = sorted((r for r in rows if "copy" in r["Kernel_Name"].lower()),
+                        key=lambda r: int(r["Dispatch_Id"]))[-3:]
+        cal = [float(r["Counter_Value"]) * 1024.0 for r in copies]
         factor[counter] = COPY_BYTES / (sum(cal) / len(cal))
         for name, key in KERNEL_KEYS.items():
             vals = [float(r["Counter_Value"]) * 1024.0 for r in rows if key in r["Kernel_Name"]]
