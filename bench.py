@@ -132,14 +132,43 @@ def bench_spring(args, torch):
         from paper_1908_05845_amd import autotune
 
         # force passes are idempotent; node passes with dt = 0 leave the state
-        tf = autotune.tune(heap, "spring.force", "Spring", sim.args, repeat=10)
-        tn = autotune.tune(heap, "spring.node_update", "Node", frozen0, repeat=10)
+        groups = (1, 2, 4)
+        tf = autotune.tune(heap, "spring.force", "Spring", sim.args, repeat=10, groups=groups)
+        tn = autotune.tune(heap, "spring.node_update", "Node", frozen0, repeat=10, groups=groups)
         for t in (tf, tn):
             t.pop("tried")
-        tuned = {"spring.force": tf, "spring.node_update": tn}
-        n_tries = len(autotune.DEFAULT_WG) * len(autotune.DEFAULT_WAVES_PER_CU) * 12
+        n_tries = len(autotune.DEFAULT_WG) * len(autotune.DEFAULT_WAVES_PER_CU) * len(groups) * 12
         count["spring.force"] += n_tries
         count["spring.node_update"] += n_tries
+        # the kernels were tuned one at a time; keep the tuned shapes only if
+        # whole steps (force, then node with dt = 0: same traffic, unchanged
+        # state) are faster with them than with the default shapes
+        fz = smmo.C.byref(frozen0)
+
+        def frozen_steps(n=100):
+            torch.cuda.synchronize()
+            ev = events(torch, 2)
+            ev[0].record()
+            for _ in range(n):
+                lib.smmo_parallel_do(hp, cs, mf, argp, asz, stream)
+                lib.smmo_parallel_do(hp, cn, mn, fz, asz, stream)
+            ev[1].record()
+            torch.cuda.synchronize()
+            counted(n)
+            return ev[0].elapsed_time(ev[1]) / n * 1e3
+
+        frozen_steps(10)
+        t_tuned = frozen_steps()
+        smmo.smmo_set_launch(hp, mf, cs, 0, 0, 0)
+        smmo.smmo_set_launch(hp, mn, cn, 0, 0, 0)
+        frozen_steps(10)
+        t_default = frozen_steps()
+        keep = t_tuned < t_default
+        if keep:
+            smmo.smmo_set_launch(hp, mf, cs, tf["wg"], tf["waves"], tf["group"])
+            smmo.smmo_set_launch(hp, mn, cn, tn["wg"], tn["waves"], tn["group"])
+        tuned = {"spring.force": tf, "spring.node_update": tn, "step_us_tuned": t_tuned,
+                 "step_us_default": t_default, "kept": "tuned" if keep else "default"}
     # eager reference: host-launched steps (reported, not the value)
     eager_n = min(1000, steps)
     torch.cuda.synchronize()
@@ -154,11 +183,14 @@ def bench_spring(args, torch):
     eager_wall = time.perf_counter() - t0
     eager_ms = ee[0].elapsed_time(ee[1]) / max(eager_n, 1)
     warmup += eager_n
-    # the timed region replays a HIP graph of G steps: the method kernels read
-    # the block lists and their lengths on the device, so a captured step is
-    # the same work as a launched one, without the host launch cost
+    # a HIP graph of G steps: the method kernels read the block lists and
+    # their lengths on the device, so a captured step is the same work as a
+    # launched one, without the host launch cost.  The timed region uses the
+    # graph if its replays are faster than launched steps (measured here on
+    # 4 G steps, counted as warm-up), else launches the steps.
     G = args.graph_steps
     graph = None
+    graph_ms = None
     if G > 0:
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
@@ -169,6 +201,17 @@ def bench_spring(args, torch):
         counted(1)
         warmup += 1
         torch.cuda.synchronize()
+        eg = events(torch, 2)
+        eg[0].record()
+        for _ in range(4):
+            graph.replay()
+        eg[1].record()
+        torch.cuda.synchronize()
+        counted(4 * G)
+        warmup += 4 * G
+        graph_ms = eg[0].elapsed_time(eg[1]) / (4 * G)
+        if graph_ms >= eager_ms:
+            graph = None
     heap.sync()
     st0 = heap.stats()
     live0 = (st0.live_objects[cs], st0.live_objects[cn])
@@ -270,8 +313,9 @@ def bench_spring(args, torch):
         "autotune": tuned,
         "trace_window": {"note": "per-kernel dispatch index range of the timing pass (0-based, "
                                  "graph replays included)", **window},
-        "launch": {"mode": "hip graph of %d steps" % G if graph is not None else "eager",
+        "launch": {"mode": "hip graph of %d steps" % G if graph is not None else "launched steps",
                    "timed_host_wall_s": wall, "eager_ms_per_step": eager_ms,
+                   "graph_ms_per_step": graph_ms,
                    "eager_host_ms_per_step": eager_wall / max(eager_n, 1) * 1e3},
         "device_error": st2.device_error,
     }
@@ -337,7 +381,10 @@ def measure_batched(torch, plain_updates_per_s):
 def measure_adjoint(torch, plain_updates_per_s):
     """316 x 317 mesh (100,172 nodes), breaking off, 200 steps forward with a
     checkpoint every 20 steps, then the reverse sweep (segment recompute
-    included) for L = 1/2 |x_T - x_0|^2."""
+    included) for L = 1/2 |x_T - x_0|^2.  Timed twice: launched from the host
+    (every do-all one library call) and replayed from two captured HIP graphs
+    (forward from the step-0 checkpoint; reverse sweep), whose gradients must
+    equal the launched run's bit for bit."""
     import numpy as np
 
     from inputs import config_seed, spring_mesh
@@ -350,31 +397,55 @@ def measure_adjoint(torch, plain_updates_per_s):
     # one untimed pass first (module loads, block lists)
     sim.forward()
     sim.backward(torch.zeros(sim.N, device=sim.dev), torch.zeros(sim.N, device=sim.dev))
-    sim2 = DiffSpringSim(mesh, dt, T, every)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        ev = events(torch, 2)
+        ev[0].record()
+        fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1])
+
+    # launched from the host
+    sim.restart()
+    fwd = timed(sim.run_forward)
+    xT = sim.positions()
+    g = (xT - x0).contiguous()
+    sx, sy = g[:, 0].contiguous(), g[:, 1].contiguous()
+    bwd = timed(lambda: sim.run_backward(sx, sy))
+    want = [t.cpu().numpy() for t in sim.gradients()]
+    # captured once, replayed
+    gf, gb = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
     torch.cuda.synchronize()
-    e = events(torch, 3)
-    t0 = time.perf_counter()
-    e[0].record()
-    xT = sim2.forward()
-    e[1].record()
-    g = xT - x0
-    gk, gv, _ = sim2.backward(g[:, 0], g[:, 1])
-    e[2].record()
+    with torch.cuda.graph(gf):
+        st = torch.cuda.current_stream().cuda_stream
+        sim.restart(st)
+        sim.run_forward(st)
+    with torch.cuda.graph(gb):
+        sim.run_backward(sx, sy, stream=torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    fwd = e[0].elapsed_time(e[1])
-    bwd = e[1].elapsed_time(e[2])
-    per_step = sim2.N + sim2.S
-    res = {"workload": "316x317 spring mesh, 100,172 nodes, %d springs, breaking off, dt 1e-5" % sim2.S,
-           "steps": T, "checkpoint_every": every, "forward_ms": fwd, "backward_ms": bwd,
-           "backward_over_forward": bwd / fwd,
-           "forward_updates_per_s": T * per_step / (fwd * 1e-3),
-           "backward_updates_per_s": T * per_step / (bwd * 1e-3),
-           "backward_vs_plain_updates_per_s": T * per_step / (bwd * 1e-3) / plain_updates_per_s,
-           "loss": float(0.5 * (g ** 2).sum().item()), "grad_k_norm": float(gk.norm().item()),
-           "grad_v0_norm": float(gv.norm().item()), "host_wall_s": wall}
+    gfw, gbw = [], []
+    same = True
+    for _ in range(3):
+        gfw.append(timed(gf.replay))
+        gbw.append(timed(gb.replay))
+        got = [t.cpu().numpy() for t in sim.gradients()]
+        same = same and all(np.array_equal(a, b) for a, b in zip(got, want))
+    gfm, gbm = sorted(gfw)[1], sorted(gbw)[1]
+    per_step = sim.N + sim.S
+    gk, gv = want[0], want[1]
+    res = {"workload": "316x317 spring mesh, 100,172 nodes, %d springs, breaking off, dt 1e-5" % sim.S,
+           "steps": T, "checkpoint_every": every,
+           "launched": {"forward_ms": fwd, "backward_ms": bwd, "backward_over_forward": bwd / fwd},
+           "graph": {"forward_ms": gfm, "backward_ms": gbm, "backward_over_forward": gbm / gfm,
+                     "replays": 3, "gradients_equal_launched": bool(same)},
+           "forward_updates_per_s": T * per_step / (gfm * 1e-3),
+           "backward_updates_per_s": T * per_step / (gbm * 1e-3),
+           "backward_vs_plain_updates_per_s": T * per_step / (gbm * 1e-3) / plain_updates_per_s,
+           "loss": float(0.5 * (g.double() ** 2).sum().item()), "grad_k_norm": float(np.linalg.norm(gk)),
+           "grad_v0_norm": float(np.linalg.norm(gv))}
     sim.heap.close()
-    sim2.heap.close()
     return res
 
 

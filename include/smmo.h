@@ -109,7 +109,10 @@ typedef struct {
     uint32_t spin_limit;        /* bound on every retry loop; exceeding it sets
                                    SMMO_EDEVICE instead of hanging; default 1<<22 */
     uint32_t grid_waves;        /* wavefronts per method launch (0 = automatic) */
-    uint32_t reserved[10];
+    uint32_t block_group;       /* blocks a wavefront loads together before it
+                                   computes, in the methods that support it
+                                   (1, 2 or 4; 0 = each method's default) */
+    uint32_t reserved[9];
 } smmo_config;
 
 typedef struct {
@@ -248,13 +251,17 @@ smmo_status smmo_clear_error(smmo_heap *h, smmo_stream stream);
 smmo_status smmo_heap_info(const smmo_heap *h, uint64_t *blocks, uint32_t *block_bytes);
 
 /* Launch shape of `method_id` on class `class_id` for this heap (the
- * autotuner's knob): work-group size wg_threads (64, 128, 256, 512 or 1024;
- * 0 = default 256) and grid_waves wavefronts in total (0 = default, 64 per
- * CU).  Each wavefront walks blocks grid_waves apart, so blocks per
- * wavefront = ceil(blocks of the class / grid_waves).  Methods with a fixed
- * shape (nbody.force) ignore it. */
+ * autotuner's knobs): work-group size wg_threads (64, 128, 256, 512 or 1024;
+ * 0 = default 256), grid_waves wavefronts in total (0 = default, 64 per CU)
+ * and group, the number of blocks (1, 2 or 4; 0 = default) a wavefront loads
+ * together before it computes on them, in the methods that support it
+ * (spring.force, spring.node_update).  Each wavefront takes `group`
+ * consecutive entries of the class's block list per iteration and skips
+ * grid_waves * group entries, so blocks per wavefront = ceil(blocks of the
+ * class / grid_waves).  Methods with a fixed shape (nbody.force) ignore it.
+ * SMMO_EINVAL for another work-group size or group. */
 smmo_status smmo_set_launch(smmo_heap *h, uint32_t method_id, uint32_t class_id,
-                            uint32_t wg_threads, uint32_t grid_waves);
+                            uint32_t wg_threads, uint32_t grid_waves, uint32_t group);
 
 /* Method id of a method compiled into the library (names in smmo_methods.h),
  * SMMO_EINVAL if unknown. */

@@ -83,8 +83,21 @@ class DiffSpringSim:
         self.plane = 64 * self.heap.blocks
         nck = (self.T + self.every - 1) // self.every if self.T else 0
         self.ckpt = torch.empty(max(1, nck) * 4 * self.plane, dtype=torch.float32, device=dev)
-        self.tape = torch.empty(max(1, min(self.every, max(self.T, 1))) * 2 * self.plane,
-                                dtype=torch.float32, device=dev)
+        seg = max(1, min(self.every, max(self.T, 1)))
+        self.tape = torch.empty(seg * 2 * self.plane, dtype=torch.float32, device=dev)
+        # every launch of forward and backward, bound once (the seed launch
+        # names the caller's tensors and is bound per backward call)
+        B = smmo.BoundLaunch
+        hp = self.heap.h
+        self.L_force = B(hp, self.cs, ids["spring.force"], self.fargs) if S else None
+        self.L_node = B(hp, self.cn, ids["spring.node_update"], self.fargs)
+        self.L_save = [B(hp, self.cn, ids["adjoint.save"], self._aargs(self.ckpt, slot=c)) for c in range(nck)]
+        self.L_load = [B(hp, self.cn, ids["adjoint.load"], self._aargs(self.ckpt, slot=c)) for c in range(nck)]
+        self.L_record = [B(hp, self.cn, ids["adjoint.record"], self._aargs(self.tape, slot=t)) for t in range(seg)]
+        self.L_anode = {m: B(hp, self.cn, ids["adjoint.node"], self._aargs(self.tape, mode=m)) for m in (1, 2, 3)}
+        self.L_aspring = [B(hp, self.cs, ids["adjoint.spring"], self._aargs(self.tape, slot=t))
+                          for t in range(seg)] if S else None
+        self.L_zero = B(hp, self.cs, ids["adjoint.zero"], self._aargs(self.tape)) if S else None
 
     # ------------------------------------------------------------ helpers --
     def _do(self, cls, name, args):
@@ -96,18 +109,37 @@ class DiffSpringSim:
                                       self.plane, slot, count, P[0] or None, P[1] or None,
                                       P[2] or None, P[3] or None)
 
-    def step(self):
-        self._do(self.cs, "spring.force", self.fargs)
-        self._do(self.cn, "spring.node_update", self.fargs)
+    def _stream(self):
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def step(self, stream=None):
+        st = self._stream() if stream is None else stream
+        if self.L_force is not None:
+            self.L_force(st)
+        self.L_node(st)
 
     # ------------------------------------------------------------ forward --
     def forward(self):
         """T steps; checkpoints at 0, every, 2 every, ...  Returns x_T as (N, 2) by node id."""
+        self.run_forward()
+        return self.positions()
+
+    def restart(self, stream=None):
+        """Restores positions and velocities saved at step 0 by the last
+        forward run, so that forward and backward can run again (for
+        instance replayed from a captured HIP graph)."""
+        if not self.L_save:
+            return
+        self.L_load[0](self._stream() if stream is None else stream)
+
+    def run_forward(self, stream=None):
+        """The T forward steps with their checkpoints, launched on `stream`
+        (default: the current stream); no host synchronization."""
+        st = self._stream() if stream is None else stream
         for n in range(self.T):
             if n % self.every == 0:
-                self._do(self.cn, "adjoint.save", self._aargs(self.ckpt, slot=n // self.every))
-            self.step()
-        return self.positions()
+                self.L_save[n // self.every](st)
+            self.step(st)
 
     def positions(self):
         torch = self.torch
@@ -122,31 +154,40 @@ class DiffSpringSim:
     def backward(self, gx, gy, gvx=None, gvy=None):
         """Reverse sweep from dL/dx_T (and dL/dv_T, default 0), tensors of N by
         node id.  Returns (dL/dk by spring id, dL/dv0 (N, 2), dL/dx0 (N, 2))."""
+        self.run_backward(gx, gy, gvx, gvy)
+        self.heap.sync()
+        return self.gradients()
+
+    def run_backward(self, gx, gy, gvx=None, gvy=None, stream=None):
+        """The reverse sweep's launches on `stream` (default: the current
+        stream); no host synchronization.  The seed tensors must stay alive
+        until the sweep has run."""
         torch = self.torch
+        st = self._stream() if stream is None else stream
         seeds = [t.detach().to(device=self.dev, dtype=torch.float32).contiguous() if t is not None else None
                  for t in (gx, gy, gvx, gvy)]
-        self._do(self.cn, "adjoint.seed", self._aargs(self.tape, seeds=seeds, count=self.N))
-        if self.S:
-            self._do(self.cs, "adjoint.zero", self._aargs(self.tape))
+        self._seeds = seeds
+        smmo.BoundLaunch(self.heap.h, self.cn, self.mid["adjoint.seed"],
+                         self._aargs(self.tape, seeds=seeds, count=self.N))(st)
+        if self.L_zero is not None:
+            self.L_zero(st)
         first = True
         nseg = (self.T + self.every - 1) // self.every
         for seg in range(nseg - 1, -1, -1):
             n0 = seg * self.every
             n1 = min(n0 + self.every, self.T)
-            self._do(self.cn, "adjoint.load", self._aargs(self.ckpt, slot=seg))
+            self.L_load[seg](st)
             for t in range(n1 - n0):
-                self._do(self.cn, "adjoint.record", self._aargs(self.tape, slot=t))
+                self.L_record[t](st)
                 if t < n1 - n0 - 1:       # the segment's last step is not needed
-                    self.step()
+                    self.step(st)
             for t in range(n1 - n0 - 1, -1, -1):
-                self._do(self.cn, "adjoint.node", self._aargs(self.tape, mode=2 if first else 3))
+                self.L_anode[2 if first else 3](st)
                 first = False
-                if self.S:
-                    self._do(self.cs, "adjoint.spring", self._aargs(self.tape, slot=t))
+                if self.L_aspring is not None:
+                    self.L_aspring[t](st)
         if not first:
-            self._do(self.cn, "adjoint.node", self._aargs(self.tape, mode=1))
-        self.heap.sync()
-        return self.gradients()
+            self.L_anode[1](st)
 
     def gradients(self):
         torch = self.torch

@@ -1,9 +1,9 @@
 """Autotuner of do-all launch shapes.
 
-A do-all launch has two knobs (``smmo_set_launch``): the work-group size
-(64 .. 1024 threads) and the total number of wavefronts; each wavefront walks
-the class's blocks that far apart, so blocks per wavefront = ceil(blocks /
-wavefronts).  ``tune`` times every candidate with HIP events over repeated
+A do-all launch has three knobs (``smmo_set_launch``): the work-group size
+(64 .. 1024 threads), the total number of wavefronts and, in the methods that
+support it, the group: how many blocks a wavefront loads together before it
+computes (1, 2 or 4).  Blocks per wavefront = ceil(blocks / wavefronts).  ``tune`` times every candidate with HIP events over repeated
 launches of the method with arguments that make it idempotent (the caller
 supplies them, e.g. dt = 0 for an update), keeps the fastest, applies it to
 the heap and stores it in a JSON cache keyed by (method, class layout,
@@ -53,9 +53,10 @@ def time_launches(heap, method: str, cls_name: str, args, repeat: int) -> float:
 
 
 def tune(heap, method: str, cls_name: str, args, repeat: int = 20, wg_sizes=DEFAULT_WG,
-         waves_per_cu=DEFAULT_WAVES_PER_CU, cache_path: str | None = None) -> dict:
-    """Times every (work-group size, wavefronts) candidate, applies the best.
-    Returns {"wg", "waves", "us", "tried": [...]}."""
+         waves_per_cu=DEFAULT_WAVES_PER_CU, groups=(0,), cache_path: str | None = None) -> dict:
+    """Times every (work-group size, wavefronts, group) candidate, applies the
+    best.  groups=(0,) keeps the method's default group.
+    Returns {"wg", "waves", "group", "us", "tried": [...]}."""
     import torch
 
     cus = _cu_count(torch)
@@ -65,22 +66,25 @@ def tune(heap, method: str, cls_name: str, args, repeat: int = 20, wg_sizes=DEFA
     blocks = int(st.blocks[cls])
     tried = []
     best = None
-    for wg in wg_sizes:
-        for wpc in waves_per_cu:
-            waves = wpc * cus
-            smmo.smmo_set_launch(heap.h, mid, cls, wg, waves)
-            t = time_launches(heap, method, cls_name, args, repeat)
-            tried.append({"wg": wg, "waves": waves, "us": t * 1e6})
-            if best is None or t < best[2]:
-                best = (wg, waves, t)
-    smmo.smmo_set_launch(heap.h, mid, cls, best[0], best[1])
-    res = {"wg": best[0], "waves": best[1], "us": best[2] * 1e6, "blocks": blocks, "tried": tried}
+    for grp in groups:
+        for wg in wg_sizes:
+            for wpc in waves_per_cu:
+                waves = wpc * cus
+                smmo.smmo_set_launch(heap.h, mid, cls, wg, waves, grp)
+                t = time_launches(heap, method, cls_name, args, repeat)
+                tried.append({"wg": wg, "waves": waves, "group": grp, "us": t * 1e6})
+                if best is None or t < best[3]:
+                    best = (wg, waves, grp, t)
+    smmo.smmo_set_launch(heap.h, mid, cls, best[0], best[1], best[2])
+    res = {"wg": best[0], "waves": best[1], "group": best[2], "us": best[3] * 1e6, "blocks": blocks,
+           "tried": tried}
     if cache_path:
         cache = {}
         if os.path.exists(cache_path):
             with open(cache_path) as f:
                 cache = json.load(f)
-        cache[_key(heap, method, cls_name, blocks)] = {"wg": best[0], "waves": best[1], "us": best[2] * 1e6}
+        cache[_key(heap, method, cls_name, blocks)] = {"wg": best[0], "waves": best[1], "group": best[2],
+                                                      "us": best[3] * 1e6}
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return res
@@ -97,5 +101,5 @@ def apply_cached(heap, method: str, cls_name: str, cache_path: str) -> dict | No
     ent = cache.get(_key(heap, method, cls_name, blocks))
     if ent is None:
         return None
-    smmo.smmo_set_launch(heap.h, smmo.smmo_method_id(method), cls, ent["wg"], ent["waves"])
+    smmo.smmo_set_launch(heap.h, smmo.smmo_method_id(method), cls, ent["wg"], ent["waves"], ent.get("group", 0))
     return ent

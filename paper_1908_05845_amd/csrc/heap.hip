@@ -529,7 +529,7 @@ smmo_status run_stats(smmo_heap *h, hipStream_t st)
     smmo_status s = launch_check("k_stats");
     if (s) return s;
     h->last = st;
-    return read_ctrl(h, 0, CTRL_STATS + nw);
+    return read_ctrl(h, 0, kCtrlWords);
 }
 
 } // namespace
@@ -591,19 +591,23 @@ smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStre
     return SMMO_OK;
 }
 
-LaunchShape method_shape(const smmo_heap *h, uint32_t cls)
+LaunchShape method_shape(const smmo_heap *h, uint32_t cls, uint32_t def_group)
 {
     uint32_t wg = 256;
     uint64_t waves = h->cfg.grid_waves ? h->cfg.grid_waves : 64ull * h->cu_count;
+    uint32_t group = def_group == 0 ? 1 : h->cfg.block_group ? h->cfg.block_group : def_group;
     if (h->cur_method < 64) {
         if (h->launch_wg[h->cur_method][cls]) wg = h->launch_wg[h->cur_method][cls];
         if (h->launch_waves[h->cur_method][cls]) waves = h->launch_waves[h->cur_method][cls];
+        if (def_group && h->launch_group[h->cur_method][cls]) group = h->launch_group[h->cur_method][cls];
     }
-    waves = std::min<uint64_t>(waves, std::max<uint64_t>(1, h->ub_blocks[cls]));
+    const uint64_t groups = (std::max<uint64_t>(1, h->ub_blocks[cls]) + group - 1) / group;
+    waves = std::min<uint64_t>(waves, groups);
     const uint32_t wpg = wg / 64;
     LaunchShape ls;
     ls.grid = dim3((uint32_t)((waves + wpg - 1) / wpg));
     ls.block = dim3(wg);
+    ls.group = group;
     return ls;
 }
 
@@ -734,6 +738,8 @@ smmo_status smmo_alloc_heap(smmo_schema *s, void *dev_buf, size_t bytes, const s
     else smmo_config_default(&c);
     if (c.lookup_retries == 0) c.lookup_retries = 1;
     if (c.spin_limit < 1024) c.spin_limit = 1024;
+    if (c.block_group != 0 && c.block_group != 1 && c.block_group != 2 && c.block_group != 4)
+        return fail(SMMO_EINVAL, "block_group must be 0, 1, 2 or 4");
     const uint32_t bb = schema_block_bytes(s);
     // largest M whose layout fits
     uint64_t lo = 0, hi = std::min<uint64_t>(bytes / bb, kMaxBlocks);
@@ -876,7 +882,7 @@ smmo_status smmo_parallel_do(smmo_heap *h, uint32_t class_id, uint32_t method_id
 }
 
 smmo_status smmo_set_launch(smmo_heap *h, uint32_t method_id, uint32_t class_id, uint32_t wg_threads,
-                            uint32_t grid_waves)
+                            uint32_t grid_waves, uint32_t group)
 {
     smmo_status s = check_class(h, class_id);
     if (s) return s;
@@ -886,7 +892,10 @@ smmo_status smmo_set_launch(smmo_heap *h, uint32_t method_id, uint32_t class_id,
     if (wg_threads != 0 && wg_threads != 64 && wg_threads != 128 && wg_threads != 256 && wg_threads != 512 &&
         wg_threads != 1024)
         return fail(SMMO_EINVAL, "work-group size must be 0 or one of 64, 128, 256, 512, 1024");
+    if (group != 0 && group != 1 && group != 2 && group != 4)
+        return fail(SMMO_EINVAL, "group must be 0, 1, 2 or 4");
     h->launch_wg[method_id][class_id] = (uint16_t)wg_threads;
+    h->launch_group[method_id][class_id] = (uint8_t)group;
     h->launch_waves[method_id][class_id] = grid_waves;
     return SMMO_OK;
 }
@@ -958,10 +967,13 @@ smmo_status smmo_heap_stats(smmo_heap *h, smmo_stats *out)
     out->total_blocks = h->v.M;
     out->fragmentation = slots ? (double)(slots - used) / (double)slots : 0.0;
     out->block_bytes = (uint32_t)h->v.block_bytes;
-    out->slow_paths = *reinterpret_cast<const uint64_t *>(w + CTRL_SLOW);
-    out->alloc_retries = *reinterpret_cast<const uint64_t *>(w + CTRL_RETRY);
-    out->device_news = *reinterpret_cast<const uint64_t *>(w + CTRL_NEWS);
-    out->device_deletes = *reinterpret_cast<const uint64_t *>(w + CTRL_DELS);
+    for (uint32_t k = 0; k < kEventStripes; ++k) {
+        const uint32_t *e = w + CTRL_EVENTS + k * kStripeWords;
+        out->slow_paths += *reinterpret_cast<const uint64_t *>(e + EV_SLOW);
+        out->alloc_retries += *reinterpret_cast<const uint64_t *>(e + EV_RETRY);
+        out->device_news += *reinterpret_cast<const uint64_t *>(e + EV_NEWS);
+        out->device_deletes += *reinterpret_cast<const uint64_t *>(e + EV_DELS);
+    }
     const uint32_t err = w[CTRL_ERR];
     out->device_error = err == 0 ? SMMO_OK : (err == ERR_NOMEM ? SMMO_ENOMEM : SMMO_EDEVICE);
     return SMMO_OK;

@@ -60,6 +60,38 @@ __device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, 
     }
 }
 
+// Calls f(bid, bm, own) for the blocks of class `cls` in R, U at a time: a
+// wavefront takes U consecutive R entries per iteration (consecutive blocks of
+// an ordered bulk allocation, whose objects share their neighbours) and loads
+// every block id, type and bitmap before f runs, so that f can issue the
+// loads of all U blocks before it waits for any.  own[j] says whether entry j
+// is a block of the class; for an entry past the end of R, bid[j] repeats a
+// valid block and own[j] is false; bm[j] is 0 whenever own[j] is false.  f may
+// load from any bid[j] but must store only to blocks it owns.
+template <int U, class F>
+__device__ __forceinline__ void for_each_block_group(const HeapView &h, uint32_t cls, F &&f)
+{
+    const uint32_t r = __builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_RFINAL + cls));
+    const uint32_t *R = h.R + (uint64_t)cls * h.M;
+    const uint32_t wpg = blockDim.x >> 6;
+    const uint32_t step = gridDim.x * wpg * U;
+    for (uint32_t base = (xcd_logical_wg() * wpg + (threadIdx.x >> 6)) * U; base < r; base += step) {
+        uint32_t bid[U];
+        uint64_t bm[U];
+        bool own[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) bid[j] = __builtin_amdgcn_readfirstlane(R[base + j < r ? base + j : base]);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid[j]]);
+            const uint64_t b = uniform64(h.alloc_bm[bid[j]]);
+            own[j] = base + j < r && t == cls;
+            bm[j] = own[j] ? b : 0;
+        }
+        f(bid, bm, own);
+    }
+}
+
 template <class T>
 __device__ __forceinline__ T *farr(const HeapView &h, uint32_t bid, uint32_t off)
 {

@@ -309,94 +309,126 @@ __device__ __forceinline__ bool spring_breaks(float dx, float dy, float L0, floa
 
 // Spring::compute_force (Ch.7 "structure"): Hooke's law on the length change;
 // a spring strained past the limit empties its two adjacency slots and
-// deletes itself (the thesis's remove_spring followed by destroy).
+// deletes itself (the thesis's remove_spring followed by destroy).  A
+// wavefront works on U blocks at once: the spring fields of all U blocks are
+// loaded, then all position gathers issued, then the forces computed.
+template <int U>
 __global__ __launch_bounds__(1024) void k_spring_force(HeapView h, SpringK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        const bool live = (bm >> s) & 1;
-        // the block's own fields for all 64 slots (one contiguous run each);
-        // gathers through the node handles only for live slots
-        const uint32_t a = farr<uint32_t>(h, bid, p.s_a)[s];
-        const uint32_t b = farr<uint32_t>(h, bid, p.s_b)[s];
-        const float k = farr<float>(h, bid, p.s_k)[s];
-        const float L0 = farr<float>(h, bid, p.s_L0)[s];
-        float xa = 0.f, ya = 0.f, xb = 0.f, yb = 0.f;
-        if (live) {
-            xa = fref<float>(h, a, p.n_x);
-            ya = fref<float>(h, a, p.n_y);
-            xb = fref<float>(h, b, p.n_x);
-            yb = fref<float>(h, b, p.n_y);
+    const uint32_t s = lane_id();
+    for_each_block_group<U>(h, p.spring_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
+        uint32_t a[U], b[U];
+        float k[U], L0[U], xa[U], ya[U], xb[U], yb[U];
+        bool live[U];
+        // the blocks' own fields for all 64 slots (one contiguous run each)
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            live[j] = (bm[j] >> s) & 1;
+            a[j] = farr<uint32_t>(h, bid[j], p.s_a)[s];
+            b[j] = farr<uint32_t>(h, bid[j], p.s_b)[s];
+            k[j] = farr<float>(h, bid[j], p.s_k)[s];
+            L0[j] = farr<float>(h, bid[j], p.s_L0)[s];
         }
-        const float dx = xb - xa, dy = yb - ya;
-        float l;
-        const bool brk = live && spring_breaks(dx, dy, L0, p.limit, l);
-        float fx = 0.f, fy = 0.f;
-        if (live && !brk) {
-            const float c = k * (l - L0) / l;
-            fx = c * dx;
-            fy = c * dy;
+        // gathers through the node handles, live slots only
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            xa[j] = ya[j] = xb[j] = yb[j] = 0.f;
+            if (live[j]) {
+                xa[j] = fref<float>(h, a[j], p.n_x);
+                ya[j] = fref<float>(h, a[j], p.n_y);
+                xb[j] = fref<float>(h, b[j], p.n_x);
+                yb[j] = fref<float>(h, b[j], p.n_y);
+            }
         }
-        // full-width stores: dead and broken slots get 0, never read
-        farr<float>(h, bid, p.s_fx)[s] = fx;
-        farr<float>(h, bid, p.s_fy)[s] = fy;
-        if (brk) {
-            const uint32_t qa = farr<uint8_t>(h, bid, p.s_sa)[s];
-            const uint32_t qb = farr<uint8_t>(h, bid, p.s_sb)[s];
-            fref<uint32_t>(h, a, p.n_adj + qa * p.n_adj_stride) = kNull;
-            fref<uint32_t>(h, b, p.n_adj + qb * p.n_adj_stride) = kNull;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (!own[j]) continue;
+            const float dx = xb[j] - xa[j], dy = yb[j] - ya[j];
+            float l;
+            const bool brk = live[j] && spring_breaks(dx, dy, L0[j], p.limit, l);
+            float fx = 0.f, fy = 0.f;
+            if (live[j] && !brk) {
+                const float c = k[j] * (l - L0[j]) / l;
+                fx = c * dx;
+                fy = c * dy;
+            }
+            // full-width stores: dead and broken slots get 0, never read
+            farr<float>(h, bid[j], p.s_fx)[s] = fx;
+            farr<float>(h, bid[j], p.s_fy)[s] = fy;
+            if (brk) {
+                const uint32_t qa = farr<uint8_t>(h, bid[j], p.s_sa)[s];
+                const uint32_t qb = farr<uint8_t>(h, bid[j], p.s_sb)[s];
+                fref<uint32_t>(h, a[j], p.n_adj + qa * p.n_adj_stride) = kNull;
+                fref<uint32_t>(h, b[j], p.n_adj + qb * p.n_adj_stride) = kNull;
+            }
+            wave_release_own_block(h, p.spring_cls, bid[j], __ballot(brk));
         }
-        wave_release_own_block(h, p.spring_cls, bid, __ballot(brk));
     });
 }
 
 // Node::update: sum the attached springs' forces in slot order (+f if this
-// node is endpoint a, -f if b), then v += F/m dt, x += v dt.
+// node is endpoint a, -f if b), then v += F/m dt, x += v dt.  U blocks at
+// once, as in the force kernel.
+template <int U>
 __global__ __launch_bounds__(1024) void k_spring_node(HeapView h, SpringK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        const bool live = (bm >> s) & 1;
-        uint32_t e[8];
+    const uint32_t s = lane_id();
+    for_each_block_group<U>(h, p.node_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
+        uint32_t e[U][8];
+        float m[U], x[U], y[U], vx[U], vy[U], Fx[U], Fy[U];
+        bool live[U];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) e[q] = farr<uint32_t>(h, bid, p.n_adj + q * p.n_adj_stride)[s];
-        const float m = farr<float>(h, bid, p.n_m)[s];
-        float x = farr<float>(h, bid, p.n_x)[s], y = farr<float>(h, bid, p.n_y)[s];
-        float vx = farr<float>(h, bid, p.n_vx)[s], vy = farr<float>(h, bid, p.n_vy)[s];
-        float gx[8], gy[8];
+        for (int j = 0; j < U; ++j) {
+            live[j] = (bm[j] >> s) & 1;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            gx[q] = 0.f;
-            gy[q] = 0.f;
-            if (live && e[q] != kNull) {
-                const uint32_t sh = e[q] & 0x7FFFFFFFu;
-                gx[q] = fref<float>(h, sh, p.s_fx);
-                gy[q] = fref<float>(h, sh, p.s_fy);
+            for (int q = 0; q < 8; ++q) e[j][q] = farr<uint32_t>(h, bid[j], p.n_adj + q * p.n_adj_stride)[s];
+            m[j] = farr<float>(h, bid[j], p.n_m)[s];
+            x[j] = farr<float>(h, bid[j], p.n_x)[s];
+            y[j] = farr<float>(h, bid[j], p.n_y)[s];
+            vx[j] = farr<float>(h, bid[j], p.n_vx)[s];
+            vy[j] = farr<float>(h, bid[j], p.n_vy)[s];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            float gx[8], gy[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                gx[q] = 0.f;
+                gy[q] = 0.f;
+                if (live[j] && e[j][q] != kNull) {
+                    const uint32_t sh = e[j][q] & 0x7FFFFFFFu;
+                    gx[q] = fref<float>(h, sh, p.s_fx);
+                    gy[q] = fref<float>(h, sh, p.s_fy);
+                }
+            }
+            Fx[j] = 0.f;
+            Fy[j] = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (e[j][q] == kNull) continue;
+                if (e[j][q] >> 31) {
+                    Fx[j] -= gx[q];
+                    Fy[j] -= gy[q];
+                } else {
+                    Fx[j] += gx[q];
+                    Fy[j] += gy[q];
+                }
             }
         }
-        float Fx = 0.f, Fy = 0.f;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (e[q] == kNull) continue;
-            if (e[q] >> 31) {
-                Fx -= gx[q];
-                Fy -= gy[q];
-            } else {
-                Fx += gx[q];
-                Fy += gy[q];
-            }
+        for (int j = 0; j < U; ++j) {
+            if (!live[j]) continue;
+            vx[j] += Fx[j] / m[j] * p.dt;
+            vy[j] += Fy[j] / m[j] * p.dt;
+            x[j] += vx[j] * p.dt;
+            y[j] += vy[j] * p.dt;
+            farr<float>(h, bid[j], p.n_vx)[s] = vx[j];
+            farr<float>(h, bid[j], p.n_vy)[s] = vy[j];
+            farr<float>(h, bid[j], p.n_x)[s] = x[j];
+            farr<float>(h, bid[j], p.n_y)[s] = y[j];
         }
-        if (!live) return;
-        vx += Fx / m * p.dt;
-        vy += Fy / m * p.dt;
-        x += vx * p.dt;
-        y += vy * p.dt;
-        farr<float>(h, bid, p.n_vx)[s] = vx;
-        farr<float>(h, bid, p.n_vy)[s] = vy;
-        farr<float>(h, bid, p.n_x)[s] = x;
-        farr<float>(h, bid, p.n_y)[s] = y;
     });
 }
 
@@ -451,6 +483,9 @@ smmo_status bind_spring(smmo_heap *h, const smmo_spring_args &a, SpringK &k)
     return SMMO_OK;
 }
 
+// blocks per wavefront iteration of the spring do-alls unless set otherwise
+constexpr uint32_t kSpringGroup = 1;
+
 template <int Which>
 smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
 {
@@ -463,10 +498,21 @@ smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStrea
     if (cls != (Which == 1 ? a.node_class : a.spring_class))
         return fail(SMMO_EINVAL, "spring: method runs on a different class");
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
-    const LaunchShape ls = method_shape(h, cls);
-    if (Which == 0) hipLaunchKernelGGL(k_spring_force, ls.grid, ls.block, 0, st, h->v, k);
-    if (Which == 1) hipLaunchKernelGGL(k_spring_node, ls.grid, ls.block, 0, st, h->v, k);
-    if (Which == 2) hipLaunchKernelGGL(k_spring_link, ls.grid, ls.block, 0, st, h->v, k);
+    const LaunchShape ls = method_shape(h, cls, kSpringGroup);
+    if (Which == 0) {
+        if (ls.group == 4) hipLaunchKernelGGL(k_spring_force<4>, ls.grid, ls.block, 0, st, h->v, k);
+        else if (ls.group == 2) hipLaunchKernelGGL(k_spring_force<2>, ls.grid, ls.block, 0, st, h->v, k);
+        else hipLaunchKernelGGL(k_spring_force<1>, ls.grid, ls.block, 0, st, h->v, k);
+    }
+    if (Which == 1) {
+        if (ls.group == 4) hipLaunchKernelGGL(k_spring_node<4>, ls.grid, ls.block, 0, st, h->v, k);
+        else if (ls.group == 2) hipLaunchKernelGGL(k_spring_node<2>, ls.grid, ls.block, 0, st, h->v, k);
+        else hipLaunchKernelGGL(k_spring_node<1>, ls.grid, ls.block, 0, st, h->v, k);
+    }
+    if (Which == 2) {
+        const LaunchShape l1 = method_shape(h, cls);
+        hipLaunchKernelGGL(k_spring_link, l1.grid, l1.block, 0, st, h->v, k);
+    }
     return launched("spring kernel");
 }
 

@@ -57,17 +57,16 @@ __device__ __forceinline__ void raise_error(const HeapView &h, uint32_t bits)
     __hip_atomic_fetch_or(h.ctrl + CTRL_ERR, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void count_event(const HeapView &h, uint32_t word)
+// adds n to event counter `ev` in this wavefront's stripe
+__device__ __forceinline__ void count_events(const HeapView &h, uint32_t ev, uint64_t n)
 {
-    __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(h.ctrl + word), 1ull,
+    const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    uint32_t *w = h.ctrl + CTRL_EVENTS + (wave % kEventStripes) * kStripeWords + ev;
+    __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(w), (unsigned long long)n,
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void count_events(const HeapView &h, uint32_t word, uint64_t n)
-{
-    __hip_atomic_fetch_add(reinterpret_cast<unsigned long long *>(h.ctrl + word), (unsigned long long)n,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ void count_event(const HeapView &h, uint32_t ev) { count_events(h, ev, 1); }
 
 __device__ __forceinline__ bool heap_failed(const HeapView &h)
 {
@@ -357,7 +356,7 @@ __device__ __forceinline__ void release_slots(const HeapView &h, uint32_t cls, u
         raise_error(h, ERR_BADHANDLE);   // releasing a free slot
         return;
     }
-    count_events(h, CTRL_DELS, (uint64_t)__popcll(mask));
+    count_events(h, EV_DELS, (uint64_t)__popcll(mask));
     if (prev == ~0ull) q.push(bm_active(cls), bid, +1);
     if ((prev & ~mask) == 0) invalidate_block(h, bid, q);
 }
@@ -384,7 +383,7 @@ __device__ __forceinline__ uint32_t leader_allocate(const HeapView &h, uint32_t 
             initialize_block(h, (uint32_t)bid, cls);
             switch_bit_lane(h, bm_alloc(cls), (uint32_t)bid, +1);
             switch_bit_lane(h, bm_active(cls), (uint32_t)bid, +1);
-            count_event(h, CTRL_SLOW);
+            count_event(h, EV_SLOW);
         }
         bool filled;
         const uint64_t g = reserve_slots(h, (uint32_t)bid, n, filled);
@@ -393,7 +392,7 @@ __device__ __forceinline__ uint32_t leader_allocate(const HeapView &h, uint32_t 
             if (filled) switch_bit_lane(h, bm_active(t), (uint32_t)bid, -1);
             if (t == cls) {
                 got = g;
-                count_events(h, CTRL_NEWS, (uint64_t)__popcll(g));
+                count_events(h, EV_NEWS, (uint64_t)__popcll(g));
                 return (uint32_t)bid;
             }
             OpQueue q;                     // block re-typed meanwhile: roll back
@@ -401,7 +400,7 @@ __device__ __forceinline__ uint32_t leader_allocate(const HeapView &h, uint32_t 
             release_slots(h, t, (uint32_t)bid, g, q);
             run_ops_lane(h, q);
         }
-        count_event(h, CTRL_RETRY);
+        count_event(h, EV_RETRY);
     }
     raise_error(h, ERR_SPIN);
     return kNoBlock;

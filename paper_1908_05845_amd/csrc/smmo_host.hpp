@@ -64,6 +64,7 @@ struct smmo_heap {
     // launch shape per (method, class) set by smmo_set_launch (0 = default)
     uint16_t launch_wg[64][SMMO_MAX_CLASSES] = {};
     uint32_t launch_waves[64][SMMO_MAX_CLASSES] = {};
+    uint8_t launch_group[64][SMMO_MAX_CLASSES] = {};
     uint32_t cur_method = 0xFFFFFFFFu;     // method being launched by smmo_parallel_do
 };
 
@@ -86,12 +87,16 @@ smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStre
 
 // launch shape of a do-all over class cls: the (method, class) setting of
 // smmo_set_launch if any, else 256-thread work-groups and 64 wavefronts per
-// CU, never more wavefronts than the class can have blocks
+// CU, never more wavefronts than the class has groups of blocks; group =
+// blocks a wavefront takes per iteration: 1 for a method without groups
+// (def_group 0), else the setting, else the heap's block_group, else the
+// method's default def_group
 struct LaunchShape {
     dim3 grid;
     dim3 block;
+    uint32_t group;
 };
-LaunchShape method_shape(const smmo_heap *h, uint32_t cls);
+LaunchShape method_shape(const smmo_heap *h, uint32_t cls, uint32_t def_group = 0);
 
 // bookkeeping after a launch that creates objects of class cls
 void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects);

@@ -35,7 +35,13 @@ constexpr uint32_t kNoBlock = 0xFFFFFFFFu;
 constexpr uint32_t kMaxLevels = 6;
 constexpr uint32_t kMaxClasses = 16;
 constexpr uint32_t kMaxBlocks = (1u << 25) - 2;
-constexpr uint32_t kCtrlWords = 1024;         // 4 KiB of control words
+// Event counters are striped: 64 stripes of 128 bytes each, a wavefront
+// adds to stripe (its global wavefront id mod 64), so that concurrent
+// allocations and deletions do not all hit one address; readers sum them.
+constexpr uint32_t kEventStripes = 64;
+constexpr uint32_t kStripeWords = 32;
+constexpr uint32_t CTRL_EVENTS = 1024;        // first word of stripe 0
+constexpr uint32_t kCtrlWords = CTRL_EVENTS + kEventStripes * kStripeWords;   // 12 KiB
 
 constexpr uint32_t BM_FREE = 0;
 __host__ __device__ constexpr uint32_t bm_alloc(uint32_t c) { return 1 + 2 * c; }
@@ -52,16 +58,20 @@ enum : uint32_t {
 // control word indices (uint32 units; 64-bit counters take two words)
 enum : uint32_t {
     CTRL_ERR = 0,
-    CTRL_SLOW = 2,        // u64: blocks initialized by device allocation
-    CTRL_RETRY = 4,       // u64: failed slot reservations (retried)
     CTRL_GCOUNT = 8,      // gather: running output count
     CTRL_GDONE = 9,       // gather: finished wavefronts
-    CTRL_NEWS = 10,       // u64: objects created by device allocation
-    CTRL_DELS = 12,       // u64: objects released by device deallocation
     CTRL_RCOUNT = 16,     // [class] enumeration: running length of R
     CTRL_RDONE = 32,      // [class] enumeration: finished wavefronts
     CTRL_RFINAL = 48,     // [class] length of R after the last enumeration
     CTRL_STATS = 128,     // u64 statistics / invariant results (host reads)
+};
+
+// u64 event counters inside each stripe (word offsets)
+enum : uint32_t {
+    EV_SLOW = 0,          // blocks initialized by device allocation
+    EV_RETRY = 2,         // failed slot reservations (retried)
+    EV_NEWS = 4,          // objects created by device allocation
+    EV_DELS = 6,          // objects released by device deallocation
 };
 
 // statistics block (u64 words starting at CTRL_STATS)

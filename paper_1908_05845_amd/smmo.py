@@ -45,7 +45,7 @@ class smmo_field_desc(C.Structure):
 class smmo_config(C.Structure):
     _fields_ = [("lookup_retries", C.c_uint32), ("rotation", C.c_uint32), ("coalescing", C.c_uint32),
                 ("bulk_ordered", C.c_uint32), ("spin_limit", C.c_uint32), ("grid_waves", C.c_uint32),
-                ("reserved", C.c_uint32 * 10)]
+                ("block_group", C.c_uint32), ("reserved", C.c_uint32 * 9)]
 
 
 class smmo_stats(C.Structure):
@@ -146,7 +146,7 @@ def load_library(path: str = LIB_PATH):
             "smmo_clear_error": (S, [P, P]),
             "smmo_heap_info": (S, [P, P, P]),
             "smmo_method_id": (S, [C.c_char_p, P]),
-            "smmo_set_launch": (S, [P, U32, U32, U32, U32]),
+            "smmo_set_launch": (S, [P, U32, U32, U32, U32, U32]),
             "smmo_last_error": (S, [C.c_char_p, C.c_size_t]),
         }
         for name, (res, args) in sig.items():
@@ -271,6 +271,27 @@ def smmo_parallel_do(heap, class_id: int, method_id: int, args=None, stream=None
                                      0 if args is None else C.sizeof(args), _stream(stream)))
 
 
+class BoundLaunch:
+    """One do-all with its heap, class, method and argument struct fixed, for
+    drivers that issue many launches: a call is one foreign call of
+    smmo_parallel_do on the given stream (the struct is kept alive here and
+    passed by reference), and a nonzero status raises SmmoError."""
+
+    __slots__ = ("lib", "fn", "h", "cls", "mid", "args", "ref", "size")
+
+    def __init__(self, heap, class_id: int, method_id: int, args):
+        self.lib = load_library()
+        self.fn = self.lib.smmo_parallel_do
+        self.h, self.cls, self.mid, self.args = heap, class_id, method_id, args
+        self.ref = C.byref(args)
+        self.size = C.sizeof(args)
+
+    def __call__(self, stream) -> None:
+        st = self.fn(self.h, self.cls, self.mid, self.ref, self.size, stream)
+        if st:
+            raise SmmoError(st, _last_error(self.lib))
+
+
 def smmo_destroy(heap, class_id: int, handles, n: int, stream=None) -> None:
     lib = load_library()
     _check(lib, lib.smmo_destroy(heap, class_id, _ptr(handles), n, _stream(stream)))
@@ -325,9 +346,10 @@ def smmo_method_id(name: str) -> int:
     return out.value
 
 
-def smmo_set_launch(heap, method_id: int, class_id: int, wg_threads: int = 0, grid_waves: int = 0) -> None:
+def smmo_set_launch(heap, method_id: int, class_id: int, wg_threads: int = 0, grid_waves: int = 0,
+                    group: int = 0) -> None:
     lib = load_library()
-    _check(lib, lib.smmo_set_launch(heap, method_id, class_id, wg_threads, grid_waves))
+    _check(lib, lib.smmo_set_launch(heap, method_id, class_id, wg_threads, grid_waves, group))
 
 
 def smmo_last_error() -> str:

@@ -285,3 +285,26 @@ def test_gather_capacity_and_bad_method_binding(dev):
     with pytest.raises(smmo.SmmoError):
         smmo.smmo_parallel_do(heap.h, heap.cls["A"], smmo.smmo_method_id("test.axpy"),
                               smmo.smmo_spawn_args(0, 1, 0, 1, 1, 0))   # wrong argument struct size
+
+
+def test_launch_shape_validation(dev):
+    """smmo_set_launch and the heap configuration reject shapes outside the
+    documented sets; a method without block groups ignores the group knob."""
+    import torch
+
+    with pytest.raises(smmo.SmmoError) as e:
+        smmo.Heap(ALL, blocks=16, cfg=cfg(block_group=3))
+    assert e.value.status == smmo.SMMO_EINVAL
+    heap = smmo.Heap(ALL, blocks=64)
+    mid = smmo.smmo_method_id("test.axpy")
+    a = heap.cls["A"]
+    for bad in ((96, 0, 0), (0, 0, 3), (2048, 0, 0)):
+        with pytest.raises(smmo.SmmoError) as e:
+            smmo.smmo_set_launch(heap.h, mid, a, *bad)
+        assert e.value.status == smmo.SMMO_EINVAL
+    heap.new("A", 1000, x=torch.ones(1000, device=dev), key=torch.arange(1000, dtype=torch.int32, device=dev))
+    smmo.smmo_set_launch(heap.h, mid, a, 64, 3, 4)
+    heap.do("A", "test.axpy", smmo.smmo_axpy_args(2.0, 1.0))
+    g = heap.gather("A", ["x"])
+    assert torch.all(g["x"] == 3.0)
+    clean(heap)

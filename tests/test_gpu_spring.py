@@ -16,6 +16,7 @@ import pytest
 
 from inputs import spring_mesh
 from oracle import spring_steps
+from paper_1908_05845_amd import smmo
 from paper_1908_05845_amd.sims import SpringSim
 
 pytestmark = pytest.mark.gpu
@@ -50,11 +51,20 @@ def check_step(sim, mesh, dt, limit):
     return ref["nbroken"]
 
 
-def test_small_mesh_with_breaking_every_step(dev):
-    print("spring 40x30 breaking", flush=True)
+def group_cfg(group):
+    """Heap configuration whose spring do-alls take `group` blocks per
+    wavefront iteration (0 = the library's default)."""
+    cfg = smmo.smmo_config_default()
+    cfg.block_group = group
+    return cfg
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_small_mesh_with_breaking_every_step(dev, group):
+    print("spring 40x30 breaking, group %d" % group, flush=True)
     mesh = spring_mesh(40, 30, seed=21, v_sigma=1.0)
     dt, limit = 1e-4, 0.3
-    sim = SpringSim(mesh, dt, limit)
+    sim = SpringSim(mesh, dt, limit, cfg=group_cfg(group))
     broken = 0
     for _ in range(150):
         broken += check_step(sim, mesh, dt, limit)
@@ -64,18 +74,21 @@ def test_small_mesh_with_breaking_every_step(dev):
     assert inv.type_violations == 0 and inv.empty_allocated == 0
 
 
-@pytest.mark.parametrize("W,H", [(1, 2), (2, 2), (9, 7), (65, 3)])
-def test_ragged_meshes(dev, W, H):
-    print("spring %dx%d" % (W, H), flush=True)
+@pytest.mark.parametrize("group", [1, 2, 4])
+@pytest.mark.parametrize("W,H", [(1, 2), (2, 2), (9, 7), (65, 3), (33, 17)])
+def test_ragged_meshes(dev, W, H, group):
+    print("spring %dx%d group %d" % (W, H, group), flush=True)
     mesh = spring_mesh(W, H, seed=W * 7 + H, v_sigma=2.0)
-    sim = SpringSim(mesh, 1e-4, 0.05)
+    sim = SpringSim(mesh, 1e-4, 0.05, cfg=group_cfg(group))
     for _ in range(40):
         check_step(sim, mesh, 1e-4, 0.05)
 
 
-def test_everything_breaks(dev):
+@pytest.mark.parametrize("group", [1, 4])
+def test_everything_breaks(dev, group):
+    print("spring 12x12 everything breaks, group %d" % group, flush=True)
     mesh = spring_mesh(12, 12, seed=3, v_sigma=20.0)
-    sim = SpringSim(mesh, 1e-3, 0.01)
+    sim = SpringSim(mesh, 1e-3, 0.01, cfg=group_cfg(group))
     for _ in range(30):
         check_step(sim, mesh, 1e-3, 0.01)
     st = sim.heap.stats()
