@@ -13,4 +13,5 @@ from .workloads import (  # noqa: F401
     spring_mesh,
     batched_meshes,
     concat_meshes,
+    wator_init,
 )

@@ -13,6 +13,10 @@ Recipes (stated once here and repeated in the design notes):
   1; initial velocity N(0, 0.01**2) per component.
 * batched meshes: node counts log-uniform in [1e3, 6.4e4], W = round(sqrt(n)),
   H = ceil(n / W), each mesh built as above with its own seed.
+* wa-tor: W x H torus; a cell starts with a fish iff its uniform draw is
+  below p_fish, with a shark iff it lies in [p_fish, p_fish + p_shark); the
+  agent's spawn timer is uniform in {0 .. its threshold}, a shark's energy is
+  energy0.
 
 Everything is produced in float64 and rounded to float32 where the simulated
 state is float32; both the oracle and the GPU receive the rounded values.
@@ -122,6 +126,22 @@ def spring_mesh(W: int, H: int, seed: int | None = None, jitter: float = 0.3,
         "a": a.astype(np.int32), "b": b.astype(np.int32), "k": k, "L0": L0,
         "adj": adj, "adj_is_b": adj_is_b, "slot_a": slot_a, "slot_b": slot_b,
     }
+
+
+def wator_init(W: int, H: int, seed: int | None = None, p_fish: float = 0.3, p_shark: float = 0.05,
+               fish_spawn: int = 4, shark_spawn: int = 12, energy0: int = 8) -> dict:
+    """Initial wa-tor agents per cell index y*W + x: kind (u8: 0 empty, 1 fish,
+    2 shark), timer and energy (i32; 0 where they do not apply)."""
+    if seed is None:
+        seed = config_seed(6)
+    ids = np.arange(W * H)
+    u = uniform(seed, 0, ids)
+    kind = np.where(u < p_fish, 1, np.where(u < p_fish + p_shark, 2, 0)).astype(np.uint8)
+    v = uniform(seed, 1, ids)
+    thr = np.where(kind == 1, fish_spawn, shark_spawn)
+    timer = np.where(kind > 0, np.floor(v * (thr + 1)), 0).astype(np.int32)
+    energy = np.where(kind == 2, energy0, 0).astype(np.int32)
+    return {"kind": kind, "timer": timer, "energy": energy}
 
 
 def struct_seed(base: int, s: int) -> int:

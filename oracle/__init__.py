@@ -8,6 +8,7 @@ its Python binding) never imports, links or runs it.
 from .oracle import (  # noqa: F401
     build,
     GolWorld,
+    WatorWorld,
     nbody_steps,
     nbody_force_at,
     nbody_update,

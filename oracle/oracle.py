@@ -65,6 +65,14 @@ def _load():
                                                     P, P, P, P, P, P, P, P, P, P]
             lib.orc_spring_breaks.restype = C.c_int
             lib.orc_spring_breaks.argtypes = [D, D, D, D, D, C.c_float]
+            lib.orc_wator_create.restype = P
+            lib.orc_wator_create.argtypes = [C.c_int, C.c_int, C.c_uint64, P, P, P, P]
+            lib.orc_wator_step.restype = C.c_int
+            lib.orc_wator_step.argtypes = [P, C.c_int]
+            lib.orc_wator_read.restype = C.c_int
+            lib.orc_wator_read.argtypes = [P, P, P, P, P]
+            lib.orc_wator_free.restype = None
+            lib.orc_wator_free.argtypes = [P]
             _lib = lib
     return _lib
 
@@ -109,6 +117,50 @@ class GolWorld:
     def __del__(self):
         if getattr(self, "h", None):
             self.lib.orc_gol_free(self.h)
+            self.h = None
+
+
+class WatorWorld:
+    """wa-tor in SMMO form on a W x H torus (thesis Ch.7 "wa-tor"): Cell, Fish
+    and Shark objects, eight do-alls per iteration.  params = (fish_spawn,
+    shark_spawn, energy0, boost); init = dict of per-cell arrays kind (0
+    empty, 1 fish, 2 shark), timer and energy; seed keys the random choices."""
+
+    def __init__(self, W: int, H: int, seed: int, params, init: dict):
+        self.lib = _load()
+        self.W, self.H = W, H
+        nc = W * H
+        self._keep = [np.ascontiguousarray(init["kind"], dtype=np.uint8),
+                      np.ascontiguousarray(init["timer"], dtype=np.int32),
+                      np.ascontiguousarray(init["energy"], dtype=np.int32),
+                      np.ascontiguousarray(params, dtype=np.int32)]
+        assert all(a.size == nc for a in self._keep[:3]) and self._keep[3].size == 4
+        kind, timer, energy, prm = self._keep
+        self.h = self.lib.orc_wator_create(W, H, seed, _p(prm), _p(kind), _p(timer), _p(energy))
+        if not self.h:
+            raise ValueError("bad grid")
+
+    def step(self, n: int = 1):
+        err = self.lib.orc_wator_step(self.h, n)
+        if err:
+            raise RuntimeError("oracle wa-tor error %d" % err)
+
+    def read(self):
+        """Per cell index: kind (u8), spawn timer and energy (i32, 0 where no
+        agent / no shark); plus (live fish, live sharks)."""
+        nc = self.W * self.H
+        kind = np.empty(nc, np.uint8)
+        timer = np.empty(nc, np.int32)
+        energy = np.empty(nc, np.int32)
+        counts = np.empty(2, np.int64)
+        err = self.lib.orc_wator_read(self.h, _p(kind), _p(timer), _p(energy), _p(counts))
+        if err:
+            raise RuntimeError("oracle wa-tor error %d" % err)
+        return kind, timer, energy, (int(counts[0]), int(counts[1]))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.orc_wator_free(self.h)
             self.h = None
 
 

@@ -794,3 +794,311 @@ int orc_spring_adjoint_step(long long N, const double *px, const double *py, con
     os_free(&w.spring);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* wa-tor (thesis Ch.7 "wa-tor"): fish and sharks on a W x H torus of cells. */
+/*                                                                          */
+/* Classes (Fish and Shark stand for the thesis's Agent subclasses):         */
+/*   Cell  {agent, kind (0 empty, 1 fish, 2 shark), request[5], cell_id,     */
+/*          neighbours[4]: up, right, down, left}                            */
+/*   Fish  {position, new_position, spawn_timer}                             */
+/*   Shark {position, new_position, spawn_timer, energy}                     */
+/* One iteration t is eight do-alls, in the thesis's order:                  */
+/*   Cell::prepare, Fish::prepare, Cell::decide, Fish::update,              */
+/*   Cell::prepare, Shark::prepare, Cell::decide, Shark::update.            */
+/* Random choices are uniform picks among candidates: r mod (number of       */
+/* candidates), where r is the splitmix64 output (Steele, Lea and Flood,    */
+/* OOPSLA 2014) for counter (stream << 32) + cell index, with stream = 4t +  */
+/* phase (0 fish prepare, 1 fish decide, 2 shark prepare, 3 shark decide),  */
+/* always drawn for the cell whose method runs or on which the agent sits.  */
+/* Parameters the thesis leaves open (spawn thresholds, energies) are inputs.*/
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    long long agent;      /* object id in the fish or shark store, -1 = none */
+    uint8_t kind;
+    uint8_t request[5];
+    int32_t cell_id;
+    size_t nb[4];
+} wt_cell;
+typedef struct { size_t pos, new_pos; int32_t spawn_timer; } wt_fish;
+typedef struct { size_t pos, new_pos; int32_t spawn_timer, energy; } wt_shark;
+
+typedef struct {
+    int W, H;
+    uint64_t seed;
+    int32_t fish_spawn, shark_spawn, energy0, boost;
+    long long t;
+    ostore cell, fish, shark;
+    size_t *cells;   /* cell index -> Cell object id */
+    size_t *snap;
+    size_t snap_cap;
+    int err;
+} wt_world;
+
+static uint64_t wt_rand(uint64_t seed, uint64_t stream, uint64_t idx)
+{
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * ((stream << 32) + idx + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static wt_cell *wt_c(wt_world *w, size_t id) { return os_at(&w->cell, id); }
+
+static size_t wt_snapshot(wt_world *w, ostore *s)
+{
+    if (s->n > w->snap_cap) {
+        size_t *p = realloc(w->snap, s->n * sizeof(size_t));
+        if (!p) { w->err = 2; return 0; }
+        w->snap = p;
+        w->snap_cap = s->n;
+    }
+    return os_snapshot(s, w->snap);
+}
+
+/* Cell::prepare: no requests yet */
+static void wt_cell_prepare(wt_cell *c) { memset(c->request, 0, sizeof c->request); }
+
+/* An agent on cell c asks to enter one neighbour: among the neighbours whose
+ * kind is `want` (tried first) or, if none and `fallback` >= 0, of kind
+ * `fallback`, one uniformly at random; with no candidate it asks to stay. */
+static void wt_request(wt_world *w, wt_cell *c, int want, int fallback, uint64_t stream)
+{
+    int cand[4], n = 0;
+    for (int i = 0; i < 4; i++)
+        if (wt_c(w, c->nb[i])->kind == want) cand[n++] = i;
+    if (n == 0 && fallback >= 0)
+        for (int i = 0; i < 4; i++)
+            if (wt_c(w, c->nb[i])->kind == fallback) cand[n++] = i;
+    if (n == 0) {
+        c->request[4] = 1;
+        return;
+    }
+    int sel = cand[wt_rand(w->seed, stream, (uint64_t)c->cell_id) % (uint64_t)n];
+    wt_c(w, c->nb[sel])->request[(sel + 2) % 4] = 1;
+}
+
+/* Fish::prepare: older by one iteration; ask for a random empty neighbour */
+static void wt_fish_prepare(wt_world *w, wt_fish *f)
+{
+    f->spawn_timer++;
+    f->new_pos = f->pos;
+    wt_request(w, wt_c(w, f->pos), 0, -1, (uint64_t)(4 * w->t + 0));
+}
+
+/* Shark::prepare: older and hungrier by one iteration; ask for a random
+ * neighbour with a fish, else a random empty one */
+static void wt_shark_prepare(wt_world *w, wt_shark *s)
+{
+    s->spawn_timer++;
+    s->energy--;
+    s->new_pos = s->pos;
+    wt_request(w, wt_c(w, s->pos), 1, 0, (uint64_t)(4 * w->t + 2));
+}
+
+/* Cell::decide: the cell's own agent stays if it asked to; otherwise one of
+ * the requesting neighbours' agents (of kind `kind`), picked at random, is
+ * told to move here */
+static void wt_cell_decide(wt_world *w, size_t self, int kind, uint64_t stream)
+{
+    wt_cell *c = wt_c(w, self);
+    if (c->request[4]) {
+        if (kind == 1) ((wt_fish *)os_at(&w->fish, (size_t)c->agent))->new_pos = self;
+        else ((wt_shark *)os_at(&w->shark, (size_t)c->agent))->new_pos = self;
+        return;
+    }
+    int cand[4], n = 0;
+    for (int i = 0; i < 4; i++)
+        if (c->request[i]) cand[n++] = i;
+    if (n == 0) return;
+    int sel = cand[wt_rand(w->seed, stream, (uint64_t)c->cell_id) % (uint64_t)n];
+    wt_cell *o = wt_c(w, c->nb[sel]);
+    if (o->kind != kind || o->agent < 0) { w->err = 3; return; }
+    if (kind == 1) ((wt_fish *)os_at(&w->fish, (size_t)o->agent))->new_pos = self;
+    else ((wt_shark *)os_at(&w->shark, (size_t)o->agent))->new_pos = self;
+}
+
+static void wt_set(wt_cell *c, int kind, long long agent)
+{
+    c->kind = (uint8_t)kind;
+    c->agent = agent;
+}
+
+/* Fish::update: move if granted; a fish that moves after more than
+ * fish_spawn iterations leaves a new fish behind */
+static void wt_fish_update(wt_world *w, size_t self)
+{
+    wt_fish *f = os_at(&w->fish, self);
+    if (f->new_pos == f->pos) return;
+    size_t old = f->pos;
+    f->pos = f->new_pos;
+    wt_set(wt_c(w, f->pos), 1, (long long)self);
+    if (f->spawn_timer > w->fish_spawn) {
+        long long id = os_new(&w->fish);
+        if (id < 0) { w->err = 2; return; }
+        f = os_at(&w->fish, self);          /* the store may have moved */
+        wt_fish *nf = os_at(&w->fish, (size_t)id);
+        nf->pos = nf->new_pos = old;
+        nf->spawn_timer = 0;
+        wt_set(wt_c(w, old), 1, id);
+        f->spawn_timer = 0;
+    } else {
+        wt_set(wt_c(w, old), 0, -1);
+    }
+}
+
+/* Shark::update: a shark without energy dies where it is; otherwise it moves
+ * if granted, eating the fish on the target cell (energy + boost), and
+ * leaves a new shark (energy0) behind after more than shark_spawn
+ * iterations */
+static void wt_shark_update(wt_world *w, size_t self)
+{
+    wt_shark *s = os_at(&w->shark, self);
+    if (s->energy <= 0) {
+        wt_set(wt_c(w, s->pos), 0, -1);
+        if (os_destroy(&w->shark, self)) w->err = 1;    /* last statement: delete this */
+        return;
+    }
+    if (s->new_pos == s->pos) return;
+    size_t old = s->pos;
+    wt_cell *tgt = wt_c(w, s->new_pos);
+    if (tgt->kind == 1) {
+        if (os_destroy(&w->fish, (size_t)tgt->agent)) w->err = 1;
+        s->energy += w->boost;
+    } else if (tgt->kind != 0) {
+        w->err = 4;
+        return;
+    }
+    s->pos = s->new_pos;
+    wt_set(tgt, 2, (long long)self);
+    if (s->spawn_timer > w->shark_spawn) {
+        long long id = os_new(&w->shark);
+        if (id < 0) { w->err = 2; return; }
+        s = os_at(&w->shark, self);
+        wt_shark *ns = os_at(&w->shark, (size_t)id);
+        ns->pos = ns->new_pos = old;
+        ns->spawn_timer = 0;
+        ns->energy = w->energy0;
+        wt_set(wt_c(w, old), 2, id);
+        s->spawn_timer = 0;
+    } else {
+        wt_set(wt_c(w, old), 0, -1);
+    }
+}
+
+/* kind[i] (0/1/2), timer[i] and energy[i] per cell index give the initial
+ * agents; params = {fish_spawn, shark_spawn, energy0, boost} */
+void *orc_wator_create(int W, int H, uint64_t seed, const int32_t *params, const uint8_t *kind,
+                       const int32_t *timer, const int32_t *energy)
+{
+    if (W <= 0 || H <= 0) return NULL;
+    wt_world *w = calloc(1, sizeof *w);
+    size_t nc = (size_t)W * H;
+    w->W = W; w->H = H; w->seed = seed;
+    w->fish_spawn = params[0]; w->shark_spawn = params[1]; w->energy0 = params[2]; w->boost = params[3];
+    w->cells = malloc(nc * sizeof(size_t));
+    if (os_init(&w->cell, sizeof(wt_cell), nc) || os_init(&w->fish, sizeof(wt_fish), nc) ||
+        os_init(&w->shark, sizeof(wt_shark), nc) || !w->cells)
+        return NULL;
+    for (size_t i = 0; i < nc; i++) {
+        long long id = os_new(&w->cell);
+        wt_cell *c = wt_c(w, (size_t)id);
+        c->cell_id = (int32_t)i;
+        c->agent = -1;
+        w->cells[i] = (size_t)id;
+    }
+    for (size_t i = 0; i < nc; i++) {
+        int x = (int)(i % W), y = (int)(i / W);
+        wt_cell *c = wt_c(w, w->cells[i]);
+        c->nb[0] = w->cells[(size_t)((y - 1 + H) % H) * W + x];
+        c->nb[1] = w->cells[(size_t)y * W + (x + 1) % W];
+        c->nb[2] = w->cells[(size_t)((y + 1) % H) * W + x];
+        c->nb[3] = w->cells[(size_t)y * W + (x - 1 + W) % W];
+    }
+    for (size_t i = 0; i < nc; i++) {
+        wt_cell *c = wt_c(w, w->cells[i]);
+        if (kind[i] == 1) {
+            long long id = os_new(&w->fish);
+            wt_fish *f = os_at(&w->fish, (size_t)id);
+            f->pos = f->new_pos = w->cells[i];
+            f->spawn_timer = timer[i];
+            wt_set(c, 1, id);
+        }
+    }
+    for (size_t i = 0; i < nc; i++) {
+        wt_cell *c = wt_c(w, w->cells[i]);
+        if (kind[i] == 2) {
+            long long id = os_new(&w->shark);
+            wt_shark *s = os_at(&w->shark, (size_t)id);
+            s->pos = s->new_pos = w->cells[i];
+            s->spawn_timer = timer[i];
+            s->energy = energy[i];
+            wt_set(c, 2, id);
+        }
+    }
+    return w;
+}
+
+int orc_wator_step(void *wp, int iterations)
+{
+    wt_world *w = wp;
+    for (int it = 0; it < iterations && !w->err; it++) {
+        size_t k = wt_snapshot(w, &w->cell);
+        for (size_t i = 0; i < k; i++) wt_cell_prepare(wt_c(w, w->snap[i]));
+        k = wt_snapshot(w, &w->fish);
+        for (size_t i = 0; i < k; i++) wt_fish_prepare(w, os_at(&w->fish, w->snap[i]));
+        k = wt_snapshot(w, &w->cell);
+        for (size_t i = 0; i < k; i++) wt_cell_decide(w, w->snap[i], 1, (uint64_t)(4 * w->t + 1));
+        k = wt_snapshot(w, &w->fish);
+        for (size_t i = 0; i < k; i++) wt_fish_update(w, w->snap[i]);
+        k = wt_snapshot(w, &w->cell);
+        for (size_t i = 0; i < k; i++) wt_cell_prepare(wt_c(w, w->snap[i]));
+        k = wt_snapshot(w, &w->shark);
+        for (size_t i = 0; i < k; i++) wt_shark_prepare(w, os_at(&w->shark, w->snap[i]));
+        k = wt_snapshot(w, &w->cell);
+        for (size_t i = 0; i < k; i++) wt_cell_decide(w, w->snap[i], 2, (uint64_t)(4 * w->t + 3));
+        k = wt_snapshot(w, &w->shark);
+        for (size_t i = 0; i < k; i++) wt_shark_update(w, w->snap[i]);
+        w->t++;
+    }
+    return w->err;
+}
+
+/* per cell index: kind, spawn timer and energy of its agent (0 where none);
+ * counts[0..1] = live fish, live sharks.  Checks that cells and agents agree. */
+int orc_wator_read(void *wp, uint8_t *kind, int32_t *timer, int32_t *energy, long long *counts)
+{
+    wt_world *w = wp;
+    size_t nc = (size_t)w->W * w->H;
+    for (size_t i = 0; i < nc; i++) {
+        const wt_cell *c = wt_c(w, w->cells[i]);
+        kind[i] = c->kind;
+        timer[i] = 0;
+        energy[i] = 0;
+        if (c->kind == 1) {
+            const wt_fish *f = os_at(&w->fish, (size_t)c->agent);
+            if (!w->fish.live[c->agent] || f->pos != w->cells[i]) w->err = 5;
+            timer[i] = f->spawn_timer;
+        } else if (c->kind == 2) {
+            const wt_shark *s = os_at(&w->shark, (size_t)c->agent);
+            if (!w->shark.live[c->agent] || s->pos != w->cells[i]) w->err = 5;
+            timer[i] = s->spawn_timer;
+            energy[i] = s->energy;
+        }
+    }
+    counts[0] = (long long)w->fish.nlive;
+    counts[1] = (long long)w->shark.nlive;
+    return w->err;
+}
+
+void orc_wator_free(void *wp)
+{
+    wt_world *w = wp;
+    if (!w) return;
+    os_free(&w->cell);
+    os_free(&w->fish);
+    os_free(&w->shark);
+    free(w->cells);
+    free(w->snap);
+    free(w);
+}
