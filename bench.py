@@ -131,21 +131,19 @@ def bench_spring(args, torch):
     if not args.no_autotune:
         from paper_1908_05845_amd import autotune
 
-        # force passes are idempotent; node passes with dt = 0 leave the state
+        # Candidates are timed on whole frozen steps (the force pass, then the
+        # node pass with dt = 0: the traffic of a real step, the state
+        # unchanged), one kernel at a time with the other at its current
+        # shape: each kernel evicts part of the other's inputs from the L2
+        # and MALL, so shapes tuned on a kernel alone need not help a step.
         groups = (1, 2, 4)
-        tf = autotune.tune(heap, "spring.force", "Spring", sim.args, repeat=10, groups=groups)
-        tn = autotune.tune(heap, "spring.node_update", "Node", frozen0, repeat=10, groups=groups)
-        for t in (tf, tn):
-            t.pop("tried")
-        n_tries = len(autotune.DEFAULT_WG) * len(autotune.DEFAULT_WAVES_PER_CU) * len(groups) * 12
-        count["spring.force"] += n_tries
-        count["spring.node_update"] += n_tries
-        # the kernels were tuned one at a time; keep the tuned shapes only if
-        # whole steps (force, then node with dt = 0: same traffic, unchanged
-        # state) are faster with them than with the default shapes
         fz = smmo.C.byref(frozen0)
+        n_frozen = [0]
 
-        def frozen_steps(n=100):
+        def frozen_steps(n=30, warm=3):
+            for _ in range(warm):
+                lib.smmo_parallel_do(hp, cs, mf, argp, asz, stream)
+                lib.smmo_parallel_do(hp, cn, mn, fz, asz, stream)
             torch.cuda.synchronize()
             ev = events(torch, 2)
             ev[0].record()
@@ -154,19 +152,21 @@ def bench_spring(args, torch):
                 lib.smmo_parallel_do(hp, cn, mn, fz, asz, stream)
             ev[1].record()
             torch.cuda.synchronize()
-            counted(n)
-            return ev[0].elapsed_time(ev[1]) / n * 1e3
+            n_frozen[0] += n + warm
+            return ev[0].elapsed_time(ev[1]) / n * 1e-3
 
-        frozen_steps(10)
-        t_tuned = frozen_steps()
-        smmo.smmo_set_launch(hp, mf, cs, 0, 0, 0)
-        smmo.smmo_set_launch(hp, mn, cn, 0, 0, 0)
-        frozen_steps(10)
-        t_default = frozen_steps()
+        t_default = frozen_steps(200) * 1e6
+        tf = autotune.tune(heap, "spring.force", "Spring", sim.args, groups=groups, timer=frozen_steps)
+        tn = autotune.tune(heap, "spring.node_update", "Node", frozen0, groups=groups, timer=frozen_steps)
+        for t in (tf, tn):
+            t.pop("tried")
+        t_tuned = frozen_steps(200) * 1e6
         keep = t_tuned < t_default
-        if keep:
-            smmo.smmo_set_launch(hp, mf, cs, tf["wg"], tf["waves"], tf["group"])
-            smmo.smmo_set_launch(hp, mn, cn, tn["wg"], tn["waves"], tn["group"])
+        if not keep:
+            smmo.smmo_set_launch(hp, mf, cs, 0, 0, 0)
+            smmo.smmo_set_launch(hp, mn, cn, 0, 0, 0)
+        count["spring.force"] += n_frozen[0]
+        count["spring.node_update"] += n_frozen[0]
         tuned = {"spring.force": tf, "spring.node_update": tn, "step_us_tuned": t_tuned,
                  "step_us_default": t_default, "kept": "tuned" if keep else "default"}
     # eager reference: host-launched steps (reported, not the value)
@@ -490,6 +490,159 @@ def measure_gol_extra(torch):
     return res
 
 
+def measure_linux_scalability(torch):
+    """Linux Scalability pattern (Ch.8 "Raw Allocation Performance") in SMMO
+    form: a 1 GiB heap, 16,384 Worker objects each allocate n 64-byte Obj
+    objects through the device allocator (one do-all), a second do-all frees
+    them; time per n = (allocation + free time) / n.  Also: the largest n the
+    heap holds (utilization = objects x 64 B / 1 GiB), and the allocator
+    ablations of the thesis at n = 64."""
+    from paper_1908_05845_amd import smmo
+
+    classes = {"Worker": [("id", "i32", 1)], "Obj": [("payload", "u32", 16)]}
+    workers = 16384
+
+    def run(n, **kw):
+        cfg = smmo.smmo_config_default()
+        for k, v in kw.items():
+            setattr(cfg, k, v)
+        heap = smmo.Heap(classes, nbytes=1 << 30, cfg=cfg)
+        heap.new("Worker", workers, id=torch.arange(workers, dtype=torch.int32, device="cuda"))
+        handles = torch.full((n * workers,), -1, dtype=torch.int32, device="cuda")
+        args = smmo.smmo_ls_args(heap.cls["Obj"], n, workers, 0, handles.data_ptr())
+        heap.sync()
+        ev = events(torch, 3)
+        ev[0].record()
+        heap.do("Worker", "alloc.ls_alloc", args)
+        ev[1].record()
+        heap.do("Worker", "alloc.ls_free", args)
+        ev[2].record()
+        torch.cuda.synchronize()
+        st = heap.stats()
+        out = {"n": n, "alloc_ms": ev[0].elapsed_time(ev[1]), "free_ms": ev[1].elapsed_time(ev[2]),
+               "device_error": st.device_error, "allocated": int(st.device_news),
+               "live_after_free": int(st.live_objects[heap.cls["Obj"]]), "retries": int(st.alloc_retries),
+               "heap_blocks": heap.blocks}
+        out["us_per_n"] = (out["alloc_ms"] + out["free_ms"]) * 1e3 / n
+        heap.close()
+        del handles
+        return out
+
+    res = {"workload": "1 GiB heap, 16,384 Worker objects, 64-byte Obj objects", "runs": []}
+    for n in (1, 4, 16, 64, 256, 1000):
+        res["runs"].append(run(n))
+    # largest n that fits: the heap's blocks minus the Worker blocks, 64 objects each
+    nblk = res["runs"][0]["heap_blocks"] - (workers + 63) // 64
+    n_max = nblk * 64 // workers
+    top = run(n_max)
+    top["utilization"] = workers * n_max * 64 / float(1 << 30)
+    res["max_n"] = top
+    res["ablations_n64"] = {k: run(64, **kw) for k, kw in (
+        ("no_rotation", {"rotation": 0}), ("no_coalescing", {"coalescing": 0}),
+        ("retries_1", {"lookup_retries": 1}))}
+    return res
+
+
+def measure_wator(torch):
+    """wa-tor (Ch.7 "wa-tor"), 1024 x 1024 torus, 30 % fish and 5 % sharks at
+    the start, fish spawn 4, shark spawn 12, energy 8, boost 4: 500 timed
+    iterations (eight do-alls each, fish and sharks created and deleted by
+    the device allocator), then the fragmentation of the Fish and Shark
+    blocks over a second run (sampled every 25 iterations), and the
+    allocator ablations on a 512 x 512 torus."""
+    from inputs import config_seed, wator_init
+    from paper_1908_05845_amd import smmo
+    from paper_1908_05845_amd.sims import WatorSim
+
+    prm = (4, 12, 8, 4)
+    seed = config_seed(7)
+
+    def agent_frag(sim):
+        st = sim.heap.stats()
+        c = sim.heap.cls
+        blocks = st.blocks[c["Fish"]] + st.blocks[c["Shark"]]
+        live = st.live_objects[c["Fish"]] + st.live_objects[c["Shark"]]
+        return st, (1.0 - live / (64.0 * blocks)) if blocks else 0.0
+
+    def make(W, cfg=None):
+        init = wator_init(W, W, fish_spawn=prm[0], shark_spawn=prm[1], energy0=prm[2])
+        return WatorSim(W, W, seed, prm, init, cfg=cfg)
+
+    W, iters = 1024, 500
+    sim = make(W)
+    sim.step(5)
+    st0, _ = agent_frag(sim)
+    torch.cuda.synchronize()
+    ev = events(torch, 2)
+    ev[0].record()
+    sim.step(iters)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    st1, frag_end = agent_frag(sim)
+    res = {"workload": "wa-tor 1024x1024 torus, fish/shark 0.30/0.05, params (fish_spawn, shark_spawn, "
+                       "energy0, boost) = %s" % (prm,),
+           "iterations": iters, "ms_per_iteration": ms / iters,
+           "device_news_per_s": (st1.device_news - st0.device_news) / (ms * 1e-3),
+           "device_deletes_per_s": (st1.device_deletes - st0.device_deletes) / (ms * 1e-3),
+           "fish_end": int(st1.live_objects[sim.heap.cls["Fish"]]),
+           "sharks_end": int(st1.live_objects[sim.heap.cls["Shark"]]),
+           "agent_fragmentation_end": frag_end, "device_error": st1.device_error}
+    sim.heap.close()
+    sim = make(W)
+    curve = []
+    for k in range(0, iters + 1, 25):
+        if k:
+            sim.step(25)
+        st, fr = agent_frag(sim)
+        curve.append([k, int(st.live_objects[sim.heap.cls["Fish"]]), int(st.live_objects[sim.heap.cls["Shark"]]),
+                      round(fr, 4)])
+    res["fragmentation_curve"] = {"columns": ["iteration", "fish", "sharks", "agent_fragmentation"],
+                                  "rows": curve}
+    sim.heap.close()
+    abl = {}
+    for name, kw in (("default", {}), ("no_rotation", {"rotation": 0}), ("no_coalescing", {"coalescing": 0}),
+                     ("retries_1", {"lookup_retries": 1})):
+        cfg = smmo.smmo_config_default()
+        for k, v in kw.items():
+            setattr(cfg, k, v)
+        sim = make(512, cfg)
+        torch.cuda.synchronize()
+        ev = events(torch, 2)
+        ev[0].record()
+        sim.step(300)
+        ev[1].record()
+        torch.cuda.synchronize()
+        st, fr = agent_frag(sim)
+        abl[name] = {"ms_per_iteration": ev[0].elapsed_time(ev[1]) / 300, "agent_fragmentation": fr,
+                     "retries": int(st.alloc_retries), "slow_paths": int(st.slow_paths),
+                     "device_error": st.device_error}
+        sim.heap.close()
+    res["ablations_512x512_300it"] = abl
+    return res
+
+
+def measure_copy_bandwidth(torch):
+    """Attainable HBM bandwidth on this GPU: a device-to-device copy of 512
+    MiB (read + write = 1 GiB of traffic), median of 5 timed copies."""
+    n = (512 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(5):
+        ev = events(torch, 2)
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]))
+    t = sorted(ts)[2]
+    del src, dst
+    return {"bytes_moved": 2 * 4 * n, "ms": t, "gbs": 2 * 4 * n / (t * 1e-3) / 1e9,
+            "frac_of_peak": 2 * 4 * n / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def measure_nbody_extra(torch):
     """n-body, 65,536 bodies, 50 steps: device_do over all pairs (FP32 VALU bound)."""
     from inputs import nbody_init
@@ -721,10 +874,13 @@ def main():
     res, cpu_leg, steps, warmup = fn(args, torch)
     extras = {}
     if args.workload == "spring" and not args.no_extras:
+        extras["copy_bandwidth"] = measure_copy_bandwidth(torch)
         extras["batched"] = measure_batched(torch, res["value"])
         extras["adjoint"] = measure_adjoint(torch, res["value"])
         extras["gol"] = measure_gol_extra(torch)
         extras["nbody"] = measure_nbody_extra(torch)
+        extras["linux_scalability"] = measure_linux_scalability(torch)
+        extras["wator"] = measure_wator(torch)
     cpu = None if args.no_cpu_baseline else cpu_leg()
     if cpu is not None:
         cpu["cpu_model"] = _cpu_model()

@@ -137,6 +137,80 @@ typedef struct {
     int32_t key_add;
 } smmo_spawn_args;
 
+/* ---- allocator microbenchmark (Ch.8 "Raw Allocation Performance", the
+ * Linux Scalability benchmark in SMMO form) ---------------------------------
+ * "alloc.ls_alloc" on any class with I32 field "id" (0 <= id < workers): every
+ *                  object allocates n objects of target_class with the device
+ *                  allocator, one after another, and stores the i-th handle
+ *                  at handles[i * workers + id] (SMMO_NULL once the heap is
+ *                  exhausted; the device error is then set and the remaining
+ *                  allocations are skipped).
+ * "alloc.ls_free"  on the same class: every object deletes the n objects
+ *                  named at handles[i * workers + id]; SMMO_NULL entries are
+ *                  skipped, any other handle that names no object of
+ *                  target_class sets the device error (bad handle).
+ * target_class must differ from the running class; handles is a device array
+ * of n * workers entries owned by the caller; an id outside [0, workers)
+ * sets the device error (bad handle) and that object does nothing.         */
+typedef struct {
+    uint32_t target_class;
+    uint32_t n;
+    uint32_t workers;
+    uint32_t reserved;
+    uint32_t *handles;
+} smmo_ls_args;
+
+/* ---- wa-tor (Ch.7 "wa-tor"): fish and sharks on a W x H torus ------------
+ * Classes and fields (the thesis's Agent subclasses Fish and Shark are two
+ * classes here):
+ *   Cell  U32 "agent" (a Fish handle, a Shark handle with bit 31 set, or
+ *         SMMO_NULL), HANDLE "nb" x4 (neighbour cells up, right, down, left),
+ *         U8 "req" x5 (requests from those neighbours; [4] = stay), I32
+ *         "cell_id" (y * width + x)
+ *   Fish  HANDLE "pos", HANDLE "new_pos", I32 "timer"
+ *   Shark HANDLE "pos", HANDLE "new_pos", I32 "timer", I32 "energy"
+ * One iteration = cell_prepare, fish_prepare, cell_decide (kind 1),
+ * fish_update, cell_prepare, shark_prepare, cell_decide (kind 2),
+ * shark_update, each with iteration = t.  Random choices: the splitmix64
+ * output for seed and counter ((4t + phase) << 32) + cell_id, phase 0 fish
+ * prepare, 1 fish decide, 2 shark prepare, 3 shark decide, taken mod the
+ * number of candidates.
+ * "wator.cell_link"     on Cell: nb from cell_id, with cells[i] = handle of
+ *                       the Cell with cell_id i (device array of width*height)
+ * "wator.link"          on Fish (kind 1) or Shark (kind 2): its cell's agent
+ *                       = this object
+ * "wator.cell_prepare"  on Cell: clears req
+ * "wator.fish_prepare"  on Fish: timer + 1, new_pos = pos, asks a random
+ *                       empty neighbour (or to stay)
+ * "wator.shark_prepare" on Shark: timer + 1, energy - 1, new_pos = pos, asks
+ *                       a random neighbour with a fish, else a random empty
+ *                       one (or to stay)
+ * "wator.cell_decide"   on Cell: grants its own agent's stay request, or one
+ *                       random requesting neighbour's agent of class `kind`
+ *                       (new_pos = this cell)
+ * "wator.fish_update"   on Fish: moves if granted; after more than
+ *                       fish_spawn iterations a moving fish leaves a new Fish
+ * "wator.shark_update"  on Shark: dies (deletes itself) when energy <= 0;
+ *                       else moves if granted, deletes the fish it lands on
+ *                       (energy + boost), and after more than shark_spawn
+ *                       iterations leaves a new Shark with energy0         */
+typedef struct {
+    uint32_t cell_class;
+    uint32_t fish_class;
+    uint32_t shark_class;
+    uint32_t iteration;
+    uint64_t seed;
+    int32_t fish_spawn;
+    int32_t shark_spawn;
+    int32_t energy0;
+    int32_t boost;
+    uint32_t kind;
+    int32_t width;
+    int32_t height;
+    uint32_t reserved;
+    const uint32_t *cells;
+} smmo_wator_args;
+
 #ifdef __cplusplus
 }
 #endif

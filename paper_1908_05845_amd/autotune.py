@@ -53,9 +53,14 @@ def time_launches(heap, method: str, cls_name: str, args, repeat: int) -> float:
 
 
 def tune(heap, method: str, cls_name: str, args, repeat: int = 20, wg_sizes=DEFAULT_WG,
-         waves_per_cu=DEFAULT_WAVES_PER_CU, groups=(0,), cache_path: str | None = None) -> dict:
+         waves_per_cu=DEFAULT_WAVES_PER_CU, groups=(0,), cache_path: str | None = None,
+         timer=None) -> dict:
     """Times every (work-group size, wavefronts, group) candidate, applies the
-    best.  groups=(0,) keeps the method's default group.
+    best.  groups=(0,) keeps the method's default group.  By default a
+    candidate is timed over `repeat` back-to-back launches of the method
+    alone; `timer()` (seconds per unit, called with the candidate applied)
+    replaces that, e.g. to time whole steps of a loop whose other launches
+    evict this method's inputs from the caches.
     Returns {"wg", "waves", "group", "us", "tried": [...]}."""
     import torch
 
@@ -71,7 +76,7 @@ def tune(heap, method: str, cls_name: str, args, repeat: int = 20, wg_sizes=DEFA
             for wpc in waves_per_cu:
                 waves = wpc * cus
                 smmo.smmo_set_launch(heap.h, mid, cls, wg, waves, grp)
-                t = time_launches(heap, method, cls_name, args, repeat)
+                t = timer() if timer is not None else time_launches(heap, method, cls_name, args, repeat)
                 tried.append({"wg": wg, "waves": waves, "group": grp, "us": t * 1e6})
                 if best is None or t < best[3]:
                     best = (wg, waves, grp, t)

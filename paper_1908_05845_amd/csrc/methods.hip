@@ -624,6 +624,86 @@ smmo_status launch_spawn(smmo_heap *h, uint32_t cls, const void *args, hipStream
     return SMMO_OK;
 }
 
+// ============================================ allocator microbenchmark =====
+// Linux Scalability (Ch.8 "Raw Allocation Performance"): each worker object
+// allocates n objects of the target class through the device allocator, then
+// a second do-all frees them.  The objects' memory is not touched.
+struct LsK {
+    uint32_t cls, target, o_id, n, workers;
+    uint32_t *handles;
+};
+
+__device__ __forceinline__ bool ls_worker(const HeapView &h, const LsK &p, uint32_t bid, uint64_t bm,
+                                          uint32_t &id)
+{
+    const uint32_t s = lane_id();
+    id = 0;
+    if (!((bm >> s) & 1)) return false;
+    id = (uint32_t)farr<int32_t>(h, bid, p.o_id)[s];
+    if (id >= p.workers) {
+        raise_error(h, ERR_BADHANDLE);
+        return false;
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(1024) void k_ls_alloc(HeapView h, LsK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        uint32_t id;
+        const bool live = ls_worker(h, p, bid, bm, id);
+        for (uint32_t i = 0; i < p.n; ++i) {
+            if (__builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_ERR))) break;
+            const uint32_t hd = wave_allocate(h, p.target, live);
+            if (live) p.handles[(uint64_t)i * p.workers + id] = hd;
+        }
+    });
+}
+
+__global__ __launch_bounds__(1024) void k_ls_free(HeapView h, LsK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        uint32_t id;
+        const bool live = ls_worker(h, p, bid, bm, id);
+        for (uint32_t i = 0; i < p.n; ++i) {
+            uint32_t hd = kNull;
+            bool want = false;
+            if (live) {
+                hd = p.handles[(uint64_t)i * p.workers + id];
+                if (hd != kNull) {
+                    const uint32_t b = hd >> 6;
+                    want = b < h.M && ald32(h.type + b) == p.target;
+                    if (!want) raise_error(h, ERR_BADHANDLE);
+                }
+            }
+            wave_deallocate(h, p.target, hd, want);
+        }
+    });
+}
+
+template <int Which>
+smmo_status launch_ls(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_ls_args a;
+    memcpy(&a, args, sizeof a);
+    if (!a.handles || a.n == 0 || a.workers == 0 || a.target_class >= h->schema->nclasses ||
+        a.target_class == cls)
+        return fail(SMMO_EINVAL, "alloc.ls: bad arguments");
+    if ((uint64_t)a.n * a.workers > 0xFFFFFFFFull) return fail(SMMO_EINVAL, "alloc.ls: n * workers too large");
+    LsK k{cls, a.target_class, 0, a.n, a.workers, a.handles};
+    BIND(cls, "id", SMMO_I32, 1, &k.o_id, nullptr);
+    smmo_status s = ensure_enumerated(h, cls, false, st);
+    if (s) return s;
+    const LaunchShape ls = method_shape(h, cls);
+    if (Which == 0) hipLaunchKernelGGL(k_ls_alloc, ls.grid, ls.block, 0, st, h->v, k);
+    else hipLaunchKernelGGL(k_ls_free, ls.grid, ls.block, 0, st, h->v, k);
+    if ((s = launched("alloc.ls kernel"))) return s;
+    if (Which == 0) note_allocation(h, a.target_class, (uint64_t)a.n * a.workers);
+    return SMMO_OK;
+}
+
 const MethodEntry kMethods[] = {
     {"gol.cell_count", sizeof(smmo_gol_args), launch_gol<0>},
     {"gol.alive_death", sizeof(smmo_gol_args), launch_gol<1>},
@@ -643,6 +723,16 @@ const MethodEntry kMethods[] = {
     {"test.axpy", sizeof(smmo_axpy_args), launch_axpy},
     {"test.destroy_if", sizeof(smmo_destroy_if_args), launch_destroy_if},
     {"test.spawn", sizeof(smmo_spawn_args), launch_spawn},
+    {"alloc.ls_alloc", sizeof(smmo_ls_args), launch_ls<0>},
+    {"alloc.ls_free", sizeof(smmo_ls_args), launch_ls<1>},
+    {"wator.cell_prepare", sizeof(smmo_wator_args), launch_wator_cell_prepare},
+    {"wator.fish_prepare", sizeof(smmo_wator_args), launch_wator_fish_prepare},
+    {"wator.shark_prepare", sizeof(smmo_wator_args), launch_wator_shark_prepare},
+    {"wator.cell_decide", sizeof(smmo_wator_args), launch_wator_cell_decide},
+    {"wator.fish_update", sizeof(smmo_wator_args), launch_wator_fish_update},
+    {"wator.shark_update", sizeof(smmo_wator_args), launch_wator_shark_update},
+    {"wator.cell_link", sizeof(smmo_wator_args), launch_wator_cell_link},
+    {"wator.link", sizeof(smmo_wator_args), launch_wator_link},
 };
 
 } // namespace

@@ -439,15 +439,44 @@ __device__ __forceinline__ uint32_t wave_allocate(const HeapView &h, uint32_t cl
     return result;
 }
 
+// OR of v over the lanes of the wavefront (butterfly over both halves)
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v)
+{
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        lo |= (uint32_t)__shfl_xor((int)lo, d);
+        hi |= (uint32_t)__shfl_xor((int)hi, d);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Deallocation of arbitrary handles of class `cls` (one per lane with want).
-// Converged call.  Handles must name live objects of the class.
+// Converged call.  Handles must name live objects of the class.  Lanes whose
+// objects share a block are released together: one atomic per distinct
+// block (the multi-slot release of sec.5.3.2), its bitmap switches completed
+// before the next block's release.
 __device__ __forceinline__ void wave_deallocate(const HeapView &h, uint32_t cls, uint32_t handle,
                                                 bool want)
 {
-    OpQueue q;
-    q.reset();
-    if (want) release_slots(h, cls, handle >> 6, 1ull << (handle & 63), q);
-    run_ops_wave(h, q);
+    const uint32_t lane = lane_id();
+    uint64_t pending = __ballot(want);
+    while (pending) {
+        const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)pending) - 1);
+        const uint32_t b = (uint32_t)__shfl((int)(handle >> 6), (int)leader);
+        const bool mine = ((pending >> lane) & 1) && (handle >> 6) == b;
+        const uint64_t slots = wave_or64(mine ? 1ull << (handle & 63) : 0ull);
+        const uint64_t group = __ballot(mine);
+        pending &= ~group;
+        OpQueue q;
+        q.reset();
+        if (lane == leader) {
+            // two lanes naming one object: released once, reported as a bad handle
+            if (__popcll(slots) != __popcll(group)) raise_error(h, ERR_BADHANDLE);
+            release_slots(h, cls, b, slots, q);
+        }
+        run_ops_wave(h, q);
+    }
 }
 
 // Deallocation of objects that delete themselves inside a method: the

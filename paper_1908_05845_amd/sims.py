@@ -1,4 +1,4 @@
-"""Workload drivers on the SMMO heap: Game of Life, n-body and spring meshes.
+"""Workload drivers on the SMMO heap: Game of Life, n-body, spring meshes, wa-tor.
 
 Each driver builds a heap, creates its objects with smmo_parallel_new from
 dense arrays (as produced by the ``inputs`` package), runs steps as
@@ -19,6 +19,12 @@ GOL_CLASSES = {
 NBODY_CLASSES = {
     "Body": [("pos_x", "f32", 1), ("pos_y", "f32", 1), ("vel_x", "f32", 1), ("vel_y", "f32", 1),
              ("force_x", "f32", 1), ("force_y", "f32", 1), ("mass", "f32", 1), ("id", "i32", 1)],
+}
+
+WATOR_CLASSES = {
+    "Cell": [("agent", "u32", 1), ("nb", "handle", 4), ("req", "u8", 5), ("cell_id", "i32", 1)],
+    "Fish": [("pos", "handle", 1), ("new_pos", "handle", 1), ("timer", "i32", 1)],
+    "Shark": [("pos", "handle", 1), ("new_pos", "handle", 1), ("timer", "i32", 1), ("energy", "i32", 1)],
 }
 
 SPRING_CLASSES = {
@@ -222,3 +228,109 @@ class SpringSim:
         out["adj_is_b"] = np.where(used, raw >> 31, 0).astype(np.uint8)
         out["node_handles_by_id"] = _np(gn["_handle"])[order]
         return out
+
+
+class WatorSim:
+    """wa-tor (classes Cell, Fish, Shark) on a W x H torus.
+
+    params = (fish_spawn, shark_spawn, energy0, boost); init = per-cell arrays
+    kind / timer / energy as made by ``inputs.wator_init``; seed keys the
+    random choices.  The heap holds the cells plus room for `agent_room`
+    agents of each kind (default: one per cell)."""
+
+    STEPS = (("Cell", "wator.cell_prepare", 0), ("Fish", "wator.fish_prepare", 0),
+             ("Cell", "wator.cell_decide", 1), ("Fish", "wator.fish_update", 0),
+             ("Cell", "wator.cell_prepare", 0), ("Shark", "wator.shark_prepare", 0),
+             ("Cell", "wator.cell_decide", 2), ("Shark", "wator.shark_update", 0))
+
+    def __init__(self, W: int, H: int, seed: int, params, init: dict, cfg=None, agent_room: int | None = None):
+        import torch
+
+        self.torch = torch
+        self.W, self.H = W, H
+        n = W * H
+        room = n if agent_room is None else agent_room
+        self.heap = smmo.Heap(WATOR_CLASSES, blocks=_blocks(n) + 2 * (2 * _blocks(room) + 64), cfg=cfg)
+        dev = self.heap.buf.device
+        self.dev = dev
+        ids = torch.arange(n, dtype=torch.int32, device=dev)
+        null = torch.full((n,), -1, dtype=torch.int32, device=dev)
+        self.cells = self.heap.new("Cell", n, agent=null, nb=torch.full((4 * n,), -1, dtype=torch.int32,
+                                                                       device=dev),
+                                   cell_id=ids).clone()
+        c = self.heap.cls
+        fs, ss, e0, boost = (int(v) for v in params)
+        self.args = smmo.smmo_wator_args(c["Cell"], c["Fish"], c["Shark"], 0, seed & ((1 << 64) - 1),
+                                         fs, ss, e0, boost, 0, W, H, 0, self.cells.data_ptr())
+        self.heap.do("Cell", "wator.cell_link", self.args)
+        kind = np.asarray(init["kind"])
+        for k, cname in ((1, "Fish"), (2, "Shark")):
+            where = np.flatnonzero(kind == k)
+            if where.size == 0:
+                continue
+            idx = torch.from_numpy(where.astype(np.int64)).to(dev)
+            pos = self.cells[idx]
+            vals = {"pos": pos, "new_pos": pos,
+                    "timer": torch.from_numpy(np.asarray(init["timer"])[where].astype(np.int32)).to(dev)}
+            if k == 2:
+                vals["energy"] = torch.from_numpy(np.asarray(init["energy"])[where].astype(np.int32)).to(dev)
+            self.heap.new(cname, where.size, **vals)
+            self.args.kind = k
+            self.heap.do(cname, "wator.link", self.args)
+        self.t = 0
+        self._launch = [(c[cn], smmo.smmo_method_id(m), kd) for cn, m, kd in self.STEPS]
+
+    def step(self, n: int = 1, stream=None):
+        lib = smmo.load_library()
+        st = smmo._stream(stream)
+        ref = smmo.C.byref(self.args)
+        size = smmo.C.sizeof(self.args)
+        for _ in range(n):
+            self.args.iteration = self.t
+            for cls, mid, kd in self._launch:
+                self.args.kind = kd
+                status = lib.smmo_parallel_do(self.heap.h, cls, mid, ref, size, st)
+                if status:
+                    raise smmo.SmmoError(status, smmo._last_error(lib))
+            self.t += 1
+
+    def read(self):
+        """Per cell index: kind (u8), timer, energy (i32; 0 where they do not
+        apply); (live fish, live sharks).  Raises if a cell and its agent
+        disagree."""
+        n = self.W * self.H
+        cells = self.cells.cpu().numpy().view(np.uint32)
+        order = np.argsort(cells)
+        sc = cells[order]
+
+        def cell_of(handles):
+            hh = handles.cpu().numpy().view(np.uint32)
+            j = np.searchsorted(sc, hh)
+            if hh.size and (np.any(j >= n) or np.any(sc[np.minimum(j, n - 1)] != hh)):
+                raise RuntimeError("an agent names no cell")
+            return order[j]
+
+        g = self.heap.gather("Cell", ["cell_id", "agent"])
+        agent = np.full(n, 0xFFFFFFFF, np.uint32)
+        agent[g["cell_id"].cpu().numpy()] = g["agent"].cpu().numpy().view(np.uint32)
+        kind = np.zeros(n, np.uint8)
+        timer = np.zeros(n, np.int32)
+        energy = np.zeros(n, np.int32)
+        f = self.heap.gather("Fish", ["pos", "timer"])
+        fc = cell_of(f["pos"])
+        sh = self.heap.gather("Shark", ["pos", "timer", "energy"])
+        scl = cell_of(sh["pos"])
+        if np.unique(np.concatenate([fc, scl])).size != fc.size + scl.size:
+            raise RuntimeError("two agents on one cell")
+        kind[fc] = 1
+        timer[fc] = f["timer"].cpu().numpy()
+        kind[scl] = 2
+        timer[scl] = sh["timer"].cpu().numpy()
+        energy[scl] = sh["energy"].cpu().numpy()
+        want = np.full(n, 0xFFFFFFFF, np.uint32)
+        want[fc] = f["_handle"].cpu().numpy().view(np.uint32)
+        want[scl] = sh["_handle"].cpu().numpy().view(np.uint32) | np.uint32(0x80000000)
+        if not np.array_equal(agent, want):
+            raise RuntimeError("cell agent fields disagree with the agents' positions in %d cells"
+                               % int(np.sum(agent != want)))
+        return kind, timer, energy, (int(fc.size), int(scl.size))

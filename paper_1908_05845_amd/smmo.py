@@ -89,6 +89,19 @@ class smmo_adjoint_args(C.Structure):
                 ("seed_vy", C.c_void_p)]
 
 
+class smmo_ls_args(C.Structure):
+    _fields_ = [("target_class", C.c_uint32), ("n", C.c_uint32), ("workers", C.c_uint32),
+                ("reserved", C.c_uint32), ("handles", C.c_void_p)]
+
+
+class smmo_wator_args(C.Structure):
+    _fields_ = [("cell_class", C.c_uint32), ("fish_class", C.c_uint32), ("shark_class", C.c_uint32),
+                ("iteration", C.c_uint32), ("seed", C.c_uint64), ("fish_spawn", C.c_int32),
+                ("shark_spawn", C.c_int32), ("energy0", C.c_int32), ("boost", C.c_int32),
+                ("kind", C.c_uint32), ("width", C.c_int32), ("height", C.c_int32),
+                ("reserved", C.c_uint32), ("cells", C.c_void_p)]
+
+
 class smmo_axpy_args(C.Structure):
     _fields_ = [("a", C.c_float), ("b", C.c_float)]
 

@@ -96,8 +96,10 @@ def test_too_many_classes_and_duplicates(lib):
 def test_method_ids(lib):
     names = ["gol.cell_count", "gol.alive_death", "gol.cell_birth", "nbody.force", "nbody.update",
              "spring.force", "spring.node_update", "spring.link", "adjoint.record", "adjoint.save",
-             "adjoint.load", "adjoint.seed", "adjoint.zero", "adjoint.node", "adjoint.spring", "test.axpy", "test.destroy_if",
-             "test.spawn"]
+             "adjoint.load", "adjoint.seed", "adjoint.zero", "adjoint.node", "adjoint.spring", "test.axpy",
+             "test.destroy_if", "test.spawn", "alloc.ls_alloc", "alloc.ls_free", "wator.cell_prepare",
+             "wator.fish_prepare", "wator.shark_prepare", "wator.cell_decide", "wator.fish_update",
+             "wator.shark_update", "wator.cell_link", "wator.link"]
     ids = [smmo.smmo_method_id(n) for n in names]
     assert len(set(ids)) == len(ids)
     with pytest.raises(smmo.SmmoError) as e:
@@ -124,5 +126,7 @@ def test_struct_sizes_match_header(lib):
     assert C.sizeof(smmo.smmo_nbody_args) == 16
     assert C.sizeof(smmo.smmo_spring_args) == 16
     assert C.sizeof(smmo.smmo_spawn_args) == 24
+    assert C.sizeof(smmo.smmo_ls_args) == 24
+    assert C.sizeof(smmo.smmo_wator_args) == 64
     assert C.sizeof(smmo.smmo_config) == 64
     assert C.sizeof(smmo.smmo_adjoint_args) == 80

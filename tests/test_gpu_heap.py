@@ -129,6 +129,17 @@ def test_host_destroy_and_bad_handles(dev):
     assert e.value.status == smmo.SMMO_EDEVICE
     smmo.smmo_clear_error(heap.h)
     heap.sync()
+    # one object named twice in one call: released once, reported
+    live = np.setdiff1d(model, [])
+    dup = hd[torch.from_numpy(np.array([model[0], model[0]])).to(dev)]
+    heap.destroy("A", dup)
+    with pytest.raises(smmo.SmmoError) as e:
+        heap.sync()
+    assert e.value.status == smmo.SMMO_EDEVICE
+    smmo.smmo_clear_error(heap.h)
+    model = live[1:]
+    assert np.array_equal(keys_of(heap), model)
+    clean(heap)
     # a handle of the wrong class is rejected too
     hb = heap.new("B", 10, key=torch.arange(10, dtype=torch.int32, device=dev))
     heap.destroy("A", hb[:1])
