@@ -44,9 +44,13 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three plain 512 MiB device copies (reference for rocprofv3 byte counters)")
-    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="summarize two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this bench into "
-                         "profiles/spring_counters.json and print a text summary; needs no GPU")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR_OR_JSON",
+                    help="FETCH_DIR WRITE_DIR [FETCH_JSON WRITE_JSON]: summarize two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of this bench (and their JSON lines, to keep only the "
+                         "timing-window dispatches) into profiles/spring_counters.json; needs no GPU")
+    ap.add_argument("--counter-pass", metavar="BENCH_JSON",
+                    help="profiling aid: replay the state of the given bench run's timing window "
+                         "(for rocprofv3 --pmc)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint measurements")
     ap.add_argument("--no-autotune", action="store_true")
@@ -312,7 +316,8 @@ def bench_spring(args, torch):
         "kernels": kernels,
         "autotune": tuned,
         "trace_window": {"note": "per-kernel dispatch index range of the timing pass (0-based, "
-                                 "graph replays included)", **window},
+                                 "graph replays included); after_steps = real steps before it",
+                         "after_steps": warmup + half, **window},
         "launch": {"mode": "hip graph of %d steps" % G if graph is not None else "launched steps",
                    "timed_host_wall_s": wall, "eager_ms_per_step": eager_ms,
                    "graph_ms_per_step": graph_ms,
@@ -785,9 +790,17 @@ def _read_counter_csv(d):
     return rows
 
 
-def summarize_counters(fetch_dir, write_dir):
+def summarize_counters(fetch_dir, write_dir, fetch_json=None, write_json=None):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the spring kernels,
-    scaled by the ratio of true to counted bytes of the calibration copy."""
+    scaled by the ratio of true to counted bytes of the calibration copy.
+    With the bench JSON lines of the two profiled runs, only the dispatches
+    of each run's per-kernel timing window (its timed launch shapes) are
+    averaged."""
+    windows = {}
+    for counter, jf in (("FETCH_SIZE", fetch_json), ("WRITE_SIZE", write_json)):
+        if jf:
+            with open(jf) as f:
+                windows[counter] = json.loads([ln for ln in f if ln.startswith("{")][-1])["trace_window"]
     out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES, "kernels": {}}
     lines = []
     factor = {}
@@ -803,7 +816,11 @@ def summarize_counters(fetch_dir, write_dir):
         cal = [float(r["Counter_Value"]) * 1024.0 for r in copies]
         factor[counter] = COPY_BYTES / (sum(cal) / len(cal))
         for name, key in KERNEL_KEYS.items():
-            vals = [float(r["Counter_Value"]) * 1024.0 for r in rows if key in r["Kernel_Name"]]
+            mine = sorted((r for r in rows if key in r["Kernel_Name"]), key=lambda r: int(r["Dispatch_Id"]))
+            if counter in windows:
+                lo, hi = windows[counter][name]
+                mine = mine[lo:hi]
+            vals = [float(r["Counter_Value"]) * 1024.0 for r in mine]
             per.setdefault(name, {})[counter] = (sum(vals) / len(vals), len(vals))
     for name, d in per.items():
         fetch = d["FETCH_SIZE"][0] * factor["FETCH_SIZE"]
@@ -822,6 +839,55 @@ def summarize_counters(fetch_dir, write_dir):
     print("|---|---|---|---|---|")
     print("\n".join(lines))
     print("written", path)
+
+
+def counter_pass(args, torch):
+    """Profiling aid for rocprofv3 --pmc (one counter per run): rebuilds the
+    bench's mesh, applies the launch shapes a bench run timed (its JSON line,
+    args.counter_pass), runs as many real steps as that run did before its
+    per-kernel timing pass, then the same timing pass (50 force launches, 50
+    node launches with dt = 0) and, with --calibrate-copy, the calibration
+    copies.  So the profiled window sees the same live objects as the bench's.
+    Prints progress to stderr and a JSON line with the window's dispatch
+    indices."""
+    from inputs import spring_mesh
+    from paper_1908_05845_amd import smmo
+    from paper_1908_05845_amd.sims import SpringSim
+
+    with open(args.counter_pass) as f:
+        ref = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    n = int(ref["trace_window"]["after_steps"])
+    sim = SpringSim(spring_mesh(1000, 1000), 1e-5, 0.3)
+    heap = sim.heap
+    lib = smmo.load_library()
+    stream = torch.cuda.current_stream().cuda_stream
+    hp, cs, cn = heap.h, heap.cls["Spring"], heap.cls["Node"]
+    argp, asz = smmo.C.byref(sim.args), smmo.C.sizeof(sim.args)
+    tuned = ref.get("autotune") or {}
+    if tuned.get("kept") == "tuned":
+        for m, cls, key in ((sim.m_force, cs, "spring.force"), (sim.m_node, cn, "spring.node_update")):
+            t = tuned[key]
+            smmo.smmo_set_launch(hp, m, cls, t["wg"], t["waves"], t.get("group", 0))
+    for i in range(n):
+        lib.smmo_parallel_do(hp, cs, sim.m_force, argp, asz, stream)
+        lib.smmo_parallel_do(hp, cn, sim.m_node, argp, asz, stream)
+        if (i + 1) % 1000 == 0:
+            torch.cuda.synchronize()
+            print("counter pass: %d of %d steps" % (i + 1, n), file=sys.stderr, flush=True)
+    frozen = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit)
+    ks = args.kernel_steps
+    for _ in range(ks):
+        lib.smmo_parallel_do(hp, cs, sim.m_force, smmo.C.byref(frozen), asz, stream)
+    for _ in range(ks):
+        lib.smmo_parallel_do(hp, cn, sim.m_node, smmo.C.byref(frozen), asz, stream)
+    torch.cuda.synchronize()
+    st = heap.stats()
+    print(json.dumps({"counter_pass_of": ref.get("config", {}).get("workload"), "steps_before": n,
+                      "live_springs": int(st.live_objects[cs]),
+                      "trace_window": {"spring.force": [n, n + ks], "spring.node_update": [n, n + ks]},
+                      "kernels": ref.get("kernels")}), flush=True)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
 
 
 def summarize_trace(trace_dir, bench_json):
@@ -870,6 +936,9 @@ def main():
     from paper_1908_05845_amd import smmo
 
     smmo.load_library()
+    if args.counter_pass:
+        counter_pass(args, torch)
+        return
     fn = {"spring": bench_spring, "gol": bench_gol, "nbody": bench_nbody}[args.workload]
     res, cpu_leg, steps, warmup = fn(args, torch)
     extras = {}
