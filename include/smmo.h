@@ -130,6 +130,10 @@ typedef struct {
                                                 (methods, non-ordered parallel_new) */
     uint64_t device_deletes;                 /* objects released by device
                                                 deallocation (methods, smmo_destroy) */
+    uint64_t bitmap_spins;                   /* extra rounds of converged bitmap
+                                                switches (a switch found its bit
+                                                not yet in the expected state) */
+    uint64_t lookups;                        /* active-block and free-block searches */
 } smmo_stats;
 
 typedef struct {

@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_enumerate(HeapView h, uint32_t cls, uin
     }
     if (lane == 0) {
         const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-        const uint32_t d = __hip_atomic_fetch_add(h.ctrl + CTRL_RDONE + cls, 1u, __ATOMIC_ACQ_REL,
+        const uint32_t d = __hip_atomic_fetch_add(h.ctrl + CTRL_RDONE + cls, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
         if (d == nwaves - 1) {
             const uint32_t r = ald32(h.ctrl + CTRL_RCOUNT + cls);
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(256) void k_gather(HeapView h, uint32_t cls, FieldS
         }
     }
     if (lane == 0) {
-        const uint32_t d = __hip_atomic_fetch_add(h.ctrl + CTRL_GDONE, 1u, __ATOMIC_ACQ_REL,
+        const uint32_t d = __hip_atomic_fetch_add(h.ctrl + CTRL_GDONE, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
         if (d == nw - 1) {
             *out_count = ald32(h.ctrl + CTRL_GCOUNT);
@@ -973,6 +973,8 @@ smmo_status smmo_heap_stats(smmo_heap *h, smmo_stats *out)
         out->alloc_retries += *reinterpret_cast<const uint64_t *>(e + EV_RETRY);
         out->device_news += *reinterpret_cast<const uint64_t *>(e + EV_NEWS);
         out->device_deletes += *reinterpret_cast<const uint64_t *>(e + EV_DELS);
+        out->bitmap_spins += *reinterpret_cast<const uint64_t *>(e + EV_SPIN);
+        out->lookups += *reinterpret_cast<const uint64_t *>(e + EV_FIND);
     }
     const uint32_t err = w[CTRL_ERR];
     out->device_error = err == 0 ? SMMO_OK : (err == ERR_NOMEM ? SMMO_ENOMEM : SMMO_EDEVICE);

@@ -23,8 +23,15 @@ namespace smmo {
 
 // ---------------------------------------------------------------- atomics --
 // Bitmap words and block headers are shared mutable state; all accesses go
-// through agent-scope atomics so that they bypass the non-coherent per-CU
-// vector L1.
+// through agent-scope atomics, which are performed at the device's point of
+// coherence (past the per-CU L1 and the per-XCD L2).  They are relaxed: an
+// acquire or release at agent scope makes the compiler write back and
+// invalidate the whole L2 of the XCD around the atomic, which on this chip
+// costs far more than the atomic.  The orderings the allocator needs are
+// among these atomics themselves: a thread's atomic whose result it uses has
+// been performed before its next access is issued, and a block-type store is
+// made complete (complete_prior) before the bitmap update that publishes
+// it.  Object data written by methods is published at kernel boundaries.
 __device__ __forceinline__ uint64_t ald(const uint64_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -41,16 +48,9 @@ __device__ __forceinline__ uint64_t aand(uint64_t *p, uint64_t v)
 {
     return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// allocation-bitmap updates order the block type (published before the
-// bitmap is reset, Alg. initialize_block) against slot reservation
-__device__ __forceinline__ uint64_t aor_ar(uint64_t *p, uint64_t v)
-{
-    return __hip_atomic_fetch_or(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t aand_ar(uint64_t *p, uint64_t v)
-{
-    return __hip_atomic_fetch_and(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
+// waits until every earlier memory access of this thread (stores included)
+// has been performed
+__device__ __forceinline__ void complete_prior() { __builtin_amdgcn_s_waitcnt(0); }
 
 __device__ __forceinline__ void raise_error(const HeapView &h, uint32_t bits)
 {
@@ -202,7 +202,9 @@ __device__ __forceinline__ void run_ops_wave(const HeapView &h, OpQueue &q)
                 bitop_try(h, q.op[i]);
                 pend |= q.op[i].dir != 0;
             }
-        if (__ballot(pend) == 0) break;
+        const uint64_t pending = __ballot(pend);
+        if (pending == 0) break;
+        if (lane_id() == (uint32_t)(__ffsll((unsigned long long)pending) - 1)) count_event(h, EV_SPIN);
         if (it >= h.spin_limit) {
             if (pend) raise_error(h, ERR_SPIN);
             break;
@@ -219,6 +221,7 @@ __device__ __forceinline__ void run_ops_lane(const HeapView &h, OpQueue &q)
             raise_error(h, ERR_SPIN);
             return;
         }
+        if (it) count_event(h, EV_SPIN);
 #pragma unroll
         for (int i = 0; i < kMaxOps; ++i)
             if (q.op[i].dir) bitop_try(h, q.op[i]);
@@ -238,6 +241,7 @@ __device__ __forceinline__ void switch_bit_lane(const HeapView &h, uint32_t bmid
 // Rotation", sec.5.3.2).  May fail spuriously while levels are inconsistent.
 __device__ __forceinline__ int64_t find_set(const HeapView &h, uint32_t bmid, uint32_t seed)
 {
+    count_event(h, EV_FIND);
     uint32_t idx = 0;
     for (int lvl = (int)h.nlev - 1; lvl >= 0; --lvl) {
         const uint64_t c = ald(h.bm_word(bmid, (uint32_t)lvl, idx));
@@ -284,11 +288,14 @@ __device__ __forceinline__ int64_t claim_free_block(const HeapView &h, uint32_t 
 }
 
 // Alg. initialize_block: publish the type, then reset the allocation bitmap
-// (every class has capacity 64, so no tail bits are pre-set).
+// (every class has capacity 64, so no tail bits are pre-set); both complete
+// before the caller sets the block's allocated and active bits.
 __device__ __forceinline__ void initialize_block(const HeapView &h, uint32_t bid, uint32_t cls)
 {
     __hip_atomic_store(h.type + bid, cls, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(h.alloc_bm + bid, 0ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    complete_prior();
+    __hip_atomic_store(h.alloc_bm + bid, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    complete_prior();
 }
 
 // Block::reserve, extended to up to n slots at once (reserve_multiple):
@@ -303,7 +310,7 @@ __device__ __forceinline__ uint64_t reserve_slots(const HeapView &h, uint32_t bi
     for (int it = 0; it < 64; ++it) {
         const uint64_t want = lowest_bits(~cur, n);
         if (!want) return 0;
-        const uint64_t prev = aor_ar(p, want);
+        const uint64_t prev = aor(p, want);
         const uint64_t got = want & ~prev;
         if (got) {
             filled = (prev | want) == ~0ull;
@@ -324,19 +331,21 @@ __device__ __forceinline__ bool invalidate_block(const HeapView &h, uint32_t bid
 {
     uint64_t *p = h.alloc_bm + bid;
     for (int attempt = 0; attempt < kMaxOps - 3; ++attempt) {
-        const uint64_t before = aor_ar(p, ~0ull);
+        const uint64_t before = aor(p, ~0ull);
         if (before == ~0ull) return false;
         const uint32_t t = ald32(h.type + bid);
         if (before == 0) {
             // The block is ours and empty.  Retire its type before it is
-            // marked free, so a stale block list sees it as not of class t.
+            // marked free, so a stale block list sees it as not of class t
+            // and a later initialize_block's store of a new type comes after.
             __hip_atomic_store(h.type + bid, kNull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            complete_prior();
             q.push(bm_active(t), bid, -1);
             q.push(bm_alloc(t), bid, -1);
             q.push(BM_FREE, bid, +1);
             return true;
         }
-        const uint64_t before_rb = aand_ar(p, before);
+        const uint64_t before_rb = aand(p, before);
         if (before_rb != ~0ull) q.push(bm_active(t), bid, -1);
         if ((before_rb & before) != 0) return false;
         // empty again: retry the invalidation
@@ -351,7 +360,7 @@ __device__ __forceinline__ bool invalidate_block(const HeapView &h, uint32_t bid
 __device__ __forceinline__ void release_slots(const HeapView &h, uint32_t cls, uint32_t bid,
                                               uint64_t mask, OpQueue &q)
 {
-    const uint64_t prev = aand_ar(h.alloc_bm + bid, ~mask);
+    const uint64_t prev = aand(h.alloc_bm + bid, ~mask);
     if ((prev & mask) != mask) {
         raise_error(h, ERR_BADHANDLE);   // releasing a free slot
         return;
@@ -388,7 +397,9 @@ __device__ __forceinline__ uint32_t leader_allocate(const HeapView &h, uint32_t 
         bool filled;
         const uint64_t g = reserve_slots(h, (uint32_t)bid, n, filled);
         if (g) {
-            const uint32_t t = __hip_atomic_load(h.type + bid, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            // issued after the reservation has been performed (its result
+            // is used), so it sees the type published before the reset
+            const uint32_t t = ald32(h.type + bid);
             if (filled) switch_bit_lane(h, bm_active(t), (uint32_t)bid, -1);
             if (t == cls) {
                 got = g;

@@ -72,6 +72,8 @@ enum : uint32_t {
     EV_RETRY = 2,         // failed slot reservations (retried)
     EV_NEWS = 4,          // objects created by device allocation
     EV_DELS = 6,          // objects released by device deallocation
+    EV_SPIN = 8,          // extra rounds of converged bitmap switches
+    EV_FIND = 10,         // active-block and free-block searches
 };
 
 // statistics block (u64 words starting at CTRL_STATS)

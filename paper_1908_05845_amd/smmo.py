@@ -53,7 +53,8 @@ class smmo_stats(C.Structure):
                 ("free_blocks", C.c_uint64), ("total_blocks", C.c_uint64),
                 ("fragmentation", C.c_double), ("device_error", C.c_int32),
                 ("block_bytes", C.c_uint32), ("slow_paths", C.c_uint64), ("alloc_retries", C.c_uint64),
-                ("device_news", C.c_uint64), ("device_deletes", C.c_uint64)]
+                ("device_news", C.c_uint64), ("device_deletes", C.c_uint64),
+                ("bitmap_spins", C.c_uint64), ("lookups", C.c_uint64)]
 
 
 class smmo_invariants(C.Structure):
