@@ -68,14 +68,29 @@ __device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, 
 // is a block of the class; for an entry past the end of R, bid[j] repeats a
 // valid block and own[j] is false; bm[j] is 0 whenever own[j] is false.  f may
 // load from any bid[j] but must store only to blocks it owns.
+// R is split into eight contiguous ranges, one per XCD (work-group g runs on
+// XCD g mod 8), walked by that XCD's wavefronts in grid-stride order; so a
+// class's blocks and the blocks of another class that they gather from (in
+// creation order: nodes and their springs) meet in the same L2 from one
+// do-all to the next.  With fewer than eight work-groups the whole R is one
+// range.
 template <int U, class F>
 __device__ __forceinline__ void for_each_block_group(const HeapView &h, uint32_t cls, F &&f)
 {
     const uint32_t r = __builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_RFINAL + cls));
     const uint32_t *R = h.R + (uint64_t)cls * h.M;
     const uint32_t wpg = blockDim.x >> 6;
-    const uint32_t step = gridDim.x * wpg * U;
-    for (uint32_t base = (xcd_logical_wg() * wpg + (threadIdx.x >> 6)) * U; base < r; base += step) {
+    const uint32_t G = gridDim.x, g = blockIdx.x, x = g & 7u;
+    const uint32_t ngroups = (r + U - 1) / U;
+    uint32_t glo = 0, ghi = ngroups, lw = g * wpg + (threadIdx.x >> 6), lstep = G * wpg;
+    if (G >= 8) {
+        glo = (uint32_t)((uint64_t)ngroups * x / 8);
+        ghi = (uint32_t)((uint64_t)ngroups * (x + 1) / 8);
+        lw = (g >> 3) * wpg + (threadIdx.x >> 6);
+        lstep = ((G - x + 7) / 8) * wpg;
+    }
+    for (uint32_t gi = glo + lw; gi < ghi; gi += lstep) {
+        const uint32_t base = gi * U;
         uint32_t bid[U];
         uint64_t bm[U];
         bool own[U];
