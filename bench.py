@@ -77,11 +77,21 @@ def kernel_source_hash():
     other sources is not reported as these kernels' traffic."""
     import hashlib
 
+    import re
+
     h = hashlib.sha256()
     for fn in SPRING_KERNEL_SOURCES:
-        with open(os.path.join(HERE, fn), "rb") as f:
-            h.update(fn.encode())
-            h.update(f.read())
+        with open(os.path.join(HERE, fn)) as f:
+            text = f.read()
+        # comments and blank lines do not change the compiled kernels
+        if fn.endswith(".py"):
+            text = re.sub(r"#[^\n]*", "", text)
+        else:
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+        h.update(fn.encode())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 
@@ -281,6 +291,7 @@ def bench_spring(args, torch):
     heap.sync()
     st1 = heap.stats()
     live1 = (st1.live_objects[cs], st1.live_objects[cn])
+    defrag = None if args.no_extras else measure_spring_defrag(torch, smmo, heap, lib, sim, stream, frozen)
     # live objects processed per step: springs alive at the start of each
     # force pass (breaks during the run counted at the mean) plus all nodes
     springs_mean = 0.5 * (live0[0] + live1[0])
@@ -331,6 +342,8 @@ def bench_spring(args, torch):
                    "eager_host_ms_per_step": eager_wall / max(eager_n, 1) * 1e3},
         "device_error": st2.device_error,
     }
+    if defrag is not None:
+        res["defrag"] = defrag
 
     def cpu_leg():
         from oracle import spring_steps
@@ -632,6 +645,43 @@ def measure_wator(torch):
         sim.heap.close()
     res["ablations_512x512_300it"] = abl
     return res
+
+
+def measure_spring_defrag(torch, smmo, heap, lib, sim, stream, frozen):
+    """After the timed steps (springs broken, blocks part empty): whole-step
+    time before and after CompactGpu merges the Spring blocks (n = 1, 2, 3
+    in turn), on frozen steps (force pass, then node pass with dt = 0) so
+    that the state is the same for every measurement."""
+    cs, cn = heap.cls["Spring"], heap.cls["Node"]
+    asz = smmo.C.sizeof(sim.args)
+
+    def steps(n=200):
+        for _ in range(10):
+            lib.smmo_parallel_do(heap.h, cs, sim.m_force, smmo.C.byref(sim.args), asz, stream)
+            lib.smmo_parallel_do(heap.h, cn, sim.m_node, smmo.C.byref(frozen), asz, stream)
+        torch.cuda.synchronize()
+        ev = events(torch, 2)
+        ev[0].record()
+        for _ in range(n):
+            lib.smmo_parallel_do(heap.h, cs, sim.m_force, smmo.C.byref(sim.args), asz, stream)
+            lib.smmo_parallel_do(heap.h, cn, sim.m_node, smmo.C.byref(frozen), asz, stream)
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / n * 1e3
+
+    def state():
+        st = heap.stats()
+        return {"spring_blocks": int(st.blocks[cs]), "live_springs": int(st.live_objects[cs]),
+                "spring_fragmentation": 1.0 - st.live_objects[cs] / (64.0 * st.blocks[cs])}
+
+    out = {"before": dict(state(), step_us=steps()), "after": []}
+    for n in (1, 2, 3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        passes, moved = heap.defragment("Spring", n=n, k1=0, max_passes=64)
+        ms = (time.perf_counter() - t0) * 1e3
+        out["after"].append(dict(state(), n=n, passes=passes, moved=moved, defrag_host_ms=ms, step_us=steps()))
+    return out
 
 
 def measure_copy_bandwidth(torch):
@@ -978,7 +1028,7 @@ def main():
         "roofline": res["roofline"],
         "cpu_baseline": cpu,
     }
-    for k in ("step_hbm", "kernels", "autotune", "launch", "trace_window", "device_error"):
+    for k in ("step_hbm", "kernels", "autotune", "launch", "trace_window", "device_error", "defrag"):
         if k in res:
             line[k] = res[k]
     line.update(extras)

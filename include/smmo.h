@@ -233,6 +233,30 @@ smmo_status smmo_gather_soa(smmo_heap *h, uint32_t class_id, const uint32_t *fie
                             uint32_t nfields, void *const *out_ptrs, uint32_t *out_handles,
                             uint32_t capacity, uint32_t *out_count, smmo_stream stream);
 
+/* A caller-owned device array of handles that smmo_defragment rewrites
+ * together with the heap's own HANDLE fields (bit 31 of each entry is kept). */
+typedef struct {
+    uint32_t *handles;
+    uint64_t count;
+} smmo_handle_array;
+
+/* Memory defragmentation of class `class_id` (CompactGpu, Ch.6): blocks that
+ * are at most n/(n+1) full (n = 1..8, the defragmentation factor) are
+ * candidates; in a pass, the first floor(d/(n+1)) of the d candidates are
+ * source blocks, each merged into n other candidates, and become free.
+ * Every live HANDLE field of every class, and every entry of the `next`
+ * external arrays, that names a moved object is rewritten to its new handle
+ * (bit 31 is kept; SMMO_NULL entries are skipped).  Passes repeat until at
+ * most k1 candidates remain, fewer than n + 1 do, or max_passes ran.
+ * Stop-the-world: nothing else may run on the heap meanwhile; objects keep
+ * their field values but not their handles.  Handles held anywhere else go
+ * stale.  Synchronizes (reads the candidate count once per pass).
+ * out_passes and out_moved (host, may be NULL) receive the number of passes
+ * and of moved objects. */
+smmo_status smmo_defragment(smmo_heap *h, uint32_t class_id, uint32_t n, uint32_t k1, uint32_t max_passes,
+                            const smmo_handle_array *ext, uint32_t next, smmo_stream stream,
+                            uint32_t *out_passes, uint64_t *out_moved);
+
 /* ---- synchronization, statistics, diagnostics --------------------------- */
 
 /* Waits for all work enqueued on the heap and returns the device error word

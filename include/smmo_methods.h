@@ -163,7 +163,7 @@ typedef struct {
 /* ---- wa-tor (Ch.7 "wa-tor"): fish and sharks on a W x H torus ------------
  * Classes and fields (the thesis's Agent subclasses Fish and Shark are two
  * classes here):
- *   Cell  U32 "agent" (a Fish handle, a Shark handle with bit 31 set, or
+ *   Cell  HANDLE "agent" (a Fish handle, a Shark handle with bit 31 set, or
  *         SMMO_NULL), HANDLE "nb" x4 (neighbour cells up, right, down, left),
  *         U8 "req" x5 (requests from those neighbours; [4] = stay), I32
  *         "cell_id" (y * width + x)

@@ -537,6 +537,13 @@ smmo_status run_stats(smmo_heap *h, hipStream_t st)
 // ------------------------------------------------------- internal helpers --
 namespace smmo {
 
+smmo_status heap_check_class(const smmo_heap *h, uint32_t cls) { return check_class(h, cls); }
+smmo_status heap_read_ctrl(smmo_heap *h, uint32_t first_word, uint32_t nwords)
+{
+    return read_ctrl(h, first_word, nwords);
+}
+smmo_status heap_launch_check(const char *what) { return launch_check(what); }
+
 smmo_status fail(smmo_status st, const std::string &msg)
 {
     g_last_error = msg;

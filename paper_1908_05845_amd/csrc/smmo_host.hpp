@@ -66,6 +66,7 @@ struct smmo_heap {
     uint32_t launch_waves[64][SMMO_MAX_CLASSES] = {};
     uint8_t launch_group[64][SMMO_MAX_CLASSES] = {};
     uint32_t cur_method = 0xFFFFFFFFu;     // method being launched by smmo_parallel_do
+    uint64_t defrag_nonce = 0;             // marks the source blocks of a defragmentation pass
 };
 
 namespace smmo {
@@ -108,5 +109,11 @@ struct MethodEntry {
 };
 
 const MethodEntry *method_table(uint32_t *count);
+
+// heap.hip helpers for the other translation units: class id check, control
+// word read-back (synchronizes with the heap's last stream), launch error check
+smmo_status heap_check_class(const smmo_heap *h, uint32_t cls);
+smmo_status heap_read_ctrl(smmo_heap *h, uint32_t first_word, uint32_t nwords);
+smmo_status heap_launch_check(const char *what);
 
 } // namespace smmo

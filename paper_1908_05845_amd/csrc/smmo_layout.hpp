@@ -63,6 +63,8 @@ enum : uint32_t {
     CTRL_RCOUNT = 16,     // [class] enumeration: running length of R
     CTRL_RDONE = 32,      // [class] enumeration: finished wavefronts
     CTRL_RFINAL = 48,     // [class] length of R after the last enumeration
+    CTRL_DCOUNT = 64,     // defragmentation: number of candidate blocks
+    CTRL_DMOVED = 66,     // u64: defragmentation: objects moved
     CTRL_STATS = 128,     // u64 statistics / invariant results (host reads)
 };
 

@@ -291,7 +291,7 @@ smmo_status bind_wator(smmo_heap *h, const smmo_wator_args &a, WatorK &k)
     k.cell_cls = a.cell_class;
     k.fish_cls = a.fish_class;
     k.shark_cls = a.shark_class;
-    BIND(a.cell_class, "agent", SMMO_U32, 1, &k.c_agent, nullptr);
+    BIND(a.cell_class, "agent", SMMO_HANDLE, 1, &k.c_agent, nullptr);
     BIND(a.cell_class, "nb", SMMO_HANDLE, 4, &k.c_nb, &k.c_nb_stride);
     BIND(a.cell_class, "req", SMMO_U8, 5, &k.c_req, &k.c_req_stride);
     BIND(a.cell_class, "cell_id", SMMO_I32, 1, &k.c_id, nullptr);

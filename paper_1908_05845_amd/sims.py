@@ -22,7 +22,7 @@ NBODY_CLASSES = {
 }
 
 WATOR_CLASSES = {
-    "Cell": [("agent", "u32", 1), ("nb", "handle", 4), ("req", "u8", 5), ("cell_id", "i32", 1)],
+    "Cell": [("agent", "handle", 1), ("nb", "handle", 4), ("req", "u8", 5), ("cell_id", "i32", 1)],
     "Fish": [("pos", "handle", 1), ("new_pos", "handle", 1), ("timer", "i32", 1)],
     "Shark": [("pos", "handle", 1), ("new_pos", "handle", 1), ("timer", "i32", 1), ("energy", "i32", 1)],
 }

@@ -90,6 +90,10 @@ class smmo_adjoint_args(C.Structure):
                 ("seed_vy", C.c_void_p)]
 
 
+class smmo_handle_array(C.Structure):
+    _fields_ = [("handles", C.c_void_p), ("count", C.c_uint64)]
+
+
 class smmo_ls_args(C.Structure):
     _fields_ = [("target_class", C.c_uint32), ("n", C.c_uint32), ("workers", C.c_uint32),
                 ("reserved", C.c_uint32), ("handles", C.c_void_p)]
@@ -125,7 +129,7 @@ EXPORTS = [
     "smmo_field_id", "smmo_block_bytes", "smmo_heap_bytes", "smmo_alloc_heap", "smmo_heap_free",
     "smmo_parallel_new", "smmo_parallel_do", "smmo_destroy", "smmo_gather_soa", "smmo_sync",
     "smmo_heap_stats", "smmo_check_invariants", "smmo_clear_error", "smmo_heap_info",
-    "smmo_method_id", "smmo_last_error", "smmo_set_launch",
+    "smmo_method_id", "smmo_last_error", "smmo_set_launch", "smmo_defragment",
 ]
 
 
@@ -161,6 +165,7 @@ def load_library(path: str = LIB_PATH):
             "smmo_heap_info": (S, [P, P, P]),
             "smmo_method_id": (S, [C.c_char_p, P]),
             "smmo_set_launch": (S, [P, U32, U32, U32, U32, U32]),
+            "smmo_defragment": (S, [P, U32, U32, U32, U32, P, U32, P, P, P]),
             "smmo_last_error": (S, [C.c_char_p, C.c_size_t]),
         }
         for name, (res, args) in sig.items():
@@ -306,6 +311,22 @@ class BoundLaunch:
             raise SmmoError(st, _last_error(self.lib))
 
 
+def smmo_defragment(heap, class_id: int, n: int = 1, k1: int = 0, max_passes: int = 32, external=(),
+                    stream=None):
+    """Defragments class_id (see smmo.h); external = device tensors of handles
+    to rewrite as well.  Returns (passes, moved objects)."""
+    lib = load_library()
+    arr = (smmo_handle_array * max(1, len(external)))()
+    for i, t in enumerate(external):
+        arr[i].handles = _ptr(t)
+        arr[i].count = t.numel()
+    passes = C.c_uint32()
+    moved = C.c_uint64()
+    _check(lib, lib.smmo_defragment(heap, class_id, n, k1, max_passes, arr if external else None, len(external),
+                                    _stream(stream), C.byref(passes), C.byref(moved)))
+    return passes.value, moved.value
+
+
 def smmo_destroy(heap, class_id: int, handles, n: int, stream=None) -> None:
     lib = load_library()
     _check(lib, lib.smmo_destroy(heap, class_id, _ptr(handles), n, _stream(stream)))
@@ -426,6 +447,11 @@ class Heap:
 
     def do(self, cname: str, method: str, args=None, stream=None):
         smmo_parallel_do(self.h, self.cls[cname], smmo_method_id(method), args, stream)
+
+    def defragment(self, cname: str, n: int = 1, k1: int = 0, max_passes: int = 32, external=(), stream=None):
+        """CompactGpu passes on class cname; returns (passes, moved objects).
+        `external`: int32 device tensors of handles to rewrite too."""
+        return smmo_defragment(self.h, self.cls[cname], n, k1, max_passes, external, stream)
 
     def destroy(self, cname: str, handles, stream=None):
         handles = handles.to(self.torch.int32).contiguous()

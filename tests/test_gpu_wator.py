@@ -83,3 +83,28 @@ def test_256_torus_checked(dev):
     print("  news %d deletes %d fragmentation %.3f" % (st.device_news, st.device_deletes, st.fragmentation),
           flush=True)
     assert st.device_news > 10000 and st.device_deletes > 10000
+
+
+def test_defragmented_between_iterations(dev):
+    """Fish and Shark blocks merged (CompactGpu, n = 1) every 5 iterations:
+    Cell::agent handles are rewritten with the shark tag kept, and the state
+    stays equal to the oracle's bit for bit."""
+    print("wator 48x48 with defragmentation", flush=True)
+    W = H = 48
+    prm = (3, 8, 5, 3)
+    init = wator_init(W, H, seed=5, p_fish=0.35, p_shark=0.1, fish_spawn=prm[0], shark_spawn=prm[1],
+                      energy0=prm[2])
+    ref = WatorWorld(W, H, 5, prm, init)
+    sim = WatorSim(W, H, 5, prm, init)
+    moved = 0
+    for it in range(60):
+        ref.step(1)
+        sim.step(1)
+        if it % 5 == 4:
+            for cls in ("Fish", "Shark"):
+                moved += sim.heap.defragment(cls, n=1)[1]
+            clean(sim.heap)
+        kr, tr, er, cr = ref.read()
+        kg, tg, eg, cg = sim.read()
+        assert cg == cr and np.array_equal(kg, kr) and np.array_equal(tg, tr) and np.array_equal(eg, er), it
+    assert moved > 0
