@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--counter-pass", metavar="BENCH_JSON",
                     help="profiling aid: replay the state of the given bench run's timing window "
                          "(for rocprofv3 --pmc)")
+    ap.add_argument("--alloc-pass", action="store_true",
+                    help="profiling aid: short runs of the allocator-bound kernels (for rocprofv3 --pmc)")
+    ap.add_argument("--summarize-l2", nargs="+", metavar="DIR",
+                    help="L2 hit rate and atomic counts per kernel from rocprofv3 --pmc runs; needs no GPU")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and adjoint measurements")
     ap.add_argument("--no-autotune", action="store_true")
@@ -684,6 +688,71 @@ def measure_spring_defrag(torch, smmo, heap, lib, sim, stream, frozen):
     return out
 
 
+def measure_coalescing(torch):
+    """The thesis's memory coalescing experiment (Ch.2) in wave64 form, on a
+    1 GiB float array: read-modify-write of every element with the lanes of
+    a wavefront spread over C arrays; median of 3 passes per C.  C = 1 is
+    the attainable read-modify-write bandwidth."""
+    from paper_1908_05845_amd import smmo
+
+    n = 1 << 28
+    data = torch.zeros(n, dtype=torch.float32, device="cuda")
+    out = {"bytes_per_pass": 8 * n, "runs": []}
+    for C in (1, 2, 4, 8, 16, 32, 64):
+        smmo.smmo_coalescing_probe(data, C)
+        ts = []
+        for _ in range(3):
+            ev = events(torch, 2)
+            ev[0].record()
+            smmo.smmo_coalescing_probe(data, C)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]))
+        t = sorted(ts)[1]
+        out["runs"].append({"C": C, "ms": t, "gbs": 8 * n / (t * 1e-3) / 1e9})
+    out["slowdown_C64_vs_C1"] = out["runs"][-1]["ms"] / out["runs"][0]["ms"]
+    del data
+    return out
+
+
+def measure_allocation(torch):
+    """Heap initialization and smmo_parallel_new on the spring mesh's classes
+    (1,000,000 Node and 2,996,001 Spring objects), as allocations/s: the
+    ordered bulk path, and the device allocator path (bulk_ordered = 0) for
+    the springs."""
+    from paper_1908_05845_amd import smmo
+    from paper_1908_05845_amd.sims import SPRING_CLASSES
+
+    N, S = 1_000_000, 2_996_001
+    out = {}
+    for ordered in (1, 0):
+        cfg = smmo.smmo_config_default()
+        cfg.bulk_ordered = ordered
+        t0 = time.perf_counter()
+        heap = smmo.Heap(SPRING_CLASSES, blocks=(N + 63) // 64 + (S + 63) // 64 + 64, cfg=cfg)
+        heap.sync()
+        init_ms = (time.perf_counter() - t0) * 1e3
+        ids_n = torch.arange(N, dtype=torch.int32, device="cuda")
+        ids_s = torch.arange(S, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
+        ev = events(torch, 3)
+        ev[0].record()
+        heap.new("Node", N, id=ids_n)
+        ev[1].record()
+        heap.new("Spring", S, id=ids_s)
+        ev[2].record()
+        torch.cuda.synchronize()
+        st = heap.stats()
+        key = "ordered_bulk" if ordered else "device_allocator"
+        out[key] = {"heap_init_ms_host": init_ms, "node_new_ms": ev[0].elapsed_time(ev[1]),
+                    "spring_new_ms": ev[1].elapsed_time(ev[2]),
+                    "spring_allocations_per_s": S / (ev[1].elapsed_time(ev[2]) * 1e-3),
+                    "live": [int(st.live_objects[heap.cls["Node"]]), int(st.live_objects[heap.cls["Spring"]])],
+                    "device_error": st.device_error}
+        heap.close()
+    return out
+
+
 def measure_copy_bandwidth(torch):
     """Attainable HBM bandwidth on this GPU: a device-to-device copy of 512
     MiB (read + write = 1 GiB of traffic), median of 5 timed copies."""
@@ -947,6 +1016,62 @@ def counter_pass(args, torch):
         calibrate_copy(torch)
 
 
+def alloc_pass(torch):
+    """Profiling aid for rocprofv3 --pmc on the allocator-bound kernels: Game
+    of Life 256 x 256 (50 generations), wa-tor 512 x 512 (50 iterations) and
+    the Linux Scalability pattern (16,384 workers, n = 64).  Prints progress
+    to stderr."""
+    from inputs import config_seed, gol_init, wator_init
+    from paper_1908_05845_amd import smmo
+    from paper_1908_05845_amd.sims import GolSim, WatorSim
+
+    sim = GolSim(256, 256, gol_init(256, 256))
+    sim.step(50)
+    sim.heap.sync()
+    print("alloc pass: gol done", file=sys.stderr, flush=True)
+    w = WatorSim(512, 512, config_seed(7), (4, 12, 8, 4), wator_init(512, 512))
+    w.step(50)
+    w.heap.sync()
+    print("alloc pass: wa-tor done", file=sys.stderr, flush=True)
+    heap = smmo.Heap({"Worker": [("id", "i32", 1)], "Obj": [("payload", "u32", 16)]}, nbytes=1 << 28)
+    heap.new("Worker", 16384, id=torch.arange(16384, dtype=torch.int32, device="cuda"))
+    handles = torch.full((64 * 16384,), -1, dtype=torch.int32, device="cuda")
+    args = smmo.smmo_ls_args(heap.cls["Obj"], 64, 16384, 0, handles.data_ptr())
+    heap.do("Worker", "alloc.ls_alloc", args)
+    heap.do("Worker", "alloc.ls_free", args)
+    heap.sync()
+    print("alloc pass: linux scalability done", file=sys.stderr, flush=True)
+    print(json.dumps({"alloc_pass": "gol 256x256 x 50, wa-tor 512x512 x 50, linux scalability n=64"}), flush=True)
+
+
+def summarize_l2(dirs):
+    """Per kernel: L2 hit rate (TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum))
+    and atomics per dispatch (TCC_ATOMIC_sum at the L2, TCC_EA0_ATOMIC_sum
+    towards memory), from rocprofv3 --pmc runs given as directories."""
+    import re
+    from collections import defaultdict
+
+    acc = defaultdict(lambda: defaultdict(float))
+    cnt = defaultdict(lambda: defaultdict(int))
+    for d in dirs:
+        for r in _read_counter_csv(d):
+            name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", ""))
+            acc[name][r["Counter_Name"]] += float(r["Counter_Value"])
+            cnt[name][r["Counter_Name"]] += 1
+    print("| kernel | dispatches | L2 hit rate | L2 atomics / dispatch | atomics to memory / dispatch |")
+    print("|---|---|---|---|---|")
+    for name in sorted(acc, key=lambda k: -acc[k].get("TCC_ATOMIC_sum", 0.0)):
+        a, c = acc[name], cnt[name]
+        if not (name.startswith("k_") or "copyBuffer" in name):
+            continue
+        hit, miss = a.get("TCC_HIT_sum"), a.get("TCC_MISS_sum")
+        rate = "%.1f %%" % (100.0 * hit / (hit + miss)) if hit is not None and miss is not None and hit + miss else "-"
+        at = "%.0f" % (a["TCC_ATOMIC_sum"] / c["TCC_ATOMIC_sum"]) if c.get("TCC_ATOMIC_sum") else "-"
+        ea = "%.0f" % (a["TCC_EA0_ATOMIC_sum"] / c["TCC_EA0_ATOMIC_sum"]) if c.get("TCC_EA0_ATOMIC_sum") else "-"
+        n = max(c.values())
+        print("| %s | %d | %s | %s | %s |" % (name, n, rate, at, ea))
+
+
 def summarize_trace(trace_dir, bench_json):
     """Average kernel durations from a rocprofv3 kernel trace: over the bench's
     timing-pass window (the same dispatches its HIP events timed) and over
@@ -981,6 +1106,9 @@ def main():
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
         return
+    if args.summarize_l2:
+        summarize_l2(args.summarize_l2)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)"
               % args.gpus, file=sys.stderr)
@@ -996,11 +1124,16 @@ def main():
     if args.counter_pass:
         counter_pass(args, torch)
         return
+    if args.alloc_pass:
+        alloc_pass(torch)
+        return
     fn = {"spring": bench_spring, "gol": bench_gol, "nbody": bench_nbody}[args.workload]
     res, cpu_leg, steps, warmup = fn(args, torch)
     extras = {}
     if args.workload == "spring" and not args.no_extras:
         extras["copy_bandwidth"] = measure_copy_bandwidth(torch)
+        extras["coalescing"] = measure_coalescing(torch)
+        extras["allocation"] = measure_allocation(torch)
         extras["batched"] = measure_batched(torch, res["value"])
         extras["adjoint"] = measure_adjoint(torch, res["value"])
         extras["gol"] = measure_gol_extra(torch)

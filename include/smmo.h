@@ -240,6 +240,15 @@ typedef struct {
     uint64_t count;
 } smmo_handle_array;
 
+/* The memory coalescing experiment (Ch.2, "Memory coalescing experiment")
+ * on n floats at device pointer `data` (caller-owned): every element is read
+ * and written once (x += 8) by a grid-stride loop over `grid` work-groups of
+ * 256 threads (0 = 2048); the lanes of a wavefront touch C arrays of n/C
+ * elements each (C = 1, 2, 4, .., 64; 1 = fully coalesced).  n must be a
+ * multiple of 64 * C.  Asynchronous on `stream`; the caller times it.  A
+ * measurement of the attainable bandwidth, not part of the object model. */
+smmo_status smmo_coalescing_probe(float *data, uint64_t n, uint32_t C, uint32_t grid, smmo_stream stream);
+
 /* Memory defragmentation of class `class_id` (CompactGpu, Ch.6): blocks that
  * are at most n/(n+1) full (n = 1..8, the defragmentation factor) are
  * candidates; in a pass, the first floor(d/(n+1)) of the d candidates are

@@ -129,7 +129,7 @@ EXPORTS = [
     "smmo_field_id", "smmo_block_bytes", "smmo_heap_bytes", "smmo_alloc_heap", "smmo_heap_free",
     "smmo_parallel_new", "smmo_parallel_do", "smmo_destroy", "smmo_gather_soa", "smmo_sync",
     "smmo_heap_stats", "smmo_check_invariants", "smmo_clear_error", "smmo_heap_info",
-    "smmo_method_id", "smmo_last_error", "smmo_set_launch", "smmo_defragment",
+    "smmo_method_id", "smmo_last_error", "smmo_set_launch", "smmo_defragment", "smmo_coalescing_probe",
 ]
 
 
@@ -166,6 +166,7 @@ def load_library(path: str = LIB_PATH):
             "smmo_method_id": (S, [C.c_char_p, P]),
             "smmo_set_launch": (S, [P, U32, U32, U32, U32, U32]),
             "smmo_defragment": (S, [P, U32, U32, U32, U32, P, U32, P, P, P]),
+            "smmo_coalescing_probe": (S, [P, U64, U32, U32, P]),
             "smmo_last_error": (S, [C.c_char_p, C.c_size_t]),
         }
         for name, (res, args) in sig.items():
@@ -325,6 +326,12 @@ def smmo_defragment(heap, class_id: int, n: int = 1, k1: int = 0, max_passes: in
     _check(lib, lib.smmo_defragment(heap, class_id, n, k1, max_passes, arr if external else None, len(external),
                                     _stream(stream), C.byref(passes), C.byref(moved)))
     return passes.value, moved.value
+
+
+def smmo_coalescing_probe(data, C: int, grid: int = 0, stream=None) -> None:
+    """One pass of the coalescing experiment over a float32 device tensor."""
+    lib = load_library()
+    _check(lib, lib.smmo_coalescing_probe(_ptr(data), data.numel(), C, grid, _stream(stream)))
 
 
 def smmo_destroy(heap, class_id: int, handles, n: int, stream=None) -> None:

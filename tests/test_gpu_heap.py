@@ -319,3 +319,17 @@ def test_launch_shape_validation(dev):
     g = heap.gather("A", ["x"])
     assert torch.all(g["x"] == 3.0)
     clean(heap)
+
+
+@pytest.mark.parametrize("C", [1, 2, 64])
+def test_coalescing_probe_touches_every_element_once(dev, C):
+    import torch
+
+    data = torch.zeros(64 * 64 * 10, dtype=torch.float32, device=dev)
+    smmo.smmo_coalescing_probe(data, C, grid=3)
+    torch.cuda.synchronize()
+    assert torch.all(data == 8.0)
+    with pytest.raises(smmo.SmmoError):
+        smmo.smmo_coalescing_probe(data, 3)
+    with pytest.raises(smmo.SmmoError):
+        smmo.smmo_coalescing_probe(data[:100], 1)
