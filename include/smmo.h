@@ -107,12 +107,24 @@ typedef struct {
                                    0: every object goes through the device
                                    allocator; default 1 */
     uint32_t spin_limit;        /* bound on every retry loop; exceeding it sets
-                                   SMMO_EDEVICE instead of hanging; default 1<<22 */
+                                   SMMO_EDEVICE instead of hanging; default 1<<20 */
     uint32_t grid_waves;        /* wavefronts per method launch (0 = automatic) */
     uint32_t block_group;       /* blocks a wavefront loads together before it
                                    computes, in the methods that support it
                                    (1, 2 or 4; 0 = each method's default) */
-    uint32_t reserved[9];
+    uint32_t sparse_packing;    /* methods that can run packed do-alls (the
+                                   classes that births and deaths fragment): a
+                                   block with at most 32 live objects is sparse,
+                                   and two sparse blocks share a wavefront.
+                                   0: never pack (default; every block gets a
+                                   wavefront of its own);
+                                   1: pack when the class may have more blocks
+                                   than the launch has wavefronts, so that
+                                   packing shortens the wavefronts' walks;
+                                   2: always pack.  Modes 1 and 2 make the
+                                   enumeration read every listed block's bitmap
+                                   to build the packing plan. */
+    uint32_t reserved[8];
 } smmo_config;
 
 typedef struct {

@@ -56,16 +56,15 @@ __global__ void k_defrag_reset(HeapView h, uint32_t all)
 __global__ __launch_bounds__(256) void k_defrag_select(HeapView h, uint32_t cls, uint32_t cap)
 {
     if (heap_failed(h)) return;
-    const uint32_t r = __builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_RFINAL + cls));
-    const uint32_t *R = h.R + (uint64_t)cls * h.M;
+    const BlockList L = block_list(h, cls);
     const uint32_t lane = lane_id();
     const uint32_t nw = gridDim.x * (blockDim.x >> 6);
-    for (uint32_t i0 = global_wave_id() * 64; i0 < r; i0 += nw * 64) {
+    for (uint32_t i0 = global_wave_id() * 64; i0 < L.r; i0 += nw * 64) {
         const uint32_t i = i0 + lane;
         bool cand = false;
         uint32_t bid = 0;
-        if (i < r) {
-            bid = R[i];
+        if (i < L.r) {
+            bid = L.at(i);
             if (h.type[bid] == cls) {
                 const uint32_t c = (uint32_t)__popcll(h.alloc_bm[bid]);
                 cand = c > 0 && c <= cap;

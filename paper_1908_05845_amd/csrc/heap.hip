@@ -144,7 +144,7 @@ __global__ void k_heap_init(HeapView h)
 // atomic add (R is therefore ordered within a wavefront's range only).  The
 // last wavefront to finish publishes the length and resets the counters, so
 // the pass needs no separate reset launch and can be captured in a graph.
-__global__ __launch_bounds__(256) void k_enumerate(HeapView h, uint32_t cls, uint32_t snapshot)
+__global__ __launch_bounds__(256) void k_enumerate(HeapView h, uint32_t cls, uint32_t snapshot, uint32_t split)
 {
     const uint32_t w = global_wave_id();
     const uint32_t lane = lane_id();
@@ -155,33 +155,64 @@ __global__ __launch_bounds__(256) void k_enumerate(HeapView h, uint32_t cls, uin
         const uint64_t summ = h.nlev > 1 ? ald(h.bm_word(bm_alloc(cls), 1, w)) : 1ull;
         if (cidx < n0 && ((summ >> lane) & 1)) c = ald(h.bm_word(bm_alloc(cls), 0, cidx));
     }
-    const uint32_t cnt = (uint32_t)__popcll(c);
-    const uint32_t incl = wave_incl_scan(cnt);
-    const uint32_t tot = __shfl(incl, 63);
-    uint32_t base = 0;
-    if (tot) {
-        if (lane == 0)
-            base = __hip_atomic_fetch_add(h.ctrl + CTRL_RCOUNT + cls, tot, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        base = __shfl(base, 0);
+    // The packing plan (split): blocks with more than 32 live objects are
+    // dense.  Without it every block counts as dense.  No wavefront changes
+    // a bitmap while this kernel runs, so plain loads are enough; a lane
+    // keeps four of its blocks' bitmap loads in flight.
+    uint64_t dense = c;
+    if (snapshot || split) {
+        dense = 0;
+        const uint64_t *abm = h.alloc_bm + (uint64_t)cidx * 64;
+        uint64_t *ibm = h.iter_bm + (uint64_t)cidx * 64;
+        for (uint64_t cc = c; cc;) {
+            uint32_t b[4];
+            uint64_t bm[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                b[k] = cc ? (uint32_t)(__ffsll((unsigned long long)cc) - 1) : 64u;
+                cc &= cc - 1;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bm[k] = b[k] < 64 ? abm[b[k]] : 0ull;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (b[k] == 64) continue;
+                if (snapshot) ibm[b[k]] = bm[k];
+                if (!split || __popcll(bm[k]) > 32) dense |= 1ull << b[k];
+            }
+        }
     }
+    const uint32_t nd = (uint32_t)__popcll(dense), ns = (uint32_t)__popcll(c) - nd;
+    const uint32_t incl_d = wave_incl_scan(nd), incl_s = wave_incl_scan(ns);
+    const uint32_t tot_d = __shfl(incl_d, 63), tot_s = __shfl(incl_s, 63);
+    uint32_t base_d = 0, base_s = 0;
+    if (lane == 0) {
+        if (tot_d)
+            base_d = __hip_atomic_fetch_add(h.ctrl + CTRL_RCOUNT + cls, tot_d, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        if (tot_s)
+            base_s = __hip_atomic_fetch_add(h.ctrl + CTRL_RSCOUNT + cls, tot_s, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    }
+    base_d = __shfl(base_d, 0);
+    base_s = __shfl(base_s, 0);
     uint32_t *R = h.R + (uint64_t)cls * h.M;
-    uint32_t k = base + incl - cnt;
-    while (c) {
+    uint32_t kd = base_d + incl_d - nd, ks = base_s + incl_s - ns;
+    for (; c; c &= c - 1) {
         const uint32_t b = (uint32_t)(__ffsll((unsigned long long)c) - 1);
-        c &= c - 1;
-        const uint32_t bid = cidx * 64 + b;
-        R[k++] = bid;
-        if (snapshot) h.iter_bm[bid] = ald(h.alloc_bm + bid);
+        if ((dense >> b) & 1) R[kd++] = cidx * 64 + b;
+        else R[h.M - 1 - ks++] = cidx * 64 + b;
     }
     if (lane == 0) {
         const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
         const uint32_t d = __hip_atomic_fetch_add(h.ctrl + CTRL_RDONE + cls, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
         if (d == nwaves - 1) {
-            const uint32_t r = ald32(h.ctrl + CTRL_RCOUNT + cls);
-            __hip_atomic_store(h.ctrl + CTRL_RFINAL + cls, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t rd = ald32(h.ctrl + CTRL_RCOUNT + cls), rs = ald32(h.ctrl + CTRL_RSCOUNT + cls);
+            __hip_atomic_store(h.ctrl + CTRL_RFINAL + cls, rd + rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(h.ctrl + CTRL_RSFINAL + cls, rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(h.ctrl + CTRL_RCOUNT + cls, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(h.ctrl + CTRL_RSCOUNT + cls, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(h.ctrl + CTRL_RDONE + cls, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -360,10 +391,9 @@ __global__ __launch_bounds__(256) void k_gather(HeapView h, uint32_t cls, FieldS
     const uint32_t lane = lane_id();
     const uint32_t nw = gridDim.x * (blockDim.x >> 6);
     if (!heap_failed(h)) {
-        const uint32_t r = ald32(h.ctrl + CTRL_RFINAL + cls);
-        const uint32_t *R = h.R + (uint64_t)cls * h.M;
-        for (uint32_t i = global_wave_id(); i < r; i += nw) {
-            const uint32_t bid = R[i];
+        const BlockList L = block_list(h, cls);
+        for (uint32_t i = global_wave_id(); i < L.r; i += nw) {
+            const uint32_t bid = L.at(i);
             if (ald32(h.type + bid) != cls) continue;
             const uint64_t bm = ald(h.alloc_bm + bid);
             const uint32_t cnt = (uint32_t)__popcll(bm);
@@ -586,16 +616,23 @@ smmo_status bind_field(const smmo_schema *s, uint32_t cls, const char *name, int
                                  "' required by this method");
 }
 
-smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st)
+smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st, bool split)
 {
-    if (h->rstate[cls] == R_VALID && !snapshot) return SMMO_OK;
+    if (!snapshot && (h->rstate[cls] == R_SPLIT || (h->rstate[cls] == R_VALID && !split))) return SMMO_OK;
     const uint32_t nwaves = (h->v.lvl_n[0] + 63) / 64;
     const uint32_t grid = (nwaves + 3) / 4;
-    hipLaunchKernelGGL(k_enumerate, dim3(grid), dim3(256), 0, st, h->v, cls, snapshot ? 1u : 0u);
+    hipLaunchKernelGGL(k_enumerate, dim3(grid), dim3(256), 0, st, h->v, cls, snapshot ? 1u : 0u,
+                       split ? 1u : 0u);
     smmo_status s = launch_check("k_enumerate");
     if (s) return s;
-    h->rstate[cls] = R_VALID;
+    h->rstate[cls] = split ? R_SPLIT : R_VALID;
     return SMMO_OK;
+}
+
+bool packing_wanted(const smmo_heap *h, uint32_t cls, const LaunchShape &ls)
+{
+    const uint64_t waves = (uint64_t)ls.grid.x * (ls.block.x / 64);
+    return h->cfg.sparse_packing == 2 || (h->cfg.sparse_packing == 1 && h->ub_blocks[cls] > waves);
 }
 
 LaunchShape method_shape(const smmo_heap *h, uint32_t cls, uint32_t def_group)
@@ -747,6 +784,7 @@ smmo_status smmo_alloc_heap(smmo_schema *s, void *dev_buf, size_t bytes, const s
     if (c.spin_limit < 1024) c.spin_limit = 1024;
     if (c.block_group != 0 && c.block_group != 1 && c.block_group != 2 && c.block_group != 4)
         return fail(SMMO_EINVAL, "block_group must be 0, 1, 2 or 4");
+    if (c.sparse_packing > 2) return fail(SMMO_EINVAL, "sparse_packing must be 0, 1 or 2");
     const uint32_t bb = schema_block_bytes(s);
     // largest M whose layout fits
     uint64_t lo = 0, hi = std::min<uint64_t>(bytes / bb, kMaxBlocks);
@@ -799,6 +837,7 @@ smmo_status smmo_alloc_heap(smmo_schema *s, void *dev_buf, size_t bytes, const s
     v.rotation = c.rotation ? 1u : 0u;
     v.coalescing = c.coalescing ? 1u : 0u;
     v.spin_limit = c.spin_limit;
+    v.sparse_packing = c.sparse_packing;
     h->schema = s;
     h->base = dev_buf;
     h->bytes = bytes;

@@ -41,16 +41,16 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 template <class F>
 __device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, bool snapshot, F &&f)
 {
-    const uint32_t r = __builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_RFINAL + cls));
-    const uint32_t *R = h.R + (uint64_t)cls * h.M;
+    const BlockList L = block_list(h, cls);
+    const uint32_t r = L.r;
     const uint32_t wpg = blockDim.x >> 6;
     const uint32_t nw = gridDim.x * wpg;
     uint32_t i = xcd_logical_wg() * wpg + (threadIdx.x >> 6);
     if (i >= r) return;
-    uint32_t bid = __builtin_amdgcn_readfirstlane(R[i]);
+    uint32_t bid = __builtin_amdgcn_readfirstlane(L.at(i));
     for (;;) {
         const uint32_t in = i + nw;
-        const uint32_t bnext = __builtin_amdgcn_readfirstlane(in < r ? R[in] : 0u);
+        const uint32_t bnext = __builtin_amdgcn_readfirstlane(in < r ? L.at(in) : 0u);
         const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
         const uint64_t bm = uniform64(snapshot ? h.iter_bm[bid] : h.alloc_bm[bid]);
         if (t == cls) f(bid, bm);
@@ -77,8 +77,8 @@ __device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, 
 template <int U, class F>
 __device__ __forceinline__ void for_each_block_group(const HeapView &h, uint32_t cls, F &&f)
 {
-    const uint32_t r = __builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_RFINAL + cls));
-    const uint32_t *R = h.R + (uint64_t)cls * h.M;
+    const BlockList L = block_list(h, cls);
+    const uint32_t r = L.r;
     const uint32_t wpg = blockDim.x >> 6;
     const uint32_t G = gridDim.x, g = blockIdx.x, x = g & 7u;
     const uint32_t ngroups = (r + U - 1) / U;
@@ -95,7 +95,7 @@ __device__ __forceinline__ void for_each_block_group(const HeapView &h, uint32_t
         uint64_t bm[U];
         bool own[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) bid[j] = __builtin_amdgcn_readfirstlane(R[base + j < r ? base + j : base]);
+        for (int j = 0; j < U; ++j) bid[j] = __builtin_amdgcn_readfirstlane(L.at(base + j < r ? base + j : base));
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid[j]]);
@@ -105,6 +105,80 @@ __device__ __forceinline__ void for_each_block_group(const HeapView &h, uint32_t
         }
         f(bid, bm, own);
     }
+}
+
+// Calls f(bid, slot, live, pair) once per lane for the live objects of class cls
+// (a packed do-all): a wavefront takes one dense block of the class's list
+// (lane = slot), or two sparse blocks, lanes 0..31 serving the live slots of
+// the first in slot order and lanes 32..63 those of the second.  bid and slot
+// may differ between lanes; live is false for idle lanes (bid is then a valid
+// block and slot 0); pair (wave-uniform) says whether the wavefront holds two
+// blocks.  A block is never split across wavefronts, so the
+// deletions of one block's objects by one launch are released together.  As
+// in for_each_block, a listed block whose type is no longer cls is skipped.
+// Packing halves the wavefronts the sparse blocks need; while the list is no
+// longer than the grid every block already has a wavefront of its own, and
+// packing would only lengthen the wavefronts that get two (sparse_packing 1
+// then gives every block one wavefront; 0 never packs).  A list built without
+// the packing plan lists every block as dense.
+template <class F>
+__device__ __forceinline__ void for_each_object_packed(const HeapView &h, uint32_t cls, bool snapshot, F &&f)
+{
+    const BlockList L = block_list(h, cls);
+    const uint32_t wpg = blockDim.x >> 6;
+    const uint32_t nw = gridDim.x * wpg;
+    const bool pack = h.sparse_packing == 2 || (h.sparse_packing == 1 && L.r > nw);
+    const uint32_t nd = pack ? L.nd : L.r;       // items served one block per wavefront
+    const uint32_t ns = L.r - nd;
+    const uint32_t items = nd + (ns + 1) / 2;
+    const uint32_t lane = lane_id();
+    for (uint32_t item = xcd_logical_wg() * wpg + (threadIdx.x >> 6); item < items; item += nw) {
+        uint32_t bid, slot = lane;
+        bool live;
+        const bool pair = item >= nd;
+        if (!pair) {
+            bid = __builtin_amdgcn_readfirstlane(L.at(item));
+            const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
+            const uint64_t bm = uniform64(snapshot ? h.iter_bm[bid] : h.alloc_bm[bid]);
+            live = t == cls && ((bm >> lane) & 1);
+        } else {
+            const uint32_t j = 2 * (item - nd) + (lane >> 5);
+            const bool valid = j < ns;
+            bid = L.R[L.M - 1 - (valid ? j : j - 1)];
+            const uint64_t bm = snapshot ? h.iter_bm[bid] : h.alloc_bm[bid];
+            const uint32_t rank = lane & 31;
+            live = valid && h.type[bid] == cls && rank < (uint32_t)__popcll(bm);
+            slot = live ? nth_set_bit(bm, rank) : 0;
+        }
+        f(bid, slot, live, pair);
+    }
+}
+
+// Releases the objects that delete themselves in a packed do-all (die on the
+// lanes whose object is deleted; bid, slot and pair as for_each_object_packed
+// passes them): one multi-slot release per block of the wavefront, the two
+// blocks of a pair released side by side by lanes 0 and 32.  Converged call.
+__device__ __forceinline__ void wave_release_packed(const HeapView &h, uint32_t cls, uint32_t bid, uint32_t slot,
+                                                    bool die, bool pair)
+{
+    if (!pair) {
+        wave_release_own_block(h, cls, bid, __ballot(die));
+        return;
+    }
+    if (!__ballot(die)) return;
+    // slot mask of each half's block: an OR over the 32 lanes of the half
+    const uint64_t bit = die ? 1ull << slot : 0ull;
+    uint32_t lo = (uint32_t)bit, hi = (uint32_t)(bit >> 32);
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        lo |= (uint32_t)__shfl_xor((int)lo, d);
+        hi |= (uint32_t)__shfl_xor((int)hi, d);
+    }
+    const uint64_t mask = ((uint64_t)hi << 32) | lo;
+    OpQueue q;
+    q.reset();
+    if ((lane_id() & 31) == 0 && mask) release_slots(h, cls, bid, mask, q);
+    run_ops_wave(h, q);
 }
 
 template <class T>

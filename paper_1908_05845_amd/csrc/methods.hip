@@ -57,13 +57,13 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 }
 
 // Alive::death - if the cell's count is not 2 or 3: cell dies, delete this
+// (a packed do-all: the Alive class is the sparse one)
 __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.alive_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
+    for_each_object_packed(h, p.alive_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         bool die = false;
-        if ((bm >> s) & 1) {
+        if (live) {
             const int32_t cid = farr<int32_t>(h, bid, p.a_id)[s];
             const uint32_t hc = p.cells[cid];
             const int32_t n = fref<int32_t>(h, hc, p.c_count);
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
                 die = true;
             }
         }
-        wave_release_own_block(h, p.alive_cls, bid, __ballot(die));
+        wave_release_packed(h, p.alive_cls, bid, s, die, pair);
     });
 }
 
@@ -127,8 +127,8 @@ smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     if (s) return s;
     const uint32_t want = Which == 1 ? a.alive_class : a.cell_class;
     if (cls != want) return fail(SMMO_EINVAL, "gol: method runs on a different class");
-    if ((s = ensure_enumerated(h, cls, false, st))) return s;
     const LaunchShape ls = method_shape(h, cls);
+    if ((s = ensure_enumerated(h, cls, false, st, Which == 1 && packing_wanted(h, cls, ls)))) return s;
     if (Which == 0) hipLaunchKernelGGL(k_gol_count, ls.grid, ls.block, 0, st, h->v, k);
     if (Which == 1) hipLaunchKernelGGL(k_gol_death, ls.grid, ls.block, 0, st, h->v, k);
     if (Which == 2) hipLaunchKernelGGL(k_gol_birth, ls.grid, ls.block, 0, st, h->v, k);
@@ -158,20 +158,19 @@ __global__ __launch_bounds__(256) void k_nbody_force(HeapView h, NbodyK p)
     __shared__ float4 tile[4][64];
     __shared__ float2 red[4][64];
     if (heap_failed(h)) return;
-    const uint32_t r = __builtin_amdgcn_readfirstlane(ald32(h.ctrl + CTRL_RFINAL + p.cls));
-    const uint32_t *R = h.R + (uint64_t)p.cls * h.M;
+    const BlockList L = block_list(h, p.cls);
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (uint32_t ib = xcd_logical_wg(); ib < r; ib += gridDim.x) {
-        const uint32_t bid = R[ib];
+    for (uint32_t ib = xcd_logical_wg(); ib < L.r; ib += gridDim.x) {
+        const uint32_t bid = L.at(ib);
         if (ald32(h.type + bid) != p.cls) continue;     // same for the whole work-group
         const uint64_t bmi = ald(h.alloc_bm + bid);
         const float xi = farr<float>(h, bid, p.o_x)[lane];
         const float yi = farr<float>(h, bid, p.o_y)[lane];
         float ax = 0.f, ay = 0.f, cx = 0.f, cy = 0.f;
-        for (uint32_t j0 = 0; j0 < r; j0 += 4) {
+        for (uint32_t j0 = 0; j0 < L.r; j0 += 4) {
             const uint32_t jt = j0 + w;
-            if (jt >= r) break;                          // wave-uniform
-            const uint32_t jb = __builtin_amdgcn_readfirstlane(R[jt]);
+            if (jt >= L.r) break;                        // wave-uniform
+            const uint32_t jb = __builtin_amdgcn_readfirstlane(L.at(jt));
             if (__builtin_amdgcn_readfirstlane(ald32(h.type + jb)) != p.cls) continue;
             const uint64_t bmj = uniform64(ald(h.alloc_bm + jb));
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -522,12 +521,12 @@ struct AxpyK {
     float a, b;
 };
 
+// packed do-all (sparse blocks two per wavefront)
 __global__ __launch_bounds__(1024) void k_axpy(HeapView h, AxpyK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        if ((bm >> s) & 1) {
+    for_each_object_packed(h, p.cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
+        if (live) {
             float &x = farr<float>(h, bid, p.o_x)[s];
             x = p.a * x + p.b;
         }
@@ -540,9 +539,10 @@ smmo_status launch_axpy(smmo_heap *h, uint32_t cls, const void *args, hipStream_
     memcpy(&a, args, sizeof a);
     AxpyK k{cls, 0, a.a, a.b};
     BIND(cls, "x", SMMO_F32, 1, &k.o_x, nullptr);
-    smmo_status s = ensure_enumerated(h, cls, false, st);
+    const LaunchShape ls = method_shape(h, cls);
+    smmo_status s = ensure_enumerated(h, cls, false, st, packing_wanted(h, cls, ls));
     if (s) return s;
-    hipLaunchKernelGGL(k_axpy, method_shape(h, cls).grid, method_shape(h, cls).block, 0, st, h->v, k);
+    hipLaunchKernelGGL(k_axpy, ls.grid, ls.block, 0, st, h->v, k);
     return launched("k_axpy");
 }
 
@@ -554,16 +554,15 @@ struct DestroyIfK {
 __global__ __launch_bounds__(1024) void k_destroy_if(HeapView h, DestroyIfK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
+    for_each_object_packed(h, p.cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         bool d = false;
-        if ((bm >> s) & 1) {
+        if (live) {
             const int32_t key = farr<int32_t>(h, bid, p.o_key)[s];
             int32_t m = key % p.mod;
             if (m < 0) m += p.mod;
             d = m == p.rem;
         }
-        wave_release_own_block(h, p.cls, bid, __ballot(d));
+        wave_release_packed(h, p.cls, bid, s, d, pair);
     });
 }
 
@@ -574,9 +573,10 @@ smmo_status launch_destroy_if(smmo_heap *h, uint32_t cls, const void *args, hipS
     if (a.mod <= 0) return fail(SMMO_EINVAL, "destroy_if: mod must be > 0");
     DestroyIfK k{cls, 0, a.mod, a.rem};
     BIND(cls, "key", SMMO_I32, 1, &k.o_key, nullptr);
-    smmo_status s = ensure_enumerated(h, cls, false, st);
+    const LaunchShape ls = method_shape(h, cls);
+    smmo_status s = ensure_enumerated(h, cls, false, st, packing_wanted(h, cls, ls));
     if (s) return s;
-    hipLaunchKernelGGL(k_destroy_if, method_shape(h, cls).grid, method_shape(h, cls).block, 0, st, h->v, k);
+    hipLaunchKernelGGL(k_destroy_if, ls.grid, ls.block, 0, st, h->v, k);
     return launched("k_destroy_if");
 }
 

@@ -68,6 +68,21 @@ __device__ __forceinline__ void count_events(const HeapView &h, uint32_t ev, uin
 
 __device__ __forceinline__ void count_event(const HeapView &h, uint32_t ev) { count_events(h, ev, 1); }
 
+// the block list of class cls (wave-uniform)
+__device__ __forceinline__ BlockList block_list(const HeapView &h, uint32_t cls)
+{
+    BlockList L;
+    L.R = h.R + (uint64_t)cls * h.M;
+    L.r = __builtin_amdgcn_readfirstlane(__hip_atomic_load(h.ctrl + CTRL_RFINAL + cls, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT));
+    const uint32_t ns = __builtin_amdgcn_readfirstlane(__hip_atomic_load(h.ctrl + CTRL_RSFINAL + cls,
+                                                                         __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_AGENT));
+    L.nd = L.r - ns;
+    L.M = h.M;
+    return L;
+}
+
 __device__ __forceinline__ bool heap_failed(const HeapView &h)
 {
     return ald32(h.ctrl + CTRL_ERR) != 0;

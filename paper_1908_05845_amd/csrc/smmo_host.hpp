@@ -33,7 +33,7 @@ struct smmo_schema {
     bool frozen = false;
 };
 
-enum RState : int { R_DIRTY = 0, R_VALID = 1 };
+enum RState : int { R_DIRTY = 0, R_VALID = 1, R_SPLIT = 2 };   // R_SPLIT: valid, with the packing plan
 
 // A method launch resolves its fields by name; the schema is frozen once a
 // heap exists, so the resolved kernel parameters are cached per
@@ -83,8 +83,12 @@ smmo_status bind_field(const smmo_schema *s, uint32_t cls, const char *name, int
                        uint32_t count, uint32_t *offset, uint32_t *stride);
 
 // block list of a class for the next launch: rebuilds it if it is stale;
-// snapshot = copy allocation bitmaps to iteration bitmaps on the way
-smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st);
+// snapshot = copy allocation bitmaps to iteration bitmaps on the way; split =
+// the list must carry the packing plan of packed do-alls: dense blocks at the
+// front, sparse ones (at most 32 live objects) at the back (without it every
+// block is listed as dense).
+smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st, bool split = false);
+
 
 // launch shape of a do-all over class cls: the (method, class) setting of
 // smmo_set_launch if any, else 256-thread work-groups and 64 wavefronts per
@@ -98,6 +102,11 @@ struct LaunchShape {
     uint32_t group;
 };
 LaunchShape method_shape(const smmo_heap *h, uint32_t cls, uint32_t def_group = 0);
+
+// whether a packed do-all of class cls launched with shape ls should get a
+// list with the packing plan (sparse_packing 2, or 1 with a class that may
+// have more blocks than the launch has wavefronts)
+bool packing_wanted(const smmo_heap *h, uint32_t cls, const LaunchShape &ls);
 
 // bookkeeping after a launch that creates objects of class cls
 void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects);

@@ -65,6 +65,8 @@ enum : uint32_t {
     CTRL_RFINAL = 48,     // [class] length of R after the last enumeration
     CTRL_DCOUNT = 64,     // defragmentation: number of candidate blocks
     CTRL_DMOVED = 66,     // u64: defragmentation: objects moved
+    CTRL_RSCOUNT = 96,    // [class] enumeration: running count of sparse blocks
+    CTRL_RSFINAL = 112,   // [class] sparse blocks (the back of R) after the last enumeration
     CTRL_STATS = 128,     // u64 statistics / invariant results (host reads)
 };
 
@@ -112,12 +114,25 @@ struct HeapView {
     uint32_t rotation;
     uint32_t coalescing;
     uint32_t spin_limit;
+    uint32_t sparse_packing;      // 0 never, 1 when the list outgrows the grid, 2 always
 
     __host__ __device__ uint64_t *bm_word(uint32_t bmid, uint32_t lvl, uint32_t c) const
     {
         return bm + (uint64_t)bmid * bm_words + lvl_off[lvl] + c;
     }
     __host__ __device__ char *block(uint32_t bid) const { return blocks + (uint64_t)bid * block_bytes; }
+};
+
+// The block list R of a class as the enumeration leaves it: its r entries are
+// the dense blocks (more than 32 live objects when enumerated) from the front
+// of the class's M-entry region, then the sparse blocks from the back.  A list
+// stays in use until something may allocate objects of its class, so a block
+// listed as sparse never holds more than 32 live objects while it is used
+// (deletions only move blocks from dense towards sparse).
+struct BlockList {
+    const uint32_t *R;
+    uint32_t r, nd, M;
+    __host__ __device__ uint32_t at(uint32_t i) const { return i < nd ? R[i] : R[M - 1 - (i - nd)]; }
 };
 
 } // namespace smmo

@@ -113,9 +113,8 @@ __device__ __forceinline__ void wt_request(const HeapView &h, const WatorK &p, u
 __global__ __launch_bounds__(1024) void k_wt_fish_prepare(HeapView h, WatorK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.fish_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        if (!((bm >> s) & 1)) return;
+    for_each_object_packed(h, p.fish_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
+        if (!live) return;
         int32_t &timer = farr<int32_t>(h, bid, p.f_timer)[s];
         timer += 1;
         const uint32_t pos = farr<uint32_t>(h, bid, p.f_pos)[s];
@@ -128,9 +127,8 @@ __global__ __launch_bounds__(1024) void k_wt_fish_prepare(HeapView h, WatorK p)
 __global__ __launch_bounds__(1024) void k_wt_shark_prepare(HeapView h, WatorK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.shark_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        if (!((bm >> s) & 1)) return;
+    for_each_object_packed(h, p.shark_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
+        if (!live) return;
         farr<int32_t>(h, bid, p.s_timer)[s] += 1;
         farr<int32_t>(h, bid, p.s_energy)[s] -= 1;
         const uint32_t pos = farr<uint32_t>(h, bid, p.s_pos)[s];
@@ -175,9 +173,7 @@ __global__ __launch_bounds__(1024) void k_wt_cell_decide(HeapView h, WatorK p)
 __global__ __launch_bounds__(1024) void k_wt_fish_update(HeapView h, WatorK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.fish_cls, true, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        const bool live = (bm >> s) & 1;
+    for_each_object_packed(h, p.fish_cls, true, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         uint32_t pos = 0, np = 0;
         int32_t timer = 0;
         if (live) {
@@ -187,7 +183,7 @@ __global__ __launch_bounds__(1024) void k_wt_fish_update(HeapView h, WatorK p)
         }
         const bool moved = live && np != pos && wt_valid(h, np) && wt_valid(h, pos);
         if (moved) {
-            fref<uint32_t>(h, np, p.c_agent) = self_handle(bid);
+            fref<uint32_t>(h, np, p.c_agent) = (bid << 6) | s;
             farr<uint32_t>(h, bid, p.f_pos)[s] = np;
         }
         const bool spawn = moved && timer > p.fish_spawn;
@@ -206,9 +202,7 @@ __global__ __launch_bounds__(1024) void k_wt_fish_update(HeapView h, WatorK p)
 __global__ __launch_bounds__(1024) void k_wt_shark_update(HeapView h, WatorK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.shark_cls, true, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        const bool live = (bm >> s) & 1;
+    for_each_object_packed(h, p.shark_cls, true, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         uint32_t pos = 0, np = 0;
         int32_t timer = 0, energy = 0;
         if (live) {
@@ -228,7 +222,7 @@ __global__ __launch_bounds__(1024) void k_wt_shark_update(HeapView h, WatorK p)
                 prey = kNull;
             }
             if (prey != kNull) farr<int32_t>(h, bid, p.s_energy)[s] = energy + p.boost;
-            fref<uint32_t>(h, np, p.c_agent) = self_handle(bid) | kShark;
+            fref<uint32_t>(h, np, p.c_agent) = (bid << 6) | s | kShark;
             farr<uint32_t>(h, bid, p.s_pos)[s] = np;
         }
         wave_deallocate(h, p.fish_cls, prey, prey != kNull);
@@ -242,7 +236,7 @@ __global__ __launch_bounds__(1024) void k_wt_shark_update(HeapView h, WatorK p)
             farr<int32_t>(h, bid, p.s_timer)[s] = 0;
         }
         if (moved) fref<uint32_t>(h, pos, p.c_agent) = spawn && child != kNull ? child | kShark : kNull;
-        wave_release_own_block(h, p.shark_cls, bid, __ballot(die));
+        wave_release_packed(h, p.shark_cls, bid, s, die, pair);
     });
 }
 
@@ -347,8 +341,10 @@ smmo_status launch_wator(smmo_heap *h, uint32_t cls, const void *args, hipStream
                        (int64_t)a.width * a.height > 0x7FFFFFFF))
         return fail(SMMO_EINVAL, "wator.cell_link: bad grid");
     const bool snapshot = Which == 4 || Which == 5;
-    if ((s = ensure_enumerated(h, cls, snapshot, st))) return s;
+    // the agent classes (fragmented by births and deaths) run packed do-alls
+    const bool packed = Which == 1 || Which == 2 || Which == 4 || Which == 5;
     const LaunchShape ls = method_shape(h, cls);
+    if ((s = ensure_enumerated(h, cls, snapshot, st, packed && packing_wanted(h, cls, ls)))) return s;
     switch (Which) {
     case 0: hipLaunchKernelGGL(k_wt_cell_prepare, ls.grid, ls.block, 0, st, h->v, k); break;
     case 1: hipLaunchKernelGGL(k_wt_fish_prepare, ls.grid, ls.block, 0, st, h->v, k); break;

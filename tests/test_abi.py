@@ -45,7 +45,7 @@ def test_config_defaults(lib):
     cfg = smmo.smmo_config_default()
     assert cfg.lookup_retries == 5 and cfg.rotation == 1 and cfg.coalescing == 1
     assert cfg.bulk_ordered == 1 and cfg.spin_limit >= 1024
-    assert cfg.grid_waves == 0 and cfg.block_group == 0
+    assert cfg.grid_waves == 0 and cfg.block_group == 0 and cfg.sparse_packing == 0
 
 
 def test_schema_and_layout(lib):

@@ -60,7 +60,8 @@ def test_empty_and_full_boards(dev):
 
 
 @pytest.mark.parametrize("variant", [dict(rotation=0), dict(coalescing=0), dict(lookup_retries=1),
-                                     dict(bulk_ordered=0)])
+                                     dict(bulk_ordered=0), dict(sparse_packing=2),
+                                     dict(sparse_packing=1, grid_waves=8)])
 def test_allocator_variants_same_result(dev, variant):
     print("gol variant", variant, flush=True)
     c = smmo.smmo_config_default()

@@ -305,6 +305,8 @@ def test_launch_shape_validation(dev):
 
     with pytest.raises(smmo.SmmoError) as e:
         smmo.Heap(ALL, blocks=16, cfg=cfg(block_group=3))
+    with pytest.raises(smmo.SmmoError):
+        smmo.Heap(ALL, blocks=16, cfg=cfg(sparse_packing=3))
     assert e.value.status == smmo.SMMO_EINVAL
     heap = smmo.Heap(ALL, blocks=64)
     mid = smmo.smmo_method_id("test.axpy")
@@ -333,3 +335,42 @@ def test_coalescing_probe_touches_every_element_once(dev, C):
         smmo.smmo_coalescing_probe(data, 3)
     with pytest.raises(smmo.SmmoError):
         smmo.smmo_coalescing_probe(data[:100], 1)
+
+
+@pytest.mark.parametrize("packing,waves", [(2, 0), (1, 4), (2, 3), (0, 0), (1, 0)])
+@pytest.mark.parametrize("keep_frac,seed", [(0.2, 1), (0.5, 2), (0.03, 3), (0.51, 4)])
+def test_packed_do_all_on_sparse_blocks(dev, keep_frac, seed, packing, waves):
+    """test.axpy and test.destroy_if run packed (a wavefront takes one block
+    with more than 32 live objects, or two with at most 32): after random
+    deletions every live object is visited exactly once, and self-deletion
+    from two blocks per wavefront keeps the live set and the block states
+    right.  Packing always on (also with a 3-wavefront grid), on in mode 1
+    once the list (38 blocks) is longer than the grid (4 wavefronts, so that
+    wavefronts loop), off (the default), and off in mode 1 with a grid as
+    long as the list."""
+    import torch
+
+    print("packed keep %.2f packing %d waves %d" % (keep_frac, packing, waves), flush=True)
+    rng = np.random.default_rng(seed)
+    n = 64 * 37 + 11
+    heap = smmo.Heap(ALL, blocks=128, cfg=cfg(sparse_packing=packing, grid_waves=waves))
+    hd = heap.new("A", n, x=torch.arange(n, dtype=torch.float32, device=dev),
+                  key=torch.arange(n, dtype=torch.int32, device=dev))
+    # blocks 0 and 1 keep exactly 32 and 33 objects; the rest a random share
+    keep = rng.random(n) < keep_frac
+    keep[:64] = np.arange(64) < 32
+    keep[64:128] = np.arange(64) < 33
+    dead = np.flatnonzero(~keep)
+    heap.destroy("A", hd[torch.from_numpy(dead).to(dev)])
+    model = np.flatnonzero(keep)
+    heap.do("A", "test.axpy", smmo.smmo_axpy_args(2.0, 1.0))
+    g = heap.gather("A", ["x", "key"])
+    o = np.argsort(g["key"].cpu().numpy())
+    assert np.array_equal(g["key"].cpu().numpy()[o], model)
+    assert np.array_equal(g["x"].cpu().numpy()[o], 2.0 * model.astype(np.float32) + 1.0)
+    clean(heap)
+    heap.do("A", "test.destroy_if", smmo.smmo_destroy_if_args(3, 1))
+    heap.sync()
+    model = model[model % 3 != 1]
+    assert np.array_equal(keys_of(heap), model)
+    clean(heap)

@@ -62,11 +62,15 @@ def test_every_iteration(dev, W, H, prm):
     assert events > 0
 
 
-@pytest.mark.parametrize("config", ["no_rotation", "no_coalescing", "retries_1"])
+@pytest.mark.parametrize("config", ["no_rotation", "no_coalescing", "retries_1", "packed", "packed_short_grid"])
 def test_allocator_configurations(dev, config):
+    """Allocator variants, and packed do-alls for the agent classes (always,
+    and in mode 1 with a grid shorter than the agent lists): the same
+    world as the oracle's."""
     print("wator 40x40 %s" % config, flush=True)
     kw = {"no_rotation": {"rotation": 0}, "no_coalescing": {"coalescing": 0},
-          "retries_1": {"lookup_retries": 1}}[config]
+          "retries_1": {"lookup_retries": 1}, "packed": {"sparse_packing": 2},
+          "packed_short_grid": {"sparse_packing": 1, "grid_waves": 6}}[config]
     cfg = smmo.smmo_config_default()
     for k, v in kw.items():
         setattr(cfg, k, v)
