@@ -70,10 +70,12 @@ def events(torch, n):
     return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
 
 
-# the files the spring kernels are compiled from (and the build flags)
-SPRING_KERNEL_SOURCES = ("paper_1908_05845_amd/csrc/methods.hip", "paper_1908_05845_amd/csrc/method_common.hpp",
+# the files the spring kernels are compiled from (and the build flags); for
+# the method header only its spring-mass section counts
+SPRING_KERNEL_SOURCES = ("paper_1908_05845_amd/csrc/spring.hip", "paper_1908_05845_amd/csrc/method_common.hpp",
                          "paper_1908_05845_amd/csrc/smmo_device.hpp", "paper_1908_05845_amd/csrc/smmo_layout.hpp",
                          "include/smmo_methods.h", "paper_1908_05845_amd/build.py")
+SPRING_HEADER_SECTION = ("/* ---- spring-mass mesh", "} smmo_spring_args;")
 
 
 def kernel_source_hash():
@@ -87,6 +89,9 @@ def kernel_source_hash():
     for fn in SPRING_KERNEL_SOURCES:
         with open(os.path.join(HERE, fn)) as f:
             text = f.read()
+        if fn.endswith("smmo_methods.h"):
+            a = text.index(SPRING_HEADER_SECTION[0])
+            text = text[a:text.index(SPRING_HEADER_SECTION[1], a) + len(SPRING_HEADER_SECTION[1])]
         # comments and blank lines do not change the compiled kernels
         if fn.endswith(".py"):
             text = re.sub(r"#[^\n]*", "", text)
@@ -151,7 +156,8 @@ def bench_spring(args, torch):
         step()
     counted(warmup)
     heap.sync()
-    frozen0 = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit)
+    frozen0 = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit,
+                                    sim.args.flags)
     tuned = None
     if not args.no_autotune:
         from paper_1908_05845_amd import autotune
@@ -246,7 +252,8 @@ def bench_spring(args, torch):
     # Repeated force passes are idempotent and the node passes run with dt = 0,
     # so the simulation state is unchanged.
     ks = args.kernel_steps
-    frozen = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit)
+    frozen = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit,
+                                    sim.args.flags)
     fp = smmo.C.byref(frozen)
 
     window = {}
@@ -1000,7 +1007,8 @@ def counter_pass(args, torch):
         if (i + 1) % 1000 == 0:
             torch.cuda.synchronize()
             print("counter pass: %d of %d steps" % (i + 1, n), file=sys.stderr, flush=True)
-    frozen = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit)
+    frozen = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit,
+                                    sim.args.flags)
     ks = args.kernel_steps
     for _ in range(ks):
         lib.smmo_parallel_do(hp, cs, sim.m_force, smmo.C.byref(frozen), asz, stream)

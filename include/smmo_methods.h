@@ -56,17 +56,22 @@ typedef struct {
  * "spring.force"       on Spring: d = x_b - x_a, l = |d|; if
  *        (l - L0) / L0 > strain_limit the spring empties its two adjacency
  *        slots and deletes itself; otherwise (fx, fy) = k (l - L0) d / l,
- *        the force on a (b receives the negative).
+ *        the force on a (b receives the negative).  With
+ *        SMMO_SPRING_TENSION_ONLY in flags a spring only pulls (the thesis's
+ *        springs, Ch.7 "structure": Hooke's law while stretched): (fx, fy) = 0
+ *        while l <= L0.
  * "spring.node_update" on Node: F = sum over occupied slots, in slot order,
  *        of +-(fx, fy); v += F / m * dt; x += v * dt.
  * "spring.link"        on Spring: writes the spring's handle into a.adj[slot_a]
  *        and (handle | 1 << 31) into b.adj[slot_b]; builds the topology after
  *        parallel_new of the nodes (adj empty) and the springs.               */
+#define SMMO_SPRING_TENSION_ONLY 1u
 typedef struct {
     uint32_t node_class;
     uint32_t spring_class;
     float dt;
     float strain_limit;
+    uint32_t flags;              /* 0 or SMMO_SPRING_TENSION_ONLY; other bits: SMMO_EINVAL */
 } smmo_spring_args;
 
 /* ---- reverse mode through the spring-mesh step (breaking off) ------------

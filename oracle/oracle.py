@@ -56,7 +56,7 @@ def _load():
             lib.orc_nbody_force_at.argtypes = [LL, P, P, P, D, D, P, LL, P, P, P, P]
             lib.orc_spring_steps.restype = LL
             lib.orc_spring_steps.argtypes = [LL, P, P, P, P, P, P, P, LL, P, P, P, P, P, P,
-                                             P, P, P, D, C.c_float, C.c_int, P, P, P, P, P]
+                                             P, P, P, D, C.c_float, C.c_int, P, P, P, P, P, C.c_int]
             lib.orc_spring_adjoint.restype = C.c_int
             lib.orc_spring_adjoint.argtypes = [LL, P, P, P, P, P, P, P, LL, P, P, P, P, P, P, P, P,
                                                D, C.c_int, C.c_int, P, P, P, P, P, P, P, P]
@@ -206,9 +206,10 @@ def nbody_force_at(x, y, m, G, eps, idx):
 
 
 def spring_steps(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1,
-                 alive=None, fx=None, fy=None):
+                 alive=None, fx=None, fy=None, tension_only: bool = False):
     """Thesis Ch.7 "structure" compute steps: `steps` x {Spring::compute_force,
-    Node::update} in float64 with the float32 break decision.
+    Node::update} in float64 with the float32 break decision; tension_only =
+    springs that only pull (no force while l <= L0, decided in float32).
 
     `mesh` holds x, y, vx, vy, m, adj, adj_is_b, a, b, k, L0, slot_a, slot_b
     (ids local to the arrays).  Returns a new dict with the updated state, the
@@ -235,7 +236,7 @@ def spring_steps(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1,
     nb = lib.orc_spring_steps(N, _p(x), _p(y), _p(vx), _p(vy), _p(m), _p(adj), _p(adjb),
                               S, _p(a), _p(b), _p(kk), _p(L0), _p(sa), _p(sb), _p(al),
                               _p(fxo), _p(fyo), float(dt), float(thresh), int(steps),
-                              _p(sf), _p(svx), _p(svy), _p(sx), _p(sy))
+                              _p(sf), _p(svx), _p(svy), _p(sx), _p(sy), int(bool(tension_only)))
     if nb < 0:
         raise RuntimeError("oracle spring error %d" % nb)
     out = dict(mesh)

@@ -395,6 +395,9 @@ int orc_nbody_force_at(long long n, const double *x, const double *y, const doub
 /*   dx = xb - xa; dy = yb - ya; l2 = fma(dx, dx, dy*dy); l = sqrt(l2);       */
 /*   strain = (l - L0) / L0;  break iff strain > threshold                   */
 /* with every operation rounded to float32.  Forces and the update are float64. */
+/* Tension-only springs (the thesis's springs act only while stretched) give  */
+/* no force while l <= L0; that decision is integer-valued too and uses the   */
+/* same float32 l and float32 L0.                                            */
 /* Nodes keep up to 8 spring slots; a break empties the two slots (the       */
 /* spring remembers its slot index in each node); Node::update sums the      */
 /* occupied slots in slot order.                                             */
@@ -418,19 +421,26 @@ typedef struct {
     ostore node, spring;
     size_t *snap;
     float thresh;
+    int tension_only;
     double dt;
     long long nbroken;
     int err;
 } sp_world;
 
-/* the float32 break decision (see above) */
-static int sp_breaks(double xa, double ya, double xb, double yb, double L0, float thresh)
+/* the spring length in float32, in the operation order given above */
+static float sp_len32(double xa, double ya, double xb, double yb)
 {
     float dx = (float)xb - (float)xa;
     float dy = (float)yb - (float)ya;
     float dy2 = dy * dy;
     float l2 = fmaf(dx, dx, dy2);
-    float l = sqrtf(l2);
+    return sqrtf(l2);
+}
+
+/* the float32 break decision (see above) */
+static int sp_breaks(double xa, double ya, double xb, double yb, double L0, float thresh)
+{
+    float l = sp_len32(xa, ya, xb, yb);
     float L0f = (float)L0;
     float strain = (l - L0f) / L0f;
     return strain > thresh;
@@ -448,6 +458,10 @@ static void sp_spring_force(sp_world *w, size_t self)
         s->fx = s->fy = s->sf = 0;
         w->nbroken++;
         if (os_destroy(&w->spring, self)) w->err = 5;   /* last statement: delete this */
+        return;
+    }
+    if (w->tension_only && !(sp_len32(a->x, a->y, b->x, b->y) > (float)s->L0)) {
+        s->fx = s->fy = s->sf = 0;     /* slack: a tension-only spring does not push */
         return;
     }
     double dx = b->x - a->x, dy = b->y - a->y;
@@ -487,6 +501,7 @@ static void sp_node_update(sp_world *w, sp_node *n)
  * Optional outputs (NULL to skip), all of the last step:
  *   sf (S)               scale of each spring force
  *   svx, svy, sx, sy (N) scales of the node velocity and position updates
+ * tension_only: springs give no force while l <= L0 (see above).
  * Returns the number of springs broken, or a negative error code.
  */
 long long orc_spring_steps(long long N, double *x, double *y, double *vx, double *vy,
@@ -496,12 +511,14 @@ long long orc_spring_steps(long long N, double *x, double *y, double *vx, double
                            const int32_t *slot_a, const int32_t *slot_b,
                            uint8_t *alive, double *fx, double *fy,
                            double dt, float thresh, int steps,
-                           double *sf, double *svx, double *svy, double *sx, double *sy)
+                           double *sf, double *svx, double *svy, double *sx, double *sy,
+                           int tension_only)
 {
     sp_world w;
     memset(&w, 0, sizeof w);
     w.dt = dt;
     w.thresh = thresh;
+    w.tension_only = tension_only != 0;
     if (N < 0 || S < 0) return -1;
     if (os_init(&w.node, sizeof(sp_node), (size_t)(N ? N : 1)) ||
         os_init(&w.spring, sizeof(sp_spring), (size_t)(S ? S : 1))) return -1;

@@ -230,24 +230,4 @@ smmo_status cached_bind(smmo_heap *h, const void *tag, uint32_t cls, const A &a,
         if (_s) return _s;                                                                 \
     } while (0)
 
-
-// launchers defined in adjoint.hip
-smmo_status launch_adj_record(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_adj_save(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_adj_load(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_adj_seed(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_adj_zero(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_adj_node(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_adj_spring(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-
-// launchers defined in wator.hip
-smmo_status launch_wator_cell_prepare(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_wator_fish_prepare(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_wator_shark_prepare(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_wator_cell_decide(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_wator_fish_update(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_wator_shark_update(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_wator_cell_link(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-smmo_status launch_wator_link(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
-
 } // namespace smmo

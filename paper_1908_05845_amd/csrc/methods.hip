@@ -1,5 +1,7 @@
-// Methods that smmo_parallel_do() can run (argument structs and field
-// contracts in include/smmo_methods.h).
+// Methods that smmo_parallel_do() can run: Game of Life, n-body, the test
+// methods and the allocator microbenchmark (argument structs and field
+// contracts in include/smmo_methods.h; the spring-mass methods are in
+// spring.hip, wa-tor in wator.hip, the adjoint in adjoint.hip).
 //
 // Every method kernel walks the class's block list R (built by the
 // enumeration pre-pass) with one wavefront per block and one lane per slot,
@@ -255,12 +257,12 @@ smmo_status bind_nbody(smmo_heap *h, uint32_t cls, const smmo_nbody_args &a, Nbo
     return SMMO_OK;
 }
 
-smmo_status launch_nbody_force(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+smmo_status nbody_force_launch(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
 {
     smmo_nbody_args a;
     memcpy(&a, args, sizeof a);
     NbodyK k;
-    smmo_status s = cached_bind(h, (const void *)&launch_nbody_force, cls, a, k,
+    smmo_status s = cached_bind(h, (const void *)&nbody_force_launch, cls, a, k,
                                 [&] { return bind_nbody(h, cls, a, k); });
     if (s) return s;
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
@@ -272,247 +274,17 @@ smmo_status launch_nbody_force(smmo_heap *h, uint32_t cls, const void *args, hip
     return launched("k_nbody_force");
 }
 
-smmo_status launch_nbody_update(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+smmo_status nbody_update_launch(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
 {
     smmo_nbody_args a;
     memcpy(&a, args, sizeof a);
     NbodyK k;
-    smmo_status s = cached_bind(h, (const void *)&launch_nbody_update, cls, a, k,
+    smmo_status s = cached_bind(h, (const void *)&nbody_update_launch, cls, a, k,
                                 [&] { return bind_nbody(h, cls, a, k); });
     if (s) return s;
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     hipLaunchKernelGGL(k_nbody_update, method_shape(h, cls).grid, method_shape(h, cls).block, 0, st, h->v, k);
     return launched("k_nbody_update");
-}
-
-// ======================================================== spring-mass =====
-struct SpringK {
-    uint32_t node_cls, spring_cls;
-    uint32_t s_a, s_b, s_k, s_L0, s_fx, s_fy, s_sa, s_sb;      // Spring fields
-    uint32_t n_x, n_y, n_vx, n_vy, n_m, n_adj, n_adj_stride;   // Node fields
-    float dt, limit;
-};
-
-// The break decision is integer-valued, so it is evaluated in float32 with a
-// fixed operation order (no contraction): dx, dy; l2 = fma(dx, dx, dy*dy);
-// l = sqrt(l2) (correctly rounded); strain = (l - L0) / L0 (correctly rounded).
-__device__ __forceinline__ bool spring_breaks(float dx, float dy, float L0, float limit, float &l)
-{
-#pragma clang fp contract(off)
-    const float dy2 = dy * dy;
-    const float l2 = __builtin_fmaf(dx, dx, dy2);
-    l = __builtin_sqrtf(l2);
-    const float strain = (l - L0) / L0;
-    return strain > limit;
-}
-
-// Spring::compute_force (Ch.7 "structure"): Hooke's law on the length change;
-// a spring strained past the limit empties its two adjacency slots and
-// deletes itself (the thesis's remove_spring followed by destroy).  A
-// wavefront works on U blocks at once: the spring fields of all U blocks are
-// loaded, then all position gathers issued, then the forces computed.
-template <int U>
-__global__ __launch_bounds__(1024) void k_spring_force(HeapView h, SpringK p)
-{
-    if (heap_failed(h)) return;
-    const uint32_t s = lane_id();
-    for_each_block_group<U>(h, p.spring_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
-        uint32_t a[U], b[U];
-        float k[U], L0[U], xa[U], ya[U], xb[U], yb[U];
-        bool live[U];
-        // the blocks' own fields for all 64 slots (one contiguous run each)
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            live[j] = (bm[j] >> s) & 1;
-            a[j] = farr<uint32_t>(h, bid[j], p.s_a)[s];
-            b[j] = farr<uint32_t>(h, bid[j], p.s_b)[s];
-            k[j] = farr<float>(h, bid[j], p.s_k)[s];
-            L0[j] = farr<float>(h, bid[j], p.s_L0)[s];
-        }
-        // gathers through the node handles, live slots only
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            xa[j] = ya[j] = xb[j] = yb[j] = 0.f;
-            if (live[j]) {
-                xa[j] = fref<float>(h, a[j], p.n_x);
-                ya[j] = fref<float>(h, a[j], p.n_y);
-                xb[j] = fref<float>(h, b[j], p.n_x);
-                yb[j] = fref<float>(h, b[j], p.n_y);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            if (!own[j]) continue;
-            const float dx = xb[j] - xa[j], dy = yb[j] - ya[j];
-            float l;
-            const bool brk = live[j] && spring_breaks(dx, dy, L0[j], p.limit, l);
-            float fx = 0.f, fy = 0.f;
-            if (live[j] && !brk) {
-                const float c = k[j] * (l - L0[j]) / l;
-                fx = c * dx;
-                fy = c * dy;
-            }
-            // full-width stores: dead and broken slots get 0, never read
-            farr<float>(h, bid[j], p.s_fx)[s] = fx;
-            farr<float>(h, bid[j], p.s_fy)[s] = fy;
-            if (brk) {
-                const uint32_t qa = farr<uint8_t>(h, bid[j], p.s_sa)[s];
-                const uint32_t qb = farr<uint8_t>(h, bid[j], p.s_sb)[s];
-                fref<uint32_t>(h, a[j], p.n_adj + qa * p.n_adj_stride) = kNull;
-                fref<uint32_t>(h, b[j], p.n_adj + qb * p.n_adj_stride) = kNull;
-            }
-            wave_release_own_block(h, p.spring_cls, bid[j], __ballot(brk));
-        }
-    });
-}
-
-// Node::update: sum the attached springs' forces in slot order (+f if this
-// node is endpoint a, -f if b), then v += F/m dt, x += v dt.  U blocks at
-// once, as in the force kernel.
-template <int U>
-__global__ __launch_bounds__(1024) void k_spring_node(HeapView h, SpringK p)
-{
-    if (heap_failed(h)) return;
-    const uint32_t s = lane_id();
-    for_each_block_group<U>(h, p.node_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
-        uint32_t e[U][8];
-        float m[U], x[U], y[U], vx[U], vy[U], Fx[U], Fy[U];
-        bool live[U];
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            live[j] = (bm[j] >> s) & 1;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) e[j][q] = farr<uint32_t>(h, bid[j], p.n_adj + q * p.n_adj_stride)[s];
-            m[j] = farr<float>(h, bid[j], p.n_m)[s];
-            x[j] = farr<float>(h, bid[j], p.n_x)[s];
-            y[j] = farr<float>(h, bid[j], p.n_y)[s];
-            vx[j] = farr<float>(h, bid[j], p.n_vx)[s];
-            vy[j] = farr<float>(h, bid[j], p.n_vy)[s];
-        }
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            float gx[8], gy[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                gx[q] = 0.f;
-                gy[q] = 0.f;
-                if (live[j] && e[j][q] != kNull) {
-                    const uint32_t sh = e[j][q] & 0x7FFFFFFFu;
-                    gx[q] = fref<float>(h, sh, p.s_fx);
-                    gy[q] = fref<float>(h, sh, p.s_fy);
-                }
-            }
-            Fx[j] = 0.f;
-            Fy[j] = 0.f;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (e[j][q] == kNull) continue;
-                if (e[j][q] >> 31) {
-                    Fx[j] -= gx[q];
-                    Fy[j] -= gy[q];
-                } else {
-                    Fx[j] += gx[q];
-                    Fy[j] += gy[q];
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            if (!live[j]) continue;
-            vx[j] += Fx[j] / m[j] * p.dt;
-            vy[j] += Fy[j] / m[j] * p.dt;
-            x[j] += vx[j] * p.dt;
-            y[j] += vy[j] * p.dt;
-            farr<float>(h, bid[j], p.n_vx)[s] = vx[j];
-            farr<float>(h, bid[j], p.n_vy)[s] = vy[j];
-            farr<float>(h, bid[j], p.n_x)[s] = x[j];
-            farr<float>(h, bid[j], p.n_y)[s] = y[j];
-        }
-    });
-}
-
-// Spring::link: registers the spring in its two nodes' adjacency slots
-// (slot_a of a, slot_b of b, the latter flagged as endpoint b).  Builds a
-// mesh's topology on the device after parallel_new of nodes and springs;
-// every (node, slot) pair belongs to one spring, so the writes never collide.
-__global__ __launch_bounds__(1024) void k_spring_link(HeapView h, SpringK p)
-{
-    if (heap_failed(h)) return;
-    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        if (!((bm >> s) & 1)) return;
-        const uint32_t self = (bid << 6) | s;
-        const uint32_t a = farr<uint32_t>(h, bid, p.s_a)[s];
-        const uint32_t b = farr<uint32_t>(h, bid, p.s_b)[s];
-        const uint32_t qa = farr<uint8_t>(h, bid, p.s_sa)[s];
-        const uint32_t qb = farr<uint8_t>(h, bid, p.s_sb)[s];
-        if (qa >= 8 || qb >= 8) {
-            raise_error(h, ERR_BADHANDLE);
-            return;
-        }
-        fref<uint32_t>(h, a, p.n_adj + qa * p.n_adj_stride) = self;
-        fref<uint32_t>(h, b, p.n_adj + qb * p.n_adj_stride) = self | 0x80000000u;
-    });
-}
-
-smmo_status bind_spring(smmo_heap *h, const smmo_spring_args &a, SpringK &k)
-{
-    const uint32_t nc = h->schema->nclasses;
-    if (a.node_class >= nc || a.spring_class >= nc || a.node_class == a.spring_class)
-        return fail(SMMO_EINVAL, "spring: bad class ids");
-    if (!(a.dt == a.dt) || !(a.strain_limit == a.strain_limit)) return fail(SMMO_EINVAL, "spring: NaN parameter");
-    k.node_cls = a.node_class;
-    k.spring_cls = a.spring_class;
-    BIND(a.spring_class, "a", SMMO_HANDLE, 1, &k.s_a, nullptr);
-    BIND(a.spring_class, "b", SMMO_HANDLE, 1, &k.s_b, nullptr);
-    BIND(a.spring_class, "k", SMMO_F32, 1, &k.s_k, nullptr);
-    BIND(a.spring_class, "L0", SMMO_F32, 1, &k.s_L0, nullptr);
-    BIND(a.spring_class, "fx", SMMO_F32, 1, &k.s_fx, nullptr);
-    BIND(a.spring_class, "fy", SMMO_F32, 1, &k.s_fy, nullptr);
-    BIND(a.spring_class, "slot_a", SMMO_U8, 1, &k.s_sa, nullptr);
-    BIND(a.spring_class, "slot_b", SMMO_U8, 1, &k.s_sb, nullptr);
-    BIND(a.node_class, "x", SMMO_F32, 1, &k.n_x, nullptr);
-    BIND(a.node_class, "y", SMMO_F32, 1, &k.n_y, nullptr);
-    BIND(a.node_class, "vx", SMMO_F32, 1, &k.n_vx, nullptr);
-    BIND(a.node_class, "vy", SMMO_F32, 1, &k.n_vy, nullptr);
-    BIND(a.node_class, "m", SMMO_F32, 1, &k.n_m, nullptr);
-    BIND(a.node_class, "adj", SMMO_HANDLE, 8, &k.n_adj, &k.n_adj_stride);
-    k.dt = a.dt;
-    k.limit = a.strain_limit;
-    return SMMO_OK;
-}
-
-// blocks per wavefront iteration of the spring do-alls unless set otherwise
-constexpr uint32_t kSpringGroup = 1;
-
-template <int Which>
-smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
-{
-    smmo_spring_args a;
-    memcpy(&a, args, sizeof a);
-    SpringK k;
-    smmo_status s = cached_bind(h, (const void *)&launch_spring<Which>, cls, a, k,
-                                [&] { return bind_spring(h, a, k); });
-    if (s) return s;
-    if (cls != (Which == 1 ? a.node_class : a.spring_class))
-        return fail(SMMO_EINVAL, "spring: method runs on a different class");
-    if ((s = ensure_enumerated(h, cls, false, st))) return s;
-    const LaunchShape ls = method_shape(h, cls, kSpringGroup);
-    if (Which == 0) {
-        if (ls.group == 4) hipLaunchKernelGGL(k_spring_force<4>, ls.grid, ls.block, 0, st, h->v, k);
-        else if (ls.group == 2) hipLaunchKernelGGL(k_spring_force<2>, ls.grid, ls.block, 0, st, h->v, k);
-        else hipLaunchKernelGGL(k_spring_force<1>, ls.grid, ls.block, 0, st, h->v, k);
-    }
-    if (Which == 1) {
-        if (ls.group == 4) hipLaunchKernelGGL(k_spring_node<4>, ls.grid, ls.block, 0, st, h->v, k);
-        else if (ls.group == 2) hipLaunchKernelGGL(k_spring_node<2>, ls.grid, ls.block, 0, st, h->v, k);
-        else hipLaunchKernelGGL(k_spring_node<1>, ls.grid, ls.block, 0, st, h->v, k);
-    }
-    if (Which == 2) {
-        const LaunchShape l1 = method_shape(h, cls);
-        hipLaunchKernelGGL(k_spring_link, l1.grid, l1.block, 0, st, h->v, k);
-    }
-    return launched("spring kernel");
 }
 
 // ======================================================= test methods =====
@@ -704,43 +476,17 @@ smmo_status launch_ls(smmo_heap *h, uint32_t cls, const void *args, hipStream_t 
     return SMMO_OK;
 }
 
-const MethodEntry kMethods[] = {
-    {"gol.cell_count", sizeof(smmo_gol_args), launch_gol<0>},
-    {"gol.alive_death", sizeof(smmo_gol_args), launch_gol<1>},
-    {"gol.cell_birth", sizeof(smmo_gol_args), launch_gol<2>},
-    {"nbody.force", sizeof(smmo_nbody_args), launch_nbody_force},
-    {"nbody.update", sizeof(smmo_nbody_args), launch_nbody_update},
-    {"spring.force", sizeof(smmo_spring_args), launch_spring<0>},
-    {"spring.node_update", sizeof(smmo_spring_args), launch_spring<1>},
-    {"spring.link", sizeof(smmo_spring_args), launch_spring<2>},
-    {"adjoint.record", sizeof(smmo_adjoint_args), launch_adj_record},
-    {"adjoint.save", sizeof(smmo_adjoint_args), launch_adj_save},
-    {"adjoint.load", sizeof(smmo_adjoint_args), launch_adj_load},
-    {"adjoint.seed", sizeof(smmo_adjoint_args), launch_adj_seed},
-    {"adjoint.zero", sizeof(smmo_adjoint_args), launch_adj_zero},
-    {"adjoint.node", sizeof(smmo_adjoint_args), launch_adj_node},
-    {"adjoint.spring", sizeof(smmo_adjoint_args), launch_adj_spring},
-    {"test.axpy", sizeof(smmo_axpy_args), launch_axpy},
-    {"test.destroy_if", sizeof(smmo_destroy_if_args), launch_destroy_if},
-    {"test.spawn", sizeof(smmo_spawn_args), launch_spawn},
-    {"alloc.ls_alloc", sizeof(smmo_ls_args), launch_ls<0>},
-    {"alloc.ls_free", sizeof(smmo_ls_args), launch_ls<1>},
-    {"wator.cell_prepare", sizeof(smmo_wator_args), launch_wator_cell_prepare},
-    {"wator.fish_prepare", sizeof(smmo_wator_args), launch_wator_fish_prepare},
-    {"wator.shark_prepare", sizeof(smmo_wator_args), launch_wator_shark_prepare},
-    {"wator.cell_decide", sizeof(smmo_wator_args), launch_wator_cell_decide},
-    {"wator.fish_update", sizeof(smmo_wator_args), launch_wator_fish_update},
-    {"wator.shark_update", sizeof(smmo_wator_args), launch_wator_shark_update},
-    {"wator.cell_link", sizeof(smmo_wator_args), launch_wator_cell_link},
-    {"wator.link", sizeof(smmo_wator_args), launch_wator_link},
-};
-
 } // namespace
 
 namespace smmo {
-const MethodEntry *method_table(uint32_t *count)
-{
-    *count = (uint32_t)(sizeof(kMethods) / sizeof(kMethods[0]));
-    return kMethods;
-}
+smmo_status launch_gol_cell_count(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_gol<0>(h, c, a, s); }
+smmo_status launch_gol_alive_death(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_gol<1>(h, c, a, s); }
+smmo_status launch_gol_cell_birth(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_gol<2>(h, c, a, s); }
+smmo_status launch_nbody_force(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return nbody_force_launch(h, c, a, s); }
+smmo_status launch_nbody_update(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return nbody_update_launch(h, c, a, s); }
+smmo_status launch_test_axpy(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_axpy(h, c, a, s); }
+smmo_status launch_test_destroy_if(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_destroy_if(h, c, a, s); }
+smmo_status launch_test_spawn(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_spawn(h, c, a, s); }
+smmo_status launch_ls_alloc(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_ls<0>(h, c, a, s); }
+smmo_status launch_ls_free(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_ls<1>(h, c, a, s); }
 } // namespace smmo

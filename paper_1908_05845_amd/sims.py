@@ -136,10 +136,11 @@ class SpringSim:
     The mesh dict has the arrays of ``inputs.spring_mesh`` (ids local to the
     arrays).  Springs with alive == 0 (if an 'alive' array is given) are not
     created.  Node adjacency is built on the device by spring.link.
+    tension_only: springs pull only (no force while shorter than L0).
     """
 
     def __init__(self, mesh: dict, dt: float, strain_limit: float = 0.3, cfg=None, extra_blocks: int = 16,
-                 blocks: int | None = None):
+                 blocks: int | None = None, tension_only: bool = False):
         import torch
 
         N = int(np.asarray(mesh["x"]).size)
@@ -178,7 +179,8 @@ class SpringSim:
                 slot_a=torch.from_numpy(np.asarray(mesh["slot_a"])[sid].astype(np.uint8)).to(dev),
                 slot_b=torch.from_numpy(np.asarray(mesh["slot_b"])[sid].astype(np.uint8)).to(dev),
                 id=i32(sid), **kw).clone()
-        self.args = smmo.smmo_spring_args(self.heap.cls["Node"], self.heap.cls["Spring"], dt, strain_limit)
+        self.args = smmo.smmo_spring_args(self.heap.cls["Node"], self.heap.cls["Spring"], dt, strain_limit,
+                                          smmo.SMMO_SPRING_TENSION_ONLY if tension_only else 0)
         self.m_force = smmo.smmo_method_id("spring.force")
         self.m_node = smmo.smmo_method_id("spring.node_update")
         self.m_link = smmo.smmo_method_id("spring.link")

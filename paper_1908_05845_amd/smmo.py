@@ -78,9 +78,12 @@ class smmo_nbody_args(C.Structure):
     _fields_ = [("G", C.c_float), ("eps", C.c_float), ("dt", C.c_float), ("reserved", C.c_uint32)]
 
 
+SMMO_SPRING_TENSION_ONLY = 1
+
+
 class smmo_spring_args(C.Structure):
     _fields_ = [("node_class", C.c_uint32), ("spring_class", C.c_uint32), ("dt", C.c_float),
-                ("strain_limit", C.c_float)]
+                ("strain_limit", C.c_float), ("flags", C.c_uint32)]
 
 
 class smmo_adjoint_args(C.Structure):

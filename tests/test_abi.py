@@ -124,7 +124,7 @@ def test_struct_sizes_match_header(lib):
     # sizes of the argument structs the methods check against
     assert C.sizeof(smmo.smmo_gol_args) == 24
     assert C.sizeof(smmo.smmo_nbody_args) == 16
-    assert C.sizeof(smmo.smmo_spring_args) == 16
+    assert C.sizeof(smmo.smmo_spring_args) == 20
     assert C.sizeof(smmo.smmo_spawn_args) == 24
     assert C.sizeof(smmo.smmo_ls_args) == 24
     assert C.sizeof(smmo.smmo_wator_args) == 64

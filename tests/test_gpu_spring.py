@@ -32,10 +32,11 @@ def state_dict(mesh, st):
     return d
 
 
-def check_step(sim, mesh, dt, limit):
+def check_step(sim, mesh, dt, limit, tension_only=False):
     st = sim.read()
     assert (st["adj"] != -2).all(), "adjacency names a dead spring"
-    ref = spring_steps(state_dict(mesh, st), dt, limit, 1, alive=st["alive"], fx=st["fx"], fy=st["fy"])
+    ref = spring_steps(state_dict(mesh, st), dt, limit, 1, alive=st["alive"], fx=st["fx"], fy=st["fy"],
+                       tension_only=tension_only)
     sim.step(1)
     s1 = sim.read()
     assert np.array_equal(s1["alive"], ref["alive"]), int(np.sum(s1["alive"] != ref["alive"]))
@@ -82,6 +83,33 @@ def test_ragged_meshes(dev, W, H, group):
     sim = SpringSim(mesh, 1e-4, 0.05, cfg=group_cfg(group))
     for _ in range(40):
         check_step(sim, mesh, 1e-4, 0.05)
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_tension_only_springs(dev, group):
+    """Springs that only pull (SMMO_SPRING_TENSION_ONLY): fast random
+    velocities compress many springs, which must then exert exactly zero force
+    (the slack decision is taken in float32 on both sides), while stretched
+    ones pull and break as usual."""
+    print("spring 40x30 tension-only, group %d" % group, flush=True)
+    mesh = spring_mesh(40, 30, seed=23, v_sigma=1.0)
+    dt, limit = 1e-4, 0.3
+    sim = SpringSim(mesh, dt, limit, cfg=group_cfg(group), tension_only=True)
+    slack = broken = 0
+    for _ in range(120):
+        broken += check_step(sim, mesh, dt, limit, tension_only=True)
+        st = sim.read()
+        al = st["alive"].astype(bool)
+        slack += int(np.sum((st["fx"][al] == 0) & (st["fy"][al] == 0)))
+    assert slack > 1000 and broken > 10, (slack, broken)
+
+
+def test_spring_flags_validated(dev):
+    mesh = spring_mesh(3, 3, seed=1)
+    sim = SpringSim(mesh, 1e-4, 0.3)
+    bad = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 1e-4, 0.3, 2)
+    with pytest.raises(smmo.SmmoError):
+        smmo.smmo_parallel_do(sim.heap.h, sim.heap.cls["Spring"], sim.m_force, bad)
 
 
 @pytest.mark.parametrize("group", [1, 4])

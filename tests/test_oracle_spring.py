@@ -158,3 +158,51 @@ def test_batched_equals_separate():
         assert np.array_equal(r[key], np.concatenate([r1[key], r2[key]]))
     assert np.array_equal(r["alive"], np.concatenate([r1["alive"], r2["alive"]]))
     assert r["nbroken"] == r1["nbroken"] + r2["nbroken"]
+
+
+def test_tension_only_hand_computed():
+    # compressed: nodes at 0 and 0.5, k = 2, L0 = 1.  Two-sided: the force on
+    # a is k (l - L0) d / l = 2 (-0.5) = -1 (pushed away from b); a
+    # tension-only spring is slack and exerts nothing.
+    m = line_mesh([0.0, 0.5], [2.0], [1.0])
+    two = spring_steps(m, dt=0.5, thresh=1.0)
+    assert two["fx"].tolist() == [-1.0] and two["vx"].tolist() == [-0.5, 0.5]
+    slack = spring_steps(m, dt=0.5, thresh=1.0, tension_only=True)
+    assert slack["fx"].tolist() == [0.0] and slack["vx"].tolist() == [0.0, 0.0]
+    assert slack["x"].tolist() == [0.0, 0.5]
+    # stretched: the same as the two-sided spring (the hand-computed step above)
+    r = spring_steps(line_mesh([0.0, 1.5], [2.0], [1.0]), dt=0.5, thresh=1.0, tension_only=True)
+    assert r["fx"].tolist() == [1.0] and r["vx"].tolist() == [0.5, -0.5] and r["x"].tolist() == [0.25, 1.25]
+
+
+def test_tension_only_oscillator_goes_slack():
+    # Two nodes released from a stretch u0 (separation L0 + 2 u0): while the
+    # spring is stretched the motion is the harmonic one (the discrete closed
+    # form of the two-sided test); after the separation drops below L0 there
+    # is no force, so the velocities stay exactly constant and the nodes move
+    # in a straight line until they would meet, about 1/(2 u0 w dt) steps on.
+    k, L0, u0, dt = 50.0, 1.0, 0.05, 1e-3
+    w2 = 2 * k
+    mesh = line_mesh([-(L0 / 2 + u0), L0 / 2 + u0], [k], [L0])
+    th = math.acos(1 - w2 * dt * dt / 2)
+    u1 = u0 + dt * (0 - w2 * dt * u0)
+    B = (u1 - u0 * math.cos(th)) / math.sin(th)
+    n = 100                                       # u_n > 0: still stretched
+    r = spring_steps(mesh, dt=dt, thresh=1.0, steps=n, tension_only=True)
+    u_n = u0 * math.cos(n * th) + B * math.sin(n * th)
+    assert u_n > 0.02
+    assert abs((r["x"][1] - L0 / 2) - u_n) < 1e-12
+    # first slack step: u turns negative near n* = pi / (2 th) ~ 157
+    r1 = spring_steps(mesh, dt=dt, thresh=1.0, steps=200, tension_only=True)
+    r2 = spring_steps(mesh, dt=dt, thresh=1.0, steps=600, tension_only=True)
+    assert r1["x"][1] - r1["x"][0] < L0 and r2["x"][1] - r2["x"][0] > 0
+    assert r1["vx"].tolist() == r2["vx"].tolist()                  # no force at all
+    assert r1["vx"][1] < 0 and r1["vx"][0] == -r1["vx"][1]
+    assert abs(r2["x"][1] - (r1["x"][1] + 400 * dt * r1["vx"][1])) < 1e-12
+    # the slack speed is the harmonic phase's speed when the spring reached L0
+    # (|u'| = u0 w up to O(dt) for the discrete map)
+    assert abs(-r1["vx"][1] - u0 * math.sqrt(w2)) < 2e-2 * u0 * math.sqrt(w2)
+    # the two-sided spring instead pushes back: at step 600 it is compressed
+    # and decelerating, not coasting
+    t = spring_steps(mesh, dt=dt, thresh=1.0, steps=600)
+    assert t["vx"][1] != r2["vx"][1]
