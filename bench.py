@@ -526,6 +526,117 @@ def measure_gol_extra(torch):
     return res
 
 
+def measure_gol_large(torch):
+    """Game of Life, 16384 x 16384 torus (268M Cell objects), 25 % start:
+    the supplemental size whose state (about 10 GB of blocks) is far beyond
+    the 256 MB MALL, for an HBM figure.  Two generations to settle, then
+    five timed with events around each of the three do-alls.
+
+    Algorithmic bytes: Cell::count reads cell_id (4 B), the neighbour handle
+    row (4 B, each handle reused by eight neighbours) and the state byte of
+    each cell once, and writes count (4 B): 13 B per cell.  Cell::birth reads
+    state and count (5 B per cell) and writes the state of a newborn.
+    Alive::death reads cell_id, the cell handle and the cell's count (12 B per
+    live Alive)."""
+    from inputs import gol_init
+    from paper_1908_05845_amd import smmo
+    from paper_1908_05845_amd.sims import GolSim
+
+    W = H = 16384
+    print("extras: gol 16384^2 setup", file=sys.stderr, flush=True)
+    sim = GolSim(W, H, gol_init(W, H))
+    heap = sim.heap
+    h, c, a = heap.h, heap.cls["Cell"], heap.cls["Alive"]
+    sim.step(2)
+    heap.sync()
+    st0 = heap.stats()
+    n = 5
+    tot = [0.0, 0.0, 0.0]
+    alive_sum = 0.0
+    for _ in range(n):
+        alive_sum += heap.stats().live_objects[a]
+        ev = events(torch, 4)
+        ev[0].record()
+        smmo.smmo_parallel_do(h, c, sim.m_count, sim.args)
+        ev[1].record()
+        smmo.smmo_parallel_do(h, a, sim.m_death, sim.args)
+        ev[2].record()
+        smmo.smmo_parallel_do(h, c, sim.m_birth, sim.args)
+        ev[3].record()
+        torch.cuda.synchronize()
+        for i in range(3):
+            tot[i] += ev[i].elapsed_time(ev[i + 1]) * 1e3
+    st1 = heap.stats()
+    cells = W * H
+    alive = alive_sum / n
+    us = [t / n for t in tot]
+    gen_us = sum(us)
+    res = {"workload": "Game of Life in SMMO form, 16384x16384 torus (268M cells), 25% start",
+           "generations_timed": n, "us_per_generation": gen_us,
+           "cell_updates_per_s": cells / (gen_us * 1e-6),
+           "updates_per_s": (2 * cells + alive) / (gen_us * 1e-6),
+           "alive_mean": alive,
+           "count_us": us[0], "death_us": us[1], "birth_us": us[2],
+           "count_gbs": 13.0 * cells / (us[0] * 1e-6) / 1e9,
+           "birth_gbs": 5.0 * cells / (us[2] * 1e-6) / 1e9,
+           "death_gbs": 12.0 * alive / (us[1] * 1e-6) / 1e9,
+           "births_per_s": (st1.device_news - st0.device_news) / (gen_us * n * 1e-6),
+           "deaths_per_s": (st1.device_deletes - st0.device_deletes) / (gen_us * n * 1e-6),
+           "device_error": st1.device_error}
+    heap.close()
+    return res
+
+
+def measure_spring_large(torch, tuned):
+    """Spring mesh 2000 x 2000 (4M nodes, 12.0M springs; about 900 MB of
+    blocks, beyond the 256 MB MALL): the plain step's supplemental size.  The
+    launch shapes are the ones tuned for the 1000 x 1000 mesh.  20 steps to
+    settle, then 50 timed with events around each do-all; bytes per object as
+    for the 1000 x 1000 mesh (40 B per live spring; 68 B per node + 16 B per
+    live spring)."""
+    from inputs import spring_mesh
+    from paper_1908_05845_amd import smmo
+    from paper_1908_05845_amd.sims import SpringSim
+
+    print("extras: spring 2000^2 setup", file=sys.stderr, flush=True)
+    mesh = spring_mesh(2000, 2000)
+    sim = SpringSim(mesh, 1e-5, 0.3)
+    heap = sim.heap
+    cs, cn = heap.cls["Spring"], heap.cls["Node"]
+    for name, mid, cls in (("spring.force", sim.m_force, cs), ("spring.node_update", sim.m_node, cn)):
+        t = (tuned or {}).get(name)
+        if t:
+            smmo.smmo_set_launch(heap.h, mid, cls, t["wg"], t["waves"], t.get("group", 0))
+    sim.step(20)
+    heap.sync()
+    n = 50
+    ev = events(torch, 2 * n + 1)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i in range(n):
+        sim.spring_force()
+        ev[2 * i + 1].record()
+        sim.node_update()
+        ev[2 * i + 2].record()
+    torch.cuda.synchronize()
+    tf = sum(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(n)) * 1e3 / n
+    tn = sum(ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) for i in range(n)) * 1e3 / n
+    st = heap.stats()
+    live = st.live_objects[cs]
+    N = st.live_objects[cn]
+    step_us = ev[0].elapsed_time(ev[2 * n]) * 1e3 / n
+    fb, nb = 40.0 * live, 68.0 * N + 16.0 * live
+    res = {"workload": "spring-mass structure, 2000x2000 jittered grid: 4,000,000 Node and %d Spring objects"
+                       % len(mesh["a"]),
+           "steps_timed": n, "us_per_step": step_us, "updates_per_s": (N + live) / (step_us * 1e-6),
+           "springs_live": int(live),
+           "force_us": tf, "force_gbs": fb / (tf * 1e-6) / 1e9,
+           "node_us": tn, "node_gbs": nb / (tn * 1e-6) / 1e9,
+           "step_gbs": (fb + nb) / (step_us * 1e-6) / 1e9, "device_error": st.device_error}
+    heap.close()
+    return res
+
+
 def measure_linux_scalability(torch):
     """Linux Scalability pattern (Ch.8 "Raw Allocation Performance") in SMMO
     form: a 1 GiB heap, 16,384 Worker objects each allocate n 64-byte Obj
@@ -1145,6 +1256,9 @@ def main():
         extras["batched"] = measure_batched(torch, res["value"])
         extras["adjoint"] = measure_adjoint(torch, res["value"])
         extras["gol"] = measure_gol_extra(torch)
+        extras["gol_16384"] = measure_gol_large(torch)
+        tuned = res.get("autotune") or {}
+        extras["spring_2000"] = measure_spring_large(torch, tuned if tuned.get("kept") == "tuned" else None)
         extras["nbody"] = measure_nbody_extra(torch)
         extras["linux_scalability"] = measure_linux_scalability(torch)
         extras["wator"] = measure_wator(torch)

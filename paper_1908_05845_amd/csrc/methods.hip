@@ -33,28 +33,50 @@ struct GolK {
     uint32_t a_id;                     // Alive field offset
 };
 
-// Cell::count - live cells among the 8 neighbours on the torus
+// Cell::count - live cells among the 8 neighbours on the torus.  One
+// integer division per cell (gfx950 has no integer divide instruction); the
+// wrap-around of the neighbour coordinates is a compare and select.  U
+// blocks at once: a wavefront issues the neighbour-handle loads and then the
+// state loads of all U blocks before it waits, since each block's chain of
+// dependent loads (cell id, handles, states) is what bounds the walk.
+template <int U>
 __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        if (!((bm >> s) & 1)) return;
-        const int32_t id = farr<int32_t>(h, bid, p.c_id)[s];
-        const int32_t x = id % p.W, y = id / p.W;
-        int32_t n = 0;
+    const uint32_t s = lane_id();
+    for_each_block_group<U>(h, p.cell_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
+        bool live[U];
+        int32_t id[U];
 #pragma unroll
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int32_t ny = (y + dy + p.H) % p.H;
-#pragma unroll
-            for (int dx = -1; dx <= 1; ++dx) {
-                if (!dx && !dy) continue;
-                const int32_t nx = (x + dx + p.W) % p.W;
-                const uint32_t hc = p.cells[ny * p.W + nx];
-                n += fref<uint8_t>(h, hc, p.c_state);
-            }
+        for (int j = 0; j < U; ++j) {
+            live[j] = (bm[j] >> s) & 1;
+            id[j] = live[j] ? farr<int32_t>(h, bid[j], p.c_id)[s] : 0;
         }
-        farr<int32_t>(h, bid, p.c_count)[s] = n;
+        uint32_t hc[U][8];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int32_t y = id[j] / p.W, x = id[j] - y * p.W;
+            const int32_t xs[3] = {x == 0 ? p.W - 1 : x - 1, x, x == p.W - 1 ? 0 : x + 1};
+            const int32_t rows[3] = {(y == 0 ? p.H - 1 : y - 1) * p.W, y * p.W,
+                                     (y == p.H - 1 ? 0 : y + 1) * p.W};
+            int k = 0;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    if (dx == 1 && dy == 1) continue;
+                    hc[j][k++] = live[j] ? p.cells[rows[dy] + xs[dx]] : kNull;
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (!own[j]) continue;
+            int32_t n = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (live[j]) n += fref<uint8_t>(h, hc[j][k], p.c_state);
+            if (live[j]) farr<int32_t>(h, bid[j], p.c_count)[s] = n;
+        }
     });
 }
 
@@ -118,6 +140,9 @@ smmo_status bind_gol(smmo_heap *h, const smmo_gol_args &a, GolK &k)
     return SMMO_OK;
 }
 
+// blocks per wavefront iteration of Cell::count unless set otherwise
+constexpr uint32_t kGolCountGroup = 2;
+
 template <int Which>
 smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
 {
@@ -129,9 +154,13 @@ smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     if (s) return s;
     const uint32_t want = Which == 1 ? a.alive_class : a.cell_class;
     if (cls != want) return fail(SMMO_EINVAL, "gol: method runs on a different class");
-    const LaunchShape ls = method_shape(h, cls);
+    const LaunchShape ls = method_shape(h, cls, Which == 0 ? kGolCountGroup : 0);
     if ((s = ensure_enumerated(h, cls, false, st, Which == 1 && packing_wanted(h, cls, ls)))) return s;
-    if (Which == 0) hipLaunchKernelGGL(k_gol_count, ls.grid, ls.block, 0, st, h->v, k);
+    if (Which == 0) {
+        if (ls.group == 4) hipLaunchKernelGGL(k_gol_count<4>, ls.grid, ls.block, 0, st, h->v, k);
+        else if (ls.group == 2) hipLaunchKernelGGL(k_gol_count<2>, ls.grid, ls.block, 0, st, h->v, k);
+        else hipLaunchKernelGGL(k_gol_count<1>, ls.grid, ls.block, 0, st, h->v, k);
+    }
     if (Which == 1) hipLaunchKernelGGL(k_gol_death, ls.grid, ls.block, 0, st, h->v, k);
     if (Which == 2) hipLaunchKernelGGL(k_gol_birth, ls.grid, ls.block, 0, st, h->v, k);
     if ((s = launched("gol kernel"))) return s;
