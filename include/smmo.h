@@ -182,8 +182,33 @@ smmo_status smmo_define_class(smmo_schema *s, const char *name,
                               const smmo_field_desc *fields, uint32_t nfields,
                               uint32_t *class_id);
 
+/* Declares a class that derives from `parent` (single inheritance, thesis
+ * Ch.5 sec.5.1.1 "Class Inheritance"; the block's data segment holds the
+ * inherited field arrays first, then the new ones, sec.5.2.1 "Block
+ * Structure").  Its fields are the parent's, at the same offsets inside a
+ * block and with the same field ids, followed by `fields` (nfields may be 0;
+ * fields may then be NULL).  So a method bound to the fields of a class runs
+ * unchanged on the blocks of every descendant.  parent = SMMO_NO_PARENT
+ * declares a root class.  flags: SMMO_CLASS_ABSTRACT for a class without
+ * objects of its own (the thesis's kIsAbstract): smmo_parallel_new refuses it
+ * and no method allocates it.
+ * A do-all (smmo_parallel_do) on a class runs the method on the objects of
+ * the class and of all its descendants: one kernel per concrete class of that
+ * family, in class-id order, each class enumerated just before its kernel
+ * (the thesis launches a separate kernel per type to avoid divergence).
+ * Errors as smmo_define_class; SMMO_EINVAL for a bad parent or flags. */
+#define SMMO_NO_PARENT 0xFFFFFFFFu
+#define SMMO_CLASS_ABSTRACT 1u
+smmo_status smmo_define_subclass(smmo_schema *s, const char *name, uint32_t parent, uint32_t flags,
+                                 const smmo_field_desc *fields, uint32_t nfields,
+                                 uint32_t *class_id);
+
+/* *out = 1 if class `cls` is `ancestor` or derives from it, else 0 (the
+ * relation behind cast<T>, Ch.5 sec.5.1.1). */
+smmo_status smmo_class_is_a(const smmo_schema *s, uint32_t cls, uint32_t ancestor, uint32_t *out);
+
 /* Looks up a field of a class by name; *field_id is its index in the
- * class's field list. */
+ * class's field list (inherited fields first). */
 smmo_status smmo_field_id(const smmo_schema *s, uint32_t class_id, const char *name,
                           uint32_t *field_id);
 

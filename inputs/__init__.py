@@ -14,4 +14,5 @@ from .workloads import (  # noqa: F401
     batched_meshes,
     concat_meshes,
     wator_init,
+    structure_mesh,
 )

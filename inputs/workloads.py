@@ -198,3 +198,80 @@ def concat_meshes(meshes: list) -> dict:
     out["node_offsets"] = noff
     out["spring_offsets"] = soff
     return out
+
+
+def structure_mesh(W: int, H: int, seed: int | None = None, jitter: float = 0.2, pull_speed: float = 0.5,
+                   break_strain: float = 0.04, break_spread: float = 0.5, v_sigma: float = 0.0) -> dict:
+    """Mesh of the fracture simulation ("structure"): a W x H brick-wall
+    lattice (every node has springs to its left and right neighbours and, on
+    alternating columns, to the node above or below: at most three springs per
+    node), jittered positions with spacing h = 1/W.  Column 0 holds anchor
+    nodes, column W-1 pull nodes moving at (pull_speed, 0), the rest ordinary
+    nodes of mass 1 at rest (or with N(0, v_sigma^2) velocities).  Spring
+    stiffness k = 10^U(2, 3); rest length L0 = initial length; force limit
+    k * L0 * break_strain * (1 + break_spread * U(-1, 1)).
+
+    Returned arrays (float32 state, int32 topology; node id = j*W + i):
+      ntype (0 anchor, 1 pull, 2 node), nalive, x, y, vx, vy, m,
+      slot (N*3 spring ids, -1 empty), isp2 (N*3), nspr, dist,
+      p1, p2, k, L0, maxf, s1, s2, salive (spring id = position).
+    """
+    if seed is None:
+        seed = config_seed(6)
+    N = W * H
+    ids = np.arange(N, dtype=np.int64)
+    i = ids % W
+    j = ids // W
+    h = 1.0 / W
+    x = ((i + (2.0 * uniform(seed, 0, ids) - 1.0) * jitter) * h).astype(np.float32)
+    y = ((j + (2.0 * uniform(seed, 1, ids) - 1.0) * jitter) * h).astype(np.float32)
+    ntype = np.full(N, 2, np.int32)
+    ntype[i == W - 1] = 1
+    ntype[i == 0] = 0
+    vx = np.zeros(N, np.float32)
+    vy = np.zeros(N, np.float32)
+    if v_sigma > 0:
+        vx = (v_sigma * normal(seed, 2, ids)).astype(np.float32)
+        vy = (v_sigma * normal(seed, 3, ids)).astype(np.float32)
+        vx[ntype == 0] = 0
+        vy[ntype == 0] = 0
+    vx[ntype == 1] = pull_speed
+    vy[ntype == 1] = 0
+    # horizontal springs, then the vertical ones of the columns with (i + j) even
+    hor = ids[i + 1 < W]
+    ver = ids[((i + j) % 2 == 0) & (j + 1 < H)]
+    p1 = np.concatenate([hor, ver])
+    p2 = np.concatenate([hor + 1, ver + W])
+    S = p1.size
+    sid = np.arange(S, dtype=np.int64)
+    k = (10.0 ** (2.0 + uniform(seed, 4, sid))).astype(np.float32)
+    dx = x[p2].astype(np.float64) - x[p1].astype(np.float64)
+    dy = y[p2].astype(np.float64) - y[p1].astype(np.float64)
+    L0 = np.sqrt(dx * dx + dy * dy).astype(np.float32)
+    maxf = (k.astype(np.float64) * L0 * break_strain
+            * (1.0 + break_spread * (2.0 * uniform(seed, 5, sid) - 1.0))).astype(np.float32)
+    node = np.concatenate([p1, p2])
+    spr = np.concatenate([sid, sid])
+    isb = np.concatenate([np.zeros(S, np.uint8), np.ones(S, np.uint8)])
+    order = np.lexsort((spr, node))
+    node_s, spr_s, isb_s = node[order], spr[order], isb[order]
+    first = np.searchsorted(node_s, node_s, side="left")
+    rank = np.arange(node_s.size) - first
+    if N and rank.max(initial=0) >= 3:
+        raise ValueError("node degree above 3")
+    slot = np.full((N, 3), -1, np.int32)
+    isp2 = np.zeros((N, 3), np.uint8)
+    slot[node_s, rank] = spr_s
+    isp2[node_s, rank] = isb_s
+    s1 = np.empty(S, np.int32)
+    s2 = np.empty(S, np.int32)
+    sel = isb_s == 0
+    s1[spr_s[sel]] = rank[sel]
+    s2[spr_s[~sel]] = rank[~sel]
+    return {
+        "ntype": ntype, "nalive": np.ones(N, np.uint8), "x": x, "y": y, "vx": vx, "vy": vy,
+        "m": np.ones(N, np.float32), "slot": slot.reshape(-1), "isp2": isp2.reshape(-1),
+        "nspr": (slot >= 0).sum(axis=1).astype(np.int32), "dist": np.zeros(N, np.int32),
+        "p1": p1.astype(np.int32), "p2": p2.astype(np.int32), "k": k, "L0": L0, "maxf": maxf,
+        "s1": s1, "s2": s2, "salive": np.ones(S, np.uint8),
+    }

@@ -16,4 +16,11 @@ from .oracle import (  # noqa: F401
     spring_adjoint,
     spring_adjoint_step,
     spring_breaks,
+    structure_pull,
+    structure_step,
+    structure_bfs,
+    STRUCTURE_ANCHOR,
+    STRUCTURE_PULL,
+    STRUCTURE_NODE,
+    STRUCTURE_MAXDIST,
 )

@@ -73,6 +73,13 @@ def _load():
             lib.orc_wator_read.argtypes = [P, P, P, P, P]
             lib.orc_wator_free.restype = None
             lib.orc_wator_free.argtypes = [P]
+            lib.orc_structure_pull.restype = C.c_int
+            lib.orc_structure_pull.argtypes = [LL, P, P, P, P, P, P, D]
+            lib.orc_structure_step.restype = LL
+            lib.orc_structure_step.argtypes = [LL, P, P, P, P, P, P, P, P, P, P, LL, P, P, P, P, P, P, P,
+                                               P, P, P, D, P, P, P, P, P]
+            lib.orc_structure_bfs.restype = LL
+            lib.orc_structure_bfs.argtypes = [LL, P, P, P, P, P, P, LL, P, P, P, P, P, P, P]
             _lib = lib
     return _lib
 
@@ -304,3 +311,77 @@ def spring_adjoint_step(mesh: dict, px, py, dt, lx, ly, lvx, lvy):
     if rc:
         raise RuntimeError("oracle adjoint step error %d" % rc)
     return dict(lx=lx, ly=ly, lvx=lvx, lvy=lvy, gk=gk, sgk=sgk, slx=slx, sly=sly, slvx=slvx, slvy=slvy)
+
+
+# ---------------------------------------------------------------- structure --
+STRUCTURE_ANCHOR, STRUCTURE_PULL, STRUCTURE_NODE = 0, 1, 2
+STRUCTURE_MAXDIST = 0x7FFFFFFF
+
+
+def _structure_arrays(st: dict) -> dict:
+    """Private, contiguous copies of a structure state (see structure_step)."""
+    N = int(np.asarray(st["x"]).size)
+    S = int(np.asarray(st["p1"]).size)
+    c = lambda a, dt: np.array(a, dtype=dt, copy=True).reshape(-1)
+    out = dict(st)
+    for key in ("x", "y", "vx", "vy", "m"):
+        out[key] = c(st[key], np.float64)
+    for key in ("k", "L0", "maxf"):
+        out[key] = c(st[key], np.float64)
+    out["fx"] = c(st.get("fx", np.zeros(S)), np.float64)
+    out["fy"] = c(st.get("fy", np.zeros(S)), np.float64)
+    for key in ("ntype", "nspr", "p1", "p2", "s1", "s2"):
+        out[key] = c(st[key], np.int32)
+    out["dist"] = c(st.get("dist", np.zeros(N)), np.int32)
+    out["slot"] = c(st["slot"], np.int32)
+    for key in ("nalive", "salive", "isp2"):
+        out[key] = c(st[key], np.uint8)
+    out["sdel"] = c(st.get("sdel", np.zeros(S)), np.uint8)
+    assert out["slot"].size == 3 * N and out["isp2"].size == 3 * N
+    return out
+
+
+def structure_pull(st: dict, dt: float) -> dict:
+    """AnchorPullNode::pull (thesis Ch.7 "structure", step 1) in float64."""
+    o = _structure_arrays(st)
+    _load().orc_structure_pull(o["x"].size, _p(o["ntype"]), _p(o["nalive"]), _p(o["x"]), _p(o["y"]),
+                               _p(o["vx"]), _p(o["vy"]), float(dt))
+    return o
+
+
+def structure_step(st: dict, dt: float) -> dict:
+    """One compute step of "structure" (Spring::force, then Node::update).
+
+    State: per node id ntype (0 anchor, 1 pull, 2 node), nalive, x, y, vx, vy,
+    m, slot (3 per node: spring id or -1), isp2 (3 per node), nspr, dist; per
+    spring id p1, p2, k, L0, maxf, s1, s2, salive, fx, fy, sdel.  Returns the
+    new state with nbroken and the conditioning scales sf, svx, svy, sx, sy.
+    """
+    o = _structure_arrays(st)
+    N, S = o["x"].size, o["p1"].size
+    sf = np.zeros(S)
+    svx, svy, sx, sy = (np.zeros(N) for _ in range(4))
+    nb = _load().orc_structure_step(
+        N, _p(o["ntype"]), _p(o["nalive"]), _p(o["x"]), _p(o["y"]), _p(o["vx"]), _p(o["vy"]), _p(o["m"]),
+        _p(o["slot"]), _p(o["isp2"]), _p(o["nspr"]), S, _p(o["p1"]), _p(o["p2"]), _p(o["k"]), _p(o["L0"]),
+        _p(o["maxf"]), _p(o["s1"]), _p(o["s2"]), _p(o["salive"]), _p(o["fx"]), _p(o["fy"]), float(dt),
+        _p(sf), _p(svx), _p(svy), _p(sx), _p(sy))
+    if nb < 0:
+        raise RuntimeError("oracle structure error %d" % nb)
+    o.update(nbroken=int(nb), sf=sf, svx=svx, svy=svy, sx=sx, sy=sy)
+    return o
+
+
+def structure_bfs(st: dict) -> dict:
+    """Removal of disconnected nodes (thesis Ch.7 "structure", step 3).
+    Returns the new state with dist, levels (visit passes) and ndeleted."""
+    o = _structure_arrays(st)
+    N, S = o["x"].size, o["p1"].size
+    lv = C.c_int(0)
+    nd = _load().orc_structure_bfs(N, _p(o["ntype"]), _p(o["nalive"]), _p(o["slot"]), _p(o["isp2"]),
+                                   _p(o["nspr"]), _p(o["dist"]), S, _p(o["p1"]), _p(o["p2"]), _p(o["s1"]),
+                                   _p(o["s2"]), _p(o["salive"]), _p(o["sdel"]), C.byref(lv))
+    if nd < 0:
+        raise RuntimeError("oracle structure error %d" % nd)
+    o.update(levels=int(lv.value), ndeleted=int(nd))
+    return o

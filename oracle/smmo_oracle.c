@@ -1119,3 +1119,183 @@ void orc_wator_free(void *wp)
     free(w->snap);
     free(w);
 }
+
+/* ------------------------------------------------------------------------ */
+/* structure (thesis Ch.7 "structure": the fracture FEM).  Classes:          */
+/*   NodeBase (abstract): position, up to three spring slots, the number of */
+/*     occupied slots, the BFS distance;                                     */
+/*   AnchorNode: fixed; AnchorPullNode: moves at a constant velocity;        */
+/*   Node: moves under the spring forces (velocity, mass);                   */
+/*   Spring: its two endpoint nodes, stiffness k, rest length L0, the force  */
+/*     limit, the force of the last compute step, a delete flag.             */
+/* One iteration: pull the pull nodes; compute steps, each Spring::force     */
+/* then Node::update; remove the nodes no longer connected to an anchor     */
+/* node (BFS from the anchor nodes) with their springs.                      */
+/* Readings (listed in the design notes): a spring pulls only while          */
+/* stretched (Hooke's law on the elongation l - L0 > 0); it breaks when that */
+/* force k (l - L0) exceeds its limit, and then unlinks itself from both     */
+/* endpoints and is deleted; a node whose last spring is unlinked is deleted */
+/* (the unlink decrements its spring count, and the unlink that takes it to  */
+/* zero deletes the node).  The force is stored on the spring as a vector,   */
+/* (fx, fy) = k (l - L0) d / l with d = x_p2 - x_p1 acting on p1 (p2 gets    */
+/* the negative), so that Node::update reads no other node.  The stretch and */
+/* break decisions are integer-valued and taken in float32 in the kernel's   */
+/* operation order: l as for the mesh springs, stretched iff l > L0,         */
+/* F = k * (l - L0) with each operation rounded, break iff stretched and     */
+/* F > limit.  Everything else is float64.                                   */
+/* State arrays (node id i, spring id s; ids are canonical, alive flags      */
+/* mark the live objects):                                                   */
+/*   ntype[i] 0 anchor, 1 pull, 2 node; nalive[i]; x, y, vx, vy, m;          */
+/*   slot[3i+q] spring id or -1, isp2[3i+q] 1 if node i is the spring's p2;  */
+/*   nspr[i] occupied slots; dist[i] BFS distance                            */
+/*   p1[s], p2[s], k, L0, maxf, s1[s], s2[s] (slot in p1 / p2), salive[s],   */
+/*   fx, fy, sdel[s]                                                         */
+/* ------------------------------------------------------------------------ */
+#define ST_ANCHOR 0
+#define ST_PULL 1
+#define ST_NODE 2
+#define ST_MAXDIST 0x7FFFFFFF
+
+/* Node::remove_spring: empty the slot; the unlink that removes the last
+ * spring deletes the node */
+static int st_unlink(long long node, int q, long long sid, int32_t *slot, int32_t *nspr, uint8_t *nalive)
+{
+    if (!nalive[node] || slot[3 * node + q] != sid || nspr[node] <= 0) return 7;
+    slot[3 * node + q] = -1;
+    if (--nspr[node] == 0) nalive[node] = 0;
+    return 0;
+}
+
+/* AnchorPullNode::pull on every pull node */
+int orc_structure_pull(long long N, const int32_t *ntype, const uint8_t *nalive, double *x, double *y,
+                       const double *vx, const double *vy, double dt)
+{
+    for (long long i = 0; i < N; i++)
+        if (nalive[i] && ntype[i] == ST_PULL) {
+            x[i] += vx[i] * dt;
+            y[i] += vy[i] * dt;
+        }
+    return 0;
+}
+
+/* One compute step: Spring::force over the live springs, then Node::update
+ * over the live Nodes.  sf (S) and svx, svy, sx, sy (N), optional, receive
+ * the conditioning scales as for the mesh springs.  Returns the number of
+ * springs broken, or a negative error code. */
+long long orc_structure_step(long long N, const int32_t *ntype, uint8_t *nalive, double *x, double *y,
+                             double *vx, double *vy, const double *m, int32_t *slot, const uint8_t *isp2,
+                             int32_t *nspr, long long S, const int32_t *p1, const int32_t *p2,
+                             const double *k, const double *L0, const double *maxf, const int32_t *s1,
+                             const int32_t *s2, uint8_t *salive, double *fx, double *fy, double dt,
+                             double *sf, double *svx, double *svy, double *sx, double *sy)
+{
+    long long nbroken = 0;
+    uint8_t *snap = malloc((size_t)(S ? S : 1));
+    if (!snap) return -1;
+    memcpy(snap, salive, (size_t)S);
+    for (long long s = 0; s < S; s++) {            /* Spring::force over the snapshot */
+        if (!snap[s]) continue;
+        const long long a = p1[s], b = p2[s];
+        if (a < 0 || a >= N || b < 0 || b >= N || !nalive[a] || !nalive[b]) { free(snap); return -12; }
+        const float l32 = sp_len32(x[a], y[a], x[b], y[b]);
+        const float L0f = (float)L0[s];
+        const float d32 = l32 - L0f;
+        const float F32 = (float)k[s] * d32;
+        const int stretched = l32 > L0f;
+        if (stretched && F32 > (float)maxf[s]) {
+            if (st_unlink(a, s1[s], s, slot, nspr, nalive) || st_unlink(b, s2[s], s, slot, nspr, nalive)) {
+                free(snap);
+                return -17;
+            }
+            salive[s] = 0;
+            fx[s] = fy[s] = 0;
+            if (sf) sf[s] = 0;
+            nbroken++;
+            continue;
+        }
+        if (!stretched) {
+            fx[s] = fy[s] = 0;
+            if (sf) sf[s] = 0;
+            continue;
+        }
+        const double dx = x[b] - x[a], dy = y[b] - y[a];
+        const double l = sqrt(dx * dx + dy * dy);
+        const double c = k[s] * (l - L0[s]) / l;
+        fx[s] = c * dx;
+        fy[s] = c * dy;
+        if (sf) sf[s] = k[s] * (l + L0[s]);
+    }
+    free(snap);
+    for (long long i = 0; i < N; i++) {            /* Node::update over the live Nodes */
+        if (!nalive[i] || ntype[i] != ST_NODE) continue;
+        double Fx = 0, Fy = 0, SF = 0;
+        for (int q = 0; q < 3; q++) {
+            const long long s = slot[3 * i + q];
+            if (s < 0) continue;
+            if (s >= S || !salive[s]) return -13;
+            const double sg = isp2[3 * i + q] ? -1.0 : 1.0;
+            Fx += sg * fx[s];
+            Fy += sg * fy[s];
+            if (sf) SF += sf[s];
+        }
+        const double svxi = fabs(vx[i]) + dt * SF / m[i], svyi = fabs(vy[i]) + dt * SF / m[i];
+        if (svx) svx[i] = svxi;
+        if (svy) svy[i] = svyi;
+        if (sx) sx[i] = fabs(x[i]) + dt * svxi;
+        if (sy) sy[i] = fabs(y[i]) + dt * svyi;
+        vx[i] += Fx / m[i] * dt;
+        vy[i] += Fy / m[i] * dt;
+        x[i] += vx[i] * dt;
+        y[i] += vy[i] * dt;
+    }
+    return nbroken;
+}
+
+/* Removal of disconnected nodes: distance 0 at the anchor nodes and "infinite"
+ * elsewhere; BFS levels while the frontier is not empty (the frontier of
+ * level d is the set of nodes at distance d; each gives its unvisited
+ * neighbours distance d + 1); every node left unvisited flags its springs;
+ * every flagged spring unlinks itself from both endpoints (deleting nodes
+ * whose last spring it was) and is deleted.  *levels receives the number of
+ * visit passes (the last one finds an empty frontier).  Returns the number of
+ * springs deleted, or a negative error code. */
+long long orc_structure_bfs(long long N, const int32_t *ntype, uint8_t *nalive, int32_t *slot,
+                            const uint8_t *isp2, int32_t *nspr, int32_t *dist, long long S,
+                            const int32_t *p1, const int32_t *p2, const int32_t *s1, const int32_t *s2,
+                            uint8_t *salive, uint8_t *sdel, int *levels)
+{
+    for (long long i = 0; i < N; i++)
+        if (nalive[i]) dist[i] = ntype[i] == ST_ANCHOR ? 0 : ST_MAXDIST;
+    int lv = 0;
+    for (int d = 0;; d++) {
+        int cont = 0;
+        lv++;
+        for (long long i = 0; i < N; i++) {
+            if (!nalive[i] || dist[i] != d) continue;
+            cont = 1;
+            for (int q = 0; q < 3; q++) {
+                const long long s = slot[3 * i + q];
+                if (s < 0) continue;
+                if (s >= S || !salive[s]) return -14;
+                const long long o = isp2[3 * i + q] ? p1[s] : p2[s];
+                if (o < 0 || o >= N || !nalive[o]) return -15;
+                if (dist[o] == ST_MAXDIST) dist[o] = d + 1;
+            }
+        }
+        if (!cont || d == ST_MAXDIST - 1) break;
+    }
+    *levels = lv;
+    for (long long i = 0; i < N; i++)
+        if (nalive[i] && dist[i] == ST_MAXDIST)
+            for (int q = 0; q < 3; q++)
+                if (slot[3 * i + q] >= 0) sdel[slot[3 * i + q]] = 1;
+    long long ndel = 0;
+    for (long long s = 0; s < S; s++) {
+        if (!salive[s] || !sdel[s]) continue;
+        if (st_unlink(p1[s], s1[s], s, slot, nspr, nalive) || st_unlink(p2[s], s2[s], s, slot, nspr, nalive))
+            return -16;
+        salive[s] = 0;
+        ndel++;
+    }
+    return ndel;
+}

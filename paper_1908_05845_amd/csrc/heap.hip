@@ -655,6 +655,18 @@ LaunchShape method_shape(const smmo_heap *h, uint32_t cls, uint32_t def_group)
     return ls;
 }
 
+uint32_t class_family(const smmo_schema *s, uint32_t cls)
+{
+    uint32_t fam = 0;
+    for (uint32_t c = 0; c < s->nclasses; ++c)
+        for (uint32_t a = c; a != SMMO_NO_PARENT; a = s->c[a].parent)
+            if (a == cls) {
+                fam |= 1u << c;
+                break;
+            }
+    return fam;
+}
+
 void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects)
 {
     const uint64_t add = (max_new_objects + 63) / 64 + 1;
@@ -695,20 +707,42 @@ smmo_status smmo_schema_free(smmo_schema *s)
 smmo_status smmo_define_class(smmo_schema *s, const char *name, const smmo_field_desc *fields,
                               uint32_t nfields, uint32_t *class_id)
 {
-    if (!s || !name || !fields || !class_id) return fail(SMMO_EINVAL, "NULL argument");
+    if (!fields) return fail(SMMO_EINVAL, "NULL argument");
+    return smmo_define_subclass(s, name, SMMO_NO_PARENT, 0, fields, nfields, class_id);
+}
+
+smmo_status smmo_define_subclass(smmo_schema *s, const char *name, uint32_t parent, uint32_t flags,
+                                 const smmo_field_desc *fields, uint32_t nfields, uint32_t *class_id)
+{
+    if (!s || !name || !class_id || (nfields && !fields)) return fail(SMMO_EINVAL, "NULL argument");
     if (s->frozen) return fail(SMMO_ESTATE, "schema is frozen: a heap was created from it");
     if (s->nclasses >= SMMO_MAX_CLASSES) return fail(SMMO_ENOMEM, "too many classes");
+    if (flags & ~SMMO_CLASS_ABSTRACT) return fail(SMMO_EINVAL, "unknown class flags");
+    if (parent != SMMO_NO_PARENT && parent >= s->nclasses) return fail(SMMO_EINVAL, "parent class id out of range");
     const size_t nl = strlen(name);
     if (nl == 0 || nl > 31) return fail(SMMO_EINVAL, "class name must have 1..31 characters");
     for (uint32_t c = 0; c < s->nclasses; ++c)
         if (strcmp(s->c[c].name, name) == 0) return fail(SMMO_EINVAL, "duplicate class name");
-    if (nfields == 0 || nfields > SMMO_MAX_FIELDS) return fail(SMMO_EINVAL, "bad field count");
+    // the inherited fields first (same order, hence the same offsets), then the new ones
+    smmo_field_desc all[SMMO_MAX_FIELDS];
+    uint32_t ninh = 0;
+    if (parent != SMMO_NO_PARENT) {
+        const smmo_class_info &pc = s->c[parent];
+        for (uint32_t j = 0; j < pc.nfields; ++j)
+            all[ninh++] = smmo_field_desc{pc.f[j].name, pc.f[j].dtype, pc.f[j].count};
+    }
+    if (nfields > SMMO_MAX_FIELDS - ninh) return fail(SMMO_EINVAL, "bad field count");
+    for (uint32_t j = 0; j < nfields; ++j) all[ninh + j] = fields[j];
+    nfields += ninh;
+    if (nfields == 0) return fail(SMMO_EINVAL, "bad field count");
     smmo_class_info ci{};
     memcpy(ci.name, name, nl + 1);
     ci.nfields = nfields;
+    ci.parent = parent;
+    ci.flags = flags;
     uint32_t cur = 0, arrays = 0;
     for (uint32_t j = 0; j < nfields; ++j) {
-        const smmo_field_desc &fd = fields[j];
+        const smmo_field_desc &fd = all[j];
         if (!fd.name) return fail(SMMO_EINVAL, "field name is NULL");
         const size_t fl = strlen(fd.name);
         if (fl == 0 || fl > 31) return fail(SMMO_EINVAL, "field name must have 1..31 characters");
@@ -736,6 +770,14 @@ smmo_status smmo_define_class(smmo_schema *s, const char *name, const smmo_field
     ci.data_bytes = (uint32_t)align256(cur);
     s->c[s->nclasses] = ci;
     *class_id = s->nclasses++;
+    return SMMO_OK;
+}
+
+smmo_status smmo_class_is_a(const smmo_schema *s, uint32_t cls, uint32_t ancestor, uint32_t *out)
+{
+    if (!s || !out) return fail(SMMO_EINVAL, "NULL argument");
+    if (cls >= s->nclasses || ancestor >= s->nclasses) return fail(SMMO_EINVAL, "class id out of range");
+    *out = (smmo::class_family(s, ancestor) >> cls) & 1u;
     return SMMO_OK;
 }
 
@@ -873,6 +915,7 @@ smmo_status smmo_parallel_new(smmo_heap *h, uint32_t class_id, uint32_t n, const
 {
     smmo_status s = check_class(h, class_id);
     if (s) return s;
+    if (class_abstract(h->schema, class_id)) return fail(SMMO_EINVAL, "class is abstract");
     if (ninit && !init) return fail(SMMO_EINVAL, "init is NULL");
     if (n == 0) return SMMO_OK;
     if ((uint64_t)n > 64ull * h->v.M) return fail(SMMO_ENOMEM, "more objects than the heap has slots");
@@ -919,10 +962,15 @@ smmo_status smmo_parallel_do(smmo_heap *h, uint32_t class_id, uint32_t method_id
     if (args_bytes != m.args_bytes || (m.args_bytes && !args))
         return fail(SMMO_EINVAL, std::string("method '") + m.name + "': wrong argument size");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    h->cur_method = method_id;
-    s = m.launch(h, class_id, args, st);
-    h->cur_method = 0xFFFFFFFFu;
-    if (s) return s;
+    // the class and its descendants: one launch per concrete class
+    const uint32_t fam = class_family(h->schema, class_id);
+    for (uint32_t c = 0; c < h->schema->nclasses; ++c) {
+        if (!((fam >> c) & 1) || class_abstract(h->schema, c)) continue;
+        h->cur_method = method_id;
+        s = m.launch(h, c, args, st);
+        h->cur_method = 0xFFFFFFFFu;
+        if (s) return s;
+    }
     h->last = st;
     return SMMO_OK;
 }

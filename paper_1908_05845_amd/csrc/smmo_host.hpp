@@ -25,6 +25,8 @@ struct smmo_class_info {
     uint32_t narrays;
     smmo_field_info f[SMMO_MAX_FIELDS];
     uint32_t data_bytes;
+    uint32_t parent = SMMO_NO_PARENT;
+    uint32_t flags = 0;               // SMMO_CLASS_ABSTRACT
 };
 
 struct smmo_schema {
@@ -32,6 +34,12 @@ struct smmo_schema {
     smmo_class_info c[SMMO_MAX_CLASSES];
     bool frozen = false;
 };
+
+namespace smmo {
+// bit c set for every class c that is cls or derives from it
+uint32_t class_family(const smmo_schema *s, uint32_t cls);
+inline bool class_abstract(const smmo_schema *s, uint32_t cls) { return (s->c[cls].flags & SMMO_CLASS_ABSTRACT) != 0; }
+} // namespace smmo
 
 enum RState : int { R_DIRTY = 0, R_VALID = 1, R_SPLIT = 2 };   // R_SPLIT: valid, with the packing plan
 

@@ -130,6 +130,7 @@ _lib = None
 #: every symbol include/smmo.h declares
 EXPORTS = [
     "smmo_config_default", "smmo_schema_create", "smmo_schema_free", "smmo_define_class",
+    "smmo_define_subclass", "smmo_class_is_a",
     "smmo_field_id", "smmo_block_bytes", "smmo_heap_bytes", "smmo_alloc_heap", "smmo_heap_free",
     "smmo_parallel_new", "smmo_parallel_do", "smmo_destroy", "smmo_gather_soa", "smmo_sync",
     "smmo_heap_stats", "smmo_check_invariants", "smmo_clear_error", "smmo_heap_info",
@@ -153,6 +154,8 @@ def load_library(path: str = LIB_PATH):
             "smmo_schema_create": (S, [P]),
             "smmo_schema_free": (S, [P]),
             "smmo_define_class": (S, [P, C.c_char_p, P, U32, P]),
+            "smmo_define_subclass": (S, [P, C.c_char_p, U32, U32, P, U32, P]),
+            "smmo_class_is_a": (S, [P, U32, U32, P]),
             "smmo_field_id": (S, [P, U32, C.c_char_p, P]),
             "smmo_block_bytes": (S, [P, P]),
             "smmo_heap_bytes": (S, [P, U64, P]),
@@ -242,6 +245,33 @@ def smmo_define_class(schema, name: str, fields) -> int:
     cid = C.c_uint32()
     _check(lib, lib.smmo_define_class(schema, name.encode(), arr, len(fields), C.byref(cid)))
     return cid.value
+
+
+SMMO_NO_PARENT = 0xFFFFFFFF
+SMMO_CLASS_ABSTRACT = 1
+
+
+def smmo_define_subclass(schema, name: str, parent: int, fields=(), abstract: bool = False) -> int:
+    """A class deriving from `parent` (SMMO_NO_PARENT for a root): the
+    parent's fields, then `fields` (sequence of (name, dtype, count))."""
+    lib = load_library()
+    arr = (smmo_field_desc * max(1, len(fields)))()
+    keep = []
+    for i, (fname, dt, cnt) in enumerate(fields):
+        b = fname.encode()
+        keep.append(b)
+        arr[i] = smmo_field_desc(b, DTYPE_NAMES.get(dt, dt) if isinstance(dt, str) else dt, cnt)
+    cid = C.c_uint32()
+    _check(lib, lib.smmo_define_subclass(schema, name.encode(), parent, SMMO_CLASS_ABSTRACT if abstract else 0,
+                                         arr if fields else None, len(fields), C.byref(cid)))
+    return cid.value
+
+
+def smmo_class_is_a(schema, cls: int, ancestor: int) -> bool:
+    lib = load_library()
+    out = C.c_uint32()
+    _check(lib, lib.smmo_class_is_a(schema, cls, ancestor, C.byref(out)))
+    return bool(out.value)
 
 
 def smmo_field_id(schema, class_id: int, name: str) -> int:
@@ -409,7 +439,9 @@ _TORCH_DT = {U8: "uint8", I32: "int32", U32: "int32", F32: "float32", HANDLE: "i
 class Heap:
     """A schema plus a heap in a torch-allocated device buffer.
 
-    classes: {class name: [(field, dtype, count), ...]} in definition order.
+    classes: {class name: [(field, dtype, count), ...]} in definition order,
+    or {class name: {"parent": name or None, "abstract": bool, "fields": [...]}}
+    for a class in a hierarchy (its field list starts with the parent's).
     Give either `blocks` (heap size in blocks) or `nbytes`.
     """
 
@@ -421,11 +453,23 @@ class Heap:
         self.schema = smmo_schema_create()
         self.cls = {}
         self.fields = {}
-        for cname, flds in classes.items():
-            cid = smmo_define_class(self.schema, cname, flds)
+        self._field_list = {}
+        for cname, spec in classes.items():
+            if isinstance(spec, dict):
+                parent = spec.get("parent")
+                flds = list(spec.get("fields", ()))
+                cid = smmo_define_subclass(self.schema, cname, SMMO_NO_PARENT if parent is None else self.cls[parent],
+                                           flds, bool(spec.get("abstract", False)))
+                inherited = [] if parent is None else self._field_list[parent]
+            else:
+                flds = list(spec)
+                cid = smmo_define_class(self.schema, cname, flds)
+                inherited = []
             self.cls[cname] = cid
+            full = inherited + flds
+            self._field_list[cname] = full
             self.fields[cname] = {f[0]: (i, DTYPE_NAMES.get(f[1], f[1]) if isinstance(f[1], str) else f[1], f[2])
-                                  for i, f in enumerate(flds)}
+                                  for i, f in enumerate(full)}
         if nbytes is None:
             nbytes = smmo_heap_bytes(self.schema, blocks)
         self.nbytes = nbytes

@@ -62,6 +62,38 @@ def test_schema_and_layout(lib):
     smmo.smmo_schema_free(s)
 
 
+def test_subclass_schema(lib):
+    """Single inheritance: a subclass's field list is its parent's (same ids)
+    followed by its own; is_a follows the parent chain; bad parents, flags,
+    redefined inherited fields are refused."""
+    s = smmo.smmo_schema_create()
+    base = smmo.smmo_define_subclass(s, "NodeBase", smmo.SMMO_NO_PARENT,
+                                     [("x", "f32", 1), ("springs", "handle", 3), ("n", "i32", 1)], abstract=True)
+    anchor = smmo.smmo_define_subclass(s, "AnchorNode", base)
+    node = smmo.smmo_define_subclass(s, "Node", base, [("vx", "f32", 1)])
+    leaf = smmo.smmo_define_subclass(s, "HeavyNode", node, [("m", "f32", 1)])
+    other = smmo.smmo_define_class(s, "Spring", [("a", "handle", 1)])
+    assert (base, anchor, node, leaf, other) == (0, 1, 2, 3, 4)
+    assert smmo.smmo_field_id(s, anchor, "springs") == 1 and smmo.smmo_field_id(s, node, "vx") == 3
+    assert smmo.smmo_field_id(s, leaf, "n") == 2 and smmo.smmo_field_id(s, leaf, "m") == 4
+    # largest class: HeavyNode = x, 3 springs, n, vx, m = 7 arrays of 256 B
+    assert smmo.smmo_block_bytes(s) == 7 * 256
+    isa = lambda c, a: smmo.smmo_class_is_a(s, c, a)
+    assert isa(leaf, node) and isa(leaf, base) and isa(anchor, base) and isa(base, base)
+    assert not isa(node, leaf) and not isa(anchor, node) and not isa(other, base) and not isa(base, anchor)
+    with pytest.raises(smmo.SmmoError):
+        smmo.smmo_define_subclass(s, "Bad", 17)
+    with pytest.raises(smmo.SmmoError) as e:
+        smmo.smmo_define_subclass(s, "Dup", node, [("x", "f32", 1)])
+    assert "duplicate field" in str(e.value)
+    with pytest.raises(smmo.SmmoError):
+        smmo.smmo_define_subclass(s, "Empty", smmo.SMMO_NO_PARENT, [])
+    lib_ = smmo.load_library()
+    cid = smmo.C.c_uint32()
+    assert lib_.smmo_define_subclass(s, b"Flags", base, 2, None, 0, smmo.C.byref(cid)) == smmo.SMMO_EINVAL
+    smmo.smmo_schema_free(s)
+
+
 @pytest.mark.parametrize("fields,msg", [
     ([], "bad field count"),
     ([("x", "f32", 0)], "count 0"),
