@@ -216,6 +216,54 @@ typedef struct {
     const uint32_t *cells;
 } smmo_wator_args;
 
+/* ---- structure (thesis Ch.7 "structure": fracture of a spring mesh) -------
+ * Class hierarchy (smmo_define_subclass; inherited fields first):
+ * NodeBase (abstract) {x, y: F32, springs: HANDLE x 3, nspr: I32, dist: I32,
+ *        id: I32}; springs[q] = spring handle | (1 << 31 if this node is the
+ *        spring's p2), SMMO_NULL for an empty slot; nspr = occupied slots
+ * AnchorNode     : NodeBase {}                 fixed
+ * AnchorPullNode : NodeBase {vx, vy: F32}      moves at a constant velocity
+ * Node           : NodeBase {vx, vy, m: F32}   moves under the spring forces
+ * Spring {p1, p2: HANDLE (any NodeBase class), k, L0, maxf, fx, fy: F32,
+ *        s1, s2: U8 (slot of the spring in p1 / p2), del: U8, id: I32}
+ * Unlinking a spring from a node empties the node's slot and decrements
+ * nspr; the unlink that takes nspr to 0 deletes the node.
+ * "structure.pull"        on AnchorPullNode: x += vx dt, y += vy dt.
+ * "structure.force"       on Spring: d = x_p2 - x_p1, l = |d|; stretched iff
+ *        l > L0 and F = k (l - L0) (both in float32: l2 = fma(dx, dx, dy*dy),
+ *        l = sqrt(l2) correctly rounded, each operation rounded); if
+ *        stretched and F > maxf the spring unlinks itself from p1 and p2 and
+ *        deletes itself; else (fx, fy) = k (l - L0) d / l if stretched, (0, 0)
+ *        if slack: the force on p1 (p2 receives the negative).
+ * "structure.node_update" on Node: F = sum over the occupied slots, in slot
+ *        order, of +-(fx, fy); v += F / m dt; x += v dt.
+ * "structure.bfs_init"    on NodeBase (all node classes): dist = 0 for
+ *        AnchorNode objects, SMMO_STRUCTURE_FAR for the others.
+ * "structure.bfs_visit"   on NodeBase: a node with dist == distance sets
+ *        *flag = 1 and gives each neighbour with dist SMMO_STRUCTURE_FAR the
+ *        distance distance + 1.
+ * "structure.bfs_mark"    on NodeBase: a node with dist SMMO_STRUCTURE_FAR
+ *        sets del on its springs.
+ * "structure.bfs_delete"  on Spring: a spring with del set unlinks itself
+ *        from p1 and p2 and deletes itself.
+ * "structure.link"        on Spring: writes the spring's handle into
+ *        p1.springs[s1] and (handle | 1 << 31) into p2.springs[s2]; builds the
+ *        topology after parallel_new of the nodes (springs empty, nspr set)
+ *        and the springs.
+ * A do-all on NodeBase runs once per concrete node class; the methods bind
+ * the node fields on nodebase_class, whose offsets every node class shares. */
+#define SMMO_STRUCTURE_FAR 0x7FFFFFFF
+typedef struct {
+    uint32_t nodebase_class;
+    uint32_t anchor_class;
+    uint32_t spring_class;
+    int32_t distance;            /* bfs_visit: the frontier's distance */
+    float dt;                    /* pull, node_update */
+    uint32_t reserved;
+    uint32_t *flag;              /* bfs_visit: device word, set to 1 when the
+                                    frontier is not empty; the caller clears it */
+} smmo_structure_args;
+
 #ifdef __cplusplus
 }
 #endif

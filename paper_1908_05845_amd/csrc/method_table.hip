@@ -25,6 +25,16 @@ smmo_status launch_spring_force(smmo_heap *h, uint32_t cls, const void *args, hi
 smmo_status launch_spring_node_update(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_spring_link(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 
+// launchers defined in structure.hip
+smmo_status launch_structure_pull(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_structure_force(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_structure_node_update(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_structure_bfs_init(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_structure_bfs_visit(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_structure_bfs_mark(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_structure_bfs_delete(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_structure_link(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+
 // launchers defined in adjoint.hip
 smmo_status launch_adj_record(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_adj_save(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
@@ -74,6 +84,14 @@ const MethodEntry kMethods[] = {
     {"wator.shark_update", sizeof(smmo_wator_args), launch_wator_shark_update},
     {"wator.cell_link", sizeof(smmo_wator_args), launch_wator_cell_link},
     {"wator.link", sizeof(smmo_wator_args), launch_wator_link},
+    {"structure.pull", sizeof(smmo_structure_args), launch_structure_pull},
+    {"structure.force", sizeof(smmo_structure_args), launch_structure_force},
+    {"structure.node_update", sizeof(smmo_structure_args), launch_structure_node_update},
+    {"structure.bfs_init", sizeof(smmo_structure_args), launch_structure_bfs_init},
+    {"structure.bfs_visit", sizeof(smmo_structure_args), launch_structure_bfs_visit},
+    {"structure.bfs_mark", sizeof(smmo_structure_args), launch_structure_bfs_mark},
+    {"structure.bfs_delete", sizeof(smmo_structure_args), launch_structure_bfs_delete},
+    {"structure.link", sizeof(smmo_structure_args), launch_structure_link},
 };
 } // namespace
 

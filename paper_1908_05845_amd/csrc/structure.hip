@@ -1,0 +1,383 @@
+// structure (Ch.7 "structure"): a spring mesh with anchor, pull and free
+// nodes that breaks under load; disconnected parts are found with a BFS and
+// deleted (field contracts in include/smmo_methods.h).
+//
+// The node classes derive from an abstract NodeBase whose fields sit at the
+// same offsets in every node class, so a spring reads either endpoint through
+// one set of offsets whatever the endpoint's class, and a do-all on NodeBase
+// is one launch per concrete node class (the library dispatches it).  The
+// runtime type test of the thesis (cast<T>, from the object's address) is the
+// block's type id here; since every launch covers one concrete class, the
+// test on `this` is settled on the host at launch.
+//
+// Unlinking a spring decrements its endpoints' spring counts with an atomic,
+// because several springs of one node may unlink in the same launch; the
+// unlink that takes a count to zero deletes that node, which may belong to
+// any node class: such deletions are grouped by block and released with the
+// class read from the block's type id.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "../../include/smmo_methods.h"
+#include "method_common.hpp"
+
+using namespace smmo;
+
+namespace {
+
+constexpr uint32_t kP2 = 0x80000000u;        // tag of a slot whose node is the spring's p2
+constexpr int32_t kFar = SMMO_STRUCTURE_FAR;
+
+struct StructK {
+    uint32_t cls, spring_cls;
+    // NodeBase fields (the same offsets in every node class)
+    uint32_t n_x, n_y, n_spr, n_spr_stride, n_nspr, n_dist;
+    // fields of the launched node class, where it has them
+    uint32_t n_vx, n_vy, n_m;
+    // Spring fields
+    uint32_t s_p1, s_p2, s_k, s_L0, s_maxf, s_fx, s_fy, s_s1, s_s2, s_del;
+    float dt;
+    int32_t distance;
+    uint32_t anchor;          // bfs_init: the launched class is AnchorNode (or derives from it)
+    uint32_t *flag;
+};
+
+__device__ __forceinline__ bool st_valid(const HeapView &h, uint32_t handle)
+{
+    if (handle != kNull && (handle >> 6) < h.M) return true;
+    raise_error(h, ERR_BADHANDLE);
+    return false;
+}
+
+// Deletes the objects named by `handle` on the lanes with want, of whatever
+// class each block holds (the block's type id).  Converged call.  Lanes
+// naming slots of one block are released together, one block per round.
+__device__ __forceinline__ void wave_delete_any(const HeapView &h, uint32_t handle, bool want)
+{
+    const uint32_t lane = lane_id();
+    uint64_t pending = __ballot(want);
+    while (pending) {
+        const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)pending) - 1);
+        const uint32_t b = (uint32_t)__shfl((int)(handle >> 6), (int)leader);
+        const bool mine = ((pending >> lane) & 1) && (handle >> 6) == b;
+        const uint64_t slots = wave_or64(mine ? 1ull << (handle & 63) : 0ull);
+        pending &= ~__ballot(mine);
+        OpQueue q;
+        q.reset();
+        if (lane == leader) {
+            const uint32_t cls = h.type[b];
+            if (cls < h.nclasses) release_slots(h, cls, b, slots, q);
+            else raise_error(h, ERR_BADHANDLE);
+        }
+        run_ops_wave(h, q);
+    }
+}
+
+// Node::remove_spring for the spring in slot q of node `node`; returns true
+// if it was the node's last spring (the caller deletes the node)
+__device__ __forceinline__ bool unlink(const HeapView &h, const StructK &p, uint32_t node, uint32_t q)
+{
+    if (q >= 3) {
+        raise_error(h, ERR_BADHANDLE);
+        return false;
+    }
+    fref<uint32_t>(h, node, p.n_spr + q * p.n_spr_stride) = kNull;
+    const int32_t prev = __hip_atomic_fetch_add(&fref<int32_t>(h, node, p.n_nspr), -1, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (prev <= 0) raise_error(h, ERR_INTERNAL);
+    return prev == 1;
+}
+
+// a spring of this wavefront's block unlinks from both endpoints (want) and
+// deletes itself, deleting the endpoints whose last spring it was
+__device__ __forceinline__ void unlink_and_delete(const HeapView &h, const StructK &p, uint32_t bid, uint32_t s,
+                                                  uint32_t a, uint32_t b, bool want)
+{
+    bool last_a = false, last_b = false;
+    if (want) {
+        last_a = unlink(h, p, a, farr<uint8_t>(h, bid, p.s_s1)[s]);
+        last_b = unlink(h, p, b, farr<uint8_t>(h, bid, p.s_s2)[s]);
+    }
+    wave_delete_any(h, a, last_a);
+    wave_delete_any(h, b, last_b);
+    wave_release_own_block(h, p.spring_cls, bid, __ballot(want));
+}
+
+// AnchorPullNode::pull
+__global__ __launch_bounds__(1024) void k_st_pull(HeapView h, StructK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if (!((bm >> s) & 1)) return;
+        farr<float>(h, bid, p.n_x)[s] += farr<float>(h, bid, p.n_vx)[s] * p.dt;
+        farr<float>(h, bid, p.n_y)[s] += farr<float>(h, bid, p.n_vy)[s] * p.dt;
+    });
+}
+
+// Spring::force: tension-only Hooke's law; a spring pulled harder than its
+// limit unlinks itself and is deleted.  The stretch and break decisions use
+// one fixed float32 operation order (no contraction).
+__global__ __launch_bounds__(1024) void k_st_force(HeapView h, StructK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
+#pragma clang fp contract(off)
+        const uint32_t s = lane_id();
+        bool live = (bm >> s) & 1;
+        uint32_t a = 0, b = 0;
+        float fx = 0.f, fy = 0.f;
+        bool brk = false;
+        if (live) {
+            a = farr<uint32_t>(h, bid, p.s_p1)[s];
+            b = farr<uint32_t>(h, bid, p.s_p2)[s];
+            live = st_valid(h, a) && st_valid(h, b);
+        }
+        if (live) {
+            const float dx = fref<float>(h, b, p.n_x) - fref<float>(h, a, p.n_x);
+            const float dy = fref<float>(h, b, p.n_y) - fref<float>(h, a, p.n_y);
+            const float k = farr<float>(h, bid, p.s_k)[s], L0 = farr<float>(h, bid, p.s_L0)[s];
+            const float dy2 = dy * dy;
+            const float l = __builtin_sqrtf(__builtin_fmaf(dx, dx, dy2));
+            const float d = l - L0;
+            const float F = k * d;
+            const bool stretched = l > L0;
+            brk = stretched && F > farr<float>(h, bid, p.s_maxf)[s];
+            if (stretched && !brk) {
+                const float c = k * d / l;
+                fx = c * dx;
+                fy = c * dy;
+            }
+        }
+        // full-width stores: dead, broken and slack slots get 0
+        farr<float>(h, bid, p.s_fx)[s] = fx;
+        farr<float>(h, bid, p.s_fy)[s] = fy;
+        unlink_and_delete(h, p, bid, s, a, b, brk);
+    });
+}
+
+// Node::update: the attached springs' forces in slot order, then v and x
+__global__ __launch_bounds__(1024) void k_st_node_update(HeapView h, StructK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if (!((bm >> s) & 1)) return;
+        float Fx = 0.f, Fy = 0.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const uint32_t hs = farr<uint32_t>(h, bid, p.n_spr + q * p.n_spr_stride)[s];
+            if (hs == kNull) continue;
+            const uint32_t sp = hs & ~kP2;
+            if (!st_valid(h, sp)) continue;
+            const float fx = fref<float>(h, sp, p.s_fx), fy = fref<float>(h, sp, p.s_fy);
+            if (hs & kP2) {
+                Fx -= fx;
+                Fy -= fy;
+            } else {
+                Fx += fx;
+                Fy += fy;
+            }
+        }
+        const float m = farr<float>(h, bid, p.n_m)[s];
+        float &vx = farr<float>(h, bid, p.n_vx)[s];
+        float &vy = farr<float>(h, bid, p.n_vy)[s];
+        vx += Fx / m * p.dt;
+        vy += Fy / m * p.dt;
+        farr<float>(h, bid, p.n_x)[s] += vx * p.dt;
+        farr<float>(h, bid, p.n_y)[s] += vy * p.dt;
+    });
+}
+
+// NodeBase::initialize_frontier
+__global__ __launch_bounds__(1024) void k_st_bfs_init(HeapView h, StructK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if ((bm >> s) & 1) farr<int32_t>(h, bid, p.n_dist)[s] = p.anchor ? 0 : kFar;
+    });
+}
+
+// NodeBase::visit(distance).  Concurrent writers of a neighbour's distance
+// all write distance + 1, and no node of this level's frontier changes.
+__global__ __launch_bounds__(1024) void k_st_bfs_visit(HeapView h, StructK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        const bool front = ((bm >> s) & 1) && farr<int32_t>(h, bid, p.n_dist)[s] == p.distance;
+        if (__ballot(front) && s == (uint32_t)(__ffsll((unsigned long long)__ballot(front)) - 1))
+            __hip_atomic_store(p.flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!front) return;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const uint32_t hs = farr<uint32_t>(h, bid, p.n_spr + q * p.n_spr_stride)[s];
+            if (hs == kNull) continue;
+            const uint32_t sp = hs & ~kP2;
+            if (!st_valid(h, sp)) continue;
+            const uint32_t o = fref<uint32_t>(h, sp, (hs & kP2) ? p.s_p1 : p.s_p2);
+            if (!st_valid(h, o)) continue;
+            int32_t &d = fref<int32_t>(h, o, p.n_dist);
+            if (d == kFar) d = p.distance + 1;
+        }
+    });
+}
+
+// NodeBase::delete_node: an unvisited node flags its springs
+__global__ __launch_bounds__(1024) void k_st_bfs_mark(HeapView h, StructK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if (!((bm >> s) & 1) || farr<int32_t>(h, bid, p.n_dist)[s] != kFar) return;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const uint32_t hs = farr<uint32_t>(h, bid, p.n_spr + q * p.n_spr_stride)[s];
+            if (hs != kNull && st_valid(h, hs & ~kP2)) fref<uint8_t>(h, hs & ~kP2, p.s_del) = 1;
+        }
+    });
+}
+
+// Spring::delete_spring
+__global__ __launch_bounds__(1024) void k_st_bfs_delete(HeapView h, StructK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        bool del = ((bm >> s) & 1) && farr<uint8_t>(h, bid, p.s_del)[s];
+        uint32_t a = 0, b = 0;
+        if (del) {
+            a = farr<uint32_t>(h, bid, p.s_p1)[s];
+            b = farr<uint32_t>(h, bid, p.s_p2)[s];
+            del = st_valid(h, a) && st_valid(h, b);
+        }
+        unlink_and_delete(h, p, bid, s, a, b, del);
+    });
+}
+
+// Spring::link: register the spring in its endpoints' slots
+__global__ __launch_bounds__(1024) void k_st_link(HeapView h, StructK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        if (!((bm >> s) & 1)) return;
+        const uint32_t a = farr<uint32_t>(h, bid, p.s_p1)[s], b = farr<uint32_t>(h, bid, p.s_p2)[s];
+        const uint32_t q1 = farr<uint8_t>(h, bid, p.s_s1)[s], q2 = farr<uint8_t>(h, bid, p.s_s2)[s];
+        if (!st_valid(h, a) || !st_valid(h, b)) return;
+        if (q1 >= 3 || q2 >= 3) {
+            raise_error(h, ERR_BADHANDLE);
+            return;
+        }
+        const uint32_t me = (bid << 6) | s;
+        fref<uint32_t>(h, a, p.n_spr + q1 * p.n_spr_stride) = me;
+        fref<uint32_t>(h, b, p.n_spr + q2 * p.n_spr_stride) = me | kP2;
+    });
+}
+
+enum Which { W_PULL, W_FORCE, W_NODE, W_BFS_INIT, W_BFS_VISIT, W_BFS_MARK, W_BFS_DELETE, W_LINK };
+
+smmo_status bind_structure(smmo_heap *h, uint32_t cls, const smmo_structure_args &a, int which, StructK &k)
+{
+    const smmo_schema *sc = h->schema;
+    const uint32_t nc = sc->nclasses;
+    if (a.nodebase_class >= nc || a.anchor_class >= nc || a.spring_class >= nc)
+        return fail(SMMO_EINVAL, "structure: class id out of range");
+    const uint32_t nodes = class_family(sc, a.nodebase_class);
+    if (!((nodes >> a.anchor_class) & 1) || ((nodes >> a.spring_class) & 1))
+        return fail(SMMO_EINVAL, "structure: anchor class must derive from the node base, the spring class not");
+    const bool on_spring = which == W_FORCE || which == W_BFS_DELETE || which == W_LINK;
+    if (on_spring ? cls != a.spring_class : !((nodes >> cls) & 1))
+        return fail(SMMO_EINVAL, "structure: method runs on a different class");
+    memset(&k, 0, sizeof k);
+    k.cls = cls;
+    k.spring_cls = a.spring_class;
+    const uint32_t nb = a.nodebase_class;
+    BIND(nb, "x", SMMO_F32, 1, &k.n_x, nullptr);
+    BIND(nb, "y", SMMO_F32, 1, &k.n_y, nullptr);
+    BIND(nb, "springs", SMMO_HANDLE, 3, &k.n_spr, &k.n_spr_stride);
+    BIND(nb, "nspr", SMMO_I32, 1, &k.n_nspr, nullptr);
+    BIND(nb, "dist", SMMO_I32, 1, &k.n_dist, nullptr);
+    if (which == W_PULL || which == W_NODE) {
+        BIND(cls, "vx", SMMO_F32, 1, &k.n_vx, nullptr);
+        BIND(cls, "vy", SMMO_F32, 1, &k.n_vy, nullptr);
+    }
+    if (which == W_NODE) BIND(cls, "m", SMMO_F32, 1, &k.n_m, nullptr);
+    const uint32_t sp = a.spring_class;
+    BIND(sp, "p1", SMMO_HANDLE, 1, &k.s_p1, nullptr);
+    BIND(sp, "p2", SMMO_HANDLE, 1, &k.s_p2, nullptr);
+    BIND(sp, "k", SMMO_F32, 1, &k.s_k, nullptr);
+    BIND(sp, "L0", SMMO_F32, 1, &k.s_L0, nullptr);
+    BIND(sp, "maxf", SMMO_F32, 1, &k.s_maxf, nullptr);
+    BIND(sp, "fx", SMMO_F32, 1, &k.s_fx, nullptr);
+    BIND(sp, "fy", SMMO_F32, 1, &k.s_fy, nullptr);
+    BIND(sp, "s1", SMMO_U8, 1, &k.s_s1, nullptr);
+    BIND(sp, "s2", SMMO_U8, 1, &k.s_s2, nullptr);
+    BIND(sp, "del", SMMO_U8, 1, &k.s_del, nullptr);
+    // the node fields every class of the family shares (same offsets)
+    for (uint32_t c = 0; c < nc; ++c) {
+        if (!((nodes >> c) & 1)) continue;
+        uint32_t off = 0, stride = 0;
+        const char *names[5] = {"x", "y", "springs", "nspr", "dist"};
+        const uint32_t want[5] = {k.n_x, k.n_y, k.n_spr, k.n_nspr, k.n_dist};
+        for (int f = 0; f < 5; ++f) {
+            smmo_status s = bind_field(sc, c, names[f], f == 2 ? SMMO_HANDLE : (f < 2 ? SMMO_F32 : SMMO_I32),
+                                       f == 2 ? 3 : 1, &off, f == 2 ? &stride : nullptr);
+            if (s) return s;
+            if (off != want[f]) return fail(SMMO_EINVAL, "structure: node classes disagree on a NodeBase field");
+        }
+    }
+    uint32_t is_anchor = 0;
+    if (smmo_class_is_a(sc, cls, a.anchor_class, &is_anchor)) return fail(SMMO_EINVAL, "structure: class relation");
+    k.anchor = is_anchor;
+    return SMMO_OK;
+}
+
+template <int W>
+smmo_status launch_structure(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_structure_args a;
+    memcpy(&a, args, sizeof a);
+    if (W == W_BFS_VISIT && !a.flag) return fail(SMMO_EINVAL, "structure.bfs_visit: flag is NULL");
+    if (!(a.dt == a.dt)) return fail(SMMO_EINVAL, "structure: NaN dt");
+    // the per-call fields do not take part in the binding
+    smmo_structure_args key = a;
+    key.distance = 0;
+    key.dt = 0.f;
+    key.flag = nullptr;
+    StructK k;
+    smmo_status s = cached_bind(h, (const void *)&launch_structure<W>, cls, key, k,
+                                [&] { return bind_structure(h, cls, a, W, k); });
+    if (s) return s;
+    k.dt = a.dt;
+    k.distance = a.distance;
+    k.flag = a.flag;
+    if ((s = ensure_enumerated(h, cls, false, st))) return s;
+    const LaunchShape ls = method_shape(h, cls);
+    switch (W) {
+    case W_PULL: hipLaunchKernelGGL(k_st_pull, ls.grid, ls.block, 0, st, h->v, k); break;
+    case W_FORCE: hipLaunchKernelGGL(k_st_force, ls.grid, ls.block, 0, st, h->v, k); break;
+    case W_NODE: hipLaunchKernelGGL(k_st_node_update, ls.grid, ls.block, 0, st, h->v, k); break;
+    case W_BFS_INIT: hipLaunchKernelGGL(k_st_bfs_init, ls.grid, ls.block, 0, st, h->v, k); break;
+    case W_BFS_VISIT: hipLaunchKernelGGL(k_st_bfs_visit, ls.grid, ls.block, 0, st, h->v, k); break;
+    case W_BFS_MARK: hipLaunchKernelGGL(k_st_bfs_mark, ls.grid, ls.block, 0, st, h->v, k); break;
+    case W_BFS_DELETE: hipLaunchKernelGGL(k_st_bfs_delete, ls.grid, ls.block, 0, st, h->v, k); break;
+    default: hipLaunchKernelGGL(k_st_link, ls.grid, ls.block, 0, st, h->v, k); break;
+    }
+    return launched("structure kernel");
+}
+
+} // namespace
+
+namespace smmo {
+smmo_status launch_structure_pull(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_structure<W_PULL>(h, c, a, s); }
+smmo_status launch_structure_force(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_structure<W_FORCE>(h, c, a, s); }
+smmo_status launch_structure_node_update(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_structure<W_NODE>(h, c, a, s); }
+smmo_status launch_structure_bfs_init(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_structure<W_BFS_INIT>(h, c, a, s); }
+smmo_status launch_structure_bfs_visit(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_structure<W_BFS_VISIT>(h, c, a, s); }
+smmo_status launch_structure_bfs_mark(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_structure<W_BFS_MARK>(h, c, a, s); }
+smmo_status launch_structure_bfs_delete(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_structure<W_BFS_DELETE>(h, c, a, s); }
+smmo_status launch_structure_link(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_structure<W_LINK>(h, c, a, s); }
+} // namespace smmo

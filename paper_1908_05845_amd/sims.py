@@ -36,6 +36,20 @@ SPRING_CLASSES = {
 }
 
 
+STRUCTURE_CLASSES = {
+    "NodeBase": {"parent": None, "abstract": True,
+                 "fields": [("x", "f32", 1), ("y", "f32", 1), ("springs", "handle", 3), ("nspr", "i32", 1),
+                            ("dist", "i32", 1), ("id", "i32", 1)]},
+    "AnchorNode": {"parent": "NodeBase"},
+    "AnchorPullNode": {"parent": "NodeBase", "fields": [("vx", "f32", 1), ("vy", "f32", 1)]},
+    "Node": {"parent": "NodeBase", "fields": [("vx", "f32", 1), ("vy", "f32", 1), ("m", "f32", 1)]},
+    "Spring": [("p1", "handle", 1), ("p2", "handle", 1), ("k", "f32", 1), ("L0", "f32", 1), ("maxf", "f32", 1),
+               ("fx", "f32", 1), ("fy", "f32", 1), ("s1", "u8", 1), ("s2", "u8", 1), ("del", "u8", 1),
+               ("id", "i32", 1)],
+}
+STRUCTURE_NODE_CLASSES = ("AnchorNode", "AnchorPullNode", "Node")   # node types 0, 1, 2
+
+
 def _blocks(n: int) -> int:
     return (n + 63) // 64
 
@@ -336,3 +350,152 @@ class WatorSim:
             raise RuntimeError("cell agent fields disagree with the agents' positions in %d cells"
                                % int(np.sum(agent != want)))
         return kind, timer, energy, (int(fc.size), int(scl.size))
+
+
+class StructureSim:
+    """The fracture simulation (thesis Ch.7 "structure") on a mesh dict of
+    ``inputs.structure_mesh``: classes NodeBase (abstract), AnchorNode,
+    AnchorPullNode, Node and Spring.  One iteration: AnchorPullNode::pull,
+    `substeps` x (Spring::force, Node::update), then the removal of the nodes
+    no longer connected to an anchor node (a BFS whose levels are launched
+    `bfs_batch` at a time between reads of their frontier flags)."""
+
+    def __init__(self, mesh: dict, dt: float, cfg=None, extra_blocks: int = 16, bfs_batch: int = 8):
+        import torch
+
+        self.torch = torch
+        self.dt = dt
+        self.bfs_batch = bfs_batch
+        ntype = np.asarray(mesh["ntype"], np.int32)
+        N = ntype.size
+        S = int(np.asarray(mesh["p1"]).size)
+        self.N, self.S = N, S
+        per = [int((ntype == t).sum()) for t in range(3)]
+        blocks = sum(_blocks(n) for n in per) + _blocks(S) + extra_blocks
+        self.heap = smmo.Heap(STRUCTURE_CLASSES, blocks=blocks, cfg=cfg)
+        dev = self.heap.buf.device
+        self.dev = dev
+        f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+        i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+        node_h = torch.full((max(N, 1),), -1, dtype=torch.int32, device=dev)
+        self.node_ids = []
+        for t, cname in enumerate(STRUCTURE_NODE_CLASSES):
+            ids = np.flatnonzero(ntype == t)
+            self.node_ids.append(ids)
+            if ids.size == 0:
+                continue
+            vals = dict(x=f32(np.asarray(mesh["x"])[ids]), y=f32(np.asarray(mesh["y"])[ids]),
+                        springs=torch.full((ids.size * 3,), -1, dtype=torch.int32, device=dev),
+                        nspr=i32(np.asarray(mesh["nspr"])[ids]), dist=i32(np.zeros(ids.size)), id=i32(ids))
+            if cname != "AnchorNode":
+                vals["vx"] = f32(np.asarray(mesh["vx"])[ids])
+                vals["vy"] = f32(np.asarray(mesh["vy"])[ids])
+            if cname == "Node":
+                vals["m"] = f32(np.asarray(mesh["m"])[ids])
+            node_h[torch.from_numpy(ids).to(dev)] = self.heap.new(cname, ids.size, **vals)
+        self.node_h = node_h
+        c = self.heap.cls
+        self.flags = torch.zeros(max(bfs_batch, 1), dtype=torch.int32, device=dev)
+        self.args = smmo.smmo_structure_args(c["NodeBase"], c["AnchorNode"], c["Spring"], 0, dt, 0, None)
+        self.m = {n: smmo.smmo_method_id("structure." + n) for n in
+                  ("pull", "force", "node_update", "bfs_init", "bfs_visit", "bfs_mark", "bfs_delete", "link")}
+        if S:
+            p1 = torch.from_numpy(np.asarray(mesh["p1"], np.int64)).to(dev)
+            p2 = torch.from_numpy(np.asarray(mesh["p2"], np.int64)).to(dev)
+            u8 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint8)).to(dev)
+            # "del" is a Python keyword: the field values go in as a dict
+            vals = {"p1": node_h[p1], "p2": node_h[p2], "k": f32(mesh["k"]), "L0": f32(mesh["L0"]),
+                    "maxf": f32(mesh["maxf"]), "s1": u8(mesh["s1"]), "s2": u8(mesh["s2"]),
+                    "del": u8(np.zeros(S)), "id": i32(np.arange(S))}
+            self.heap.new("Spring", S, **vals)
+            self.do("Spring", "link")
+        self.levels = 0
+
+    def do(self, cname: str, method: str, stream=None):
+        smmo.smmo_parallel_do(self.heap.h, self.heap.cls[cname], self.m[method], self.args, stream)
+
+    def pull(self, dt: float, stream=None):
+        self.args.dt = dt
+        self.do("AnchorPullNode", "pull", stream)
+
+    def compute_step(self, stream=None):
+        self.args.dt = self.dt
+        self.do("Spring", "force", stream)
+        self.do("Node", "node_update", stream)
+
+    def remove_disconnected(self, stream=None) -> int:
+        """BFS from the anchor nodes, then deletion of the unvisited nodes and
+        their springs.  Returns the number of visit passes until the first
+        empty frontier (as the thesis's loop runs them)."""
+        self.do("NodeBase", "bfs_init", stream)
+        d = 0
+        while True:
+            self.flags.zero_()
+            for j in range(self.bfs_batch):
+                self.args.distance = d + j
+                self.args.flag = self.flags.data_ptr() + 4 * j
+                self.do("NodeBase", "bfs_visit", stream)
+            self.args.flag = None
+            fl = self.flags.cpu().numpy()
+            empty = np.flatnonzero(fl == 0)
+            if empty.size:
+                self.levels = d + int(empty[0]) + 1
+                break
+            d += self.bfs_batch
+        self.do("NodeBase", "bfs_mark", stream)
+        self.do("Spring", "bfs_delete", stream)
+        return self.levels
+
+    def iterate(self, substeps: int, stream=None) -> int:
+        self.pull(self.dt * substeps, stream)
+        for _ in range(substeps):
+            self.compute_step(stream)
+        return self.remove_disconnected(stream)
+
+    def read(self) -> dict:
+        """Canonical state in the layout of ``inputs.structure_mesh`` (node
+        arrays by node id, spring arrays by spring id, alive flags, slots as
+        spring ids)."""
+        N, S = self.N, self.S
+        gs = self.heap.gather("Spring", ["id", "fx", "fy", "del"])
+        sid = _np(gs["id"])
+        sh = _np(gs["_handle"]).astype(np.int64)
+        out = {"nalive": np.zeros(N, np.uint8), "salive": np.zeros(S, np.uint8)}
+        out["salive"][sid] = 1
+        for key, dt in (("fx", np.float32), ("fy", np.float32), ("sdel", np.uint8)):
+            out[key] = np.zeros(S, dt)
+            out[key][sid] = _np(gs["del" if key == "sdel" else key])
+        hs = np.argsort(sh)
+        sh_sorted, sid_sorted = sh[hs], sid[hs]
+        for key, dt in (("x", np.float32), ("y", np.float32), ("vx", np.float32), ("vy", np.float32),
+                        ("m", np.float32), ("nspr", np.int32), ("dist", np.int32), ("ntype", np.int32)):
+            out[key] = np.zeros(N, dt)
+        out["m"][:] = 1
+        raw = np.full((N, 3), 0xFFFFFFFF, np.int64)
+        for t, cname in enumerate(STRUCTURE_NODE_CLASSES):
+            names = ["id", "x", "y", "springs", "nspr", "dist"] + (["vx", "vy"] if cname != "AnchorNode" else []) \
+                + (["m"] if cname == "Node" else [])
+            g = self.heap.gather(cname, names)
+            ids = _np(g["id"])
+            out["nalive"][ids] = 1
+            out["ntype"][ids] = t
+            for key in names[1:]:
+                if key == "springs":
+                    raw[ids] = _np(g["springs"]).reshape(-1, 3).astype(np.int64) & 0xFFFFFFFF
+                else:
+                    out[key][ids] = _np(g[key])
+        dead = out["nalive"] == 0
+        for t, ids in enumerate(self.node_ids):
+            out["ntype"][ids] = t
+        used = raw != 0xFFFFFFFF
+        hh = raw & 0x7FFFFFFF
+        if sh_sorted.size:
+            pos = np.clip(np.searchsorted(sh_sorted, hh), 0, sh_sorted.size - 1)
+            found = sh_sorted[pos] == hh
+            slot = np.where(used, np.where(found, sid_sorted[pos], -2), -1)
+        else:
+            slot = np.where(used, -2, -1)
+        slot[dead] = -1
+        out["slot"] = slot.astype(np.int32).reshape(-1)
+        out["isp2"] = np.where(used & ~dead[:, None], raw >> 31, 0).astype(np.uint8).reshape(-1)
+        return out

@@ -111,6 +111,14 @@ class smmo_wator_args(C.Structure):
                 ("reserved", C.c_uint32), ("cells", C.c_void_p)]
 
 
+SMMO_STRUCTURE_FAR = 0x7FFFFFFF
+
+
+class smmo_structure_args(C.Structure):
+    _fields_ = [("nodebase_class", C.c_uint32), ("anchor_class", C.c_uint32), ("spring_class", C.c_uint32),
+                ("distance", C.c_int32), ("dt", C.c_float), ("reserved", C.c_uint32), ("flag", C.c_void_p)]
+
+
 class smmo_axpy_args(C.Structure):
     _fields_ = [("a", C.c_float), ("b", C.c_float)]
 
