@@ -637,6 +637,69 @@ def measure_spring_large(torch, tuned):
     return res
 
 
+def measure_structure(torch):
+    """The fracture simulation ("structure"), 1000 x 1000 brick-wall mesh
+    (1M nodes in three node classes, 1.5M springs), stretched uniformly
+    (strain rate 0.5, pull nodes at the same speed) until its springs break
+    (limits at 0.5-1.5 % strain): per iteration one pull, 40 compute steps
+    (Spring::force, Node::update) and the BFS removal of disconnected nodes.
+    One iteration to settle, then six timed (the mesh cracks and falls apart
+    within them) with events around each phase; the BFS's frontier flags are
+    read every 32 levels."""
+    from inputs import structure_mesh
+    from paper_1908_05845_amd import smmo
+    from paper_1908_05845_amd.sims import StructureSim
+
+    print("extras: structure 1000^2 setup", file=sys.stderr, flush=True)
+    W = H = 1000
+    sub = 40
+    mesh = structure_mesh(W, H, pull_speed=0.5, stretch_rate=0.5, break_strain=0.01)
+    sim = StructureSim(mesh, 1e-4, bfs_batch=32)
+    heap = sim.heap
+    c = heap.cls
+    nodes = lambda st: sum(st.live_objects[c[n]] for n in ("AnchorNode", "AnchorPullNode", "Node"))
+    sim.iterate(sub)
+    heap.sync()
+    st0 = heap.stats()
+    n_it = 6
+    t_pull = t_comp = t_bfs = 0.0
+    levels = 0
+    upd = 0.0
+
+    for _ in range(n_it):
+        st = heap.stats()
+        upd += sub * (st.live_objects[c["Spring"]] + st.live_objects[c["Node"]])
+        e = events(torch, 3)
+        e[0].record()
+        sim.pull(sim.dt * sub)
+        e[1].record()
+        for _ in range(sub):
+            sim.compute_step()
+        e[2].record()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        levels += sim.remove_disconnected()
+        torch.cuda.synchronize()
+        t_bfs += (time.perf_counter() - t0) * 1e6
+        t_pull += e[0].elapsed_time(e[1]) * 1e3
+        t_comp += e[1].elapsed_time(e[2]) * 1e3
+    st1 = heap.stats()
+    res = {"workload": "structure (fracture), 1000x1000 brick-wall mesh: %d nodes (anchor, pull and free node "
+                       "classes under an abstract NodeBase), %d springs" % (W * H, len(mesh["p1"])),
+           "iterations_timed": n_it, "substeps_per_iteration": sub,
+           "us_per_iteration": (t_pull + t_comp + t_bfs) / n_it,
+           "compute_us_per_substep": t_comp / (n_it * sub),
+           "compute_updates_per_s": upd / (t_comp * 1e-6),
+           "bfs_us_per_iteration": t_bfs / n_it, "bfs_levels_per_iteration": levels / n_it,
+           "bfs_us_per_level": t_bfs / max(levels, 1),
+           "springs_start": int(st0.live_objects[c["Spring"]]), "springs_end": int(st1.live_objects[c["Spring"]]),
+           "nodes_start": int(nodes(st0)), "nodes_end": int(nodes(st1)),
+           "device_deletions": int(st1.device_deletes - st0.device_deletes),
+           "device_error": st1.device_error}
+    heap.close()
+    return res
+
+
 def measure_linux_scalability(torch):
     """Linux Scalability pattern (Ch.8 "Raw Allocation Performance") in SMMO
     form: a 1 GiB heap, 16,384 Worker objects each allocate n 64-byte Obj
@@ -1257,6 +1320,7 @@ def main():
         extras["adjoint"] = measure_adjoint(torch, res["value"])
         extras["gol"] = measure_gol_extra(torch)
         extras["gol_16384"] = measure_gol_large(torch)
+        extras["structure"] = measure_structure(torch)
         tuned = res.get("autotune") or {}
         extras["spring_2000"] = measure_spring_large(torch, tuned if tuned.get("kept") == "tuned" else None)
         extras["nbody"] = measure_nbody_extra(torch)

@@ -201,13 +201,15 @@ def concat_meshes(meshes: list) -> dict:
 
 
 def structure_mesh(W: int, H: int, seed: int | None = None, jitter: float = 0.2, pull_speed: float = 0.5,
-                   break_strain: float = 0.04, break_spread: float = 0.5, v_sigma: float = 0.0) -> dict:
+                   break_strain: float = 0.04, break_spread: float = 0.5, v_sigma: float = 0.0,
+                   stretch_rate: float = 0.0) -> dict:
     """Mesh of the fracture simulation ("structure"): a W x H brick-wall
     lattice (every node has springs to its left and right neighbours and, on
     alternating columns, to the node above or below: at most three springs per
     node), jittered positions with spacing h = 1/W.  Column 0 holds anchor
     nodes, column W-1 pull nodes moving at (pull_speed, 0), the rest ordinary
-    nodes of mass 1 at rest (or with N(0, v_sigma^2) velocities).  Spring
+    nodes of mass 1 at rest (or with N(0, v_sigma^2) velocities), plus
+    vx = stretch_rate * x (a uniform stretch of the whole mesh).  Spring
     stiffness k = 10^U(2, 3); rest length L0 = initial length; force limit
     k * L0 * break_strain * (1 + break_spread * U(-1, 1)).
 
@@ -235,6 +237,9 @@ def structure_mesh(W: int, H: int, seed: int | None = None, jitter: float = 0.2,
         vy = (v_sigma * normal(seed, 3, ids)).astype(np.float32)
         vx[ntype == 0] = 0
         vy[ntype == 0] = 0
+    if stretch_rate:
+        vx = (vx + stretch_rate * x).astype(np.float32)
+        vx[ntype == 0] = 0
     vx[ntype == 1] = pull_speed
     vy[ntype == 1] = 0
     # horizontal springs, then the vertical ones of the columns with (i + j) even

@@ -962,9 +962,17 @@ smmo_status smmo_parallel_do(smmo_heap *h, uint32_t class_id, uint32_t method_id
     if (args_bytes != m.args_bytes || (m.args_bytes && !args))
         return fail(SMMO_EINVAL, std::string("method '") + m.name + "': wrong argument size");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // the class and its descendants: one launch per concrete class
-    const uint32_t fam = class_family(h->schema, class_id);
+    // the class and its descendants: one launch per concrete class, or one
+    // for the whole family where the method covers it
+    const uint32_t fam = (m.flags & kFamilyLaunch) ? 1u << class_id : class_family(h->schema, class_id);
     for (uint32_t c = 0; c < h->schema->nclasses; ++c) {
+        if ((m.flags & kFamilyLaunch) && c == class_id) {
+            h->cur_method = method_id;
+            s = m.launch(h, c, args, st);
+            h->cur_method = 0xFFFFFFFFu;
+            if (s) return s;
+            continue;
+        }
         if (!((fam >> c) & 1) || class_abstract(h->schema, c)) continue;
         h->cur_method = method_id;
         s = m.launch(h, c, args, st);

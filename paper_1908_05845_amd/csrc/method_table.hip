@@ -87,9 +87,9 @@ const MethodEntry kMethods[] = {
     {"structure.pull", sizeof(smmo_structure_args), launch_structure_pull},
     {"structure.force", sizeof(smmo_structure_args), launch_structure_force},
     {"structure.node_update", sizeof(smmo_structure_args), launch_structure_node_update},
-    {"structure.bfs_init", sizeof(smmo_structure_args), launch_structure_bfs_init},
-    {"structure.bfs_visit", sizeof(smmo_structure_args), launch_structure_bfs_visit},
-    {"structure.bfs_mark", sizeof(smmo_structure_args), launch_structure_bfs_mark},
+    {"structure.bfs_init", sizeof(smmo_structure_args), launch_structure_bfs_init, kFamilyLaunch},
+    {"structure.bfs_visit", sizeof(smmo_structure_args), launch_structure_bfs_visit, kFamilyLaunch},
+    {"structure.bfs_mark", sizeof(smmo_structure_args), launch_structure_bfs_mark, kFamilyLaunch},
     {"structure.bfs_delete", sizeof(smmo_structure_args), launch_structure_bfs_delete},
     {"structure.link", sizeof(smmo_structure_args), launch_structure_link},
 };

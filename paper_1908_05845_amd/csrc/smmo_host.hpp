@@ -123,7 +123,12 @@ struct MethodEntry {
     const char *name;
     size_t args_bytes;
     smmo_status (*launch)(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+    // kFamilyLaunch: a do-all on a class with descendants calls `launch` once
+    // with the class itself, and the method covers the whole family in that
+    // launch (it uses only fields every class of the family shares)
+    uint32_t flags = 0;
 };
+constexpr uint32_t kFamilyLaunch = 1;
 
 const MethodEntry *method_table(uint32_t *count);
 

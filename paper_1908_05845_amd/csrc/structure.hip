@@ -17,6 +17,7 @@
 // class read from the block's type id.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "../../include/smmo_methods.h"
@@ -39,9 +40,56 @@ struct StructK {
     uint32_t s_p1, s_p2, s_k, s_L0, s_maxf, s_fx, s_fy, s_s1, s_s2, s_del;
     float dt;
     int32_t distance;
-    uint32_t anchor;          // bfs_init: the launched class is AnchorNode (or derives from it)
+    uint32_t fam_mask;        // BFS methods: the concrete node classes one launch covers
+    uint32_t anchor_mask;     // BFS methods: those of them that are AnchorNode or derive from it
     uint32_t *flag;
 };
+
+constexpr uint32_t kMaxFamily = 4;   // concrete classes one family launch walks
+
+// Calls f(bid, bm, cls) for every block of the classes in `mask` (at most
+// kMaxFamily), one wavefront per block: a grid-stride walk over their block
+// lists taken one after the other.  As in for_each_block, listed blocks whose
+// type changed are skipped.  The list lengths were written by earlier
+// launches (the enumerations), so plain loads read them.
+template <class F>
+__device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_t mask, F &&f)
+{
+    BlockList L[kMaxFamily];
+    uint32_t cls[kMaxFamily], end[kMaxFamily];
+    uint32_t total = 0, m = mask;
+#pragma unroll
+    for (uint32_t j = 0; j < kMaxFamily; ++j) {
+        cls[j] = m ? (uint32_t)(__ffs(m) - 1) : 0u;
+        L[j].R = h.R + (uint64_t)cls[j] * h.M;
+        L[j].M = h.M;
+        L[j].r = L[j].nd = 0;
+        if (m) {
+            L[j].r = __builtin_amdgcn_readfirstlane(h.ctrl[CTRL_RFINAL + cls[j]]);
+            L[j].nd = L[j].r - __builtin_amdgcn_readfirstlane(h.ctrl[CTRL_RSFINAL + cls[j]]);
+            m &= m - 1;
+        }
+        total += L[j].r;
+        end[j] = total;
+    }
+    const uint32_t wpg = blockDim.x >> 6;
+    const uint32_t nw = gridDim.x * wpg;
+    for (uint32_t i = xcd_logical_wg() * wpg + (threadIdx.x >> 6); i < total; i += nw) {
+        uint32_t bid = 0, c = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kMaxFamily; ++j) {
+            const uint32_t start = end[j] - L[j].r;
+            if (i >= start && i < end[j]) {       // exactly one segment holds entry i
+                bid = L[j].at(i - start);
+                c = cls[j];
+            }
+        }
+        bid = __builtin_amdgcn_readfirstlane(bid);
+        const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
+        const uint64_t bm = uniform64(h.alloc_bm[bid]);
+        if (t == c) f(bid, bm, t);
+    }
+}
 
 __device__ __forceinline__ bool st_valid(const HeapView &h, uint32_t handle)
 {
@@ -190,26 +238,30 @@ __global__ __launch_bounds__(1024) void k_st_node_update(HeapView h, StructK p)
     });
 }
 
-// NodeBase::initialize_frontier
+// NodeBase::initialize_frontier (the cast to AnchorNode is the block's type)
 __global__ __launch_bounds__(1024) void k_st_bfs_init(HeapView h, StructK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+    for_each_family_block(h, p.fam_mask, [&](uint32_t bid, uint64_t bm, uint32_t t) {
         const uint32_t s = lane_id();
-        if ((bm >> s) & 1) farr<int32_t>(h, bid, p.n_dist)[s] = p.anchor ? 0 : kFar;
+        if ((bm >> s) & 1) farr<int32_t>(h, bid, p.n_dist)[s] = ((p.anchor_mask >> t) & 1) ? 0 : kFar;
     });
 }
 
 // NodeBase::visit(distance).  Concurrent writers of a neighbour's distance
-// all write distance + 1, and no node of this level's frontier changes.
+// all write distance + 1, and no node of this level's frontier changes.  The
+// frontier flag is read only after the kernel, so plain stores of the same
+// value suffice (the end of the kernel writes the caches back); a wavefront
+// that already sees the flag set skips its store.  (Agent-scope stores to
+// one word from every frontier wavefront would queue at that word.)
 __global__ __launch_bounds__(1024) void k_st_bfs_visit(HeapView h, StructK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+    for_each_family_block(h, p.fam_mask, [&](uint32_t bid, uint64_t bm, uint32_t) {
         const uint32_t s = lane_id();
         const bool front = ((bm >> s) & 1) && farr<int32_t>(h, bid, p.n_dist)[s] == p.distance;
-        if (__ballot(front) && s == (uint32_t)(__ffsll((unsigned long long)__ballot(front)) - 1))
-            __hip_atomic_store(p.flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t fb = __ballot(front);
+        if (fb && s == (uint32_t)(__ffsll((unsigned long long)fb) - 1) && *p.flag == 0) *p.flag = 1u;
         if (!front) return;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -229,7 +281,7 @@ __global__ __launch_bounds__(1024) void k_st_bfs_visit(HeapView h, StructK p)
 __global__ __launch_bounds__(1024) void k_st_bfs_mark(HeapView h, StructK p)
 {
     if (heap_failed(h)) return;
-    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+    for_each_family_block(h, p.fam_mask, [&](uint32_t bid, uint64_t bm, uint32_t) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1) || farr<int32_t>(h, bid, p.n_dist)[s] != kFar) return;
 #pragma unroll
@@ -329,10 +381,30 @@ smmo_status bind_structure(smmo_heap *h, uint32_t cls, const smmo_structure_args
             if (off != want[f]) return fail(SMMO_EINVAL, "structure: node classes disagree on a NodeBase field");
         }
     }
-    uint32_t is_anchor = 0;
-    if (smmo_class_is_a(sc, cls, a.anchor_class, &is_anchor)) return fail(SMMO_EINVAL, "structure: class relation");
-    k.anchor = is_anchor;
+    // BFS methods: the concrete classes of the launched class's family
+    const uint32_t fam = class_family(sc, cls), anchors = class_family(sc, a.anchor_class);
+    for (uint32_t c = 0; c < nc; ++c)
+        if (((fam >> c) & 1) && !class_abstract(sc, c)) k.fam_mask |= 1u << c;
+    k.anchor_mask = k.fam_mask & anchors;
+    if (__builtin_popcount(k.fam_mask) > (int)kMaxFamily)
+        return fail(SMMO_EINVAL, "structure: more than 4 concrete node classes in one do-all");
     return SMMO_OK;
+}
+
+// the launch shape of a family launch: the method's shape, with as many
+// wavefronts as the family's classes may have blocks
+LaunchShape family_shape(smmo_heap *h, uint32_t cls, uint32_t mask)
+{
+    LaunchShape ls = method_shape(h, cls);
+    uint64_t blocks = 0;
+    for (uint32_t c = 0; c < h->schema->nclasses; ++c)
+        if ((mask >> c) & 1) blocks += h->ub_blocks[c];
+    uint64_t waves = h->cfg.grid_waves ? h->cfg.grid_waves : 64ull * h->cu_count;
+    if (h->cur_method < 64 && h->launch_waves[h->cur_method][cls]) waves = h->launch_waves[h->cur_method][cls];
+    waves = std::min<uint64_t>(waves, std::max<uint64_t>(1, blocks));
+    const uint32_t wpg = ls.block.x / 64;
+    ls.grid = dim3((uint32_t)((waves + wpg - 1) / wpg));
+    return ls;
 }
 
 template <int W>
@@ -354,8 +426,17 @@ smmo_status launch_structure(smmo_heap *h, uint32_t cls, const void *args, hipSt
     k.dt = a.dt;
     k.distance = a.distance;
     k.flag = a.flag;
-    if ((s = ensure_enumerated(h, cls, false, st))) return s;
-    const LaunchShape ls = method_shape(h, cls);
+    const bool family = W == W_BFS_INIT || W == W_BFS_VISIT || W == W_BFS_MARK;
+    LaunchShape ls;
+    if (family) {
+        for (uint32_t c = 0; c < h->schema->nclasses; ++c)
+            if (((k.fam_mask >> c) & 1) && (s = ensure_enumerated(h, c, false, st))) return s;
+        ls = family_shape(h, cls, k.fam_mask);
+        if (!k.fam_mask) return SMMO_OK;
+    } else {
+        if ((s = ensure_enumerated(h, cls, false, st))) return s;
+        ls = method_shape(h, cls);
+    }
     switch (W) {
     case W_PULL: hipLaunchKernelGGL(k_st_pull, ls.grid, ls.block, 0, st, h->v, k); break;
     case W_FORCE: hipLaunchKernelGGL(k_st_force, ls.grid, ls.block, 0, st, h->v, k); break;
