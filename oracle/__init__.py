@@ -23,4 +23,8 @@ from .oracle import (  # noqa: F401
     STRUCTURE_PULL,
     STRUCTURE_NODE,
     STRUCTURE_MAXDIST,
+    generation_steps,
+    BURST_SURVIVE,
+    BURST_BIRTH,
+    BURST_DYING,
 )

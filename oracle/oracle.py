@@ -73,6 +73,9 @@ def _load():
             lib.orc_wator_read.argtypes = [P, P, P, P, P]
             lib.orc_wator_free.restype = None
             lib.orc_wator_free.argtypes = [P]
+            lib.orc_generation_steps.restype = C.c_int
+            lib.orc_generation_steps.argtypes = [C.c_int, C.c_int, P, P, C.c_uint32, C.c_uint32, C.c_int32,
+                                                 C.c_int]
             lib.orc_structure_pull.restype = C.c_int
             lib.orc_structure_pull.argtypes = [LL, P, P, P, P, P, P, D]
             lib.orc_structure_step.restype = LL
@@ -385,3 +388,31 @@ def structure_bfs(st: dict) -> dict:
         raise RuntimeError("oracle structure error %d" % nd)
     o.update(levels=int(lv.value), ndeleted=int(nd))
     return o
+
+
+# --------------------------------------------------------------- generation --
+BURST_SURVIVE = (0, 2, 3, 5, 6, 7, 8)
+BURST_BIRTH = (3, 4, 6, 8)
+BURST_DYING = 255
+
+
+def _mask(counts) -> int:
+    m = 0
+    for c in counts:
+        m |= 1 << int(c)
+    return m
+
+
+def generation_steps(W: int, H: int, state, left, steps: int = 1, survive=BURST_SURVIVE, birth=BURST_BIRTH,
+                     dying: int = BURST_DYING):
+    """The generational cellular automaton of thesis Ch.7 "generation" (rule
+    Burst by default) on a W x H torus: returns new (state, left) arrays
+    (state 0 empty, 1 live, 2 dying; left = dying generations left)."""
+    st = np.array(state, dtype=np.uint8, copy=True).reshape(-1)
+    lf = np.array(left, dtype=np.int32, copy=True).reshape(-1)
+    assert st.size == W * H and lf.size == W * H
+    rc = _load().orc_generation_steps(int(W), int(H), _p(st), _p(lf), _mask(survive), _mask(birth), int(dying),
+                                      int(steps))
+    if rc:
+        raise RuntimeError("oracle generation error %d" % rc)
+    return st, lf

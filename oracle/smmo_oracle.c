@@ -1299,3 +1299,63 @@ long long orc_structure_bfs(long long N, const int32_t *ntype, uint8_t *nalive, 
     }
     return ndel;
 }
+
+/* ------------------------------------------------------------------------ */
+/* generation (thesis Ch.7 "generation"): a generational cellular automaton, */
+/* Game of Life extended by dying cells.  The thesis's rule is "Burst"       */
+/* (0235678/3468/255): a live cell survives with a live-neighbour count in   */
+/* the survive set S, otherwise it dies but keeps blocking its cell for D    */
+/* more generations; an empty cell comes alive with a count in the birth set */
+/* B.  Dying cells are not live neighbours and cannot be born into.  The     */
+/* result is fully defined per cell, so this is that definition, on a W x H  */
+/* torus (as the Game of Life here):                                         */
+/*   count = live (state 1) cells among the 8 neighbours at generation t;    */
+/*   state 0: -> 1 if count in B, else 0;                                    */
+/*   state 1: -> 1 if count in S, else dying with D generations left;        */
+/*   dying with r left: r - 1 left, and empty (0) once none is left.         */
+/* state[i] (0 empty, 1 live, 2 dying) and left[i] (generations of dying     */
+/* left, 0 unless dying) are updated in place; S and B are bit masks over    */
+/* the counts 0..8.  Returns 0, or -1 for bad arguments.                     */
+/* ------------------------------------------------------------------------ */
+int orc_generation_steps(int W, int H, uint8_t *state, int32_t *left, uint32_t S, uint32_t B, int32_t D,
+                         int steps)
+{
+    if (W <= 0 || H <= 0 || D < 1) return -1;
+    const size_t n = (size_t)W * (size_t)H;
+    uint8_t *ns = malloc(n);
+    int32_t *nl = malloc(n * sizeof(int32_t));
+    if (!ns || !nl) {
+        free(ns);
+        free(nl);
+        return -1;
+    }
+    for (int st = 0; st < steps; st++) {
+        for (int y = 0; y < H; y++)
+            for (int x = 0; x < W; x++) {
+                int count = 0;
+                for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                        if (!dx && !dy) continue;
+                        const int xx = ((x + dx) % W + W) % W, yy = ((y + dy) % H + H) % H;
+                        count += state[(size_t)yy * W + xx] == 1;
+                    }
+                const size_t i = (size_t)y * W + x;
+                if (state[i] == 0) {
+                    ns[i] = (B >> count) & 1;
+                    nl[i] = 0;
+                } else if (state[i] == 1) {
+                    const int live = (S >> count) & 1;
+                    ns[i] = live ? 1 : 2;
+                    nl[i] = live ? 0 : D;
+                } else {
+                    nl[i] = left[i] - 1;
+                    ns[i] = nl[i] > 0 ? 2 : 0;
+                }
+            }
+        memcpy(state, ns, n);
+        memcpy(left, nl, n * sizeof(int32_t));
+    }
+    free(ns);
+    free(nl);
+    return 0;
+}
