@@ -700,6 +700,44 @@ def measure_structure(torch):
     return res
 
 
+def measure_generation(torch):
+    """generation (Game of Life with dying cells, rule Burst: survive
+    0235678, birth 3468, dying 255), 256 x 256 torus, 25 % start: 300
+    generations (past the dying period) captured in one HIP graph, three
+    do-alls per generation; births are device allocations, expiries device
+    deletions."""
+    from inputs import gol_init
+    from paper_1908_05845_amd.sims import GenerationSim
+
+    W = H = 256
+    sim = GenerationSim(W, H, gol_init(W, H))
+    heap = sim.heap
+    sim.step(2)
+    heap.sync()
+    n = 300
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sim.step(n, stream=torch.cuda.current_stream())
+    st0 = heap.stats()
+    e0, e1 = events(torch, 2)
+    torch.cuda.synchronize()
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st1 = heap.stats()
+    ca = heap.cls["Alive"]
+    res = {"workload": "generation (rule Burst 0235678/3468/255), 256x256 torus, 25%% start, %d generations" % n,
+           "launch": "one HIP graph", "us_per_generation": ms * 1e3 / n,
+           "births_per_s": (st1.device_news - st0.device_news) / (ms * 1e-3),
+           "expiries_per_s": (st1.device_deletes - st0.device_deletes) / (ms * 1e-3),
+           "alive_objects_end": int(st1.live_objects[ca]), "fragmentation_end": st1.fragmentation,
+           "device_error": st1.device_error}
+    heap.close()
+    return res
+
+
 def measure_linux_scalability(torch):
     """Linux Scalability pattern (Ch.8 "Raw Allocation Performance") in SMMO
     form: a 1 GiB heap, 16,384 Worker objects each allocate n 64-byte Obj
@@ -1321,6 +1359,7 @@ def main():
         extras["gol"] = measure_gol_extra(torch)
         extras["gol_16384"] = measure_gol_large(torch)
         extras["structure"] = measure_structure(torch)
+        extras["generation"] = measure_generation(torch)
         tuned = res.get("autotune") or {}
         extras["spring_2000"] = measure_spring_large(torch, tuned if tuned.get("kept") == "tuned" else None)
         extras["nbody"] = measure_nbody_extra(torch)

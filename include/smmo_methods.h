@@ -216,6 +216,35 @@ typedef struct {
     const uint32_t *cells;
 } smmo_wator_args;
 
+/* ---- generation (thesis Ch.7 "generation": Game of Life with dying cells) --
+ * Cell  {state: U8 (0 empty, 1 live, 2 dying), count: I32, cell_id: I32}
+ * Alive {cell_id: I32, left: I32 (dying generations left, 0 while live),
+ *        is_new: U8}
+ * One generation on a W x H torus = "generation.cell_count", then
+ * "generation.cell_birth", then "generation.alive_update":
+ * "generation.cell_count"   on Cell: count = live (state 1) neighbours.
+ * "generation.cell_birth"   on Cell: an empty cell whose count is in the
+ *        birth set becomes live and gets a new Alive (left 0, is_new 1).
+ * "generation.alive_update" on Alive: a new object only clears is_new; a
+ *        live one whose cell's count is not in the survive set starts dying
+ *        (left = dying, cell state 2); a dying one counts left down and, at
+ *        0, empties its cell (state 0) and deletes itself.
+ * Births run before the update so that they see the generation's starting
+ * states; is_new keeps the update away from this generation's births.  The
+ * thesis's rule "Burst" is survive {0,2,3,5,6,7,8}, birth {3,4,6,8},
+ * dying 255. */
+typedef struct {
+    uint32_t cell_class;
+    uint32_t alive_class;
+    int32_t width;
+    int32_t height;
+    uint32_t survive;            /* bit c: a live cell with c live neighbours stays live (c = 0..8) */
+    uint32_t birth;              /* bit c: an empty cell with c live neighbours comes alive */
+    int32_t dying;               /* generations a dead cell keeps blocking, >= 1 */
+    uint32_t reserved;
+    const uint32_t *cells;       /* W*H Cell handles, index y*W + x */
+} smmo_generation_args;
+
 /* ---- structure (thesis Ch.7 "structure": fracture of a spring mesh) -------
  * Class hierarchy (smmo_define_subclass; inherited fields first):
  * NodeBase (abstract) {x, y: F32, springs: HANDLE x 3, nspr: I32, dist: I32,

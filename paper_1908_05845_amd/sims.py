@@ -16,6 +16,11 @@ GOL_CLASSES = {
     "Alive": [("cell_id", "i32", 1)],
 }
 
+GENERATION_CLASSES = {
+    "Cell": [("state", "u8", 1), ("count", "i32", 1), ("cell_id", "i32", 1)],
+    "Alive": [("cell_id", "i32", 1), ("left", "i32", 1), ("is_new", "u8", 1)],
+}
+
 NBODY_CLASSES = {
     "Body": [("pos_x", "f32", 1), ("pos_y", "f32", 1), ("vel_x", "f32", 1), ("vel_y", "f32", 1),
              ("force_x", "f32", 1), ("force_y", "f32", 1), ("mass", "f32", 1), ("id", "i32", 1)],
@@ -98,6 +103,65 @@ class GolSim:
         count[cid] = _np(g["count"])
         a = self.heap.gather("Alive", ["cell_id"])
         return state, count, np.sort(_np(a["cell_id"]))
+
+
+def _rule_mask(counts) -> int:
+    m = 0
+    for c in counts:
+        m |= 1 << int(c)
+    return m
+
+
+class GenerationSim:
+    """The generational cellular automaton of thesis Ch.7 "generation" (Game
+    of Life with dying cells; rule Burst by default) on a W x H torus, in the
+    Cell + Alive form: an Alive object per live or dying cell."""
+
+    def __init__(self, W: int, H: int, init, survive=(0, 2, 3, 5, 6, 7, 8), birth=(3, 4, 6, 8), dying: int = 255,
+                 cfg=None, extra_blocks: int = 16):
+        import torch
+
+        self.W, self.H = W, H
+        n = W * H
+        self.heap = smmo.Heap(GENERATION_CLASSES, blocks=3 * _blocks(n) + extra_blocks, cfg=cfg)
+        dev = self.heap.buf.device
+        init = np.ascontiguousarray(init, dtype=np.uint8).reshape(-1)
+        assert init.size == n and init.max(initial=0) <= 1
+        ids = torch.arange(n, dtype=torch.int32, device=dev)
+        self.cells = self.heap.new("Cell", n, state=torch.from_numpy(init).to(dev), cell_id=ids).clone()
+        live = np.flatnonzero(init).astype(np.int32)
+        if live.size:
+            self.heap.new("Alive", live.size, cell_id=torch.from_numpy(live).to(dev))
+        self.args = smmo.smmo_generation_args(self.heap.cls["Cell"], self.heap.cls["Alive"], W, H,
+                                              _rule_mask(survive), _rule_mask(birth), dying, 0,
+                                              self.cells.data_ptr())
+        self.m_count = smmo.smmo_method_id("generation.cell_count")
+        self.m_birth = smmo.smmo_method_id("generation.cell_birth")
+        self.m_update = smmo.smmo_method_id("generation.alive_update")
+
+    def step(self, n: int = 1, stream=None):
+        h, c, a = self.heap.h, self.heap.cls["Cell"], self.heap.cls["Alive"]
+        for _ in range(n):
+            smmo.smmo_parallel_do(h, c, self.m_count, self.args, stream)
+            smmo.smmo_parallel_do(h, c, self.m_birth, self.args, stream)
+            smmo.smmo_parallel_do(h, a, self.m_update, self.args, stream)
+
+    def read(self):
+        """(state u8[W*H], left i32[W*H], number of Alive objects); raises if
+        a cell and its Alive object disagree."""
+        n = self.W * self.H
+        g = self.heap.gather("Cell", ["state", "cell_id"])
+        state = np.zeros(n, np.uint8)
+        state[_np(g["cell_id"])] = _np(g["state"])
+        a = self.heap.gather("Alive", ["cell_id", "left", "is_new"])
+        cid = _np(a["cell_id"])
+        left = np.zeros(n, np.int32)
+        left[cid] = _np(a["left"])
+        occupied = np.zeros(n, np.int64)
+        np.add.at(occupied, cid, 1)
+        if np.any(occupied > 1) or not np.array_equal(occupied > 0, state > 0) or np.any(_np(a["is_new"])):
+            raise AssertionError("generation: cells and Alive objects disagree")
+        return state, left, int(cid.size)
 
 
 class NbodySim:

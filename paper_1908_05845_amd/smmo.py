@@ -111,6 +111,12 @@ class smmo_wator_args(C.Structure):
                 ("reserved", C.c_uint32), ("cells", C.c_void_p)]
 
 
+class smmo_generation_args(C.Structure):
+    _fields_ = [("cell_class", C.c_uint32), ("alive_class", C.c_uint32), ("width", C.c_int32),
+                ("height", C.c_int32), ("survive", C.c_uint32), ("birth", C.c_uint32), ("dying", C.c_int32),
+                ("reserved", C.c_uint32), ("cells", C.c_void_p)]
+
+
 SMMO_STRUCTURE_FAR = 0x7FFFFFFF
 
 
