@@ -15,4 +15,5 @@ from .workloads import (  # noqa: F401
     concat_meshes,
     wator_init,
     structure_mesh,
+    hub_mesh,
 )

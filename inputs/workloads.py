@@ -280,3 +280,64 @@ def structure_mesh(W: int, H: int, seed: int | None = None, jitter: float = 0.2,
         "p1": p1.astype(np.int32), "p2": p2.astype(np.int32), "k": k, "L0": L0, "maxf": maxf,
         "s1": s1, "s2": s2, "salive": np.ones(S, np.uint8),
     }
+
+
+def hub_mesh(W: int, H: int, hubs: int = 8, hub_springs: int = 32, seed: int | None = None, **kw) -> dict:
+    """spring_mesh(W, H) plus `hub_springs` extra springs from each of `hubs`
+    hub nodes to other nodes drawn at random (stiffness 10^U(2,4), rest length
+    the initial distance): a mesh of high-degree nodes.  adj / adj_is_b have
+    shape (N, D) with D the largest degree; slots in spring-id order; the
+    extra springs follow the mesh's springs in id order."""
+    if seed is None:
+        seed = config_seed(7)
+    m = spring_mesh(W, H, seed=seed, **kw)
+    N = W * H
+    hub_ids = np.unique((uniform(seed, 10, np.arange(hubs)) * N).astype(np.int64) % max(N, 1))
+    src, dst = [], []
+    for h in hub_ids:
+        j = np.arange(hub_springs, dtype=np.int64)
+        t = (uniform(seed, 11 + int(h) % 1000, j + int(h) * hub_springs) * N).astype(np.int64) % N
+        t = np.unique(t[t != h])
+        src.append(np.full(t.size, h))
+        dst.append(t)
+    src = np.concatenate(src) if src else np.zeros(0, np.int64)
+    dst = np.concatenate(dst) if dst else np.zeros(0, np.int64)
+    a0 = np.asarray(m["a"], np.int64)
+    b0 = np.asarray(m["b"], np.int64)
+    # no duplicate of an existing spring
+    key0 = set(zip(np.minimum(a0, b0).tolist(), np.maximum(a0, b0).tolist()))
+    keep = np.array([(min(s, d), max(s, d)) not in key0 for s, d in zip(src.tolist(), dst.tolist())], bool)
+    if keep.size:
+        src, dst = src[keep], dst[keep]
+    a = np.concatenate([a0, np.minimum(src, dst)])
+    b = np.concatenate([b0, np.maximum(src, dst)])
+    S = a.size
+    sid = np.arange(S, dtype=np.int64)
+    x = np.asarray(m["x"])
+    y = np.asarray(m["y"])
+    kx = (10.0 ** (2.0 + 2.0 * uniform(seed, 12, sid[a0.size:]))).astype(np.float32)
+    k = np.concatenate([np.asarray(m["k"], np.float32), kx])
+    dx = x[b].astype(np.float64) - x[a].astype(np.float64)
+    dy = y[b].astype(np.float64) - y[a].astype(np.float64)
+    L0 = np.sqrt(dx * dx + dy * dy).astype(np.float32)
+    node = np.concatenate([a, b])
+    spr = np.concatenate([sid, sid])
+    isb = np.concatenate([np.zeros(S, np.uint8), np.ones(S, np.uint8)])
+    order = np.lexsort((spr, node))
+    node_s, spr_s, isb_s = node[order], spr[order], isb[order]
+    first = np.searchsorted(node_s, node_s, side="left")
+    rank = np.arange(node_s.size) - first
+    D = int(rank.max(initial=0)) + 1
+    adj = np.full((N, D), -1, np.int32)
+    adj_is_b = np.zeros((N, D), np.uint8)
+    adj[node_s, rank] = spr_s
+    adj_is_b[node_s, rank] = isb_s
+    slot_a = np.empty(S, np.int32)
+    slot_b = np.empty(S, np.int32)
+    sel = isb_s == 0
+    slot_a[spr_s[sel]] = rank[sel]
+    slot_b[spr_s[~sel]] = rank[~sel]
+    out = dict(m)
+    out.update(a=a.astype(np.int32), b=b.astype(np.int32), k=k, L0=L0, adj=adj, adj_is_b=adj_is_b,
+               slot_a=slot_a, slot_b=slot_b, S=int(S))
+    return out

@@ -16,6 +16,7 @@ from .oracle import (  # noqa: F401
     spring_adjoint,
     spring_adjoint_step,
     spring_breaks,
+    spring_steps_deg,
     structure_pull,
     structure_step,
     structure_bfs,

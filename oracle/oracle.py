@@ -73,6 +73,9 @@ def _load():
             lib.orc_wator_read.argtypes = [P, P, P, P, P]
             lib.orc_wator_free.restype = None
             lib.orc_wator_free.argtypes = [P]
+            lib.orc_spring_steps_deg.restype = LL
+            lib.orc_spring_steps_deg.argtypes = [LL, C.c_int, P, P, P, P, P, P, P, LL, P, P, P, P, P, P,
+                                                 P, P, P, D, C.c_float, C.c_int, P, P, P, P, P]
             lib.orc_generation_steps.restype = C.c_int
             lib.orc_generation_steps.argtypes = [C.c_int, C.c_int, P, P, C.c_uint32, C.c_uint32, C.c_int32,
                                                  C.c_int]
@@ -247,6 +250,39 @@ def spring_steps(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1,
                               S, _p(a), _p(b), _p(kk), _p(L0), _p(sa), _p(sb), _p(al),
                               _p(fxo), _p(fyo), float(dt), float(thresh), int(steps),
                               _p(sf), _p(svx), _p(svy), _p(sx), _p(sy), int(bool(tension_only)))
+    if nb < 0:
+        raise RuntimeError("oracle spring error %d" % nb)
+    out = dict(mesh)
+    out.update(x=x, y=y, vx=vx, vy=vy, adj=adj, alive=al, fx=fxo, fy=fyo, nbroken=int(nb),
+               sf=sf, svx=svx, svy=svy, sx=sx, sy=sy)
+    return out
+
+
+def spring_steps_deg(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1, alive=None, fx=None, fy=None):
+    """spring_steps for meshes of any node degree D (adj and adj_is_b of shape
+    (N, D)): the same steps and decisions, slots summed in order."""
+    lib = _load()
+    adj = np.array(mesh["adj"], dtype=np.int32, copy=True)
+    N = int(np.asarray(mesh["x"]).size)
+    adj = adj.reshape(N, -1)
+    D = adj.shape[1]
+    S = int(np.asarray(mesh["a"]).size)
+    x, y, vx, vy, m = (_f64(mesh[k]) for k in ("x", "y", "vx", "vy", "m"))
+    adjb = np.ascontiguousarray(mesh["adj_is_b"], dtype=np.uint8).reshape(N, D)
+    a = np.ascontiguousarray(mesh["a"], dtype=np.int32)
+    b = np.ascontiguousarray(mesh["b"], dtype=np.int32)
+    kk = _f64(mesh["k"])
+    L0 = _f64(mesh["L0"])
+    sa = np.ascontiguousarray(mesh["slot_a"], dtype=np.int32)
+    sb = np.ascontiguousarray(mesh["slot_b"], dtype=np.int32)
+    al = (np.ones(S, np.uint8) if alive is None else np.ascontiguousarray(alive, dtype=np.uint8).copy())
+    fxo = np.zeros(S) if fx is None else _f64(fx)
+    fyo = np.zeros(S) if fy is None else _f64(fy)
+    sf = np.zeros(S)
+    svx, svy, sx, sy = (np.zeros(N) for _ in range(4))
+    nb = lib.orc_spring_steps_deg(N, D, _p(x), _p(y), _p(vx), _p(vy), _p(m), _p(adj), _p(adjb), S, _p(a), _p(b),
+                                  _p(kk), _p(L0), _p(sa), _p(sb), _p(al), _p(fxo), _p(fyo), float(dt),
+                                  float(thresh), int(steps), _p(sf), _p(svx), _p(svy), _p(sx), _p(sy))
     if nb < 0:
         raise RuntimeError("oracle spring error %d" % nb)
     out = dict(mesh)

@@ -1359,3 +1359,91 @@ int orc_generation_steps(int W, int H, uint8_t *state, int32_t *left, uint32_t S
     free(nl);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The spring-mass mesh above with node degree up to D (any D >= 1): the    */
+/* same two steps and decisions, adjacency N*D spring ids (-1 empty) summed  */
+/* in slot order.  It serves meshes whose nodes exceed the 8 slots of        */
+/* orc_spring_steps (hubs), whose adjacency the GPU stores partly inlined    */
+/* (Ch.4 sec.4.3.1 "SOA with Partial Inlining").  Arguments and results as   */
+/* orc_spring_steps.                                                         */
+/* ------------------------------------------------------------------------ */
+long long orc_spring_steps_deg(long long N, int D, double *x, double *y, double *vx, double *vy,
+                               const double *m, int32_t *adj, const uint8_t *adjb,
+                               long long S, const int32_t *a, const int32_t *b,
+                               const double *k, const double *L0,
+                               const int32_t *slot_a, const int32_t *slot_b,
+                               uint8_t *alive, double *fx, double *fy,
+                               double dt, float thresh, int steps,
+                               double *sf, double *svx, double *svy, double *sx, double *sy)
+{
+    if (N < 0 || S < 0 || D < 1) return -1;
+    double *f_x = malloc((size_t)(S ? S : 1) * sizeof(double));
+    double *f_y = malloc((size_t)(S ? S : 1) * sizeof(double));
+    double *s_f = malloc((size_t)(S ? S : 1) * sizeof(double));
+    uint8_t *snap = malloc((size_t)(S ? S : 1));
+    if (!f_x || !f_y || !s_f || !snap) {
+        free(f_x); free(f_y); free(s_f); free(snap);
+        return -1;
+    }
+    long long err = 0, nbroken = 0;
+    for (long long s = 0; s < S; s++) {
+        f_x[s] = fx ? fx[s] : 0;
+        f_y[s] = fy ? fy[s] : 0;
+        s_f[s] = 0;
+    }
+    for (long long i = 0; i < N && !err; i++)
+        for (int q = 0; q < D; q++) {
+            const long long sid = adj[i * D + q];
+            if (sid >= S || (sid >= 0 && !alive[sid])) err = 6;
+        }
+    for (int st = 0; st < steps && !err; st++) {
+        memcpy(snap, alive, (size_t)S);
+        for (long long s = 0; s < S; s++) {           /* Spring::compute_force */
+            if (!snap[s]) continue;
+            const long long ia = a[s], ib = b[s];
+            if (sp_breaks(x[ia], y[ia], x[ib], y[ib], L0[s], thresh)) {
+                if (adj[ia * D + slot_a[s]] != s || adj[ib * D + slot_b[s]] != s) err = 4;
+                adj[ia * D + slot_a[s]] = -1;
+                adj[ib * D + slot_b[s]] = -1;
+                f_x[s] = f_y[s] = s_f[s] = 0;
+                alive[s] = 0;
+                nbroken++;
+                continue;
+            }
+            const double dx = x[ib] - x[ia], dy = y[ib] - y[ia];
+            const double l = sqrt(dx * dx + dy * dy);
+            const double c = k[s] * (l - L0[s]) / l;
+            f_x[s] = c * dx;
+            f_y[s] = c * dy;
+            s_f[s] = k[s] * (l + L0[s]);
+        }
+        for (long long i = 0; i < N; i++) {           /* Node::update */
+            double Fx = 0, Fy = 0, SF = 0;
+            for (int q = 0; q < D; q++) {
+                const long long s = adj[i * D + q];
+                if (s < 0) continue;
+                const double sg = adjb[i * D + q] ? -1.0 : 1.0;
+                Fx += sg * f_x[s];
+                Fy += sg * f_y[s];
+                SF += s_f[s];
+            }
+            const double svxi = fabs(vx[i]) + dt * SF / m[i], svyi = fabs(vy[i]) + dt * SF / m[i];
+            if (svx) svx[i] = svxi;
+            if (svy) svy[i] = svyi;
+            if (sx) sx[i] = fabs(x[i]) + dt * svxi;
+            if (sy) sy[i] = fabs(y[i]) + dt * svyi;
+            vx[i] += Fx / m[i] * dt;
+            vy[i] += Fy / m[i] * dt;
+            x[i] += vx[i] * dt;
+            y[i] += vy[i] * dt;
+        }
+    }
+    for (long long s = 0; s < S; s++) {
+        if (fx) fx[s] = f_x[s];
+        if (fy) fy[s] = f_y[s];
+        if (sf) sf[s] = s_f[s];
+    }
+    free(f_x); free(f_y); free(s_f); free(snap);
+    return err ? -err - 10 : nbroken;
+}

@@ -206,3 +206,46 @@ def test_tension_only_oscillator_goes_slack():
     # and decelerating, not coasting
     t = spring_steps(mesh, dt=dt, thresh=1.0, steps=600)
     assert t["vx"][1] != r2["vx"][1]
+
+
+def test_any_degree_oracle_equals_eight_slot_oracle():
+    """The variable-degree routine is the 8-slot one on meshes that fit 8
+    slots: bit-identical states, forces, topology and scales, with breaking."""
+    from oracle import spring_steps_deg
+    mesh = spring_mesh(30, 20, seed=4, v_sigma=1.0)
+    for steps in (3, 7):
+        r8 = spring_steps(mesh, 1e-4, 0.001, steps)
+        rd = spring_steps_deg(mesh, 1e-4, 0.001, steps)
+        assert r8["nbroken"] == rd["nbroken"] and r8["nbroken"] > 0
+        for key in ("x", "y", "vx", "vy", "fx", "fy", "alive", "adj", "sf", "svx", "svy", "sx", "sy"):
+            assert np.array_equal(np.asarray(r8[key]).reshape(-1), np.asarray(rd[key]).reshape(-1)), key
+
+
+def test_hub_mesh_momentum_and_star():
+    from inputs import hub_mesh
+    from oracle import spring_steps_deg
+    mesh = hub_mesh(24, 16, hubs=4, hub_springs=30, v_sigma=0.5)
+    assert np.asarray(mesh["adj"]).shape[1] > 8
+    p0 = np.array([np.sum(np.asarray(mesh["vx"], float)), np.sum(np.asarray(mesh["vy"], float))])
+    r = spring_steps_deg(mesh, 1e-4, 1e9, 50)
+    p1 = np.array([np.sum(r["vx"]), np.sum(r["vy"])])
+    scale = np.sum(np.abs(r["vx"])) + np.sum(np.abs(r["vy"]))
+    assert np.all(np.abs(p1 - p0) <= 1e-12 * scale)
+    # a star: a hub with 12 springs (k = 2, L0 = 1) to leaves at distance 1.5
+    n = 12
+    th = 2 * np.pi * np.arange(n) / n
+    x = np.concatenate([[0.0], 1.5 * np.cos(th)])
+    y = np.concatenate([[0.0], 1.5 * np.sin(th)])
+    adj = -np.ones((n + 1, n), np.int32)
+    adjb = np.zeros((n + 1, n), np.uint8)
+    adj[0, :] = np.arange(n)
+    adj[1:, 0] = np.arange(n)
+    adjb[1:, 0] = 1
+    star = dict(x=x, y=y, vx=np.zeros(n + 1), vy=np.zeros(n + 1), m=np.ones(n + 1), adj=adj, adj_is_b=adjb,
+                a=np.zeros(n, np.int32), b=np.arange(1, n + 1, dtype=np.int32), k=np.full(n, 2.0),
+                L0=np.ones(n), slot_a=np.arange(n, dtype=np.int32), slot_b=np.zeros(n, np.int32))
+    r = spring_steps_deg(star, 0.5, 1.0, 1)
+    # every leaf is pulled 1 towards the hub; the hub's forces cancel
+    assert np.allclose(r["vx"][1:], -0.5 * np.cos(th), atol=1e-12)
+    assert np.allclose(r["vy"][1:], -0.5 * np.sin(th), atol=1e-12)
+    assert abs(r["vx"][0]) < 1e-12 and abs(r["vy"][0]) < 1e-12
