@@ -738,6 +738,49 @@ def measure_generation(torch):
     return res
 
 
+def measure_spring_pi(torch):
+    """Partially inlined adjacency (Ch.4 "SOA with Partial Inlining") on a
+    500 x 500 mesh with 250 hub nodes of about 64 extra springs each: for K
+    inline slots in {2, 4, 6, 8}, the block size and the step's kernel times
+    (spring_pi.force, spring_pi.node_update) over 50 frozen steps.  Slots
+    past K are read from the array outside the heap."""
+    import numpy as np
+
+    from inputs import hub_mesh
+    from paper_1908_05845_amd import smmo
+    from paper_1908_05845_amd.sims import SpringPiSim
+
+    print("extras: partial inlining setup", file=sys.stderr, flush=True)
+    mesh = hub_mesh(500, 500, hubs=250, hub_springs=64)
+    deg = (np.asarray(mesh["adj"]) >= 0).sum(axis=1)
+    res = {"workload": "spring mesh 500x500 with 250 hubs: %d nodes, %d springs, degree up to %d (mean %.2f)"
+                       % (deg.size, len(mesh["a"]), int(deg.max()), float(deg.mean())), "by_K": {}}
+    for K in (2, 4, 6, 8):
+        sim = SpringPiSim(mesh, 0.0, K, strain_limit=1e9)
+        heap = sim.heap
+        h, cs, cn = heap.h, heap.cls["Spring"], heap.cls["Node"]
+        sim.step(5)
+        n = 50
+        ev = events(torch, 2 * n + 1)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for i in range(n):
+            smmo.smmo_parallel_do(h, cs, sim.m_force, sim.args)
+            ev[2 * i + 1].record()
+            smmo.smmo_parallel_do(h, cn, sim.m_node, sim.args)
+            ev[2 * i + 2].record()
+        torch.cuda.synchronize()
+        tf = sum(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(n)) * 1e3 / n
+        tn = sum(ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) for i in range(n)) * 1e3 / n
+        res["by_K"][str(K)] = {"block_bytes": heap.block_bytes, "heap_mb": heap.nbytes / 1e6,
+                               "out_of_line_slots": int(sim.args.overflow_len),
+                               "force_us": tf, "node_update_us": tn, "step_us": tf + tn,
+                               "device_error": heap.stats().device_error}
+        heap.close()
+        del sim
+    return res
+
+
 def measure_linux_scalability(torch):
     """Linux Scalability pattern (Ch.8 "Raw Allocation Performance") in SMMO
     form: a 1 GiB heap, 16,384 Worker objects each allocate n 64-byte Obj
@@ -1360,6 +1403,7 @@ def main():
         extras["gol_16384"] = measure_gol_large(torch)
         extras["structure"] = measure_structure(torch)
         extras["generation"] = measure_generation(torch)
+        extras["partial_inlining"] = measure_spring_pi(torch)
         tuned = res.get("autotune") or {}
         extras["spring_2000"] = measure_spring_large(torch, tuned if tuned.get("kept") == "tuned" else None)
         extras["nbody"] = measure_nbody_extra(torch)

@@ -74,6 +74,29 @@ typedef struct {
     uint32_t flags;              /* 0 or SMMO_SPRING_TENSION_ONLY; other bits: SMMO_EINVAL */
 } smmo_spring_args;
 
+/* ---- spring-mass mesh with partially inlined adjacency --------------------
+ * The adjacency of a node is an inner array whose first K slots are inlined
+ * as SOA arrays in the node's block and whose other slots live outside the
+ * heap (Ch.4 sec.4.3.1 "SOA with Partial Inlining"), for meshes of
+ * high-degree nodes:
+ * Node   {x, y, vx, vy, m: F32, adj: HANDLE x K, more: I32, cap: I32}
+ *        slots 0..cap-1 of the node: q < K in adj[q], q >= K in
+ *        overflow[more + q - K]; entries as for "spring.*" (spring handle |
+ *        1 << 31 if this node is the spring's endpoint b, SMMO_NULL empty)
+ * Spring {a, b: HANDLE, k, L0, fx, fy: F32, slot_a, slot_b: U8}
+ * "spring_pi.force", "spring_pi.node_update", "spring_pi.link": the methods
+ * "spring.force", "spring.node_update" and "spring.link" (two-sided Hooke's
+ * law, the float32 strain break) with this slot storage.  A slot outside
+ * 0..cap-1 or an overflow index outside the array sets SMMO_EDEVICE. */
+typedef struct {
+    uint32_t node_class;
+    uint32_t spring_class;
+    float dt;
+    float strain_limit;
+    uint32_t *overflow;          /* device array of the out-of-line slots */
+    uint64_t overflow_len;       /* its entries */
+} smmo_spring_pi_args;
+
 /* ---- reverse mode through the spring-mesh step (breaking off) ------------
  * Node   additionally {lx, ly, lvx, lvy, wx, wy: F32, id: I32}
  *        (dL/dx, dL/dv and the weighted velocity adjoint w = M^-1 mu)

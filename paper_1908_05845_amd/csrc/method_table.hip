@@ -25,6 +25,11 @@ smmo_status launch_spring_force(smmo_heap *h, uint32_t cls, const void *args, hi
 smmo_status launch_spring_node_update(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_spring_link(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 
+// launchers defined in spring_pi.hip
+smmo_status launch_spring_pi_force(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_spring_pi_node_update(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_spring_pi_link(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+
 // launchers defined in generation.hip
 smmo_status launch_generation_cell_count(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_generation_cell_birth(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
@@ -89,6 +94,9 @@ const MethodEntry kMethods[] = {
     {"wator.shark_update", sizeof(smmo_wator_args), launch_wator_shark_update},
     {"wator.cell_link", sizeof(smmo_wator_args), launch_wator_cell_link},
     {"wator.link", sizeof(smmo_wator_args), launch_wator_link},
+    {"spring_pi.force", sizeof(smmo_spring_pi_args), launch_spring_pi_force},
+    {"spring_pi.node_update", sizeof(smmo_spring_pi_args), launch_spring_pi_node_update},
+    {"spring_pi.link", sizeof(smmo_spring_pi_args), launch_spring_pi_link},
     {"generation.cell_count", sizeof(smmo_generation_args), launch_generation_cell_count},
     {"generation.cell_birth", sizeof(smmo_generation_args), launch_generation_cell_birth},
     {"generation.alive_update", sizeof(smmo_generation_args), launch_generation_alive_update},

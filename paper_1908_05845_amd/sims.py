@@ -105,6 +105,99 @@ class GolSim:
         return state, count, np.sort(_np(a["cell_id"]))
 
 
+def spring_pi_classes(K: int) -> dict:
+    """Node and Spring classes of a mesh whose node adjacency keeps K slots
+    inline (the rest outside the heap)."""
+    return {
+        "Node": [("x", "f32", 1), ("y", "f32", 1), ("vx", "f32", 1), ("vy", "f32", 1), ("m", "f32", 1),
+                 ("adj", "handle", K), ("more", "i32", 1), ("cap", "i32", 1), ("id", "i32", 1)],
+        "Spring": [("a", "handle", 1), ("b", "handle", 1), ("k", "f32", 1), ("L0", "f32", 1), ("fx", "f32", 1),
+                   ("fy", "f32", 1), ("slot_a", "u8", 1), ("slot_b", "u8", 1), ("id", "i32", 1)],
+    }
+
+
+class SpringPiSim:
+    """Spring-mass mesh of any node degree with partially inlined adjacency
+    (thesis Ch.4 sec.4.3.1): the first K slots of a node in its block, the
+    other slots in one device array, each node's at an offset `more`."""
+
+    def __init__(self, mesh: dict, dt: float, K: int, strain_limit: float = 0.3, cfg=None, extra_blocks: int = 16):
+        import torch
+
+        adj = np.asarray(mesh["adj"], np.int32)
+        N = int(np.asarray(mesh["x"]).size)
+        adj = adj.reshape(N, -1)
+        used = adj >= 0
+        cap = np.where(used.any(axis=1), adj.shape[1] - np.argmax(used[:, ::-1], axis=1), 0).astype(np.int32)
+        extra = np.maximum(cap - K, 0).astype(np.int64)
+        more = (np.cumsum(extra) - extra).astype(np.int32)
+        S = int(np.asarray(mesh["a"]).size)
+        self.N, self.S, self.K, self.D = N, S, K, adj.shape[1]
+        self.cap, self.more = cap, more
+        self.heap = smmo.Heap(spring_pi_classes(K), blocks=_blocks(N) + _blocks(S) + extra_blocks, cfg=cfg)
+        dev = self.heap.buf.device
+        f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+        i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
+        self.overflow = torch.full((max(int(extra.sum()), 1),), -1, dtype=torch.int32, device=dev)
+        self.node_h = self.heap.new("Node", N, x=f32(mesh["x"]), y=f32(mesh["y"]), vx=f32(mesh["vx"]),
+                                    vy=f32(mesh["vy"]), m=f32(mesh["m"]),
+                                    adj=torch.full((N * K,), -1, dtype=torch.int32, device=dev),
+                                    more=i32(more), cap=i32(cap), id=i32(np.arange(N))).clone()
+        u8 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint8)).to(dev)
+        if S:
+            a_idx = torch.from_numpy(np.asarray(mesh["a"], np.int64)).to(dev)
+            b_idx = torch.from_numpy(np.asarray(mesh["b"], np.int64)).to(dev)
+            self.heap.new("Spring", S, a=self.node_h[a_idx], b=self.node_h[b_idx], k=f32(mesh["k"]),
+                          L0=f32(mesh["L0"]), slot_a=u8(mesh["slot_a"]), slot_b=u8(mesh["slot_b"]),
+                          id=i32(np.arange(S)))
+        self.args = smmo.smmo_spring_pi_args(self.heap.cls["Node"], self.heap.cls["Spring"], dt, strain_limit,
+                                             self.overflow.data_ptr(), int(extra.sum()))
+        self.m_force = smmo.smmo_method_id("spring_pi.force")
+        self.m_node = smmo.smmo_method_id("spring_pi.node_update")
+        if S:
+            smmo.smmo_parallel_do(self.heap.h, self.heap.cls["Spring"], smmo.smmo_method_id("spring_pi.link"),
+                                  self.args)
+
+    def step(self, n: int = 1, stream=None):
+        h, cs, cn = self.heap.h, self.heap.cls["Spring"], self.heap.cls["Node"]
+        for _ in range(n):
+            smmo.smmo_parallel_do(h, cs, self.m_force, self.args, stream)
+            smmo.smmo_parallel_do(h, cn, self.m_node, self.args, stream)
+
+    def read(self) -> dict:
+        """Node arrays by id; adjacency (N, D) as spring ids (-1 empty, -2 a
+        handle of no live spring), from the inline and out-of-line slots."""
+        N, S, K, D = self.N, self.S, self.K, self.D
+        gs = self.heap.gather("Spring", ["id", "fx", "fy"])
+        sid = _np(gs["id"])
+        sh = _np(gs["_handle"]).astype(np.int64)
+        out = {"alive": np.zeros(S, np.uint8), "fx": np.zeros(S, np.float32), "fy": np.zeros(S, np.float32)}
+        out["alive"][sid] = 1
+        out["fx"][sid] = _np(gs["fx"])
+        out["fy"][sid] = _np(gs["fy"])
+        gn = self.heap.gather("Node", ["id", "x", "y", "vx", "vy", "m", "adj"])
+        order = np.argsort(_np(gn["id"]))
+        for key in ("x", "y", "vx", "vy", "m"):
+            out[key] = _np(gn[key])[order]
+        raw = np.full((N, D), 0xFFFFFFFF, np.int64)
+        raw[:, :min(K, D)] = (_np(gn["adj"]).reshape(-1, K)[order].astype(np.int64) & 0xFFFFFFFF)[:, :min(K, D)]
+        ovf = _np(self.overflow).astype(np.int64) & 0xFFFFFFFF
+        for i in np.flatnonzero(self.cap > K):
+            raw[i, K:self.cap[i]] = ovf[self.more[i]:self.more[i] + self.cap[i] - K]
+        used = raw != 0xFFFFFFFF
+        hh = raw & 0x7FFFFFFF
+        hs = np.argsort(sh)
+        sh_sorted, sid_sorted = sh[hs], sid[hs]
+        if sh_sorted.size:
+            pos = np.clip(np.searchsorted(sh_sorted, hh), 0, sh_sorted.size - 1)
+            adj = np.where(used, np.where(sh_sorted[pos] == hh, sid_sorted[pos], -2), -1)
+        else:
+            adj = np.where(used, -2, -1)
+        out["adj"] = adj.astype(np.int32)
+        out["adj_is_b"] = np.where(used, raw >> 31, 0).astype(np.uint8)
+        return out
+
+
 def _rule_mask(counts) -> int:
     m = 0
     for c in counts:

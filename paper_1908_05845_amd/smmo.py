@@ -111,6 +111,11 @@ class smmo_wator_args(C.Structure):
                 ("reserved", C.c_uint32), ("cells", C.c_void_p)]
 
 
+class smmo_spring_pi_args(C.Structure):
+    _fields_ = [("node_class", C.c_uint32), ("spring_class", C.c_uint32), ("dt", C.c_float),
+                ("strain_limit", C.c_float), ("overflow", C.c_void_p), ("overflow_len", C.c_uint64)]
+
+
 class smmo_generation_args(C.Structure):
     _fields_ = [("cell_class", C.c_uint32), ("alive_class", C.c_uint32), ("width", C.c_int32),
                 ("height", C.c_int32), ("survive", C.c_uint32), ("birth", C.c_uint32), ("dying", C.c_int32),

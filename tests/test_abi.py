@@ -131,7 +131,8 @@ def test_method_ids(lib):
              "adjoint.load", "adjoint.seed", "adjoint.zero", "adjoint.node", "adjoint.spring", "test.axpy",
              "test.destroy_if", "test.spawn", "alloc.ls_alloc", "alloc.ls_free", "wator.cell_prepare",
              "wator.fish_prepare", "wator.shark_prepare", "wator.cell_decide", "wator.fish_update",
-             "wator.shark_update", "wator.cell_link", "wator.link", "generation.cell_count",
+             "wator.shark_update", "wator.cell_link", "wator.link", "spring_pi.force", "spring_pi.node_update",
+             "spring_pi.link", "generation.cell_count",
              "generation.cell_birth", "generation.alive_update", "structure.pull", "structure.force",
              "structure.node_update", "structure.bfs_init", "structure.bfs_visit", "structure.bfs_mark",
              "structure.bfs_delete", "structure.link"]
@@ -165,5 +166,6 @@ def test_struct_sizes_match_header(lib):
     assert C.sizeof(smmo.smmo_wator_args) == 64
     assert C.sizeof(smmo.smmo_structure_args) == 32
     assert C.sizeof(smmo.smmo_generation_args) == 40
+    assert C.sizeof(smmo.smmo_spring_pi_args) == 32
     assert C.sizeof(smmo.smmo_config) == 64
     assert C.sizeof(smmo.smmo_adjoint_args) == 80
