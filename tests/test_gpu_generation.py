@@ -64,3 +64,28 @@ def test_rule_masks_validated(dev):
         setattr(bad, field, value)
         with pytest.raises(smmo.SmmoError):
             smmo.smmo_parallel_do(sim.heap.h, sim.heap.cls["Cell"], sim.m_count, bad)
+
+
+def test_graph_replays_match_the_oracle(dev):
+    """Twelve generations in one HIP graph (the bench's launch form), replayed
+    five times with eager reads in between; dying 7 so that cells expire
+    within the replays."""
+    import torch
+
+    W, H, D = 80, 64, 7
+    init = gol_init(W, H, seed=13)
+    sim = GenerationSim(W, H, init, dying=D)
+    state, left = init.copy(), np.zeros(W * H, np.int32)
+    sim.step(2)
+    state, left = generation_steps(W, H, state, left, 2, dying=D)
+    sim.heap.sync()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sim.step(12, stream=torch.cuda.current_stream())
+    for r in range(5):
+        g.replay()
+        torch.cuda.synchronize()
+        state, left = generation_steps(W, H, state, left, 12, dying=D)
+        s, lf, na = sim.read()
+        assert np.array_equal(s, state) and np.array_equal(lf, left), r
+        assert na == int(np.count_nonzero(state))
