@@ -279,24 +279,44 @@ def bench_spring(args, torch):
     half = steps // 2
     ms = 0.0
     wall = 0.0
+    seg_ms = []      # five event-bounded segments per half (whole graph replays)
+    seg_steps = []
     for part, n in enumerate((half, steps - half)):
         torch.cuda.synchronize()
         e0, e1 = events(torch, 2)
+        bounds = []
         t0 = time.perf_counter()
         e0.record()
         if graph is not None:
-            for _ in range(n // G):
+            reps = n // G
+            cut = {max(1, round(reps * (j + 1) / 5)) for j in range(5)} if reps else set()
+            for r in range(reps):
                 graph.replay()
+                if r + 1 in cut:
+                    ev = events(torch, 1)[0]
+                    ev.record()
+                    bounds.append((ev, (r + 1) * G))
             for _ in range(n % G):
                 step()
         else:
-            for _ in range(n):
+            cut = {max(1, round(n * (j + 1) / 5)) for j in range(5)} if n else set()
+            for i in range(n):
                 step()
+                if i + 1 in cut:
+                    ev = events(torch, 1)[0]
+                    ev.record()
+                    bounds.append((ev, i + 1))
         e1.record()
         counted(n)
         torch.cuda.synchronize()
         wall += time.perf_counter() - t0
         ms += e0.elapsed_time(e1)
+        prev_ev, prev_n = e0, 0
+        for ev, k in bounds:
+            if k > prev_n:
+                seg_ms.append(prev_ev.elapsed_time(ev))
+                seg_steps.append(k - prev_n)
+            prev_ev, prev_n = ev, k
         if part == 0:
             t_force, t_node, s_mid = kernel_pass()
     heap.sync()
@@ -355,6 +375,12 @@ def bench_spring(args, torch):
     }
     if defrag is not None:
         res["defrag"] = defrag
+    if seg_ms:
+        rates = sorted(k * (springs_mean + live0[1]) / (t * 1e-3) for k, t in zip(seg_steps, seg_ms) if t > 0)
+        res["segments"] = {"note": "the timed steps in event-bounded segments (five per half); rates at the "
+                                   "run's mean live springs", "count": len(rates),
+                           "median_updates_per_s": float(np.median(rates)), "min_updates_per_s": rates[0],
+                           "max_updates_per_s": rates[-1]}
 
     def cpu_leg():
         from oracle import spring_steps
@@ -1430,7 +1456,7 @@ def main():
         "roofline": res["roofline"],
         "cpu_baseline": cpu,
     }
-    for k in ("step_hbm", "kernels", "autotune", "launch", "trace_window", "device_error", "defrag"):
+    for k in ("step_hbm", "kernels", "autotune", "launch", "trace_window", "device_error", "defrag", "segments"):
         if k in res:
             line[k] = res[k]
     line.update(extras)
