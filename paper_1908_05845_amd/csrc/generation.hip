@@ -24,6 +24,14 @@ struct GenK {
     uint32_t a_id, a_left, a_new;      // Alive fields
 };
 
+// a Cell handle from the caller's grid array names a block of the heap
+__device__ __forceinline__ bool gen_valid(const HeapView &h, uint32_t handle)
+{
+    if ((handle >> 6) < h.M) return true;
+    raise_error(h, ERR_BADHANDLE);
+    return false;
+}
+
 // Cell::count - live neighbours on the torus (dying cells do not count).
 // One integer division per cell, neighbour wrap-around by compare and select,
 // two blocks per wavefront iteration (as the Game of Life's count).
@@ -32,6 +40,7 @@ __global__ __launch_bounds__(1024) void k_gen_count(HeapView h, GenK p)
 {
     if (heap_failed(h)) return;
     const uint32_t s = lane_id();
+    bool bad = false;                  // a cell id outside the grid or a handle outside the heap
     for_each_block_group<U>(h, p.cell_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
         bool live[U];
         int32_t id[U];
@@ -39,6 +48,10 @@ __global__ __launch_bounds__(1024) void k_gen_count(HeapView h, GenK p)
         for (int j = 0; j < U; ++j) {
             live[j] = (bm[j] >> s) & 1;
             id[j] = live[j] ? farr<int32_t>(h, bid[j], p.c_id)[s] : 0;
+            if (live[j] && (uint32_t)id[j] >= (uint32_t)(p.W * p.H)) {
+                bad = true;                        // a cell id outside the grid
+                live[j] = false;
+            }
         }
         uint32_t hc[U][8];
 #pragma unroll
@@ -53,7 +66,12 @@ __global__ __launch_bounds__(1024) void k_gen_count(HeapView h, GenK p)
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
                     if (dx == 1 && dy == 1) continue;
-                    hc[j][k++] = live[j] ? p.cells[rows[dy] + xs[dx]] : kNull;
+                    uint32_t c = live[j] ? p.cells[rows[dy] + xs[dx]] : 0u;
+                    if ((c >> 6) >= h.M) {          // not a handle of this heap: read block 0 instead
+                        bad = true;
+                        c = 0;
+                    }
+                    hc[j][k++] = c;
                 }
         }
 #pragma unroll
@@ -65,6 +83,9 @@ __global__ __launch_bounds__(1024) void k_gen_count(HeapView h, GenK p)
             farr<int32_t>(h, bid[j], p.c_count)[s] = n;
         }
     });
+    // reported once, after the walk
+    if (__ballot(bad) && s == (uint32_t)(__ffsll((unsigned long long)__ballot(bad)) - 1))
+        raise_error(h, ERR_BADHANDLE);
 }
 
 // Cell::birth - an empty cell with a count in the birth set comes alive
@@ -99,10 +120,15 @@ __global__ __launch_bounds__(1024) void k_gen_alive_update(HeapView h, GenK p)
     if (heap_failed(h)) return;
     for_each_object_packed(h, p.alive_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         bool gone = false;
+        const int32_t cid = live ? farr<int32_t>(h, bid, p.a_id)[s] : 0;
+        if (live && ((uint32_t)cid >= (uint32_t)(p.W * p.H) || !gen_valid(h, p.cells[cid]))) {
+            raise_error(h, ERR_BADHANDLE);
+            live = false;
+        }
         if (live) {
             uint8_t &fresh = farr<uint8_t>(h, bid, p.a_new)[s];
             int32_t &left = farr<int32_t>(h, bid, p.a_left)[s];
-            const uint32_t hc = p.cells[farr<int32_t>(h, bid, p.a_id)[s]];
+            const uint32_t hc = p.cells[cid];
             if (fresh) {
                 fresh = 0;
             } else if (left == 0) {

@@ -33,6 +33,14 @@ struct GolK {
     uint32_t a_id;                     // Alive field offset
 };
 
+// a Cell handle from the caller's grid array names a block of the heap
+__device__ __forceinline__ bool gol_valid(const HeapView &h, uint32_t handle)
+{
+    if ((handle >> 6) < h.M) return true;
+    raise_error(h, ERR_BADHANDLE);
+    return false;
+}
+
 // Cell::count - live cells among the 8 neighbours on the torus.  One
 // integer division per cell (gfx950 has no integer divide instruction); the
 // wrap-around of the neighbour coordinates is a compare and select.  U
@@ -44,6 +52,7 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 {
     if (heap_failed(h)) return;
     const uint32_t s = lane_id();
+    bool bad = false;                  // a cell id outside the grid or a handle outside the heap
     for_each_block_group<U>(h, p.cell_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
         bool live[U];
         int32_t id[U];
@@ -51,6 +60,10 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
         for (int j = 0; j < U; ++j) {
             live[j] = (bm[j] >> s) & 1;
             id[j] = live[j] ? farr<int32_t>(h, bid[j], p.c_id)[s] : 0;
+            if (live[j] && (uint32_t)id[j] >= (uint32_t)(p.W * p.H)) {
+                bad = true;                        // a cell id outside the grid
+                live[j] = false;
+            }
         }
         uint32_t hc[U][8];
 #pragma unroll
@@ -65,7 +78,12 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
                     if (dx == 1 && dy == 1) continue;
-                    hc[j][k++] = live[j] ? p.cells[rows[dy] + xs[dx]] : kNull;
+                    uint32_t c = live[j] ? p.cells[rows[dy] + xs[dx]] : 0u;
+                    if ((c >> 6) >= h.M) {          // not a handle of this heap: read block 0 instead
+                        bad = true;
+                        c = 0;
+                    }
+                    hc[j][k++] = c;
                 }
         }
 #pragma unroll
@@ -78,6 +96,9 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
             if (live[j]) farr<int32_t>(h, bid[j], p.c_count)[s] = n;
         }
     });
+    // reported once, after the walk
+    if (__ballot(bad) && s == (uint32_t)(__ffsll((unsigned long long)__ballot(bad)) - 1))
+        raise_error(h, ERR_BADHANDLE);
 }
 
 // Alive::death - if the cell's count is not 2 or 3: cell dies, delete this
@@ -87,8 +108,12 @@ __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
     if (heap_failed(h)) return;
     for_each_object_packed(h, p.alive_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         bool die = false;
+        const int32_t cid = live ? farr<int32_t>(h, bid, p.a_id)[s] : 0;
+        if (live && ((uint32_t)cid >= (uint32_t)(p.W * p.H) || !gol_valid(h, p.cells[cid]))) {
+            raise_error(h, ERR_BADHANDLE);
+            live = false;
+        }
         if (live) {
-            const int32_t cid = farr<int32_t>(h, bid, p.a_id)[s];
             const uint32_t hc = p.cells[cid];
             const int32_t n = fref<int32_t>(h, hc, p.c_count);
             if (n != 2 && n != 3) {
@@ -127,7 +152,8 @@ smmo_status bind_gol(smmo_heap *h, const smmo_gol_args &a, GolK &k)
     if (a.cell_class >= h->schema->nclasses || a.alive_class >= h->schema->nclasses ||
         a.cell_class == a.alive_class)
         return fail(SMMO_EINVAL, "gol: bad class ids");
-    if (!a.cells || a.width <= 0 || a.height <= 0) return fail(SMMO_EINVAL, "gol: bad grid");
+    if (!a.cells || a.width <= 0 || a.height <= 0 || (int64_t)a.width * a.height > 0x7FFFFFFF)
+        return fail(SMMO_EINVAL, "gol: bad grid");
     k.cell_cls = a.cell_class;
     k.alive_cls = a.alive_class;
     k.cells = a.cells;

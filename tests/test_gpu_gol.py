@@ -95,3 +95,18 @@ def test_graph_replays_match_the_oracle(dev):
         gs, gc, ga = sim.read()
         rs, rc, ra = ref.read()
         assert np.array_equal(gs, rs) and np.array_equal(gc, rc) and np.array_equal(ga, ra), r
+
+
+def test_cell_ids_outside_the_grid_are_a_device_error(dev):
+    """A Cell whose id lies outside the W x H grid (a caller's mistake) is
+    reported as SMMO_EDEVICE; the kernels do not read past the grid array."""
+    import torch
+
+    W = H = 8
+    sim = GolSim(W, H, gol_init(W, H, seed=3))
+    bad = torch.tensor([W * H + 5], dtype=torch.int32, device=dev)
+    sim.heap.new("Cell", 1, cell_id=bad)
+    smmo.smmo_parallel_do(sim.heap.h, sim.heap.cls["Cell"], sim.m_count, sim.args)
+    with pytest.raises(smmo.SmmoError) as e:
+        sim.heap.sync()
+    assert e.value.status == smmo.SMMO_EDEVICE
