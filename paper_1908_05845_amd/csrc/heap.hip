@@ -290,14 +290,15 @@ __global__ __launch_bounds__(1024) void k_bulk_claim(HeapView h, uint32_t cls, u
         const uint32_t p = block_excl_scan(k, s_w, T);
         if (k && found + p < need) {
             const uint32_t take = std::min(k, need - found - p);
-            uint64_t bits = lowest_bits(v, take);
-            F0[c] = v & ~bits;
+            const uint64_t taken = lowest_bits(v, take);
+            F0[c] = v & ~taken;
+            // the container's blocks join allocated[cls] with one OR per level
+            aor(h.bm_word(bm_alloc(cls), 0, c), taken);
+            for (uint32_t l = 1; l < h.nlev; ++l)
+                aor(h.bm_word(bm_alloc(cls), l, c >> (6 * l)), 1ull << ((c >> (6 * (l - 1))) & 63));
             uint32_t o = found + p;
-            while (bits) {
-                const uint32_t b = (uint32_t)(__ffsll((unsigned long long)bits) - 1);
-                bits &= bits - 1;
-                h.claim[o++] = c * 64 + b;
-            }
+            for (uint64_t bits = taken; bits; bits &= bits - 1)
+                h.claim[o++] = c * 64 + (uint32_t)(__ffsll((unsigned long long)bits) - 1);
             atomicMin(&s_lo, c);
             atomicMax(&s_hi, c);
         }
@@ -318,19 +319,26 @@ __global__ __launch_bounds__(1024) void k_bulk_claim(HeapView h, uint32_t cls, u
         }
         __syncthreads();
     }
-    for (uint32_t i = t; i < need; i += blockDim.x) {
+    // the partly filled last block is active (it has free slots)
+    if (partial && t == 0) {
+        uint32_t pos = h.claim[need - 1];
+        for (uint32_t l = 0; l < h.nlev; ++l, pos >>= 6)
+            aor(h.bm_word(bm_active(cls), l, pos >> 6), 1ull << (pos & 63));
+    }
+}
+
+// Block headers of the claimed blocks (type, allocation bitmap): one thread
+// per block, any number of work-groups.  The heap is quiescent during a bulk
+// parallel_new, so the launch boundaries order these stores against the
+// bitmaps written by k_bulk_claim.
+__global__ __launch_bounds__(256) void k_bulk_headers(HeapView h, uint32_t cls, uint32_t need, uint32_t partial)
+{
+    if (heap_failed(h)) return;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < need; i += gridDim.x * blockDim.x) {
         const uint32_t bid = h.claim[i];
         const bool full = !(partial && i == need - 1);
         h.type[bid] = cls;
         h.alloc_bm[bid] = full ? ~0ull : ((1ull << partial) - 1);
-        uint32_t pos = bid;
-        for (uint32_t l = 0; l < h.nlev; ++l, pos >>= 6)
-            aor(h.bm_word(bm_alloc(cls), l, pos >> 6), 1ull << (pos & 63));
-        if (!full) {
-            pos = bid;
-            for (uint32_t l = 0; l < h.nlev; ++l, pos >>= 6)
-                aor(h.bm_word(bm_active(cls), l, pos >> 6), 1ull << (pos & 63));
-        }
     }
 }
 
@@ -939,6 +947,9 @@ smmo_status smmo_parallel_new(smmo_heap *h, uint32_t class_id, uint32_t n, const
         const uint32_t need = (uint32_t)(((uint64_t)n + 63) / 64);
         hipLaunchKernelGGL(k_bulk_claim, dim3(1), dim3(1024), 0, st, h->v, class_id, need, n % 64);
         if ((s = launch_check("k_bulk_claim"))) return s;
+        const uint32_t hgrid = (uint32_t)std::min<uint64_t>((need + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_bulk_headers, dim3(hgrid), dim3(256), 0, st, h->v, class_id, need, n % 64);
+        if ((s = launch_check("k_bulk_headers"))) return s;
         hipLaunchKernelGGL(k_bulk_init, dim3(grid), dim3(256), 0, st, h->v, fs, n, out_handles);
         if ((s = launch_check("k_bulk_init"))) return s;
     } else {
