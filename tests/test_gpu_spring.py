@@ -124,12 +124,24 @@ def test_everything_breaks(dev, group):
     assert st.live_objects[spr] == int(sim.read()["alive"].sum())
 
 
-def test_config_1000x1000_checked_steps(dev):
-    print("spring 1000x1000", flush=True)
+# launch shapes (work-group threads, wavefronts, blocks per iteration) of the
+# timed 1000 x 1000 run: the library's defaults, and the shapes the autotuner
+# kept for the committed reference measurement
+SHAPES_1000 = {"default": None,
+               "tuned": {"spring.force": (64, 16384, 2), "spring.node_update": (128, 32768, 1)}}
+
+
+@pytest.mark.parametrize("shapes", sorted(SHAPES_1000))
+def test_config_1000x1000_checked_steps(dev, shapes):
+    print("spring 1000x1000 shapes", shapes, flush=True)
     mesh = spring_mesh(1000, 1000)
     assert mesh["N"] == 1_000_000 and mesh["S"] == 2_996_001
     dt, limit = 1e-5, 0.3
     sim = SpringSim(mesh, dt, limit)
+    if SHAPES_1000[shapes]:
+        for name, shape in SHAPES_1000[shapes].items():
+            cls = sim.heap.cls["Spring" if name == "spring.force" else "Node"]
+            smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), cls, *shape)
     checks = (0, 1, 10, 1000, 3000, 9999)
     step = 0
     broken = 0
