@@ -374,3 +374,43 @@ def test_packed_do_all_on_sparse_blocks(dev, keep_frac, seed, packing, waves):
     model = model[model % 3 != 1]
     assert np.array_equal(keys_of(heap), model)
     clean(heap)
+
+
+def test_maximum_heap_size(dev):
+    """A heap of the largest block count (2^25 - 2 blocks, 2,147,483,520
+    slots): an ordered bulk allocation of every slot gives the handles 0 ..
+    n-1 (bit 31 stays clear), one more object is out of memory, a do-all over
+    all of them and a self-deleting do-all keep counts and invariants, and a
+    sampled gather reads the do-all's result."""
+    import torch
+
+    M = (1 << 25) - 2
+    n = 64 * M
+    print("max heap: %d blocks, %d objects" % (M, n), flush=True)
+    heap = smmo.Heap({"A": [("x", "f32", 1), ("key", "i32", 1)]}, blocks=M)
+    assert heap.blocks == M
+    key = torch.arange(n, dtype=torch.int32, device=dev)
+    hd = heap.new("A", n, x=key.float(), key=key)
+    assert torch.equal(hd, key) and int(hd.max().item()) < (1 << 31)
+    del hd
+    assert heap.stats().free_blocks == 0
+    # no free block left: the device reports the allocation at the next sync
+    heap.new("A", 1, key=torch.zeros(1, dtype=torch.int32, device=dev))
+    with pytest.raises(smmo.SmmoError) as e:
+        heap.sync()
+    assert e.value.status == smmo.SMMO_ENOMEM
+    smmo.smmo_clear_error(heap.h)
+    assert heap.stats().live_objects[heap.cls["A"]] == n
+    heap.do("A", "test.axpy", smmo.smmo_axpy_args(2.0, 1.0))
+    g = heap.gather("A", ["x", "key"], capacity=1 << 20)
+    assert g["_count"] == n
+    k = g["key"].double()
+    assert torch.equal(g["x"].double(), (2.0 * k.float().double() + 1.0).float().double())
+    heap.do("A", "test.destroy_if", smmo.smmo_destroy_if_args(3, 1))
+    st = heap.stats()
+    want = n - len(range(1, n, 3))
+    assert st.live_objects[heap.cls["A"]] == want and st.device_error == 0
+    clean(heap)
+    heap.close()
+    del heap, key, g, k
+    torch.cuda.empty_cache()
