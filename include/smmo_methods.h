@@ -145,7 +145,13 @@ typedef struct {
  *                   target_class (which must have an I32 field "key") with
  *                   key = key * key_mul + key_add + c, c = 0 .. copies-1.
  *                   target_class may be the running class: the new objects
- *                   are not visited by the same launch.                     */
+ *                   are not visited by the same launch.
+ * "test.transmute" on any class with I32 field "key", arguments as
+ *                   "test.spawn" with a target_class other than the running
+ *                   class: a selected object creates its copies and then
+ *                   deletes itself, so blocks emptied by one wavefront can be
+ *                   taken by another wavefront's allocations of the other
+ *                   class within the same launch.                           */
 typedef struct {
     float a;
     float b;

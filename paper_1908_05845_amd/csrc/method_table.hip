@@ -17,6 +17,7 @@ smmo_status launch_nbody_update(smmo_heap *h, uint32_t cls, const void *args, hi
 smmo_status launch_test_axpy(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_test_destroy_if(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_test_spawn(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_test_transmute(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_ls_alloc(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_ls_free(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 
@@ -84,6 +85,7 @@ const MethodEntry kMethods[] = {
     {"test.axpy", sizeof(smmo_axpy_args), launch_test_axpy},
     {"test.destroy_if", sizeof(smmo_destroy_if_args), launch_test_destroy_if},
     {"test.spawn", sizeof(smmo_spawn_args), launch_test_spawn},
+    {"test.transmute", sizeof(smmo_spawn_args), launch_test_transmute},
     {"alloc.ls_alloc", sizeof(smmo_ls_args), launch_ls_alloc},
     {"alloc.ls_free", sizeof(smmo_ls_args), launch_ls_free},
     {"wator.cell_prepare", sizeof(smmo_wator_args), launch_wator_cell_prepare},

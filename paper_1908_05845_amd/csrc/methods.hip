@@ -433,6 +433,48 @@ __global__ __launch_bounds__(1024) void k_spawn(HeapView h, SpawnK p)
     });
 }
 
+// test.transmute: the selected objects create their copies of the other
+// class, then delete themselves (the replacement pattern of the thesis's
+// Game of Life, Alive -> Candidate)
+__global__ __launch_bounds__(1024) void k_transmute(HeapView h, SpawnK p)
+{
+    if (heap_failed(h)) return;
+    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
+        const uint32_t s = lane_id();
+        bool sel = false;
+        int32_t key = 0;
+        if ((bm >> s) & 1) {
+            key = farr<int32_t>(h, bid, p.o_key)[s];
+            int32_t m = key % p.mod;
+            if (m < 0) m += p.mod;
+            sel = m == p.rem;
+        }
+        for (uint32_t c = 0; c < p.copies; ++c) {
+            const uint32_t nh = wave_allocate(h, p.target, sel);
+            if (sel && nh != kNull) fref<int32_t>(h, nh, p.t_key) = key * p.mul + p.add + (int32_t)c;
+        }
+        wave_release_own_block(h, p.cls, bid, __ballot(sel));
+    });
+}
+
+smmo_status launch_transmute(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_spawn_args a;
+    memcpy(&a, args, sizeof a);
+    if (a.mod <= 0 || a.copies > 8 || a.target_class >= h->schema->nclasses || a.target_class == cls)
+        return fail(SMMO_EINVAL, "transmute: bad arguments");
+    SpawnK k{cls, a.target_class, 0, 0, a.mod, a.rem, a.key_mul, a.key_add, a.copies, 0u};
+    BIND(cls, "key", SMMO_I32, 1, &k.o_key, nullptr);
+    BIND(a.target_class, "key", SMMO_I32, 1, &k.t_key, nullptr);
+    smmo_status s = ensure_enumerated(h, cls, false, st);
+    if (s) return s;
+    const LaunchShape ls = method_shape(h, cls);
+    hipLaunchKernelGGL(k_transmute, ls.grid, ls.block, 0, st, h->v, k);
+    if ((s = launched("k_transmute"))) return s;
+    note_allocation(h, a.target_class, 64ull * h->v.M);
+    return SMMO_OK;
+}
+
 smmo_status launch_spawn(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
 {
     smmo_spawn_args a;
@@ -542,6 +584,7 @@ smmo_status launch_nbody_update(smmo_heap *h, uint32_t c, const void *a, hipStre
 smmo_status launch_test_axpy(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_axpy(h, c, a, s); }
 smmo_status launch_test_destroy_if(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_destroy_if(h, c, a, s); }
 smmo_status launch_test_spawn(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_spawn(h, c, a, s); }
+smmo_status launch_test_transmute(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_transmute(h, c, a, s); }
 smmo_status launch_ls_alloc(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_ls<0>(h, c, a, s); }
 smmo_status launch_ls_free(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_ls<1>(h, c, a, s); }
 } // namespace smmo

@@ -414,3 +414,48 @@ def test_maximum_heap_size(dev):
     heap.close()
     del heap, key, g, k
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("variant", [dict(), dict(rotation=0, lookup_retries=1), dict(coalescing=0),
+                                     dict(lookup_retries=1)])
+def test_blocks_change_class_within_a_launch(dev, variant):
+    """test.transmute moves selected objects between two classes in one
+    launch (create the replacement, then delete this), so blocks emptied by
+    self-deletions are invalidated and taken by the other class's
+    allocations while the launch still runs: the enumerated races of a block
+    replaced by another type, delete-last against allocate and re-activation.
+    The key sets of both classes must follow a model exactly, round after
+    round, with clean bitmaps; contention variants included."""
+    import torch
+
+    print("transmute", variant, flush=True)
+    # a small heap (100 blocks in use of 400) makes the classes take each
+    # other's freed blocks; the peak of a full transfer (the new class's
+    # blocks before the old ones are freed, plus a partly filled block per
+    # allocating wavefront) still fits.  Without rotation that fragmentation
+    # is larger, so that variant gets more headroom
+    blocks = 800 if variant.get("rotation", 1) == 0 else 400
+    heap = smmo.Heap(ALL, blocks=blocks, cfg=cfg(**variant))
+    n = 6400
+    heap.new("A", n, key=torch.arange(n, dtype=torch.int32, device=dev))
+    model = {"A": np.arange(n, dtype=np.int64), "B": np.zeros(0, np.int64)}
+    rng = np.random.default_rng(17)
+    for rnd in range(16):
+        src, dst = ("A", "B") if rnd % 2 == 0 else ("B", "A")
+        mod = int(rng.integers(1, 4))
+        rem = int(rng.integers(0, mod))
+        heap.do(src, "test.transmute", smmo.smmo_spawn_args(heap.cls[dst], mod, rem, 1, 1, 0))
+        sel = model[src] % mod == rem
+        model[dst] = np.sort(np.concatenate([model[dst], model[src][sel]]))
+        model[src] = model[src][~sel]
+        for c in ("A", "B"):
+            assert np.array_equal(keys_of(heap, c), model[c]), (variant, rnd, c)
+        clean(heap)
+    st = heap.stats()
+    if blocks == 400:
+        # more block initializations than blocks that were never used: freed
+        # blocks were taken again, by either class
+        assert st.slow_paths > blocks - n // 64, st.slow_paths
+    with pytest.raises(smmo.SmmoError):
+        heap.do("A", "test.transmute", smmo.smmo_spawn_args(heap.cls["A"], 1, 0, 1, 1, 0))
+    heap.close()
