@@ -1480,7 +1480,7 @@ def main():
         summarize_l2(args.summarize_l2)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)"
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus %d requested)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
