@@ -102,7 +102,8 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 }
 
 // Alive::death - if the cell's count is not 2 or 3: cell dies, delete this
-// (a packed do-all: the Alive class is the sparse one)
+// (a packed do-all, packed as the heap's sparse_packing setting asks: the
+// Alive class is the sparse one)
 __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
 {
     if (heap_failed(h)) return;
@@ -348,7 +349,8 @@ struct AxpyK {
     float a, b;
 };
 
-// packed do-all (sparse blocks two per wavefront)
+// packed do-all (sparse blocks two per wavefront where the heap's
+// sparse_packing setting asks for it)
 __global__ __launch_bounds__(1024) void k_axpy(HeapView h, AxpyK p)
 {
     if (heap_failed(h)) return;

@@ -341,7 +341,8 @@ smmo_status launch_wator(smmo_heap *h, uint32_t cls, const void *args, hipStream
                        (int64_t)a.width * a.height > 0x7FFFFFFF))
         return fail(SMMO_EINVAL, "wator.cell_link: bad grid");
     const bool snapshot = Which == 4 || Which == 5;
-    // the agent classes (fragmented by births and deaths) run packed do-alls
+    // the agent classes (fragmented by births and deaths) run packed do-alls,
+    // packed as the heap's sparse_packing setting asks
     const bool packed = Which == 1 || Which == 2 || Which == 4 || Which == 5;
     const LaunchShape ls = method_shape(h, cls);
     if ((s = ensure_enumerated(h, cls, snapshot, st, packed && packing_wanted(h, cls, ls)))) return s;
