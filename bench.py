@@ -536,7 +536,7 @@ def measure_adjoint(torch, plain_updates_per_s):
 
     t_default = min(sweep() for _ in range(3)) * 1e6
     tuned = {}
-    for method, cname, groups in (("spring.force", "Spring", (1, 2, 4)), ("spring.node_update", "Node", (1, 2, 4)),
+    for method, cname, groups in (("spring.force", "Spring", (1, 2, 4)), ("adjoint.step_node", "Node", (1, 2, 4)),
                                   ("adjoint.spring", "Spring", (0,)), ("adjoint.node", "Node", (0,))):
         r = autotune.tune(sim.heap, method, cname, None, groups=groups, timer=sweep,
                           waves_per_cu=(4, 8, 16, 64))
@@ -545,7 +545,7 @@ def measure_adjoint(torch, plain_updates_per_s):
     t_tuned = min(sweep() for _ in range(3)) * 1e6
     keep = t_tuned < t_default
     if not keep:
-        for method, cname in (("spring.force", "Spring"), ("spring.node_update", "Node"),
+        for method, cname in (("spring.force", "Spring"), ("adjoint.step_node", "Node"),
                               ("adjoint.spring", "Spring"), ("adjoint.node", "Node")):
             smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(method), sim.heap.cls[cname], 0, 0, 0)
     tuned.update(sweep_us_tuned=t_tuned, sweep_us_default=t_default, kept="tuned" if keep else "default")

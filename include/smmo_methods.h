@@ -117,6 +117,12 @@ typedef struct {
  *                             mode bit 1: mu, w, lv as above (bit 0 first)
  * "adjoint.spring" on Spring: c and gk with positions x_n read from tape
  *                             plane pair `slot`
+ * "adjoint.step_node" on Node: the node pass of the forward step (the update
+ *                             of "spring.node_update" from the Spring fields
+ *                             fx, fy that "spring.force" wrote); with a
+ *                             non-NULL tape the new (x, y) also go to tape
+ *                             plane pair `slot`, by handle (tape NULL: no
+ *                             tape, tape_floats and plane unused)
  * The tape holds planes of `plane` floats (plane >= 64 * heap blocks, one
  * float per handle); tape_floats is its capacity, checked on the host.
  * seed arrays have seed_count entries, indexed by the node's id field.     */

@@ -2,9 +2,11 @@
 
 ``DiffSpringSim`` runs the forward steps (breaking off) with (x, v)
 checkpoints every ``every`` steps and, given dL/dx_T, the reverse sweep:
-each segment is recomputed from its checkpoint while ``adjoint.record``
-writes the positions to a tape, then reversed step by step with the
-``adjoint.node`` / ``adjoint.spring`` methods.  All of it runs in libsmmo;
+each segment is recomputed from its checkpoint by the forward step whose
+node pass (``adjoint.step_node``) also writes the new positions to a tape,
+then reversed step by step with the ``adjoint.node`` / ``adjoint.spring``
+methods (the segment's first step reads its positions from the
+checkpoint).  All of it runs in libsmmo;
 this module only orders the calls.
 
 ``SpringRollout`` wraps it as a ``torch.autograd.Function`` of the spring
@@ -74,8 +76,8 @@ class DiffSpringSim:
         self.cn, self.cs = self.heap.cls["Node"], self.heap.cls["Spring"]
         self.fargs = smmo.smmo_spring_args(self.cn, self.cs, self.dt, math.inf)
         ids = {n: smmo.smmo_method_id(n) for n in (
-            "spring.force", "spring.node_update", "spring.link", "adjoint.record", "adjoint.save",
-            "adjoint.load", "adjoint.seed", "adjoint.zero", "adjoint.node", "adjoint.spring")}
+            "spring.force", "spring.link", "adjoint.record", "adjoint.save", "adjoint.load",
+            "adjoint.seed", "adjoint.zero", "adjoint.node", "adjoint.spring", "adjoint.step_node")}
         self.mid = ids
         if S:
             self._do(self.cs, "spring.link", self.fargs)
@@ -90,13 +92,20 @@ class DiffSpringSim:
         B = smmo.BoundLaunch
         hp = self.heap.h
         self.L_force = B(hp, self.cs, ids["spring.force"], self.fargs) if S else None
-        self.L_node = B(hp, self.cn, ids["spring.node_update"], self.fargs)
+        # the forward node pass: the same kernel as the recompute's, without a tape
+        self.L_node = B(hp, self.cn, ids["adjoint.step_node"], self._aargs(None))
         self.L_save = [B(hp, self.cn, ids["adjoint.save"], self._aargs(self.ckpt, slot=c)) for c in range(nck)]
         self.L_load = [B(hp, self.cn, ids["adjoint.load"], self._aargs(self.ckpt, slot=c)) for c in range(nck)]
-        self.L_record = [B(hp, self.cn, ids["adjoint.record"], self._aargs(self.tape, slot=t)) for t in range(seg)]
+        # recompute: step t of a segment writes the positions of step t + 1 to
+        # tape slot t + 1; the spring pass of step 0 reads the checkpoint's
+        # (x, y), its planes 4c, 4c + 1 being plane pair 2c of that tape
+        self.L_stepr = [B(hp, self.cn, ids["adjoint.step_node"], self._aargs(self.tape, slot=t))
+                        for t in range(seg)]
         self.L_anode = {m: B(hp, self.cn, ids["adjoint.node"], self._aargs(self.tape, mode=m)) for m in (1, 2, 3)}
         self.L_aspring = [B(hp, self.cs, ids["adjoint.spring"], self._aargs(self.tape, slot=t))
                           for t in range(seg)] if S else None
+        self.L_aspring0 = [B(hp, self.cs, ids["adjoint.spring"], self._aargs(self.ckpt, slot=2 * c))
+                           for c in range(nck)] if S else None
         self.L_zero = B(hp, self.cs, ids["adjoint.zero"], self._aargs(self.tape)) if S else None
 
     # ------------------------------------------------------------ helpers --
@@ -105,7 +114,8 @@ class DiffSpringSim:
 
     def _aargs(self, tape, slot=0, mode=0, seeds=(None, None, None, None), count=0):
         P = [0 if s is None else s.data_ptr() for s in seeds]
-        return smmo.smmo_adjoint_args(self.cn, self.cs, self.dt, mode, tape.data_ptr(), tape.numel(),
+        tp, tn = (None, 0) if tape is None else (tape.data_ptr(), tape.numel())
+        return smmo.smmo_adjoint_args(self.cn, self.cs, self.dt, mode, tp, tn,
                                       self.plane, slot, count, P[0] or None, P[1] or None,
                                       P[2] or None, P[3] or None)
 
@@ -177,15 +187,15 @@ class DiffSpringSim:
             n0 = seg * self.every
             n1 = min(n0 + self.every, self.T)
             self.L_load[seg](st)
-            for t in range(n1 - n0):
-                self.L_record[t](st)
-                if t < n1 - n0 - 1:       # the segment's last step is not needed
-                    self.step(st)
+            for t in range(n1 - n0 - 1):  # the segment's last step is not needed
+                if self.L_force is not None:
+                    self.L_force(st)
+                self.L_stepr[t + 1](st)
             for t in range(n1 - n0 - 1, -1, -1):
                 self.L_anode[2 if first else 3](st)
                 first = False
                 if self.L_aspring is not None:
-                    self.L_aspring[t](st)
+                    (self.L_aspring[t] if t else self.L_aspring0[seg])(st)
         if not first:
             self.L_anode[1](st)
 

@@ -4,9 +4,9 @@
 // pass's terms (in adjacency-slot order, no atomics) and then forms
 // mu = lv + dt lx and w = M^-1 mu; the Spring pass turns w into the terms
 // dt K g of both endpoints and accumulates dL/dk.  Positions of step n come
-// from a tape of planes indexed by node handle, filled by "adjoint.record"
-// while a segment is recomputed from an (x, v) checkpoint ("adjoint.save" /
-// "adjoint.load").
+// from a tape of planes indexed by node handle, filled by "adjoint.step_node"
+// (or "adjoint.record") while a segment is recomputed from an (x, v)
+// checkpoint ("adjoint.save" / "adjoint.load").
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -21,7 +21,7 @@ struct AdjK {
     uint32_t node_cls, spring_cls;
     uint32_t n_x, n_y, n_vx, n_vy, n_m, n_adj, n_adj_stride, n_id;
     uint32_t n_lx, n_ly, n_lvx, n_lvy, n_wx, n_wy;
-    uint32_t s_a, s_b, s_k, s_L0, s_cx, s_cy, s_gk;
+    uint32_t s_a, s_b, s_k, s_L0, s_cx, s_cy, s_gk, s_fx, s_fy;
     float dt;
     uint32_t mode;
     float *tape;
@@ -50,6 +50,81 @@ __global__ __launch_bounds__(1024) void k_adj_record(HeapView h, AdjK p)
         const uint32_t hd = (bid << 6) | s;
         px[hd] = farr<float>(h, bid, p.n_x)[s];
         py[hd] = farr<float>(h, bid, p.n_y)[s];
+    });
+}
+
+// Node pass of the forward step (the update of "spring.node_update": the
+// springs' forces summed in slot order, then symplectic Euler), which with a
+// tape also stores the new positions in tape plane pair `slot`, so that a
+// recomputed segment fills its tape without launches of its own.  The
+// adjoint's forward run takes the same kernel without a tape: the recomputed
+// positions are those of the forward run bit for bit.
+template <int U>
+__global__ __launch_bounds__(1024) void k_adj_step_node(HeapView h, AdjK p)
+{
+    if (heap_failed(h)) return;
+    const uint32_t s = lane_id();
+    float *px = p.tape ? plane_ptr(p, 2 * p.slot) : nullptr;
+    float *py = p.tape ? plane_ptr(p, 2 * p.slot + 1) : nullptr;
+    for_each_block_group<U>(h, p.node_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *) {
+        uint32_t e[U][8];
+        float m[U], x[U], y[U], vx[U], vy[U], Fx[U], Fy[U];
+        bool live[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            live[j] = (bm[j] >> s) & 1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) e[j][q] = farr<uint32_t>(h, bid[j], p.n_adj + q * p.n_adj_stride)[s];
+            m[j] = farr<float>(h, bid[j], p.n_m)[s];
+            x[j] = farr<float>(h, bid[j], p.n_x)[s];
+            y[j] = farr<float>(h, bid[j], p.n_y)[s];
+            vx[j] = farr<float>(h, bid[j], p.n_vx)[s];
+            vy[j] = farr<float>(h, bid[j], p.n_vy)[s];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            float gx[8], gy[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                gx[q] = 0.f;
+                gy[q] = 0.f;
+                if (live[j] && e[j][q] != kNull) {
+                    const uint32_t sh = e[j][q] & 0x7FFFFFFFu;
+                    gx[q] = fref<float>(h, sh, p.s_fx);
+                    gy[q] = fref<float>(h, sh, p.s_fy);
+                }
+            }
+            Fx[j] = 0.f;
+            Fy[j] = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (e[j][q] == kNull) continue;
+                if (e[j][q] >> 31) {
+                    Fx[j] -= gx[q];
+                    Fy[j] -= gy[q];
+                } else {
+                    Fx[j] += gx[q];
+                    Fy[j] += gy[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (!live[j]) continue;
+            vx[j] += Fx[j] / m[j] * p.dt;
+            vy[j] += Fy[j] / m[j] * p.dt;
+            x[j] += vx[j] * p.dt;
+            y[j] += vy[j] * p.dt;
+            farr<float>(h, bid[j], p.n_vx)[s] = vx[j];
+            farr<float>(h, bid[j], p.n_vy)[s] = vy[j];
+            farr<float>(h, bid[j], p.n_x)[s] = x[j];
+            farr<float>(h, bid[j], p.n_y)[s] = y[j];
+            if (px) {
+                const uint32_t hd = (bid[j] << 6) | s;
+                px[hd] = x[j];
+                py[hd] = y[j];
+            }
+        }
     });
 }
 
@@ -204,10 +279,15 @@ smmo_status bind_adj(smmo_heap *h, const AdjKey &key, AdjK &k)
     BIND(S, "cx", SMMO_F32, 1, &k.s_cx, nullptr);
     BIND(S, "cy", SMMO_F32, 1, &k.s_cy, nullptr);
     BIND(S, "gk", SMMO_F32, 1, &k.s_gk, nullptr);
+    BIND(S, "fx", SMMO_F32, 1, &k.s_fx, nullptr);
+    BIND(S, "fy", SMMO_F32, 1, &k.s_fy, nullptr);
     return SMMO_OK;
 }
 
-enum Which { W_RECORD, W_SAVE, W_LOAD, W_SEED, W_ZERO, W_NODE, W_SPRING };
+enum Which { W_RECORD, W_SAVE, W_LOAD, W_SEED, W_ZERO, W_NODE, W_SPRING, W_STEP };
+
+// blocks per wavefront iteration of the forward node pass unless set otherwise
+constexpr uint32_t kStepGroup = 1;
 
 template <int Which>
 smmo_status launch_adj(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
@@ -234,7 +314,8 @@ smmo_status launch_adj(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     k.seed_vx = a.seed_vx;
     k.seed_vy = a.seed_vy;
     const uint32_t planes = (Which == W_SAVE || Which == W_LOAD) ? 4u : 2u;
-    if (Which == W_RECORD || Which == W_SAVE || Which == W_LOAD || Which == W_SPRING) {
+    if (Which == W_RECORD || Which == W_SAVE || Which == W_LOAD || Which == W_SPRING ||
+        (Which == W_STEP && a.tape)) {
         if (!a.tape) return fail(SMMO_EINVAL, "adjoint: tape is NULL");
         if (a.plane < 64ull * h->v.M) return fail(SMMO_EINVAL, "adjoint: tape plane shorter than 64 * heap blocks");
         if (((uint64_t)a.slot + 1) * planes * a.plane > a.tape_floats)
@@ -243,6 +324,13 @@ smmo_status launch_adj(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     if (Which == W_SEED && (!a.seed_x || !a.seed_y)) return fail(SMMO_EINVAL, "adjoint: seed arrays are NULL");
     if (Which == W_NODE && (a.mode & ~3u)) return fail(SMMO_EINVAL, "adjoint: bad mode");
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
+    if (Which == W_STEP) {
+        const LaunchShape ls = method_shape(h, cls, kStepGroup);
+        if (ls.group == 4) hipLaunchKernelGGL(k_adj_step_node<4>, ls.grid, ls.block, 0, st, h->v, k);
+        else if (ls.group == 2) hipLaunchKernelGGL(k_adj_step_node<2>, ls.grid, ls.block, 0, st, h->v, k);
+        else hipLaunchKernelGGL(k_adj_step_node<1>, ls.grid, ls.block, 0, st, h->v, k);
+        return launched("adjoint kernel");
+    }
     const LaunchShape ls = method_shape(h, cls);
     const dim3 grid = ls.grid, blk = ls.block;
     switch (Which) {
@@ -267,4 +355,5 @@ smmo_status launch_adj_seed(smmo_heap *h, uint32_t c, const void *a, hipStream_t
 smmo_status launch_adj_zero(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_adj<W_ZERO>(h, c, a, s); }
 smmo_status launch_adj_node(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_adj<W_NODE>(h, c, a, s); }
 smmo_status launch_adj_spring(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_adj<W_SPRING>(h, c, a, s); }
+smmo_status launch_adj_step_node(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_adj<W_STEP>(h, c, a, s); }
 } // namespace smmo

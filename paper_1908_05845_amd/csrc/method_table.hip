@@ -48,6 +48,7 @@ smmo_status launch_structure_link(smmo_heap *h, uint32_t cls, const void *args, 
 
 // launchers defined in adjoint.hip
 smmo_status launch_adj_record(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_adj_step_node(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_adj_save(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_adj_load(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_adj_seed(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
@@ -82,6 +83,7 @@ const MethodEntry kMethods[] = {
     {"adjoint.zero", sizeof(smmo_adjoint_args), launch_adj_zero},
     {"adjoint.node", sizeof(smmo_adjoint_args), launch_adj_node},
     {"adjoint.spring", sizeof(smmo_adjoint_args), launch_adj_spring},
+    {"adjoint.step_node", sizeof(smmo_adjoint_args), launch_adj_step_node},
     {"test.axpy", sizeof(smmo_axpy_args), launch_test_axpy},
     {"test.destroy_if", sizeof(smmo_destroy_if_args), launch_test_destroy_if},
     {"test.spawn", sizeof(smmo_spawn_args), launch_test_spawn},

@@ -128,7 +128,7 @@ def test_too_many_classes_and_duplicates(lib):
 def test_method_ids(lib):
     names = ["gol.cell_count", "gol.alive_death", "gol.cell_birth", "nbody.force", "nbody.update",
              "spring.force", "spring.node_update", "spring.link", "adjoint.record", "adjoint.save",
-             "adjoint.load", "adjoint.seed", "adjoint.zero", "adjoint.node", "adjoint.spring", "test.axpy",
+             "adjoint.load", "adjoint.seed", "adjoint.zero", "adjoint.node", "adjoint.spring", "adjoint.step_node", "test.axpy",
              "test.destroy_if", "test.spawn", "test.transmute", "alloc.ls_alloc", "alloc.ls_free", "wator.cell_prepare",
              "wator.fish_prepare", "wator.shark_prepare", "wator.cell_decide", "wator.fish_update",
              "wator.shark_update", "wator.cell_link", "wator.link", "spring_pi.force", "spring_pi.node_update",

@@ -142,3 +142,55 @@ def test_graph_replay_matches_eager(dev):
             assert np.array_equal(a, b), rep
     sim.restart()
     assert np.array_equal(sim.forward().cpu().numpy(), want[3])
+
+
+def test_step_node_tape_and_forward_step(dev):
+    """adjoint.step_node writes to tape plane pair `slot` exactly the positions
+    it leaves in the heap, moves the mesh as spring.node_update does (1e-6),
+    and refuses a slot beyond the tape."""
+    import torch
+
+    from paper_1908_05845_amd import smmo
+
+    print("adjoint step_node tape 33x21", flush=True)
+    mesh = spring_mesh(33, 21, seed=21, v_sigma=0.5)
+    a = DiffSpringSim(mesh, 1e-3, steps=4, every=4)
+    b = DiffSpringSim(mesh, 1e-3, steps=4, every=4)
+    mid_node = smmo.smmo_method_id("spring.node_update")
+    for t in range(3):
+        a.L_force(a._stream())
+        a._do(a.cn, "adjoint.step_node", a._aargs(a.tape, slot=t + 1))
+        b.L_force(b._stream())
+        smmo.smmo_parallel_do(b.heap.h, b.cn, mid_node, b.fargs)
+        a.heap.sync()
+        b.heap.sync()
+        pa, pb = a.positions().cpu().numpy(), b.positions().cpu().numpy()
+        np.testing.assert_allclose(pa, pb, rtol=1e-6, atol=0)
+        h = a.node_h.long()
+        tx = a.tape[(2 * (t + 1)) * a.plane + h].cpu().numpy()
+        ty = a.tape[(2 * (t + 1) + 1) * a.plane + h].cpu().numpy()
+        assert np.array_equal(tx, pa[:, 0]) and np.array_equal(ty, pa[:, 1]), t
+    with pytest.raises(smmo.SmmoError):
+        a._do(a.cn, "adjoint.step_node", a._aargs(a.tape, slot=4))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("group", [2, 4])
+def test_step_node_groups_change_no_bit(dev, group):
+    """The node pass's blocks per wavefront iteration (1, 2 or 4) leave the
+    positions and gradients of a checkpointed sweep unchanged bit for bit."""
+    from paper_1908_05845_amd import smmo
+
+    print("adjoint step_node group %d" % group, flush=True)
+    mesh = spring_mesh(40, 30, seed=4, v_sigma=0.5)
+    want = _gpu_adjoint(mesh, 1e-3, 30, 7)
+    import torch
+
+    sim = DiffSpringSim(mesh, 1e-3, 30, 7)
+    smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id("adjoint.step_node"), sim.cn, 0, 0, group)
+    xT = sim.forward()
+    x0 = torch.from_numpy(np.stack([mesh["x"], mesh["y"]], 1).astype(np.float32)).to(xT.device)
+    g = xT - x0
+    got = [t.cpu().numpy() for t in sim.backward(g[:, 0], g[:, 1])] + [xT.cpu().numpy()]
+    for x, y in zip(got, want):
+        assert np.array_equal(x, y)
