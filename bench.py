@@ -488,12 +488,20 @@ def measure_batched(torch, plain_updates_per_s):
 
 
 def measure_adjoint(torch, plain_updates_per_s):
+    """The adjoint measurement on a created stream, on which the reverse sweep
+    recomputes each segment beside the reverse steps of the one after it."""
+    with torch.cuda.stream(torch.cuda.Stream()):
+        return _measure_adjoint(torch, plain_updates_per_s)
+
+
+def _measure_adjoint(torch, plain_updates_per_s):
     """316 x 317 mesh (100,172 nodes), breaking off, 200 steps forward with a
     checkpoint every 20 steps, then the reverse sweep (segment recompute
     included) for L = 1/2 |x_T - x_0|^2.  Timed twice: launched from the host
-    (every do-all one library call) and replayed from two captured HIP graphs
-    (forward from the step-0 checkpoint; reverse sweep), whose gradients must
-    equal the launched run's bit for bit."""
+    (every do-all one library call; the reverse sweep also on one stream,
+    without the recompute of the next segment beside it) and replayed from
+    two captured HIP graphs (forward from the step-0 checkpoint; reverse
+    sweep), whose gradients must equal the launched run's bit for bit."""
     import numpy as np
 
     from inputs import config_seed, spring_mesh
@@ -556,6 +564,7 @@ def measure_adjoint(torch, plain_updates_per_s):
     xT = sim.positions()
     g = (xT - x0).contiguous()
     sx, sy = g[:, 0].contiguous(), g[:, 1].contiguous()
+    bwd1 = timed(lambda: sim.run_backward(sx, sy, overlap=False))
     bwd = timed(lambda: sim.run_backward(sx, sy))
     want = [t.cpu().numpy() for t in sim.gradients()]
     # captured once, replayed
@@ -580,7 +589,8 @@ def measure_adjoint(torch, plain_updates_per_s):
     gk, gv = want[0], want[1]
     res = {"workload": "316x317 spring mesh, 100,172 nodes, %d springs, breaking off, dt 1e-5" % sim.S,
            "steps": T, "checkpoint_every": every,
-           "launched": {"forward_ms": fwd, "backward_ms": bwd, "backward_over_forward": bwd / fwd},
+           "launched": {"forward_ms": fwd, "backward_ms": bwd, "backward_over_forward": bwd / fwd,
+                        "backward_one_stream_ms": bwd1},
            "graph": {"forward_ms": gfm, "backward_ms": gbm, "backward_over_forward": gbm / gfm,
                      "replays": 3, "gradients_equal_launched": bool(same)},
            "forward_updates_per_s": T * per_step / (gfm * 1e-3),

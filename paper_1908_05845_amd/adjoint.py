@@ -86,7 +86,19 @@ class DiffSpringSim:
         nck = (self.T + self.every - 1) // self.every if self.T else 0
         self.ckpt = torch.empty(max(1, nck) * 4 * self.plane, dtype=torch.float32, device=dev)
         seg = max(1, min(self.every, max(self.T, 1)))
-        self.tape = torch.empty(seg * 2 * self.plane, dtype=torch.float32, device=dev)
+        # two tapes when there are several segments: the reverse steps of one
+        # segment read one while the next segment is recomputed into the other
+        self.tapes = [torch.empty(seg * 2 * self.plane, dtype=torch.float32, device=dev)
+                      for _ in range(2 if nck > 1 else 1)]
+        self.tape = self.tapes[0]
+        self.overlap = nck > 1
+        self._side = torch.cuda.Stream(device=dev) if self.overlap else None
+        # events of the overlapped sweep, kept for the sim's life (a captured
+        # graph refers to them): fork, recompute of segment s done, reverse
+        # steps of segment s done
+        self._ev_fork = torch.cuda.Event() if self.overlap else None
+        self._ev_rec = [torch.cuda.Event() for _ in range(nck)] if self.overlap else []
+        self._ev_rev = [torch.cuda.Event() for _ in range(nck)] if self.overlap else []
         # every launch of forward and backward, bound once (the seed launch
         # names the caller's tensors and is bound per backward call)
         B = smmo.BoundLaunch
@@ -99,11 +111,11 @@ class DiffSpringSim:
         # recompute: step t of a segment writes the positions of step t + 1 to
         # tape slot t + 1; the spring pass of step 0 reads the checkpoint's
         # (x, y), its planes 4c, 4c + 1 being plane pair 2c of that tape
-        self.L_stepr = [B(hp, self.cn, ids["adjoint.step_node"], self._aargs(self.tape, slot=t))
-                        for t in range(seg)]
+        self.L_stepr = [[B(hp, self.cn, ids["adjoint.step_node"], self._aargs(tp, slot=t)) for t in range(seg)]
+                        for tp in self.tapes]
         self.L_anode = {m: B(hp, self.cn, ids["adjoint.node"], self._aargs(self.tape, mode=m)) for m in (1, 2, 3)}
-        self.L_aspring = [B(hp, self.cs, ids["adjoint.spring"], self._aargs(self.tape, slot=t))
-                          for t in range(seg)] if S else None
+        self.L_aspring = [[B(hp, self.cs, ids["adjoint.spring"], self._aargs(tp, slot=t)) for t in range(seg)]
+                          for tp in self.tapes] if S else None
         self.L_aspring0 = [B(hp, self.cs, ids["adjoint.spring"], self._aargs(self.ckpt, slot=2 * c))
                            for c in range(nck)] if S else None
         self.L_zero = B(hp, self.cs, ids["adjoint.zero"], self._aargs(self.tape)) if S else None
@@ -168,10 +180,44 @@ class DiffSpringSim:
         self.heap.sync()
         return self.gradients()
 
-    def run_backward(self, gx, gy, gvx=None, gvy=None, stream=None):
+    def _recompute(self, seg):
+        """Launches recomputing segment seg from its checkpoint into tape seg % 2."""
+        n0 = seg * self.every
+        n1 = min(n0 + self.every, self.T)
+        out = [self.L_load[seg]]
+        for t in range(n1 - n0 - 1):      # the segment's last step is not needed
+            if self.L_force is not None:
+                out.append(self.L_force)
+            out.append(self.L_stepr[seg % 2][t + 1])
+        return out
+
+    def _reverse(self, seg, first):
+        """Launches of segment seg's reverse steps, last step first, reading
+        tape seg % 2 (step 0: the checkpoint)."""
+        n0 = seg * self.every
+        n1 = min(n0 + self.every, self.T)
+        out = []
+        for t in range(n1 - n0 - 1, -1, -1):
+            out.append(self.L_anode[2 if first else 3])
+            first = False
+            if self.L_aspring is not None:
+                out.append(self.L_aspring[seg % 2][t] if t else self.L_aspring0[seg])
+        return out
+
+    def run_backward(self, gx, gy, gvx=None, gvy=None, stream=None, overlap=None):
         """The reverse sweep's launches on `stream` (default: the current
         stream); no host synchronization.  The seed tensors must stay alive
-        until the sweep has run."""
+        until the sweep has run.
+
+        With overlap (the default when there are several segments) each
+        segment but the last is recomputed on a second stream while the
+        segment after it is reversed on `stream`: the recompute writes x, v,
+        the springs' forces and its own tape, the reverse steps the adjoint
+        fields, and events order each tape's reuse.  The second stream forks
+        from `stream` and joins it again, so the sweep can be captured in a
+        HIP graph like the single-stream one, and the results are the same
+        bit for bit.  The ordering needs a created stream: on the legacy null
+        stream (torch's default) the sweep runs on that stream alone."""
         torch = self.torch
         st = self._stream() if stream is None else stream
         seeds = [t.detach().to(device=self.dev, dtype=torch.float32).contiguous() if t is not None else None
@@ -181,22 +227,38 @@ class DiffSpringSim:
                          self._aargs(self.tape, seeds=seeds, count=self.N))(st)
         if self.L_zero is not None:
             self.L_zero(st)
-        first = True
         nseg = (self.T + self.every - 1) // self.every
-        for seg in range(nseg - 1, -1, -1):
-            n0 = seg * self.every
-            n1 = min(n0 + self.every, self.T)
-            self.L_load[seg](st)
-            for t in range(n1 - n0 - 1):  # the segment's last step is not needed
-                if self.L_force is not None:
-                    self.L_force(st)
-                self.L_stepr[t + 1](st)
-            for t in range(n1 - n0 - 1, -1, -1):
-                self.L_anode[2 if first else 3](st)
-                first = False
-                if self.L_aspring is not None:
-                    (self.L_aspring[t] if t else self.L_aspring0[seg])(st)
-        if not first:
+        if overlap is None:
+            overlap = self.overlap
+        if not (overlap and self.overlap) or not st:
+            for seg in range(nseg - 1, -1, -1):
+                for launch in self._recompute(seg) + self._reverse(seg, seg == nseg - 1):
+                    launch(st)
+        else:
+            A = torch.cuda.ExternalStream(st, device=self.dev)
+            side = self._side
+            sst = side.cuda_stream
+            self._ev_fork.record(A)       # the forward run and the seeds come first
+            side.wait_event(self._ev_fork)
+            for launch in self._recompute(nseg - 1):
+                launch(sst)
+            self._ev_rec[nseg - 1].record(side)
+            for seg in range(nseg - 1, -1, -1):
+                A.wait_event(self._ev_rec[seg])       # tape seg % 2 holds segment seg
+                rev, rec = self._reverse(seg, seg == nseg - 1), []
+                if seg > 0:
+                    if seg + 1 < nseg:    # the reverse of seg + 1 is done with tape (seg - 1) % 2
+                        side.wait_event(self._ev_rev[seg + 1])
+                    rec = self._recompute(seg - 1)
+                for i in range(max(len(rev), len(rec))):
+                    if i < len(rev):
+                        rev[i](st)
+                    if i < len(rec):
+                        rec[i](sst)
+                self._ev_rev[seg].record(A)
+                if seg > 0:
+                    self._ev_rec[seg - 1].record(side)
+        if nseg:
             self.L_anode[1](st)
 
     def gradients(self):

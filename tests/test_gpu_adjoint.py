@@ -194,3 +194,34 @@ def test_step_node_groups_change_no_bit(dev, group):
     got = [t.cpu().numpy() for t in sim.backward(g[:, 0], g[:, 1])] + [xT.cpu().numpy()]
     for x, y in zip(got, want):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("T,every", [(60, 7), (41, 20), (40, 20)])
+def test_overlapped_sweep_equals_single_stream(dev, T, every):
+    """The reverse sweep with each segment's recompute on a second stream
+    gives the single-stream sweep's gradients bit for bit, run twice in a row."""
+    import torch
+
+    print("adjoint overlap T=%d every=%d" % (T, every), flush=True)
+    mesh = spring_mesh(30, 22, seed=T + every, v_sigma=0.5)
+    x0 = torch.from_numpy(np.stack([mesh["x"], mesh["y"]], 1).astype(np.float32)).to(dev)
+    ref = DiffSpringSim(mesh, 1e-3, T, every)
+    xT = ref.forward()
+    g = (xT - x0).contiguous()
+    sx, sy = g[:, 0].contiguous(), g[:, 1].contiguous()
+    ref.run_backward(sx, sy, overlap=False)
+    ref.heap.sync()
+    want = [t.cpu().numpy() for t in ref.gradients()]
+    # a fresh sim on a created stream: its first sweep already overlaps
+    ms = torch.cuda.Stream()
+    with torch.cuda.stream(ms):
+        sim = DiffSpringSim(mesh, 1e-3, T, every)
+        assert sim.overlap
+        assert np.array_equal(sim.forward().cpu().numpy(), xT.cpu().numpy())
+        for rep in range(2):
+            sim.run_backward(sx, sy)
+            sim.heap.sync()
+            torch.cuda.synchronize()
+            got = [t.cpu().numpy() for t in sim.gradients()]
+            for a, b in zip(got, want):
+                assert np.array_equal(a, b), rep
