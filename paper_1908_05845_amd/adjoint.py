@@ -217,7 +217,8 @@ class DiffSpringSim:
         from `stream` and joins it again, so the sweep can be captured in a
         HIP graph like the single-stream one, and the results are the same
         bit for bit.  The ordering needs a created stream: on the legacy null
-        stream (torch's default) the sweep runs on that stream alone."""
+        stream (torch's default) the sweep runs on that stream alone.  One
+        sweep of a sim at a time: its tapes, heap and events are shared."""
         torch = self.torch
         st = self._stream() if stream is None else stream
         seeds = [t.detach().to(device=self.dev, dtype=torch.float32).contiguous() if t is not None else None
