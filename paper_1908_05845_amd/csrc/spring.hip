@@ -42,9 +42,8 @@ __device__ __forceinline__ bool spring_breaks(float dx, float dy, float L0, floa
 // wavefront works on U blocks at once: the spring fields of all U blocks are
 // loaded, then all position gathers issued, then the forces computed.
 template <int U>
-__global__ __launch_bounds__(1024) void k_spring_force(HeapView h, SpringK p)
+__device__ __forceinline__ void spring_force(const HeapView &h, const SpringK &p)
 {
-    if (heap_failed(h)) return;
     const uint32_t s = lane_id();
     for_each_block_group<U>(h, p.spring_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
         uint32_t a[U], b[U];
@@ -94,6 +93,25 @@ __global__ __launch_bounds__(1024) void k_spring_force(HeapView h, SpringK p)
             wave_release_own_block(h, p.spring_cls, bid[j], __ballot(brk));
         }
     });
+}
+
+// One and two blocks per iteration: the registers are held to what eight
+// wavefronts per SIMD allow (the rare release path of a breaking spring would
+// otherwise raise the scalar registers past that), so one grid of 32
+// wavefronts per CU stays resident.  Four blocks per iteration need more
+// registers than that and keep the compiler's allocation.
+template <int U>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spring_force(HeapView h,
+                                                                                                 SpringK p)
+{
+    if (heap_failed(h)) return;
+    spring_force<U>(h, p);
+}
+
+__global__ __launch_bounds__(1024) void k_spring_force4(HeapView h, SpringK p)
+{
+    if (heap_failed(h)) return;
+    spring_force<4>(h, p);
 }
 
 // Node::update: sum the attached springs' forces in slot order (+f if this
@@ -231,7 +249,7 @@ smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStrea
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     const LaunchShape ls = method_shape(h, cls, kSpringGroup);
     if (Which == 0) {
-        if (ls.group == 4) hipLaunchKernelGGL(k_spring_force<4>, ls.grid, ls.block, 0, st, h->v, k);
+        if (ls.group == 4) hipLaunchKernelGGL(k_spring_force4, ls.grid, ls.block, 0, st, h->v, k);
         else if (ls.group == 2) hipLaunchKernelGGL(k_spring_force<2>, ls.grid, ls.block, 0, st, h->v, k);
         else hipLaunchKernelGGL(k_spring_force<1>, ls.grid, ls.block, 0, st, h->v, k);
     }
