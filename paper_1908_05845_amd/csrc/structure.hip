@@ -47,28 +47,38 @@ struct StructK {
 
 constexpr uint32_t kMaxFamily = 4;   // concrete classes one family launch walks
 
-// Calls f(bid, bm, cls) for every block of the classes in `mask` (at most
-// kMaxFamily), one wavefront per block: a grid-stride walk over their block
-// lists taken one after the other.  As in for_each_block, listed blocks whose
-// type changed are skipped.  The list lengths were written by earlier
-// launches (the enumerations), so plain loads read them.
+// Calls f(bid, bm, cls) for every listed block of the classes in `mask` (at
+// most kMaxFamily), one wavefront per block: a grid-stride walk over their
+// block lists taken one after the other.  A listed block whose type changed
+// comes with bm = 0 (no live slot), so f may load from any block it is given
+// before it looks at bm (the loads then overlap the header's) but stores only
+// to live slots.  The list lengths were written by earlier launches (the
+// enumerations), so plain loads read them.
 template <class F>
 __device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_t mask, F &&f)
 {
     BlockList L[kMaxFamily];
-    uint32_t cls[kMaxFamily], end[kMaxFamily];
+    uint32_t cls[kMaxFamily], end[kMaxFamily], rf[kMaxFamily], rs[kMaxFamily];
+    bool used[kMaxFamily];
     uint32_t total = 0, m = mask;
 #pragma unroll
     for (uint32_t j = 0; j < kMaxFamily; ++j) {
+        used[j] = m != 0;
         cls[j] = m ? (uint32_t)(__ffs(m) - 1) : 0u;
+        m &= m - 1;
+    }
+    // all list lengths at once (an unused entry reads class 0's words)
+#pragma unroll
+    for (uint32_t j = 0; j < kMaxFamily; ++j) {
+        rf[j] = __builtin_amdgcn_readfirstlane(h.ctrl[CTRL_RFINAL + cls[j]]);
+        rs[j] = __builtin_amdgcn_readfirstlane(h.ctrl[CTRL_RSFINAL + cls[j]]);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kMaxFamily; ++j) {
         L[j].R = h.R + (uint64_t)cls[j] * h.M;
         L[j].M = h.M;
-        L[j].r = L[j].nd = 0;
-        if (m) {
-            L[j].r = __builtin_amdgcn_readfirstlane(h.ctrl[CTRL_RFINAL + cls[j]]);
-            L[j].nd = L[j].r - __builtin_amdgcn_readfirstlane(h.ctrl[CTRL_RSFINAL + cls[j]]);
-            m &= m - 1;
-        }
+        L[j].r = used[j] ? rf[j] : 0u;
+        L[j].nd = used[j] ? rf[j] - rs[j] : 0u;
         total += L[j].r;
         end[j] = total;
     }
@@ -87,7 +97,7 @@ __device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_
         bid = __builtin_amdgcn_readfirstlane(bid);
         const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
         const uint64_t bm = uniform64(h.alloc_bm[bid]);
-        if (t == c) f(bid, bm, t);
+        f(bid, t == c ? bm : 0ull, c);
     }
 }
 
@@ -259,7 +269,8 @@ __global__ __launch_bounds__(1024) void k_st_bfs_visit(HeapView h, StructK p)
     if (heap_failed(h)) return;
     for_each_family_block(h, p.fam_mask, [&](uint32_t bid, uint64_t bm, uint32_t) {
         const uint32_t s = lane_id();
-        const bool front = ((bm >> s) & 1) && farr<int32_t>(h, bid, p.n_dist)[s] == p.distance;
+        const int32_t dist = farr<int32_t>(h, bid, p.n_dist)[s];   // issued beside the header loads
+        const bool front = (((bm >> s) & 1) != 0) & (dist == p.distance);   // no branch before the load
         const uint64_t fb = __ballot(front);
         if (fb && s == (uint32_t)(__ffsll((unsigned long long)fb) - 1) && *p.flag == 0) *p.flag = 1u;
         if (!front) return;
@@ -283,7 +294,8 @@ __global__ __launch_bounds__(1024) void k_st_bfs_mark(HeapView h, StructK p)
     if (heap_failed(h)) return;
     for_each_family_block(h, p.fam_mask, [&](uint32_t bid, uint64_t bm, uint32_t) {
         const uint32_t s = lane_id();
-        if (!((bm >> s) & 1) || farr<int32_t>(h, bid, p.n_dist)[s] != kFar) return;
+        const int32_t dist = farr<int32_t>(h, bid, p.n_dist)[s];
+        if (!((((bm >> s) & 1) != 0) & (dist == kFar))) return;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const uint32_t hs = farr<uint32_t>(h, bid, p.n_spr + q * p.n_spr_stride)[s];
