@@ -93,6 +93,7 @@ class DiffSpringSim:
         self.tape = self.tapes[0]
         self.overlap = nck > 1
         self._side = torch.cuda.Stream(device=dev) if self.overlap else None
+        self._main = torch.cuda.Stream(device=dev) if self.overlap else None
         # events of the overlapped sweep, kept for the sim's life (a captured
         # graph refers to them): fork, recompute of segment s done, reverse
         # steps of segment s done
@@ -176,8 +177,18 @@ class DiffSpringSim:
     def backward(self, gx, gy, gvx=None, gvy=None):
         """Reverse sweep from dL/dx_T (and dL/dv_T, default 0), tensors of N by
         node id.  Returns (dL/dk by spring id, dL/dv0 (N, 2), dL/dx0 (N, 2))."""
-        self.run_backward(gx, gy, gvx, gvy)
-        self.heap.sync()
+        torch = self.torch
+        if self.overlap and not self._stream():
+            # on the legacy null stream the sweep goes to a created stream
+            # between two host synchronizations, so that only events of
+            # created streams order its two streams
+            torch.cuda.current_stream().synchronize()
+            with torch.cuda.stream(self._main):
+                self.run_backward(gx, gy, gvx, gvy)
+                self.heap.sync()
+        else:
+            self.run_backward(gx, gy, gvx, gvy)
+            self.heap.sync()
         return self.gradients()
 
     def _recompute(self, seg):
