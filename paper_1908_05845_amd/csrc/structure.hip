@@ -43,19 +43,23 @@ struct StructK {
     uint32_t fam_mask;        // BFS methods: the concrete node classes one launch covers
     uint32_t anchor_mask;     // BFS methods: those of them that are AnchorNode or derive from it
     uint32_t *flag;
+    uint32_t wpg;             // wavefronts per work-group of this launch (whole groups only)
 };
 
 constexpr uint32_t kMaxFamily = 4;   // concrete classes one family launch walks
 
 // Calls f(bid, bm, cls) for every listed block of the classes in `mask` (at
-// most kMaxFamily), one wavefront per block: a grid-stride walk over their
-// block lists taken one after the other.  A listed block whose type changed
+// most kMaxFamily; wpg = the launch's wavefronts per work-group, passed in so
+// that no load of the work-group size delays the walk), one wavefront per block: a grid-stride walk over their
+// block lists taken one after the other.  Nothing is called once the heap
+// has failed: the error word is read in the same batch of loads as the list
+// lengths (the kernels that use this walker need no check of their own).  A listed block whose type changed
 // comes with bm = 0 (no live slot), so f may load from any block it is given
 // before it looks at bm (the loads then overlap the header's) but stores only
 // to live slots.  The list lengths were written by earlier launches (the
 // enumerations), so plain loads read them.
 template <class F>
-__device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_t mask, F &&f)
+__device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_t mask, uint32_t wpg, F &&f)
 {
     BlockList L[kMaxFamily];
     uint32_t cls[kMaxFamily], end[kMaxFamily], rf[kMaxFamily], rs[kMaxFamily];
@@ -67,12 +71,15 @@ __device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_
         cls[j] = m ? (uint32_t)(__ffs(m) - 1) : 0u;
         m &= m - 1;
     }
-    // all list lengths at once (an unused entry reads class 0's words)
+    // the error word and all list lengths at once (an unused entry reads
+    // class 0's words)
+    const uint32_t err = ald32(h.ctrl + CTRL_ERR);
 #pragma unroll
     for (uint32_t j = 0; j < kMaxFamily; ++j) {
         rf[j] = __builtin_amdgcn_readfirstlane(h.ctrl[CTRL_RFINAL + cls[j]]);
         rs[j] = __builtin_amdgcn_readfirstlane(h.ctrl[CTRL_RSFINAL + cls[j]]);
     }
+    if (err) return;
 #pragma unroll
     for (uint32_t j = 0; j < kMaxFamily; ++j) {
         L[j].R = h.R + (uint64_t)cls[j] * h.M;
@@ -82,7 +89,6 @@ __device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_
         total += L[j].r;
         end[j] = total;
     }
-    const uint32_t wpg = blockDim.x >> 6;
     const uint32_t nw = gridDim.x * wpg;
     for (uint32_t i = xcd_logical_wg() * wpg + (threadIdx.x >> 6); i < total; i += nw) {
         uint32_t bid = 0, c = 0;
@@ -251,8 +257,7 @@ __global__ __launch_bounds__(1024) void k_st_node_update(HeapView h, StructK p)
 // NodeBase::initialize_frontier (the cast to AnchorNode is the block's type)
 __global__ __launch_bounds__(1024) void k_st_bfs_init(HeapView h, StructK p)
 {
-    if (heap_failed(h)) return;
-    for_each_family_block(h, p.fam_mask, [&](uint32_t bid, uint64_t bm, uint32_t t) {
+    for_each_family_block(h, p.fam_mask, p.wpg, [&](uint32_t bid, uint64_t bm, uint32_t t) {
         const uint32_t s = lane_id();
         if ((bm >> s) & 1) farr<int32_t>(h, bid, p.n_dist)[s] = ((p.anchor_mask >> t) & 1) ? 0 : kFar;
     });
@@ -266,8 +271,7 @@ __global__ __launch_bounds__(1024) void k_st_bfs_init(HeapView h, StructK p)
 // one word from every frontier wavefront would queue at that word.)
 __global__ __launch_bounds__(1024) void k_st_bfs_visit(HeapView h, StructK p)
 {
-    if (heap_failed(h)) return;
-    for_each_family_block(h, p.fam_mask, [&](uint32_t bid, uint64_t bm, uint32_t) {
+    for_each_family_block(h, p.fam_mask, p.wpg, [&](uint32_t bid, uint64_t bm, uint32_t) {
         const uint32_t s = lane_id();
         const int32_t dist = farr<int32_t>(h, bid, p.n_dist)[s];   // issued beside the header loads
         const bool front = (((bm >> s) & 1) != 0) & (dist == p.distance);   // no branch before the load
@@ -291,8 +295,7 @@ __global__ __launch_bounds__(1024) void k_st_bfs_visit(HeapView h, StructK p)
 // NodeBase::delete_node: an unvisited node flags its springs
 __global__ __launch_bounds__(1024) void k_st_bfs_mark(HeapView h, StructK p)
 {
-    if (heap_failed(h)) return;
-    for_each_family_block(h, p.fam_mask, [&](uint32_t bid, uint64_t bm, uint32_t) {
+    for_each_family_block(h, p.fam_mask, p.wpg, [&](uint32_t bid, uint64_t bm, uint32_t) {
         const uint32_t s = lane_id();
         const int32_t dist = farr<int32_t>(h, bid, p.n_dist)[s];
         if (!((((bm >> s) & 1) != 0) & (dist == kFar))) return;
@@ -445,6 +448,7 @@ smmo_status launch_structure(smmo_heap *h, uint32_t cls, const void *args, hipSt
             if (((k.fam_mask >> c) & 1) && (s = ensure_enumerated(h, c, false, st))) return s;
         ls = family_shape(h, cls, k.fam_mask);
         if (!k.fam_mask) return SMMO_OK;
+        k.wpg = ls.block.x / 64;
     } else {
         if ((s = ensure_enumerated(h, cls, false, st))) return s;
         ls = method_shape(h, cls);
