@@ -190,24 +190,25 @@ __global__ __launch_bounds__(1024) void k_st_force(HeapView h, StructK p)
 #pragma clang fp contract(off)
         const uint32_t s = lane_id();
         bool live = (bm >> s) & 1;
-        uint32_t a = 0, b = 0;
         float fx = 0.f, fy = 0.f;
         bool brk = false;
-        if (live) {
-            a = farr<uint32_t>(h, bid, p.s_p1)[s];
-            b = farr<uint32_t>(h, bid, p.s_p2)[s];
-            live = st_valid(h, a) && st_valid(h, b);
-        }
+        // the block's own fields for all 64 slots at once (one contiguous run
+        // each), so that they arrive with the endpoint handles
+        uint32_t a = farr<uint32_t>(h, bid, p.s_p1)[s];
+        uint32_t b = farr<uint32_t>(h, bid, p.s_p2)[s];
+        const float k = farr<float>(h, bid, p.s_k)[s], L0 = farr<float>(h, bid, p.s_L0)[s];
+        const float maxf = farr<float>(h, bid, p.s_maxf)[s];
+        if (live) live = st_valid(h, a) && st_valid(h, b);
+        if (!live) a = b = 0;
         if (live) {
             const float dx = fref<float>(h, b, p.n_x) - fref<float>(h, a, p.n_x);
             const float dy = fref<float>(h, b, p.n_y) - fref<float>(h, a, p.n_y);
-            const float k = farr<float>(h, bid, p.s_k)[s], L0 = farr<float>(h, bid, p.s_L0)[s];
             const float dy2 = dy * dy;
             const float l = __builtin_sqrtf(__builtin_fmaf(dx, dx, dy2));
             const float d = l - L0;
             const float F = k * d;
             const bool stretched = l > L0;
-            brk = stretched && F > farr<float>(h, bid, p.s_maxf)[s];
+            brk = stretched && F > maxf;
             if (stretched && !brk) {
                 const float c = k * d / l;
                 fx = c * dx;
