@@ -61,23 +61,22 @@ __global__ __launch_bounds__(1024) void k_pi_force(HeapView h, PiK p)
 #pragma clang fp contract(off)
         const uint32_t s = lane_id();
         bool live = (bm >> s) & 1;
-        uint32_t a = 0, b = 0;
-        if (live) {
-            a = farr<uint32_t>(h, bid, p.s_a)[s];
-            b = farr<uint32_t>(h, bid, p.s_b)[s];
-            live = pi_valid(h, a) && pi_valid(h, b);
-        }
+        // the spring's own fields for all 64 slots at once, with its handles
+        uint32_t a = farr<uint32_t>(h, bid, p.s_a)[s];
+        uint32_t b = farr<uint32_t>(h, bid, p.s_b)[s];
+        const float L0 = farr<float>(h, bid, p.s_L0)[s], k = farr<float>(h, bid, p.s_k)[s];
+        if (live) live = pi_valid(h, a) && pi_valid(h, b);
+        if (!live) a = b = 0;
         float fx = 0.f, fy = 0.f;
         bool brk = false;
         if (live) {
             const float dx = fref<float>(h, b, p.n_x) - fref<float>(h, a, p.n_x);
             const float dy = fref<float>(h, b, p.n_y) - fref<float>(h, a, p.n_y);
-            const float L0 = farr<float>(h, bid, p.s_L0)[s];
             const float dy2 = dy * dy;
             const float l = __builtin_sqrtf(__builtin_fmaf(dx, dx, dy2));
             brk = (l - L0) / L0 > p.limit;
             if (!brk) {
-                const float c = farr<float>(h, bid, p.s_k)[s] * (l - L0) / l;
+                const float c = k * (l - L0) / l;
                 fx = c * dx;
                 fy = c * dy;
             }

@@ -228,16 +228,23 @@ __global__ __launch_bounds__(1024) void k_st_node_update(HeapView h, StructK p)
     if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
+        // the node's slots and own fields for all 64 slots at once (one
+        // contiguous run each), before the gathers that depend on the slots
+        uint32_t hs[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) hs[q] = farr<uint32_t>(h, bid, p.n_spr + q * p.n_spr_stride)[s];
+        const float m = farr<float>(h, bid, p.n_m)[s];
+        float vx = farr<float>(h, bid, p.n_vx)[s], vy = farr<float>(h, bid, p.n_vy)[s];
+        float x = farr<float>(h, bid, p.n_x)[s], y = farr<float>(h, bid, p.n_y)[s];
         if (!((bm >> s) & 1)) return;
         float Fx = 0.f, Fy = 0.f;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const uint32_t hs = farr<uint32_t>(h, bid, p.n_spr + q * p.n_spr_stride)[s];
-            if (hs == kNull) continue;
-            const uint32_t sp = hs & ~kP2;
+            if (hs[q] == kNull) continue;
+            const uint32_t sp = hs[q] & ~kP2;
             if (!st_valid(h, sp)) continue;
             const float fx = fref<float>(h, sp, p.s_fx), fy = fref<float>(h, sp, p.s_fy);
-            if (hs & kP2) {
+            if (hs[q] & kP2) {
                 Fx -= fx;
                 Fy -= fy;
             } else {
@@ -245,13 +252,14 @@ __global__ __launch_bounds__(1024) void k_st_node_update(HeapView h, StructK p)
                 Fy += fy;
             }
         }
-        const float m = farr<float>(h, bid, p.n_m)[s];
-        float &vx = farr<float>(h, bid, p.n_vx)[s];
-        float &vy = farr<float>(h, bid, p.n_vy)[s];
         vx += Fx / m * p.dt;
         vy += Fy / m * p.dt;
-        farr<float>(h, bid, p.n_x)[s] += vx * p.dt;
-        farr<float>(h, bid, p.n_y)[s] += vy * p.dt;
+        x += vx * p.dt;
+        y += vy * p.dt;
+        farr<float>(h, bid, p.n_vx)[s] = vx;
+        farr<float>(h, bid, p.n_vy)[s] = vy;
+        farr<float>(h, bid, p.n_x)[s] = x;
+        farr<float>(h, bid, p.n_y)[s] = y;
     });
 }
 
