@@ -192,6 +192,10 @@ __global__ __launch_bounds__(1024) void k_adj_node(HeapView h, AdjK p)
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;
         float lx = farr<float>(h, bid, p.n_lx)[s], ly = farr<float>(h, bid, p.n_ly)[s];
+        // the node's own fields of the second part, loaded before the gathers
+        // of the first
+        const float m = farr<float>(h, bid, p.n_m)[s];
+        const float lvx = farr<float>(h, bid, p.n_lvx)[s], lvy = farr<float>(h, bid, p.n_lvy)[s];
         if (p.mode & 1u) {
             uint32_t e[8];
 #pragma unroll
@@ -213,9 +217,8 @@ __global__ __launch_bounds__(1024) void k_adj_node(HeapView h, AdjK p)
             farr<float>(h, bid, p.n_ly)[s] = ly;
         }
         if (p.mode & 2u) {
-            const float m = farr<float>(h, bid, p.n_m)[s];
-            const float mux = farr<float>(h, bid, p.n_lvx)[s] + p.dt * lx;
-            const float muy = farr<float>(h, bid, p.n_lvy)[s] + p.dt * ly;
+            const float mux = lvx + p.dt * lx;
+            const float muy = lvy + p.dt * ly;
             farr<float>(h, bid, p.n_wx)[s] = mux / m;
             farr<float>(h, bid, p.n_wy)[s] = muy / m;
             farr<float>(h, bid, p.n_lvx)[s] = mux;
