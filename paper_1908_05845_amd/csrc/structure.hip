@@ -423,8 +423,9 @@ LaunchShape family_shape(smmo_heap *h, uint32_t cls, uint32_t mask)
     uint64_t blocks = 0;
     for (uint32_t c = 0; c < h->schema->nclasses; ++c)
         if ((mask >> c) & 1) blocks += h->ub_blocks[c];
-    // the family walks are latency-bound scans: one resident round of 32
-    // wavefronts per CU walks a BFS level faster than two rounds of 32
+    // the family walks are latency-bound scans: a grid that is resident all at
+    // once (32 wavefronts per CU) walks a BFS level faster than one twice as
+    // large
     uint64_t waves = h->cfg.grid_waves ? h->cfg.grid_waves : 32ull * h->cu_count;
     if (h->cur_method < 64 && h->launch_waves[h->cur_method][cls]) waves = h->launch_waves[h->cur_method][cls];
     waves = std::min<uint64_t>(waves, std::max<uint64_t>(1, blocks));
