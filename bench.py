@@ -385,7 +385,7 @@ def bench_spring(args, torch):
     def cpu_leg():
         from oracle import spring_steps
 
-        k = args.cpu_steps or 50
+        k = args.cpu_steps or 200     # about 10-15 s of float64 oracle work on one core
         t = time.perf_counter()
         r = spring_steps(mesh, dt, limit, k)
         el = time.perf_counter() - t
