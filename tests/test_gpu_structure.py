@@ -151,3 +151,27 @@ def test_abstract_class_and_family_dispatch(dev):
     # a node method on the spring class is refused
     with pytest.raises(smmo.SmmoError):
         sim.do("Spring", "bfs_init")
+
+
+@pytest.mark.parametrize("wg,waves", [(64, 1), (64, 3), (128, 2)])
+def test_bfs_walks_with_small_grids(dev, wg, waves):
+    """The family walk with fewer wavefronts than blocks: each wavefront steps
+    through several blocks and across the three node classes' lists, and the
+    distances, levels and deletions still equal the oracle's."""
+    from paper_1908_05845_amd import smmo
+
+    print("structure bfs grid wg %d waves %d" % (wg, waves), flush=True)
+    mesh = structure_mesh(40, 16, seed=3, pull_speed=2.0, break_strain=0.02, v_sigma=0.05)
+    sim = StructureSim(mesh, 1e-4, bfs_batch=4)
+    nb = sim.heap.cls["NodeBase"]
+    for name in ("structure.bfs_init", "structure.bfs_visit", "structure.bfs_mark"):
+        smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), nb, wg, waves, 0)
+    removed = 0
+    for _ in range(8):
+        sim.pull(10 * sim.dt)
+        for _ in range(10):
+            sim.compute_step()
+        removed += check_bfs(sim, mesh)[1]
+    assert removed > 0
+    st = sim.heap.stats()
+    assert st.device_error == 0
