@@ -16,9 +16,11 @@ from .oracle import (  # noqa: F401
     spring_adjoint,
     spring_adjoint_step,
     spring_breaks,
+    spring_tie_band,
     spring_steps_deg,
     structure_pull,
     structure_step,
+    STRUCTURE_TIE_REL,
     structure_bfs,
     STRUCTURE_ANCHOR,
     STRUCTURE_PULL,

@@ -56,7 +56,7 @@ def _load():
             lib.orc_nbody_force_at.argtypes = [LL, P, P, P, D, D, P, LL, P, P, P, P]
             lib.orc_spring_steps.restype = LL
             lib.orc_spring_steps.argtypes = [LL, P, P, P, P, P, P, P, LL, P, P, P, P, P, P,
-                                             P, P, P, D, C.c_float, C.c_int, P, P, P, P, P, C.c_int]
+                                             P, P, P, D, D, C.c_int, P, P, P, P, P, C.c_int, P, P]
             lib.orc_spring_adjoint.restype = C.c_int
             lib.orc_spring_adjoint.argtypes = [LL, P, P, P, P, P, P, P, LL, P, P, P, P, P, P, P, P,
                                                D, C.c_int, C.c_int, P, P, P, P, P, P, P, P]
@@ -64,7 +64,9 @@ def _load():
             lib.orc_spring_adjoint_step.argtypes = [LL, P, P, P, P, P, LL, P, P, P, P, D,
                                                     P, P, P, P, P, P, P, P, P, P]
             lib.orc_spring_breaks.restype = C.c_int
-            lib.orc_spring_breaks.argtypes = [D, D, D, D, D, C.c_float]
+            lib.orc_spring_breaks.argtypes = [D, D, D, D, D, D, P]
+            lib.orc_spring_tie_band.restype = D
+            lib.orc_spring_tie_band.argtypes = []
             lib.orc_wator_create.restype = P
             lib.orc_wator_create.argtypes = [C.c_int, C.c_int, C.c_uint64, P, P, P, P]
             lib.orc_wator_step.restype = C.c_int
@@ -75,7 +77,7 @@ def _load():
             lib.orc_wator_free.argtypes = [P]
             lib.orc_spring_steps_deg.restype = LL
             lib.orc_spring_steps_deg.argtypes = [LL, C.c_int, P, P, P, P, P, P, P, LL, P, P, P, P, P, P,
-                                                 P, P, P, D, C.c_float, C.c_int, P, P, P, P, P]
+                                                 P, P, P, D, D, C.c_int, P, P, P, P, P, P, P]
             lib.orc_generation_steps.restype = C.c_int
             lib.orc_generation_steps.argtypes = [C.c_int, C.c_int, P, P, C.c_uint32, C.c_uint32, C.c_int32,
                                                  C.c_int]
@@ -83,7 +85,7 @@ def _load():
             lib.orc_structure_pull.argtypes = [LL, P, P, P, P, P, P, D]
             lib.orc_structure_step.restype = LL
             lib.orc_structure_step.argtypes = [LL, P, P, P, P, P, P, P, P, P, P, LL, P, P, P, P, P, P, P,
-                                               P, P, P, D, P, P, P, P, P]
+                                               P, P, P, D, P, P, P, P, P, P, P]
             lib.orc_structure_bfs.restype = LL
             lib.orc_structure_bfs.argtypes = [LL, P, P, P, P, P, P, LL, P, P, P, P, P, P, P]
             _lib = lib
@@ -218,16 +220,33 @@ def nbody_force_at(x, y, m, G, eps, idx):
     return fx, fy, sfx, sfy
 
 
+def _ties(tie, S):
+    if tie is None:
+        return None
+    t = np.ascontiguousarray(tie, dtype=np.int8)
+    assert t.size == S
+    return t
+
+
+def spring_tie_band() -> float:
+    """Half-width of the band of strains around the break threshold within
+    which either break decision is correct (float32 rounding of the strain)."""
+    return float(_load().orc_spring_tie_band())
+
+
 def spring_steps(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1,
-                 alive=None, fx=None, fy=None, tension_only: bool = False):
+                 alive=None, fx=None, fy=None, tension_only: bool = False, tie=None):
     """Thesis Ch.7 "structure" compute steps: `steps` x {Spring::compute_force,
-    Node::update} in float64 with the float32 break decision; tension_only =
-    springs that only pull (no force while l <= L0, decided in float32).
+    Node::update} in float64, the break rule (strain > thresh) decided in
+    float64; tension_only = springs that only pull (no force while l <= L0).
 
     `mesh` holds x, y, vx, vy, m, adj, adj_is_b, a, b, k, L0, slot_a, slot_b
-    (ids local to the arrays).  Returns a new dict with the updated state, the
-    spring forces fx, fy, the alive flags, the number of springs broken and
-    the conditioning scales sf (per spring), svx, svy, sx, sy (per node).
+    (ids local to the arrays).  tie (int8 per spring, optional): fixed break
+    decisions (0 keep, 1 break, -1 decide) of springs within the tie band in
+    the first step.  Returns a new dict with the updated state, the spring
+    forces fx, fy, the alive flags, the number of springs broken, the strain
+    of each spring at its last force pass (NaN for springs dead at the start)
+    and the conditioning scales sf (per spring), svx, svy, sx, sy (per node).
     """
     lib = _load()
     N = int(np.asarray(mesh["x"]).size)
@@ -245,20 +264,24 @@ def spring_steps(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1,
     fxo = np.zeros(S) if fx is None else _f64(fx)
     fyo = np.zeros(S) if fy is None else _f64(fy)
     sf = np.zeros(S)
+    strain = np.full(S, np.nan)
     svx, svy, sx, sy = (np.zeros(N) for _ in range(4))
+    t = _ties(tie, S)
     nb = lib.orc_spring_steps(N, _p(x), _p(y), _p(vx), _p(vy), _p(m), _p(adj), _p(adjb),
                               S, _p(a), _p(b), _p(kk), _p(L0), _p(sa), _p(sb), _p(al),
                               _p(fxo), _p(fyo), float(dt), float(thresh), int(steps),
-                              _p(sf), _p(svx), _p(svy), _p(sx), _p(sy), int(bool(tension_only)))
+                              _p(sf), _p(svx), _p(svy), _p(sx), _p(sy), int(bool(tension_only)),
+                              _p(t), _p(strain))
     if nb < 0:
         raise RuntimeError("oracle spring error %d" % nb)
     out = dict(mesh)
     out.update(x=x, y=y, vx=vx, vy=vy, adj=adj, alive=al, fx=fxo, fy=fyo, nbroken=int(nb),
-               sf=sf, svx=svx, svy=svy, sx=sx, sy=sy)
+               sf=sf, svx=svx, svy=svy, sx=sx, sy=sy, strain=strain)
     return out
 
 
-def spring_steps_deg(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1, alive=None, fx=None, fy=None):
+def spring_steps_deg(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1, alive=None, fx=None, fy=None,
+                     tie=None):
     """spring_steps for meshes of any node degree D (adj and adj_is_b of shape
     (N, D)): the same steps and decisions, slots summed in order."""
     lib = _load()
@@ -279,22 +302,28 @@ def spring_steps_deg(mesh: dict, dt: float, thresh: float = 0.3, steps: int = 1,
     fxo = np.zeros(S) if fx is None else _f64(fx)
     fyo = np.zeros(S) if fy is None else _f64(fy)
     sf = np.zeros(S)
+    strain = np.full(S, np.nan)
     svx, svy, sx, sy = (np.zeros(N) for _ in range(4))
+    t = _ties(tie, S)
     nb = lib.orc_spring_steps_deg(N, D, _p(x), _p(y), _p(vx), _p(vy), _p(m), _p(adj), _p(adjb), S, _p(a), _p(b),
                                   _p(kk), _p(L0), _p(sa), _p(sb), _p(al), _p(fxo), _p(fyo), float(dt),
-                                  float(thresh), int(steps), _p(sf), _p(svx), _p(svy), _p(sx), _p(sy))
+                                  float(thresh), int(steps), _p(sf), _p(svx), _p(svy), _p(sx), _p(sy),
+                                  _p(t), _p(strain))
     if nb < 0:
         raise RuntimeError("oracle spring error %d" % nb)
     out = dict(mesh)
     out.update(x=x, y=y, vx=vx, vy=vy, adj=adj, alive=al, fx=fxo, fy=fyo, nbroken=int(nb),
-               sf=sf, svx=svx, svy=svy, sx=sx, sy=sy)
+               sf=sf, svx=svx, svy=svy, sx=sx, sy=sy, strain=strain)
     return out
 
 
-def spring_breaks(xa, ya, xb, yb, L0, thresh=0.3) -> bool:
-    """The float32 break decision of one spring."""
-    return bool(_load().orc_spring_breaks(float(xa), float(ya), float(xb), float(yb),
-                                          float(L0), float(thresh)))
+def spring_breaks(xa, ya, xb, yb, L0, thresh=0.3, with_strain=False):
+    """The break decision of one spring (float64: strain (l - L0)/L0 > thresh);
+    with_strain: (decision, strain)."""
+    e = C.c_double()
+    r = bool(_load().orc_spring_breaks(float(xa), float(ya), float(xb), float(yb),
+                                       float(L0), float(thresh), C.byref(e)))
+    return (r, e.value) if with_strain else r
 
 
 def spring_adjoint(mesh: dict, dt: float, steps: int, every: int = 20, xhat=None, yhat=None):
@@ -388,26 +417,33 @@ def structure_pull(st: dict, dt: float) -> dict:
     return o
 
 
-def structure_step(st: dict, dt: float) -> dict:
+STRUCTURE_TIE_REL = 1e-6   # tie band of the force limit, relative to k (l + L0)
+
+
+def structure_step(st: dict, dt: float, tie=None) -> dict:
     """One compute step of "structure" (Spring::force, then Node::update).
 
     State: per node id ntype (0 anchor, 1 pull, 2 node), nalive, x, y, vx, vy,
     m, slot (3 per node: spring id or -1), isp2 (3 per node), nspr, dist; per
-    spring id p1, p2, k, L0, maxf, s1, s2, salive, fx, fy, sdel.  Returns the
-    new state with nbroken and the conditioning scales sf, svx, svy, sx, sy.
+    spring id p1, p2, k, L0, maxf, s1, s2, salive, fx, fy, sdel.  tie (int8 per
+    spring, optional): fixed break decisions of ties.  Returns the new state
+    with nbroken, the float64 force F = k (l - L0) of each spring live at the
+    start (NaN otherwise) and the conditioning scales sf, svx, svy, sx, sy.
     """
     o = _structure_arrays(st)
     N, S = o["x"].size, o["p1"].size
     sf = np.zeros(S)
+    F = np.full(S, np.nan)
     svx, svy, sx, sy = (np.zeros(N) for _ in range(4))
+    t = _ties(tie, S)
     nb = _load().orc_structure_step(
         N, _p(o["ntype"]), _p(o["nalive"]), _p(o["x"]), _p(o["y"]), _p(o["vx"]), _p(o["vy"]), _p(o["m"]),
         _p(o["slot"]), _p(o["isp2"]), _p(o["nspr"]), S, _p(o["p1"]), _p(o["p2"]), _p(o["k"]), _p(o["L0"]),
         _p(o["maxf"]), _p(o["s1"]), _p(o["s2"]), _p(o["salive"]), _p(o["fx"]), _p(o["fy"]), float(dt),
-        _p(sf), _p(svx), _p(svy), _p(sx), _p(sy))
+        _p(sf), _p(svx), _p(svy), _p(sx), _p(sy), _p(t), _p(F))
     if nb < 0:
         raise RuntimeError("oracle structure error %d" % nb)
-    o.update(nbroken=int(nb), sf=sf, svx=svx, svy=svy, sx=sx, sy=sy)
+    o.update(nbroken=int(nb), sf=sf, svx=svx, svy=svy, sx=sx, sy=sy, F=F)
     return o
 
 

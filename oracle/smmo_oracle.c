@@ -390,14 +390,19 @@ int orc_nbody_force_at(long long n, const double *x, const double *y, const doub
 /* change l - L0), the force on endpoint a is k (l - L0) d / l with          */
 /* d = x_b - x_a and the force on b is its negative; a spring breaks when    */
 /* its strain (l - L0) / L0 exceeds a threshold, and it then exerts no force */
-/* in that step.  The break decision is integer-valued, so it is taken in    */
-/* float32, in the same operation order as the GPU kernel:                   */
-/*   dx = xb - xa; dy = yb - ya; l2 = fma(dx, dx, dy*dy); l = sqrt(l2);       */
-/*   strain = (l - L0) / L0;  break iff strain > threshold                   */
-/* with every operation rounded to float32.  Forces and the update are float64. */
-/* Tension-only springs (the thesis's springs act only while stretched) give  */
-/* no force while l <= L0; that decision is integer-valued too and uses the   */
-/* same float32 l and float32 L0.                                            */
+/* in that step.  Both decisions (break; for tension-only springs, which    */
+/* give no force while l <= L0, slack) are taken in float64 from the state  */
+/* as given: the plain definition of the rule, in no particular float32     */
+/* operation order.                                                          */
+/* Ties.  A float32 implementation fed the same float32 state computes the  */
+/* strain with an error of a few units in the last place (dx, dy rounded,   */
+/* the square, the sum and the root rounded, l - L0 exact near the limit,   */
+/* the quotient rounded: about 4.2 * 2^-24 = 2.5e-7 near strain 0.3).  A     */
+/* spring whose float64 strain lies within SP_TIE_STRAIN of the threshold is */
+/* a tie: either decision is correct.  A caller may fix the decision of     */
+/* such springs for the first step of a call (tie[s] = 0 keep, 1 break,     */
+/* -1 decide); fixing one outside the band is an error.  Slack ties need no */
+/* such care: there the force k (l - L0) is within rounding of zero.        */
 /* Nodes keep up to 8 spring slots; a break empties the two slots (the       */
 /* spring remembers its slot index in each node); Node::update sums the      */
 /* occupied slots in slot order.                                             */
@@ -420,30 +425,36 @@ typedef struct {
 typedef struct {
     ostore node, spring;
     size_t *snap;
-    float thresh;
+    double thresh;
     int tension_only;
     double dt;
     long long nbroken;
     int err;
+    const int8_t *tie;         /* fixed decisions of ties in the first step, or NULL */
+    double *strain;            /* strain of each spring at its last force pass, or NULL */
+    int first;                 /* 1 during the first step of the call */
 } sp_world;
 
-/* the spring length in float32, in the operation order given above */
-static float sp_len32(double xa, double ya, double xb, double yb)
+/* half-width of the tie band around the break threshold, in strain (see above) */
+#define SP_TIE_STRAIN 1e-6
+
+/* the break decision of one spring in float64: strain (l - L0) / L0 above
+ * the threshold; *strain receives the strain */
+static int sp_breaks(double xa, double ya, double xb, double yb, double L0, double thresh, double *strain)
 {
-    float dx = (float)xb - (float)xa;
-    float dy = (float)yb - (float)ya;
-    float dy2 = dy * dy;
-    float l2 = fmaf(dx, dx, dy2);
-    return sqrtf(l2);
+    const double dx = xb - xa, dy = yb - ya;
+    const double l = sqrt(dx * dx + dy * dy);
+    *strain = (l - L0) / L0;
+    return *strain > thresh;
 }
 
-/* the float32 break decision (see above) */
-static int sp_breaks(double xa, double ya, double xb, double yb, double L0, float thresh)
+/* the decision of spring `sid` with strain `strain`: the rule, or the fixed
+ * decision of a tie; -1 if a fixed decision lies outside the tie band */
+static int sp_decide(const int8_t *tie, long long sid, double strain, double thresh, int rule)
 {
-    float l = sp_len32(xa, ya, xb, yb);
-    float L0f = (float)L0;
-    float strain = (l - L0f) / L0f;
-    return strain > thresh;
+    if (!tie || tie[sid] < 0) return rule;
+    if (!(fabs(strain - thresh) <= SP_TIE_STRAIN)) return -1;
+    return tie[sid] != 0;
 }
 
 static void sp_spring_force(sp_world *w, size_t self)
@@ -451,7 +462,15 @@ static void sp_spring_force(sp_world *w, size_t self)
     sp_spring *s = os_at(&w->spring, self);
     sp_node *a = os_at(&w->node, (size_t)s->a);
     sp_node *b = os_at(&w->node, (size_t)s->b);
-    if (sp_breaks(a->x, a->y, b->x, b->y, s->L0, w->thresh)) {
+    double strain;
+    int brk = sp_breaks(a->x, a->y, b->x, b->y, s->L0, w->thresh, &strain);
+    if (w->strain) w->strain[self] = strain;
+    brk = sp_decide(w->first ? w->tie : NULL, (long long)self, strain, w->thresh, brk);
+    if (brk < 0) {
+        w->err = 8;
+        return;
+    }
+    if (brk) {
         if (a->adj[s->sa] != (long long)self || b->adj[s->sb] != (long long)self) w->err = 4;
         a->adj[s->sa] = -1;
         b->adj[s->sb] = -1;
@@ -460,16 +479,19 @@ static void sp_spring_force(sp_world *w, size_t self)
         if (os_destroy(&w->spring, self)) w->err = 5;   /* last statement: delete this */
         return;
     }
-    if (w->tension_only && !(sp_len32(a->x, a->y, b->x, b->y) > (float)s->L0)) {
-        s->fx = s->fy = s->sf = 0;     /* slack: a tension-only spring does not push */
-        return;
-    }
     double dx = b->x - a->x, dy = b->y - a->y;
     double l = sqrt(dx * dx + dy * dy);
+    /* scale of the float32 rounding error of f: the terms k l and k L0 of
+     * k (l - L0) in magnitude (also for a slack spring, whose decision is
+     * within that error of the other one at a tie) */
+    s->sf = s->k * (l + s->L0);
+    if (w->tension_only && !(l > s->L0)) {
+        s->fx = s->fy = 0;     /* slack: a tension-only spring does not push */
+        return;
+    }
     double c = s->k * (l - s->L0) / l;
     s->fx = c * dx;
     s->fy = c * dy;
-    s->sf = s->k * (l + s->L0);    /* scale of the float32 rounding error of f */
 }
 
 static void sp_node_update(sp_world *w, sp_node *n)
@@ -501,8 +523,12 @@ static void sp_node_update(sp_world *w, sp_node *n)
  * Optional outputs (NULL to skip), all of the last step:
  *   sf (S)               scale of each spring force
  *   svx, svy, sx, sy (N) scales of the node velocity and position updates
+ *   strain (S)           strain of each spring at its last force pass
+ *                        (entries of springs dead at the start untouched)
  * tension_only: springs give no force while l <= L0 (see above).
- * Returns the number of springs broken, or a negative error code.
+ * tie (S, or NULL): fixed decisions of ties in the first step (see above).
+ * Returns the number of springs broken, or a negative error code (-18: a
+ * fixed decision outside the tie band).
  */
 long long orc_spring_steps(long long N, double *x, double *y, double *vx, double *vy,
                            const double *m, int32_t *adj, const uint8_t *adjb,
@@ -510,15 +536,17 @@ long long orc_spring_steps(long long N, double *x, double *y, double *vx, double
                            const double *k, const double *L0,
                            const int32_t *slot_a, const int32_t *slot_b,
                            uint8_t *alive, double *fx, double *fy,
-                           double dt, float thresh, int steps,
+                           double dt, double thresh, int steps,
                            double *sf, double *svx, double *svy, double *sx, double *sy,
-                           int tension_only)
+                           int tension_only, const int8_t *tie, double *strain)
 {
     sp_world w;
     memset(&w, 0, sizeof w);
     w.dt = dt;
     w.thresh = thresh;
     w.tension_only = tension_only != 0;
+    w.tie = tie;
+    w.strain = strain;
     if (N < 0 || S < 0) return -1;
     if (os_init(&w.node, sizeof(sp_node), (size_t)(N ? N : 1)) ||
         os_init(&w.spring, sizeof(sp_spring), (size_t)(S ? S : 1))) return -1;
@@ -546,6 +574,7 @@ long long orc_spring_steps(long long N, double *x, double *y, double *vx, double
             if (sid >= S || (sid >= 0 && !alive[sid])) w.err = 6;
         }
     for (int st = 0; st < steps && !w.err; st++) {
+        w.first = st == 0;
         size_t kk = os_snapshot(&w.spring, w.snap);
         for (size_t i = 0; i < kk; i++) sp_spring_force(&w, w.snap[i]);
         kk = os_snapshot(&w.node, w.snap);
@@ -573,11 +602,18 @@ long long orc_spring_steps(long long N, double *x, double *y, double *vx, double
     return w.err ? -(long long)w.err - 10 : w.nbroken;
 }
 
-/* the float32 break decision alone, for tests of its edge cases */
-int orc_spring_breaks(double xa, double ya, double xb, double yb, double L0, float thresh)
+/* the break decision alone, for tests of its edge cases; *strain (or NULL)
+ * receives the strain */
+int orc_spring_breaks(double xa, double ya, double xb, double yb, double L0, double thresh, double *strain)
 {
-    return sp_breaks(xa, ya, xb, yb, L0, thresh);
+    double e;
+    const int r = sp_breaks(xa, ya, xb, yb, L0, thresh, &e);
+    if (strain) *strain = e;
+    return r;
 }
+
+/* half-width of the tie band (for the tests that count ties) */
+double orc_spring_tie_band(void) { return SP_TIE_STRAIN; }
 
 /* ------------------------------------------------------------------------ */
 /* Differentiable spring mesh (reverse mode through the compute steps above,  */
@@ -1138,11 +1174,12 @@ void orc_wator_free(void *wp)
 /* (the unlink decrements its spring count, and the unlink that takes it to  */
 /* zero deletes the node).  The force is stored on the spring as a vector,   */
 /* (fx, fy) = k (l - L0) d / l with d = x_p2 - x_p1 acting on p1 (p2 gets    */
-/* the negative), so that Node::update reads no other node.  The stretch and */
-/* break decisions are integer-valued and taken in float32 in the kernel's   */
-/* operation order: l as for the mesh springs, stretched iff l > L0,         */
-/* F = k * (l - L0) with each operation rounded, break iff stretched and     */
-/* F > limit.  Everything else is float64.                                   */
+/* the negative), so that Node::update reads no other node.  The stretch    */
+/* (l > L0) and break (k (l - L0) > limit) decisions are taken in float64   */
+/* from the state as given, like those of the mesh springs.  A spring whose  */
+/* float64 force lies within ST_TIE_REL k (l + L0) of its limit is a tie (a  */
+/* float32 evaluation of k (l - L0) errs by at most about 5 * 2^-24 of that */
+/* scale); the caller may fix its decision (tie[s] = 0 keep, 1 break).      */
 /* State arrays (node id i, spring id s; ids are canonical, alive flags      */
 /* mark the live objects):                                                   */
 /*   ntype[i] 0 anchor, 1 pull, 2 node; nalive[i]; x, y, vx, vy, m;          */
@@ -1155,6 +1192,7 @@ void orc_wator_free(void *wp)
 #define ST_PULL 1
 #define ST_NODE 2
 #define ST_MAXDIST 0x7FFFFFFF
+#define ST_TIE_REL 1e-6
 
 /* Node::remove_spring: empty the slot; the unlink that removes the last
  * spring deletes the node */
@@ -1180,14 +1218,17 @@ int orc_structure_pull(long long N, const int32_t *ntype, const uint8_t *nalive,
 
 /* One compute step: Spring::force over the live springs, then Node::update
  * over the live Nodes.  sf (S) and svx, svy, sx, sy (N), optional, receive
- * the conditioning scales as for the mesh springs.  Returns the number of
- * springs broken, or a negative error code. */
+ * the conditioning scales as for the mesh springs; F (S), optional, the
+ * float64 force k (l - L0) of each live spring; tie (S), optional, fixed
+ * decisions of ties (see above).  Returns the number of springs broken, or a
+ * negative error code (-18: a fixed decision outside the tie band). */
 long long orc_structure_step(long long N, const int32_t *ntype, uint8_t *nalive, double *x, double *y,
                              double *vx, double *vy, const double *m, int32_t *slot, const uint8_t *isp2,
                              int32_t *nspr, long long S, const int32_t *p1, const int32_t *p2,
                              const double *k, const double *L0, const double *maxf, const int32_t *s1,
                              const int32_t *s2, uint8_t *salive, double *fx, double *fy, double dt,
-                             double *sf, double *svx, double *svy, double *sx, double *sy)
+                             double *sf, double *svx, double *svy, double *sx, double *sy,
+                             const int8_t *tie, double *F)
 {
     long long nbroken = 0;
     uint8_t *snap = malloc((size_t)(S ? S : 1));
@@ -1197,12 +1238,20 @@ long long orc_structure_step(long long N, const int32_t *ntype, uint8_t *nalive,
         if (!snap[s]) continue;
         const long long a = p1[s], b = p2[s];
         if (a < 0 || a >= N || b < 0 || b >= N || !nalive[a] || !nalive[b]) { free(snap); return -12; }
-        const float l32 = sp_len32(x[a], y[a], x[b], y[b]);
-        const float L0f = (float)L0[s];
-        const float d32 = l32 - L0f;
-        const float F32 = (float)k[s] * d32;
-        const int stretched = l32 > L0f;
-        if (stretched && F32 > (float)maxf[s]) {
+        const double dx = x[b] - x[a], dy = y[b] - y[a];
+        const double l = sqrt(dx * dx + dy * dy);
+        const double Fs = k[s] * (l - L0[s]);
+        const int stretched = l > L0[s];
+        if (F) F[s] = Fs;
+        int brk = stretched && Fs > maxf[s];
+        if (tie && tie[s] >= 0) {
+            if (!(fabs(Fs - maxf[s]) <= ST_TIE_REL * k[s] * (l + L0[s]))) {
+                free(snap);
+                return -18;
+            }
+            brk = tie[s] != 0;
+        }
+        if (brk) {
             if (st_unlink(a, s1[s], s, slot, nspr, nalive) || st_unlink(b, s2[s], s, slot, nspr, nalive)) {
                 free(snap);
                 return -17;
@@ -1213,17 +1262,16 @@ long long orc_structure_step(long long N, const int32_t *ntype, uint8_t *nalive,
             nbroken++;
             continue;
         }
+        /* the scale also for a slack spring: at a stretch tie its force is
+         * within that rounding of zero either way */
+        if (sf) sf[s] = k[s] * (l + L0[s]);
         if (!stretched) {
             fx[s] = fy[s] = 0;
-            if (sf) sf[s] = 0;
             continue;
         }
-        const double dx = x[b] - x[a], dy = y[b] - y[a];
-        const double l = sqrt(dx * dx + dy * dy);
         const double c = k[s] * (l - L0[s]) / l;
         fx[s] = c * dx;
         fy[s] = c * dy;
-        if (sf) sf[s] = k[s] * (l + L0[s]);
     }
     free(snap);
     for (long long i = 0; i < N; i++) {            /* Node::update over the live Nodes */
@@ -1366,7 +1414,7 @@ int orc_generation_steps(int W, int H, uint8_t *state, int32_t *left, uint32_t S
 /* in slot order.  It serves meshes whose nodes exceed the 8 slots of        */
 /* orc_spring_steps (hubs), whose adjacency the GPU stores partly inlined    */
 /* (Ch.4 sec.4.3.1 "SOA with Partial Inlining").  Arguments and results as   */
-/* orc_spring_steps.                                                         */
+/* orc_spring_steps (two-sided springs).                                     */
 /* ------------------------------------------------------------------------ */
 long long orc_spring_steps_deg(long long N, int D, double *x, double *y, double *vx, double *vy,
                                const double *m, int32_t *adj, const uint8_t *adjb,
@@ -1374,8 +1422,9 @@ long long orc_spring_steps_deg(long long N, int D, double *x, double *y, double 
                                const double *k, const double *L0,
                                const int32_t *slot_a, const int32_t *slot_b,
                                uint8_t *alive, double *fx, double *fy,
-                               double dt, float thresh, int steps,
-                               double *sf, double *svx, double *svy, double *sx, double *sy)
+                               double dt, double thresh, int steps,
+                               double *sf, double *svx, double *svy, double *sx, double *sy,
+                               const int8_t *tie, double *strain)
 {
     if (N < 0 || S < 0 || D < 1) return -1;
     double *f_x = malloc((size_t)(S ? S : 1) * sizeof(double));
@@ -1402,7 +1451,15 @@ long long orc_spring_steps_deg(long long N, int D, double *x, double *y, double 
         for (long long s = 0; s < S; s++) {           /* Spring::compute_force */
             if (!snap[s]) continue;
             const long long ia = a[s], ib = b[s];
-            if (sp_breaks(x[ia], y[ia], x[ib], y[ib], L0[s], thresh)) {
+            double e;
+            int brk = sp_breaks(x[ia], y[ia], x[ib], y[ib], L0[s], thresh, &e);
+            if (strain) strain[s] = e;
+            brk = sp_decide(st == 0 ? tie : NULL, s, e, thresh, brk);
+            if (brk < 0) {
+                err = 8;
+                break;
+            }
+            if (brk) {
                 if (adj[ia * D + slot_a[s]] != s || adj[ib * D + slot_b[s]] != s) err = 4;
                 adj[ia * D + slot_a[s]] = -1;
                 adj[ib * D + slot_b[s]] = -1;

@@ -24,3 +24,15 @@ def dev():
 
     smmo.load_library()   # raises if libsmmo.so is missing
     return torch.device("cuda:0")
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Break-decision ties met by the GPU parity checks of this session."""
+    mod = sys.modules.get("spring_parity")
+    if mod is None or not mod.TIES["checked_spring_steps"]:
+        return
+    t = mod.TIES
+    terminalreporter.write_line(
+        "spring break decisions: %d checked steps; springs within the tie band of the limit: %d; "
+        "decided by the GPU otherwise than the float64 rule: %d" % (t["checked_spring_steps"], t["near"],
+                                                                   t["flipped"]))

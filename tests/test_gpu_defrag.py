@@ -13,7 +13,6 @@ import numpy as np
 import pytest
 
 from inputs import spring_mesh
-from oracle import spring_steps
 from paper_1908_05845_amd import smmo
 from paper_1908_05845_amd.sims import SpringSim
 

@@ -4,19 +4,21 @@ steps) against the float64 oracle.
 Per checked step k the GPU's float32 state (positions, velocities, live
 springs, adjacency) is read back; the oracle takes those values and runs
 one step.  Topology is integer work and must match exactly: the set of live
-springs and every adjacency slot (the break decision is taken in float32 on
-both sides, in the same operation order).  Float results must match within
-1e-5 of their conditioning scale (spring force: k (l + L0); node velocity
-and position: |v| + dt S_F / m and |x| + dt S_v, S_F = sum of the scales of
-the attached springs).
+springs and every adjacency slot.  The oracle decides breaks in float64, the
+kernel in float32: a spring decided differently must lie within float32
+rounding of the limit (a tie, where both decisions are valid; counted and
+reported), and the oracle's step is then rerun with the GPU's decision for
+it.  Float results must match within 1e-5 of their conditioning scale
+(spring force: k (l + L0); node velocity and position: |v| + dt S_F / m and
+|x| + dt S_v, S_F = sum of the scales of the attached springs).
 """
 
 import numpy as np
 import pytest
 
 from inputs import spring_mesh
-from oracle import spring_steps
 from paper_1908_05845_amd import smmo
+from spring_parity import mesh_step
 from paper_1908_05845_amd.sims import SpringSim
 
 pytestmark = pytest.mark.gpu
@@ -32,13 +34,18 @@ def state_dict(mesh, st):
     return d
 
 
-def check_step(sim, mesh, dt, limit, tension_only=False):
+def check_step(sim, mesh, dt, limit, tension_only=False, ties=None):
+    """One GPU step against one oracle step from the GPU's state; `ties`
+    (a dict, optional) accumulates the near-tie and flipped counts."""
     st = sim.read()
     assert (st["adj"] != -2).all(), "adjacency names a dead spring"
-    ref = spring_steps(state_dict(mesh, st), dt, limit, 1, alive=st["alive"], fx=st["fx"], fy=st["fy"],
-                       tension_only=tension_only)
     sim.step(1)
     s1 = sim.read()
+    ref, near, flipped = mesh_step(state_dict(mesh, st), dt, limit, st["alive"], st["fx"], st["fy"], s1["alive"],
+                                   tension_only=tension_only)
+    if ties is not None:
+        ties["near"] = ties.get("near", 0) + near
+        ties["flipped"] = ties.get("flipped", 0) + flipped
     assert np.array_equal(s1["alive"], ref["alive"]), int(np.sum(s1["alive"] != ref["alive"]))
     assert np.array_equal(s1["adj"], ref["adj"])
     assert np.array_equal(s1["adj_is_b"][s1["adj"] >= 0], np.asarray(mesh["adj_is_b"])[s1["adj"] >= 0])
@@ -143,17 +150,19 @@ def test_config_1000x1000_checked_steps(dev, shapes):
         for name, shape in SHAPES_1000[shapes].items():
             cls = sim.heap.cls["Spring" if name == "spring.force" else "Node"]
             smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), cls, *shape)
-    checks = (0, 1, 10, 1000, 3000, 9999)
+    checks = (0, 1, 10, 1000, 3000, 5000, 7000, 9999)
     step = 0
     broken = 0
+    ties = {}
     while step <= checks[-1]:
         if step in checks:
             print("  check step", step, flush=True)
-            broken += check_step(sim, mesh, dt, limit)
+            broken += check_step(sim, mesh, dt, limit, ties=ties)
         else:
             sim.step(1)
         step += 1
-    print("  springs broken at checked steps:", broken, flush=True)
+    print("  springs broken at checked steps: %d; within the tie band: %d, decided otherwise than the "
+          "float64 rule: %d" % (broken, ties.get("near", 0), ties.get("flipped", 0)), flush=True)
     st = sim.read()
     n_alive = int(st["alive"].sum())
     assert sim.heap.stats().live_objects[sim.heap.cls["Spring"]] == n_alive

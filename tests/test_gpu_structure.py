@@ -5,9 +5,11 @@ the nodes no longer connected to an anchor node) against the float64 oracle.
 Every phase is checked from the GPU's own state: the oracle takes the state
 read back before the phase and runs that phase once.  Integer results must
 match exactly: which nodes and springs are alive, every spring slot of every
-node, the spring counts, the BFS distances and the number of BFS levels (the
-stretch and break decisions are taken in float32 on both sides, in the same
-operation order).  Floats must match within 1e-5 of their conditioning scale
+node, the spring counts, the BFS distances and the number of BFS levels.  The
+oracle decides breaks in float64 and the kernel in float32: a spring decided
+differently must be a tie (its float64 force within float32 rounding of the
+limit; counted and reported), and the oracle's step is then rerun with the
+GPU's decision for it.  Floats must match within 1e-5 of their conditioning scale
 (spring force: k (l + L0); node velocity and position: |v| + dt S_F / m and
 |x| + dt S_v).
 """
@@ -16,9 +18,10 @@ import numpy as np
 import pytest
 
 from inputs import structure_mesh
-from oracle import STRUCTURE_MAXDIST, structure_bfs, structure_pull, structure_step
+from oracle import STRUCTURE_MAXDIST, structure_bfs, structure_pull
 from paper_1908_05845_amd import smmo
 from paper_1908_05845_amd.sims import StructureSim
+from spring_parity import structure_compute_step
 
 pytestmark = pytest.mark.gpu
 
@@ -47,9 +50,9 @@ def check_topology(s1, ref):
 def check_step(sim, mesh):
     st = sim.read()
     assert (st["slot"] != -2).all(), "a slot names a dead spring"
-    ref = structure_step(state(mesh, st), sim.dt)
     sim.compute_step()
     s1 = sim.read()
+    ref, _, _ = structure_compute_step(state(mesh, st), sim.dt, s1["salive"])
     check_topology(s1, ref)
     sal = ref["salive"].astype(bool)
     for key in ("fx", "fy"):

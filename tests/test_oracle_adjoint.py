@@ -150,6 +150,10 @@ def test_single_step_function_composes_to_full_adjoint():
         r = spring_adjoint_step(mesh, xs[n], ys[n], dt, lx, ly, lvx, lvy)
         lx, ly, lvx, lvy = r["lx"], r["ly"], r["lvx"], r["lvy"]
         gk += r["gk"]
-        assert np.all(r["slx"] >= np.abs(r["lx"]) * 0) and np.all(r["sgk"] >= 0)
+        # each scale bounds its quantity (triangle inequality over its terms)
+        assert np.all(np.abs(r["lx"]) <= r["slx"] * (1 + 1e-12))
+        assert np.all(np.abs(r["ly"]) <= r["sly"] * (1 + 1e-12))
+        assert np.all(np.abs(r["lvx"]) <= r["slvx"] * (1 + 1e-12))
+        assert np.all(np.abs(r["gk"]) <= r["sgk"] * (1 + 1e-12))
     assert np.allclose(gk, full["gk"], rtol=1e-12, atol=0)
     assert np.array_equal(lvx, full["gvx"]) and np.array_equal(lx, full["gx"])
