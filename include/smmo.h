@@ -345,6 +345,12 @@ smmo_status smmo_method_id(const char *name, uint32_t *method_id);
  * truncated to n bytes). */
 smmo_status smmo_last_error(char *buf, size_t n);
 
+/* Hash of the sources the library was built from (every file of csrc/ and
+ * include/, and the compiler flags), as a NUL-terminated hex string owned by
+ * the library.  Bindings compare it with the sources beside them and refuse
+ * a library built from other sources. */
+const char *smmo_source_hash(void);
+
 #ifdef __cplusplus
 }
 #endif

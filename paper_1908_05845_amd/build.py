@@ -13,6 +13,7 @@ shared library.  Flags:
 
 import concurrent.futures as cf
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -38,9 +39,26 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def source_hash() -> str:
+    """Hash of what the library is built from: every file of csrc/ and
+    include/ (name and contents) and the compiler flags.  The library
+    returns the value it was built with (smmo_source_hash), and the binding
+    refuses a library whose value differs from that of the sources beside it."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*")) + glob.glob(os.path.join(ROOT, "include", "*")))
+    for fn in files:
+        if not os.path.isfile(fn):
+            continue
+        h.update(os.path.relpath(fn, ROOT).encode())
+        with open(fn, "rb") as f:
+            h.update(f.read())
+    h.update(" ".join(f for f in FLAGS if not f.startswith("/")).encode())
+    return h.hexdigest()[:32]
+
+
+def _compile(src: str, digest: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, '-DSMMO_SOURCE_HASH="%s"' % digest, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-8000:]))
@@ -51,8 +69,9 @@ def build(verbose: bool = False) -> str:
     """Compiles every csrc/*.hip and links libsmmo.so (always rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    digest = source_hash()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda src: _compile(src, digest), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

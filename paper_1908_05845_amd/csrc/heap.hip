@@ -1150,4 +1150,9 @@ smmo_status smmo_last_error(char *buf, size_t n)
     return SMMO_OK;
 }
 
+#ifndef SMMO_SOURCE_HASH
+#error "SMMO_SOURCE_HASH is set by the build (paper_1908_05845_amd/build.py)"
+#endif
+const char *smmo_source_hash(void) { return SMMO_SOURCE_HASH; }
+
 } // extern "C"

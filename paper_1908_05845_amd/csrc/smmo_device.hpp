@@ -146,14 +146,27 @@ struct BitOp {
 
 constexpr int kMaxOps = 6;
 
+// Invalidation attempts of one block (Alg. invalidate with rollback) before
+// the release that emptied it gives up, and the most switches one release
+// queues: a re-activation, a rollback per failed attempt but the last, and
+// the three switches of a successful invalidation.
+constexpr int kInvalidateAttempts = kMaxOps - 3;
+constexpr int kMaxReleaseOps = 1 + (kInvalidateAttempts - 1) + 3;
+static_assert(kMaxReleaseOps <= kMaxOps, "a release can queue more bitmap switches than the queue holds");
+
+// A lane's queue of pending switches.  A push into a full queue is not
+// dropped silently: it marks the queue, and completing the queue raises
+// ERR_INTERNAL (run_ops_wave, run_ops_lane).
 struct OpQueue {
     BitOp op[kMaxOps];
-    __device__ __forceinline__ void reset()
+    bool overflow;
+    __host__ __device__ __forceinline__ void reset()
     {
 #pragma unroll
         for (int i = 0; i < kMaxOps; ++i) op[i].dir = 0;
+        overflow = false;
     }
-    __device__ __forceinline__ bool push(uint32_t bmid, uint32_t pos, int dir)
+    __host__ __device__ __forceinline__ bool push(uint32_t bmid, uint32_t pos, int dir)
     {
 #pragma unroll
         for (int i = 0; i < kMaxOps; ++i)
@@ -164,9 +177,10 @@ struct OpQueue {
                 op[i].dir = (int8_t)dir;
                 return true;
             }
+        overflow = true;
         return false;
     }
-    __device__ __forceinline__ bool pending() const
+    __host__ __device__ __forceinline__ bool pending() const
     {
         bool p = false;
 #pragma unroll
@@ -209,6 +223,7 @@ __device__ __forceinline__ void bitop_try(const HeapView &h, BitOp &o)
 // that waits for another lane's switch cannot block it.
 __device__ __forceinline__ void run_ops_wave(const HeapView &h, OpQueue &q)
 {
+    if (q.overflow) raise_error(h, ERR_INTERNAL);
     for (uint32_t it = 0;; ++it) {
         bool pend = false;
 #pragma unroll
@@ -231,6 +246,7 @@ __device__ __forceinline__ void run_ops_wave(const HeapView &h, OpQueue &q)
 // lane of its wavefront holds pending switches while it runs).
 __device__ __forceinline__ void run_ops_lane(const HeapView &h, OpQueue &q)
 {
+    if (q.overflow) raise_error(h, ERR_INTERNAL);
     for (uint32_t it = 0; q.pending(); ++it) {
         if (it >= h.spin_limit) {
             raise_error(h, ERR_SPIN);
@@ -345,7 +361,7 @@ __device__ __forceinline__ uint64_t reserve_slots(const HeapView &h, uint32_t bi
 __device__ __forceinline__ bool invalidate_block(const HeapView &h, uint32_t bid, OpQueue &q)
 {
     uint64_t *p = h.alloc_bm + bid;
-    for (int attempt = 0; attempt < kMaxOps - 3; ++attempt) {
+    for (int attempt = 0; attempt < kInvalidateAttempts; ++attempt) {
         const uint64_t before = aor(p, ~0ull);
         if (before == ~0ull) return false;
         const uint32_t t = ald32(h.type + bid);

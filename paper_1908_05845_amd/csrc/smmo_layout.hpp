@@ -19,14 +19,8 @@
 // kept.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
-
-#ifndef __HIPCC__
-#ifndef __host__
-#define __host__
-#define __device__
-#endif
-#endif
 
 namespace smmo {
 

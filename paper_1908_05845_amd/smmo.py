@@ -154,6 +154,7 @@ EXPORTS = [
     "smmo_parallel_new", "smmo_parallel_do", "smmo_destroy", "smmo_gather_soa", "smmo_sync",
     "smmo_heap_stats", "smmo_check_invariants", "smmo_clear_error", "smmo_heap_info",
     "smmo_method_id", "smmo_last_error", "smmo_set_launch", "smmo_defragment", "smmo_coalescing_probe",
+    "smmo_source_hash",
 ]
 
 
@@ -167,6 +168,15 @@ def load_library(path: str = LIB_PATH):
             raise RuntimeError("libsmmo.so not found at %s: build it with "
                                "`python -m paper_1908_05845_amd.build`" % path)
         lib = C.CDLL(path)
+        lib.smmo_source_hash.restype = C.c_char_p
+        lib.smmo_source_hash.argtypes = []
+        from . import build as _build
+
+        built, here = lib.smmo_source_hash().decode(), _build.source_hash()
+        if built != here:
+            raise RuntimeError("libsmmo.so at %s was built from other sources (%s) than those beside it "
+                               "(%s): rebuild it with `python -m paper_1908_05845_amd.build`"
+                               % (path, built, here))
         P, S, U32, U64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64
         sig = {
             "smmo_config_default": (None, [P]),

@@ -19,7 +19,7 @@ def declared_functions():
             continue
         text = open(os.path.join(ROOT, "include", fn)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        for m in re.finditer(r"^\s*(?:smmo_status|void)\s+\**\s*(smmo_\w+)\s*\(", text, flags=re.M):
+        for m in re.finditer(r"^\s*(?:smmo_status|void|const char)\s+\**\s*(smmo_\w+)\s*\(", text, flags=re.M):
             names.add(m.group(1))
     return names
 
@@ -169,3 +169,15 @@ def test_struct_sizes_match_header(lib):
     assert C.sizeof(smmo.smmo_spring_pi_args) == 32
     assert C.sizeof(smmo.smmo_config) == 64
     assert C.sizeof(smmo.smmo_adjoint_args) == 80
+
+
+def test_library_refuses_other_sources(lib, tmp_path, monkeypatch):
+    """The library carries the hash of the sources it was built from; the
+    binding compares it with the sources beside it."""
+    from paper_1908_05845_amd import build
+
+    assert lib.smmo_source_hash().decode() == build.source_hash()
+    # a changed source changes the hash the binding expects
+    h0 = build.source_hash()
+    monkeypatch.setattr(build, "CSRC", str(tmp_path))
+    assert build.source_hash() != h0
