@@ -17,7 +17,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math"]
 
 
 def build() -> str:
@@ -59,7 +59,7 @@ def _load():
                                              P, P, P, D, D, C.c_int, P, P, P, P, P, C.c_int, P, P]
             lib.orc_spring_adjoint.restype = C.c_int
             lib.orc_spring_adjoint.argtypes = [LL, P, P, P, P, P, P, P, LL, P, P, P, P, P, P, P, P,
-                                               D, C.c_int, C.c_int, P, P, P, P, P, P, P, P]
+                                               D, C.c_int, C.c_int, P, P, P, P, P, P, P, P, P]
             lib.orc_spring_adjoint_step.restype = C.c_int
             lib.orc_spring_adjoint_step.argtypes = [LL, P, P, P, P, P, LL, P, P, P, P, D,
                                                     P, P, P, P, P, P, P, P, P, P]
@@ -67,6 +67,8 @@ def _load():
             lib.orc_spring_breaks.argtypes = [D, D, D, D, D, D, P]
             lib.orc_spring_tie_band.restype = D
             lib.orc_spring_tie_band.argtypes = []
+            lib.orc_threads.restype = C.c_int
+            lib.orc_threads.argtypes = []
             lib.orc_wator_create.restype = P
             lib.orc_wator_create.argtypes = [C.c_int, C.c_int, C.c_uint64, P, P, P, P]
             lib.orc_wator_step.restype = C.c_int
@@ -228,6 +230,11 @@ def _ties(tie, S):
     return t
 
 
+def threads() -> int:
+    """Host threads the oracle's parallel do-alls use (OMP_NUM_THREADS)."""
+    return int(_load().orc_threads())
+
+
 def spring_tie_band() -> float:
     """Half-width of the band of strains around the break threshold within
     which either break decision is correct (float32 rounding of the strain)."""
@@ -330,7 +337,9 @@ def spring_adjoint(mesh: dict, dt: float, steps: int, every: int = 20, xhat=None
     """Reverse-mode gradients of L = 1/2 |x_T - xhat|^2 through `steps`
     spring-mesh steps with breaking off (float64), checkpointing (x, v) every
     `every` steps.  xhat defaults to the initial positions.  Returns dict with
-    loss, gk (dL/dk), gvx, gvy (dL/dv0), gx, gy (dL/dx0), xT, yT."""
+    loss, gk (dL/dk), gvx, gvy (dL/dv0), gx, gy (dL/dx0), xT, yT, and agk =
+    sum over the reverse steps of dt |u . g| per spring (an error e in every
+    stretch l - L0 moves dL/dk by at most e agk)."""
     lib = _load()
     N = int(np.asarray(mesh["x"]).size)
     S = int(np.asarray(mesh["a"]).size)
@@ -345,16 +354,16 @@ def spring_adjoint(mesh: dict, dt: float, steps: int, every: int = 20, xhat=None
     sb = np.ascontiguousarray(mesh["slot_b"], dtype=np.int32)
     xh = x.copy() if xhat is None else _f64(xhat)
     yh = y.copy() if yhat is None else _f64(yhat)
-    gk = np.zeros(S)
+    gk, agk = np.zeros(S), np.zeros(S)
     gvx, gvy, gx, gy, xT, yT = (np.zeros(N) for _ in range(6))
     loss = C.c_double()
     rc = lib.orc_spring_adjoint(N, _p(x), _p(y), _p(vx), _p(vy), _p(m), _p(adj), _p(adjb), S, _p(a),
                                 _p(b), _p(kk), _p(L0), _p(sa), _p(sb), _p(xh), _p(yh), float(dt),
                                 int(steps), int(every), _p(gk), _p(gvx), _p(gvy), _p(gx), _p(gy),
-                                _p(xT), _p(yT), C.byref(loss))
+                                _p(xT), _p(yT), C.byref(loss), _p(agk))
     if rc:
         raise RuntimeError("oracle adjoint error %d" % rc)
-    return dict(loss=loss.value, gk=gk, gvx=gvx, gvy=gvy, gx=gx, gy=gy, xT=xT, yT=yT)
+    return dict(loss=loss.value, gk=gk, gvx=gvx, gvy=gvy, gx=gx, gy=gy, xT=xT, yT=yT, agk=agk)
 
 
 def spring_adjoint_step(mesh: dict, px, py, dt, lx, ly, lvx, lvy):

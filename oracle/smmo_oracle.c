@@ -1,10 +1,10 @@
 /*
  * CPU oracle of SMMO execution.  TEST INFRASTRUCTURE ONLY.
  *
- * Plain, slow, single-threaded C; float64 arithmetic; array-of-structs object
- * stores.  Only the test suite, the smoke check and the bench's CPU-baseline
- * leg load this library.  It shares no code, header, table or helper with the
- * HIP library, and it never calls it.
+ * Plain, slow C; float64 arithmetic; array-of-structs object stores.  Only
+ * the test suite, the smoke check and the bench's CPU-baseline leg load this
+ * library.  It shares no code, header, table or helper with the HIP library,
+ * and it never calls it.
  *
  * Semantics followed (Springer, "Memory-Efficient Object-Oriented Programming
  * on GPUs"):
@@ -20,7 +20,13 @@
  * on each id in ascending order, one after the other.  Every method below
  * reads only fields that the same do-all does not write (or its own
  * object's), so this sequential loop is one valid schedule of the parallel
- * operation.
+ * operation.  For the same reason the do-alls of the n-body and spring-mesh
+ * methods, which write only their own object, may hand the snapshot to
+ * several host threads (OpenMP, OMP_NUM_THREADS): any interleaving of such
+ * calls gives the same result as the loop.  The one shared update among
+ * them, a spring deleting itself (the free list and the break count), is
+ * serialized.  Sums over other objects stay sequential loops inside one
+ * call, so results do not depend on the thread count.
  *
  * Parity pins (what checks this file against something other than itself)
  * are in tests/test_oracle_*.py.  Block and slot placement is not modelled:
@@ -28,6 +34,7 @@
  * fields (cell index, node id, spring id).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -312,8 +319,10 @@ int orc_nbody_steps(long long n, double *x, double *y, double *vx, double *vy,
     }
     for (int s = 0; s < steps; s++) {
         size_t k = os_snapshot(&st, snap);
+#pragma omp parallel for schedule(dynamic, 64)
         for (size_t i = 0; i < k; i++) nb_force(&st, snap, k, snap[i], G, eps * eps);
         k = os_snapshot(&st, snap);
+#pragma omp parallel for schedule(static)
         for (size_t i = 0; i < k; i++) nb_update(os_at(&st, snap[i]), dt);
     }
     for (long long i = 0; i < n; i++) {   /* ids equal the construction index */
@@ -467,16 +476,28 @@ static void sp_spring_force(sp_world *w, size_t self)
     if (w->strain) w->strain[self] = strain;
     brk = sp_decide(w->first ? w->tie : NULL, (long long)self, strain, w->thresh, brk);
     if (brk < 0) {
+#pragma omp atomic write
         w->err = 8;
         return;
     }
     if (brk) {
-        if (a->adj[s->sa] != (long long)self || b->adj[s->sb] != (long long)self) w->err = 4;
-        a->adj[s->sa] = -1;
+        if (a->adj[s->sa] != (long long)self || b->adj[s->sb] != (long long)self) {
+#pragma omp atomic write
+            w->err = 4;
+        }
+        a->adj[s->sa] = -1;     /* the two slots are this spring's own */
         b->adj[s->sb] = -1;
         s->fx = s->fy = s->sf = 0;
-        w->nbroken++;
-        if (os_destroy(&w->spring, self)) w->err = 5;   /* last statement: delete this */
+        int bad;
+#pragma omp critical(sp_delete)
+        {
+            w->nbroken++;
+            bad = os_destroy(&w->spring, self);   /* last statement: delete this */
+        }
+        if (bad) {
+#pragma omp atomic write
+            w->err = 5;
+        }
         return;
     }
     double dx = b->x - a->x, dy = b->y - a->y;
@@ -576,8 +597,10 @@ long long orc_spring_steps(long long N, double *x, double *y, double *vx, double
     for (int st = 0; st < steps && !w.err; st++) {
         w.first = st == 0;
         size_t kk = os_snapshot(&w.spring, w.snap);
+#pragma omp parallel for schedule(static)
         for (size_t i = 0; i < kk; i++) sp_spring_force(&w, w.snap[i]);
         kk = os_snapshot(&w.node, w.snap);
+#pragma omp parallel for schedule(static)
         for (size_t i = 0; i < kk; i++) sp_node_update(&w, os_at(&w.node, w.snap[i]));
     }
     for (long long i = 0; i < N; i++) {
@@ -612,6 +635,9 @@ int orc_spring_breaks(double xa, double ya, double xb, double yb, double L0, dou
     return r;
 }
 
+/* threads the OpenMP do-alls use (reported with CPU timings) */
+int orc_threads(void) { return omp_get_max_threads(); }
+
 /* half-width of the tie band (for the tests that count ties) */
 double orc_spring_tie_band(void) { return SP_TIE_STRAIN; }
 
@@ -638,6 +664,7 @@ typedef struct {
 
 typedef struct {
     double cx, cy, gk;
+    double agk;     /* sum over the reverse steps of dt |u . g| (see below) */
 } adj_spring;
 
 static void adj_node_mu(sp_world *w, adj_node *an, const sp_node *n)
@@ -664,6 +691,7 @@ static void adj_spring_jg(sp_world *w, size_t self, const double *px, const doub
     as[self].cx = w->dt * kgx;
     as[self].cy = w->dt * kgy;
     as[self].gk += w->dt * (l - s->L0) * ug;
+    as[self].agk += w->dt * fabs(ug);
 }
 
 static void adj_node_sum(sp_world *w, size_t self, adj_node *an, const adj_spring *as)
@@ -680,8 +708,11 @@ static void adj_node_sum(sp_world *w, size_t self, adj_node *an, const adj_sprin
 /*
  * Forward T steps from (x, y, vx, vy) with breaking off, then the reverse
  * sweep.  Outputs (NULL to skip): gk (S), gvx, gvy, gx, gy (N) = dL/dk,
- * dL/dv0, dL/dx0; xT, yT (N) final positions; *loss.  `every` = checkpoint
- * interval (1..T).  Returns 0, or a negative error code.
+ * dL/dv0, dL/dx0; xT, yT (N) final positions; *loss; agk (S) = the sum over
+ * the reverse steps of dt |u . g|, the magnitude by which each step's
+ * stretch l - L0 enters dL/dk (an error e in every stretch moves dL/dk by at
+ * most e agk).  `every` = checkpoint interval (1..T).  Returns 0, or a
+ * negative error code.
  */
 int orc_spring_adjoint(long long N, const double *x, const double *y, const double *vx,
                        const double *vy, const double *m, const int32_t *adj, const uint8_t *adjb,
@@ -689,7 +720,7 @@ int orc_spring_adjoint(long long N, const double *x, const double *y, const doub
                        const double *L0, const int32_t *slot_a, const int32_t *slot_b,
                        const double *xhat, const double *yhat, double dt, int T, int every,
                        double *gk, double *gvx, double *gvy, double *gx, double *gy,
-                       double *xT, double *yT, double *loss)
+                       double *xT, double *yT, double *loss, double *agk)
 {
     if (N < 0 || S < 0 || T < 0 || every < 1) return -1;
     sp_world w;
@@ -727,8 +758,10 @@ int orc_spring_adjoint(long long N, const double *x, const double *y, const doub
             }
         }
         size_t kk = os_snapshot(&w.spring, w.snap);
+#pragma omp parallel for schedule(static)
         for (size_t i = 0; i < kk; i++) sp_spring_force(&w, w.snap[i]);
         kk = os_snapshot(&w.node, w.snap);
+#pragma omp parallel for schedule(static)
         for (size_t i = 0; i < kk; i++) sp_node_update(&w, os_at(&w.node, w.snap[i]));
     }
     if (w.nbroken) w.err = 7;
@@ -756,21 +789,29 @@ int orc_spring_adjoint(long long N, const double *x, const double *y, const doub
                 px[i] = p->x; py[i] = p->y;
             }
             size_t kk = os_snapshot(&w.spring, w.snap);
+#pragma omp parallel for schedule(static)
             for (size_t i = 0; i < kk; i++) sp_spring_force(&w, w.snap[i]);
             kk = os_snapshot(&w.node, w.snap);
+#pragma omp parallel for schedule(static)
             for (size_t i = 0; i < kk; i++) sp_node_update(&w, os_at(&w.node, w.snap[i]));
         }
         for (int n = n1 - 1; n >= n0; n--) {
             const double *px = tx + (size_t)(n - n0) * N, *py = ty + (size_t)(n - n0) * N;
             size_t kk = os_snapshot(&w.node, w.snap);
+#pragma omp parallel for schedule(static)
             for (size_t i = 0; i < kk; i++) adj_node_mu(&w, &an[w.snap[i]], os_at(&w.node, w.snap[i]));
             kk = os_snapshot(&w.spring, w.snap);
+#pragma omp parallel for schedule(static)
             for (size_t i = 0; i < kk; i++) adj_spring_jg(&w, w.snap[i], px, py, an, as);
             kk = os_snapshot(&w.node, w.snap);
+#pragma omp parallel for schedule(static)
             for (size_t i = 0; i < kk; i++) adj_node_sum(&w, w.snap[i], an, as);
         }
     }
-    for (long long i = 0; i < S; i++) if (gk) gk[i] = as[i].gk;
+    for (long long i = 0; i < S; i++) {
+        if (gk) gk[i] = as[i].gk;
+        if (agk) agk[i] = as[i].agk;
+    }
     for (long long i = 0; i < N; i++) {
         if (gvx) gvx[i] = an[i].lvx;
         if (gvy) gvy[i] = an[i].lvy;

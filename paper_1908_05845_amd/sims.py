@@ -119,7 +119,10 @@ def spring_pi_classes(K: int) -> dict:
 class SpringPiSim:
     """Spring-mass mesh of any node degree with partially inlined adjacency
     (thesis Ch.4 sec.4.3.1): the first K slots of a node in its block, the
-    other slots in one device array, each node's at an offset `more`."""
+    other slots in one device array, each node's at an offset `more`.
+    Springs with alive == 0 (if an 'alive' array is given) are not created;
+    a node's slot count is its highest slot in `adj` that names a spring,
+    plus one."""
 
     def __init__(self, mesh: dict, dt: float, K: int, strain_limit: float = 0.3, cfg=None, extra_blocks: int = 16):
         import torch
@@ -127,12 +130,15 @@ class SpringPiSim:
         adj = np.asarray(mesh["adj"], np.int32)
         N = int(np.asarray(mesh["x"]).size)
         adj = adj.reshape(N, -1)
+        S_all = int(np.asarray(mesh["a"]).size)
+        alive = np.ones(S_all, bool) if mesh.get("alive") is None else np.asarray(mesh["alive"]).astype(bool)
+        sid = np.flatnonzero(alive).astype(np.int64)
         used = adj >= 0
         cap = np.where(used.any(axis=1), adj.shape[1] - np.argmax(used[:, ::-1], axis=1), 0).astype(np.int32)
         extra = np.maximum(cap - K, 0).astype(np.int64)
         more = (np.cumsum(extra) - extra).astype(np.int32)
-        S = int(np.asarray(mesh["a"]).size)
-        self.N, self.S, self.K, self.D = N, S, K, adj.shape[1]
+        S = sid.size
+        self.N, self.S, self.K, self.D = N, S_all, K, adj.shape[1]
         self.cap, self.more = cap, more
         self.heap = smmo.Heap(spring_pi_classes(K), blocks=_blocks(N) + _blocks(S) + extra_blocks, cfg=cfg)
         dev = self.heap.buf.device
@@ -145,11 +151,12 @@ class SpringPiSim:
                                     more=i32(more), cap=i32(cap), id=i32(np.arange(N))).clone()
         u8 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint8)).to(dev)
         if S:
-            a_idx = torch.from_numpy(np.asarray(mesh["a"], np.int64)).to(dev)
-            b_idx = torch.from_numpy(np.asarray(mesh["b"], np.int64)).to(dev)
-            self.heap.new("Spring", S, a=self.node_h[a_idx], b=self.node_h[b_idx], k=f32(mesh["k"]),
-                          L0=f32(mesh["L0"]), slot_a=u8(mesh["slot_a"]), slot_b=u8(mesh["slot_b"]),
-                          id=i32(np.arange(S)))
+            a_idx = torch.from_numpy(np.asarray(mesh["a"], np.int64)[sid]).to(dev)
+            b_idx = torch.from_numpy(np.asarray(mesh["b"], np.int64)[sid]).to(dev)
+            self.heap.new("Spring", S, a=self.node_h[a_idx], b=self.node_h[b_idx],
+                          k=f32(np.asarray(mesh["k"])[sid]), L0=f32(np.asarray(mesh["L0"])[sid]),
+                          slot_a=u8(np.asarray(mesh["slot_a"])[sid]), slot_b=u8(np.asarray(mesh["slot_b"])[sid]),
+                          id=i32(sid))
         self.args = smmo.smmo_spring_pi_args(self.heap.cls["Node"], self.heap.cls["Spring"], dt, strain_limit,
                                              self.overflow.data_ptr(), int(extra.sum()))
         self.m_force = smmo.smmo_method_id("spring_pi.force")
@@ -515,7 +522,10 @@ class StructureSim:
     AnchorPullNode, Node and Spring.  One iteration: AnchorPullNode::pull,
     `substeps` x (Spring::force, Node::update), then the removal of the nodes
     no longer connected to an anchor node (a BFS whose levels are launched
-    `bfs_batch` at a time between reads of their frontier flags)."""
+    `bfs_batch` at a time between reads of their frontier flags).
+    A state with deleted objects loads too: nodes with nalive == 0 and
+    springs with salive == 0 (where those arrays are given) are not created;
+    nspr and dist are taken from the state."""
 
     def __init__(self, mesh: dict, dt: float, cfg=None, extra_blocks: int = 16, bfs_batch: int = 8):
         import torch
@@ -527,8 +537,12 @@ class StructureSim:
         N = ntype.size
         S = int(np.asarray(mesh["p1"]).size)
         self.N, self.S = N, S
-        per = [int((ntype == t).sum()) for t in range(3)]
-        blocks = sum(_blocks(n) for n in per) + _blocks(S) + extra_blocks
+        self.ntype_all = ntype.copy()
+        nalive = np.ones(N, bool) if mesh.get("nalive") is None else np.asarray(mesh["nalive"]).astype(bool)
+        salive = np.ones(S, bool) if mesh.get("salive") is None else np.asarray(mesh["salive"]).astype(bool)
+        dist0 = np.zeros(N, np.int32) if mesh.get("dist") is None else np.asarray(mesh["dist"], np.int32)
+        per = [int(((ntype == t) & nalive).sum()) for t in range(3)]
+        blocks = sum(_blocks(n) for n in per) + _blocks(int(salive.sum())) + extra_blocks
         self.heap = smmo.Heap(STRUCTURE_CLASSES, blocks=blocks, cfg=cfg)
         dev = self.heap.buf.device
         self.dev = dev
@@ -537,13 +551,13 @@ class StructureSim:
         node_h = torch.full((max(N, 1),), -1, dtype=torch.int32, device=dev)
         self.node_ids = []
         for t, cname in enumerate(STRUCTURE_NODE_CLASSES):
-            ids = np.flatnonzero(ntype == t)
+            ids = np.flatnonzero((ntype == t) & nalive)
             self.node_ids.append(ids)
             if ids.size == 0:
                 continue
             vals = dict(x=f32(np.asarray(mesh["x"])[ids]), y=f32(np.asarray(mesh["y"])[ids]),
                         springs=torch.full((ids.size * 3,), -1, dtype=torch.int32, device=dev),
-                        nspr=i32(np.asarray(mesh["nspr"])[ids]), dist=i32(np.zeros(ids.size)), id=i32(ids))
+                        nspr=i32(np.asarray(mesh["nspr"])[ids]), dist=i32(dist0[ids]), id=i32(ids))
             if cname != "AnchorNode":
                 vals["vx"] = f32(np.asarray(mesh["vx"])[ids])
                 vals["vy"] = f32(np.asarray(mesh["vy"])[ids])
@@ -556,15 +570,17 @@ class StructureSim:
         self.args = smmo.smmo_structure_args(c["NodeBase"], c["AnchorNode"], c["Spring"], 0, dt, 0, None)
         self.m = {n: smmo.smmo_method_id("structure." + n) for n in
                   ("pull", "force", "node_update", "bfs_init", "bfs_visit", "bfs_mark", "bfs_delete", "link")}
-        if S:
-            p1 = torch.from_numpy(np.asarray(mesh["p1"], np.int64)).to(dev)
-            p2 = torch.from_numpy(np.asarray(mesh["p2"], np.int64)).to(dev)
+        sid = np.flatnonzero(salive)
+        if sid.size:
+            p1 = torch.from_numpy(np.asarray(mesh["p1"], np.int64)[sid]).to(dev)
+            p2 = torch.from_numpy(np.asarray(mesh["p2"], np.int64)[sid]).to(dev)
             u8 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint8)).to(dev)
+            sel = lambda key: np.asarray(mesh[key])[sid]
             # "del" is a Python keyword: the field values go in as a dict
-            vals = {"p1": node_h[p1], "p2": node_h[p2], "k": f32(mesh["k"]), "L0": f32(mesh["L0"]),
-                    "maxf": f32(mesh["maxf"]), "s1": u8(mesh["s1"]), "s2": u8(mesh["s2"]),
-                    "del": u8(np.zeros(S)), "id": i32(np.arange(S))}
-            self.heap.new("Spring", S, **vals)
+            vals = {"p1": node_h[p1], "p2": node_h[p2], "k": f32(sel("k")), "L0": f32(sel("L0")),
+                    "maxf": f32(sel("maxf")), "s1": u8(sel("s1")), "s2": u8(sel("s2")),
+                    "del": u8(np.zeros(sid.size)), "id": i32(sid)}
+            self.heap.new("Spring", sid.size, **vals)
             self.do("Spring", "link")
         self.levels = 0
 
@@ -642,8 +658,7 @@ class StructureSim:
                 else:
                     out[key][ids] = _np(g[key])
         dead = out["nalive"] == 0
-        for t, ids in enumerate(self.node_ids):
-            out["ntype"][ids] = t
+        out["ntype"][:] = self.ntype_all
         used = raw != 0xFFFFFFFF
         hh = raw & 0x7FFFFFFF
         if sh_sorted.size:

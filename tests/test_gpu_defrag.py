@@ -127,18 +127,33 @@ def test_defragment_arguments(dev):
 
 def test_spring_mesh_defragmented_between_steps(dev):
     """Breaking spring mesh with the Spring class defragmented every 10
-    steps: parity with the oracle at every step is unchanged."""
-    from test_gpu_spring import check_step
+    steps: every defragmentation leaves the read-back state unchanged bit for
+    bit, the defragmented heap steps exactly as a fresh heap loaded with its
+    state (same-heap check, every step), and restarts from the oracle's
+    trajectory hold as without defragmentation."""
+    from oracle import spring_steps
+    from spring_parity import mesh_restart, same_heap
 
     print("spring 40x30 breaking with defragmentation", flush=True)
     mesh = spring_mesh(40, 30, seed=21, v_sigma=1.0)
     dt, limit = 1e-4, 0.3
-    sim = SpringSim(mesh, dt, limit)
+    make = lambda state: SpringSim(state, dt, limit)
+    sim = make(mesh)
+    cur = dict(mesh, alive=np.ones(mesh["S"], np.uint8))
     broken = 0
     moved = 0
     for step in range(150):
-        broken += check_step(sim, mesh, dt, limit)
+        if step % 10 == 0:
+            mesh_restart(cur, dt, limit, make)
+        same_heap(sim, mesh, make)
+        cur = spring_steps(cur, dt, limit, 1, alive=cur["alive"])
+        broken += cur["nbroken"]
         if step % 10 == 9:
+            before = sim.read()
             moved += sim.heap.defragment("Spring", n=1)[1]
+            after = sim.read()
+            for key in ("alive", "adj", "adj_is_b", "x", "y", "vx", "vy", "fx", "fy"):
+                assert np.array_equal(before[key], after[key]), key
             clean(sim.heap)
-    assert broken > 20 and moved > 0, (broken, moved)
+    gpu_broken = mesh["S"] - int(sim.read()["alive"].sum())
+    assert broken > 20 and gpu_broken > 20 and moved > 0, (broken, gpu_broken, moved)

@@ -1,93 +1,97 @@
-"""GPU parity of n-body (thesis Ch.7 "nbody") against the float64 oracle.
+"""GPU parity of n-body (thesis Ch.7 "nbody") against the float64 oracle, with
+no GPU value given to the oracle.
 
-Per checked step k the GPU's float32 state is read back; the oracle takes
-exactly those values and computes one step in float64.  Tolerance (1e-5 per
-step, relative to the conditioning scale of each quantity):
+The oracle's trajectory is kept in float32 storage: state s_{k+1} is its
+float64 step from s_k, rounded to float32.  At every checked step k, s_k is
+loaded into a fresh heap; the GPU's force pass and update from there are
+compared, for every body, with the oracle's step from s_k.  Tolerance (1e-5
+per step, relative to the conditioning scale of each quantity):
   force    |f_gpu - f_ref| <= 1e-5 * sum_j |term_ij|
   velocity |v_gpu - v_ref| <= 1e-5 * (|v_k| + dt * S_f / m)
   position |x_gpu - x_ref| <= 1e-5 * (|x_k| + dt * S_v)
+Beside it the GPU runs the whole trajectory on one heap (reported against
+the oracle's, not gated), and a property that holds at any size is checked
+on it: momentum stays near zero from rest.
 """
 
 import numpy as np
 import pytest
 
 from inputs import nbody_init
-from oracle import nbody_force_at, nbody_steps, nbody_update
+from oracle import nbody_steps
 from paper_1908_05845_amd.sims import NbodySim
+from spring_parity import round32
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 
 
-def check_force(s0, f, G, eps, idx):
-    fx, fy, sx, sy = nbody_force_at(s0["x"], s0["y"], s0["m"], G, eps, idx)
-    ex = np.abs(f["fx"][idx] - fx)
-    ey = np.abs(f["fy"][idx] - fy)
-    assert np.all(ex <= TOL * sx), float(np.max(ex / sx))
-    assert np.all(ey <= TOL * sy), float(np.max(ey / sy))
-    return sx, sy
-
-
-def check_full_step(sim, G, eps, dt, sample=None):
-    s0 = sim.read()
-    n = s0["x"].size
-    idx = np.arange(n) if sample is None else sample
+def restart_step(s, G, eps, dt):
+    """Fresh heap from the float32 state `s`, one GPU step against one oracle
+    step from `s`, every body.  Returns the oracle's step (float64)."""
+    sim = NbodySim(s, G, eps, dt)
     sim.force()
     f = sim.read()
-    sx, sy = check_force(s0, f, G, eps, idx)
     sim.update()
     s1 = sim.read()
-    # update from the GPU's own forces, every body
-    up = nbody_update(s0["x"], s0["y"], s0["vx"], s0["vy"], f["fx"], f["fy"], s0["m"], dt)
-    svx = np.abs(s0["vx"]) + dt * np.abs(f["fx"]) / s0["m"]
-    svy = np.abs(s0["vy"]) + dt * np.abs(f["fy"]) / s0["m"]
-    assert np.all(np.abs(s1["vx"] - up["vx"]) <= TOL * svx)
-    assert np.all(np.abs(s1["vy"] - up["vy"]) <= TOL * svy)
-    assert np.all(np.abs(s1["x"] - up["x"]) <= TOL * (np.abs(s0["x"]) + dt * svx))
-    assert np.all(np.abs(s1["y"] - up["y"]) <= TOL * (np.abs(s0["y"]) + dt * svy))
-    # one full oracle step from the same state, on the checked bodies
-    if sample is None:
-        ref = nbody_steps(s0["x"], s0["y"], s0["vx"], s0["vy"], s0["m"], G, eps, dt, 1)
-        Svx = np.abs(s0["vx"]) + dt * ref["sfx"] / s0["m"]
-        Svy = np.abs(s0["vy"]) + dt * ref["sfy"] / s0["m"]
-        assert np.all(np.abs(s1["vx"] - ref["vx"]) <= TOL * Svx)
-        assert np.all(np.abs(s1["vy"] - ref["vy"]) <= TOL * Svy)
-        assert np.all(np.abs(s1["x"] - ref["x"]) <= TOL * (np.abs(s0["x"]) + dt * Svx))
-        assert np.all(np.abs(s1["y"] - ref["y"]) <= TOL * (np.abs(s0["y"]) + dt * Svy))
+    ref = nbody_steps(s["x"], s["y"], s["vx"], s["vy"], s["m"], G, eps, dt, 1)
+    for c in ("x", "y"):
+        err = np.abs(f["f" + c].astype(np.float64) - ref["f" + c])
+        assert np.all(err <= TOL * ref["sf" + c]), ("f" + c, float(np.max(err / np.maximum(ref["sf" + c], 1e-300))))
+        sv = np.abs(s["v" + c]) + dt * ref["sf" + c] / s["m"]
+        assert np.all(np.abs(s1["v" + c] - ref["v" + c]) <= TOL * sv), "v" + c
+        sx = np.abs(s[c]) + dt * sv
+        assert np.all(np.abs(s1[c] - ref[c]) <= TOL * sx), c
+    sim.heap.sync()
+    return ref
+
+
+def run(n, G, eps, dt, steps, seed=None, checks=None):
+    """The float32-stored oracle trajectory with restarts at `checks`
+    (default every step) and the GPU's own run beside it.  Returns (GPU sim,
+    oracle state at the end)."""
+    s = nbody_init(n) if seed is None else nbody_init(n, seed=seed)
+    s = round32(s)
+    sim = NbodySim(s, G, eps, dt)
+    checks = set(range(steps)) if checks is None else set(checks)
+    for k in range(steps):
+        if k in checks:
+            ref = restart_step(s, G, eps, dt)
+        else:
+            ref = nbody_steps(s["x"], s["y"], s["vx"], s["vy"], s["m"], G, eps, dt, 1)
+        s = round32(dict(s, x=ref["x"], y=ref["y"], vx=ref["vx"], vy=ref["vy"]))
+        sim.step(1)
+        if n >= 10_000:
+            print("  step %d checked" % k, flush=True)
+    return sim, s
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 1000, 3000])
 def test_small_every_body_every_step(dev, n):
     print("nbody n=%d" % n, flush=True)
-    st = nbody_init(n, seed=100 + n)
     G, eps, dt = 1.0 / max(n, 1), 1e-3, 1e-4
-    sim = NbodySim(st, G, eps, dt)
-    for _ in range(4):
-        check_full_step(sim, G, eps, dt)
+    run(n, G, eps, dt, 4, seed=100 + n)
 
 
 def test_unsoftened_force_skips_self(dev):
-    st = nbody_init(500, seed=9)
-    sim = NbodySim(st, 1.0 / 500, 0.0, 1e-5)
-    check_full_step(sim, 1.0 / 500, 0.0, 1e-5)
+    sim, _ = run(500, 1.0 / 500, 0.0, 1e-5, 1, seed=9)
     assert np.all(np.isfinite(sim.read()["fx"]))
 
 
-def test_config_65536_bodies_sampled(dev):
+def test_config_65536_bodies_every_step(dev):
+    """All 50 steps of the configuration, every body.  The oracle's 50
+    force passes (4.3e9 pairs each) run on the host's threads."""
     print("nbody 65536", flush=True)
     n = 65536
     G, eps, dt = 1.0 / n, 1e-3, 1e-4
-    sim = NbodySim(nbody_init(n), G, eps, dt)
-    rng = np.random.default_rng(5)
-    for step in range(50):
-        if step in (0, 1, 25, 49):
-            sample = np.sort(rng.choice(n, 384, replace=False))
-            sample[0], sample[-1] = 0, n - 1
-            check_full_step(sim, G, eps, dt, sample=sample)
-        else:
-            sim.step(1)
+    sim, s = run(n, G, eps, dt, 50)
+    g = sim.read()
+    # the GPU's own run against the float32-stored oracle trajectory
+    # (reported): the system is not chaotic over 50 steps of 1e-4
+    d = np.hypot(g["x"] - s["x"], g["y"] - s["y"])
+    print("  own run after 50 steps: position difference rms %.3g, max %.3g" % (np.sqrt(np.mean(d * d)), d.max()),
+          flush=True)
     # momentum stays near zero (started at rest): a property at any size
-    s = sim.read()
-    p = np.array([np.sum(s["m"] * s["vx"]), np.sum(s["m"] * s["vy"])])
-    assert np.all(np.abs(p) <= 1e-4 * np.sum(s["m"] * np.hypot(s["vx"], s["vy"])))
+    p = np.array([np.sum(g["m"] * g["vx"]), np.sum(g["m"] * g["vy"])])
+    assert np.all(np.abs(p) <= 1e-4 * np.sum(g["m"] * np.hypot(g["vx"], g["vy"])))

@@ -1,62 +1,31 @@
 """GPU parity of the spring-mass mesh (thesis Ch.7 "structure", compute
-steps) against the float64 oracle.
+steps) against the float64 oracle, with no GPU value given to the oracle.
 
-Per checked step k the GPU's float32 state (positions, velocities, live
-springs, adjacency) is read back; the oracle takes those values and runs
-one step.  Topology is integer work and must match exactly: the set of live
-springs and every adjacency slot.  The oracle decides breaks in float64, the
-kernel in float32: a spring decided differently must lie within float32
-rounding of the limit (a tie, where both decisions are valid; counted and
-reported), and the oracle's step is then rerun with the GPU's decision for
-it.  Float results must match within 1e-5 of their conditioning scale
-(spring force: k (l + L0); node velocity and position: |v| + dt S_F / m and
-|x| + dt S_v, S_F = sum of the scales of the attached springs).
+The oracle runs its own float64 trajectory from the mesh's initial state.
+At each checked step its state, rounded to float32, is loaded into a fresh
+heap; one GPU step from there is compared with one oracle step from the
+same rounded state (restart).  Beside it the GPU runs the whole trajectory
+on one heap; at the checked steps that heap and a fresh heap loaded with its
+state must take the next step bit for bit alike (same heap, GPU against
+GPU).  Topology is integer work and must match exactly: the set of live
+springs and every adjacency slot, except a spring decided otherwise within
+float32 rounding of the limit (a tie; counted and reported), whose two slots
+and two end nodes are then left out.  Float results must match within 1e-5
+of their conditioning scale (spring force: k (l + L0); node velocity and
+position: |v| + dt S_F / m and |x| + dt S_v, S_F = sum of the scales of the
+attached springs).
 """
 
 import numpy as np
 import pytest
 
 from inputs import spring_mesh
+from oracle import spring_steps
 from paper_1908_05845_amd import smmo
-from spring_parity import mesh_step
 from paper_1908_05845_amd.sims import SpringSim
+from spring_parity import drift, mesh_restart, same_heap
 
 pytestmark = pytest.mark.gpu
-
-TOL = 1e-5
-TOPO = ("a", "b", "k", "L0", "slot_a", "slot_b")
-
-
-def state_dict(mesh, st):
-    d = {k: mesh[k] for k in TOPO}
-    for k in ("x", "y", "vx", "vy", "m", "adj", "adj_is_b", "alive", "fx", "fy"):
-        d[k] = st[k]
-    return d
-
-
-def check_step(sim, mesh, dt, limit, tension_only=False, ties=None):
-    """One GPU step against one oracle step from the GPU's state; `ties`
-    (a dict, optional) accumulates the near-tie and flipped counts."""
-    st = sim.read()
-    assert (st["adj"] != -2).all(), "adjacency names a dead spring"
-    sim.step(1)
-    s1 = sim.read()
-    ref, near, flipped = mesh_step(state_dict(mesh, st), dt, limit, st["alive"], st["fx"], st["fy"], s1["alive"],
-                                   tension_only=tension_only)
-    if ties is not None:
-        ties["near"] = ties.get("near", 0) + near
-        ties["flipped"] = ties.get("flipped", 0) + flipped
-    assert np.array_equal(s1["alive"], ref["alive"]), int(np.sum(s1["alive"] != ref["alive"]))
-    assert np.array_equal(s1["adj"], ref["adj"])
-    assert np.array_equal(s1["adj_is_b"][s1["adj"] >= 0], np.asarray(mesh["adj_is_b"])[s1["adj"] >= 0])
-    al = ref["alive"].astype(bool)
-    for key in ("fx", "fy"):
-        err = np.abs(s1[key][al] - ref[key][al])
-        assert np.all(err <= TOL * ref["sf"][al]), (key, float(np.max(err / ref["sf"][al])))
-    for key, sc in (("vx", "svx"), ("vy", "svy"), ("x", "sx"), ("y", "sy")):
-        err = np.abs(s1[key] - ref[key])
-        assert np.all(err <= TOL * ref[sc]), (key, float(np.max(err / ref[sc])))
-    return ref["nbroken"]
 
 
 def group_cfg(group):
@@ -67,19 +36,61 @@ def group_cfg(group):
     return cfg
 
 
+def run_checked(mesh, dt, limit, steps, group=0, tension_only=False, checks=None, shapes=None, ties=None):
+    """The oracle trajectory and the GPU's unrestarted run side by side for
+    `steps` steps; restart and same-heap checks at `checks` (default: every
+    step).  Returns (springs the oracle broke, springs the GPU run broke,
+    GPU sim, oracle state at the end)."""
+    cfg = group_cfg(group)
+
+    def make(state):
+        sim = SpringSim(state, dt, limit, cfg=cfg, tension_only=tension_only)
+        set_shapes(sim, shapes)
+        return sim
+
+    sim = make(mesh)
+    cur = dict(mesh, alive=np.ones(mesh["S"], np.uint8))
+    broken = 0
+    step = 0
+    checks = range(steps) if checks is None else checks
+    for k in sorted(checks):
+        if k >= steps:
+            break
+        if k > step:
+            cur = spring_steps(cur, dt, limit, k - step, alive=cur["alive"], tension_only=tension_only)
+            broken += cur["nbroken"]
+            sim.step(k - step)
+            step = k
+        mesh_restart(cur, dt, limit, make, tension_only=tension_only, ties=ties)
+        same_heap(sim, mesh, make)
+        cur = spring_steps(cur, dt, limit, 1, alive=cur["alive"], tension_only=tension_only)
+        broken += cur["nbroken"]
+        step += 1
+    if steps > step:
+        cur = spring_steps(cur, dt, limit, steps - step, alive=cur["alive"], tension_only=tension_only)
+        broken += cur["nbroken"]
+        sim.step(steps - step)
+    gpu_broken = mesh["S"] - int(sim.read()["alive"].sum())
+    inv = sim.heap.invariants()
+    assert inv.hierarchy_violations == 0 and inv.state_violations == 0 and inv.active_violations == 0
+    assert inv.type_violations == 0 and inv.empty_allocated == 0
+    st = sim.heap.stats()
+    assert st.live_objects[sim.heap.cls["Spring"]] == mesh["S"] - gpu_broken
+    return broken, gpu_broken, sim, cur
+
+
+def set_shapes(sim, shapes):
+    for name, shape in (shapes or {}).items():
+        cls = sim.heap.cls["Spring" if name == "spring.force" else "Node"]
+        smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), cls, *shape)
+
+
 @pytest.mark.parametrize("group", [1, 2, 4])
 def test_small_mesh_with_breaking_every_step(dev, group):
     print("spring 40x30 breaking, group %d" % group, flush=True)
     mesh = spring_mesh(40, 30, seed=21, v_sigma=1.0)
-    dt, limit = 1e-4, 0.3
-    sim = SpringSim(mesh, dt, limit, cfg=group_cfg(group))
-    broken = 0
-    for _ in range(150):
-        broken += check_step(sim, mesh, dt, limit)
-    assert broken > 20, broken       # the run exercises destruction
-    inv = sim.heap.invariants()
-    assert inv.hierarchy_violations == 0 and inv.state_violations == 0 and inv.active_violations == 0
-    assert inv.type_violations == 0 and inv.empty_allocated == 0
+    broken, gpu_broken, _, _ = run_checked(mesh, 1e-4, 0.3, 150, group)
+    assert broken > 20 and gpu_broken > 20, (broken, gpu_broken)   # the run exercises destruction
 
 
 @pytest.mark.parametrize("group", [1, 2, 4])
@@ -87,28 +98,25 @@ def test_small_mesh_with_breaking_every_step(dev, group):
 def test_ragged_meshes(dev, W, H, group):
     print("spring %dx%d group %d" % (W, H, group), flush=True)
     mesh = spring_mesh(W, H, seed=W * 7 + H, v_sigma=2.0)
-    sim = SpringSim(mesh, 1e-4, 0.05, cfg=group_cfg(group))
-    for _ in range(40):
-        check_step(sim, mesh, 1e-4, 0.05)
+    run_checked(mesh, 1e-4, 0.05, 40, group)
 
 
 @pytest.mark.parametrize("group", [1, 2, 4])
 def test_tension_only_springs(dev, group):
     """Springs that only pull (SMMO_SPRING_TENSION_ONLY): fast random
-    velocities compress many springs, which must then exert exactly zero force
-    (the slack decision is taken in float32 on both sides), while stretched
-    ones pull and break as usual."""
+    velocities compress many springs, which must then exert exactly zero
+    force, while stretched ones pull and break as usual."""
     print("spring 40x30 tension-only, group %d" % group, flush=True)
     mesh = spring_mesh(40, 30, seed=23, v_sigma=1.0)
     dt, limit = 1e-4, 0.3
-    sim = SpringSim(mesh, dt, limit, cfg=group_cfg(group), tension_only=True)
-    slack = broken = 0
-    for _ in range(120):
-        broken += check_step(sim, mesh, dt, limit, tension_only=True)
-        st = sim.read()
-        al = st["alive"].astype(bool)
-        slack += int(np.sum((st["fx"][al] == 0) & (st["fy"][al] == 0)))
-    assert slack > 1000 and broken > 10, (slack, broken)
+    broken, gpu_broken, sim, _ = run_checked(mesh, dt, limit, 120, group, tension_only=True)
+    st = sim.read()
+    al = st["alive"].astype(bool)
+    sim.step(1)
+    st = sim.read()
+    al &= st["alive"].astype(bool)
+    slack = int(np.sum((st["fx"][al] == 0) & (st["fy"][al] == 0)))
+    assert slack > 100 and broken > 10 and gpu_broken > 10, (slack, broken, gpu_broken)
 
 
 def test_spring_flags_validated(dev):
@@ -123,46 +131,76 @@ def test_spring_flags_validated(dev):
 def test_everything_breaks(dev, group):
     print("spring 12x12 everything breaks, group %d" % group, flush=True)
     mesh = spring_mesh(12, 12, seed=3, v_sigma=20.0)
-    sim = SpringSim(mesh, 1e-3, 0.01, cfg=group_cfg(group))
-    for _ in range(30):
-        check_step(sim, mesh, 1e-3, 0.01)
-    st = sim.heap.stats()
-    spr = sim.heap.cls["Spring"]
-    assert st.live_objects[spr] == int(sim.read()["alive"].sum())
+    broken, gpu_broken, _, cur = run_checked(mesh, 1e-3, 0.01, 30, group)
+    assert int(cur["alive"].sum()) < mesh["S"] // 4, int(cur["alive"].sum())
 
 
 # launch shapes (work-group threads, wavefronts, blocks per iteration) of the
-# timed 1000 x 1000 run: the library's defaults, and the shapes the autotuner
-# kept for the committed reference measurement
+# timed 1000 x 1000 run: the library's defaults, and shapes the autotuner may
+# keep for it (one and two blocks per wavefront iteration)
 SHAPES_1000 = {"default": None,
                "tuned": {"spring.force": (256, 8192, 1), "spring.node_update": (128, 32768, 1)},
-               "group2": {"spring.force": (64, 16384, 2), "spring.node_update": (128, 32768, 1)}}
+               "group2": {"spring.force": (64, 16384, 2), "spring.node_update": (256, 32768, 2)}}
+CHECKS_1000 = (0, 1, 2, 10, 100, 1000, 3000, 5000, 7000, 9999)
 
 
-@pytest.mark.parametrize("shapes", sorted(SHAPES_1000))
-def test_config_1000x1000_checked_steps(dev, shapes):
-    print("spring 1000x1000 shapes", shapes, flush=True)
+@pytest.fixture(scope="module")
+def trajectory_1000():
+    """The float64 oracle trajectory of the 1000 x 1000 mesh (dt 1e-5,
+    strain limit 0.3): its state at each checked step and after 10,000
+    steps.  Computed once for the module (several host threads)."""
     mesh = spring_mesh(1000, 1000)
     assert mesh["N"] == 1_000_000 and mesh["S"] == 2_996_001
     dt, limit = 1e-5, 0.3
-    sim = SpringSim(mesh, dt, limit)
-    if SHAPES_1000[shapes]:
-        for name, shape in SHAPES_1000[shapes].items():
-            cls = sim.heap.cls["Spring" if name == "spring.force" else "Node"]
-            smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), cls, *shape)
-    checks = (0, 1, 10, 1000, 3000, 5000, 7000, 9999)
+    keep = ("x", "y", "vx", "vy", "adj", "alive")
+    cur = dict(mesh, alive=np.ones(mesh["S"], np.uint8))
+    states = {}
     step = 0
     broken = 0
+    for k in CHECKS_1000 + (10_000,):
+        while step < k:
+            n = min(k - step, 1000)
+            cur = spring_steps(cur, dt, limit, n, alive=cur["alive"])
+            broken += cur["nbroken"]
+            step += n
+            print("  oracle step %d, springs broken %d" % (step, broken), flush=True)
+        states[k] = {key: np.array(cur[key], copy=True) for key in keep}
+    return mesh, dt, limit, states
+
+
+@pytest.mark.parametrize("shapes", sorted(SHAPES_1000))
+def test_config_1000x1000_checked_steps(dev, shapes, trajectory_1000):
+    """The 10,000-step configuration: restarts from the oracle trajectory at
+    the checked steps, the same-heap check of the GPU's own run there, and
+    the float32 run's end-to-end drift from the float64 trajectory
+    (reported, not gated: threshold decisions diverge)."""
+    print("spring 1000x1000 shapes", shapes, flush=True)
+    mesh, dt, limit, states = trajectory_1000
+
+    def make(state):
+        sim = SpringSim(state, dt, limit)
+        set_shapes(sim, SHAPES_1000[shapes])
+        return sim
+
+    sim = make(mesh)
     ties = {}
-    while step <= checks[-1]:
-        if step in checks:
-            print("  check step", step, flush=True)
-            broken += check_step(sim, mesh, dt, limit, ties=ties)
-        else:
-            sim.step(1)
+    step = 0
+    for k in CHECKS_1000:
+        sim.step(k - step)
+        step = k
+        print("  check step", k, flush=True)
+        state = dict(mesh, **states[k])
+        ref = mesh_restart(state, dt, limit, make, ties=ties)
+        assert ref["nbroken"] >= 0
+        same_heap(sim, mesh, make)
         step += 1
-    print("  springs broken at checked steps: %d; within the tie band: %d, decided otherwise than the "
-          "float64 rule: %d" % (broken, ties.get("near", 0), ties.get("flipped", 0)), flush=True)
-    st = sim.read()
-    n_alive = int(st["alive"].sum())
-    assert sim.heap.stats().live_objects[sim.heap.cls["Spring"]] == n_alive
+    sim.step(10_000 - step)
+    end = sim.read()
+    rec = drift("spring 1000x1000 (%s shapes)" % shapes, end, dict(mesh, **states[10_000]), 10_000)
+    print("  ties at checked steps: %d within the band, %d decided otherwise; drift after 10,000 steps: %s"
+          % (ties.get("near", 0), ties.get("flipped", 0), rec), flush=True)
+    assert sim.heap.stats().live_objects[sim.heap.cls["Spring"]] == int(end["alive"].sum())
+    # the run breaks springs, and the float32 run breaks about as many as the
+    # float64 trajectory (a sanity bound, not a parity claim)
+    assert rec["live_springs_f64"] < mesh["S"] - 100_000
+    assert abs(rec["live_springs_gpu"] - rec["live_springs_f64"]) <= 0.01 * mesh["S"]

@@ -1,109 +1,176 @@
 """GPU parity of "structure" (thesis Ch.7: node subclasses under an abstract
 NodeBase, tension-only springs that break above a force limit, BFS removal of
-the nodes no longer connected to an anchor node) against the float64 oracle.
+the nodes no longer connected to an anchor node) against the float64 oracle,
+with no GPU value given to the oracle.
 
-Every phase is checked from the GPU's own state: the oracle takes the state
-read back before the phase and runs that phase once.  Integer results must
-match exactly: which nodes and springs are alive, every spring slot of every
-node, the spring counts, the BFS distances and the number of BFS levels.  The
-oracle decides breaks in float64 and the kernel in float32: a spring decided
-differently must be a tie (its float64 force within float32 rounding of the
-limit; counted and reported), and the oracle's step is then rerun with the
-GPU's decision for it.  Floats must match within 1e-5 of their conditioning scale
-(spring force: k (l + L0); node velocity and position: |v| + dt S_F / m and
-|x| + dt S_v).
+The oracle runs its own trajectory (pull, compute steps, BFS removal) from
+the mesh.  Every phase is checked by a restart: the oracle's state before
+the phase, rounded to float32, is loaded into a fresh heap, the GPU runs the
+phase, and the result is compared with the oracle's phase from the same
+rounded state.  Beside it the GPU runs the whole trajectory on one heap, and
+every phase of that run must give bit for bit what a fresh heap loaded with
+its state gives (same-heap check).  Integer results must match exactly:
+which nodes and springs are alive, every spring slot of every node, the
+spring counts, the BFS distances and the number of BFS levels.  The oracle
+decides breaks in float64 and the kernel in float32: a spring decided
+otherwise must be a tie (its float64 force within float32 rounding of the
+limit; counted and reported), and it and its two end nodes are then left
+out of the comparison.  Floats must match within 1e-5 of their conditioning
+scale (spring force: k (l + L0); node velocity and position: |v| + dt S_F / m
+and |x| + dt S_v).
 """
 
 import numpy as np
 import pytest
 
 from inputs import structure_mesh
-from oracle import STRUCTURE_MAXDIST, structure_bfs, structure_pull
+from oracle import STRUCTURE_MAXDIST, structure_bfs, structure_pull, structure_step
 from paper_1908_05845_amd import smmo
 from paper_1908_05845_amd.sims import StructureSim
-from spring_parity import structure_compute_step
+from spring_parity import round32, structure_compare
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
 TOPO = ("p1", "p2", "k", "L0", "maxf", "s1", "s2", "m")
+STATE = ("ntype", "nalive", "x", "y", "vx", "vy", "slot", "isp2", "nspr", "dist", "salive", "fx", "fy", "sdel")
+DT = 1e-4
 
 
 def state(mesh, st):
+    """A GPU read-back as a structure state (constants from the mesh)."""
     d = {k: mesh[k] for k in TOPO}
-    for k in ("ntype", "nalive", "x", "y", "vx", "vy", "slot", "isp2", "nspr", "dist", "salive", "fx", "fy",
-              "sdel"):
+    for k in STATE:
         d[k] = st[k]
     return d
 
 
-def check_topology(s1, ref):
-    assert np.array_equal(s1["nalive"], ref["nalive"]), np.flatnonzero(s1["nalive"] != ref["nalive"])[:10]
-    assert np.array_equal(s1["salive"], ref["salive"]), np.flatnonzero(s1["salive"] != ref["salive"])[:10]
-    al = ref["nalive"].astype(bool)
+def check_topology(s1, ref, node_ok=None, sdiff=None):
+    N = ref["nalive"].size
+    node_ok = np.ones(N, bool) if node_ok is None else node_ok
+    sok = np.ones(ref["salive"].size, bool) if sdiff is None else ~sdiff
+    assert np.array_equal(s1["nalive"][node_ok], ref["nalive"][node_ok]), \
+        np.flatnonzero((s1["nalive"] != ref["nalive"]) & node_ok)[:10]
+    assert np.array_equal(s1["salive"][sok], ref["salive"][sok]), \
+        np.flatnonzero((s1["salive"] != ref["salive"]) & sok)[:10]
+    al = ref["nalive"].astype(bool) & node_ok
     assert np.array_equal(s1["nspr"][al], ref["nspr"][al])
     sl = s1["slot"].reshape(-1, 3)[al]
+    assert (s1["slot"] != -2).all(), "a slot names a dead spring"
     assert np.array_equal(sl, ref["slot"].reshape(-1, 3)[al])
     assert np.array_equal(s1["isp2"].reshape(-1, 3)[al][sl >= 0], ref["isp2"].reshape(-1, 3)[al][sl >= 0])
 
 
-def check_step(sim, mesh):
-    st = sim.read()
-    assert (st["slot"] != -2).all(), "a slot names a dead spring"
-    sim.compute_step()
-    s1 = sim.read()
-    ref, _, _ = structure_compute_step(state(mesh, st), sim.dt, s1["salive"])
-    check_topology(s1, ref)
-    sal = ref["salive"].astype(bool)
-    for key in ("fx", "fy"):
-        err = np.abs(s1[key][sal] - ref[key][sal])
-        assert np.all(err <= TOL * ref["sf"][sal]), (key, float(np.max(err / np.maximum(ref["sf"][sal], 1e-30))))
-    mov = ref["nalive"].astype(bool) & (ref["ntype"] == 2)
-    for key, sc in (("vx", "svx"), ("vy", "svy"), ("x", "sx"), ("y", "sy")):
-        err = np.abs(s1[key][mov] - ref[key][mov])
-        assert np.all(err <= TOL * ref[sc][mov]), (key, float(np.max(err / ref[sc][mov])))
-    fixed = ref["nalive"].astype(bool) & (ref["ntype"] != 2)
-    assert np.array_equal(s1["x"][fixed], st["x"][fixed]) and np.array_equal(s1["y"][fixed], st["y"][fixed])
-    return ref["nbroken"]
+def make_sim(batch=8, shapes=None):
+    def make(st):
+        sim = StructureSim(st, DT, bfs_batch=batch)
+        for name, shape in (shapes or {}).items():
+            smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), sim.heap.cls["NodeBase"], *shape)
+        return sim
+    return make
 
 
-def check_pull(sim, mesh, dt):
-    st = sim.read()
-    ref = structure_pull(state(mesh, st), dt)
+def restart_pull(cur, dt, make):
+    s32 = round32(cur)
+    sim = make(s32)
     sim.pull(dt)
     s1 = sim.read()
+    ref = structure_pull(s32, dt)
     al = ref["nalive"].astype(bool)
     for key, v in (("x", "vx"), ("y", "vy")):
-        sc = np.abs(st[key][al]) + dt * np.abs(st[v][al])
+        sc = np.abs(s32[key][al]) + dt * np.abs(s32[v][al])
         assert np.all(np.abs(s1[key][al] - ref[key][al]) <= TOL * np.maximum(sc, 1e-30))
 
 
-def check_bfs(sim, mesh):
-    st = sim.read()
-    ref = structure_bfs(state(mesh, st))
+def restart_step(cur, make):
+    s32 = round32(cur)
+    sim = make(s32)
+    sim.compute_step()
+    s1 = sim.read()
+    ref = structure_step(s32, DT)
+    _, _, node_ok, sdiff = structure_compare(s1, ref, s32)
+    check_topology(s1, ref, node_ok, sdiff)
+    sal = ref["salive"].astype(bool) & ~sdiff
+    for key in ("fx", "fy"):
+        err = np.abs(s1[key][sal] - ref[key][sal])
+        assert np.all(err <= TOL * ref["sf"][sal]), (key, float(np.max(err / np.maximum(ref["sf"][sal], 1e-30))))
+    mov = ref["nalive"].astype(bool) & (ref["ntype"] == 2) & node_ok
+    for key, sc in (("vx", "svx"), ("vy", "svy"), ("x", "sx"), ("y", "sy")):
+        err = np.abs(s1[key][mov] - ref[key][mov])
+        assert np.all(err <= TOL * ref[sc][mov]), (key, float(np.max(err / ref[sc][mov])))
+    fixed = ref["nalive"].astype(bool) & (ref["ntype"] != 2) & node_ok
+    assert np.array_equal(s1["x"][fixed], s32["x"][fixed]) and np.array_equal(s1["y"][fixed], s32["y"][fixed])
+
+
+def restart_bfs(cur, make):
+    s32 = round32(cur)
+    sim = make(s32)
     levels = sim.remove_disconnected()
     s1 = sim.read()
+    ref = structure_bfs(s32)
     check_topology(s1, ref)
     al = ref["nalive"].astype(bool)
     assert np.array_equal(s1["dist"][al], ref["dist"][al])
     assert levels == ref["levels"], (levels, ref["levels"])
-    return ref["ndeleted"], int(np.sum(st["nalive"]) - np.sum(ref["nalive"]))
+
+
+def same_heap(sim, mesh, make, phase):
+    """`phase` on the GPU's own heap and on a fresh heap loaded with its
+    state: bit for bit the same result.  Returns the state after it."""
+    fresh = make(state(mesh, sim.read()))
+    ra = phase(sim)
+    rb = phase(fresh)
+    assert ra == rb
+    a, b = sim.read(), fresh.read()
+    for key in ("nalive", "salive", "slot", "isp2", "nspr", "dist", "x", "y", "vx", "vy"):
+        assert np.array_equal(a[key], b[key]), key
+    sal = a["salive"].astype(bool)
+    for key in ("fx", "fy"):
+        assert np.array_equal(a[key][sal], b[key][sal]), key
+    return a
+
+
+def run_checked(mesh, iters, substeps, pull_mult, make):
+    """The oracle trajectory and the GPU's own run, iteration by iteration;
+    every phase restarted and same-heap checked.  Returns the oracle's
+    (springs broken, nodes removed by BFS) and the GPU run's sim."""
+    sim = make(mesh)
+    cur = structure_bfs_ready(mesh)
+    broken = removed = 0
+    for _ in range(iters):
+        dt_pull = pull_mult * DT
+        restart_pull(cur, dt_pull, make)
+        same_heap(sim, mesh, make, lambda s: s.pull(dt_pull))
+        cur = structure_pull(cur, dt_pull)
+        for _ in range(substeps):
+            restart_step(cur, make)
+            same_heap(sim, mesh, make, lambda s: s.compute_step())
+            cur = structure_step(cur, DT)
+            broken += cur["nbroken"]
+        restart_bfs(cur, make)
+        same_heap(sim, mesh, make, lambda s: s.remove_disconnected())
+        before = int(cur["nalive"].sum())
+        cur = structure_bfs(cur)
+        removed += before - int(cur["nalive"].sum())
+    return broken, removed, sim
+
+
+def structure_bfs_ready(mesh):
+    """The mesh as an oracle state (every object alive, no forces yet)."""
+    d = dict(mesh)
+    S = np.asarray(mesh["p1"]).size
+    d.setdefault("fx", np.zeros(S))
+    d.setdefault("fy", np.zeros(S))
+    d.setdefault("sdel", np.zeros(S, np.uint8))
+    return d
 
 
 @pytest.mark.parametrize("W,H,seed,batch", [(24, 10, 1, 8), (17, 9, 2, 1), (40, 16, 3, 3)])
 def test_iterations_phase_by_phase(dev, W, H, seed, batch):
     print("structure %dx%d seed %d bfs batch %d" % (W, H, seed, batch), flush=True)
     mesh = structure_mesh(W, H, seed=seed, pull_speed=2.0, break_strain=0.02, v_sigma=0.05)
-    sim = StructureSim(mesh, 1e-4, bfs_batch=batch)
-    broken = springs_removed = nodes_removed = 0
-    for it in range(8):
-        check_pull(sim, mesh, 10 * sim.dt)
-        for _ in range(10):
-            broken += check_step(sim, mesh)
-        ds, dn = check_bfs(sim, mesh)
-        springs_removed += ds
-        nodes_removed += dn
-    assert broken > 0 and nodes_removed > 0, (broken, springs_removed, nodes_removed)
+    broken, removed, sim = run_checked(mesh, 8, 10, 10, make_sim(batch))
+    assert broken > 0 and removed > 0, (broken, removed)
     inv = sim.heap.invariants()
     assert inv.hierarchy_violations == 0 and inv.state_violations == 0 and inv.active_violations == 0
     assert inv.type_violations == 0 and inv.empty_allocated == 0
@@ -112,6 +179,7 @@ def test_iterations_phase_by_phase(dev, W, H, seed, batch):
     s = sim.read()
     assert st.live_objects[c["Spring"]] == int(s["salive"].sum())
     assert sum(st.live_objects[c[n]] for n in ("AnchorNode", "AnchorPullNode", "Node")) == int(s["nalive"].sum())
+    assert int(s["nalive"].sum()) < mesh["ntype"].size        # the GPU's own run removed nodes too
 
 
 @pytest.mark.parametrize("W,H", [(1, 3), (2, 5), (3, 1), (5, 2)])
@@ -119,12 +187,7 @@ def test_small_meshes(dev, W, H):
     """Meshes without free nodes, without pull nodes or with one row."""
     print("structure %dx%d" % (W, H), flush=True)
     mesh = structure_mesh(W, H, seed=W * 10 + H, pull_speed=5.0, break_strain=0.01)
-    sim = StructureSim(mesh, 1e-4)
-    for it in range(3):
-        check_pull(sim, mesh, 5 * sim.dt)
-        for _ in range(5):
-            check_step(sim, mesh)
-        check_bfs(sim, mesh)
+    run_checked(mesh, 3, 5, 5, make_sim())
 
 
 def test_no_anchor_removes_everything(dev):
@@ -133,10 +196,12 @@ def test_no_anchor_removes_everything(dev):
     it); the level count is 1."""
     mesh = structure_mesh(6, 4, seed=5)
     mesh["ntype"] = np.where(mesh["ntype"] == 0, 2, mesh["ntype"]).astype(np.int32)
-    sim = StructureSim(mesh, 1e-4)
-    ref = check_bfs(sim, mesh)
+    make = make_sim()
+    restart_bfs(structure_bfs_ready(mesh), make)
+    sim = make(mesh)
+    sim.remove_disconnected()
     s = sim.read()
-    assert s["nalive"].sum() == 0 and s["salive"].sum() == 0 and sim.levels == 1, ref
+    assert s["nalive"].sum() == 0 and s["salive"].sum() == 0 and sim.levels == 1
 
 
 def test_abstract_class_and_family_dispatch(dev):
@@ -160,21 +225,20 @@ def test_abstract_class_and_family_dispatch(dev):
 def test_bfs_walks_with_small_grids(dev, wg, waves):
     """The family walk with fewer wavefronts than blocks: each wavefront steps
     through several blocks and across the three node classes' lists, and the
-    distances, levels and deletions still equal the oracle's."""
-    from paper_1908_05845_amd import smmo
-
+    distances, levels and deletions still equal the oracle's (restarts from
+    the oracle trajectory after each iteration's compute steps)."""
     print("structure bfs grid wg %d waves %d" % (wg, waves), flush=True)
     mesh = structure_mesh(40, 16, seed=3, pull_speed=2.0, break_strain=0.02, v_sigma=0.05)
-    sim = StructureSim(mesh, 1e-4, bfs_batch=4)
-    nb = sim.heap.cls["NodeBase"]
-    for name in ("structure.bfs_init", "structure.bfs_visit", "structure.bfs_mark"):
-        smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), nb, wg, waves, 0)
+    shapes = {n: (wg, waves, 0) for n in ("structure.bfs_init", "structure.bfs_visit", "structure.bfs_mark")}
+    make = make_sim(4, shapes)
+    cur = structure_bfs_ready(mesh)
     removed = 0
     for _ in range(8):
-        sim.pull(10 * sim.dt)
+        cur = structure_pull(cur, 10 * DT)
         for _ in range(10):
-            sim.compute_step()
-        removed += check_bfs(sim, mesh)[1]
+            cur = structure_step(cur, DT)
+        restart_bfs(cur, make)
+        before = int(cur["nalive"].sum())
+        cur = structure_bfs(cur)
+        removed += before - int(cur["nalive"].sum())
     assert removed > 0
-    st = sim.heap.stats()
-    assert st.device_error == 0

@@ -157,3 +157,62 @@ def test_single_step_function_composes_to_full_adjoint():
         assert np.all(np.abs(r["gk"]) <= r["sgk"] * (1 + 1e-12))
     assert np.allclose(gk, full["gk"], rtol=1e-12, atol=0)
     assert np.array_equal(lvx, full["gvx"]) and np.array_equal(lx, full["gx"])
+
+
+def test_stretch_multiplier_by_hand_and_as_a_bound():
+    # single spring, one step (as above): lambda_x1 = (1/4, -1/4), lambda_v1 = 0,
+    # mu = dt lambda_x1 = (1/8, -1/8), g = w_a - w_b = 1/4 along u = (1, 0):
+    # agk = dt |u . g| = 1/8, and gk = dt (l - L0) u . g = 1/2 * 1/2 * 1/4
+    r = spring_adjoint(line2(), dt=0.5, steps=1, every=1)
+    assert r["agk"][0] == 0.125 and r["gk"][0] == 0.0625
+    # on a mesh: |dL/dk| <= max over the steps of |l - L0| times agk
+    mesh = _as64(spring_mesh(7, 6, seed=9, v_sigma=0.5))
+    dt, T = 1e-3, 60
+    r = spring_adjoint(mesh, dt, T, every=20)
+    st, stretch = mesh, np.zeros(mesh["S"])
+    for _ in range(T):
+        l = np.hypot(st["x"][mesh["b"]] - st["x"][mesh["a"]], st["y"][mesh["b"]] - st["y"][mesh["a"]])
+        stretch = np.maximum(stretch, np.abs(l - mesh["L0"]))
+        st = spring_steps(st, dt, 1e30, 1)
+    assert np.all(np.abs(r["gk"]) <= stretch * r["agk"] * (1 + 1e-12))
+    assert np.all(r["agk"] > 0)
+
+
+@pytest.mark.slow
+def test_directional_derivatives_at_the_100k_node_configuration():
+    """The adjoint configuration itself (316 x 317 mesh, 100,172 nodes, dt
+    1e-5, 200 steps, checkpoints every 20, L = 1/2 |x_T - x_0|^2): the
+    directional derivatives of the oracle's gradients along random
+    directions in v0 and in k equal central differences of the float64
+    forward, to 1e-6.  The loss is smooth in both (breaking off).  Along v0 a
+    relative step of 1e-4 is used.  L depends on k only weakly over 200 steps
+    of 1e-5 (it changes by about 1e-9 of itself per unit relative change of
+    k), so there a small step would leave the difference to the float64
+    rounding of L (the cancellation in x_T - x_0); a relative step of 1e-2
+    keeps that noise far below the tolerance, and the truncation error of a
+    central difference, second order in the step, stays below it because L
+    is close to quadratic in k over that range."""
+    mesh = _as64(spring_mesh(316, 317))
+    assert mesh["N"] == 100_172
+    dt, T = 1e-5, 200
+    xh, yh = mesh["x"].copy(), mesh["y"].copy()
+    r = spring_adjoint(mesh, dt, T, every=20)
+    rng = np.random.default_rng(316)
+    # initial velocities: direction d (both components), step h |v0|
+    dvx, dvy = rng.standard_normal(mesh["N"]), rng.standard_normal(mesh["N"])
+    scale = np.sqrt(np.mean(mesh["vx"] ** 2 + mesh["vy"] ** 2))
+    h = 1e-4 * scale
+    mp, mm = dict(mesh), dict(mesh)
+    mp["vx"], mp["vy"] = mesh["vx"] + h * dvx, mesh["vy"] + h * dvy
+    mm["vx"], mm["vy"] = mesh["vx"] - h * dvx, mesh["vy"] - h * dvy
+    fd = (_loss(mp, dt, T, xh, yh) - _loss(mm, dt, T, xh, yh)) / (2 * h)
+    ad = np.dot(r["gvx"], dvx) + np.dot(r["gvy"], dvy)
+    assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+    # stiffnesses: relative direction k * d
+    dk = mesh["k"] * rng.standard_normal(mesh["S"])
+    h = 1e-2
+    mp, mm = dict(mesh), dict(mesh)
+    mp["k"], mm["k"] = mesh["k"] + h * dk, mesh["k"] - h * dk
+    fd = (_loss(mp, dt, T, xh, yh) - _loss(mm, dt, T, xh, yh)) / (2 * h)
+    ad = np.dot(r["gk"], dk)
+    assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
