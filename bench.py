@@ -104,15 +104,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel, launches_bytes):
+def traffic_for(kernel, state):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if there is none for this kernel or the sources changed since."""
+    None if there is none for this kernel, the sources changed since, or the
+    counters were taken at another mesh state (steps before the timing pass
+    and live springs there) than `state`."""
     try:
         with open(COUNTERS_FILE) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
-    if c.get("source_hash") != kernel_source_hash():
+    if c.get("source_hash") != kernel_source_hash() or c.get("state") != state:
         return None
     k = c.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
@@ -128,7 +130,8 @@ def bench_spring(args, torch):
 
     W = H = 1000
     dt, limit = 1e-5, 0.3
-    steps = 10_000 if args.steps is None else args.steps
+    total = 10_000                      # the workload's steps
+    steps = total if args.steps is None else args.steps
     warmup = 20 if args.warmup is None else args.warmup
     mesh = spring_mesh(W, H)
     sim = SpringSim(mesh, dt, limit)
@@ -152,9 +155,6 @@ def bench_spring(args, torch):
         count["spring.force"] += n
         count["spring.node_update"] += n
 
-    for _ in range(warmup):
-        step()
-    counted(warmup)
     heap.sync()
     frozen0 = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit,
                                     sim.args.flags)
@@ -213,7 +213,7 @@ def bench_spring(args, torch):
     torch.cuda.synchronize()
     eager_wall = time.perf_counter() - t0
     eager_ms = ee[0].elapsed_time(ee[1]) / max(eager_n, 1)
-    warmup += eager_n
+    done = eager_n                      # real steps taken so far
     # a HIP graph of G steps: the method kernels read the block lists and
     # their lengths on the device, so a captured step is the same work as a
     # launched one, without the host launch cost.  The timed region uses the
@@ -230,7 +230,7 @@ def bench_spring(args, torch):
                 step(cap)
         step()          # one launched step: the heap's last stream is ours again
         counted(1)
-        warmup += 1
+        done += 1
         torch.cuda.synchronize()
         eg = events(torch, 2)
         eg[0].record()
@@ -239,10 +239,33 @@ def bench_spring(args, torch):
         eg[1].record()
         torch.cuda.synchronize()
         counted(4 * G)
-        warmup += 4 * G
+        done += 4 * G
         graph_ms = eg[0].elapsed_time(eg[1]) / (4 * G)
         if graph_ms >= eager_ms:
             graph = None
+
+    def advance(n):
+        """n real steps, as graph replays where whole graphs fit."""
+        if graph is not None:
+            for _ in range(n // G):
+                graph.replay()
+            for _ in range(n % G):
+                step()
+        else:
+            for _ in range(n):
+                step()
+        counted(n)
+
+    # The timed steps are the last `steps` of the workload's 10,000 (or, for
+    # a longer request, start right after the probes and the warm-up), so a
+    # short timed window sees the mesh as late in the run, springs breaking.
+    # Untimed before them: the probes above, the steps that bring the mesh to
+    # that point, and the requested warm-up steps right before the window.
+    probes = done
+    first_timed = max(warmup + probes, total - steps)
+    advance(first_timed - warmup - probes)
+    advance(warmup)
+    done = first_timed
     heap.sync()
     st0 = heap.stats()
     live0 = (st0.live_objects[cs], st0.live_objects[cn])
@@ -330,13 +353,14 @@ def bench_spring(args, torch):
     st2 = st1
     S = float(s_mid)
     N = live0[1]
-    # algorithmic bytes (design minimum, each byte once):
+    # algorithmic bytes per launch (each byte once, at the live degree):
     #   spring.force per live spring: a, b, k, L0 (16) + x, y of both nodes
     #     (16) + fx, fy written (8) = 40 B
-    #   spring.node_update per node: adjacency (32) + x, y, vx, vy, m (20) +
-    #     x, y, vx, vy written (16) = 68 B, plus fx, fy (8) per attached spring
+    #   spring.node_update per node: a slot count (4) + one adjacency entry (4)
+    #     and one gathered force (8) per live spring end + x, y, vx, vy, m read
+    #     (20) + x, y, vx, vy written (16) = 40 + 12 deg B, deg = 2 S / N
     bytes_force = 40.0 * S
-    bytes_node = 68.0 * N + 16.0 * S
+    bytes_node = 40.0 * N + 24.0 * S
     kernels = {
         "spring.force": {"avg_us": t_force * 1e6, "bytes": bytes_force,
                          "gbs": bytes_force / t_force / 1e9},
@@ -345,7 +369,8 @@ def bench_spring(args, torch):
     }
     dom = "spring.force" if t_force >= t_node else "spring.node_update"
     kd = kernels[dom]
-    traffic = traffic_for(dom, kd["bytes"])
+    kernel_state = {"after_steps": done + half, "live_springs": int(s_mid)}
+    traffic = traffic_for(dom, kernel_state)
     step_bytes = bytes_force + bytes_node
     res = {
         "value": updates / (ms * 1e-3),
@@ -354,19 +379,23 @@ def bench_spring(args, torch):
         "dtype": "f32",
         "config": {"workload": "spring-mass structure, 1000x1000 jittered grid: 1,000,000 Node and "
                                "2,996,001 Spring objects, dt 1e-5, strain limit 0.3",
-                   "nodes": int(N), "springs_at_start": int(live0[0]), "springs_at_end": int(live1[0]),
-                   "steps_total_incl_warmup": warmup + steps, "heap_blocks": heap.blocks,
-                   "block_bytes": heap.block_bytes},
+                   "nodes": int(N), "first_timed_step": first_timed,
+                   "untimed_before_warmup": {"probe_steps": probes,
+                                             "state_steps": first_timed - warmup - probes},
+                   "springs_at_start": int(live0[0]), "springs_at_end": int(live1[0]),
+                   "springs_deleted_in_timed_steps": int(live0[0] - live1[0]),
+                   "heap_blocks": heap.blocks, "block_bytes": heap.block_bytes},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": kd["bytes"], "avg_launch_us": kd["avg_us"]},
+                     "algorithmic_bytes_per_launch": kd["bytes"], "avg_launch_us": kd["avg_us"],
+                     "state": kernel_state},
         "step_hbm": {"algorithmic_bytes": step_bytes, "gbs": step_bytes / (ms * 1e-3 / steps) / 1e9,
                      "frac": step_bytes / (ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS},
         "kernels": kernels,
         "autotune": tuned,
         "trace_window": {"note": "per-kernel dispatch index range of the timing pass (0-based, "
                                  "graph replays included); after_steps = real steps before it",
-                         "after_steps": warmup + half, **window},
+                         "after_steps": done + half, **window},
         "launch": {"mode": "hip graph of %d steps" % G if graph is not None else "launched steps",
                    "timed_host_wall_s": wall, "eager_ms_per_step": eager_ms,
                    "graph_ms_per_step": graph_ms,
@@ -383,14 +412,14 @@ def bench_spring(args, torch):
                            "max_updates_per_s": rates[-1]}
 
     def cpu_leg():
-        from oracle import spring_steps
+        from oracle import spring_steps, threads
 
-        k = args.cpu_steps or 200     # about 10-15 s of float64 oracle work on one core
+        k = args.cpu_steps or 1000     # about 10-20 s of float64 oracle work on 16 host threads
         t = time.perf_counter()
         r = spring_steps(mesh, dt, limit, k)
         el = time.perf_counter() - t
         objs = k * (mesh["N"] + 0.5 * (mesh["S"] + int(r["alive"].sum())))
-        return {"value": objs / el, "unit": "updates/s", "cores": 1, "kind": "oracle",
+        return {"value": objs / el, "unit": "updates/s", "cores": threads(), "kind": "oracle",
                 "sample": "first %d steps of the same 1000x1000 mesh from its initial state, one "
                           "call of the float64 oracle (load, steps, unload), %.1f s" % (k, el)}
 
@@ -493,7 +522,9 @@ def measure_batched(torch, plain_updates_per_s):
     s1 = st1.live_objects[heap.cls["Spring"]]
     n = st1.live_objects[heap.cls["Node"]]
     ups = T * (n + 0.5 * (s0 + s1)) / (ms * 1e-3)
-    step_bytes = 68.0 * n + 56.0 * 0.5 * (s0 + s1)
+    # algorithmic bytes of a step as for the single mesh: 40 B per live
+    # spring (force) and 40 + 12 deg B per node (update), deg = 2 S / N
+    step_bytes = 40.0 * n + 64.0 * 0.5 * (s0 + s1)
     res = {"workload": "256 spring meshes in one heap, node counts log-uniform in [1e3, 6.4e4]",
            "nodes": int(n), "springs_at_start": int(s0), "springs_at_end": int(s1), "steps": T,
            "launch": "one HIP graph of %d steps (%d kernel launches)" % (T, 2 * T),
@@ -780,8 +811,10 @@ def measure_structure(torch):
     (limits at 0.5-1.5 % strain): per iteration one pull, 40 compute steps
     (Spring::force, Node::update) and the BFS removal of disconnected nodes.
     One iteration to settle, then six timed (the mesh cracks and falls apart
-    within them) with events around each phase; the BFS's frontier flags are
-    read every 32 levels."""
+    within them) with events around each phase.  The BFS runs as one call
+    with its frontier in a queue (timed with events around its launches);
+    the thesis's form, level passes launched 32 at a time between reads of
+    their frontier flags, is timed on a second run of the same iterations."""
     from inputs import structure_mesh
     from paper_1908_05845_amd import smmo
     from paper_1908_05845_amd.sims import StructureSim
@@ -790,49 +823,66 @@ def measure_structure(torch):
     W = H = 1000
     sub = 40
     mesh = structure_mesh(W, H, pull_speed=0.5, stretch_rate=0.5, break_strain=0.01)
-    sim = StructureSim(mesh, 1e-4, bfs_batch=32)
-    heap = sim.heap
-    c = heap.cls
-    nodes = lambda st: sum(st.live_objects[c[n]] for n in ("AnchorNode", "AnchorPullNode", "Node"))
-    sim.iterate(sub)
-    heap.sync()
-    st0 = heap.stats()
-    n_it = 6
-    t_pull = t_comp = t_bfs = 0.0
-    levels = 0
-    upd = 0.0
 
-    for _ in range(n_it):
-        st = heap.stats()
-        upd += sub * (st.live_objects[c["Spring"]] + st.live_objects[c["Node"]])
-        e = events(torch, 3)
-        e[0].record()
-        sim.pull(sim.dt * sub)
-        e[1].record()
-        for _ in range(sub):
-            sim.compute_step()
-        e[2].record()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        levels += sim.remove_disconnected()
-        torch.cuda.synchronize()
-        t_bfs += (time.perf_counter() - t0) * 1e6
-        t_pull += e[0].elapsed_time(e[1]) * 1e3
-        t_comp += e[1].elapsed_time(e[2]) * 1e3
-    st1 = heap.stats()
+    def run(bfs):
+        sim = StructureSim(mesh, 1e-4, bfs_batch=32, bfs=bfs)
+        heap = sim.heap
+        c = heap.cls
+        nodes = lambda st: sum(st.live_objects[c[n]] for n in ("AnchorNode", "AnchorPullNode", "Node"))
+        sim.iterate(sub)
+        heap.sync()
+        st0 = heap.stats()
+        n_it = 6
+        t_pull = t_comp = t_bfs = 0.0
+        levels = 0
+        upd = 0.0
+        for _ in range(n_it):
+            st = heap.stats()
+            upd += sub * (st.live_objects[c["Spring"]] + st.live_objects[c["Node"]])
+            e = events(torch, 3)
+            e[0].record()
+            sim.pull(sim.dt * sub)
+            e[1].record()
+            for _ in range(sub):
+                sim.compute_step()
+            e[2].record()
+            torch.cuda.synchronize()
+            if bfs == "queue":
+                eb = events(torch, 2)
+                eb[0].record()
+                smmo.smmo_structure_remove_disconnected(heap.h, sim.args, sim.bfs_work, sim.bfs_levels)
+                eb[1].record()
+                torch.cuda.synchronize()
+                levels += int(sim.bfs_levels.cpu().item())
+                t_bfs += eb[0].elapsed_time(eb[1]) * 1e3
+            else:
+                t0 = time.perf_counter()
+                levels += sim.remove_disconnected()
+                torch.cuda.synchronize()
+                t_bfs += (time.perf_counter() - t0) * 1e6
+            t_pull += e[0].elapsed_time(e[1]) * 1e3
+            t_comp += e[1].elapsed_time(e[2]) * 1e3
+        st1 = heap.stats()
+        out = {"us_per_iteration": (t_pull + t_comp + t_bfs) / n_it,
+               "compute_us_per_substep": t_comp / (n_it * sub), "compute_updates_per_s": upd / (t_comp * 1e-6),
+               "bfs_us_per_iteration": t_bfs / n_it, "bfs_levels_per_iteration": levels / n_it,
+               "bfs_us_per_level": t_bfs / max(levels, 1),
+               "springs_start": int(st0.live_objects[c["Spring"]]),
+               "springs_end": int(st1.live_objects[c["Spring"]]),
+               "nodes_start": int(nodes(st0)), "nodes_end": int(nodes(st1)),
+               "device_deletions": int(st1.device_deletes - st0.device_deletes),
+               "device_error": st1.device_error}
+        heap.close()
+        return out, n_it
+
+    res, n_it = run("queue")
+    levels_form, _ = run("levels")
     res = {"workload": "structure (fracture), 1000x1000 brick-wall mesh: %d nodes (anchor, pull and free node "
                        "classes under an abstract NodeBase), %d springs" % (W * H, len(mesh["p1"])),
-           "iterations_timed": n_it, "substeps_per_iteration": sub,
-           "us_per_iteration": (t_pull + t_comp + t_bfs) / n_it,
-           "compute_us_per_substep": t_comp / (n_it * sub),
-           "compute_updates_per_s": upd / (t_comp * 1e-6),
-           "bfs_us_per_iteration": t_bfs / n_it, "bfs_levels_per_iteration": levels / n_it,
-           "bfs_us_per_level": t_bfs / max(levels, 1),
-           "springs_start": int(st0.live_objects[c["Spring"]]), "springs_end": int(st1.live_objects[c["Spring"]]),
-           "nodes_start": int(nodes(st0)), "nodes_end": int(nodes(st1)),
-           "device_deletions": int(st1.device_deletes - st0.device_deletes),
-           "device_error": st1.device_error}
-    heap.close()
+           "iterations_timed": n_it, "substeps_per_iteration": sub, "bfs": "frontier queue, one call", **res,
+           "bfs_level_passes": {k: levels_form[k] for k in ("us_per_iteration", "bfs_us_per_iteration",
+                                                            "bfs_levels_per_iteration", "bfs_us_per_level",
+                                                            "nodes_end", "springs_end")}}
     return res
 
 
@@ -1323,11 +1373,17 @@ def summarize_counters(fetch_dir, write_dir, fetch_json=None, write_json=None):
     of each run's per-kernel timing window (its timed launch shapes) are
     averaged."""
     windows = {}
+    states = []
     for counter, jf in (("FETCH_SIZE", fetch_json), ("WRITE_SIZE", write_json)):
         if jf:
             with open(jf) as f:
-                windows[counter] = json.loads([ln for ln in f if ln.startswith("{")][-1])["trace_window"]
-    out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES, "kernels": {}}
+                ln = json.loads([ln for ln in f if ln.startswith("{")][-1])
+            windows[counter] = ln["trace_window"]
+            states.append({"after_steps": int(ln["steps_before"]), "live_springs": int(ln["live_springs"])})
+    if len(states) == 2 and states[0] != states[1]:
+        raise SystemExit("the two counter runs saw different mesh states: %s" % states)
+    out = {"source_hash": kernel_source_hash(), "copy_bytes": COPY_BYTES, "kernels": {},
+           "state": states[0] if states else None}
     lines = []
     factor = {}
     per = {}
@@ -1560,6 +1616,10 @@ def main():
     if cpu is not None:
         cpu["cpu_model"] = _cpu_model()
         cpu["host_nproc"] = os.cpu_count()
+        if args.workload == "spring" and not args.no_extras:
+            for name, rec in cpu_baselines_of_extras().items():
+                if isinstance(extras.get(name), dict):
+                    extras[name]["cpu_baseline"] = rec
     line = {
         "metric": METRIC,
         "value": res["value"],
@@ -1584,6 +1644,46 @@ def main():
     print(json.dumps(line), flush=True)
     if args.calibrate_copy:
         calibrate_copy(torch)
+
+
+def cpu_baselines_of_extras():
+    """The float64 oracle timed on the other configurations, each on the
+    bounded sample its own cost allows (the host's threads for the do-alls
+    that use them): Game of Life 256 x 256 for all 100 generations, n-body
+    65,536 for 2 steps, the 256-mesh batch for 10 steps, the adjoint
+    configuration (316 x 317, 200 steps, checkpoints every 20) in full."""
+    from inputs import batched_meshes, concat_meshes, gol_init, nbody_init, spring_mesh
+    from oracle import GolWorld, nbody_steps, spring_adjoint, spring_steps, threads
+
+    out = {}
+    init = gol_init(256, 256)
+    t = time.perf_counter()
+    w = GolWorld(256, 256, init)
+    w.step(100)
+    el = time.perf_counter() - t
+    out["gol"] = {"value": 100 * 2 * 256 * 256 / el, "unit": "cell updates/s", "cores": 1, "kind": "oracle",
+                  "sample": "all 100 generations from the same start, %.1f s" % el}
+    s = nbody_init(65536)
+    n = 65536
+    t = time.perf_counter()
+    nbody_steps(s["x"], s["y"], s["vx"], s["vy"], s["m"], 1.0 / n, 1e-3, 1e-4, 2)
+    el = time.perf_counter() - t
+    out["nbody"] = {"value": 2.0 * n * n / el, "unit": "pairs/s", "cores": threads(), "kind": "oracle",
+                    "sample": "first 2 of the 50 steps, %.1f s" % el}
+    mesh = concat_meshes(batched_meshes(256))
+    t = time.perf_counter()
+    r = spring_steps(mesh, 1e-5, 0.3, 10)
+    el = time.perf_counter() - t
+    out["batched"] = {"value": 10 * (mesh["N"] + 0.5 * (mesh["S"] + int(r["alive"].sum()))) / el,
+                      "unit": "updates/s", "cores": threads(), "kind": "oracle",
+                      "sample": "first 10 of the 1,000 steps (load, steps, unload), %.1f s" % el}
+    mesh = spring_mesh(316, 317)
+    t = time.perf_counter()
+    spring_adjoint(mesh, 1e-5, 200, every=20)
+    el = time.perf_counter() - t
+    out["adjoint"] = {"value": el * 1e3, "unit": "ms per forward + checkpointed reverse sweep",
+                      "cores": threads(), "kind": "oracle", "sample": "the whole configuration, %.1f s" % el}
+    return out
 
 
 def _cpu_model():

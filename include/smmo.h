@@ -51,6 +51,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "smmo_methods.h"   /* argument structs of the compiled-in methods */
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -302,6 +304,28 @@ smmo_status smmo_coalescing_probe(float *data, uint64_t n, uint32_t C, uint32_t 
 smmo_status smmo_defragment(smmo_heap *h, uint32_t class_id, uint32_t n, uint32_t k1, uint32_t max_passes,
                             const smmo_handle_array *ext, uint32_t next, smmo_stream stream,
                             uint32_t *out_passes, uint64_t *out_moved);
+
+/* The removal of disconnected nodes (Ch.7 "structure": a breadth-first
+ * search from the anchor nodes over the springs, then every node it does not
+ * reach, and every spring of such a node, is deleted) as one call: the
+ * do-alls bfs_init, bfs_visit (until a pass finds the frontier empty),
+ * bfs_mark and bfs_delete with the same results (distances, deletions), the
+ * frontier kept as a queue instead of found by a pass over every node.
+ *   h, args   the heap and the structure classes (args->nodebase_class is the
+ *             family searched, args->anchor_class its start nodes; distance,
+ *             dt and flag are not used)
+ *   work      device buffer of work_words uint32 words owned by the caller,
+ *             at least 64 + 64 * (the blocks the node classes may hold) (the
+ *             heap's block count bounds that); its contents on entry do not
+ *             matter and on return are unspecified
+ *   levels    device word: receives the number of visit passes the
+ *             level-by-level form runs (the non-empty levels plus the one that
+ *             finds the frontier empty), 0 if the heap has failed
+ * Asynchronous on `stream`; SMMO_EINVAL (nothing enqueued) for NULL
+ * pointers, bad classes or a workspace too small; device errors as for
+ * smmo_parallel_do. */
+smmo_status smmo_structure_remove_disconnected(smmo_heap *h, const smmo_structure_args *args, uint32_t *work,
+                                               uint64_t work_words, uint32_t *levels, smmo_stream stream);
 
 /* ---- synchronization, statistics, diagnostics --------------------------- */
 

@@ -338,7 +338,8 @@ def spring_adjoint(mesh: dict, dt: float, steps: int, every: int = 20, xhat=None
     spring-mesh steps with breaking off (float64), checkpointing (x, v) every
     `every` steps.  xhat defaults to the initial positions.  Returns dict with
     loss, gk (dL/dk), gvx, gvy (dL/dv0), gx, gy (dL/dx0), xT, yT, and agk =
-    sum over the reverse steps of dt |u . g| per spring (an error e in every
+    sum over the reverse steps of dt |g| per spring, g = w_a - w_b (it bounds
+    the factor dt |u . g| of each step's stretch in dL/dk: an error e in every
     stretch l - L0 moves dL/dk by at most e agk)."""
     lib = _load()
     N = int(np.asarray(mesh["x"]).size)

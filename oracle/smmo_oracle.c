@@ -664,7 +664,7 @@ typedef struct {
 
 typedef struct {
     double cx, cy, gk;
-    double agk;     /* sum over the reverse steps of dt |u . g| (see below) */
+    double agk;     /* sum over the reverse steps of dt |g| (see below) */
 } adj_spring;
 
 static void adj_node_mu(sp_world *w, adj_node *an, const sp_node *n)
@@ -691,7 +691,7 @@ static void adj_spring_jg(sp_world *w, size_t self, const double *px, const doub
     as[self].cx = w->dt * kgx;
     as[self].cy = w->dt * kgy;
     as[self].gk += w->dt * (l - s->L0) * ug;
-    as[self].agk += w->dt * fabs(ug);
+    as[self].agk += w->dt * sqrt(gx * gx + gy * gy);
 }
 
 static void adj_node_sum(sp_world *w, size_t self, adj_node *an, const adj_spring *as)
@@ -709,10 +709,10 @@ static void adj_node_sum(sp_world *w, size_t self, adj_node *an, const adj_sprin
  * Forward T steps from (x, y, vx, vy) with breaking off, then the reverse
  * sweep.  Outputs (NULL to skip): gk (S), gvx, gvy, gx, gy (N) = dL/dk,
  * dL/dv0, dL/dx0; xT, yT (N) final positions; *loss; agk (S) = the sum over
- * the reverse steps of dt |u . g|, the magnitude by which each step's
- * stretch l - L0 enters dL/dk (an error e in every stretch moves dL/dk by at
- * most e agk).  `every` = checkpoint interval (1..T).  Returns 0, or a
- * negative error code.
+ * the reverse steps of dt |g|, which bounds the factor dt |u . g| with which
+ * each step's stretch l - L0 enters dL/dk (an error e in every stretch moves
+ * dL/dk by at most e agk).  `every` = checkpoint interval (1..T).  Returns 0,
+ * or a negative error code.
  */
 int orc_spring_adjoint(long long N, const double *x, const double *y, const double *vx,
                        const double *vy, const double *m, const int32_t *adj, const uint8_t *adjb,

@@ -316,6 +316,106 @@ __global__ __launch_bounds__(1024) void k_st_bfs_mark(HeapView h, StructK p)
     });
 }
 
+// ---- BFS removal with a frontier queue ------------------------------------
+// The same breadth-first search as the level-by-level visits above (every
+// node's distance from the nearest anchor node, the nodes it never reaches
+// deleted), with the frontier kept as a queue instead of found by a walk over
+// every node block in every level.  The workspace holds kBfsHeader header
+// words (word 0: the queue length) and then the queue: node handles in the
+// order they were reached, all nodes of distance 0, then all of distance 1,
+// and so on, each node at most once.
+constexpr uint32_t kBfsHeader = 64;
+
+__global__ __launch_bounds__(64) void k_st_bfs_clear(uint32_t *work)
+{
+    work[threadIdx.x] = 0u;
+}
+
+// NodeBase::initialize_frontier, appending the anchor nodes to the queue (one
+// atomic per wavefront for all of its anchors)
+__global__ __launch_bounds__(1024) void k_st_bfs_queue_init(HeapView h, StructK p, uint32_t *work, uint32_t cap)
+{
+    for_each_family_block(h, p.fam_mask, p.wpg, [&](uint32_t bid, uint64_t bm, uint32_t t) {
+        const uint32_t s = lane_id();
+        const bool live = ((bm >> s) & 1) != 0;
+        const bool anchor = live && ((p.anchor_mask >> t) & 1);
+        if (live) farr<int32_t>(h, bid, p.n_dist)[s] = anchor ? 0 : kFar;
+        const uint64_t am = __ballot(anchor);
+        if (!am) return;
+        const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)am) - 1);
+        uint32_t base = 0;
+        if (s == leader) base = atomicAdd(work, (uint32_t)__popcll(am));
+        base = (uint32_t)__shfl((int)base, (int)leader);
+        const uint32_t pos = base + (uint32_t)__popcll(am & ((1ull << s) - 1));
+        if (anchor) {
+            if (pos < cap) work[kBfsHeader + pos] = (bid << 6) | s;
+            else raise_error(h, ERR_INTERNAL);
+        }
+    });
+}
+
+// NodeBase::visit for every level, in one work-group: the threads take the
+// current level's range of the queue, a neighbour still at SMMO_STRUCTURE_FAR
+// is claimed with a compare-and-swap (so it is appended once, whichever
+// thread reaches it first; its distance is d + 1 either way) and appended
+// through a counter in LDS.  One barrier ends a level; the next level is what
+// it appended.  The loop ends when a level appends nothing, after at most
+// one level per node.  *levels = the number of levels the thesis's loop runs:
+// the non-empty ones plus the pass that finds the frontier empty.
+__global__ __launch_bounds__(1024) void k_st_bfs_levels(HeapView h, StructK p, uint32_t *work, uint32_t cap,
+                                                        uint32_t *levels)
+{
+    __shared__ uint32_t s_lo, s_hi, s_tail, s_stop;
+    uint32_t *queue = work + kBfsHeader;
+    if (threadIdx.x == 0) {
+        s_stop = heap_failed(h) ? 1u : 0u;
+        const uint32_t n = std::min(__hip_atomic_load(work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), cap);
+        s_lo = 0;
+        s_hi = n;
+        s_tail = n;
+    }
+    __syncthreads();
+    if (s_stop) {
+        if (threadIdx.x == 0) *levels = 0;
+        return;
+    }
+    uint32_t d = 0;
+    for (;;) {
+        const uint32_t lo = s_lo, hi = s_hi;
+        if (lo >= hi) break;
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const uint32_t node = queue[i];
+            uint32_t hs[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) hs[q] = fref<uint32_t>(h, node, p.n_spr + q * p.n_spr_stride);
+            uint32_t o[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                o[q] = kNull;
+                if (hs[q] == kNull || !st_valid(h, hs[q] & ~kP2)) continue;
+                o[q] = fref<uint32_t>(h, hs[q] & ~kP2, (hs[q] & kP2) ? p.s_p1 : p.s_p2);
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (o[q] == kNull || !st_valid(h, o[q])) continue;
+                int32_t *dp = &fref<int32_t>(h, o[q], p.n_dist);
+                if (atomicCAS(dp, kFar, (int32_t)d + 1) != kFar) continue;
+                const uint32_t pos = atomicAdd(&s_tail, 1u);
+                if (pos < cap) queue[pos] = o[q];
+                else raise_error(h, ERR_INTERNAL);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_lo = hi;
+            s_hi = std::min(s_tail, cap);
+        }
+        __syncthreads();
+        ++d;
+    }
+    if (threadIdx.x == 0) *levels = d + 1;
+}
+
 // Spring::delete_spring
 __global__ __launch_bounds__(1024) void k_st_bfs_delete(HeapView h, StructK p)
 {
@@ -478,7 +578,55 @@ smmo_status launch_structure(smmo_heap *h, uint32_t cls, const void *args, hipSt
     return launched("structure kernel");
 }
 
+// BFS removal with the queue in `work` (words >= kBfsHeader + one per node
+// slot of the family): queue set-up, all levels, then the mark and delete
+// do-alls of the level-by-level form.
+smmo_status remove_disconnected(smmo_heap *h, const smmo_structure_args &a, uint32_t *work, uint64_t words,
+                                uint32_t *levels, hipStream_t st)
+{
+    smmo_status s = heap_check_class(h, a.nodebase_class);
+    if (s) return s;
+    if ((s = heap_check_class(h, a.spring_class))) return s;
+    if (!work || !levels) return fail(SMMO_EINVAL, "structure BFS: workspace or level count is NULL");
+    smmo_structure_args key = a;
+    key.distance = 0;
+    key.dt = 0.f;
+    key.flag = nullptr;
+    StructK k;
+    s = cached_bind(h, (const void *)&k_st_bfs_levels, a.nodebase_class, key, k,
+                    [&] { return bind_structure(h, a.nodebase_class, key, W_BFS_INIT, k); });
+    if (s) return s;
+    uint64_t slots = 0;
+    for (uint32_t c = 0; c < h->schema->nclasses; ++c)
+        if ((k.fam_mask >> c) & 1) slots += 64 * h->ub_blocks[c];
+    if (slots > 0xFFFFFFFFull - kBfsHeader) return fail(SMMO_EINVAL, "structure BFS: too many node slots");
+    if (words < kBfsHeader + slots)
+        return fail(SMMO_EINVAL, "structure BFS: the workspace needs 64 header words and one word per node slot "
+                                 "of the node classes (64 per block they may hold)");
+    for (uint32_t c = 0; c < h->schema->nclasses; ++c)
+        if (((k.fam_mask >> c) & 1) && (s = ensure_enumerated(h, c, false, st))) return s;
+    const uint32_t cap = (uint32_t)slots;
+    hipLaunchKernelGGL(k_st_bfs_clear, dim3(1), dim3(kBfsHeader), 0, st, work);
+    if (k.fam_mask) {
+        LaunchShape ls = family_shape(h, a.nodebase_class, k.fam_mask);
+        k.wpg = ls.block.x / 64;
+        hipLaunchKernelGGL(k_st_bfs_queue_init, ls.grid, ls.block, 0, st, h->v, k, work, cap);
+    }
+    hipLaunchKernelGGL(k_st_bfs_levels, dim3(1), dim3(1024), 0, st, h->v, k, work, cap, levels);
+    if ((s = launched("structure BFS kernel"))) return s;
+    h->last = st;
+    if ((s = launch_structure<W_BFS_MARK>(h, a.nodebase_class, &a, st))) return s;
+    return launch_structure<W_BFS_DELETE>(h, a.spring_class, &a, st);
+}
+
 } // namespace
+
+smmo_status smmo_structure_remove_disconnected(smmo_heap *h, const smmo_structure_args *args, uint32_t *work,
+                                               uint64_t work_words, uint32_t *levels, smmo_stream stream)
+{
+    if (!args) return fail(SMMO_EINVAL, "structure BFS: args is NULL");
+    return remove_disconnected(h, *args, work, work_words, levels, static_cast<hipStream_t>(stream));
+}
 
 namespace smmo {
 smmo_status launch_structure_pull(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_structure<W_PULL>(h, c, a, s); }

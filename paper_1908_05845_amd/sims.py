@@ -521,18 +521,25 @@ class StructureSim:
     ``inputs.structure_mesh``: classes NodeBase (abstract), AnchorNode,
     AnchorPullNode, Node and Spring.  One iteration: AnchorPullNode::pull,
     `substeps` x (Spring::force, Node::update), then the removal of the nodes
-    no longer connected to an anchor node (a BFS whose levels are launched
-    `bfs_batch` at a time between reads of their frontier flags).
+    no longer connected to an anchor node: a BFS whose frontier is a queue,
+    all levels run on the device by one call (bfs="queue", the default), or
+    the thesis's form, the level passes launched `bfs_batch` at a time
+    between reads of their frontier flags (bfs="levels").
     A state with deleted objects loads too: nodes with nalive == 0 and
     springs with salive == 0 (where those arrays are given) are not created;
-    nspr and dist are taken from the state."""
+    nspr, dist and (where given) the spring forces fx, fy are taken from the
+    state."""
 
-    def __init__(self, mesh: dict, dt: float, cfg=None, extra_blocks: int = 16, bfs_batch: int = 8):
+    def __init__(self, mesh: dict, dt: float, cfg=None, extra_blocks: int = 16, bfs_batch: int = 8,
+                 bfs: str = "queue"):
         import torch
 
+        if bfs not in ("queue", "levels"):
+            raise ValueError("bfs must be 'queue' or 'levels'")
         self.torch = torch
         self.dt = dt
         self.bfs_batch = bfs_batch
+        self.bfs = bfs
         ntype = np.asarray(mesh["ntype"], np.int32)
         N = ntype.size
         S = int(np.asarray(mesh["p1"]).size)
@@ -567,6 +574,9 @@ class StructureSim:
         self.node_h = node_h
         c = self.heap.cls
         self.flags = torch.zeros(max(bfs_batch, 1), dtype=torch.int32, device=dev)
+        # the queue BFS's workspace: 64 header words and one per slot of the heap
+        self.bfs_work = torch.empty(64 + 64 * self.heap.blocks, dtype=torch.int32, device=dev)
+        self.bfs_levels = torch.zeros(1, dtype=torch.int32, device=dev)
         self.args = smmo.smmo_structure_args(c["NodeBase"], c["AnchorNode"], c["Spring"], 0, dt, 0, None)
         self.m = {n: smmo.smmo_method_id("structure." + n) for n in
                   ("pull", "force", "node_update", "bfs_init", "bfs_visit", "bfs_mark", "bfs_delete", "link")}
@@ -580,6 +590,9 @@ class StructureSim:
             vals = {"p1": node_h[p1], "p2": node_h[p2], "k": f32(sel("k")), "L0": f32(sel("L0")),
                     "maxf": f32(sel("maxf")), "s1": u8(sel("s1")), "s2": u8(sel("s2")),
                     "del": u8(np.zeros(sid.size)), "id": i32(sid)}
+            if mesh.get("fx") is not None:
+                vals["fx"] = f32(sel("fx"))
+                vals["fy"] = f32(sel("fy"))
             self.heap.new("Spring", sid.size, **vals)
             self.do("Spring", "link")
         self.levels = 0
@@ -600,15 +613,25 @@ class StructureSim:
         """BFS from the anchor nodes, then deletion of the unvisited nodes and
         their springs.  Returns the number of visit passes until the first
         empty frontier (as the thesis's loop runs them)."""
+        if self.bfs == "queue":
+            smmo.smmo_structure_remove_disconnected(self.heap.h, self.args, self.bfs_work, self.bfs_levels, stream)
+            self.heap.sync()
+            self.levels = int(self.bfs_levels.cpu().item())
+            return self.levels
         self.do("NodeBase", "bfs_init", stream)
         d = 0
         while True:
+            # the flags are cleared and read back between host synchronizations
+            # with the heap's stream, which the visit launches run on
+            self.heap.sync()
             self.flags.zero_()
+            self.torch.cuda.synchronize()
             for j in range(self.bfs_batch):
                 self.args.distance = d + j
                 self.args.flag = self.flags.data_ptr() + 4 * j
                 self.do("NodeBase", "bfs_visit", stream)
             self.args.flag = None
+            self.heap.sync()
             fl = self.flags.cpu().numpy()
             empty = np.flatnonzero(fl == 0)
             if empty.size:

@@ -61,9 +61,9 @@ def check_topology(s1, ref, node_ok=None, sdiff=None):
     assert np.array_equal(s1["isp2"].reshape(-1, 3)[al][sl >= 0], ref["isp2"].reshape(-1, 3)[al][sl >= 0])
 
 
-def make_sim(batch=8, shapes=None):
+def make_sim(batch=8, shapes=None, bfs="queue"):
     def make(st):
-        sim = StructureSim(st, DT, bfs_batch=batch)
+        sim = StructureSim(st, DT, bfs_batch=batch, bfs=bfs)
         for name, shape in (shapes or {}).items():
             smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), sim.heap.cls["NodeBase"], *shape)
         return sim
@@ -165,11 +165,13 @@ def structure_bfs_ready(mesh):
     return d
 
 
-@pytest.mark.parametrize("W,H,seed,batch", [(24, 10, 1, 8), (17, 9, 2, 1), (40, 16, 3, 3)])
-def test_iterations_phase_by_phase(dev, W, H, seed, batch):
-    print("structure %dx%d seed %d bfs batch %d" % (W, H, seed, batch), flush=True)
+@pytest.mark.parametrize("W,H,seed,batch,bfs", [(24, 10, 1, 8, "levels"), (17, 9, 2, 1, "levels"),
+                                                (40, 16, 3, 3, "levels"), (24, 10, 1, 0, "queue"),
+                                                (40, 16, 3, 0, "queue")])
+def test_iterations_phase_by_phase(dev, W, H, seed, batch, bfs):
+    print("structure %dx%d seed %d bfs %s batch %d" % (W, H, seed, bfs, batch), flush=True)
     mesh = structure_mesh(W, H, seed=seed, pull_speed=2.0, break_strain=0.02, v_sigma=0.05)
-    broken, removed, sim = run_checked(mesh, 8, 10, 10, make_sim(batch))
+    broken, removed, sim = run_checked(mesh, 8, 10, 10, make_sim(max(batch, 1), bfs=bfs))
     assert broken > 0 and removed > 0, (broken, removed)
     inv = sim.heap.invariants()
     assert inv.hierarchy_violations == 0 and inv.state_violations == 0 and inv.active_violations == 0
@@ -182,21 +184,23 @@ def test_iterations_phase_by_phase(dev, W, H, seed, batch):
     assert int(s["nalive"].sum()) < mesh["ntype"].size        # the GPU's own run removed nodes too
 
 
+@pytest.mark.parametrize("bfs", ["queue", "levels"])
 @pytest.mark.parametrize("W,H", [(1, 3), (2, 5), (3, 1), (5, 2)])
-def test_small_meshes(dev, W, H):
+def test_small_meshes(dev, W, H, bfs):
     """Meshes without free nodes, without pull nodes or with one row."""
-    print("structure %dx%d" % (W, H), flush=True)
+    print("structure %dx%d bfs %s" % (W, H, bfs), flush=True)
     mesh = structure_mesh(W, H, seed=W * 10 + H, pull_speed=5.0, break_strain=0.01)
-    run_checked(mesh, 3, 5, 5, make_sim())
+    run_checked(mesh, 3, 5, 5, make_sim(bfs=bfs))
 
 
-def test_no_anchor_removes_everything(dev):
+@pytest.mark.parametrize("bfs", ["queue", "levels"])
+def test_no_anchor_removes_everything(dev, bfs):
     """Without anchor nodes the BFS visits nothing: every node with springs
     and every spring is deleted (a node loses its last spring and goes with
     it); the level count is 1."""
     mesh = structure_mesh(6, 4, seed=5)
     mesh["ntype"] = np.where(mesh["ntype"] == 0, 2, mesh["ntype"]).astype(np.int32)
-    make = make_sim()
+    make = make_sim(bfs=bfs)
     restart_bfs(structure_bfs_ready(mesh), make)
     sim = make(mesh)
     sim.remove_disconnected()
@@ -230,7 +234,7 @@ def test_bfs_walks_with_small_grids(dev, wg, waves):
     print("structure bfs grid wg %d waves %d" % (wg, waves), flush=True)
     mesh = structure_mesh(40, 16, seed=3, pull_speed=2.0, break_strain=0.02, v_sigma=0.05)
     shapes = {n: (wg, waves, 0) for n in ("structure.bfs_init", "structure.bfs_visit", "structure.bfs_mark")}
-    make = make_sim(4, shapes)
+    make = make_sim(4, shapes, bfs="levels")
     cur = structure_bfs_ready(mesh)
     removed = 0
     for _ in range(8):
@@ -242,3 +246,39 @@ def test_bfs_walks_with_small_grids(dev, wg, waves):
         cur = structure_bfs(cur)
         removed += before - int(cur["nalive"].sum())
     assert removed > 0
+
+
+def test_queue_bfs_on_a_larger_broken_mesh(dev):
+    """The queue BFS at a size where levels hold hundreds of nodes and the
+    frontier outgrows the work-group: a 300 x 200 mesh that the oracle has
+    pulled apart for a few iterations, restarted on the GPU with both BFS
+    forms; distances, levels and deletions equal the oracle's."""
+    print("structure 300x200 queue BFS", flush=True)
+    mesh = structure_mesh(300, 200, seed=11, pull_speed=5.0, break_strain=0.05, v_sigma=0.05)
+    cur = structure_bfs_ready(mesh)
+    for it in range(4):
+        cur = structure_pull(cur, 20 * DT)
+        for _ in range(20):
+            cur = structure_step(cur, DT)
+        for bfs in ("queue", "levels"):
+            restart_bfs(cur, make_sim(8, bfs=bfs))
+        before = int(cur["nalive"].sum())
+        cur = structure_bfs(cur)
+        print("  iteration %d: %d levels, %d nodes removed" % (it, cur["levels"], before - int(cur["nalive"].sum())),
+              flush=True)
+
+
+def test_queue_bfs_workspace_checks(dev):
+    import torch
+
+    mesh = structure_mesh(6, 4, seed=5)
+    sim = StructureSim(mesh, DT)
+    small = torch.empty(64 + 10, dtype=torch.int32, device=dev)
+    with pytest.raises(smmo.SmmoError) as e:
+        smmo.smmo_structure_remove_disconnected(sim.heap.h, sim.args, small, sim.bfs_levels)
+    assert e.value.status == smmo.SMMO_EINVAL
+    bad = smmo.smmo_structure_args.from_buffer_copy(sim.args)
+    bad.anchor_class = sim.heap.cls["Spring"]
+    with pytest.raises(smmo.SmmoError):
+        smmo.smmo_structure_remove_disconnected(sim.heap.h, bad, sim.bfs_work, sim.bfs_levels)
+    assert sim.remove_disconnected() >= 1

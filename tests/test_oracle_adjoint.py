@@ -162,7 +162,7 @@ def test_single_step_function_composes_to_full_adjoint():
 def test_stretch_multiplier_by_hand_and_as_a_bound():
     # single spring, one step (as above): lambda_x1 = (1/4, -1/4), lambda_v1 = 0,
     # mu = dt lambda_x1 = (1/8, -1/8), g = w_a - w_b = 1/4 along u = (1, 0):
-    # agk = dt |u . g| = 1/8, and gk = dt (l - L0) u . g = 1/2 * 1/2 * 1/4
+    # agk = dt |g| = 1/8, and gk = dt (l - L0) u . g = 1/2 * 1/2 * 1/4
     r = spring_adjoint(line2(), dt=0.5, steps=1, every=1)
     assert r["agk"][0] == 0.125 and r["gk"][0] == 0.0625
     # on a mesh: |dL/dk| <= max over the steps of |l - L0| times agk
