@@ -315,9 +315,10 @@ smmo_status smmo_defragment(smmo_heap *h, uint32_t class_id, uint32_t n, uint32_
  *             family searched, args->anchor_class its start nodes; distance,
  *             dt and flag are not used)
  *   work      device buffer of work_words uint32 words owned by the caller,
- *             at least 64 + 64 * (the blocks the node classes may hold) (the
- *             heap's block count bounds that); its contents on entry do not
- *             matter and on return are unspecified
+ *             at least 64 + 64 B_n rounded up to a multiple of 4, plus 256 M,
+ *             where B_n = the blocks the node classes may hold and M = the
+ *             heap's blocks (B_n <= M, so 68 + 320 M always suffices); its
+ *             contents on entry do not matter and on return are unspecified
  *   levels    device word: receives the number of visit passes the
  *             level-by-level form runs (the non-empty levels plus the one that
  *             finds the frontier empty), 0 if the heap has failed

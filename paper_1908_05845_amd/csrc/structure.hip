@@ -320,11 +320,22 @@ __global__ __launch_bounds__(1024) void k_st_bfs_mark(HeapView h, StructK p)
 // The same breadth-first search as the level-by-level visits above (every
 // node's distance from the nearest anchor node, the nodes it never reaches
 // deleted), with the frontier kept as a queue instead of found by a walk over
-// every node block in every level.  The workspace holds kBfsHeader header
-// words (word 0: the queue length) and then the queue: node handles in the
-// order they were reached, all nodes of distance 0, then all of distance 1,
-// and so on, each node at most once.
+// every node block in every level.  Workspace layout (uint32 words):
+//   [0, kBfsHeader)          header; word 0 = the queue's length
+//   [kBfsHeader, +cap)       the queue: node handles in the order they were
+//                            reached, all of distance 0, then 1, ...; each
+//                            node at most once (cap = node slots)
+//   [nbr_off, +4 * 64 M)     per handle of the heap, the node's neighbours
+//                            (the other end of each spring slot, SMMO_NULL
+//                            for an empty slot) and a pad word, filled for the
+//                            live nodes by the set-up walk
+// The topology does not change during the search, so resolving each node's
+// springs to its neighbours once, in one wide walk, takes two dependent loads
+// out of every level's chain.
 constexpr uint32_t kBfsHeader = 64;
+
+__host__ __device__ inline uint64_t bfs_nbr_offset(uint64_t cap) { return (kBfsHeader + cap + 3) & ~3ull; }
+__host__ __device__ inline uint64_t bfs_words(uint64_t cap, uint64_t M) { return bfs_nbr_offset(cap) + 256 * M; }
 
 __global__ __launch_bounds__(64) void k_st_bfs_clear(uint32_t *work)
 {
@@ -332,14 +343,30 @@ __global__ __launch_bounds__(64) void k_st_bfs_clear(uint32_t *work)
 }
 
 // NodeBase::initialize_frontier, appending the anchor nodes to the queue (one
-// atomic per wavefront for all of its anchors)
+// atomic per wavefront for all of its anchors), and each live node's
+// neighbours
 __global__ __launch_bounds__(1024) void k_st_bfs_queue_init(HeapView h, StructK p, uint32_t *work, uint32_t cap)
 {
+    uint4 *nbr = reinterpret_cast<uint4 *>(work + bfs_nbr_offset(cap));
     for_each_family_block(h, p.fam_mask, p.wpg, [&](uint32_t bid, uint64_t bm, uint32_t t) {
         const uint32_t s = lane_id();
         const bool live = ((bm >> s) & 1) != 0;
         const bool anchor = live && ((p.anchor_mask >> t) & 1);
-        if (live) farr<int32_t>(h, bid, p.n_dist)[s] = anchor ? 0 : kFar;
+        uint32_t hs[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) hs[q] = farr<uint32_t>(h, bid, p.n_spr + q * p.n_spr_stride)[s];
+        if (live) {
+            farr<int32_t>(h, bid, p.n_dist)[s] = anchor ? 0 : kFar;
+            uint32_t o[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                o[q] = kNull;
+                if (hs[q] == kNull || !st_valid(h, hs[q] & ~kP2)) continue;
+                const uint32_t other = fref<uint32_t>(h, hs[q] & ~kP2, (hs[q] & kP2) ? p.s_p1 : p.s_p2);
+                if (st_valid(h, other)) o[q] = other;
+            }
+            nbr[(bid << 6) | s] = make_uint4(o[0], o[1], o[2], kNull);
+        }
         const uint64_t am = __ballot(anchor);
         if (!am) return;
         const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)am) - 1);
@@ -367,6 +394,7 @@ __global__ __launch_bounds__(1024) void k_st_bfs_levels(HeapView h, StructK p, u
 {
     __shared__ uint32_t s_lo, s_hi, s_tail, s_stop;
     uint32_t *queue = work + kBfsHeader;
+    const uint4 *nbr = reinterpret_cast<const uint4 *>(work + bfs_nbr_offset(cap));
     if (threadIdx.x == 0) {
         s_stop = heap_failed(h) ? 1u : 0u;
         const uint32_t n = std::min(__hip_atomic_load(work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), cap);
@@ -384,22 +412,16 @@ __global__ __launch_bounds__(1024) void k_st_bfs_levels(HeapView h, StructK p, u
         const uint32_t lo = s_lo, hi = s_hi;
         if (lo >= hi) break;
         for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const uint32_t node = queue[i];
-            uint32_t hs[3];
+            const uint4 nb = nbr[queue[i]];
+            const uint32_t o[3] = {nb.x, nb.y, nb.z};
+            // the three claims are independent: all issued before any result is used
+            int32_t was[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) hs[q] = fref<uint32_t>(h, node, p.n_spr + q * p.n_spr_stride);
-            uint32_t o[3];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                o[q] = kNull;
-                if (hs[q] == kNull || !st_valid(h, hs[q] & ~kP2)) continue;
-                o[q] = fref<uint32_t>(h, hs[q] & ~kP2, (hs[q] & kP2) ? p.s_p1 : p.s_p2);
-            }
+            for (int q = 0; q < 3; ++q)
+                was[q] = o[q] == kNull ? 0 : atomicCAS(&fref<int32_t>(h, o[q], p.n_dist), kFar, (int32_t)d + 1);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                if (o[q] == kNull || !st_valid(h, o[q])) continue;
-                int32_t *dp = &fref<int32_t>(h, o[q], p.n_dist);
-                if (atomicCAS(dp, kFar, (int32_t)d + 1) != kFar) continue;
+                if (o[q] == kNull || was[q] != kFar) continue;
                 const uint32_t pos = atomicAdd(&s_tail, 1u);
                 if (pos < cap) queue[pos] = o[q];
                 else raise_error(h, ERR_INTERNAL);
@@ -600,9 +622,10 @@ smmo_status remove_disconnected(smmo_heap *h, const smmo_structure_args &a, uint
     for (uint32_t c = 0; c < h->schema->nclasses; ++c)
         if ((k.fam_mask >> c) & 1) slots += 64 * h->ub_blocks[c];
     if (slots > 0xFFFFFFFFull - kBfsHeader) return fail(SMMO_EINVAL, "structure BFS: too many node slots");
-    if (words < kBfsHeader + slots)
-        return fail(SMMO_EINVAL, "structure BFS: the workspace needs 64 header words and one word per node slot "
-                                 "of the node classes (64 per block they may hold)");
+    if (words < bfs_words(slots, h->v.M))
+        return fail(SMMO_EINVAL, "structure BFS: the workspace needs 64 header words, one word per node slot of "
+                                 "the node classes (64 per block they may hold), rounded up to 4, and 256 words "
+                                 "per block of the heap");
     for (uint32_t c = 0; c < h->schema->nclasses; ++c)
         if (((k.fam_mask >> c) & 1) && (s = ensure_enumerated(h, c, false, st))) return s;
     const uint32_t cap = (uint32_t)slots;

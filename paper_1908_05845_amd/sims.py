@@ -574,8 +574,9 @@ class StructureSim:
         self.node_h = node_h
         c = self.heap.cls
         self.flags = torch.zeros(max(bfs_batch, 1), dtype=torch.int32, device=dev)
-        # the queue BFS's workspace: 64 header words and one per slot of the heap
-        self.bfs_work = torch.empty(64 + 64 * self.heap.blocks, dtype=torch.int32, device=dev)
+        # the queue BFS's workspace (header, queue, neighbour table), sized by
+        # the heap's block count
+        self.bfs_work = torch.empty(68 + 320 * self.heap.blocks, dtype=torch.int32, device=dev)
         self.bfs_levels = torch.zeros(1, dtype=torch.int32, device=dev)
         self.args = smmo.smmo_structure_args(c["NodeBase"], c["AnchorNode"], c["Spring"], 0, dt, 0, None)
         self.m = {n: smmo.smmo_method_id("structure." + n) for n in
