@@ -328,6 +328,19 @@ smmo_status smmo_defragment(smmo_heap *h, uint32_t class_id, uint32_t n, uint32_
 smmo_status smmo_structure_remove_disconnected(smmo_heap *h, const smmo_structure_args *args, uint32_t *work,
                                                uint64_t work_words, uint32_t *levels, smmo_stream stream);
 
+/* smmo_structure_remove_disconnected without a workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation): the same kernels and results, the
+ * workspace being a device array of the library (about 21 MB on each GPU it
+ * runs on, held until the process ends).  Allocates nothing.  The heap's
+ * device must be the current device.  SMMO_EINVAL for a heap of more than
+ * 16,384 blocks (pass a workspace to smmo_structure_remove_disconnected
+ * instead), NULL pointers or bad classes.  All calls on one GPU share the
+ * array: calls that overlap on one GPU (other streams, other threads, other
+ * heaps) race and must be ordered by the caller. */
+smmo_status smmo_structure_remove_disconnected_noalloc(smmo_heap *h, const smmo_structure_args *args,
+                                                       uint32_t *levels, smmo_stream stream);
+
 /* ---- synchronization, statistics, diagnostics --------------------------- */
 
 /* Waits for all work enqueued on the heap and returns the device error word

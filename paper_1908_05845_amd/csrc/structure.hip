@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/smmo_methods.h"
 #include "method_common.hpp"
@@ -649,6 +650,57 @@ smmo_status smmo_structure_remove_disconnected(smmo_heap *h, const smmo_structur
 {
     if (!args) return fail(SMMO_EINVAL, "structure BFS: args is NULL");
     return remove_disconnected(h, *args, work, work_words, levels, static_cast<hipStream_t>(stream));
+}
+
+// ---- the same BFS without a caller workspace ------------------------------
+// The workspace (queue and neighbour table) lives in `scratch`, a device array
+// of this library: each GPU the library runs on holds one copy, 21 MB, until
+// the process ends.  It serves heaps of up to kScratchBlocks blocks.  In host
+// code the array's name is not a device address; its address on a device is
+// taken once per device (hipGetSymbolAddress, with that device current) and
+// kept in scratch_ptr, which is what the kernels are given.  All calls on one
+// GPU share the array and it keeps the last call's contents: the queue's
+// header is cleared by a kernel at the start of every call (the rest is
+// written before it is read), and calls that overlap on one GPU race.
+constexpr uint32_t kScratchBlocks = 16384;
+constexpr uint64_t kScratchWords = (kBfsHeader + 64ull * kScratchBlocks + 3) / 4 * 4 + 256ull * kScratchBlocks;
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+namespace {
+constexpr int kScratchDevices = 64;
+uint32_t *scratch_ptr[kScratchDevices];
+std::mutex scratch_mu;
+
+smmo_status scratch_on(int device, uint32_t **out)
+{
+    if (device < 0 || device >= kScratchDevices) return fail(SMMO_EINVAL, "structure BFS: device id out of range");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        scratch_ptr[device] = static_cast<uint32_t *>(p);
+    }
+    *out = scratch_ptr[device];
+    return SMMO_OK;
+}
+} // namespace
+
+smmo_status smmo_structure_remove_disconnected_noalloc(smmo_heap *h, const smmo_structure_args *args,
+                                                       uint32_t *levels, smmo_stream stream)
+{
+    if (!h || !args) return fail(SMMO_EINVAL, "structure BFS: heap or args is NULL");
+    int cur = -1;
+    const hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != h->device) return fail(SMMO_EINVAL, "structure BFS: the heap's device must be the current device");
+    if (h->v.M > kScratchBlocks)
+        return fail(SMMO_EINVAL, "structure BFS without a workspace: the heap has more than 16,384 blocks (what "
+                                 "the library's own array serves); pass a workspace instead");
+    uint32_t *q = nullptr;
+    smmo_status s = scratch_on(cur, &q);
+    if (s) return s;
+    return remove_disconnected(h, *args, q, kScratchWords, levels, static_cast<hipStream_t>(stream));
 }
 
 namespace smmo {

@@ -154,7 +154,7 @@ EXPORTS = [
     "smmo_parallel_new", "smmo_parallel_do", "smmo_destroy", "smmo_gather_soa", "smmo_sync",
     "smmo_heap_stats", "smmo_check_invariants", "smmo_clear_error", "smmo_heap_info",
     "smmo_method_id", "smmo_last_error", "smmo_set_launch", "smmo_defragment", "smmo_coalescing_probe",
-    "smmo_source_hash", "smmo_structure_remove_disconnected",
+    "smmo_source_hash", "smmo_structure_remove_disconnected", "smmo_structure_remove_disconnected_noalloc",
 ]
 
 
@@ -204,6 +204,7 @@ def load_library(path: str = LIB_PATH):
             "smmo_defragment": (S, [P, U32, U32, U32, U32, P, U32, P, P, P]),
             "smmo_coalescing_probe": (S, [P, U64, U32, U32, P]),
             "smmo_structure_remove_disconnected": (S, [P, P, P, U64, P, P]),
+            "smmo_structure_remove_disconnected_noalloc": (S, [P, P, P, P]),
             "smmo_last_error": (S, [C.c_char_p, C.c_size_t]),
         }
         for name, (res, args) in sig.items():
@@ -398,6 +399,12 @@ def smmo_structure_remove_disconnected(heap, args, work, levels, stream=None) ->
     lib = load_library()
     _check(lib, lib.smmo_structure_remove_disconnected(heap, C.byref(args), _ptr(work), work.numel(), _ptr(levels),
                                                        _stream(stream)))
+
+
+def smmo_structure_remove_disconnected_noalloc(heap, args, levels, stream=None) -> None:
+    """The same without a workspace (the library's own device array; see smmo.h)."""
+    lib = load_library()
+    _check(lib, lib.smmo_structure_remove_disconnected_noalloc(heap, C.byref(args), _ptr(levels), _stream(stream)))
 
 
 def smmo_coalescing_probe(data, C: int, grid: int = 0, stream=None) -> None:
