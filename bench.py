@@ -7,9 +7,11 @@ springs (1000 x 1000 jittered grid, stiffness log-uniform in [1e2, 1e4],
 rest length = initial distance, float32, dt 1e-5, springs deleted past
 strain 0.3).  One step = one pass of the hot path over the whole mesh:
 parallel_do(Spring, spring.force) (Hooke force, breaking springs delete
-themselves) and parallel_do(Node, spring.node_update).  The default run is
-the workload's 10,000 steps after W warm-up steps, all inputs resident in
-HBM before the timed region.
+themselves) and parallel_do(Node, spring.node_update).  The timed K steps
+end at step 10,000 of the workload where the untimed probe steps and the W
+warm-up steps fit before them (else they start right after those: the
+default, K = 10,000); the steps in between bring the mesh to that point.
+All inputs are resident in HBM before the timed region.
 
 Prints one JSON line: object-method updates per second (live objects
 processed by the do-alls, summed over launches, per second), the dominant
@@ -754,13 +756,13 @@ def measure_gol_large(torch):
     return res
 
 
-def measure_spring_large(torch, tuned):
+def measure_spring_large(torch):
     """Spring mesh 2000 x 2000 (4M nodes, 12.0M springs; about 900 MB of
     blocks, beyond the 256 MB MALL): the plain step's supplemental size.  The
-    launch shapes are the ones tuned for the 1000 x 1000 mesh.  20 steps to
-    settle, then 50 timed with events around each do-all; bytes per object as
-    for the 1000 x 1000 mesh (40 B per live spring; 68 B per node + 16 B per
-    live spring)."""
+    launch shapes are tuned for this heap (its own size bucket) on whole
+    frozen steps, as for the 1000 x 1000 mesh.  20 steps to settle, then 50
+    timed with events around each do-all; bytes per object as for the 1000 x
+    1000 mesh (40 B per live spring; 40 + 12 deg B per node)."""
     from inputs import spring_mesh
     from paper_1908_05845_amd import smmo
     from paper_1908_05845_amd.sims import SpringSim
@@ -770,11 +772,9 @@ def measure_spring_large(torch, tuned):
     sim = SpringSim(mesh, 1e-5, 0.3)
     heap = sim.heap
     cs, cn = heap.cls["Spring"], heap.cls["Node"]
-    for name, mid, cls in (("spring.force", sim.m_force, cs), ("spring.node_update", sim.m_node, cn)):
-        t = (tuned or {}).get(name)
-        if t:
-            smmo.smmo_set_launch(heap.h, mid, cls, t["wg"], t["waves"], t.get("group", 0))
     sim.step(20)
+    heap.sync()
+    tuned = tune_spring_step(torch, sim)
     heap.sync()
     n = 50
     ev = events(torch, 2 * n + 1)
@@ -792,14 +792,16 @@ def measure_spring_large(torch, tuned):
     live = st.live_objects[cs]
     N = st.live_objects[cn]
     step_us = ev[0].elapsed_time(ev[2 * n]) * 1e3 / n
-    fb, nb = 40.0 * live, 68.0 * N + 16.0 * live
+    fb, nb = 40.0 * live, 40.0 * N + 24.0 * live
     res = {"workload": "spring-mass structure, 2000x2000 jittered grid: 4,000,000 Node and %d Spring objects"
                        % len(mesh["a"]),
            "steps_timed": n, "us_per_step": step_us, "updates_per_s": (N + live) / (step_us * 1e-6),
            "springs_live": int(live),
            "force_us": tf, "force_gbs": fb / (tf * 1e-6) / 1e9,
            "node_us": tn, "node_gbs": nb / (tn * 1e-6) / 1e9,
-           "step_gbs": (fb + nb) / (step_us * 1e-6) / 1e9, "device_error": st.device_error}
+           "step_gbs": (fb + nb) / (step_us * 1e-6) / 1e9,
+           "force_frac": fb / (tf * 1e-6) / 1e9 / HBM_PEAK_GBS, "node_frac": nb / (tn * 1e-6) / 1e9 / HBM_PEAK_GBS,
+           "autotune": tuned, "device_error": st.device_error}
     heap.close()
     return res
 
@@ -1597,7 +1599,6 @@ def main():
                 print("extras: %s failed: %r" % (name, e), file=sys.stderr, flush=True)
                 extras[name] = {"error": repr(e)[:500]}
 
-        tuned = res.get("autotune") or {}
         extra("copy_bandwidth", measure_copy_bandwidth, torch)
         extra("coalescing", measure_coalescing, torch)
         extra("allocation", measure_allocation, torch)
@@ -1608,7 +1609,7 @@ def main():
         extra("structure", measure_structure, torch)
         extra("generation", measure_generation, torch)
         extra("partial_inlining", measure_spring_pi, torch)
-        extra("spring_2000", measure_spring_large, torch, tuned if tuned.get("kept") == "tuned" else None)
+        extra("spring_2000", measure_spring_large, torch)
         extra("nbody", measure_nbody_extra, torch)
         extra("linux_scalability", measure_linux_scalability, torch)
         extra("wator", measure_wator, torch)
