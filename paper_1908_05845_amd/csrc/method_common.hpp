@@ -60,6 +60,62 @@ __device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, 
     }
 }
 
+// The headers of the U blocks a wavefront takes in one iteration of
+// for_each_block_heads: their ids, types and allocation bitmaps as loaded,
+// and whether each R entry exists.  bm(j) is block j's bitmap if it is a
+// block of the class, else 0.  Loading the headers and using them are
+// separate steps, so a method can issue its loads from the blocks (which
+// need only the ids) before it waits for the headers.
+template <int U>
+struct BlockHeads {
+    uint32_t bid[U], type[U], cls;
+    uint64_t raw[U];
+    bool valid[U];
+    __device__ __forceinline__ bool own(int j) const { return valid[j] && type[j] == cls; }
+    __device__ __forceinline__ uint64_t bm(int j) const { return own(j) ? raw[j] : 0ull; }
+};
+
+// Calls f(heads) for the blocks of class `cls` in R, U at a time, as
+// for_each_block_group walks them, with three differences that shorten the
+// chain of dependent loads at the start of every wavefront: the error word
+// is read in the same batch of loads as the list lengths (nothing is called
+// once the heap has failed; a kernel using this walker needs no check of its
+// own), the wavefronts per work-group are passed in (wpg) instead of read
+// from the dispatch packet, and the block headers come to f unused.
+template <int U, class F>
+__device__ __forceinline__ void for_each_block_heads(const HeapView &h, uint32_t cls, uint32_t wpg, F &&f)
+{
+    const uint32_t err = ald32(h.ctrl + CTRL_ERR);
+    const BlockList L = block_list(h, cls);
+    if (__builtin_amdgcn_readfirstlane(err)) return;
+    const uint32_t r = L.r;
+    const uint32_t G = gridDim.x, g = blockIdx.x, x = g & 7u;
+    const uint32_t ngroups = (r + U - 1) / U;
+    uint32_t glo = 0, ghi = ngroups, lw = g * wpg + (threadIdx.x >> 6), lstep = G * wpg;
+    if (G >= 8) {
+        glo = (uint32_t)((uint64_t)ngroups * x / 8);
+        ghi = (uint32_t)((uint64_t)ngroups * (x + 1) / 8);
+        lw = (g >> 3) * wpg + (threadIdx.x >> 6);
+        lstep = ((G - x + 7) / 8) * wpg;
+    }
+    for (uint32_t gi = glo + lw; gi < ghi; gi += lstep) {
+        const uint32_t base = gi * U;
+        BlockHeads<U> hd;
+        hd.cls = cls;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            hd.valid[j] = base + j < r;
+            hd.bid[j] = __builtin_amdgcn_readfirstlane(L.at(hd.valid[j] ? base + j : base));
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            hd.type[j] = __builtin_amdgcn_readfirstlane(h.type[hd.bid[j]]);
+            hd.raw[j] = uniform64(h.alloc_bm[hd.bid[j]]);
+        }
+        f(hd);
+    }
+}
+
 // Calls f(bid, bm, own) for the blocks of class `cls` in R, U at a time: a
 // wavefront takes U consecutive R entries per iteration (consecutive blocks of
 // an ordered bulk allocation, whose objects share their neighbours) and loads

@@ -21,6 +21,7 @@ struct SpringK {
     uint32_t n_x, n_y, n_vx, n_vy, n_m, n_adj, n_adj_stride;   // Node fields
     float dt, limit;
     uint32_t tension_only;
+    uint32_t wpg;             // wavefronts per work-group of this launch
 };
 
 // The break decision is integer-valued, so it is evaluated in float32 with a
@@ -45,18 +46,24 @@ template <int U>
 __device__ __forceinline__ void spring_force(const HeapView &h, const SpringK &p)
 {
     const uint32_t s = lane_id();
-    for_each_block_group<U>(h, p.spring_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
+    for_each_block_heads<U>(h, p.spring_cls, p.wpg, [&](const BlockHeads<U> &hd) {
+        const uint32_t *bid = hd.bid;
         uint32_t a[U], b[U];
         float k[U], L0[U], xa[U], ya[U], xb[U], yb[U];
-        bool live[U];
-        // the blocks' own fields for all 64 slots (one contiguous run each)
+        bool live[U], own[U];
+        // the blocks' own fields for all 64 slots (one contiguous run each),
+        // issued before the headers are used
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            live[j] = (bm[j] >> s) & 1;
             a[j] = farr<uint32_t>(h, bid[j], p.s_a)[s];
             b[j] = farr<uint32_t>(h, bid[j], p.s_b)[s];
             k[j] = farr<float>(h, bid[j], p.s_k)[s];
             L0[j] = farr<float>(h, bid[j], p.s_L0)[s];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            own[j] = hd.own(j);
+            live[j] = (hd.bm(j) >> s) & 1;
         }
         // gathers through the node handles, live slots only
 #pragma unroll
@@ -104,13 +111,11 @@ template <int U>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spring_force(HeapView h,
                                                                                                  SpringK p)
 {
-    if (heap_failed(h)) return;
     spring_force<U>(h, p);
 }
 
 __global__ __launch_bounds__(1024) void k_spring_force4(HeapView h, SpringK p)
 {
-    if (heap_failed(h)) return;
     spring_force<4>(h, p);
 }
 
@@ -120,15 +125,15 @@ __global__ __launch_bounds__(1024) void k_spring_force4(HeapView h, SpringK p)
 template <int U>
 __global__ __launch_bounds__(1024) void k_spring_node(HeapView h, SpringK p)
 {
-    if (heap_failed(h)) return;
     const uint32_t s = lane_id();
-    for_each_block_group<U>(h, p.node_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
+    for_each_block_heads<U>(h, p.node_cls, p.wpg, [&](const BlockHeads<U> &hd) {
+        const uint32_t *bid = hd.bid;
         uint32_t e[U][8];
         float m[U], x[U], y[U], vx[U], vy[U], Fx[U], Fy[U];
         bool live[U];
+        // the blocks' fields, issued before the headers are used
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            live[j] = (bm[j] >> s) & 1;
 #pragma unroll
             for (int q = 0; q < 8; ++q) e[j][q] = farr<uint32_t>(h, bid[j], p.n_adj + q * p.n_adj_stride)[s];
             m[j] = farr<float>(h, bid[j], p.n_m)[s];
@@ -137,6 +142,8 @@ __global__ __launch_bounds__(1024) void k_spring_node(HeapView h, SpringK p)
             vx[j] = farr<float>(h, bid[j], p.n_vx)[s];
             vy[j] = farr<float>(h, bid[j], p.n_vy)[s];
         }
+#pragma unroll
+        for (int j = 0; j < U; ++j) live[j] = (hd.bm(j) >> s) & 1;
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             float gx[8], gy[8];
@@ -248,6 +255,7 @@ smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStrea
         return fail(SMMO_EINVAL, "spring: method runs on a different class");
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     const LaunchShape ls = method_shape(h, cls, kSpringGroup);
+    k.wpg = ls.block.x / 64;
     if (Which == 0) {
         if (ls.group == 4) hipLaunchKernelGGL(k_spring_force4, ls.grid, ls.block, 0, st, h->v, k);
         else if (ls.group == 2) hipLaunchKernelGGL(k_spring_force<2>, ls.grid, ls.block, 0, st, h->v, k);
