@@ -156,7 +156,6 @@ __global__ __launch_bounds__(1024) void k_adj_ckpt(HeapView h, AdjK p)
 
 __global__ __launch_bounds__(1024) void k_adj_seed(HeapView h, AdjK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;
@@ -174,7 +173,6 @@ __global__ __launch_bounds__(1024) void k_adj_seed(HeapView h, AdjK p)
 
 __global__ __launch_bounds__(1024) void k_adj_zero(HeapView h, AdjK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         farr<float>(h, bid, p.s_gk)[s] = 0.f;
@@ -187,7 +185,6 @@ __global__ __launch_bounds__(1024) void k_adj_zero(HeapView h, AdjK p)
 // mu = lv + dt lx, w = mu / m, lv = mu.
 __global__ __launch_bounds__(1024) void k_adj_node(HeapView h, AdjK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;

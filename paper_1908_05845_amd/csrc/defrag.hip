@@ -167,7 +167,6 @@ __device__ __forceinline__ uint32_t forwarded(const HeapView &h, uint32_t hd)
 
 __global__ __launch_bounds__(1024) void k_defrag_rewrite(HeapView h, RewriteK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;

@@ -38,7 +38,6 @@ __device__ __forceinline__ bool gen_valid(const HeapView &h, uint32_t handle)
 template <int U>
 __global__ __launch_bounds__(1024) void k_gen_count(HeapView h, GenK p)
 {
-    if (heap_failed(h)) return;
     const uint32_t s = lane_id();
     bool bad = false;                  // a cell id outside the grid or a handle outside the heap
     for_each_block_group<U>(h, p.cell_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
@@ -91,7 +90,6 @@ __global__ __launch_bounds__(1024) void k_gen_count(HeapView h, GenK p)
 // Cell::birth - an empty cell with a count in the birth set comes alive
 __global__ __launch_bounds__(1024) void k_gen_birth(HeapView h, GenK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         bool born = false;
@@ -117,7 +115,6 @@ __global__ __launch_bounds__(1024) void k_gen_birth(HeapView h, GenK p)
 // delete this at its end
 __global__ __launch_bounds__(1024) void k_gen_alive_update(HeapView h, GenK p)
 {
-    if (heap_failed(h)) return;
     for_each_object_packed(h, p.alive_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         bool gone = false;
         const int32_t cid = live ? farr<int32_t>(h, bid, p.a_id)[s] : 0;

@@ -624,9 +624,25 @@ smmo_status bind_field(const smmo_schema *s, uint32_t cls, const char *name, int
                                  "' required by this method");
 }
 
+// Heaps of at most this many blocks walk the class of a stale list directly
+// (every block, filtered by type) instead of enumerating it first, where
+// methods create objects of the class (its list would be rebuilt launch
+// after launch).
+constexpr uint32_t kDirectMaxBlocks = 8192;
+
 smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st, bool split)
 {
     if (!snapshot && (h->rstate[cls] == R_SPLIT || (h->rstate[cls] == R_VALID && !split))) return SMMO_OK;
+    // A walk that needs neither the iteration snapshot nor the packing plan
+    // reads nothing of R but its entries; on a small heap the walk over all
+    // blocks costs less than the enumeration launch it replaces, for a class
+    // whose list goes stale at every launch that creates its objects.  The
+    // list stays stale (rstate unchanged); every such launch walks directly.
+    if (!snapshot && !split && h->churn[cls] && h->v.M <= kDirectMaxBlocks) {
+        h->v.direct |= 1u << cls;
+        return SMMO_OK;
+    }
+    h->v.direct &= ~(1u << cls);
     const uint32_t nwaves = (h->v.lvl_n[0] + 63) / 64;
     const uint32_t grid = (nwaves + 3) / 4;
     hipLaunchKernelGGL(k_enumerate, dim3(grid), dim3(256), 0, st, h->v, cls, snapshot ? 1u : 0u,
@@ -675,8 +691,9 @@ uint32_t class_family(const smmo_schema *s, uint32_t cls)
     return fam;
 }
 
-void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects)
+void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects, bool in_method)
 {
+    if (in_method) h->churn[cls] = true;
     const uint64_t add = (max_new_objects + 63) / 64 + 1;
     h->ub_blocks[cls] = std::min<uint64_t>(h->v.M, h->ub_blocks[cls] + add);
     h->rstate[cls] = R_DIRTY;
@@ -956,7 +973,7 @@ smmo_status smmo_parallel_new(smmo_heap *h, uint32_t class_id, uint32_t n, const
         hipLaunchKernelGGL(k_new_device, dim3(grid), dim3(256), 0, st, h->v, class_id, fs, n, out_handles);
         if ((s = launch_check("k_new_device"))) return s;
     }
-    note_allocation(h, class_id, n);
+    note_allocation(h, class_id, n, false);
     h->last = st;
     return SMMO_OK;
 }

@@ -30,7 +30,8 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 }
 
 // Calls f(bid, bitmap) for every block of class `cls` in R, one wavefront per
-// block.  A block that was freed (or freed and re-used by another class)
+// block; nothing once the heap has failed (the error word is read in the
+// same batch of loads as the list lengths).  A block that was freed (or freed and re-used by another class)
 // since R was built has a different type and is skipped, so R may be a
 // superset of the class's blocks.  bitmap = the iteration bitmap (snapshot of
 // the allocation bitmap taken by the enumeration) or the allocation bitmap,
@@ -41,7 +42,11 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 template <class F>
 __device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, bool snapshot, F &&f)
 {
+    // the error word in the same batch of loads as the list lengths: nothing
+    // is called once the heap has failed
+    const uint32_t err = ald32(h.ctrl + CTRL_ERR);
     const BlockList L = block_list(h, cls);
+    if (__builtin_amdgcn_readfirstlane(err)) return;
     const uint32_t r = L.r;
     const uint32_t wpg = blockDim.x >> 6;
     const uint32_t nw = gridDim.x * wpg;
@@ -133,7 +138,9 @@ __device__ __forceinline__ void for_each_block_heads(const HeapView &h, uint32_t
 template <int U, class F>
 __device__ __forceinline__ void for_each_block_group(const HeapView &h, uint32_t cls, F &&f)
 {
+    const uint32_t err = ald32(h.ctrl + CTRL_ERR);
     const BlockList L = block_list(h, cls);
+    if (__builtin_amdgcn_readfirstlane(err)) return;
     const uint32_t r = L.r;
     const uint32_t wpg = blockDim.x >> 6;
     const uint32_t G = gridDim.x, g = blockIdx.x, x = g & 7u;
@@ -180,7 +187,9 @@ __device__ __forceinline__ void for_each_block_group(const HeapView &h, uint32_t
 template <class F>
 __device__ __forceinline__ void for_each_object_packed(const HeapView &h, uint32_t cls, bool snapshot, F &&f)
 {
+    const uint32_t err = ald32(h.ctrl + CTRL_ERR);
     const BlockList L = block_list(h, cls);
+    if (__builtin_amdgcn_readfirstlane(err)) return;
     const uint32_t wpg = blockDim.x >> 6;
     const uint32_t nw = gridDim.x * wpg;
     const bool pack = h.sparse_packing == 2 || (h.sparse_packing == 1 && L.r > nw);

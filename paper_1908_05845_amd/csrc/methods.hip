@@ -50,7 +50,6 @@ __device__ __forceinline__ bool gol_valid(const HeapView &h, uint32_t handle)
 template <int U>
 __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 {
-    if (heap_failed(h)) return;
     const uint32_t s = lane_id();
     bool bad = false;                  // a cell id outside the grid or a handle outside the heap
     for_each_block_group<U>(h, p.cell_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
@@ -106,7 +105,6 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 // Alive class is the sparse one)
 __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
 {
-    if (heap_failed(h)) return;
     for_each_object_packed(h, p.alive_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         bool die = false;
         const int32_t cid = live ? farr<int32_t>(h, bid, p.a_id)[s] : 0;
@@ -130,7 +128,6 @@ __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
 // gets a new Alive object
 __global__ __launch_bounds__(1024) void k_gol_birth(HeapView h, GolK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         bool born = false;
@@ -281,7 +278,6 @@ __global__ __launch_bounds__(256) void k_nbody_force(HeapView h, NbodyK p)
 // Body::update - v += f / m dt; x += v dt (velocity first)
 __global__ __launch_bounds__(1024) void k_nbody_update(HeapView h, NbodyK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;
@@ -353,7 +349,6 @@ struct AxpyK {
 // sparse_packing setting asks for it)
 __global__ __launch_bounds__(1024) void k_axpy(HeapView h, AxpyK p)
 {
-    if (heap_failed(h)) return;
     for_each_object_packed(h, p.cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         if (live) {
             float &x = farr<float>(h, bid, p.o_x)[s];
@@ -382,7 +377,6 @@ struct DestroyIfK {
 
 __global__ __launch_bounds__(1024) void k_destroy_if(HeapView h, DestroyIfK p)
 {
-    if (heap_failed(h)) return;
     for_each_object_packed(h, p.cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         bool d = false;
         if (live) {
@@ -417,7 +411,6 @@ struct SpawnK {
 
 __global__ __launch_bounds__(1024) void k_spawn(HeapView h, SpawnK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cls, p.snapshot != 0, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         bool sp = false;
@@ -440,7 +433,6 @@ __global__ __launch_bounds__(1024) void k_spawn(HeapView h, SpawnK p)
 // Game of Life, Alive -> Candidate)
 __global__ __launch_bounds__(1024) void k_transmute(HeapView h, SpawnK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         bool sel = false;
@@ -520,7 +512,6 @@ __device__ __forceinline__ bool ls_worker(const HeapView &h, const LsK &p, uint3
 
 __global__ __launch_bounds__(1024) void k_ls_alloc(HeapView h, LsK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
         uint32_t id;
         const bool live = ls_worker(h, p, bid, bm, id);
@@ -534,7 +525,6 @@ __global__ __launch_bounds__(1024) void k_ls_alloc(HeapView h, LsK p)
 
 __global__ __launch_bounds__(1024) void k_ls_free(HeapView h, LsK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
         uint32_t id;
         const bool live = ls_worker(h, p, bid, bm, id);

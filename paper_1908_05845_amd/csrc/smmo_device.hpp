@@ -73,13 +73,18 @@ __device__ __forceinline__ BlockList block_list(const HeapView &h, uint32_t cls)
 {
     BlockList L;
     L.R = h.R + (uint64_t)cls * h.M;
+    L.M = h.M;
+    L.direct = (h.direct >> cls) & 1;
+    if (L.direct) {
+        L.r = L.nd = h.M;
+        return L;
+    }
     L.r = __builtin_amdgcn_readfirstlane(__hip_atomic_load(h.ctrl + CTRL_RFINAL + cls, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT));
     const uint32_t ns = __builtin_amdgcn_readfirstlane(__hip_atomic_load(h.ctrl + CTRL_RSFINAL + cls,
                                                                          __ATOMIC_RELAXED,
                                                                          __HIP_MEMORY_SCOPE_AGENT));
     L.nd = L.r - ns;
-    L.M = h.M;
     return L;
 }
 

@@ -65,6 +65,9 @@ struct smmo_heap {
     int device = 0;
     uint64_t *host_ctrl = nullptr;     // pinned copy target for control words
     int rstate[SMMO_MAX_CLASSES] = {};
+    // classes that methods create objects of (their lists go stale launch
+    // after launch; small heaps walk them directly instead of re-enumerating)
+    bool churn[SMMO_MAX_CLASSES] = {};
     uint64_t ub_blocks[SMMO_MAX_CLASSES] = {};   // upper bound of blocks per class
     uint32_t cu_count = 256;
     smmo_bind_slot bind_cache[16];
@@ -116,8 +119,9 @@ LaunchShape method_shape(const smmo_heap *h, uint32_t cls, uint32_t def_group = 
 // have more blocks than the launch has wavefronts)
 bool packing_wanted(const smmo_heap *h, uint32_t cls, const LaunchShape &ls);
 
-// bookkeeping after a launch that creates objects of class cls
-void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects);
+// bookkeeping after a launch that creates objects of class cls (in_method:
+// a method's device allocation, not a host-side bulk creation)
+void note_allocation(smmo_heap *h, uint32_t cls, uint64_t max_new_objects, bool in_method = true);
 
 struct MethodEntry {
     const char *name;

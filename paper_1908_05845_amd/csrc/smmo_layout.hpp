@@ -109,6 +109,7 @@ struct HeapView {
     uint32_t coalescing;
     uint32_t spin_limit;
     uint32_t sparse_packing;      // 0 never, 1 when the list outgrows the grid, 2 always
+    uint32_t direct;              // classes whose walks this launch visit every block (bit c = class c)
 
     __host__ __device__ uint64_t *bm_word(uint32_t bmid, uint32_t lvl, uint32_t c) const
     {
@@ -123,10 +124,17 @@ struct HeapView {
 // stays in use until something may allocate objects of its class, so a block
 // listed as sparse never holds more than 32 live objects while it is used
 // (deletions only move blocks from dense towards sparse).
+// A direct list (HeapView::direct) is every block of the heap, 0 .. M-1, in
+// order: a walk that checks each block's type then visits the class's blocks
+// without a list.  The host uses it in place of a stale list on small heaps,
+// for walks that create no objects of the class they walk.
 struct BlockList {
     const uint32_t *R;
-    uint32_t r, nd, M;
-    __host__ __device__ uint32_t at(uint32_t i) const { return i < nd ? R[i] : R[M - 1 - (i - nd)]; }
+    uint32_t r, nd, M, direct;
+    __host__ __device__ uint32_t at(uint32_t i) const
+    {
+        return direct ? i : i < nd ? R[i] : R[M - 1 - (i - nd)];
+    }
 };
 
 } // namespace smmo

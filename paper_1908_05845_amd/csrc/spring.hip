@@ -192,7 +192,6 @@ __global__ __launch_bounds__(1024) void k_spring_node(HeapView h, SpringK p)
 // every (node, slot) pair belongs to one spring, so the writes never collide.
 __global__ __launch_bounds__(1024) void k_spring_link(HeapView h, SpringK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;

@@ -56,7 +56,6 @@ __device__ __forceinline__ bool pi_valid(const HeapView &h, uint32_t handle)
 // operation order, no contraction)
 __global__ __launch_bounds__(1024) void k_pi_force(HeapView h, PiK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
 #pragma clang fp contract(off)
         const uint32_t s = lane_id();
@@ -122,7 +121,6 @@ constexpr int32_t kLaneSerialSlots = 8;
 // reduction, instead of one lane walking them while the others wait.
 __global__ __launch_bounds__(1024) void k_pi_node(HeapView h, PiK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         const bool live = (bm >> s) & 1;
@@ -175,7 +173,6 @@ __global__ __launch_bounds__(1024) void k_pi_node(HeapView h, PiK p)
 // Spring::link: register the spring in its endpoints' slots
 __global__ __launch_bounds__(1024) void k_pi_link(HeapView h, PiK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;

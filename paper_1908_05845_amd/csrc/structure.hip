@@ -85,6 +85,11 @@ __device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_
     for (uint32_t j = 0; j < kMaxFamily; ++j) {
         L[j].R = h.R + (uint64_t)cls[j] * h.M;
         L[j].M = h.M;
+        L[j].direct = (h.direct >> cls[j]) & 1;
+        if (L[j].direct) {
+            rf[j] = h.M;
+            rs[j] = 0;
+        }
         L[j].r = used[j] ? rf[j] : 0u;
         L[j].nd = used[j] ? rf[j] - rs[j] : 0u;
         total += L[j].r;
@@ -172,7 +177,6 @@ __device__ __forceinline__ void unlink_and_delete(const HeapView &h, const Struc
 // AnchorPullNode::pull
 __global__ __launch_bounds__(1024) void k_st_pull(HeapView h, StructK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;
@@ -186,7 +190,6 @@ __global__ __launch_bounds__(1024) void k_st_pull(HeapView h, StructK p)
 // one fixed float32 operation order (no contraction).
 __global__ __launch_bounds__(1024) void k_st_force(HeapView h, StructK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
 #pragma clang fp contract(off)
         const uint32_t s = lane_id();
@@ -226,7 +229,6 @@ __global__ __launch_bounds__(1024) void k_st_force(HeapView h, StructK p)
 // Node::update: the attached springs' forces in slot order, then v and x
 __global__ __launch_bounds__(1024) void k_st_node_update(HeapView h, StructK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         // the node's slots and own fields for all 64 slots at once (one
@@ -442,7 +444,6 @@ __global__ __launch_bounds__(1024) void k_st_bfs_levels(HeapView h, StructK p, u
 // Spring::delete_spring
 __global__ __launch_bounds__(1024) void k_st_bfs_delete(HeapView h, StructK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         bool del = ((bm >> s) & 1) && farr<uint8_t>(h, bid, p.s_del)[s];
@@ -459,7 +460,6 @@ __global__ __launch_bounds__(1024) void k_st_bfs_delete(HeapView h, StructK p)
 // Spring::link: register the spring in its endpoints' slots
 __global__ __launch_bounds__(1024) void k_st_link(HeapView h, StructK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;

@@ -60,7 +60,6 @@ __device__ __forceinline__ bool wt_valid(const HeapView &h, uint32_t handle)
 // Cell::prepare
 __global__ __launch_bounds__(1024) void k_wt_cell_prepare(HeapView h, WatorK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;
@@ -112,7 +111,6 @@ __device__ __forceinline__ void wt_request(const HeapView &h, const WatorK &p, u
 // Fish::prepare
 __global__ __launch_bounds__(1024) void k_wt_fish_prepare(HeapView h, WatorK p)
 {
-    if (heap_failed(h)) return;
     for_each_object_packed(h, p.fish_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         if (!live) return;
         int32_t &timer = farr<int32_t>(h, bid, p.f_timer)[s];
@@ -126,7 +124,6 @@ __global__ __launch_bounds__(1024) void k_wt_fish_prepare(HeapView h, WatorK p)
 // Shark::prepare
 __global__ __launch_bounds__(1024) void k_wt_shark_prepare(HeapView h, WatorK p)
 {
-    if (heap_failed(h)) return;
     for_each_object_packed(h, p.shark_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         if (!live) return;
         farr<int32_t>(h, bid, p.s_timer)[s] += 1;
@@ -172,7 +169,6 @@ __global__ __launch_bounds__(1024) void k_wt_cell_decide(HeapView h, WatorK p)
 // Fish::update (the iteration snapshot keeps new fish out of this launch)
 __global__ __launch_bounds__(1024) void k_wt_fish_update(HeapView h, WatorK p)
 {
-    if (heap_failed(h)) return;
     for_each_object_packed(h, p.fish_cls, true, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         uint32_t pos = 0, np = 0;
         int32_t timer = 0;
@@ -201,7 +197,6 @@ __global__ __launch_bounds__(1024) void k_wt_fish_update(HeapView h, WatorK p)
 // Shark::update (snapshot as above); a starving shark deletes itself last
 __global__ __launch_bounds__(1024) void k_wt_shark_update(HeapView h, WatorK p)
 {
-    if (heap_failed(h)) return;
     for_each_object_packed(h, p.shark_cls, true, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
         uint32_t pos = 0, np = 0;
         int32_t timer = 0, energy = 0;
@@ -243,7 +238,6 @@ __global__ __launch_bounds__(1024) void k_wt_shark_update(HeapView h, WatorK p)
 // Cell::link - neighbours from the cell index on the torus
 __global__ __launch_bounds__(1024) void k_wt_cell_link(HeapView h, WatorK p)
 {
-    if (heap_failed(h)) return;
     for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
         if (!((bm >> s) & 1)) return;
