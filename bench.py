@@ -1140,6 +1140,49 @@ def measure_spring_defrag(torch, smmo, heap, lib, sim, stream, frozen):
     return out
 
 
+def measure_enumeration(torch):
+    """Enumeration cost against heap size (the thesis: the pre-pass that
+    lists a class's blocks before a do-all costs about the same whatever the
+    heap's size).  65,536 objects of a one-field class (1,024 full blocks) in
+    heaps of 2^12 .. 2^24 blocks; a host-side parallel_new of one object
+    (destroyed again) makes the class's list stale, so the next do-all
+    (test.axpy) first enumerates.  Enumeration = that do-all's time minus the
+    time of the same do-all right after it (list valid); medians of 20."""
+    import numpy as np
+
+    from paper_1908_05845_amd import smmo
+
+    out = {}
+    for lg in (12, 14, 16, 18, 20, 22, 24):
+        M = 1 << lg
+        heap = smmo.Heap({"Obj": [("x", "f32", 1)]}, blocks=M)
+        heap.new("Obj", 65536, x=torch.ones(65536, device="cuda"))
+        mid = smmo.smmo_method_id("test.axpy")
+        args = smmo.smmo_axpy_args(1.0, 0.0)
+        cls = heap.cls["Obj"]
+        with_enum, without = [], []
+        for _ in range(22):
+            one = heap.new("Obj", 1, x=torch.ones(1, device="cuda"))
+            smmo.smmo_destroy(heap.h, cls, one, 1)
+            torch.cuda.synchronize()
+            e = events(torch, 3)
+            e[0].record()
+            smmo.smmo_parallel_do(heap.h, cls, mid, args)
+            e[1].record()
+            smmo.smmo_parallel_do(heap.h, cls, mid, args)
+            e[2].record()
+            torch.cuda.synchronize()
+            with_enum.append(e[0].elapsed_time(e[1]) * 1e3)
+            without.append(e[1].elapsed_time(e[2]) * 1e3)
+        a, b = float(np.median(with_enum[2:])), float(np.median(without[2:]))
+        out["2^%d" % lg] = {"blocks": M, "do_all_us_with_enumeration": a, "do_all_us": b,
+                            "enumeration_us": a - b}
+        heap.close()
+        print("extras: enumeration at 2^%d blocks: %.2f us" % (lg, a - b), file=sys.stderr, flush=True)
+    return {"workload": "65,536 objects (1,024 full blocks) of a one-field class in heaps of 2^12 .. 2^24 blocks",
+            "by_heap_blocks": out}
+
+
 def measure_coalescing(torch):
     """The thesis's memory coalescing experiment (Ch.2) in wave64 form, on a
     1 GiB float array: read-modify-write of every element with the lanes of
@@ -1602,6 +1645,7 @@ def main():
         extra("copy_bandwidth", measure_copy_bandwidth, torch)
         extra("coalescing", measure_coalescing, torch)
         extra("allocation", measure_allocation, torch)
+        extra("enumeration", measure_enumeration, torch)
         extra("batched", measure_batched, torch, res["value"])
         extra("adjoint", measure_adjoint, torch, res["value"])
         extra("gol", measure_gol_extra, torch)

@@ -144,7 +144,7 @@ __global__ void k_heap_init(HeapView h)
 // atomic add (R is therefore ordered within a wavefront's range only).  The
 // last wavefront to finish publishes the length and resets the counters, so
 // the pass needs no separate reset launch and can be captured in a graph.
-__global__ __launch_bounds__(256) void k_enumerate(HeapView h, uint32_t cls, uint32_t snapshot, uint32_t split)
+__global__ __launch_bounds__(1024) void k_enumerate(HeapView h, uint32_t cls, uint32_t snapshot, uint32_t split)
 {
     const uint32_t w = global_wave_id();
     const uint32_t lane = lane_id();
@@ -203,11 +203,16 @@ __global__ __launch_bounds__(256) void k_enumerate(HeapView h, uint32_t cls, uin
         if ((dense >> b) & 1) R[kd++] = cidx * 64 + b;
         else R[h.M - 1 - ks++] = cidx * 64 + b;
     }
-    if (lane == 0) {
-        const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    // Completion is counted per work-group: after the barrier every
+    // wavefront of the group has had its list appends performed (their
+    // results were used), and one atomic per group tells the last group to
+    // publish the lengths.  (One atomic per wavefront on one word serialized
+    // at memory: 4,096 of them in a heap of 2^24 blocks.)
+    __syncthreads();
+    if (threadIdx.x == 0) {
         const uint32_t d = __hip_atomic_fetch_add(h.ctrl + CTRL_RDONE + cls, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
-        if (d == nwaves - 1) {
+        if (d == gridDim.x - 1) {
             const uint32_t rd = ald32(h.ctrl + CTRL_RCOUNT + cls), rs = ald32(h.ctrl + CTRL_RSCOUNT + cls);
             __hip_atomic_store(h.ctrl + CTRL_RFINAL + cls, rd + rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(h.ctrl + CTRL_RSFINAL + cls, rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -644,8 +649,8 @@ smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStre
     }
     h->v.direct &= ~(1u << cls);
     const uint32_t nwaves = (h->v.lvl_n[0] + 63) / 64;
-    const uint32_t grid = (nwaves + 3) / 4;
-    hipLaunchKernelGGL(k_enumerate, dim3(grid), dim3(256), 0, st, h->v, cls, snapshot ? 1u : 0u,
+    const uint32_t grid = (nwaves + 15) / 16;
+    hipLaunchKernelGGL(k_enumerate, dim3(grid), dim3(1024), 0, st, h->v, cls, snapshot ? 1u : 0u,
                        split ? 1u : 0u);
     smmo_status s = launch_check("k_enumerate");
     if (s) return s;
