@@ -63,9 +63,21 @@ def parse():
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
                     help="compare rocprofv3 --kernel-trace durations of a run of this bench with the "
                          "per-kernel times it printed (BENCH_JSON: its output line); needs no GPU")
+    ap.add_argument("--extra", choices=sorted(STANDALONE_EXTRAS),
+                    help="run one of the other measurements alone and print its JSON (for profiling it)")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="steps per captured HIP graph in the timed region (0 = eager launches)")
     return ap.parse_args()
+
+
+# the measurements besides the headline that need nothing from it, by the
+# name they have in the output line
+STANDALONE_EXTRAS = {"copy_bandwidth": "measure_copy_bandwidth", "coalescing": "measure_coalescing",
+                     "allocation": "measure_allocation", "enumeration": "measure_enumeration",
+                     "gol": "measure_gol_extra", "gol_16384": "measure_gol_large", "structure": "measure_structure",
+                     "generation": "measure_generation", "partial_inlining": "measure_spring_pi",
+                     "spring_2000": "measure_spring_large", "nbody": "measure_nbody_extra",
+                     "linux_scalability": "measure_linux_scalability", "wator": "measure_wator"}
 
 
 def events(torch, n):
@@ -1623,6 +1635,9 @@ def main():
     from paper_1908_05845_amd import smmo
 
     smmo.load_library()
+    if args.extra:
+        print(json.dumps({args.extra: globals()[STANDALONE_EXTRAS[args.extra]](torch)}), flush=True)
+        return
     if args.counter_pass:
         counter_pass(args, torch)
         return

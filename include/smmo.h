@@ -310,21 +310,24 @@ smmo_status smmo_defragment(smmo_heap *h, uint32_t class_id, uint32_t n, uint32_
  * reach, and every spring of such a node, is deleted) as one call: the
  * do-alls bfs_init, bfs_visit (until a pass finds the frontier empty),
  * bfs_mark and bfs_delete with the same results (distances, deletions), the
- * frontier kept as a queue instead of found by a pass over every node.
+ * frontier kept as a queue instead of found by a pass over every node, and
+ * the visited set as a bitmap in the work-group's LDS.
  *   h, args   the heap and the structure classes (args->nodebase_class is the
- *             family searched, args->anchor_class its start nodes; distance,
- *             dt and flag are not used)
+ *             family searched, args->anchor_class its start nodes,
+ *             args->bfs_options 0 or SMMO_BFS_* bits; distance, dt and flag
+ *             are not used)
  *   work      device buffer of work_words uint32 words owned by the caller,
- *             at least 64 + 64 B_n rounded up to a multiple of 4, plus 256 M,
- *             where B_n = the blocks the node classes may hold and M = the
- *             heap's blocks (B_n <= M, so 68 + 320 M always suffices); its
- *             contents on entry do not matter and on return are unspecified
+ *             at least 64 + C + M + C / 32 rounded up to a multiple of 4, plus
+ *             4 C, where C = 64 B_n, B_n = the blocks the node classes may
+ *             hold and M = the heap's blocks (B_n <= M, so 68 + 324 M always
+ *             suffices); its contents on entry do not matter and on return are
+ *             unspecified
  *   levels    device word: receives the number of visit passes the
  *             level-by-level form runs (the non-empty levels plus the one that
  *             finds the frontier empty), 0 if the heap has failed
  * Asynchronous on `stream`; SMMO_EINVAL (nothing enqueued) for NULL
- * pointers, bad classes or a workspace too small; device errors as for
- * smmo_parallel_do. */
+ * pointers, bad classes, unknown bfs_options bits or a workspace too small;
+ * device errors as for smmo_parallel_do. */
 smmo_status smmo_structure_remove_disconnected(smmo_heap *h, const smmo_structure_args *args, uint32_t *work,
                                                uint64_t work_words, uint32_t *levels, smmo_stream stream);
 

@@ -317,13 +317,21 @@ typedef struct {
  * A do-all on NodeBase runs once per concrete node class; the methods bind
  * the node fields on nodebase_class, whose offsets every node class shares. */
 #define SMMO_STRUCTURE_FAR 0x7FFFFFFF
+/* Forms of smmo_structure_remove_disconnected with the same results, for
+ * tests and measurements of the paths that large meshes take: the visited
+ * set in device memory for every node (without it, only for the node slots
+ * beyond 1,177,600), and a frontier buffer in LDS of 64 nodes instead of
+ * 2,048 (the queue in device memory takes the rest). */
+#define SMMO_BFS_DEVICE_VISITED 1u
+#define SMMO_BFS_SMALL_FRONTIER 2u
 typedef struct {
     uint32_t nodebase_class;
     uint32_t anchor_class;
     uint32_t spring_class;
     int32_t distance;            /* bfs_visit: the frontier's distance */
     float dt;                    /* pull, node_update */
-    uint32_t reserved;
+    uint32_t bfs_options;        /* smmo_structure_remove_disconnected: 0, or
+                                    SMMO_BFS_* bits */
     uint32_t *flag;              /* bfs_visit: device word, set to 1 when the
                                     frontier is not empty; the caller clears it */
 } smmo_structure_args;

@@ -635,7 +635,8 @@ smmo_status bind_field(const smmo_schema *s, uint32_t cls, const char *name, int
 // after launch).
 constexpr uint32_t kDirectMaxBlocks = 8192;
 
-smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st, bool split)
+smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st, bool split,
+                              bool allow_direct)
 {
     if (!snapshot && (h->rstate[cls] == R_SPLIT || (h->rstate[cls] == R_VALID && !split))) return SMMO_OK;
     // A walk that needs neither the iteration snapshot nor the packing plan
@@ -643,7 +644,7 @@ smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStre
     // blocks costs less than the enumeration launch it replaces, for a class
     // whose list goes stale at every launch that creates its objects.  The
     // list stays stale (rstate unchanged); every such launch walks directly.
-    if (!snapshot && !split && h->churn[cls] && h->v.M <= kDirectMaxBlocks) {
+    if (allow_direct && !snapshot && !split && h->churn[cls] && h->v.M <= kDirectMaxBlocks) {
         h->v.direct |= 1u << cls;
         return SMMO_OK;
     }

@@ -97,8 +97,11 @@ smmo_status bind_field(const smmo_schema *s, uint32_t cls, const char *name, int
 // snapshot = copy allocation bitmaps to iteration bitmaps on the way; split =
 // the list must carry the packing plan of packed do-alls: dense blocks at the
 // front, sparse ones (at most 32 live objects) at the back (without it every
-// block is listed as dense).
-smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st, bool split = false);
+// block is listed as dense); allow_direct = a small heap's churning class may
+// be walked over all blocks instead (false: the walk needs the list itself,
+// its positions naming the class's blocks).
+smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st, bool split = false,
+                              bool allow_direct = true);
 
 
 // launch shape of a do-all over class cls: the (method, class) setting of

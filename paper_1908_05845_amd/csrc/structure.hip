@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "../../include/smmo_methods.h"
 #include "method_common.hpp"
@@ -49,10 +50,11 @@ struct StructK {
 
 constexpr uint32_t kMaxFamily = 4;   // concrete classes one family launch walks
 
-// Calls f(bid, bm, cls) for every listed block of the classes in `mask` (at
-// most kMaxFamily; wpg = the launch's wavefronts per work-group, passed in so
-// that no load of the work-group size delays the walk), one wavefront per block: a grid-stride walk over their
-// block lists taken one after the other.  Nothing is called once the heap
+// Calls f(bid, bm, cls), or f(bid, bm, cls, i), for every listed block of the
+// classes in `mask` (at most kMaxFamily; wpg = the launch's wavefronts per
+// work-group, passed in so that no load of the work-group size delays the
+// walk), one wavefront per block: a grid-stride walk over their block lists
+// taken one after the other, i = the block's position in that sequence.  Nothing is called once the heap
 // has failed: the error word is read in the same batch of loads as the list
 // lengths (the kernels that use this walker need no check of their own).  A listed block whose type changed
 // comes with bm = 0 (no live slot), so f may load from any block it is given
@@ -109,7 +111,10 @@ __device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_
         bid = __builtin_amdgcn_readfirstlane(bid);
         const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
         const uint64_t bm = uniform64(h.alloc_bm[bid]);
-        f(bid, t == c ? bm : 0ull, c);
+        if constexpr (std::is_invocable_v<F &, uint32_t, uint64_t, uint32_t, uint32_t>)
+            f(bid, t == c ? bm : 0ull, c, i);
+        else
+            f(bid, t == c ? bm : 0ull, c);
     }
 }
 
@@ -323,36 +328,79 @@ __global__ __launch_bounds__(1024) void k_st_bfs_mark(HeapView h, StructK p)
 // The same breadth-first search as the level-by-level visits above (every
 // node's distance from the nearest anchor node, the nodes it never reaches
 // deleted), with the frontier kept as a queue instead of found by a walk over
-// every node block in every level.  Workspace layout (uint32 words):
-//   [0, kBfsHeader)          header; word 0 = the queue's length
-//   [kBfsHeader, +cap)       the queue: node handles in the order they were
-//                            reached, all of distance 0, then 1, ...; each
-//                            node at most once (cap = node slots)
-//   [nbr_off, +4 * 64 M)     per handle of the heap, the node's neighbours
-//                            (the other end of each spring slot, SMMO_NULL
-//                            for an empty slot) and a pad word, filled for the
-//                            live nodes by the set-up walk
+// every node block in every level.  During the search a node is named by a
+// dense index, 64 i + slot for the block at position i of the node classes'
+// block lists (taken one after the other), so that one visited bit per node
+// slot fits the work-group's LDS for up to kBfsLdsBits slots.
+// Workspace layout (uint32 words; cap = the node slots, 64 per block the node
+// classes may hold; M = the heap's blocks):
+//   [0, kBfsHeader)        header; word 0 = the number of anchor nodes
+//   queue  [+cap)          the anchors' dense indices, then the frontier
+//                          nodes that do not fit in LDS, level after level
+//   rank   [+M)            per node block, its position in the lists
+//   bits   [+cap / 32)     visited bits of the slots beyond the LDS bitmap
+//                          (of all slots with SMMO_BFS_DEVICE_VISITED)
+//   nbr    [+4 cap)        per dense index of a live node: its neighbours'
+//                          dense indices (the other end of each spring slot,
+//                          SMMO_NULL for an empty slot) and its handle
 // The topology does not change during the search, so resolving each node's
 // springs to its neighbours once, in one wide walk, takes two dependent loads
-// out of every level's chain.
+// out of every level's chain, and with the visited set in LDS a level's
+// chain holds one load from device memory (the neighbour entry).
 constexpr uint32_t kBfsHeader = 64;
+constexpr uint32_t kBfsLdsQ = 2048;         // frontier nodes per LDS buffer (two buffers)
+constexpr uint32_t kBfsLdsWords = 36800;    // the LDS visited bitmap: 1,177,600 slots
+constexpr uint32_t kBfsLdsBits = 32 * kBfsLdsWords;
+constexpr uint32_t kBfsThreads = 1024;      // the level kernel's one work-group
 
-__host__ __device__ inline uint64_t bfs_nbr_offset(uint64_t cap) { return (kBfsHeader + cap + 3) & ~3ull; }
-__host__ __device__ inline uint64_t bfs_words(uint64_t cap, uint64_t M) { return bfs_nbr_offset(cap) + 256 * M; }
+struct BfsLayout {
+    uint64_t queue, rank, bits, nbr, words;
+};
+
+__host__ __device__ constexpr BfsLayout bfs_layout(uint64_t cap, uint64_t M)
+{
+    BfsLayout l{};
+    l.queue = kBfsHeader;
+    l.rank = l.queue + cap;
+    l.bits = l.rank + M;
+    l.nbr = (l.bits + cap / 32 + 3) & ~3ull;
+    l.words = l.nbr + 4 * cap;
+    return l;
+}
 
 __global__ __launch_bounds__(64) void k_st_bfs_clear(uint32_t *work)
 {
     work[threadIdx.x] = 0u;
 }
 
+// the position of every node block in the lists, and its slots' visited
+// bits in device memory cleared
+__global__ __launch_bounds__(1024) void k_st_bfs_rank(HeapView h, StructK p, uint32_t *work, uint32_t cap)
+{
+    const BfsLayout L = bfs_layout(cap, h.M);
+    for_each_family_block(h, p.fam_mask, p.wpg, [&](uint32_t bid, uint64_t, uint32_t, uint32_t i) {
+        const uint32_t s = lane_id();
+        if (64ull * i + 64 > cap) {
+            if (s == 0) raise_error(h, ERR_INTERNAL);
+            return;
+        }
+        if (s == 0) work[L.rank + bid] = i;
+        if (s < 2) work[L.bits + 2 * i + s] = 0u;
+    });
+}
+
 // NodeBase::initialize_frontier, appending the anchor nodes to the queue (one
 // atomic per wavefront for all of its anchors), and each live node's
-// neighbours
+// neighbour entry
 __global__ __launch_bounds__(1024) void k_st_bfs_queue_init(HeapView h, StructK p, uint32_t *work, uint32_t cap)
 {
-    uint4 *nbr = reinterpret_cast<uint4 *>(work + bfs_nbr_offset(cap));
-    for_each_family_block(h, p.fam_mask, p.wpg, [&](uint32_t bid, uint64_t bm, uint32_t t) {
+    const BfsLayout L = bfs_layout(cap, h.M);
+    uint4 *nbr = reinterpret_cast<uint4 *>(work + L.nbr);
+    const uint32_t *rank = work + L.rank;
+    for_each_family_block(h, p.fam_mask, p.wpg, [&](uint32_t bid, uint64_t bm, uint32_t t, uint32_t i) {
+        if (64ull * i + 64 > cap) return;   // (the rank pass has raised the error)
         const uint32_t s = lane_id();
+        const uint32_t self = 64 * i + s;
         const bool live = ((bm >> s) & 1) != 0;
         const bool anchor = live && ((p.anchor_mask >> t) & 1);
         uint32_t hs[3];
@@ -360,15 +408,18 @@ __global__ __launch_bounds__(1024) void k_st_bfs_queue_init(HeapView h, StructK 
         for (int q = 0; q < 3; ++q) hs[q] = farr<uint32_t>(h, bid, p.n_spr + q * p.n_spr_stride)[s];
         if (live) {
             farr<int32_t>(h, bid, p.n_dist)[s] = anchor ? 0 : kFar;
-            uint32_t o[3];
+            uint32_t other[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                o[q] = kNull;
+                other[q] = kNull;
                 if (hs[q] == kNull || !st_valid(h, hs[q] & ~kP2)) continue;
-                const uint32_t other = fref<uint32_t>(h, hs[q] & ~kP2, (hs[q] & kP2) ? p.s_p1 : p.s_p2);
-                if (st_valid(h, other)) o[q] = other;
+                const uint32_t o = fref<uint32_t>(h, hs[q] & ~kP2, (hs[q] & kP2) ? p.s_p1 : p.s_p2);
+                if (st_valid(h, o)) other[q] = o;
             }
-            nbr[(bid << 6) | s] = make_uint4(o[0], o[1], o[2], kNull);
+            uint32_t o[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) o[q] = other[q] == kNull ? kNull : 64 * rank[other[q] >> 6] + (other[q] & 63);
+            nbr[self] = make_uint4(o[0], o[1], o[2], (bid << 6) | s);
         }
         const uint64_t am = __ballot(anchor);
         if (!am) return;
@@ -378,64 +429,131 @@ __global__ __launch_bounds__(1024) void k_st_bfs_queue_init(HeapView h, StructK 
         base = (uint32_t)__shfl((int)base, (int)leader);
         const uint32_t pos = base + (uint32_t)__popcll(am & ((1ull << s) - 1));
         if (anchor) {
-            if (pos < cap) work[kBfsHeader + pos] = (bid << 6) | s;
+            if (pos < cap) work[L.queue + pos] = self;
             else raise_error(h, ERR_INTERNAL);
         }
     });
 }
 
-// NodeBase::visit for every level, in one work-group: the threads take the
-// current level's range of the queue, a neighbour still at SMMO_STRUCTURE_FAR
-// is claimed with a compare-and-swap (so it is appended once, whichever
-// thread reaches it first; its distance is d + 1 either way) and appended
-// through a counter in LDS.  One barrier ends a level; the next level is what
-// it appended.  The loop ends when a level appends nothing, after at most
-// one level per node.  *levels = the number of levels the thesis's loop runs:
-// the non-empty ones plus the pass that finds the frontier empty.
-__global__ __launch_bounds__(1024) void k_st_bfs_levels(HeapView h, StructK p, uint32_t *work, uint32_t cap,
-                                                        uint32_t *levels)
+// NodeBase::visit for every level, in one work-group.  The visited set is a
+// bitmap over dense indices, in LDS for the first kBfsLdsBits of them and in
+// device memory beyond (or for all, SMMO_BFS_DEVICE_VISITED): a node is
+// claimed by the atomic OR that sets its bit, so each node enters the
+// frontier once, at its breadth-first distance.  Level d's frontier is an LDS
+// part (up to qlim dense indices in one of two LDS buffers) followed by a
+// range of the queue in device memory (level 0: the anchors; later: the
+// appends that did not fit in LDS).  The threads share the frontier evenly:
+// each writes a node's distance d, reads its neighbour entry and claims the
+// neighbours; a node won is appended to level d + 1's frontier, at the
+// position the LDS counter d mod 3 gives: below qlim in the other LDS
+// buffer, beyond it in the queue after level d's own range.  One barrier
+// ends a level, after which every thread knows the next frontier from that
+// counter; the counter of level d + 1 was last read after the barrier that
+// ended level d - 2, so thread 0 clears it during level d.  The loop ends at
+// the first empty frontier, at most one level per node.  *levels = the
+// number of levels the thesis's loop runs: the non-empty ones plus the pass
+// that finds the frontier empty.
+__global__ __launch_bounds__(kBfsThreads) void k_st_bfs_levels(HeapView h, StructK p, uint32_t *work, uint32_t cap,
+                                                        uint32_t options, uint32_t *levels)
 {
-    __shared__ uint32_t s_lo, s_hi, s_tail, s_stop;
-    uint32_t *queue = work + kBfsHeader;
-    const uint4 *nbr = reinterpret_cast<const uint4 *>(work + bfs_nbr_offset(cap));
+    __shared__ uint32_t s_bits[kBfsLdsWords];
+    __shared__ uint32_t s_q[2][kBfsLdsQ];
+    __shared__ uint32_t s_n0, s_stop, s_cnt[3];
+    const BfsLayout L = bfs_layout(cap, h.M);
+    uint32_t *queue = work + L.queue;
+    uint32_t *gbits = work + L.bits;
+    const uint4 *nbr = reinterpret_cast<const uint4 *>(work + L.nbr);
+    const uint32_t lds_bits = (options & SMMO_BFS_DEVICE_VISITED) ? 0u : kBfsLdsBits;
+    const uint32_t qlim = (options & SMMO_BFS_SMALL_FRONTIER) ? 64u : kBfsLdsQ;
+    for (uint32_t w = threadIdx.x; w < kBfsLdsWords; w += kBfsThreads) s_bits[w] = 0u;
     if (threadIdx.x == 0) {
         s_stop = heap_failed(h) ? 1u : 0u;
-        const uint32_t n = std::min(__hip_atomic_load(work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), cap);
-        s_lo = 0;
-        s_hi = n;
-        s_tail = n;
+        s_n0 = std::min(__hip_atomic_load(work, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), cap);
+        s_cnt[0] = s_cnt[1] = s_cnt[2] = 0;
     }
     __syncthreads();
     if (s_stop) {
         if (threadIdx.x == 0) *levels = 0;
         return;
     }
+    // sets the visited bit of dense index o; whether this call set it.
+    // LdsOnly: every dense index is below lds_bits (a uniform choice, so the
+    // level loop of a mesh that fits has no device-memory atomic at all)
+    auto claim = [&](uint32_t o, auto lds_only) -> bool {
+        const uint32_t bit = 1u << (o & 31);
+        if (decltype(lds_only)::value || o < lds_bits) return (atomicOr(&s_bits[o >> 5], bit) & bit) == 0;
+        return (atomicOr(&gbits[o >> 5], bit) & bit) == 0;
+    };
+    uint32_t nl = 0;                 // LDS part of the frontier, in s_q[cur]
+    uint32_t glo = 0, ghi = s_n0;    // queue part of the frontier
+    for (uint32_t i = threadIdx.x; i < ghi; i += kBfsThreads)
+        if (!claim(queue[i], std::false_type{})) raise_error(h, ERR_INTERNAL);   // an anchor listed twice
+    __syncthreads();
+    uint32_t cur = 0;
     uint32_t d = 0;
-    for (;;) {
-        const uint32_t lo = s_lo, hi = s_hi;
-        if (lo >= hi) break;
-        for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const uint4 nb = nbr[queue[i]];
-            const uint32_t o[3] = {nb.x, nb.y, nb.z};
-            // the three claims are independent: all issued before any result is used
-            int32_t was[3];
+    // one level: each node's three claims issued together (a missing
+    // neighbour's claim is aimed at the node itself, visited already, so it
+    // fails without a branch), then one append for all the node won, then
+    // the node's distance (a store nothing in the level waits for)
+    auto node = [&](uint32_t self, auto lds_only) {
+        uint32_t *cnt = &s_cnt[d % 3];
+        const uint4 e = nbr[self];
+        const uint32_t o[3] = {e.x, e.y, e.z};
+        bool won[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
-                was[q] = o[q] == kNull ? 0 : atomicCAS(&fref<int32_t>(h, o[q], p.n_dist), kFar, (int32_t)d + 1);
+        for (int q = 0; q < 3; ++q) won[q] = claim(o[q] == kNull ? self : o[q], lds_only);
+        const uint32_t n = (uint32_t)won[0] + (uint32_t)won[1] + (uint32_t)won[2];
+        // the wavefront's appends reserved by one LDS add: each lane's offset
+        // is the sum of n over the active lanes below it, from ballots of n's
+        // two bits (a per-lane add with a varying n would be turned into a
+        // loop over the lanes)
+        const uint64_t b0 = __ballot(n & 1), b1 = __ballot(n & 2);
+        const uint64_t below = (1ull << lane_id()) - 1;
+        const uint32_t tot = (uint32_t)(__popcll(b0) + 2 * __popcll(b1));
+        uint32_t base = 0;
+        if (tot) {   // (uniform over the active lanes)
+            const uint32_t leader = (uint32_t)(__ffsll((unsigned long long)__ballot(1)) - 1);
+            if (lane_id() == leader) base = atomicAdd(cnt, tot);
+            base = __builtin_amdgcn_readfirstlane(base);   // the leader is the first active lane
+        }
+        if (n) {
+            uint32_t pos = base + (uint32_t)(__popcll(b0 & below) + 2 * __popcll(b1 & below));
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                if (o[q] == kNull || was[q] != kFar) continue;
-                const uint32_t pos = atomicAdd(&s_tail, 1u);
-                if (pos < cap) queue[pos] = o[q];
-                else raise_error(h, ERR_INTERNAL);
+                if (!won[q]) continue;
+                if (pos < qlim) {
+                    s_q[cur ^ 1][pos] = o[q];
+                } else {
+                    const uint32_t g = ghi + (pos - qlim);
+                    if (g < cap) queue[g] = o[q];
+                    else raise_error(h, ERR_INTERNAL);
+                }
+                ++pos;
             }
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            s_lo = hi;
-            s_hi = std::min(s_tail, cap);
+        fref<int32_t>(h, e.w, p.n_dist) = (int32_t)d;
+    };
+    // the frontier's LDS part and its queue part in separate branches, so
+    // that each read is an LDS or a global load (not a flat one)
+    auto level = [&](auto lds_only) {
+        const uint32_t total = nl + (ghi - glo);
+        for (uint32_t i = threadIdx.x; i < total; i += kBfsThreads) {
+            if (i < nl) node(s_q[cur][i], lds_only);
+            else node(queue[glo + (i - nl)], lds_only);
         }
+    };
+    const bool lds_only = cap <= lds_bits;
+    for (;;) {
+        if (nl + (ghi - glo) == 0) break;
+        if (threadIdx.x == 0) s_cnt[(d + 1) % 3] = 0;
+        if (lds_only) level(std::true_type{});
+        else level(std::false_type{});
         __syncthreads();
+        const uint32_t appended = s_cnt[d % 3];   // final: every append of the level precedes the barrier
+        nl = std::min(appended, qlim);
+        glo = ghi;
+        ghi = std::min(ghi + (appended - nl), cap);
+        cur ^= 1;
         ++d;
     }
     if (threadIdx.x == 0) *levels = d + 1;
@@ -568,6 +686,7 @@ smmo_status launch_structure(smmo_heap *h, uint32_t cls, const void *args, hipSt
     smmo_structure_args key = a;
     key.distance = 0;
     key.dt = 0.f;
+    key.bfs_options = 0;
     key.flag = nullptr;
     StructK k;
     smmo_status s = cached_bind(h, (const void *)&launch_structure<W>, cls, key, k,
@@ -614,29 +733,35 @@ smmo_status remove_disconnected(smmo_heap *h, const smmo_structure_args &a, uint
     smmo_structure_args key = a;
     key.distance = 0;
     key.dt = 0.f;
+    key.bfs_options = 0;
     key.flag = nullptr;
     StructK k;
     s = cached_bind(h, (const void *)&k_st_bfs_levels, a.nodebase_class, key, k,
                     [&] { return bind_structure(h, a.nodebase_class, key, W_BFS_INIT, k); });
     if (s) return s;
+    if (a.bfs_options & ~(SMMO_BFS_DEVICE_VISITED | SMMO_BFS_SMALL_FRONTIER))
+        return fail(SMMO_EINVAL, "structure BFS: unknown bfs_options bits");
     uint64_t slots = 0;
     for (uint32_t c = 0; c < h->schema->nclasses; ++c)
         if ((k.fam_mask >> c) & 1) slots += 64 * h->ub_blocks[c];
     if (slots > 0xFFFFFFFFull - kBfsHeader) return fail(SMMO_EINVAL, "structure BFS: too many node slots");
-    if (words < bfs_words(slots, h->v.M))
-        return fail(SMMO_EINVAL, "structure BFS: the workspace needs 64 header words, one word per node slot of "
-                                 "the node classes (64 per block they may hold), rounded up to 4, and 256 words "
-                                 "per block of the heap");
+    if (words < bfs_layout(slots, h->v.M).words)
+        return fail(SMMO_EINVAL, "structure BFS: the workspace needs 64 header words, 5 + 1/32 words per node slot "
+                                 "of the node classes (64 per block they may hold), one word per block of the "
+                                 "heap, and up to 3 words of alignment");
+    // the dense indices are positions in the lists: enumerated lists, never
+    // a direct walk over all blocks
     for (uint32_t c = 0; c < h->schema->nclasses; ++c)
-        if (((k.fam_mask >> c) & 1) && (s = ensure_enumerated(h, c, false, st))) return s;
+        if (((k.fam_mask >> c) & 1) && (s = ensure_enumerated(h, c, false, st, false, false))) return s;
     const uint32_t cap = (uint32_t)slots;
     hipLaunchKernelGGL(k_st_bfs_clear, dim3(1), dim3(kBfsHeader), 0, st, work);
     if (k.fam_mask) {
         LaunchShape ls = family_shape(h, a.nodebase_class, k.fam_mask);
         k.wpg = ls.block.x / 64;
+        hipLaunchKernelGGL(k_st_bfs_rank, ls.grid, ls.block, 0, st, h->v, k, work, cap);
         hipLaunchKernelGGL(k_st_bfs_queue_init, ls.grid, ls.block, 0, st, h->v, k, work, cap);
     }
-    hipLaunchKernelGGL(k_st_bfs_levels, dim3(1), dim3(1024), 0, st, h->v, k, work, cap, levels);
+    hipLaunchKernelGGL(k_st_bfs_levels, dim3(1), dim3(kBfsThreads), 0, st, h->v, k, work, cap, a.bfs_options, levels);
     if ((s = launched("structure BFS kernel"))) return s;
     h->last = st;
     if ((s = launch_structure<W_BFS_MARK>(h, a.nodebase_class, &a, st))) return s;
@@ -653,9 +778,9 @@ smmo_status smmo_structure_remove_disconnected(smmo_heap *h, const smmo_structur
 }
 
 // ---- the same BFS without a caller workspace ------------------------------
-// The workspace (queue and neighbour table) lives in `scratch`, a device array
-// of this library: each GPU the library runs on holds one copy, 21 MB, until
-// the process ends.  It serves heaps of up to kScratchBlocks blocks.  In host
+// The workspace (queue, block positions, visited bits and neighbour table)
+// lives in `scratch`, a device array of this library: each GPU the library
+// runs on holds one copy, 21 MB, until the process ends.  It serves heaps of up to kScratchBlocks blocks.  In host
 // code the array's name is not a device address; its address on a device is
 // taken once per device (hipGetSymbolAddress, with that device current) and
 // kept in scratch_ptr, which is what the kernels are given.  All calls on one
@@ -663,7 +788,7 @@ smmo_status smmo_structure_remove_disconnected(smmo_heap *h, const smmo_structur
 // header is cleared by a kernel at the start of every call (the rest is
 // written before it is read), and calls that overlap on one GPU race.
 constexpr uint32_t kScratchBlocks = 16384;
-constexpr uint64_t kScratchWords = (kBfsHeader + 64ull * kScratchBlocks + 3) / 4 * 4 + 256ull * kScratchBlocks;
+constexpr uint64_t kScratchWords = bfs_layout(64ull * kScratchBlocks, kScratchBlocks).words;
 static __device__ __align__(256) uint32_t scratch[kScratchWords];
 
 namespace {

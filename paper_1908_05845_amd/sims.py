@@ -524,14 +524,15 @@ class StructureSim:
     no longer connected to an anchor node: a BFS whose frontier is a queue,
     all levels run on the device by one call (bfs="queue", the default), or
     the thesis's form, the level passes launched `bfs_batch` at a time
-    between reads of their frontier flags (bfs="levels").
+    between reads of their frontier flags (bfs="levels").  bfs_options
+    (SMMO_BFS_* bits) selects the queue BFS's forms for large meshes.
     A state with deleted objects loads too: nodes with nalive == 0 and
     springs with salive == 0 (where those arrays are given) are not created;
     nspr, dist and (where given) the spring forces fx, fy are taken from the
     state."""
 
     def __init__(self, mesh: dict, dt: float, cfg=None, extra_blocks: int = 16, bfs_batch: int = 8,
-                 bfs: str = "queue"):
+                 bfs: str = "queue", bfs_options: int = 0):
         import torch
 
         if bfs not in ("queue", "levels"):
@@ -574,11 +575,11 @@ class StructureSim:
         self.node_h = node_h
         c = self.heap.cls
         self.flags = torch.zeros(max(bfs_batch, 1), dtype=torch.int32, device=dev)
-        # the queue BFS's workspace (header, queue, neighbour table), sized by
-        # the heap's block count
-        self.bfs_work = torch.empty(68 + 320 * self.heap.blocks, dtype=torch.int32, device=dev)
+        # the queue BFS's workspace (header, queue, block positions, visited
+        # bits, neighbour table), sized by the heap's block count
+        self.bfs_work = torch.empty(68 + 324 * self.heap.blocks, dtype=torch.int32, device=dev)
         self.bfs_levels = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.args = smmo.smmo_structure_args(c["NodeBase"], c["AnchorNode"], c["Spring"], 0, dt, 0, None)
+        self.args = smmo.smmo_structure_args(c["NodeBase"], c["AnchorNode"], c["Spring"], 0, dt, bfs_options, None)
         self.m = {n: smmo.smmo_method_id("structure." + n) for n in
                   ("pull", "force", "node_update", "bfs_init", "bfs_visit", "bfs_mark", "bfs_delete", "link")}
         sid = np.flatnonzero(salive)

@@ -123,11 +123,14 @@ class smmo_generation_args(C.Structure):
 
 
 SMMO_STRUCTURE_FAR = 0x7FFFFFFF
+SMMO_BFS_DEVICE_VISITED = 1
+SMMO_BFS_SMALL_FRONTIER = 2
 
 
 class smmo_structure_args(C.Structure):
     _fields_ = [("nodebase_class", C.c_uint32), ("anchor_class", C.c_uint32), ("spring_class", C.c_uint32),
-                ("distance", C.c_int32), ("dt", C.c_float), ("reserved", C.c_uint32), ("flag", C.c_void_p)]
+                ("distance", C.c_int32), ("dt", C.c_float), ("bfs_options", C.c_uint32),
+                ("flag", C.c_void_p)]
 
 
 class smmo_axpy_args(C.Structure):

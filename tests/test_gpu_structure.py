@@ -61,9 +61,21 @@ def check_topology(s1, ref, node_ok=None, sdiff=None):
     assert np.array_equal(s1["isp2"].reshape(-1, 3)[al][sl >= 0], ref["isp2"].reshape(-1, 3)[al][sl >= 0])
 
 
+# the BFS forms: the one-call queue BFS with its visited set in LDS, in device
+# memory, with a 64-node LDS frontier (the rest queued in device memory), both
+# of the latter; and the thesis's level passes
+BFS_FORMS = {"queue": ("queue", 0),
+             "queue-device-visited": ("queue", smmo.SMMO_BFS_DEVICE_VISITED),
+             "queue-small-frontier": ("queue", smmo.SMMO_BFS_SMALL_FRONTIER),
+             "queue-device-both": ("queue", smmo.SMMO_BFS_DEVICE_VISITED | smmo.SMMO_BFS_SMALL_FRONTIER),
+             "levels": ("levels", 0)}
+
+
 def make_sim(batch=8, shapes=None, bfs="queue"):
+    mode, options = BFS_FORMS[bfs]
+
     def make(st):
-        sim = StructureSim(st, DT, bfs_batch=batch, bfs=bfs)
+        sim = StructureSim(st, DT, bfs_batch=batch, bfs=mode, bfs_options=options)
         for name, shape in (shapes or {}).items():
             smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), sim.heap.cls["NodeBase"], *shape)
         return sim
@@ -167,7 +179,7 @@ def structure_bfs_ready(mesh):
 
 @pytest.mark.parametrize("W,H,seed,batch,bfs", [(24, 10, 1, 8, "levels"), (17, 9, 2, 1, "levels"),
                                                 (40, 16, 3, 3, "levels"), (24, 10, 1, 0, "queue"),
-                                                (40, 16, 3, 0, "queue")])
+                                                (40, 16, 3, 0, "queue"), (40, 16, 3, 0, "queue-device-both")])
 def test_iterations_phase_by_phase(dev, W, H, seed, batch, bfs):
     print("structure %dx%d seed %d bfs %s batch %d" % (W, H, seed, bfs, batch), flush=True)
     mesh = structure_mesh(W, H, seed=seed, pull_speed=2.0, break_strain=0.02, v_sigma=0.05)
@@ -184,7 +196,7 @@ def test_iterations_phase_by_phase(dev, W, H, seed, batch, bfs):
     assert int(s["nalive"].sum()) < mesh["ntype"].size        # the GPU's own run removed nodes too
 
 
-@pytest.mark.parametrize("bfs", ["queue", "levels"])
+@pytest.mark.parametrize("bfs", ["queue", "queue-device-visited", "levels"])
 @pytest.mark.parametrize("W,H", [(1, 3), (2, 5), (3, 1), (5, 2)])
 def test_small_meshes(dev, W, H, bfs):
     """Meshes without free nodes, without pull nodes or with one row."""
@@ -193,7 +205,7 @@ def test_small_meshes(dev, W, H, bfs):
     run_checked(mesh, 3, 5, 5, make_sim(bfs=bfs))
 
 
-@pytest.mark.parametrize("bfs", ["queue", "levels"])
+@pytest.mark.parametrize("bfs", sorted(BFS_FORMS))
 def test_no_anchor_removes_everything(dev, bfs):
     """Without anchor nodes the BFS visits nothing: every node with springs
     and every spring is deleted (a node loses its last spring and goes with
@@ -250,9 +262,10 @@ def test_bfs_walks_with_small_grids(dev, wg, waves):
 
 def test_queue_bfs_on_a_larger_broken_mesh(dev):
     """The queue BFS at a size where levels hold hundreds of nodes and the
-    frontier outgrows the work-group: a 300 x 200 mesh that the oracle has
-    pulled apart for a few iterations, restarted on the GPU with both BFS
-    forms; distances, levels and deletions equal the oracle's."""
+    frontier outgrows the work-group (and the small LDS frontier): a 300 x 200
+    mesh that the oracle has pulled apart for a few iterations, restarted on
+    the GPU with every BFS form; distances, levels and deletions equal the
+    oracle's."""
     print("structure 300x200 queue BFS", flush=True)
     mesh = structure_mesh(300, 200, seed=11, pull_speed=5.0, break_strain=0.05, v_sigma=0.05)
     cur = structure_bfs_ready(mesh)
@@ -260,7 +273,7 @@ def test_queue_bfs_on_a_larger_broken_mesh(dev):
         cur = structure_pull(cur, 20 * DT)
         for _ in range(20):
             cur = structure_step(cur, DT)
-        for bfs in ("queue", "levels"):
+        for bfs in sorted(BFS_FORMS):
             restart_bfs(cur, make_sim(8, bfs=bfs))
         before = int(cur["nalive"].sum())
         cur = structure_bfs(cur)
@@ -281,4 +294,9 @@ def test_queue_bfs_workspace_checks(dev):
     bad.anchor_class = sim.heap.cls["Spring"]
     with pytest.raises(smmo.SmmoError):
         smmo.smmo_structure_remove_disconnected(sim.heap.h, bad, sim.bfs_work, sim.bfs_levels)
+    bad = smmo.smmo_structure_args.from_buffer_copy(sim.args)
+    bad.bfs_options = 4
+    with pytest.raises(smmo.SmmoError) as e:
+        smmo.smmo_structure_remove_disconnected(sim.heap.h, bad, sim.bfs_work, sim.bfs_levels)
+    assert e.value.status == smmo.SMMO_EINVAL
     assert sim.remove_disconnected() >= 1
