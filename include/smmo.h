@@ -221,16 +221,38 @@ smmo_status smmo_heap_bytes(const smmo_schema *s, uint64_t blocks, uint64_t *byt
 
 /* ---- heap -------------------------------------------------------------- */
 
+/* A caller-supplied device allocator, for heaps created without a buffer:
+ * alloc(bytes, ctx) returns `bytes` bytes of device memory on the current
+ * device, 256-byte aligned, or NULL; release(ptr, bytes, ctx) gives back
+ * what alloc returned.  Both are called on the thread that creates or frees
+ * the heap, never from a kernel or a stream callback. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*release)(void *ptr, size_t bytes, void *ctx);
+    void *ctx;
+} smmo_allocator;
+
+/* Sets the allocator that smmo_alloc_heap() uses when dev_buf is NULL
+ * (process-wide; NULL unsets it).  A heap keeps the allocator it was created
+ * with and releases its buffer through it in smmo_heap_free().  SMMO_EINVAL
+ * if alloc or release is NULL. */
+smmo_status smmo_set_allocator(const smmo_allocator *a);
+
 /* Creates a heap in the caller's device buffer `dev_buf` of `bytes` bytes
- * (256-byte aligned).  M, the number of blocks, is the largest count whose
- * arrays and blocks fit; at most 2^25 - 2.  Enqueues the initialization (all
- * blocks free, Ch.5 sec.5.2.4 "Block Bitmaps") on `stream`.  The schema is
- * frozen.  cfg may be NULL for the defaults.  The buffer must stay allocated
- * until smmo_heap_free().  SMMO_ENOMEM if not even one block fits. */
+ * (256-byte aligned), or, with dev_buf NULL, in `bytes` bytes taken from the
+ * allocator set by smmo_set_allocator() (SMMO_EINVAL if none is set,
+ * SMMO_ENOMEM if it returns NULL).  M, the number of blocks, is the largest
+ * count whose arrays and blocks fit; at most 2^25 - 2.  Enqueues the
+ * initialization (all blocks free, Ch.5 sec.5.2.4 "Block Bitmaps") on
+ * `stream`.  The schema is frozen.  cfg may be NULL for the defaults.  A
+ * caller's buffer must stay allocated until smmo_heap_free().  SMMO_ENOMEM if
+ * not even one block fits. */
 smmo_status smmo_alloc_heap(smmo_schema *s, void *dev_buf, size_t bytes,
                             const smmo_config *cfg, smmo_stream stream, smmo_heap **out);
 
-/* Waits for the heap's work and releases host-side state (not dev_buf). */
+/* Waits for the heap's work and releases host-side state, and the buffer if
+ * the heap took it from an allocator (a caller's dev_buf stays the
+ * caller's). */
 smmo_status smmo_heap_free(smmo_heap *h);
 
 /* ---- SMMO operations ---------------------------------------------------- */

@@ -48,7 +48,7 @@ class DiffSpringSim:
         self.N, self.S = N, S
         self.dt, self.T, self.every = float(dt), int(steps), max(1, int(every))
         self.heap = smmo.Heap(ADJ_CLASSES, blocks=_blocks(N) + _blocks(S) + 8, cfg=cfg)
-        dev = self.heap.buf.device
+        dev = self.heap.dev
         self.dev = dev
 
         def f32(a):

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "smmo_device.hpp"
@@ -844,10 +845,48 @@ smmo_status smmo_heap_bytes(const smmo_schema *s, uint64_t blocks, uint64_t *byt
     return SMMO_OK;
 }
 
+namespace {
+std::mutex allocator_mu;
+smmo_allocator allocator_set{};   // alloc == nullptr: none
+
+smmo_status create_heap(smmo_schema *s, void *dev_buf, size_t bytes, const smmo_config *cfg, smmo_stream stream,
+                        smmo_heap **out);
+} // namespace
+
+smmo_status smmo_set_allocator(const smmo_allocator *a)
+{
+    if (a && (!a->alloc || !a->release)) return fail(SMMO_EINVAL, "allocator: alloc and release must be set");
+    std::lock_guard<std::mutex> lock(allocator_mu);
+    allocator_set = a ? *a : smmo_allocator{};
+    return SMMO_OK;
+}
+
 smmo_status smmo_alloc_heap(smmo_schema *s, void *dev_buf, size_t bytes, const smmo_config *cfg,
                             smmo_stream stream, smmo_heap **out)
 {
-    if (!s || !dev_buf || !out) return fail(SMMO_EINVAL, "NULL argument");
+    if (!s || !out) return fail(SMMO_EINVAL, "NULL argument");
+    if (dev_buf) return create_heap(s, dev_buf, bytes, cfg, stream, out);
+    smmo_allocator a;
+    {
+        std::lock_guard<std::mutex> lock(allocator_mu);
+        a = allocator_set;
+    }
+    if (!a.alloc) return fail(SMMO_EINVAL, "dev_buf is NULL and no allocator is set (smmo_set_allocator)");
+    void *p = a.alloc(bytes, a.ctx);
+    if (!p) return fail(SMMO_ENOMEM, "the allocator returned NULL");
+    const smmo_status st = create_heap(s, p, bytes, cfg, stream, out);
+    if (st) {
+        a.release(p, bytes, a.ctx);
+        return st;
+    }
+    (*out)->owner = a;
+    return SMMO_OK;
+}
+
+namespace {
+smmo_status create_heap(smmo_schema *s, void *dev_buf, size_t bytes, const smmo_config *cfg, smmo_stream stream,
+                        smmo_heap **out)
+{
     if (!s->nclasses) return fail(SMMO_ESTATE, "schema has no classes");
     if (reinterpret_cast<uintptr_t>(dev_buf) & 255) return fail(SMMO_EINVAL, "dev_buf must be 256-byte aligned");
     smmo_config c;
@@ -930,12 +969,14 @@ smmo_status smmo_alloc_heap(smmo_schema *s, void *dev_buf, size_t bytes, const s
     *out = h;
     return SMMO_OK;
 }
+} // namespace
 
 smmo_status smmo_heap_free(smmo_heap *h)
 {
     if (!h) return SMMO_OK;
     if (h->base) (void)hipStreamSynchronize(h->last);
     if (h->host_ctrl) (void)hipHostFree(h->host_ctrl);
+    if (h->base && h->owner.release) h->owner.release(h->base, h->bytes, h->owner.ctx);
     h->base = nullptr;
     delete h;
     return SMMO_OK;

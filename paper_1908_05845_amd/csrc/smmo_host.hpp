@@ -60,6 +60,7 @@ struct smmo_heap {
     smmo::HeapView v{};
     void *base = nullptr;
     size_t bytes = 0;
+    smmo_allocator owner{};            // set when base came from an allocator
     smmo_config cfg{};
     hipStream_t last = nullptr;
     int device = 0;

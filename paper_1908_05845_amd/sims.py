@@ -72,7 +72,7 @@ class GolSim:
         self.W, self.H = W, H
         n = W * H
         self.heap = smmo.Heap(GOL_CLASSES, blocks=3 * _blocks(n) + extra_blocks, cfg=cfg)
-        dev = self.heap.buf.device
+        dev = self.heap.dev
         init = np.ascontiguousarray(init, dtype=np.uint8).reshape(-1)
         ids = torch.arange(n, dtype=torch.int32, device=dev)
         self.cells = self.heap.new("Cell", n, state=torch.from_numpy(init).to(dev), cell_id=ids).clone()
@@ -141,7 +141,7 @@ class SpringPiSim:
         self.N, self.S, self.K, self.D = N, S_all, K, adj.shape[1]
         self.cap, self.more = cap, more
         self.heap = smmo.Heap(spring_pi_classes(K), blocks=_blocks(N) + _blocks(S) + extra_blocks, cfg=cfg)
-        dev = self.heap.buf.device
+        dev = self.heap.dev
         f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
         i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)
         self.overflow = torch.full((max(int(extra.sum()), 1),), -1, dtype=torch.int32, device=dev)
@@ -224,7 +224,7 @@ class GenerationSim:
         self.W, self.H = W, H
         n = W * H
         self.heap = smmo.Heap(GENERATION_CLASSES, blocks=3 * _blocks(n) + extra_blocks, cfg=cfg)
-        dev = self.heap.buf.device
+        dev = self.heap.dev
         init = np.ascontiguousarray(init, dtype=np.uint8).reshape(-1)
         assert init.size == n and init.max(initial=0) <= 1
         ids = torch.arange(n, dtype=torch.int32, device=dev)
@@ -273,7 +273,7 @@ class NbodySim:
         n = int(np.asarray(state["x"]).size)
         self.n = n
         self.heap = smmo.Heap(NBODY_CLASSES, blocks=_blocks(n) + extra_blocks, cfg=cfg)
-        dev = self.heap.buf.device
+        dev = self.heap.dev
 
         def t(a):
             return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
@@ -330,7 +330,7 @@ class SpringSim:
         if blocks is None:
             blocks = _blocks(N) + _blocks(S) + extra_blocks
         self.heap = smmo.Heap(SPRING_CLASSES, blocks=blocks, cfg=cfg)
-        dev = self.heap.buf.device
+        dev = self.heap.dev
 
         def f32(a):
             return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
@@ -431,7 +431,7 @@ class WatorSim:
         n = W * H
         room = n if agent_room is None else agent_room
         self.heap = smmo.Heap(WATOR_CLASSES, blocks=_blocks(n) + 2 * (2 * _blocks(room) + 64), cfg=cfg)
-        dev = self.heap.buf.device
+        dev = self.heap.dev
         self.dev = dev
         ids = torch.arange(n, dtype=torch.int32, device=dev)
         null = torch.full((n,), -1, dtype=torch.int32, device=dev)
@@ -552,7 +552,7 @@ class StructureSim:
         per = [int(((ntype == t) & nalive).sum()) for t in range(3)]
         blocks = sum(_blocks(n) for n in per) + _blocks(int(salive.sum())) + extra_blocks
         self.heap = smmo.Heap(STRUCTURE_CLASSES, blocks=blocks, cfg=cfg)
-        dev = self.heap.buf.device
+        dev = self.heap.dev
         self.dev = dev
         f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
         i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(dev)

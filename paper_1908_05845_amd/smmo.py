@@ -153,7 +153,8 @@ _lib = None
 EXPORTS = [
     "smmo_config_default", "smmo_schema_create", "smmo_schema_free", "smmo_define_class",
     "smmo_define_subclass", "smmo_class_is_a",
-    "smmo_field_id", "smmo_block_bytes", "smmo_heap_bytes", "smmo_alloc_heap", "smmo_heap_free",
+    "smmo_field_id", "smmo_block_bytes", "smmo_heap_bytes", "smmo_set_allocator", "smmo_alloc_heap",
+    "smmo_heap_free",
     "smmo_parallel_new", "smmo_parallel_do", "smmo_destroy", "smmo_gather_soa", "smmo_sync",
     "smmo_heap_stats", "smmo_check_invariants", "smmo_clear_error", "smmo_heap_info",
     "smmo_method_id", "smmo_last_error", "smmo_set_launch", "smmo_defragment", "smmo_coalescing_probe",
@@ -191,6 +192,7 @@ def load_library(path: str = LIB_PATH):
             "smmo_field_id": (S, [P, U32, C.c_char_p, P]),
             "smmo_block_bytes": (S, [P, P]),
             "smmo_heap_bytes": (S, [P, U64, P]),
+            "smmo_set_allocator": (S, [P]),
             "smmo_alloc_heap": (S, [P, P, C.c_size_t, P, P, P]),
             "smmo_heap_free": (S, [P]),
             "smmo_parallel_new": (S, [P, U32, U32, P, U32, P, P]),
@@ -327,6 +329,56 @@ def smmo_heap_bytes(schema, blocks: int) -> int:
     out = C.c_uint64()
     _check(lib, lib.smmo_heap_bytes(schema, blocks, C.byref(out)))
     return out.value
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class smmo_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("ctx", C.c_void_p)]
+
+
+# every allocator ever set: a heap keeps the function pointers it was created
+# with until it is freed, so their ctypes thunks must never be collected
+_allocators = []
+
+
+def smmo_set_allocator(alloc=None, release=None) -> None:
+    """Sets the allocator for heaps created without a buffer: alloc(nbytes)
+    returns a 256-byte aligned device address (int) or 0, release(address,
+    nbytes) gives it back.  alloc=None unsets it."""
+    lib = load_library()
+    if alloc is None:
+        _check(lib, lib.smmo_set_allocator(None))
+        return
+    a = smmo_allocator(ALLOC_FN(lambda n, ctx: alloc(n) or None), RELEASE_FN(lambda ptr, n, ctx: release(ptr, n)),
+                       None)
+    _allocators.append(a)
+    _check(lib, lib.smmo_set_allocator(C.byref(a)))
+
+
+class TorchDeviceAllocator:
+    """Device memory from torch's caching allocator on the current device, as
+    a heap allocator (smmo_set_allocator(a.alloc, a.release)); counts calls."""
+
+    def __init__(self):
+        self.live = {}
+        self.allocs = 0
+        self.releases = 0
+
+    def alloc(self, nbytes: int) -> int:
+        import torch
+
+        t = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        p = (t.data_ptr() + 255) & ~255
+        self.live[p] = t
+        self.allocs += 1
+        return p
+
+    def release(self, ptr: int, nbytes: int) -> None:
+        self.live.pop(ptr, None)
+        self.releases += 1
 
 
 def smmo_alloc_heap(schema, dev_buf, nbytes: int, cfg=None, stream=None):
@@ -490,14 +542,17 @@ class Heap:
     classes: {class name: [(field, dtype, count), ...]} in definition order,
     or {class name: {"parent": name or None, "abstract": bool, "fields": [...]}}
     for a class in a hierarchy (its field list starts with the parent's).
-    Give either `blocks` (heap size in blocks) or `nbytes`.
+    Give either `blocks` (heap size in blocks) or `nbytes`.  With
+    from_allocator the heap's buffer comes from the allocator set by
+    smmo_set_allocator() and goes back to it when the heap is freed.
     """
 
     def __init__(self, classes: dict, blocks: int | None = None, nbytes: int | None = None,
-                 cfg: smmo_config | None = None, device="cuda"):
+                 cfg: smmo_config | None = None, device="cuda", from_allocator: bool = False):
         import torch
 
         self.torch = torch
+        self.dev = torch.device(device)
         self.schema = smmo_schema_create()
         self.cls = {}
         self.fields = {}
@@ -521,10 +576,13 @@ class Heap:
         if nbytes is None:
             nbytes = smmo_heap_bytes(self.schema, blocks)
         self.nbytes = nbytes
-        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
-        base = self.buf.data_ptr()
-        self.base = (base + 255) & ~255
-        self.h = smmo_alloc_heap(self.schema, self.base, nbytes, cfg)
+        if from_allocator:
+            self.buf = None
+            self.h = smmo_alloc_heap(self.schema, None, nbytes, cfg)
+        else:
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            self.base = (self.buf.data_ptr() + 255) & ~255
+            self.h = smmo_alloc_heap(self.schema, self.base, nbytes, cfg)
         self.blocks, self.block_bytes = smmo_heap_info(self.h)
         self._count = torch.zeros(1, dtype=torch.int32, device=device)
 
@@ -535,7 +593,7 @@ class Heap:
         keep = []
         for fname, v in values.items():
             fid, dt, cnt = self.fields[cname][fname]
-            v = t.as_tensor(v, device=self.buf.device)
+            v = t.as_tensor(v, device=self.dev)
             v = v.reshape(-1).contiguous()
             want = getattr(t, _TORCH_DT[dt])
             if v.dtype != want:
@@ -543,7 +601,7 @@ class Heap:
             assert v.numel() == n * cnt, (fname, v.numel(), n, cnt)
             keep.append(v)
             inits.append((fid, v))
-        out = t.empty(max(n, 1), dtype=t.int32, device=self.buf.device)
+        out = t.empty(max(n, 1), dtype=t.int32, device=self.dev)
         smmo_parallel_new(self.h, self.cls[cname], n, inits, out, stream)
         self._keep = keep   # alive until the next call (stream order keeps them valid)
         return out[:n]
@@ -575,9 +633,9 @@ class Heap:
         ids = []
         for fname in names:
             fid, dt, cnt = self.fields[cname][fname]
-            outs.append(t.empty(max(capacity * cnt, 1), dtype=getattr(t, _TORCH_DT[dt]), device=self.buf.device))
+            outs.append(t.empty(max(capacity * cnt, 1), dtype=getattr(t, _TORCH_DT[dt]), device=self.dev))
             ids.append(fid)
-        hd = t.empty(max(capacity, 1), dtype=t.int32, device=self.buf.device)
+        hd = t.empty(max(capacity, 1), dtype=t.int32, device=self.dev)
         smmo_gather_soa(self.h, self.cls[cname], ids, outs, hd, capacity, self._count, stream)
         self.sync()
         n = int(self._count.item())

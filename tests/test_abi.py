@@ -181,3 +181,34 @@ def test_library_refuses_other_sources(lib, tmp_path, monkeypatch):
     h0 = build.source_hash()
     monkeypatch.setattr(build, "CSRC", str(tmp_path))
     assert build.source_hash() != h0
+
+
+def test_allocator_callback_checks(lib):
+    """smmo_alloc_heap without a buffer: refused with no allocator set, and an
+    allocator's failures and the heap set-up's failures are handled on the
+    host (no GPU needed: the set-up fails before any device call)."""
+    s = smmo.smmo_schema_create()
+    smmo.smmo_define_class(s, "A", [("x", "f32", 1)])
+    out = C.c_void_p()
+
+    def alloc_heap(nbytes):   # the call itself, on the null stream (torch's needs a GPU)
+        return lib.smmo_alloc_heap(s, None, nbytes, None, None, C.byref(out))
+
+    keep = smmo.ALLOC_FN(lambda n, c: None)
+    no_release = smmo.smmo_allocator(keep, smmo.RELEASE_FN(), None)   # NULL release
+    assert lib.smmo_set_allocator(C.byref(no_release)) == smmo.SMMO_EINVAL
+    smmo.smmo_set_allocator(None)
+    assert alloc_heap(1 << 20) == smmo.SMMO_EINVAL and "allocator" in smmo.smmo_last_error()
+    calls = []
+    # an allocator that has no memory: ENOMEM, and nothing to release
+    smmo.smmo_set_allocator(lambda n: calls.append(("alloc", n)) or 0, lambda p, n: calls.append(("release", p, n)))
+    assert alloc_heap(1 << 20) == smmo.SMMO_ENOMEM and calls == [("alloc", 1 << 20)]
+    # memory the heap cannot use (misaligned): the set-up fails and the
+    # allocation goes back to the allocator
+    calls.clear()
+    smmo.smmo_set_allocator(lambda n: calls.append(("alloc", n)) or 0x1000010,
+                            lambda p, n: calls.append(("release", p, n)))
+    assert alloc_heap(4096) == smmo.SMMO_EINVAL
+    assert calls == [("alloc", 4096), ("release", 0x1000010, 4096)]
+    smmo.smmo_set_allocator(None)
+    smmo.smmo_schema_free(s)

@@ -459,3 +459,33 @@ def test_blocks_change_class_within_a_launch(dev, variant):
     with pytest.raises(smmo.SmmoError):
         heap.do("A", "test.transmute", smmo.smmo_spawn_args(heap.cls["A"], 1, 0, 1, 1, 0))
     heap.close()
+
+
+def test_heap_from_an_allocator_callback(dev):
+    """A heap created without a buffer takes it from the allocator set by
+    smmo_set_allocator (here torch's caching allocator) and gives it back when
+    it is freed; objects created in it round-trip, and a heap in a caller's
+    buffer does not touch the allocator."""
+    import torch
+
+    ta = smmo.TorchDeviceAllocator()
+    smmo.smmo_set_allocator(ta.alloc, ta.release)
+    try:
+        heap = smmo.Heap({"B": ALL["B"]}, blocks=64, from_allocator=True)
+        assert (ta.allocs, ta.releases, len(ta.live)) == (1, 0, 1)
+        n = 1000
+        heap.new("B", n, key=torch.arange(n, dtype=torch.int32, device=dev),
+                 x=torch.arange(n, dtype=torch.float32, device=dev) * 0.5)
+        g = heap.gather("B")
+        assert g["_count"] == n
+        k, x = g["key"].cpu().numpy(), g["x"].cpu().numpy()
+        order = np.argsort(k)
+        assert np.array_equal(k[order], np.arange(n)) and np.array_equal(x[order], np.arange(n) * 0.5)
+        clean(heap)
+        heap.close()
+        assert (ta.allocs, ta.releases, len(ta.live)) == (1, 1, 0)
+        other = smmo.Heap({"B": ALL["B"]}, blocks=8)
+        other.close()
+        assert (ta.allocs, ta.releases) == (1, 1)
+    finally:
+        smmo.smmo_set_allocator(None)

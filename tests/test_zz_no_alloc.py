@@ -36,7 +36,7 @@ def run_both(state):
     a = StructureSim(state, DT)
     b = StructureSim(state, DT)
     smmo.smmo_structure_remove_disconnected(a.heap.h, a.args, a.bfs_work, a.bfs_levels)
-    lv = torch.full((1,), -7, dtype=torch.int32, device=b.heap.buf.device)
+    lv = torch.full((1,), -7, dtype=torch.int32, device=b.heap.dev)
     smmo.smmo_structure_remove_disconnected_noalloc(b.heap.h, b.args, lv)
     a.heap.sync()
     b.heap.sync()
@@ -65,7 +65,7 @@ def test_no_alloc_bfs_refuses_a_heap_beyond_its_array(dev):
 
     mesh = structure_mesh(6, 4, seed=5)
     sim = StructureSim(mesh, DT, extra_blocks=16400)
-    lv = torch.zeros(1, dtype=torch.int32, device=sim.heap.buf.device)
+    lv = torch.zeros(1, dtype=torch.int32, device=sim.heap.dev)
     with pytest.raises(smmo.SmmoError) as e:
         smmo.smmo_structure_remove_disconnected_noalloc(sim.heap.h, sim.args, lv)
     assert e.value.status == smmo.SMMO_EINVAL
