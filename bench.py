@@ -63,12 +63,19 @@ def parse():
     ap.add_argument("--summarize-trace", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
                     help="compare rocprofv3 --kernel-trace durations of a run of this bench with the "
                          "per-kernel times it printed (BENCH_JSON: its output line); needs no GPU")
+    ap.add_argument("--launch", action="append", default=[], metavar="METHOD=WG,WAVES,GROUP",
+                    help="in the measurements that tune the spring step on a heap of their own (spring_2000, "
+                         "batched), use this launch shape instead of tuning (give spring.force and "
+                         "spring.node_update; for counter passes that must run the shapes an earlier run picked)")
     ap.add_argument("--extra", choices=sorted(STANDALONE_EXTRAS),
                     help="run one of the other measurements alone and print its JSON (for profiling it)")
     ap.add_argument("--graph-steps", type=int, default=50,
                     help="steps per captured HIP graph in the timed region (0 = eager launches)")
     return ap.parse_args()
 
+
+# launch shapes given on the command line (--launch), used instead of tuning
+GIVEN_SHAPES = {}
 
 # the measurements besides the headline that need nothing from it, by the
 # name they have in the output line
@@ -451,6 +458,13 @@ def tune_spring_step(torch, sim):
     heap = sim.heap
     hp, cs, cn = heap.h, heap.cls["Spring"], heap.cls["Node"]
     mf, mn = sim.m_force, sim.m_node
+    if GIVEN_SHAPES:
+        rec = {"kept": "given"}
+        for name, m, c in (("spring.force", mf, cs), ("spring.node_update", mn, cn)):
+            wg, waves, group = GIVEN_SHAPES[name]
+            smmo.smmo_set_launch(hp, m, c, wg, waves, group)
+            rec[name] = {"wg": wg, "waves": waves, "group": group}
+        return rec
     stream = torch.cuda.current_stream().cuda_stream
     frozen = smmo.smmo_spring_args(sim.args.node_class, sim.args.spring_class, 0.0, sim.args.strain_limit,
                                    sim.args.flags)
@@ -1635,6 +1649,12 @@ def main():
     from paper_1908_05845_amd import smmo
 
     smmo.load_library()
+    for spec in args.launch:
+        name, vals = spec.split("=")
+        GIVEN_SHAPES[name] = tuple(int(v) for v in vals.split(","))
+    if GIVEN_SHAPES and set(GIVEN_SHAPES) != {"spring.force", "spring.node_update"}:
+        print("--launch needs spring.force and spring.node_update", file=sys.stderr)
+        sys.exit(2)
     if args.extra:
         print(json.dumps({args.extra: globals()[STANDALONE_EXTRAS[args.extra]](torch)}), flush=True)
         return

@@ -126,7 +126,14 @@ typedef struct {
                                    2: always pack.  Modes 1 and 2 make the
                                    enumeration read every listed block's bitmap
                                    to build the packing plan. */
-    uint32_t reserved[8];
+    uint32_t streaming_loads;   /* spring.force and spring.node_update: load
+                                   the fields each do-all reads once (not the
+                                   gathered ones) with a non-temporal hint.
+                                   0: when the node and spring blocks exceed
+                                   the 256 MB MALL (default; a step's blocks
+                                   that fit in it are reused by the next step);
+                                   1: never; 2: always.  Same results. */
+    uint32_t reserved[7];
 } smmo_config;
 
 typedef struct {

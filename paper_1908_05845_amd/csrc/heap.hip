@@ -897,6 +897,7 @@ smmo_status create_heap(smmo_schema *s, void *dev_buf, size_t bytes, const smmo_
     if (c.block_group != 0 && c.block_group != 1 && c.block_group != 2 && c.block_group != 4)
         return fail(SMMO_EINVAL, "block_group must be 0, 1, 2 or 4");
     if (c.sparse_packing > 2) return fail(SMMO_EINVAL, "sparse_packing must be 0, 1 or 2");
+    if (c.streaming_loads > 2) return fail(SMMO_EINVAL, "streaming_loads must be 0, 1 or 2");
     const uint32_t bb = schema_block_bytes(s);
     // largest M whose layout fits
     uint64_t lo = 0, hi = std::min<uint64_t>(bytes / bb, kMaxBlocks);

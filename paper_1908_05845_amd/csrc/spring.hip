@@ -24,6 +24,17 @@ struct SpringK {
     uint32_t wpg;             // wavefronts per work-group of this launch
 };
 
+// A load of a field that a do-all reads once per object (not one of the
+// gathered fields): with NT it carries the non-temporal hint, so that these
+// lines do not displace the gathered ones (node positions, spring forces,
+// each read by several objects) from the L2 and the MALL.
+template <bool NT, class T>
+__device__ __forceinline__ T stream_ld(const T &r)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(&r);
+    else return r;
+}
+
 // The break decision is integer-valued, so it is evaluated in float32 with a
 // fixed operation order (no contraction): dx, dy; l2 = fma(dx, dx, dy*dy);
 // l = sqrt(l2) (correctly rounded); strain = (l - L0) / L0 (correctly rounded).
@@ -42,7 +53,7 @@ __device__ __forceinline__ bool spring_breaks(float dx, float dy, float L0, floa
 // deletes itself (the thesis's remove_spring followed by destroy).  A
 // wavefront works on U blocks at once: the spring fields of all U blocks are
 // loaded, then all position gathers issued, then the forces computed.
-template <int U>
+template <int U, bool NT>
 __device__ __forceinline__ void spring_force(const HeapView &h, const SpringK &p)
 {
     const uint32_t s = lane_id();
@@ -55,10 +66,10 @@ __device__ __forceinline__ void spring_force(const HeapView &h, const SpringK &p
         // issued before the headers are used
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            a[j] = farr<uint32_t>(h, bid[j], p.s_a)[s];
-            b[j] = farr<uint32_t>(h, bid[j], p.s_b)[s];
-            k[j] = farr<float>(h, bid[j], p.s_k)[s];
-            L0[j] = farr<float>(h, bid[j], p.s_L0)[s];
+            a[j] = stream_ld<NT>(farr<uint32_t>(h, bid[j], p.s_a)[s]);
+            b[j] = stream_ld<NT>(farr<uint32_t>(h, bid[j], p.s_b)[s]);
+            k[j] = stream_ld<NT>(farr<float>(h, bid[j], p.s_k)[s]);
+            L0[j] = stream_ld<NT>(farr<float>(h, bid[j], p.s_L0)[s]);
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
@@ -107,22 +118,23 @@ __device__ __forceinline__ void spring_force(const HeapView &h, const SpringK &p
 // otherwise raise the scalar registers past that), so one grid of 32
 // wavefronts per CU stays resident.  Four blocks per iteration need more
 // registers than that and keep the compiler's allocation.
-template <int U>
+template <int U, bool NT>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spring_force(HeapView h,
                                                                                                  SpringK p)
 {
-    spring_force<U>(h, p);
+    spring_force<U, NT>(h, p);
 }
 
+template <bool NT>
 __global__ __launch_bounds__(1024) void k_spring_force4(HeapView h, SpringK p)
 {
-    spring_force<4>(h, p);
+    spring_force<4, NT>(h, p);
 }
 
 // Node::update: sum the attached springs' forces in slot order (+f if this
 // node is endpoint a, -f if b), then v += F/m dt, x += v dt.  U blocks at
 // once, as in the force kernel.
-template <int U>
+template <int U, bool NT>
 __global__ __launch_bounds__(1024) void k_spring_node(HeapView h, SpringK p)
 {
     const uint32_t s = lane_id();
@@ -135,12 +147,13 @@ __global__ __launch_bounds__(1024) void k_spring_node(HeapView h, SpringK p)
 #pragma unroll
         for (int j = 0; j < U; ++j) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) e[j][q] = farr<uint32_t>(h, bid[j], p.n_adj + q * p.n_adj_stride)[s];
-            m[j] = farr<float>(h, bid[j], p.n_m)[s];
-            x[j] = farr<float>(h, bid[j], p.n_x)[s];
-            y[j] = farr<float>(h, bid[j], p.n_y)[s];
-            vx[j] = farr<float>(h, bid[j], p.n_vx)[s];
-            vy[j] = farr<float>(h, bid[j], p.n_vy)[s];
+            for (int q = 0; q < 8; ++q)
+                e[j][q] = stream_ld<NT>(farr<uint32_t>(h, bid[j], p.n_adj + q * p.n_adj_stride)[s]);
+            m[j] = stream_ld<NT>(farr<float>(h, bid[j], p.n_m)[s]);
+            x[j] = stream_ld<NT>(farr<float>(h, bid[j], p.n_x)[s]);
+            y[j] = stream_ld<NT>(farr<float>(h, bid[j], p.n_y)[s]);
+            vx[j] = stream_ld<NT>(farr<float>(h, bid[j], p.n_vx)[s]);
+            vy[j] = stream_ld<NT>(farr<float>(h, bid[j], p.n_vy)[s]);
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) live[j] = (hd.bm(j) >> s) & 1;
@@ -241,6 +254,25 @@ smmo_status bind_spring(smmo_heap *h, const smmo_spring_args &a, SpringK &k)
 // blocks per wavefront iteration of the spring do-alls unless set otherwise
 constexpr uint32_t kSpringGroup = 1;
 
+// the MALL (Infinity Cache) of an MI355X, in front of HBM
+constexpr uint64_t kMallBytes = 256ull << 20;
+
+// whether the step's once-read fields get the non-temporal hint (the heap's
+// streaming_loads; automatic: when the node and spring blocks exceed the
+// MALL, so that a step's blocks cannot stay in it for the next step anyway)
+bool streaming(const smmo_heap *h, const SpringK &k)
+{
+    if (h->cfg.streaming_loads) return h->cfg.streaming_loads == 2;
+    return (h->ub_blocks[k.node_cls] + h->ub_blocks[k.spring_cls]) * (uint64_t)h->v.block_bytes > kMallBytes;
+}
+
+template <int U, bool NT>
+void launch_force(const LaunchShape &ls, hipStream_t st, const HeapView &v, const SpringK &k)
+{
+    if constexpr (U == 4) hipLaunchKernelGGL(k_spring_force4<NT>, ls.grid, ls.block, 0, st, v, k);
+    else hipLaunchKernelGGL((k_spring_force<U, NT>), ls.grid, ls.block, 0, st, v, k);
+}
+
 template <int Which>
 smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
 {
@@ -255,15 +287,23 @@ smmo_status launch_spring(smmo_heap *h, uint32_t cls, const void *args, hipStrea
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     const LaunchShape ls = method_shape(h, cls, kSpringGroup);
     k.wpg = ls.block.x / 64;
+    const bool nt = Which != 2 && streaming(h, k);
     if (Which == 0) {
-        if (ls.group == 4) hipLaunchKernelGGL(k_spring_force4, ls.grid, ls.block, 0, st, h->v, k);
-        else if (ls.group == 2) hipLaunchKernelGGL(k_spring_force<2>, ls.grid, ls.block, 0, st, h->v, k);
-        else hipLaunchKernelGGL(k_spring_force<1>, ls.grid, ls.block, 0, st, h->v, k);
+        if (ls.group == 4) nt ? launch_force<4, true>(ls, st, h->v, k) : launch_force<4, false>(ls, st, h->v, k);
+        else if (ls.group == 2) nt ? launch_force<2, true>(ls, st, h->v, k) : launch_force<2, false>(ls, st, h->v, k);
+        else nt ? launch_force<1, true>(ls, st, h->v, k) : launch_force<1, false>(ls, st, h->v, k);
     }
     if (Which == 1) {
-        if (ls.group == 4) hipLaunchKernelGGL(k_spring_node<4>, ls.grid, ls.block, 0, st, h->v, k);
-        else if (ls.group == 2) hipLaunchKernelGGL(k_spring_node<2>, ls.grid, ls.block, 0, st, h->v, k);
-        else hipLaunchKernelGGL(k_spring_node<1>, ls.grid, ls.block, 0, st, h->v, k);
+        if (ls.group == 4) {
+            if (nt) hipLaunchKernelGGL((k_spring_node<4, true>), ls.grid, ls.block, 0, st, h->v, k);
+            else hipLaunchKernelGGL((k_spring_node<4, false>), ls.grid, ls.block, 0, st, h->v, k);
+        } else if (ls.group == 2) {
+            if (nt) hipLaunchKernelGGL((k_spring_node<2, true>), ls.grid, ls.block, 0, st, h->v, k);
+            else hipLaunchKernelGGL((k_spring_node<2, false>), ls.grid, ls.block, 0, st, h->v, k);
+        } else {
+            if (nt) hipLaunchKernelGGL((k_spring_node<1, true>), ls.grid, ls.block, 0, st, h->v, k);
+            else hipLaunchKernelGGL((k_spring_node<1, false>), ls.grid, ls.block, 0, st, h->v, k);
+        }
     }
     if (Which == 2) {
         const LaunchShape l1 = method_shape(h, cls);

@@ -45,8 +45,8 @@ class smmo_field_desc(C.Structure):
 class smmo_config(C.Structure):
     _fields_ = [("lookup_retries", C.c_uint32), ("rotation", C.c_uint32), ("coalescing", C.c_uint32),
                 ("bulk_ordered", C.c_uint32), ("spin_limit", C.c_uint32), ("grid_waves", C.c_uint32),
-                ("block_group", C.c_uint32), ("sparse_packing", C.c_uint32),
-                ("reserved", C.c_uint32 * 8)]
+                ("block_group", C.c_uint32), ("sparse_packing", C.c_uint32), ("streaming_loads", C.c_uint32),
+                ("reserved", C.c_uint32 * 7)]
 
 
 class smmo_stats(C.Structure):

@@ -28,20 +28,23 @@ from spring_parity import drift, mesh_restart, same_heap
 pytestmark = pytest.mark.gpu
 
 
-def group_cfg(group):
+def group_cfg(group, streaming=0):
     """Heap configuration whose spring do-alls take `group` blocks per
-    wavefront iteration (0 = the library's default)."""
+    wavefront iteration (0 = the library's default), with the heap's
+    streaming_loads setting (0 automatic, 1 never, 2 always)."""
     cfg = smmo.smmo_config_default()
     cfg.block_group = group
+    cfg.streaming_loads = streaming
     return cfg
 
 
-def run_checked(mesh, dt, limit, steps, group=0, tension_only=False, checks=None, shapes=None, ties=None):
+def run_checked(mesh, dt, limit, steps, group=0, tension_only=False, checks=None, shapes=None, ties=None,
+                streaming=0):
     """The oracle trajectory and the GPU's unrestarted run side by side for
     `steps` steps; restart and same-heap checks at `checks` (default: every
     step).  Returns (springs the oracle broke, springs the GPU run broke,
     GPU sim, oracle state at the end)."""
-    cfg = group_cfg(group)
+    cfg = group_cfg(group, streaming)
 
     def make(state):
         sim = SpringSim(state, dt, limit, cfg=cfg, tension_only=tension_only)
@@ -91,6 +94,34 @@ def test_small_mesh_with_breaking_every_step(dev, group):
     mesh = spring_mesh(40, 30, seed=21, v_sigma=1.0)
     broken, gpu_broken, _, _ = run_checked(mesh, 1e-4, 0.3, 150, group)
     assert broken > 20 and gpu_broken > 20, (broken, gpu_broken)   # the run exercises destruction
+
+
+@pytest.mark.parametrize("group", [1, 2, 4])
+def test_streaming_loads_with_breaking(dev, group):
+    """The spring kernels with the non-temporal hint on their once-read
+    fields (the form heaps beyond the MALL take): restarts against the oracle
+    at every step and the same-heap check, with springs breaking."""
+    print("spring 40x30 breaking, streaming loads, group %d" % group, flush=True)
+    mesh = spring_mesh(40, 30, seed=22, v_sigma=1.0)
+    broken, gpu_broken, _, _ = run_checked(mesh, 1e-4, 0.3, 100, group, streaming=2)
+    assert broken > 0 and gpu_broken > 0, (broken, gpu_broken)
+
+
+def test_streaming_loads_change_no_bit(dev):
+    """A cache hint only: 300 steps of a breaking 120 x 90 mesh with and
+    without it end in the same state, bit for bit."""
+    print("spring 120x90 streaming loads never / always", flush=True)
+    mesh = spring_mesh(120, 90, seed=5, v_sigma=1.0)
+    sims = [SpringSim(mesh, 1e-4, 0.3, cfg=group_cfg(0, st)) for st in (1, 2)]
+    for sim in sims:
+        sim.step(300)
+    a, b = sims[0].read(), sims[1].read()
+    assert int(a["alive"].sum()) < mesh["S"]
+    for key in a:
+        assert np.array_equal(np.asarray(a[key]).view(np.uint8), np.asarray(b[key]).view(np.uint8)), key
+    with pytest.raises(smmo.SmmoError) as e:
+        SpringSim(mesh, 1e-4, 0.3, cfg=group_cfg(0, 3))
+    assert e.value.status == smmo.SMMO_EINVAL
 
 
 @pytest.mark.parametrize("group", [1, 2, 4])
