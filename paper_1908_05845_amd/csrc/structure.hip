@@ -416,9 +416,18 @@ __global__ __launch_bounds__(1024) void k_st_bfs_queue_init(HeapView h, StructK 
                 const uint32_t o = fref<uint32_t>(h, hs[q] & ~kP2, (hs[q] & kP2) ? p.s_p1 : p.s_p2);
                 if (st_valid(h, o)) other[q] = o;
             }
+            // a neighbour's dense index; one beyond the slots (a spring end
+            // in a block the rank pass did not list) is an internal error,
+            // not an index the search may use
             uint32_t o[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) o[q] = other[q] == kNull ? kNull : 64 * rank[other[q] >> 6] + (other[q] & 63);
+            for (int q = 0; q < 3; ++q) {
+                o[q] = kNull;
+                if (other[q] == kNull) continue;
+                const uint64_t di = 64ull * rank[other[q] >> 6] + (other[q] & 63);
+                if (di < cap) o[q] = (uint32_t)di;
+                else raise_error(h, ERR_INTERNAL);
+            }
             nbr[self] = make_uint4(o[0], o[1], o[2], (bid << 6) | s);
         }
         const uint64_t am = __ballot(anchor);
