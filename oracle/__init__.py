@@ -6,6 +6,7 @@ its Python binding) never imports, links or runs it.
 """
 
 from .oracle import (  # noqa: F401
+    set_threads,
     threads,
     build,
     GolWorld,

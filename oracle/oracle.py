@@ -69,6 +69,8 @@ def _load():
             lib.orc_spring_tie_band.argtypes = []
             lib.orc_threads.restype = C.c_int
             lib.orc_threads.argtypes = []
+            lib.orc_set_threads.restype = None
+            lib.orc_set_threads.argtypes = [C.c_int]
             lib.orc_wator_create.restype = P
             lib.orc_wator_create.argtypes = [C.c_int, C.c_int, C.c_uint64, P, P, P, P]
             lib.orc_wator_step.restype = C.c_int
@@ -228,6 +230,11 @@ def _ties(tie, S):
     t = np.ascontiguousarray(tie, dtype=np.int8)
     assert t.size == S
     return t
+
+
+def set_threads(n: int) -> None:
+    """Host threads for the oracle's parallel do-alls from now on."""
+    _load().orc_set_threads(int(n))
 
 
 def threads() -> int:

@@ -638,6 +638,9 @@ int orc_spring_breaks(double xa, double ya, double xb, double yb, double L0, dou
 /* threads the OpenMP do-alls use (reported with CPU timings) */
 int orc_threads(void) { return omp_get_max_threads(); }
 
+/* sets them (n >= 1): the tests compare results at one and several threads */
+void orc_set_threads(int n) { omp_set_num_threads(n < 1 ? 1 : n); }
+
 /* half-width of the tie band (for the tests that count ties) */
 double orc_spring_tie_band(void) { return SP_TIE_STRAIN; }
 
