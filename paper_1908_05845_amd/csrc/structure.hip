@@ -192,82 +192,132 @@ __global__ __launch_bounds__(1024) void k_st_pull(HeapView h, StructK p)
 
 // Spring::force: tension-only Hooke's law; a spring pulled harder than its
 // limit unlinks itself and is deleted.  The stretch and break decisions use
-// one fixed float32 operation order (no contraction).
+// one fixed float32 operation order (no contraction).  A wavefront works on
+// U blocks at once: their fields are loaded before their headers are used,
+// then all endpoint gathers are issued, then the forces computed.
+template <int U>
 __global__ __launch_bounds__(1024) void k_st_force(HeapView h, StructK p)
 {
-    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
+    const uint32_t s = lane_id();
+    for_each_block_heads<U>(h, p.spring_cls, p.wpg, [&](const BlockHeads<U> &hd) {
 #pragma clang fp contract(off)
-        const uint32_t s = lane_id();
-        bool live = (bm >> s) & 1;
-        float fx = 0.f, fy = 0.f;
-        bool brk = false;
-        // the block's own fields for all 64 slots at once (one contiguous run
-        // each), so that they arrive with the endpoint handles
-        uint32_t a = farr<uint32_t>(h, bid, p.s_p1)[s];
-        uint32_t b = farr<uint32_t>(h, bid, p.s_p2)[s];
-        const float k = farr<float>(h, bid, p.s_k)[s], L0 = farr<float>(h, bid, p.s_L0)[s];
-        const float maxf = farr<float>(h, bid, p.s_maxf)[s];
-        if (live) live = st_valid(h, a) && st_valid(h, b);
-        if (!live) a = b = 0;
-        if (live) {
-            const float dx = fref<float>(h, b, p.n_x) - fref<float>(h, a, p.n_x);
-            const float dy = fref<float>(h, b, p.n_y) - fref<float>(h, a, p.n_y);
-            const float dy2 = dy * dy;
-            const float l = __builtin_sqrtf(__builtin_fmaf(dx, dx, dy2));
-            const float d = l - L0;
-            const float F = k * d;
-            const bool stretched = l > L0;
-            brk = stretched && F > maxf;
-            if (stretched && !brk) {
-                const float c = k * d / l;
-                fx = c * dx;
-                fy = c * dy;
+        uint32_t a[U], b[U];
+        float k[U], L0[U], maxf[U];
+        // the blocks' own fields for all 64 slots (one contiguous run each)
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            a[j] = farr<uint32_t>(h, hd.bid[j], p.s_p1)[s];
+            b[j] = farr<uint32_t>(h, hd.bid[j], p.s_p2)[s];
+            k[j] = farr<float>(h, hd.bid[j], p.s_k)[s];
+            L0[j] = farr<float>(h, hd.bid[j], p.s_L0)[s];
+            maxf[j] = farr<float>(h, hd.bid[j], p.s_maxf)[s];
+        }
+        bool live[U];
+        float xa[U], ya[U], xb[U], yb[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            live[j] = (hd.bm(j) >> s) & 1;
+            if (live[j]) live[j] = st_valid(h, a[j]) && st_valid(h, b[j]);
+            if (!live[j]) a[j] = b[j] = 0;
+            xa[j] = ya[j] = xb[j] = yb[j] = 0.f;
+            if (live[j]) {
+                xa[j] = fref<float>(h, a[j], p.n_x);
+                ya[j] = fref<float>(h, a[j], p.n_y);
+                xb[j] = fref<float>(h, b[j], p.n_x);
+                yb[j] = fref<float>(h, b[j], p.n_y);
             }
         }
-        // full-width stores: dead, broken and slack slots get 0
-        farr<float>(h, bid, p.s_fx)[s] = fx;
-        farr<float>(h, bid, p.s_fy)[s] = fy;
-        unlink_and_delete(h, p, bid, s, a, b, brk);
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (!hd.own(j)) continue;   // (uniform over the wavefront)
+            float fx = 0.f, fy = 0.f;
+            bool brk = false;
+            if (live[j]) {
+                const float dx = xb[j] - xa[j];
+                const float dy = yb[j] - ya[j];
+                const float dy2 = dy * dy;
+                const float l = __builtin_sqrtf(__builtin_fmaf(dx, dx, dy2));
+                const float d = l - L0[j];
+                const float F = k[j] * d;
+                const bool stretched = l > L0[j];
+                brk = stretched && F > maxf[j];
+                if (stretched && !brk) {
+                    const float c = k[j] * d / l;
+                    fx = c * dx;
+                    fy = c * dy;
+                }
+            }
+            // full-width stores: dead, broken and slack slots get 0
+            farr<float>(h, hd.bid[j], p.s_fx)[s] = fx;
+            farr<float>(h, hd.bid[j], p.s_fy)[s] = fy;
+            unlink_and_delete(h, p, hd.bid[j], s, a[j], b[j], brk);
+        }
     });
 }
 
-// Node::update: the attached springs' forces in slot order, then v and x
+// Node::update: the attached springs' forces in slot order, then v and x; U
+// blocks at once, as in the force kernel
+template <int U>
 __global__ __launch_bounds__(1024) void k_st_node_update(HeapView h, StructK p)
 {
-    for_each_block(h, p.cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        // the node's slots and own fields for all 64 slots at once (one
-        // contiguous run each), before the gathers that depend on the slots
-        uint32_t hs[3];
+    const uint32_t s = lane_id();
+    for_each_block_heads<U>(h, p.cls, p.wpg, [&](const BlockHeads<U> &hd) {
+        // the nodes' slots and own fields for all 64 slots (one contiguous run
+        // each), before the gathers that depend on the slots
+        uint32_t hs[U][3];
+        float m[U], vx[U], vy[U], x[U], y[U];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) hs[q] = farr<uint32_t>(h, bid, p.n_spr + q * p.n_spr_stride)[s];
-        const float m = farr<float>(h, bid, p.n_m)[s];
-        float vx = farr<float>(h, bid, p.n_vx)[s], vy = farr<float>(h, bid, p.n_vy)[s];
-        float x = farr<float>(h, bid, p.n_x)[s], y = farr<float>(h, bid, p.n_y)[s];
-        if (!((bm >> s) & 1)) return;
-        float Fx = 0.f, Fy = 0.f;
+        for (int j = 0; j < U; ++j) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (hs[q] == kNull) continue;
-            const uint32_t sp = hs[q] & ~kP2;
-            if (!st_valid(h, sp)) continue;
-            const float fx = fref<float>(h, sp, p.s_fx), fy = fref<float>(h, sp, p.s_fy);
-            if (hs[q] & kP2) {
-                Fx -= fx;
-                Fy -= fy;
-            } else {
-                Fx += fx;
-                Fy += fy;
+            for (int q = 0; q < 3; ++q) hs[j][q] = farr<uint32_t>(h, hd.bid[j], p.n_spr + q * p.n_spr_stride)[s];
+            m[j] = farr<float>(h, hd.bid[j], p.n_m)[s];
+            vx[j] = farr<float>(h, hd.bid[j], p.n_vx)[s];
+            vy[j] = farr<float>(h, hd.bid[j], p.n_vy)[s];
+            x[j] = farr<float>(h, hd.bid[j], p.n_x)[s];
+            y[j] = farr<float>(h, hd.bid[j], p.n_y)[s];
+        }
+        // the gathers of all U blocks, live slots only
+        float gx[U][3], gy[U][3];
+        bool use[U][3];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const bool live = (hd.bm(j) >> s) & 1;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                gx[j][q] = gy[j][q] = 0.f;
+                use[j][q] = false;
+                if (!live || hs[j][q] == kNull) continue;
+                const uint32_t sp = hs[j][q] & ~kP2;
+                if (!st_valid(h, sp)) continue;
+                use[j][q] = true;
+                gx[j][q] = fref<float>(h, sp, p.s_fx);
+                gy[j][q] = fref<float>(h, sp, p.s_fy);
             }
         }
-        vx += Fx / m * p.dt;
-        vy += Fy / m * p.dt;
-        x += vx * p.dt;
-        y += vy * p.dt;
-        farr<float>(h, bid, p.n_vx)[s] = vx;
-        farr<float>(h, bid, p.n_vy)[s] = vy;
-        farr<float>(h, bid, p.n_x)[s] = x;
-        farr<float>(h, bid, p.n_y)[s] = y;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (!((hd.bm(j) >> s) & 1)) continue;
+            float Fx = 0.f, Fy = 0.f;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (!use[j][q]) continue;
+                if (hs[j][q] & kP2) {
+                    Fx -= gx[j][q];
+                    Fy -= gy[j][q];
+                } else {
+                    Fx += gx[j][q];
+                    Fy += gy[j][q];
+                }
+            }
+            vx[j] += Fx / m[j] * p.dt;
+            vy[j] += Fy / m[j] * p.dt;
+            x[j] += vx[j] * p.dt;
+            y[j] += vy[j] * p.dt;
+            farr<float>(h, hd.bid[j], p.n_vx)[s] = vx[j];
+            farr<float>(h, hd.bid[j], p.n_vy)[s] = vy[j];
+            farr<float>(h, hd.bid[j], p.n_x)[s] = x[j];
+            farr<float>(h, hd.bid[j], p.n_y)[s] = y[j];
+        }
     });
 }
 
@@ -714,12 +764,23 @@ smmo_status launch_structure(smmo_heap *h, uint32_t cls, const void *args, hipSt
         k.wpg = ls.block.x / 64;
     } else {
         if ((s = ensure_enumerated(h, cls, false, st))) return s;
-        ls = method_shape(h, cls);
+        // the force and node passes take blocks in groups (default one)
+        ls = method_shape(h, cls, W == W_FORCE || W == W_NODE ? 1u : 0u);
+        k.wpg = ls.block.x / 64;
     }
     switch (W) {
     case W_PULL: hipLaunchKernelGGL(k_st_pull, ls.grid, ls.block, 0, st, h->v, k); break;
-    case W_FORCE: hipLaunchKernelGGL(k_st_force, ls.grid, ls.block, 0, st, h->v, k); break;
-    case W_NODE: hipLaunchKernelGGL(k_st_node_update, ls.grid, ls.block, 0, st, h->v, k); break;
+    case W_FORCE:
+        // a group of four blocks takes two at a time here: four need more
+        // registers than a work-group of 1,024 threads leaves (it spills)
+        if (ls.group >= 2) hipLaunchKernelGGL(k_st_force<2>, ls.grid, ls.block, 0, st, h->v, k);
+        else hipLaunchKernelGGL(k_st_force<1>, ls.grid, ls.block, 0, st, h->v, k);
+        break;
+    case W_NODE:
+        if (ls.group == 4) hipLaunchKernelGGL(k_st_node_update<4>, ls.grid, ls.block, 0, st, h->v, k);
+        else if (ls.group == 2) hipLaunchKernelGGL(k_st_node_update<2>, ls.grid, ls.block, 0, st, h->v, k);
+        else hipLaunchKernelGGL(k_st_node_update<1>, ls.grid, ls.block, 0, st, h->v, k);
+        break;
     case W_BFS_INIT: hipLaunchKernelGGL(k_st_bfs_init, ls.grid, ls.block, 0, st, h->v, k); break;
     case W_BFS_VISIT: hipLaunchKernelGGL(k_st_bfs_visit, ls.grid, ls.block, 0, st, h->v, k); break;
     case W_BFS_MARK: hipLaunchKernelGGL(k_st_bfs_mark, ls.grid, ls.block, 0, st, h->v, k); break;

@@ -71,13 +71,18 @@ BFS_FORMS = {"queue": ("queue", 0),
              "levels": ("levels", 0)}
 
 
-def make_sim(batch=8, shapes=None, bfs="queue"):
+def make_sim(batch=8, shapes=None, bfs="queue", class_shapes=None):
+    """A maker of fresh simulations: `shapes` are launch shapes of methods on
+    NodeBase (the BFS family walks), `class_shapes` of (method, class)
+    pairs."""
     mode, options = BFS_FORMS[bfs]
 
     def make(st):
         sim = StructureSim(st, DT, bfs_batch=batch, bfs=mode, bfs_options=options)
         for name, shape in (shapes or {}).items():
             smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), sim.heap.cls["NodeBase"], *shape)
+        for (name, cname), shape in (class_shapes or {}).items():
+            smmo.smmo_set_launch(sim.heap.h, smmo.smmo_method_id(name), sim.heap.cls[cname], *shape)
         return sim
     return make
 
@@ -194,6 +199,18 @@ def test_iterations_phase_by_phase(dev, W, H, seed, batch, bfs):
     assert st.live_objects[c["Spring"]] == int(s["salive"].sum())
     assert sum(st.live_objects[c[n]] for n in ("AnchorNode", "AnchorPullNode", "Node")) == int(s["nalive"].sum())
     assert int(s["nalive"].sum()) < mesh["ntype"].size        # the GPU's own run removed nodes too
+
+
+@pytest.mark.parametrize("group,wg", [(2, 1024), (4, 64), (2, 64)])
+def test_iterations_with_grouped_force_and_node_passes(dev, group, wg):
+    """The force and node passes taking 2 or 4 blocks per wavefront iteration,
+    in work-groups of 64 or 1,024 threads: every phase restarted against the
+    oracle and same-heap checked, with springs breaking and nodes removed."""
+    print("structure 40x16 force/node group %d wg %d" % (group, wg), flush=True)
+    mesh = structure_mesh(40, 16, seed=3, pull_speed=2.0, break_strain=0.02, v_sigma=0.05)
+    cs = {("structure.force", "Spring"): (wg, 0, group), ("structure.node_update", "Node"): (wg, 0, group)}
+    broken, removed, _ = run_checked(mesh, 6, 10, 10, make_sim(8, class_shapes=cs))
+    assert broken > 0 and removed > 0, (broken, removed)
 
 
 @pytest.mark.parametrize("bfs", ["queue", "queue-device-visited", "levels"])
