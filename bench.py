@@ -77,9 +77,10 @@ def parse():
 # launch shapes given on the command line (--launch), used instead of tuning
 GIVEN_SHAPES = {}
 
-# the measurements besides the headline that need nothing from it, by the
-# name they have in the output line
-STANDALONE_EXTRAS = {"copy_bandwidth": "measure_copy_bandwidth", "coalescing": "measure_coalescing",
+# the measurements besides the headline, by the name they have in the output
+# line (batched and adjoint give no ratio to the headline's rate alone)
+STANDALONE_EXTRAS = {"batched": "measure_batched", "adjoint": "measure_adjoint",
+                     "copy_bandwidth": "measure_copy_bandwidth", "coalescing": "measure_coalescing",
                      "allocation": "measure_allocation", "enumeration": "measure_enumeration",
                      "gol": "measure_gol_extra", "gol_16384": "measure_gol_large", "structure": "measure_structure",
                      "generation": "measure_generation", "partial_inlining": "measure_spring_pi",
@@ -556,7 +557,8 @@ def measure_batched(torch, plain_updates_per_s):
     res = {"workload": "256 spring meshes in one heap, node counts log-uniform in [1e3, 6.4e4]",
            "nodes": int(n), "springs_at_start": int(s0), "springs_at_end": int(s1), "steps": T,
            "launch": "one HIP graph of %d steps (%d kernel launches)" % (T, 2 * T),
-           "ms_per_step": ms / T, "updates_per_s": ups, "vs_plain": ups / plain_updates_per_s,
+           "ms_per_step": ms / T, "updates_per_s": ups,
+           "vs_plain": ups / plain_updates_per_s if plain_updates_per_s else None,
            "step_hbm_gbs": step_bytes / (ms * 1e-3 / T) / 1e9, "autotune": tuned,
            "device_error": st1.device_error}
     heap.close()
@@ -671,7 +673,8 @@ def _measure_adjoint(torch, plain_updates_per_s):
                      "replays": 3, "gradients_equal_launched": bool(same)},
            "forward_updates_per_s": T * per_step / (gfm * 1e-3),
            "backward_updates_per_s": T * per_step / (gbm * 1e-3),
-           "backward_vs_plain_updates_per_s": T * per_step / (gbm * 1e-3) / plain_updates_per_s,
+           "backward_vs_plain_updates_per_s": (T * per_step / (gbm * 1e-3) / plain_updates_per_s
+                                               if plain_updates_per_s else None),
            "loss": float(0.5 * (g.double() ** 2).sum().item()), "grad_k_norm": float(np.linalg.norm(gk)),
            "grad_v0_norm": float(np.linalg.norm(gv)), "autotune": tuned}
     sim.heap.close()
@@ -1656,7 +1659,10 @@ def main():
         print("--launch needs spring.force and spring.node_update", file=sys.stderr)
         sys.exit(2)
     if args.extra:
-        print(json.dumps({args.extra: globals()[STANDALONE_EXTRAS[args.extra]](torch)}), flush=True)
+        fn = globals()[STANDALONE_EXTRAS[args.extra]]
+        # the measurements compared with the plain mesh's rate get none alone
+        res = fn(torch, None) if args.extra in ("batched", "adjoint") else fn(torch)
+        print(json.dumps({args.extra: res}), flush=True)
         return
     if args.counter_pass:
         counter_pass(args, torch)

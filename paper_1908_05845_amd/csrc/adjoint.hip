@@ -29,6 +29,7 @@ struct AdjK {
     uint32_t slot;
     uint32_t seed_count;
     const float *seed_x, *seed_y, *seed_vx, *seed_vy;
+    uint32_t wpg;             // wavefronts per work-group of this launch
 };
 
 struct AdjKey {
@@ -62,17 +63,17 @@ __global__ __launch_bounds__(1024) void k_adj_record(HeapView h, AdjK p)
 template <int U>
 __global__ __launch_bounds__(1024) void k_adj_step_node(HeapView h, AdjK p)
 {
-    if (heap_failed(h)) return;
     const uint32_t s = lane_id();
     float *px = p.tape ? plane_ptr(p, 2 * p.slot) : nullptr;
     float *py = p.tape ? plane_ptr(p, 2 * p.slot + 1) : nullptr;
-    for_each_block_group<U>(h, p.node_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *) {
+    for_each_block_heads<U>(h, p.node_cls, p.wpg, [&](const BlockHeads<U> &hd) {
+        const uint32_t *bid = hd.bid;
         uint32_t e[U][8];
         float m[U], x[U], y[U], vx[U], vy[U], Fx[U], Fy[U];
         bool live[U];
+        // the blocks' fields, issued before the headers are used
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            live[j] = (bm[j] >> s) & 1;
 #pragma unroll
             for (int q = 0; q < 8; ++q) e[j][q] = farr<uint32_t>(h, bid[j], p.n_adj + q * p.n_adj_stride)[s];
             m[j] = farr<float>(h, bid[j], p.n_m)[s];
@@ -81,6 +82,8 @@ __global__ __launch_bounds__(1024) void k_adj_step_node(HeapView h, AdjK p)
             vx[j] = farr<float>(h, bid[j], p.n_vx)[s];
             vy[j] = farr<float>(h, bid[j], p.n_vy)[s];
         }
+#pragma unroll
+        for (int j = 0; j < U; ++j) live[j] = (hd.bm(j) >> s) & 1;
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             float gx[8], gy[8];
@@ -185,18 +188,21 @@ __global__ __launch_bounds__(1024) void k_adj_zero(HeapView h, AdjK p)
 // mu = lv + dt lx, w = mu / m, lv = mu.
 __global__ __launch_bounds__(1024) void k_adj_node(HeapView h, AdjK p)
 {
-    for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        if (!((bm >> s) & 1)) return;
+    const uint32_t s = lane_id();
+    for_each_block_heads<1>(h, p.node_cls, p.wpg, [&](const BlockHeads<1> &hd) {
+        const uint32_t bid = hd.bid[0];
+        // the node's own fields (the second part's too) and its slots, issued
+        // before the header is used and before the gathers of the first part
         float lx = farr<float>(h, bid, p.n_lx)[s], ly = farr<float>(h, bid, p.n_ly)[s];
-        // the node's own fields of the second part, loaded before the gathers
-        // of the first
         const float m = farr<float>(h, bid, p.n_m)[s];
         const float lvx = farr<float>(h, bid, p.n_lvx)[s], lvy = farr<float>(h, bid, p.n_lvy)[s];
+        uint32_t e[8];
         if (p.mode & 1u) {
-            uint32_t e[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) e[q] = farr<uint32_t>(h, bid, p.n_adj + q * p.n_adj_stride)[s];
+        }
+        if (!((hd.bm(0) >> s) & 1)) return;
+        if (p.mode & 1u) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 if (e[q] == kNull) continue;
@@ -227,15 +233,16 @@ __global__ __launch_bounds__(1024) void k_adj_node(HeapView h, AdjK p)
 // Spring pass: c = dt K(x_n) g with g = w_a - w_b, and dL/dk += dt (l - L0) u.g
 __global__ __launch_bounds__(1024) void k_adj_spring(HeapView h, AdjK p)
 {
-    if (heap_failed(h)) return;
+    const uint32_t s = lane_id();
     const float *px = plane_ptr(p, 2 * p.slot), *py = plane_ptr(p, 2 * p.slot + 1);
-    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        if (!((bm >> s) & 1)) return;
+    for_each_block_heads<1>(h, p.spring_cls, p.wpg, [&](const BlockHeads<1> &hd) {
+        const uint32_t bid = hd.bid[0];
+        // the spring's own fields, issued before the header is used
         const uint32_t a = farr<uint32_t>(h, bid, p.s_a)[s];
         const uint32_t b = farr<uint32_t>(h, bid, p.s_b)[s];
         const float k = farr<float>(h, bid, p.s_k)[s];
         const float L0 = farr<float>(h, bid, p.s_L0)[s];
+        if (!((hd.bm(0) >> s) & 1)) return;
         const float dx = px[b] - px[a], dy = py[b] - py[a];
         const float l = sqrtf(dx * dx + dy * dy);
         const float ux = dx / l, uy = dy / l;
@@ -326,12 +333,14 @@ smmo_status launch_adj(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     if (Which == W_STEP) {
         const LaunchShape ls = method_shape(h, cls, kStepGroup);
+        k.wpg = ls.block.x / 64;
         if (ls.group == 4) hipLaunchKernelGGL(k_adj_step_node<4>, ls.grid, ls.block, 0, st, h->v, k);
         else if (ls.group == 2) hipLaunchKernelGGL(k_adj_step_node<2>, ls.grid, ls.block, 0, st, h->v, k);
         else hipLaunchKernelGGL(k_adj_step_node<1>, ls.grid, ls.block, 0, st, h->v, k);
         return launched("adjoint kernel");
     }
     const LaunchShape ls = method_shape(h, cls);
+    k.wpg = ls.block.x / 64;
     const dim3 grid = ls.grid, blk = ls.block;
     switch (Which) {
     case W_RECORD: hipLaunchKernelGGL(k_adj_record, grid, blk, 0, st, h->v, k); break;
