@@ -31,6 +31,7 @@ struct GolK {
     int32_t W, H;
     uint32_t c_state, c_count, c_id;   // Cell field offsets
     uint32_t a_id;                     // Alive field offset
+    uint32_t wpg;                      // wavefronts per work-group of this launch
 };
 
 // a Cell handle from the caller's grid array names a block of the heap
@@ -52,13 +53,17 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 {
     const uint32_t s = lane_id();
     bool bad = false;                  // a cell id outside the grid or a handle outside the heap
-    for_each_block_group<U>(h, p.cell_cls, [&](const uint32_t *bid, const uint64_t *bm, const bool *own) {
+    for_each_block_heads<U>(h, p.cell_cls, p.wpg, [&](const BlockHeads<U> &hd) {
+        const uint32_t *bid = hd.bid;
         bool live[U];
         int32_t id[U];
+        // the cell ids, issued before the headers are used
+#pragma unroll
+        for (int j = 0; j < U; ++j) id[j] = farr<int32_t>(h, bid[j], p.c_id)[s];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            live[j] = (bm[j] >> s) & 1;
-            id[j] = live[j] ? farr<int32_t>(h, bid[j], p.c_id)[s] : 0;
+            live[j] = (hd.bm(j) >> s) & 1;
+            if (!live[j]) id[j] = 0;
             if (live[j] && (uint32_t)id[j] >= (uint32_t)(p.W * p.H)) {
                 bad = true;                        // a cell id outside the grid
                 live[j] = false;
@@ -87,7 +92,7 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            if (!own[j]) continue;
+            if (!hd.own(j)) continue;
             int32_t n = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
@@ -128,18 +133,16 @@ __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
 // gets a new Alive object
 __global__ __launch_bounds__(1024) void k_gol_birth(HeapView h, GolK p)
 {
-    for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        bool born = false;
-        int32_t id = 0;
-        if ((bm >> s) & 1) {
-            uint8_t &st = farr<uint8_t>(h, bid, p.c_state)[s];
-            if (st == 0 && farr<int32_t>(h, bid, p.c_count)[s] == 3) {
-                st = 1;
-                born = true;
-                id = farr<int32_t>(h, bid, p.c_id)[s];
-            }
-        }
+    const uint32_t s = lane_id();
+    for_each_block_heads<1>(h, p.cell_cls, p.wpg, [&](const BlockHeads<1> &hd) {
+        const uint32_t bid = hd.bid[0];
+        // the block's fields, issued before the header is used (a block of
+        // another class has no live slot: nothing is born, nothing stored)
+        const uint8_t st = farr<uint8_t>(h, bid, p.c_state)[s];
+        const int32_t n = farr<int32_t>(h, bid, p.c_count)[s];
+        const int32_t id = farr<int32_t>(h, bid, p.c_id)[s];
+        const bool born = ((hd.bm(0) >> s) & 1) && st == 0 && n == 3;
+        if (born) farr<uint8_t>(h, bid, p.c_state)[s] = 1;
         const uint32_t a = wave_allocate(h, p.alive_cls, born);
         if (born && a != kNull) fref<int32_t>(h, a, p.a_id) = id;
     });
@@ -179,6 +182,7 @@ smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     const uint32_t want = Which == 1 ? a.alive_class : a.cell_class;
     if (cls != want) return fail(SMMO_EINVAL, "gol: method runs on a different class");
     const LaunchShape ls = method_shape(h, cls, Which == 0 ? kGolCountGroup : 0);
+    k.wpg = ls.block.x / 64;
     if ((s = ensure_enumerated(h, cls, false, st, Which == 1 && packing_wanted(h, cls, ls)))) return s;
     if (Which == 0) {
         if (ls.group == 4) hipLaunchKernelGGL(k_gol_count<4>, ls.grid, ls.block, 0, st, h->v, k);
