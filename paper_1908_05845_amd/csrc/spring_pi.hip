@@ -25,6 +25,7 @@ struct PiK {
     float dt, limit;
     uint32_t *ovf;
     uint64_t ovf_len;
+    uint32_t wpg;             // wavefronts per work-group of this launch
 };
 
 // slot q of node `node`, or nullptr (and the device error set) if q is not a
@@ -56,14 +57,17 @@ __device__ __forceinline__ bool pi_valid(const HeapView &h, uint32_t handle)
 // operation order, no contraction)
 __global__ __launch_bounds__(1024) void k_pi_force(HeapView h, PiK p)
 {
-    for_each_block(h, p.spring_cls, false, [&](uint32_t bid, uint64_t bm) {
+    const uint32_t s = lane_id();
+    for_each_block_heads<1>(h, p.spring_cls, p.wpg, [&](const BlockHeads<1> &hd) {
 #pragma clang fp contract(off)
-        const uint32_t s = lane_id();
-        bool live = (bm >> s) & 1;
-        // the spring's own fields for all 64 slots at once, with its handles
+        const uint32_t bid = hd.bid[0];
+        // the spring's own fields for all 64 slots at once, with its handles,
+        // issued before the header is used
         uint32_t a = farr<uint32_t>(h, bid, p.s_a)[s];
         uint32_t b = farr<uint32_t>(h, bid, p.s_b)[s];
         const float L0 = farr<float>(h, bid, p.s_L0)[s], k = farr<float>(h, bid, p.s_k)[s];
+        if (!hd.own(0)) return;   // (uniform over the wavefront; stores below are full-width)
+        bool live = (hd.bm(0) >> s) & 1;
         if (live) live = pi_valid(h, a) && pi_valid(h, b);
         if (!live) a = b = 0;
         float fx = 0.f, fy = 0.f;
@@ -121,11 +125,15 @@ constexpr int32_t kLaneSerialSlots = 8;
 // reduction, instead of one lane walking them while the others wait.
 __global__ __launch_bounds__(1024) void k_pi_node(HeapView h, PiK p)
 {
-    for_each_block(h, p.node_cls, false, [&](uint32_t bid, uint64_t bm) {
-        const uint32_t s = lane_id();
-        const bool live = (bm >> s) & 1;
-        const int32_t cap = live ? farr<int32_t>(h, bid, p.n_cap)[s] : 0;
-        const int64_t base = live ? farr<int32_t>(h, bid, p.n_more)[s] : 0;
+    const uint32_t s = lane_id();
+    for_each_block_heads<1>(h, p.node_cls, p.wpg, [&](const BlockHeads<1> &hd) {
+        const uint32_t bid = hd.bid[0];
+        // the slot count and overflow index, issued before the header is used
+        const int32_t cap0 = farr<int32_t>(h, bid, p.n_cap)[s];
+        const int32_t more0 = farr<int32_t>(h, bid, p.n_more)[s];
+        const bool live = (hd.bm(0) >> s) & 1;
+        const int32_t cap = live ? cap0 : 0;
+        const int64_t base = live ? more0 : 0;
         const int32_t extra = cap - (int32_t)p.K;
         float Fx = 0.f, Fy = 0.f;
         if (live) {
@@ -236,6 +244,7 @@ smmo_status launch_spring_pi(smmo_heap *h, uint32_t cls, const void *args, hipSt
     if (cls != want) return fail(SMMO_EINVAL, "spring_pi: method runs on a different class");
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     const LaunchShape ls = method_shape(h, cls);
+    k.wpg = ls.block.x / 64;
     if (Which == 0) hipLaunchKernelGGL(k_pi_force, ls.grid, ls.block, 0, st, h->v, k);
     if (Which == 1) hipLaunchKernelGGL(k_pi_node, ls.grid, ls.block, 0, st, h->v, k);
     if (Which == 2) hipLaunchKernelGGL(k_pi_link, ls.grid, ls.block, 0, st, h->v, k);
