@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--extra", choices=sorted(STANDALONE_EXTRAS),
                     help="run one of the other measurements alone and print its JSON (for profiling it)")
     ap.add_argument("--graph-steps", type=int, default=50,
-                    help="steps per captured HIP graph in the timed region (0 = eager launches)")
+                    help="steps per captured HIP graph in the timed region, at most half the timed steps "
+                         "(0 = eager launches)")
     return ap.parse_args()
 
 
@@ -238,12 +239,17 @@ def bench_spring(args, torch):
     done = eager_n                      # real steps taken so far
     # a HIP graph of G steps: the method kernels read the block lists and
     # their lengths on the device, so a captured step is the same work as a
-    # launched one, without the host launch cost.  The timed region uses the
-    # graph if its replays are faster than launched steps (measured here on
-    # 4 G steps, counted as warm-up), else launches the steps.
-    G = args.graph_steps
+    # launched one, without the host launch cost.  G is at most half the
+    # timed steps, so that each timed half is whole replays (a 20-step window
+    # replays two graphs of 10 steps).  The timed region uses the graph if
+    # one replay is faster than G steps launched from an idle queue, as a
+    # timed half starts (best of four of each, counted as warm-up; the long
+    # launched run above hides the host's launch cost behind queued work),
+    # else launches the steps.
+    G = min(args.graph_steps, max(1, steps // 2)) if args.graph_steps > 0 else 0
     graph = None
     graph_ms = None
+    window_eager_ms = None
     if G > 0:
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
@@ -253,17 +259,25 @@ def bench_spring(args, torch):
         step()          # one launched step: the heap's last stream is ours again
         counted(1)
         done += 1
-        torch.cuda.synchronize()
-        eg = events(torch, 2)
-        eg[0].record()
-        for _ in range(4):
-            graph.replay()
-        eg[1].record()
-        torch.cuda.synchronize()
-        counted(4 * G)
-        done += 4 * G
-        graph_ms = eg[0].elapsed_time(eg[1]) / (4 * G)
-        if graph_ms >= eager_ms:
+
+        def window_ms(run):
+            torch.cuda.synchronize()
+            eg = events(torch, 2)
+            eg[0].record()
+            run()
+            eg[1].record()
+            torch.cuda.synchronize()
+            return eg[0].elapsed_time(eg[1]) / G
+
+        def launched():
+            for _ in range(G):
+                step()
+
+        graph_ms = min(window_ms(graph.replay) for _ in range(4))
+        window_eager_ms = min(window_ms(launched) for _ in range(4))
+        counted(8 * G)
+        done += 8 * G
+        if graph_ms >= window_eager_ms:
             graph = None
 
     def advance(n):
@@ -327,6 +341,9 @@ def bench_spring(args, torch):
     seg_ms = []      # five event-bounded segments per half (whole graph replays)
     seg_steps = []
     for part, n in enumerate((half, steps - half)):
+        # the segment events exist before the timed region: creating one
+        # inside it would hold back the host's launches
+        seg_ev = events(torch, 5)
         torch.cuda.synchronize()
         e0, e1 = events(torch, 2)
         bounds = []
@@ -338,7 +355,7 @@ def bench_spring(args, torch):
             for r in range(reps):
                 graph.replay()
                 if r + 1 in cut:
-                    ev = events(torch, 1)[0]
+                    ev = seg_ev[len(bounds)]
                     ev.record()
                     bounds.append((ev, (r + 1) * G))
             for _ in range(n % G):
@@ -348,7 +365,7 @@ def bench_spring(args, torch):
             for i in range(n):
                 step()
                 if i + 1 in cut:
-                    ev = events(torch, 1)[0]
+                    ev = seg_ev[len(bounds)]
                     ev.record()
                     bounds.append((ev, i + 1))
         e1.record()
@@ -420,7 +437,7 @@ def bench_spring(args, torch):
                          "after_steps": done + half, **window},
         "launch": {"mode": "hip graph of %d steps" % G if graph is not None else "launched steps",
                    "timed_host_wall_s": wall, "eager_ms_per_step": eager_ms,
-                   "graph_ms_per_step": graph_ms,
+                   "graph_ms_per_step": graph_ms, "window_eager_ms_per_step": window_eager_ms,
                    "eager_host_ms_per_step": eager_wall / max(eager_n, 1) * 1e3},
         "device_error": st2.device_error,
     }
