@@ -241,11 +241,13 @@ def bench_spring(args, torch):
     # their lengths on the device, so a captured step is the same work as a
     # launched one, without the host launch cost.  G is at most half the
     # timed steps, so that each timed half is whole replays (a 20-step window
-    # replays two graphs of 10 steps).  The timed region uses the graph if
-    # one replay is faster than G steps launched from an idle queue, as a
-    # timed half starts (best of four of each, counted as warm-up; the long
-    # launched run above hides the host's launch cost behind queued work),
-    # else launches the steps.
+    # replays two graphs of 10 steps).  The timed region uses the graph if it
+    # is faster for windows of the timed halves' length: for halves of at
+    # least four graphs, four replays against the long launched run above
+    # (whose rate is the host's launch rate once the queue is full); for
+    # shorter halves, one replay against G steps launched from an idle queue,
+    # as a timed half starts (best of four of each).  The probes are counted
+    # as warm-up.
     G = min(args.graph_steps, max(1, steps // 2)) if args.graph_steps > 0 else 0
     graph = None
     graph_ms = None
@@ -260,24 +262,32 @@ def bench_spring(args, torch):
         counted(1)
         done += 1
 
-        def window_ms(run):
+        def window_ms(run, reps=1):
             torch.cuda.synchronize()
             eg = events(torch, 2)
             eg[0].record()
-            run()
+            for _ in range(reps):
+                run()
             eg[1].record()
             torch.cuda.synchronize()
-            return eg[0].elapsed_time(eg[1]) / G
+            return eg[0].elapsed_time(eg[1]) / (G * reps)
 
         def launched():
             for _ in range(G):
                 step()
 
-        graph_ms = min(window_ms(graph.replay) for _ in range(4))
-        window_eager_ms = min(window_ms(launched) for _ in range(4))
-        counted(8 * G)
-        done += 8 * G
-        if graph_ms >= window_eager_ms:
+        if steps // 2 >= 4 * G:
+            graph_ms = window_ms(graph.replay, 4)
+            counted(4 * G)
+            done += 4 * G
+            rival = eager_ms
+        else:
+            graph_ms = min(window_ms(graph.replay) for _ in range(4))
+            window_eager_ms = min(window_ms(launched) for _ in range(4))
+            counted(8 * G)
+            done += 8 * G
+            rival = window_eager_ms
+        if graph_ms >= rival:
             graph = None
 
     def advance(n):
