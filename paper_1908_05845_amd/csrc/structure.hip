@@ -850,13 +850,14 @@ smmo_status smmo_structure_remove_disconnected(smmo_heap *h, const smmo_structur
 // ---- the same BFS without a caller workspace ------------------------------
 // The workspace (queue, block positions, visited bits and neighbour table)
 // lives in `scratch`, a device array of this library: each GPU the library
-// runs on holds one copy, 21 MB, until the process ends.  It serves heaps of up to kScratchBlocks blocks.  In host
-// code the array's name is not a device address; its address on a device is
-// taken once per device (hipGetSymbolAddress, with that device current) and
-// kept in scratch_ptr, which is what the kernels are given.  All calls on one
-// GPU share the array and it keeps the last call's contents: the queue's
-// header is cleared by a kernel at the start of every call (the rest is
-// written before it is read), and calls that overlap on one GPU race.
+// runs on holds one copy, 21 MB, until the process ends.  It serves heaps of
+// up to kScratchBlocks blocks.  In host code the array's name is not a
+// device address; its address on a device is taken once per device
+// (hipGetSymbolAddress, with that device current) and kept in scratch_ptr,
+// which is what the kernels are given.  All calls on one GPU share the array
+// and it keeps the last call's contents: the queue's header is cleared by a
+// kernel at the start of every call (the rest is written before it is read),
+// and calls that overlap on one GPU race.
 constexpr uint32_t kScratchBlocks = 16384;
 constexpr uint64_t kScratchWords = bfs_layout(64ull * kScratchBlocks, kScratchBlocks).words;
 static __device__ __align__(256) uint32_t scratch[kScratchWords];
