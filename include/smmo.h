@@ -35,7 +35,12 @@
  *     smmo_check_invariants() and smmo_heap_free(), which wait.  All calls on
  *     one heap must be ordered on the host and on the device (one stream, or
  *     streams joined by events); two calls on one heap that run at the same
- *     time on the device race.
+ *     time on the device race, with one exception: two parallel_do calls on
+ *     classes of different families may run at the same time (the device
+ *     allocator is safe under concurrency) if neither deletes objects of
+ *     the class the other walks, a class that gets new objects from one is
+ *     walked by the other only through a snapshot (smmo_snapshot), and
+ *     the methods' reads and writes of fields do not conflict.
  *   - Device pointers are addresses in device memory of the GPU the heap is
  *     on.  The caller owns every buffer it passes and keeps it alive until the
  *     work that uses it has completed.  libsmmo allocates no device memory:
@@ -283,6 +288,21 @@ smmo_status smmo_parallel_new(smmo_heap *h, uint32_t class_id, uint32_t n,
  * SMMO_EINVAL if the class lacks one. */
 smmo_status smmo_parallel_do(smmo_heap *h, uint32_t class_id, uint32_t method_id,
                              const void *args, size_t args_bytes, smmo_stream stream);
+
+/* Takes the iteration snapshot of class `class_id` and its concrete
+ * descendants now, in `stream` order, for the next parallel_do on the class
+ * (the enumeration of Ch.5 sec.5.2.7 with its copy of the allocation
+ * bitmaps, moved ahead of the launch).  That parallel_do runs the method on
+ * the objects alive at the snapshot, enumerates nothing, and may run on
+ * another stream while other work creates objects of the class: objects
+ * created after the snapshot are neither visited nor read.  Between the
+ * snapshot and that parallel_do, device code may not delete objects of the
+ * class (a do-all on another class that does breaks the snapshot; nothing
+ * checks this).  smmo_destroy, smmo_gather_soa or smmo_defragment of the
+ * class in between, or any other enumeration of it, drops the snapshot: the
+ * parallel_do then takes its own at its start.  Errors as
+ * smmo_parallel_do's: SMMO_EINVAL for a bad heap or class. */
+smmo_status smmo_snapshot(smmo_heap *h, uint32_t class_id, smmo_stream stream);
 
 /* destroy (Ch.5 sec.5.1.1; deallocation as in sec.5.2.6 and sec.5.4): deletes
  * the n objects whose handles are in the device array `handles`.  Each must

@@ -233,6 +233,7 @@ smmo_status smmo_defragment(smmo_heap *h, uint32_t class_id, uint32_t n, uint32_
     hipLaunchKernelGGL(k_defrag_reset, dim3(1), dim3(64), 0, st, h->v, 1u);
     if ((s = heap_launch_check("k_defrag_reset"))) return s;
     h->last = st;
+    h->snap_pending &= ~(1u << class_id);   // its objects move: a snapshot of the class no longer holds
     uint32_t passes = 0;
     while (passes < max_passes) {
         if ((s = ensure_enumerated(h, class_id, false, st))) return s;

@@ -92,6 +92,8 @@ __global__ __launch_bounds__(1024) void k_gen_birth(HeapView h, GenK p)
 {
     for_each_block(h, p.cell_cls, false, [&](uint32_t bid, uint64_t bm) {
         const uint32_t s = lane_id();
+        // a view of the Alive class's active blocks, loaded beside the fields
+        const ActiveView view = active_view(h, p.alive_cls);
         bool born = false;
         int32_t id = 0;
         if ((bm >> s) & 1) {
@@ -102,7 +104,7 @@ __global__ __launch_bounds__(1024) void k_gen_birth(HeapView h, GenK p)
                 id = farr<int32_t>(h, bid, p.c_id)[s];
             }
         }
-        const uint32_t a = wave_allocate(h, p.alive_cls, born);
+        const uint32_t a = wave_allocate(h, p.alive_cls, born, &view);
         if (born && a != kNull) {
             fref<int32_t>(h, a, p.a_id) = id;
             fref<int32_t>(h, a, p.a_left) = 0;

@@ -139,88 +139,110 @@ __global__ void k_heap_init(HeapView h)
 }
 
 // Enumeration pre-pass (sec.5.2.7 with Alg. indices of sec.5.3.1): compact
-// the set bits of allocated[cls] into R.  Wavefront w owns the 64 level-0
-// containers summarized by bit-container w of level 1 and skips those whose
-// summary bit is clear; each wavefront reserves its output range with one
-// atomic add (R is therefore ordered within a wavefront's range only).  The
-// last wavefront to finish publishes the length and resets the counters, so
-// the pass needs no separate reset launch and can be captured in a graph.
+// the set bits of allocated[cls] into R.  Work-group g owns level-0
+// containers 1024 g .. 1024 g + 1023 (thread t loads container 1024 g + t,
+// in the same batch of loads as the error word: the level-1 summary would
+// only add a dependent load, and reading every container costs 8 bytes per
+// 64 blocks).  Each group reserves its ranges of R (dense blocks at the
+// front, sparse ones at the back) and counts itself finished with one 64-bit
+// atomic add on the class's packed counter, so R is ordered within a
+// group's ranges only.  The group whose add finds every other group
+// finished knows the totals: it publishes the lengths and zeroes the
+// counter, so the pass needs no reset launch and can be captured in a
+// graph.  (The lengths are read by later launches only, after every group's
+// appends have been performed.)
+constexpr uint64_t kPackMask = (1ull << 25) - 1;
+static_assert(kMaxBlocks <= kPackMask, "block counts must fit the packed enumeration counter");
+static_assert((kMaxBlocks / 64 + 1024) / 1024 < (1u << 14), "work-group counts must fit the packed enumeration counter");
+
 __global__ __launch_bounds__(1024) void k_enumerate(HeapView h, uint32_t cls, uint32_t snapshot, uint32_t split)
 {
-    const uint32_t w = global_wave_id();
     const uint32_t lane = lane_id();
+    const uint32_t wig = threadIdx.x >> 6;
     const uint32_t n0 = h.lvl_n[0];
-    const uint32_t cidx = w * 64 + lane;
-    uint64_t c = 0;
-    if (!heap_failed(h) && w * 64 < n0) {
-        const uint64_t summ = h.nlev > 1 ? ald(h.bm_word(bm_alloc(cls), 1, w)) : 1ull;
-        if (cidx < n0 && ((summ >> lane) & 1)) c = ald(h.bm_word(bm_alloc(cls), 0, cidx));
-    }
+    const uint32_t cidx = blockIdx.x * 1024 + threadIdx.x;
+    const uint32_t err = ald32(h.ctrl + CTRL_ERR);
+    uint64_t c = cidx < n0 ? ald(h.bm_word(bm_alloc(cls), 0, cidx)) : 0ull;
+    if (err) c = 0;       // a failed heap lists nothing
     // The packing plan (split): blocks with more than 32 live objects are
     // dense.  Without it every block counts as dense.  No wavefront changes
-    // a bitmap while this kernel runs, so plain loads are enough; a lane
-    // keeps four of its blocks' bitmap loads in flight.
+    // a bitmap while this kernel runs, so plain loads are enough.  The
+    // per-block work (the snapshot copy, the plan) is spread over the
+    // work-group: container j of the group's 1,024 goes to wave j mod 16,
+    // one block per lane, so a lane issues its (at most 64) bitmap loads
+    // eight at a time, independent of each other, instead of following one
+    // container's set bits in a chain of dependent loads.
+    __shared__ uint64_t s_c[1024], s_d[1024];
+    __shared__ uint32_t s_nd[16], s_ns[16];
+    __shared__ uint64_t s_old;
     uint64_t dense = c;
     if (snapshot || split) {
-        dense = 0;
-        const uint64_t *abm = h.alloc_bm + (uint64_t)cidx * 64;
-        uint64_t *ibm = h.iter_bm + (uint64_t)cidx * 64;
-        for (uint64_t cc = c; cc;) {
-            uint32_t b[4];
-            uint64_t bm[4];
+        s_c[threadIdx.x] = c;
+        s_d[threadIdx.x] = 0;
+        __syncthreads();
+        const uint64_t gbase = (uint64_t)blockIdx.x * 1024 * 64;   // first block of the group
+        const uint64_t *abm = h.alloc_bm + gbase;
+        uint64_t *ibm = h.iter_bm + gbase;
+        for (uint32_t j0 = wig; j0 < 1024; j0 += 128) {
+            uint64_t cw[8], bm[8];
+            uint64_t any = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                b[k] = cc ? (uint32_t)(__ffsll((unsigned long long)cc) - 1) : 64u;
-                cc &= cc - 1;
+            for (int u = 0; u < 8; ++u) {
+                cw[u] = s_c[j0 + 16 * u];
+                any |= cw[u];
             }
+            if (!any) continue;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) bm[k] = b[k] < 64 ? abm[b[k]] : 0ull;
+            for (int u = 0; u < 8; ++u)
+                bm[u] = ((cw[u] >> lane) & 1) ? abm[(uint64_t)(j0 + 16 * u) * 64 + lane] : 0ull;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (b[k] == 64) continue;
-                if (snapshot) ibm[b[k]] = bm[k];
-                if (!split || __popcll(bm[k]) > 32) dense |= 1ull << b[k];
+            for (int u = 0; u < 8; ++u) {
+                const bool in = (cw[u] >> lane) & 1;
+                if (snapshot && in) ibm[(uint64_t)(j0 + 16 * u) * 64 + lane] = bm[u];
+                const uint64_t d = __ballot(in && (!split || __popcll(bm[u]) > 32));
+                if (lane == 0) s_d[j0 + 16 * u] = d;
             }
         }
+        __syncthreads();
+        dense = s_d[threadIdx.x];
     }
     const uint32_t nd = (uint32_t)__popcll(dense), ns = (uint32_t)__popcll(c) - nd;
     const uint32_t incl_d = wave_incl_scan(nd), incl_s = wave_incl_scan(ns);
-    const uint32_t tot_d = __shfl(incl_d, 63), tot_s = __shfl(incl_s, 63);
-    uint32_t base_d = 0, base_s = 0;
-    if (lane == 0) {
-        if (tot_d)
-            base_d = __hip_atomic_fetch_add(h.ctrl + CTRL_RCOUNT + cls, tot_d, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-        if (tot_s)
-            base_s = __hip_atomic_fetch_add(h.ctrl + CTRL_RSCOUNT + cls, tot_s, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 63) {
+        s_nd[wig] = incl_d;
+        s_ns[wig] = incl_s;
     }
-    base_d = __shfl(base_d, 0);
-    base_s = __shfl(base_s, 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t td = 0, ts = 0;
+        for (int k = 0; k < 16; ++k) {
+            td += s_nd[k];
+            ts += s_ns[k];
+        }
+        const uint64_t add = (uint64_t)td | ((uint64_t)ts << 25) | (1ull << 50);
+        uint64_t *pack = reinterpret_cast<uint64_t *>(h.ctrl + CTRL_RPACK + 2 * cls);
+        const uint64_t old = __hip_atomic_fetch_add(pack, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_old = old;
+        if ((old >> 50) == gridDim.x - 1) {
+            const uint64_t tot = old + add;
+            const uint32_t rd = (uint32_t)(tot & kPackMask), rs = (uint32_t)((tot >> 25) & kPackMask);
+            __hip_atomic_store(h.ctrl + CTRL_RFINAL + cls, rd + rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(h.ctrl + CTRL_RSFINAL + cls, rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(pack, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    const uint64_t old = s_old;
+    uint32_t kd = (uint32_t)(old & kPackMask) + incl_d - nd, ks = (uint32_t)((old >> 25) & kPackMask) + incl_s - ns;
+    for (uint32_t k = 0; k < wig; ++k) {      // the ranges of the group's earlier wavefronts
+        kd += s_nd[k];
+        ks += s_ns[k];
+    }
     uint32_t *R = h.R + (uint64_t)cls * h.M;
-    uint32_t kd = base_d + incl_d - nd, ks = base_s + incl_s - ns;
     for (; c; c &= c - 1) {
         const uint32_t b = (uint32_t)(__ffsll((unsigned long long)c) - 1);
         if ((dense >> b) & 1) R[kd++] = cidx * 64 + b;
         else R[h.M - 1 - ks++] = cidx * 64 + b;
-    }
-    // Completion is counted per work-group: after the barrier every
-    // wavefront of the group has had its list appends performed (their
-    // results were used), and one atomic per group tells the last group to
-    // publish the lengths.  (One atomic per wavefront on one word serialized
-    // at memory: 4,096 of them in a heap of 2^24 blocks.)
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t d = __hip_atomic_fetch_add(h.ctrl + CTRL_RDONE + cls, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        if (d == gridDim.x - 1) {
-            const uint32_t rd = ald32(h.ctrl + CTRL_RCOUNT + cls), rs = ald32(h.ctrl + CTRL_RSCOUNT + cls);
-            __hip_atomic_store(h.ctrl + CTRL_RFINAL + cls, rd + rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(h.ctrl + CTRL_RSFINAL + cls, rs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(h.ctrl + CTRL_RCOUNT + cls, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(h.ctrl + CTRL_RSCOUNT + cls, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(h.ctrl + CTRL_RDONE + cls, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
     }
 }
 
@@ -639,6 +661,8 @@ constexpr uint32_t kDirectMaxBlocks = 8192;
 smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st, bool split,
                               bool allow_direct)
 {
+    // a do-all that uses a snapshot from smmo_snapshot walks that list as it is
+    if ((h->v.snap >> cls) & 1) return SMMO_OK;
     if (!snapshot && (h->rstate[cls] == R_SPLIT || (h->rstate[cls] == R_VALID && !split))) return SMMO_OK;
     // A walk that needs neither the iteration snapshot nor the packing plan
     // reads nothing of R but its entries; on a small heap the walk over all
@@ -650,6 +674,7 @@ smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStre
         return SMMO_OK;
     }
     h->v.direct &= ~(1u << cls);
+    h->snap_pending &= ~(1u << cls);     // the list is rebuilt: a snapshot taken before is gone
     const uint32_t nwaves = (h->v.lvl_n[0] + 63) / 64;
     const uint32_t grid = (nwaves + 15) / 16;
     hipLaunchKernelGGL(k_enumerate, dim3(grid), dim3(1024), 0, st, h->v, cls, snapshot ? 1u : 0u,
@@ -1041,20 +1066,41 @@ smmo_status smmo_parallel_do(smmo_heap *h, uint32_t class_id, uint32_t method_id
     // the class and its descendants: one launch per concrete class, or one
     // for the whole family where the method covers it
     const uint32_t fam = (m.flags & kFamilyLaunch) ? 1u << class_id : class_family(h->schema, class_id);
-    for (uint32_t c = 0; c < h->schema->nclasses; ++c) {
+    // snapshots that smmo_snapshot took of the walked classes are used here,
+    // once
+    const uint32_t snap = h->snap_pending & class_family(h->schema, class_id);
+    h->v.snap = snap;
+    for (uint32_t c = 0; c < h->schema->nclasses && !s; ++c) {
         if ((m.flags & kFamilyLaunch) && c == class_id) {
             h->cur_method = method_id;
             s = m.launch(h, c, args, st);
             h->cur_method = 0xFFFFFFFFu;
-            if (s) return s;
             continue;
         }
         if (!((fam >> c) & 1) || class_abstract(h->schema, c)) continue;
         h->cur_method = method_id;
         s = m.launch(h, c, args, st);
         h->cur_method = 0xFFFFFFFFu;
-        if (s) return s;
     }
+    h->v.snap = 0;
+    h->snap_pending &= ~snap;
+    if (s) return s;
+    h->last = st;
+    return SMMO_OK;
+}
+
+smmo_status smmo_snapshot(smmo_heap *h, uint32_t class_id, smmo_stream stream)
+{
+    smmo_status s = check_class(h, class_id);
+    if (s) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t fam = class_family(h->schema, class_id);
+    for (uint32_t c = 0; c < h->schema->nclasses; ++c) {
+        if (!((fam >> c) & 1) || class_abstract(h->schema, c)) continue;
+        // with the packing plan whenever a packed do-all may ask for it
+        if ((s = ensure_enumerated(h, c, true, st, h->cfg.sparse_packing != 0, false))) return s;
+    }
+    h->snap_pending |= fam;
     h->last = st;
     return SMMO_OK;
 }
@@ -1086,6 +1132,7 @@ smmo_status smmo_destroy(smmo_heap *h, uint32_t class_id, const uint32_t *handle
     if (n == 0) return SMMO_OK;
     if (!handles) return fail(SMMO_EINVAL, "handles is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    h->snap_pending &= ~(1u << class_id);   // a snapshot would still list the deleted objects
     const uint32_t grid = (uint32_t)(((uint64_t)n + 255) / 256);
     hipLaunchKernelGGL(k_destroy, dim3(grid), dim3(256), 0, st, h->v, class_id, handles, n);
     if ((s = launch_check("k_destroy"))) return s;
@@ -1108,6 +1155,7 @@ smmo_status smmo_gather_soa(smmo_heap *h, uint32_t class_id, const uint32_t *fie
     if ((s = build_fieldset(h, class_id, field_ids, nfields, const_cast<const void *const *>(out_ptrs), fs)))
         return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    h->snap_pending &= ~(1u << class_id);
     if ((s = ensure_enumerated(h, class_id, false, st))) return s;
     h->cur_method = 0xFFFFFFFFu;
     const LaunchShape ls = method_shape(h, class_id);

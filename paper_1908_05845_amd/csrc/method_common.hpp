@@ -22,11 +22,13 @@ __device__ __forceinline__ uint32_t xcd_logical_wg()
     return x * per + (x < rem ? x : rem) + k;
 }
 
-__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+
+// The bitmaps a walk over class cls reads: the iteration bitmaps where the
+// walk asks for the snapshot or the launch uses one that smmo_snapshot took
+// before it (HeapView::snap), else the allocation bitmaps.
+__device__ __forceinline__ const uint64_t *walk_bitmaps(const HeapView &h, uint32_t cls, bool snapshot)
 {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
+    return snapshot || ((h.snap >> cls) & 1) ? h.iter_bm : h.alloc_bm;
 }
 
 // Calls f(bid, bitmap) for every block of class `cls` in R, one wavefront per
@@ -35,7 +37,8 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v)
 // since R was built has a different type and is skipped, so R may be a
 // superset of the class's blocks.  bitmap = the iteration bitmap (snapshot of
 // the allocation bitmap taken by the enumeration) or the allocation bitmap,
-// which is the same as long as the method creates no object of its own class.
+// as walk_bitmaps picks; the two are the same as long as nothing creates
+// objects of the class after the snapshot.
 // Within one launch a block's type and (outside snapshot mode) its bitmap
 // change only through the wavefront that processes it, so plain loads are
 // enough.  The next R entry is fetched one iteration ahead.
@@ -57,7 +60,7 @@ __device__ __forceinline__ void for_each_block(const HeapView &h, uint32_t cls, 
         const uint32_t in = i + nw;
         const uint32_t bnext = __builtin_amdgcn_readfirstlane(in < r ? L.at(in) : 0u);
         const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
-        const uint64_t bm = uniform64(snapshot ? h.iter_bm[bid] : h.alloc_bm[bid]);
+        const uint64_t bm = uniform64(walk_bitmaps(h, cls, snapshot)[bid]);
         if (t == cls) f(bid, bm);
         if (in >= r) break;
         i = in;
@@ -115,7 +118,7 @@ __device__ __forceinline__ void for_each_block_heads(const HeapView &h, uint32_t
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             hd.type[j] = __builtin_amdgcn_readfirstlane(h.type[hd.bid[j]]);
-            hd.raw[j] = uniform64(h.alloc_bm[hd.bid[j]]);
+            hd.raw[j] = uniform64(walk_bitmaps(h, cls, false)[hd.bid[j]]);
         }
         f(hd);
     }
@@ -162,7 +165,7 @@ __device__ __forceinline__ void for_each_block_group(const HeapView &h, uint32_t
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid[j]]);
-            const uint64_t b = uniform64(h.alloc_bm[bid[j]]);
+            const uint64_t b = uniform64(walk_bitmaps(h, cls, false)[bid[j]]);
             own[j] = base + j < r && t == cls;
             bm[j] = own[j] ? b : 0;
         }
@@ -204,13 +207,13 @@ __device__ __forceinline__ void for_each_object_packed(const HeapView &h, uint32
         if (!pair) {
             bid = __builtin_amdgcn_readfirstlane(L.at(item));
             const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
-            const uint64_t bm = uniform64(snapshot ? h.iter_bm[bid] : h.alloc_bm[bid]);
+            const uint64_t bm = uniform64(walk_bitmaps(h, cls, snapshot)[bid]);
             live = t == cls && ((bm >> lane) & 1);
         } else {
             const uint32_t j = 2 * (item - nd) + (lane >> 5);
             const bool valid = j < ns;
             bid = L.R[L.M - 1 - (valid ? j : j - 1)];
-            const uint64_t bm = snapshot ? h.iter_bm[bid] : h.alloc_bm[bid];
+            const uint64_t bm = walk_bitmaps(h, cls, snapshot)[bid];
             const uint32_t rank = lane & 31;
             live = valid && h.type[bid] == cls && rank < (uint32_t)__popcll(bm);
             slot = live ? nth_set_bit(bm, rank) : 0;

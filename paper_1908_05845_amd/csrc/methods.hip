@@ -136,14 +136,16 @@ __global__ __launch_bounds__(1024) void k_gol_birth(HeapView h, GolK p)
     const uint32_t s = lane_id();
     for_each_block_heads<1>(h, p.cell_cls, p.wpg, [&](const BlockHeads<1> &hd) {
         const uint32_t bid = hd.bid[0];
-        // the block's fields, issued before the header is used (a block of
-        // another class has no live slot: nothing is born, nothing stored)
+        // the block's fields and a view of the Alive class's active blocks,
+        // issued before the header is used (a block of another class has no
+        // live slot: nothing is born, nothing stored)
         const uint8_t st = farr<uint8_t>(h, bid, p.c_state)[s];
         const int32_t n = farr<int32_t>(h, bid, p.c_count)[s];
         const int32_t id = farr<int32_t>(h, bid, p.c_id)[s];
+        const ActiveView view = active_view(h, p.alive_cls);
         const bool born = ((hd.bm(0) >> s) & 1) && st == 0 && n == 3;
         if (born) farr<uint8_t>(h, bid, p.c_state)[s] = 1;
-        const uint32_t a = wave_allocate(h, p.alive_cls, born);
+        const uint32_t a = wave_allocate(h, p.alive_cls, born, &view);
         if (born && a != kNull) fref<int32_t>(h, a, p.a_id) = id;
     });
 }

@@ -96,6 +96,14 @@ __device__ __forceinline__ bool heap_failed(const HeapView &h)
 // ------------------------------------------------------------ bit helpers --
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// a value every lane holds alike, moved to scalar registers
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t rotr64(uint64_t x, uint32_t r)
 {
     r &= 63;
@@ -412,11 +420,13 @@ __device__ __forceinline__ void release_slots(const HeapView &h, uint32_t cls, u
 // block (slow path); reserve up to n slots; deactivate the block if this
 // filled it; roll back if the block's type changed meanwhile.
 __device__ __forceinline__ uint32_t leader_allocate(const HeapView &h, uint32_t cls, uint32_t n,
-                                                    uint64_t &got, uint32_t seed)
+                                                    uint64_t &got, uint32_t seed, int64_t first = -1)
 {
     got = 0;
     for (uint32_t attempt = 0; attempt < h.spin_limit; ++attempt) {
-        int64_t bid = -1;
+        // the first attempt may start from a block found in a prefetched
+        // view of the active bitmap (wave_allocate with an ActiveView)
+        int64_t bid = attempt == 0 ? first : -1;
         for (uint32_t t = 0; t < h.retries && bid < 0; ++t)
             bid = find_set(h, bm_active(cls), hash32(seed + attempt * 977u + t * 131u));
         if (bid < 0) {
@@ -453,13 +463,63 @@ __device__ __forceinline__ uint32_t leader_allocate(const HeapView &h, uint32_t 
     return kNoBlock;
 }
 
+// A prefetched view of the upper part of class cls's active-block bitmap:
+// lane i holds container i of level L = max(nlev - 2, 0), which has at most
+// 64 containers (the level above it is one container).  Taken with plain
+// loads before a method's allocation, in the same batch as the method's own
+// loads, it lets the allocating wavefront skip the two top levels of the
+// active-block search.  It is a hint: the reservation checks the block it
+// picks, and a block that filled since the view was taken costs one retry
+// through the ordinary search.
+struct ActiveView {
+    uint64_t w;
+};
+
+__device__ __forceinline__ ActiveView active_view(const HeapView &h, uint32_t cls)
+{
+    const uint32_t lvl = h.nlev >= 2 ? h.nlev - 2 : 0;
+    const uint32_t lane = lane_id();
+    ActiveView v;
+    v.w = lane < h.lvl_n[lvl] ? *h.bm_word(bm_active(cls), lvl, lane) : 0ull;
+    return v;
+}
+
+// The rest of Alg. try_find_set from a view: the container at level L and the
+// bit in it picked as find_set picks them (the same rotations for the same
+// seed), then the levels below L by loads.  Converged call; the result is
+// wave-uniform (-1 if the view shows no active block).
+__device__ __forceinline__ int64_t find_set_from_view(const HeapView &h, uint32_t bmid, const ActiveView &v,
+                                                      uint32_t seed)
+{
+    const int lvl = h.nlev >= 2 ? (int)h.nlev - 2 : 0;
+    const uint64_t nz = __ballot(v.w != 0);
+    if (!nz) return -1;
+    uint32_t idx = 0;
+    if (h.nlev >= 2) {           // the single container above L, as the ballot
+        const uint32_t r = h.rotation ? (hash32(seed + 0x9E3779B9u * (uint32_t)(lvl + 2)) & 63u) : 0u;
+        idx = ((uint32_t)(__ffsll((unsigned long long)rotr64(nz, r)) - 1) + r) & 63u;
+    }
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v.w, (int)idx);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v.w >> 32), (int)idx);
+    uint64_t c = ((uint64_t)hi << 32) | lo;
+    for (int l = lvl;; --l) {
+        const uint32_t r = h.rotation ? (hash32(seed + 0x9E3779B9u * (uint32_t)(l + 1)) & 63u) : 0u;
+        idx = idx * 64u + (((uint32_t)(__ffsll((unsigned long long)rotr64(c, r)) - 1) + r) & 63u);
+        if (l == 0) break;
+        c = uniform64(ald(h.bm_word(bmid, (uint32_t)l - 1, idx)));
+        if (!c) return -1;
+    }
+    return (int64_t)idx;
+}
+
 // Allocation of one object of class `cls` for every lane with want = true.
 // Must be called by all lanes of the wavefront together (converged).  With
 // coalescing the lowest requesting lane allocates for all requesting lanes;
 // each lane takes the slot whose rank among the reserved slots equals its
 // rank among the requesting lanes.  Returns the handle, or SMMO_NULL when
 // want is false or the heap is exhausted.
-__device__ __forceinline__ uint32_t wave_allocate(const HeapView &h, uint32_t cls, bool want)
+__device__ __forceinline__ uint32_t wave_allocate(const HeapView &h, uint32_t cls, bool want,
+                                                  const ActiveView *view = nullptr)
 {
     uint32_t result = kNull;
     uint64_t pending = __ballot(want);
@@ -470,7 +530,15 @@ __device__ __forceinline__ uint32_t wave_allocate(const HeapView &h, uint32_t cl
         const uint32_t n = h.coalescing ? (uint32_t)__popcll(pending) : 1u;
         uint32_t bid = kNoBlock;
         uint64_t got = 0;
-        if (lane == leader) bid = leader_allocate(h, cls, n, got, seed + round * 0x85ebca6bu);
+        const uint32_t rseed = seed + round * 0x85ebca6bu;
+        // the first round's first lookup from the view (seeded as the
+        // ordinary search's first lookup would be)
+        int64_t first = -1;
+        if (view && round == 0) {
+            if (lane == leader) count_event(h, EV_FIND);
+            first = find_set_from_view(h, bm_active(cls), *view, hash32(rseed));
+        }
+        if (lane == leader) bid = leader_allocate(h, cls, n, got, rseed, first);
         bid = __shfl(bid, (int)leader);
         const uint32_t glo = __shfl((uint32_t)got, (int)leader);
         const uint32_t ghi = __shfl((uint32_t)(got >> 32), (int)leader);

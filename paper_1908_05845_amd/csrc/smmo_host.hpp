@@ -69,6 +69,9 @@ struct smmo_heap {
     // classes that methods create objects of (their lists go stale launch
     // after launch; small heaps walk them directly instead of re-enumerating)
     bool churn[SMMO_MAX_CLASSES] = {};
+    // classes with a snapshot from smmo_snapshot that no do-all has used yet
+    // (the list R of such a class is the snapshot's)
+    uint32_t snap_pending = 0;
     uint64_t ub_blocks[SMMO_MAX_CLASSES] = {};   // upper bound of blocks per class
     uint32_t cu_count = 256;
     smmo_bind_slot bind_cache[16];

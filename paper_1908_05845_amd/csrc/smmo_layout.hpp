@@ -54,12 +54,12 @@ enum : uint32_t {
     CTRL_ERR = 0,
     CTRL_GCOUNT = 8,      // gather: running output count
     CTRL_GDONE = 9,       // gather: finished wavefronts
-    CTRL_RCOUNT = 16,     // [class] enumeration: running length of R
-    CTRL_RDONE = 32,      // [class] enumeration: finished wavefronts
+    CTRL_RPACK = 16,      // [class] u64 (words 16 + 2 class): an enumeration's running
+                          // dense count (bits 0-24), sparse count (25-49) and
+                          // finished work-groups (50-63); zero between enumerations
     CTRL_RFINAL = 48,     // [class] length of R after the last enumeration
     CTRL_DCOUNT = 64,     // defragmentation: number of candidate blocks
     CTRL_DMOVED = 66,     // u64: defragmentation: objects moved
-    CTRL_RSCOUNT = 96,    // [class] enumeration: running count of sparse blocks
     CTRL_RSFINAL = 112,   // [class] sparse blocks (the back of R) after the last enumeration
     CTRL_STATS = 128,     // u64 statistics / invariant results (host reads)
 };
@@ -110,6 +110,8 @@ struct HeapView {
     uint32_t spin_limit;
     uint32_t sparse_packing;      // 0 never, 1 when the list outgrows the grid, 2 always
     uint32_t direct;              // classes whose walks this launch visit every block (bit c = class c)
+    uint32_t snap;                // classes whose walks this launch read the iteration bitmaps of a
+                                  // snapshot taken earlier by smmo_snapshot (bit c = class c)
 
     __host__ __device__ uint64_t *bm_word(uint32_t bmid, uint32_t lvl, uint32_t c) const
     {

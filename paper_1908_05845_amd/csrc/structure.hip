@@ -110,7 +110,7 @@ __device__ __forceinline__ void for_each_family_block(const HeapView &h, uint32_
         }
         bid = __builtin_amdgcn_readfirstlane(bid);
         const uint32_t t = __builtin_amdgcn_readfirstlane(h.type[bid]);
-        const uint64_t bm = uniform64(h.alloc_bm[bid]);
+        const uint64_t bm = uniform64(walk_bitmaps(h, c, false)[bid]);
         if constexpr (std::is_invocable_v<F &, uint32_t, uint64_t, uint32_t, uint32_t>)
             f(bid, t == c ? bm : 0ull, c, i);
         else

@@ -64,12 +64,20 @@ def _np(t):
 
 
 class GolSim:
-    """Game of Life in SMMO form on a W x H torus (Cell + Alive classes)."""
+    """Game of Life in SMMO form on a W x H torus (Cell + Alive classes).
 
-    def __init__(self, W: int, H: int, init, cfg=None, extra_blocks: int = 16):
+    concurrent=True runs Alive::death on a second stream beside Cell::birth:
+    the two decide on disjoint cells (death on live cells whose count is not
+    2 or 3, birth on dead cells with count 3).  The Alive snapshot is taken on
+    that stream while Cell::count runs, so the death pass walks the Alive
+    objects of the generation's start and never meets the ones births
+    create."""
+
+    def __init__(self, W: int, H: int, init, cfg=None, extra_blocks: int = 16, concurrent: bool = False):
         import torch
 
         self.W, self.H = W, H
+        self.concurrent = concurrent
         n = W * H
         self.heap = smmo.Heap(GOL_CLASSES, blocks=3 * _blocks(n) + extra_blocks, cfg=cfg)
         dev = self.heap.dev
@@ -84,13 +92,35 @@ class GolSim:
         self.m_count = smmo.smmo_method_id("gol.cell_count")
         self.m_death = smmo.smmo_method_id("gol.alive_death")
         self.m_birth = smmo.smmo_method_id("gol.cell_birth")
+        if concurrent:
+            self._side = torch.cuda.Stream(device=dev)
+            self._ev = [torch.cuda.Event() for _ in range(3)]
 
     def step(self, n: int = 1, stream=None):
         h, c, a = self.heap.h, self.heap.cls["Cell"], self.heap.cls["Alive"]
+        if not self.concurrent:
+            for _ in range(n):
+                smmo.smmo_parallel_do(h, c, self.m_count, self.args, stream)
+                smmo.smmo_parallel_do(h, a, self.m_death, self.args, stream)
+                smmo.smmo_parallel_do(h, c, self.m_birth, self.args, stream)
+            return
+        import torch
+
+        main = torch.cuda.current_stream(self.heap.dev) if stream is None else stream
+        if isinstance(main, int):
+            main = torch.cuda.ExternalStream(main, device=self.heap.dev)
+        side, (fork, counted, died) = self._side, self._ev
         for _ in range(n):
-            smmo.smmo_parallel_do(h, c, self.m_count, self.args, stream)
-            smmo.smmo_parallel_do(h, a, self.m_death, self.args, stream)
-            smmo.smmo_parallel_do(h, c, self.m_birth, self.args, stream)
+            fork.record(main)
+            side.wait_event(fork)
+            smmo.smmo_snapshot(h, a, side)
+            smmo.smmo_parallel_do(h, c, self.m_count, self.args, main)
+            counted.record(main)
+            side.wait_event(counted)
+            smmo.smmo_parallel_do(h, a, self.m_death, self.args, side)
+            smmo.smmo_parallel_do(h, c, self.m_birth, self.args, main)
+            died.record(side)
+            main.wait_event(died)
 
     def read(self):
         """(state u8[W*H], count i32[W*H], sorted cell ids of Alive objects)."""

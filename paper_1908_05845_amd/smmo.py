@@ -155,7 +155,7 @@ EXPORTS = [
     "smmo_define_subclass", "smmo_class_is_a",
     "smmo_field_id", "smmo_block_bytes", "smmo_heap_bytes", "smmo_set_allocator", "smmo_alloc_heap",
     "smmo_heap_free",
-    "smmo_parallel_new", "smmo_parallel_do", "smmo_destroy", "smmo_gather_soa", "smmo_sync",
+    "smmo_parallel_new", "smmo_parallel_do", "smmo_snapshot", "smmo_destroy", "smmo_gather_soa", "smmo_sync",
     "smmo_heap_stats", "smmo_check_invariants", "smmo_clear_error", "smmo_heap_info",
     "smmo_method_id", "smmo_last_error", "smmo_set_launch", "smmo_defragment", "smmo_coalescing_probe",
     "smmo_source_hash", "smmo_structure_remove_disconnected", "smmo_structure_remove_disconnected_noalloc",
@@ -197,6 +197,7 @@ def load_library(path: str = LIB_PATH):
             "smmo_heap_free": (S, [P]),
             "smmo_parallel_new": (S, [P, U32, U32, P, U32, P, P]),
             "smmo_parallel_do": (S, [P, U32, U32, P, C.c_size_t, P]),
+            "smmo_snapshot": (S, [P, U32, P]),
             "smmo_destroy": (S, [P, U32, P, U32, P]),
             "smmo_gather_soa": (S, [P, U32, P, U32, P, P, U32, P, P]),
             "smmo_sync": (S, [P]),
@@ -411,6 +412,12 @@ def smmo_parallel_do(heap, class_id: int, method_id: int, args=None, stream=None
                                      0 if args is None else C.sizeof(args), _stream(stream)))
 
 
+def smmo_snapshot(heap, class_id: int, stream=None) -> None:
+    """Takes the iteration snapshot of a class for its next parallel_do."""
+    lib = load_library()
+    _check(lib, lib.smmo_snapshot(heap, class_id, _stream(stream)))
+
+
 class BoundLaunch:
     """One do-all with its heap, class, method and argument struct fixed, for
     drivers that issue many launches: a call is one foreign call of
@@ -608,6 +615,10 @@ class Heap:
 
     def do(self, cname: str, method: str, args=None, stream=None):
         smmo_parallel_do(self.h, self.cls[cname], smmo_method_id(method), args, stream)
+
+    def snapshot(self, cname: str, stream=None):
+        """Iteration snapshot of class cname for its next do-all."""
+        smmo_snapshot(self.h, self.cls[cname], stream)
 
     def defragment(self, cname: str, n: int = 1, k1: int = 0, max_passes: int = 32, external=(), stream=None):
         """CompactGpu passes on class cname; returns (passes, moved objects).

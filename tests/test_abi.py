@@ -147,6 +147,7 @@ def test_null_and_state_errors(lib):
     assert lib.smmo_define_class(None, b"x", None, 0, None) == smmo.SMMO_EINVAL
     assert lib.smmo_sync(None) == smmo.SMMO_EINVAL
     assert lib.smmo_parallel_do(None, 0, 0, None, 0, None) == smmo.SMMO_EINVAL
+    assert lib.smmo_snapshot(None, 0, None) == smmo.SMMO_EINVAL
     s = smmo.smmo_schema_create()
     out = C.c_uint64()
     assert lib.smmo_heap_bytes(s, 10, C.byref(out)) == smmo.SMMO_ESTATE   # no classes yet

@@ -190,6 +190,56 @@ def test_spawn_into_own_class_is_not_visited(dev):
     clean(heap)
 
 
+@pytest.mark.parametrize("packing", [0, 2])
+def test_snapshot_ahead_of_the_do_all(dev, packing):
+    """smmo_snapshot takes the iteration snapshot before the do-all: objects
+    created in between (by parallel_new, into the holes of the snapshot's
+    blocks as well as into new blocks) are not visited; the snapshot serves
+    one do-all; a gather or a host destroy in between drops it, and the
+    do-all then visits every object alive at its start."""
+    import torch
+
+    print("snapshot packing %d" % packing, flush=True)
+    heap = smmo.Heap(ALL, blocks=256, cfg=cfg(sparse_packing=packing, bulk_ordered=0))
+    n0, n1 = 1000, 700
+    ar = lambda a, b: torch.arange(a, b, dtype=torch.int32, device=dev)
+    hd = heap.new("A", n0, x=torch.ones(n0, device=dev), key=ar(0, n0))
+    gone = np.flatnonzero(np.arange(n0) % 5 == 0)
+    heap.destroy("A", hd[torch.from_numpy(gone).to(dev)])
+    old = np.setdiff1d(np.arange(n0), gone)
+    heap.snapshot("A")
+    heap.new("A", n1, x=torch.ones(n1, device=dev), key=ar(n0, n0 + n1))
+    heap.do("A", "test.axpy", smmo.smmo_axpy_args(2.0, 0.0))
+
+    def xs():
+        g = heap.gather("A", ["x", "key"])
+        k = g["key"].cpu().numpy()
+        o = np.argsort(k)
+        return k[o], g["x"].cpu().numpy()[o]
+
+    keys, x = xs()
+    assert np.array_equal(keys, np.concatenate([old, np.arange(n0, n0 + n1)]))
+    assert np.array_equal(x, np.where(keys < n0, 2.0, 1.0).astype(np.float32))
+    # used up: the next do-all visits every object
+    heap.do("A", "test.axpy", smmo.smmo_axpy_args(1.0, 1.0))
+    keys, x = xs()
+    assert np.array_equal(x, np.where(keys < n0, 3.0, 2.0).astype(np.float32))
+    # dropped by a gather, then by a host destroy
+    for drop in ("gather", "destroy"):
+        heap.snapshot("A")
+        if drop == "gather":
+            heap.gather("A", ["key"])
+        else:
+            e = heap.new("A", 1, x=torch.ones(1, device=dev), key=ar(10 ** 6, 10 ** 6 + 1))
+            heap.destroy("A", e)
+        before = xs()[1]
+        heap.new("A", 10, x=torch.zeros(10, device=dev), key=ar(2 * n0 + 10 * len(drop), 2 * n0 + 10 * len(drop) + 10))
+        heap.do("A", "test.axpy", smmo.smmo_axpy_args(1.0, 1.0))
+        keys, x = xs()
+        assert np.array_equal(x, np.concatenate([before + 1.0, np.ones(10, np.float32)])), drop
+    clean(heap)
+
+
 def test_churn_against_live_set_model(dev):
     import torch
 
