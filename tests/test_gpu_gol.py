@@ -45,6 +45,18 @@ def test_ragged_tori(dev, W, H):
     compare_run(W, H, (rng.random(W * H) < 0.3).astype(np.uint8), 30)
 
 
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_three_bitmap_levels(dev, concurrent):
+    """512 x 512 (12,304 blocks, three bitmap levels): births start their
+    active-block search from the prefetched middle level and load the level
+    below it; bit-exact with the oracle."""
+    print("gol 512x512 three levels, concurrent", concurrent, flush=True)
+    sim = compare_run(512, 512, gol_init(512, 512, seed=5), 12, every=4, concurrent=concurrent)
+    # more than 64 * 64 blocks: the level above the blocks' containers has
+    # more than one container, so the hierarchy has three levels
+    assert 64 * 64 < sim.heap.blocks <= 64 ** 3
+
+
 def test_glider_on_torus(dev):
     g = np.zeros((16, 16), np.uint8)
     for (x, y) in [(1, 0), (2, 1), (0, 2), (1, 2), (2, 2)]:
