@@ -107,7 +107,7 @@ __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 
 // Alive::death - if the cell's count is not 2 or 3: cell dies, delete this
 // (a packed do-all, packed as the heap's sparse_packing setting asks: the
-// Alive class is the sparse one)
+// Alive class is the sparse one; with packing off k_gol_death_heads runs)
 __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
 {
     for_each_object_packed(h, p.alive_cls, false, [&](uint32_t bid, uint32_t s, bool live, bool pair) {
@@ -126,6 +126,38 @@ __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
             }
         }
         wave_release_packed(h, p.alive_cls, bid, s, die, pair);
+    });
+}
+
+// Alive::death as above, unpacked (sparse_packing 0): walked with the
+// block-header walker, so each lane's cell id is loaded in the same batch as
+// the block's header instead of after it
+__global__ __launch_bounds__(1024) void k_gol_death_heads(HeapView h, GolK p)
+{
+    const uint32_t s = lane_id();
+    for_each_block_heads<1>(h, p.alive_cls, p.wpg, [&](const BlockHeads<1> &hd) {
+        const uint32_t bid = hd.bid[0];
+        // a block of another class has no live slot: its id is not used
+        const int32_t cid = farr<int32_t>(h, bid, p.a_id)[s];
+        bool live = (hd.bm(0) >> s) & 1;
+        uint32_t hc = 0;
+        if (live && (uint32_t)cid >= (uint32_t)(p.W * p.H)) {
+            raise_error(h, ERR_BADHANDLE);
+            live = false;
+        }
+        if (live) {
+            hc = p.cells[cid];
+            live = gol_valid(h, hc);
+        }
+        bool die = false;
+        if (live) {
+            const int32_t n = fref<int32_t>(h, hc, p.c_count);
+            if (n != 2 && n != 3) {
+                fref<uint8_t>(h, hc, p.c_state) = 0;
+                die = true;
+            }
+        }
+        wave_release_own_block(h, p.alive_cls, bid, __ballot(die));
     });
 }
 
@@ -191,7 +223,10 @@ smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
         else if (ls.group == 2) hipLaunchKernelGGL(k_gol_count<2>, ls.grid, ls.block, 0, st, h->v, k);
         else hipLaunchKernelGGL(k_gol_count<1>, ls.grid, ls.block, 0, st, h->v, k);
     }
-    if (Which == 1) hipLaunchKernelGGL(k_gol_death, ls.grid, ls.block, 0, st, h->v, k);
+    if (Which == 1) {
+        if (h->cfg.sparse_packing == 0) hipLaunchKernelGGL(k_gol_death_heads, ls.grid, ls.block, 0, st, h->v, k);
+        else hipLaunchKernelGGL(k_gol_death, ls.grid, ls.block, 0, st, h->v, k);
+    }
     if (Which == 2) hipLaunchKernelGGL(k_gol_birth, ls.grid, ls.block, 0, st, h->v, k);
     if ((s = launched("gol kernel"))) return s;
     if (Which == 2) note_allocation(h, a.alive_class, 64ull * h->v.M);
