@@ -240,6 +240,56 @@ def test_snapshot_ahead_of_the_do_all(dev, packing):
     clean(heap)
 
 
+def test_snapshot_of_a_class_family_and_its_drop_by_defragmentation(dev):
+    """A snapshot of an abstract base class covers its concrete classes and
+    is used by the next do-all on the base (one launch per concrete class);
+    a defragmentation of a class in between drops that class's snapshot, so
+    the do-all visits every object alive at its start."""
+    import torch
+
+    fam = {"Base": {"parent": None, "abstract": True, "fields": [("x", "f32", 1), ("key", "i32", 1)]},
+           "C1": {"parent": "Base"}, "C2": {"parent": "Base", "fields": [("y", "f32", 1)]}}
+    heap = smmo.Heap(fam, blocks=128, cfg=cfg(bulk_ordered=0))
+    ar = lambda a, b: torch.arange(a, b, dtype=torch.int32, device=dev)
+    heap.new("C1", 500, x=torch.ones(500, device=dev), key=ar(0, 500))
+    heap.new("C2", 300, x=torch.ones(300, device=dev), key=ar(500, 800))
+    heap.snapshot("Base")
+    heap.new("C1", 100, x=torch.ones(100, device=dev), key=ar(800, 900))
+    heap.new("C2", 50, x=torch.ones(50, device=dev), key=ar(900, 950))
+    heap.do("Base", "test.axpy", smmo.smmo_axpy_args(2.0, 0.0))
+
+    def xs(c):
+        g = heap.gather(c, ["x", "key"])
+        k = g["key"].cpu().numpy()
+        o = np.argsort(k)
+        return k[o], g["x"].cpu().numpy()[o]
+
+    for c in ("C1", "C2"):
+        keys, x = xs(c)
+        assert np.array_equal(x, np.where(keys < 800, 2.0, 1.0).astype(np.float32)), c
+    # C1 loses two thirds of its objects (sparse blocks to compact), then: a
+    # snapshot, a defragmentation of C1, new objects of both classes, a
+    # do-all on the base: C1's snapshot is gone (all C1 objects visited),
+    # C2's holds (its new objects are not)
+    g = heap.gather("C1", ["key"])
+    h1 = g["_handle"][: int(g["_count"])]
+    drop = h1[torch.from_numpy(g["key"].cpu().numpy() % 3 != 0).to(dev)]
+    heap.destroy("C1", drop)
+    b1, b2 = xs("C1")[1], xs("C2")[1]     # (a gather would drop a snapshot: read first)
+    heap.snapshot("Base")
+    passes, moved = heap.defragment("C1", n=1)
+    assert moved > 0
+    heap.new("C1", 10, x=torch.zeros(10, device=dev), key=ar(2000, 2010))
+    heap.new("C2", 10, x=torch.zeros(10, device=dev), key=ar(3000, 3010))
+    heap.do("Base", "test.axpy", smmo.smmo_axpy_args(1.0, 1.0))
+    x1 = xs("C1")[1]
+    x2 = xs("C2")[1]
+    assert np.array_equal(x1, np.concatenate([b1 + 1.0, np.ones(10, np.float32)]))
+    assert np.array_equal(x2, np.concatenate([b2 + 1.0, np.zeros(10, np.float32)]))
+    heap.sync()
+    clean(heap)
+
+
 def test_churn_against_live_set_model(dev):
     import torch
 
