@@ -32,6 +32,7 @@ METRIC = "object-method updates/sec + HBM GB/s % peak; batched & adjoint vs plai
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3
 COUNTERS_FILE = os.path.join(HERE, "profiles", "spring_counters.json")
+SEG_MIN_STEPS = 100      # shortest event-bounded segment inside the timed steps
 
 
 def parse():
@@ -348,7 +349,11 @@ def bench_spring(args, torch):
     half = steps // 2
     ms = 0.0
     wall = 0.0
-    seg_ms = []      # five event-bounded segments per half (whole graph replays)
+    # five event-bounded segments per half (whole graph replays), only where
+    # a segment spans at least SEG_MIN_STEPS steps: an event recorded between
+    # two steps is a packet the queue processes between the kernels, and in
+    # a 20-step window ten of them cost 5 percent of the timed time
+    seg_ms = []
     seg_steps = []
     for part, n in enumerate((half, steps - half)):
         # the segment events exist before the timed region: creating one
@@ -359,9 +364,10 @@ def bench_spring(args, torch):
         bounds = []
         t0 = time.perf_counter()
         e0.record()
+        segmented = n >= 5 * SEG_MIN_STEPS
         if graph is not None:
             reps = n // G
-            cut = {max(1, round(reps * (j + 1) / 5)) for j in range(5)} if reps else set()
+            cut = {max(1, round(reps * (j + 1) / 5)) for j in range(5)} if reps and segmented else set()
             for r in range(reps):
                 graph.replay()
                 if r + 1 in cut:
@@ -371,7 +377,7 @@ def bench_spring(args, torch):
             for _ in range(n % G):
                 step()
         else:
-            cut = {max(1, round(n * (j + 1) / 5)) for j in range(5)} if n else set()
+            cut = {max(1, round(n * (j + 1) / 5)) for j in range(5)} if n and segmented else set()
             for i in range(n):
                 step()
                 if i + 1 in cut:
