@@ -716,44 +716,58 @@ def _measure_adjoint(torch, plain_updates_per_s):
 
 def measure_gol_extra(torch):
     """Game of Life, 256 x 256 torus, 25 % start: 100 generations captured in
-    one HIP graph (three do-alls per generation plus the Alive block-list
-    pass), replayed once untimed and timed on a second replay from the same
-    state.  Births are device allocations, deaths device deletions."""
+    one HIP graph, replayed once untimed and timed on a second replay from the
+    same state.  Births are device allocations, deaths device deletions.  Two
+    forms of the same generation: the three do-alls (count, death, birth),
+    and gol.generation (the count with the Alive snapshot, then death and
+    birth in one launch), each on a heap of its own from the same start."""
     from inputs import gol_init
     from paper_1908_05845_amd.sims import GolSim
 
     W = H = 256
-    sim = GolSim(W, H, gol_init(W, H))
-    heap = sim.heap
-    sim.step(2)
-    heap.sync()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        cap = torch.cuda.current_stream()
-        sim.step(100, stream=cap)
-    sim.step(1)
-    heap.sync()
-    warm_replay(torch, g, heap)
-    st0 = heap.stats()
-    e0, e1 = events(torch, 2)
-    torch.cuda.synchronize()
-    e0.record()
-    g.replay()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    st1 = heap.stats()
-    ca = heap.cls["Alive"]
+
+    def run(fused):
+        sim = GolSim(W, H, gol_init(W, H), fused=fused)
+        heap = sim.heap
+        sim.step(2)
+        heap.sync()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            cap = torch.cuda.current_stream()
+            sim.step(100, stream=cap)
+        sim.step(1)
+        heap.sync()
+        warm_replay(torch, g, heap)
+        st0 = heap.stats()
+        e0, e1 = events(torch, 2)
+        torch.cuda.synchronize()
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st1 = heap.stats()
+        ca = heap.cls["Alive"]
+        heap.close()
+        return ms, st0, st1, ca
+
+    ms, st0, st1, ca = run(False)
     news = st1.device_news - st0.device_news
     dels = st1.device_deletes - st0.device_deletes
     alive = 0.5 * (st0.live_objects[ca] + st1.live_objects[ca])
+    fms, f0, f1, _ = run(True)
+    falive = 0.5 * (f0.live_objects[ca] + f1.live_objects[ca])
     res = {"workload": "Game of Life in SMMO form, 256x256 torus, 25% start, 100 generations",
            "launch": "one HIP graph of 100 generations", "us_per_generation": ms * 1e3 / 100,
            "updates_per_s": 100 * (2 * W * H + alive) / (ms * 1e-3),
            "births_per_s": news / (ms * 1e-3), "deaths_per_s": dels / (ms * 1e-3),
            "births": int(news), "deaths": int(dels), "alive_mean": alive,
-           "fragmentation_end": st1.fragmentation, "device_error": st1.device_error}
-    heap.close()
+           "fragmentation_end": st1.fragmentation, "device_error": st1.device_error,
+           "fused": {"method": "gol.generation: the count with the Alive snapshot, then death and birth in "
+                               "one launch", "us_per_generation": fms * 1e3 / 100,
+                     "updates_per_s": 100 * (2 * W * H + falive) / (fms * 1e-3),
+                     "births": int(f1.device_news - f0.device_news),
+                     "deaths": int(f1.device_deletes - f0.device_deletes), "device_error": f1.device_error}}
     return res
 
 

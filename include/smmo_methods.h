@@ -25,6 +25,15 @@ extern "C" {
  *                             dead and delete this Alive object
  * "gol.cell_birth"  on Cell : if dead and count == 3, set alive and create an
  *                             Alive object for the cell
+ * "gol.generation"  on Cell : one whole generation, with the result of the
+ *                             three do-alls above in that order.  On a heap
+ *                             of at most 8,192 blocks it takes two launches:
+ *                             the count, which also takes the Alive class's
+ *                             iteration snapshot of every block, then death
+ *                             and birth in one launch (they decide on
+ *                             disjoint cells; the snapshot keeps the new
+ *                             Alive objects out of the death walk).  On a
+ *                             larger heap it runs the three do-alls.
  * cells[i] is the handle of the Cell with cell_id i (the thesis keeps Cell
  * pointers in a global array); the grid is width x height, index y*width+x. */
 typedef struct {

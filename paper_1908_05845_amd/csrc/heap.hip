@@ -652,12 +652,6 @@ smmo_status bind_field(const smmo_schema *s, uint32_t cls, const char *name, int
                                  "' required by this method");
 }
 
-// Heaps of at most this many blocks walk the class of a stale list directly
-// (every block, filtered by type) instead of enumerating it first, where
-// methods create objects of the class (its list would be rebuilt launch
-// after launch).
-constexpr uint32_t kDirectMaxBlocks = 8192;
-
 smmo_status ensure_enumerated(smmo_heap *h, uint32_t cls, bool snapshot, hipStream_t st, bool split,
                               bool allow_direct)
 {

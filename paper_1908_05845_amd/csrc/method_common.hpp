@@ -90,14 +90,18 @@ struct BlockHeads {
 // once the heap has failed; a kernel using this walker needs no check of its
 // own), the wavefronts per work-group are passed in (wpg) instead of read
 // from the dispatch packet, and the block headers come to f unused.
+// for_each_block_heads_in walks with work-group g of G (a part of the grid
+// that starts at a multiple of eight work-groups, so that g mod 8 is still
+// the work-group's XCD), so that one launch can walk two classes.
 template <int U, class F>
-__device__ __forceinline__ void for_each_block_heads(const HeapView &h, uint32_t cls, uint32_t wpg, F &&f)
+__device__ __forceinline__ void for_each_block_heads_in(const HeapView &h, uint32_t cls, uint32_t wpg, uint32_t g,
+                                                        uint32_t G, F &&f)
 {
     const uint32_t err = ald32(h.ctrl + CTRL_ERR);
     const BlockList L = block_list(h, cls);
     if (__builtin_amdgcn_readfirstlane(err)) return;
     const uint32_t r = L.r;
-    const uint32_t G = gridDim.x, g = blockIdx.x, x = g & 7u;
+    const uint32_t x = g & 7u;
     const uint32_t ngroups = (r + U - 1) / U;
     uint32_t glo = 0, ghi = ngroups, lw = g * wpg + (threadIdx.x >> 6), lstep = G * wpg;
     if (G >= 8) {
@@ -122,6 +126,12 @@ __device__ __forceinline__ void for_each_block_heads(const HeapView &h, uint32_t
         }
         f(hd);
     }
+}
+
+template <int U, class F>
+__device__ __forceinline__ void for_each_block_heads(const HeapView &h, uint32_t cls, uint32_t wpg, F &&f)
+{
+    for_each_block_heads_in<U>(h, cls, wpg, blockIdx.x, gridDim.x, f);
 }
 
 // Calls f(bid, bm, own) for the blocks of class `cls` in R, U at a time: a

@@ -12,6 +12,7 @@ namespace smmo {
 smmo_status launch_gol_cell_count(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_gol_alive_death(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_gol_cell_birth(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
+smmo_status launch_gol_generation(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_nbody_force(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_nbody_update(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
 smmo_status launch_test_axpy(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st);
@@ -112,6 +113,7 @@ const MethodEntry kMethods[] = {
     {"structure.bfs_mark", sizeof(smmo_structure_args), launch_structure_bfs_mark, kFamilyLaunch},
     {"structure.bfs_delete", sizeof(smmo_structure_args), launch_structure_bfs_delete},
     {"structure.link", sizeof(smmo_structure_args), launch_structure_link},
+    {"gol.generation", sizeof(smmo_gol_args), launch_gol_generation},
 };
 } // namespace
 

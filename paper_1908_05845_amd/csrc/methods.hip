@@ -32,6 +32,8 @@ struct GolK {
     uint32_t c_state, c_count, c_id;   // Cell field offsets
     uint32_t a_id;                     // Alive field offset
     uint32_t wpg;                      // wavefronts per work-group of this launch
+    uint32_t snap;                     // Cell::count: also take the Alive snapshot of every block
+    uint32_t death_groups;             // fused generation: work-groups that run Alive::death
 };
 
 // a Cell handle from the caller's grid array names a block of the heap
@@ -52,6 +54,15 @@ template <int U>
 __global__ __launch_bounds__(1024) void k_gol_count(HeapView h, GolK p)
 {
     const uint32_t s = lane_id();
+    if (p.snap) {
+        // the Alive snapshot of the fused death and birth launch that
+        // follows: every block's iteration bitmap, zero for blocks of other
+        // classes (a block that becomes an Alive block in that launch then
+        // lists nothing).  Nothing allocates or releases during this pass.
+        const uint32_t n = gridDim.x * blockDim.x;
+        for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < h.M; b += n)
+            h.iter_bm[b] = h.type[b] == p.alive_cls ? h.alloc_bm[b] : 0ull;
+    }
     bool bad = false;                  // a cell id outside the grid or a handle outside the heap
     for_each_block_heads<U>(h, p.cell_cls, p.wpg, [&](const BlockHeads<U> &hd) {
         const uint32_t *bid = hd.bid;
@@ -129,57 +140,80 @@ __global__ __launch_bounds__(1024) void k_gol_death(HeapView h, GolK p)
     });
 }
 
-// Alive::death as above, unpacked (sparse_packing 0): walked with the
-// block-header walker, so each lane's cell id is loaded in the same batch as
-// the block's header instead of after it
-__global__ __launch_bounds__(1024) void k_gol_death_heads(HeapView h, GolK p)
+// Alive::death as above, unpacked (sparse_packing 0), one wavefront's pass
+// over one block: walked with the block-header walker, so each lane's cell
+// id is loaded in the same batch as the block's header instead of after it
+__device__ __forceinline__ void gol_death_block(const HeapView &h, const GolK &p, const BlockHeads<1> &hd)
 {
     const uint32_t s = lane_id();
-    for_each_block_heads<1>(h, p.alive_cls, p.wpg, [&](const BlockHeads<1> &hd) {
-        const uint32_t bid = hd.bid[0];
-        // a block of another class has no live slot: its id is not used
-        const int32_t cid = farr<int32_t>(h, bid, p.a_id)[s];
-        bool live = (hd.bm(0) >> s) & 1;
-        uint32_t hc = 0;
-        if (live && (uint32_t)cid >= (uint32_t)(p.W * p.H)) {
-            raise_error(h, ERR_BADHANDLE);
-            live = false;
+    const uint32_t bid = hd.bid[0];
+    // a block of another class has no live slot: its id is not used
+    const int32_t cid = farr<int32_t>(h, bid, p.a_id)[s];
+    bool live = (hd.bm(0) >> s) & 1;
+    uint32_t hc = 0;
+    if (live && (uint32_t)cid >= (uint32_t)(p.W * p.H)) {
+        raise_error(h, ERR_BADHANDLE);
+        live = false;
+    }
+    if (live) {
+        hc = p.cells[cid];
+        live = gol_valid(h, hc);
+    }
+    bool die = false;
+    if (live) {
+        const int32_t n = fref<int32_t>(h, hc, p.c_count);
+        if (n != 2 && n != 3) {
+            fref<uint8_t>(h, hc, p.c_state) = 0;
+            die = true;
         }
-        if (live) {
-            hc = p.cells[cid];
-            live = gol_valid(h, hc);
-        }
-        bool die = false;
-        if (live) {
-            const int32_t n = fref<int32_t>(h, hc, p.c_count);
-            if (n != 2 && n != 3) {
-                fref<uint8_t>(h, hc, p.c_state) = 0;
-                die = true;
-            }
-        }
-        wave_release_own_block(h, p.alive_cls, bid, __ballot(die));
-    });
+    }
+    wave_release_own_block(h, p.alive_cls, bid, __ballot(die));
+}
+
+__global__ __launch_bounds__(1024) void k_gol_death_heads(HeapView h, GolK p)
+{
+    for_each_block_heads<1>(h, p.alive_cls, p.wpg, [&](const BlockHeads<1> &hd) { gol_death_block(h, p, hd); });
 }
 
 // Cell::birth - if dead with exactly three live neighbours: becomes alive and
-// gets a new Alive object
-__global__ __launch_bounds__(1024) void k_gol_birth(HeapView h, GolK p)
+// gets a new Alive object (one wavefront's pass over one block)
+__device__ __forceinline__ void gol_birth_block(const HeapView &h, const GolK &p, const BlockHeads<1> &hd)
 {
     const uint32_t s = lane_id();
-    for_each_block_heads<1>(h, p.cell_cls, p.wpg, [&](const BlockHeads<1> &hd) {
-        const uint32_t bid = hd.bid[0];
-        // the block's fields and a view of the Alive class's active blocks,
-        // issued before the header is used (a block of another class has no
-        // live slot: nothing is born, nothing stored)
-        const uint8_t st = farr<uint8_t>(h, bid, p.c_state)[s];
-        const int32_t n = farr<int32_t>(h, bid, p.c_count)[s];
-        const int32_t id = farr<int32_t>(h, bid, p.c_id)[s];
-        const ActiveView view = active_view(h, p.alive_cls);
-        const bool born = ((hd.bm(0) >> s) & 1) && st == 0 && n == 3;
-        if (born) farr<uint8_t>(h, bid, p.c_state)[s] = 1;
-        const uint32_t a = wave_allocate(h, p.alive_cls, born, &view);
-        if (born && a != kNull) fref<int32_t>(h, a, p.a_id) = id;
-    });
+    const uint32_t bid = hd.bid[0];
+    // the block's fields and a view of the Alive class's active blocks,
+    // issued before the header is used (a block of another class has no
+    // live slot: nothing is born, nothing stored)
+    const uint8_t st = farr<uint8_t>(h, bid, p.c_state)[s];
+    const int32_t n = farr<int32_t>(h, bid, p.c_count)[s];
+    const int32_t id = farr<int32_t>(h, bid, p.c_id)[s];
+    const ActiveView view = active_view(h, p.alive_cls);
+    const bool born = ((hd.bm(0) >> s) & 1) && st == 0 && n == 3;
+    if (born) farr<uint8_t>(h, bid, p.c_state)[s] = 1;
+    const uint32_t a = wave_allocate(h, p.alive_cls, born, &view);
+    if (born && a != kNull) fref<int32_t>(h, a, p.a_id) = id;
+}
+
+__global__ __launch_bounds__(1024) void k_gol_birth(HeapView h, GolK p)
+{
+    for_each_block_heads<1>(h, p.cell_cls, p.wpg, [&](const BlockHeads<1> &hd) { gol_birth_block(h, p, hd); });
+}
+
+// A whole generation's Alive::death and Cell::birth in one launch: the first
+// p.death_groups work-groups walk every block of the heap for Alive objects
+// (a direct walk of the iteration bitmaps that Cell::count's snapshot wrote),
+// the others walk the Cell blocks.  The two decide on disjoint cells (death
+// on live cells whose count is not 2 or 3, birth on dead cells with count 3),
+// and the snapshot keeps the objects that births create out of the death
+// walk, so the result is that of the two do-alls in order.
+__global__ __launch_bounds__(1024) void k_gol_death_birth(HeapView h, GolK p)
+{
+    if (blockIdx.x < p.death_groups)
+        for_each_block_heads_in<1>(h, p.alive_cls, p.wpg, blockIdx.x, p.death_groups,
+                                   [&](const BlockHeads<1> &hd) { gol_death_block(h, p, hd); });
+    else
+        for_each_block_heads_in<1>(h, p.cell_cls, p.wpg, blockIdx.x - p.death_groups, gridDim.x - p.death_groups,
+                                   [&](const BlockHeads<1> &hd) { gol_birth_block(h, p, hd); });
 }
 
 smmo_status bind_gol(smmo_heap *h, const smmo_gol_args &a, GolK &k)
@@ -209,10 +243,12 @@ smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
 {
     smmo_gol_args a;
     memcpy(&a, args, sizeof a);
-    GolK k;
+    GolK k{};
     smmo_status s = cached_bind(h, (const void *)&launch_gol<Which>, cls, a, k,
                                 [&] { return bind_gol(h, a, k); });
     if (s) return s;
+    k.snap = 0;
+    k.death_groups = 0;
     const uint32_t want = Which == 1 ? a.alive_class : a.cell_class;
     if (cls != want) return fail(SMMO_EINVAL, "gol: method runs on a different class");
     const LaunchShape ls = method_shape(h, cls, Which == 0 ? kGolCountGroup : 0);
@@ -230,6 +266,54 @@ smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     if (Which == 2) hipLaunchKernelGGL(k_gol_birth, ls.grid, ls.block, 0, st, h->v, k);
     if ((s = launched("gol kernel"))) return s;
     if (Which == 2) note_allocation(h, a.alive_class, 64ull * h->v.M);
+    return SMMO_OK;
+}
+
+// gol.generation on Cell: Cell::count, Alive::death, Cell::birth.  On a heap
+// of at most kDirectMaxBlocks blocks two launches: the count, which also
+// takes the Alive snapshot of every block, then death and birth together
+// (k_gol_death_birth); on a larger heap the three do-alls one after another.
+smmo_status run_gol_generation(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
+{
+    smmo_gol_args a;
+    memcpy(&a, args, sizeof a);
+    if (h->v.M > kDirectMaxBlocks) {
+        smmo_status s = launch_gol<0>(h, cls, args, st);
+        if (!s) s = launch_gol<1>(h, a.alive_class, args, st);
+        if (!s) s = launch_gol<2>(h, cls, args, st);
+        return s;
+    }
+    GolK k{};
+    smmo_status s = cached_bind(h, (const void *)&run_gol_generation, cls, a, k,
+                                [&] { return bind_gol(h, a, k); });
+    if (s) return s;
+    if (cls != a.cell_class) return fail(SMMO_EINVAL, "gol: method runs on a different class");
+    h->snap_pending &= ~(1u << a.alive_class);   // the count pass rewrites the Alive iteration bitmaps
+    const LaunchShape lc = method_shape(h, cls, kGolCountGroup);
+    if ((s = ensure_enumerated(h, cls, false, st))) return s;
+    k.wpg = lc.block.x / 64;
+    k.snap = 1;
+    k.death_groups = 0;
+    if (lc.group == 4) hipLaunchKernelGGL(k_gol_count<4>, lc.grid, lc.block, 0, st, h->v, k);
+    else if (lc.group == 2) hipLaunchKernelGGL(k_gol_count<2>, lc.grid, lc.block, 0, st, h->v, k);
+    else hipLaunchKernelGGL(k_gol_count<1>, lc.grid, lc.block, 0, st, h->v, k);
+    if ((s = launched("gol kernel"))) return s;
+    // death walks every block (a direct list) through the snapshot's
+    // bitmaps; its work-groups come first, a multiple of eight of them so
+    // that the birth work-groups keep their XCD numbering
+    const LaunchShape lb = method_shape(h, cls, 0);
+    const uint32_t wpg = lb.block.x / 64;
+    const uint64_t dwaves = std::min<uint64_t>(h->v.M, h->cfg.grid_waves ? h->cfg.grid_waves : 64ull * h->cu_count);
+    const uint32_t dgroups = (uint32_t)(((dwaves + wpg - 1) / wpg + 7) / 8 * 8);
+    HeapView v = h->v;
+    v.direct |= 1u << a.alive_class;
+    v.snap |= 1u << a.alive_class;
+    k.wpg = wpg;
+    k.snap = 0;
+    k.death_groups = dgroups;
+    hipLaunchKernelGGL(k_gol_death_birth, dim3(dgroups + lb.grid.x), lb.block, 0, st, v, k);
+    if ((s = launched("gol kernel"))) return s;
+    note_allocation(h, a.alive_class, 64ull * h->v.M);
     return SMMO_OK;
 }
 
@@ -612,6 +696,7 @@ namespace smmo {
 smmo_status launch_gol_cell_count(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_gol<0>(h, c, a, s); }
 smmo_status launch_gol_alive_death(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_gol<1>(h, c, a, s); }
 smmo_status launch_gol_cell_birth(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_gol<2>(h, c, a, s); }
+smmo_status launch_gol_generation(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return run_gol_generation(h, c, a, s); }
 smmo_status launch_nbody_force(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return nbody_force_launch(h, c, a, s); }
 smmo_status launch_nbody_update(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return nbody_update_launch(h, c, a, s); }
 smmo_status launch_test_axpy(smmo_heap *h, uint32_t c, const void *a, hipStream_t s) { return launch_axpy(h, c, a, s); }

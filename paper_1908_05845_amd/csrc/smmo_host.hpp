@@ -41,6 +41,12 @@ uint32_t class_family(const smmo_schema *s, uint32_t cls);
 inline bool class_abstract(const smmo_schema *s, uint32_t cls) { return (s->c[cls].flags & SMMO_CLASS_ABSTRACT) != 0; }
 } // namespace smmo
 
+// Heaps of at most this many blocks walk the class of a stale list directly
+// (every block, filtered by type) instead of enumerating it first, where
+// methods create objects of the class (its list would be rebuilt launch
+// after launch).
+constexpr uint32_t kDirectMaxBlocks = 8192;
+
 enum RState : int { R_DIRTY = 0, R_VALID = 1, R_SPLIT = 2 };   // R_SPLIT: valid, with the packing plan
 
 // A method launch resolves its fields by name; the schema is frozen once a

@@ -66,6 +66,8 @@ def _np(t):
 class GolSim:
     """Game of Life in SMMO form on a W x H torus (Cell + Alive classes).
 
+    fused=True runs each generation as one gol.generation do-all (death and
+    birth in one launch on heaps of at most 8,192 blocks).
     concurrent=True runs Alive::death on a second stream beside Cell::birth:
     the two decide on disjoint cells (death on live cells whose count is not
     2 or 3, birth on dead cells with count 3).  The Alive snapshot is taken on
@@ -73,11 +75,13 @@ class GolSim:
     objects of the generation's start and never meets the ones births
     create."""
 
-    def __init__(self, W: int, H: int, init, cfg=None, extra_blocks: int = 16, concurrent: bool = False):
+    def __init__(self, W: int, H: int, init, cfg=None, extra_blocks: int = 16, concurrent: bool = False,
+                 fused: bool = False):
         import torch
 
         self.W, self.H = W, H
         self.concurrent = concurrent
+        self.fused = fused
         n = W * H
         self.heap = smmo.Heap(GOL_CLASSES, blocks=3 * _blocks(n) + extra_blocks, cfg=cfg)
         dev = self.heap.dev
@@ -92,12 +96,17 @@ class GolSim:
         self.m_count = smmo.smmo_method_id("gol.cell_count")
         self.m_death = smmo.smmo_method_id("gol.alive_death")
         self.m_birth = smmo.smmo_method_id("gol.cell_birth")
+        self.m_gen = smmo.smmo_method_id("gol.generation")
         if concurrent:
             self._side = torch.cuda.Stream(device=dev)
             self._ev = [torch.cuda.Event() for _ in range(3)]
 
     def step(self, n: int = 1, stream=None):
         h, c, a = self.heap.h, self.heap.cls["Cell"], self.heap.cls["Alive"]
+        if self.fused:
+            for _ in range(n):
+                smmo.smmo_parallel_do(h, c, self.m_gen, self.args, stream)
+            return
         if not self.concurrent:
             for _ in range(n):
                 smmo.smmo_parallel_do(h, c, self.m_count, self.args, stream)

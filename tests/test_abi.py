@@ -135,7 +135,7 @@ def test_method_ids(lib):
              "spring_pi.link", "generation.cell_count",
              "generation.cell_birth", "generation.alive_update", "structure.pull", "structure.force",
              "structure.node_update", "structure.bfs_init", "structure.bfs_visit", "structure.bfs_mark",
-             "structure.bfs_delete", "structure.link"]
+             "structure.bfs_delete", "structure.link", "gol.generation"]
     ids = [smmo.smmo_method_id(n) for n in names]
     assert len(set(ids)) == len(ids)
     with pytest.raises(smmo.SmmoError) as e:

@@ -13,8 +13,8 @@ from paper_1908_05845_amd.sims import GolSim
 pytestmark = pytest.mark.gpu
 
 
-def compare_run(W, H, init, steps, cfg=None, every=1, concurrent=False):
-    sim = GolSim(W, H, init, cfg=cfg, concurrent=concurrent)
+def compare_run(W, H, init, steps, cfg=None, every=1, concurrent=False, fused=False):
+    sim = GolSim(W, H, init, cfg=cfg, concurrent=concurrent, fused=fused)
     ref = GolWorld(W, H, init)
     for s in range(1, steps + 1):
         sim.step(1)
@@ -136,6 +136,52 @@ def test_two_stream_graph_replays_match_the_oracle(dev):
     W = H = 96
     init = gol_init(W, H, seed=32)
     sim = GolSim(W, H, init, concurrent=True)
+    ref = GolWorld(W, H, init)
+    sim.step(2)
+    ref.step(2)
+    sim.heap.sync()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sim.step(10, stream=torch.cuda.current_stream())
+    assert np.array_equal(sim.read()[0], ref.read()[0])
+    for r in range(4):
+        g.replay()
+        torch.cuda.synchronize()
+        ref.step(10)
+        gs, gc, ga = sim.read()
+        rs, rc, ra = ref.read()
+        assert np.array_equal(gs, rs) and np.array_equal(gc, rc) and np.array_equal(ga, ra), r
+    inv = sim.heap.invariants()
+    assert inv.hierarchy_violations == 0 and inv.state_violations == 0 and inv.empty_allocated == 0
+
+
+@pytest.mark.parametrize("W,H,steps,variant", [(256, 256, 100, {}), (37, 23, 30, {}), (1, 1, 5, {}),
+                                               (100, 65, 30, {}), (128, 96, 40, dict(rotation=0)),
+                                               (128, 96, 40, dict(coalescing=0)),
+                                               (128, 96, 40, dict(lookup_retries=1)),
+                                               (128, 96, 40, dict(sparse_packing=2)),
+                                               (128, 96, 40, dict(grid_waves=8)), (512, 512, 12, {})])
+def test_fused_generation(dev, W, H, steps, variant):
+    """gol.generation: the count with the Alive snapshot, then death and
+    birth in one launch (the direct walk's heaps), or the three do-alls
+    (512 x 512: 12,304 blocks): bit-exact with the oracle, block states
+    consistent."""
+    print("gol fused %dx%d" % (W, H), variant, flush=True)
+    c = smmo.smmo_config_default()
+    for k, v in variant.items():
+        setattr(c, k, v)
+    init = gol_init(W, H, seed=W * 7 + H) if W * H >= 64 else np.ones(W * H, np.uint8)
+    compare_run(W, H, init, steps, cfg=c, every=1 if steps <= 40 else 5, fused=True)
+
+
+def test_fused_generation_graph_replays(dev):
+    """Ten fused generations in one HIP graph, replayed four times with
+    eager reads between the replays."""
+    import torch
+
+    W = H = 96
+    init = gol_init(W, H, seed=33)
+    sim = GolSim(W, H, init, fused=True)
     ref = GolWorld(W, H, init)
     sim.step(2)
     ref.step(2)
