@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["spring", "gol", "nbody"], default="spring")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gol-form", choices=["three", "fused"], default="three",
+                    help="--workload gol: the three do-alls per generation, or gol.generation")
     ap.add_argument("--kernel-steps", type=int, default=50,
                     help="steps timed per kernel with HIP events for the roofline")
     ap.add_argument("--cpu-steps", type=int, default=None)
@@ -1383,7 +1385,7 @@ def bench_gol(args, torch):
     steps = 100 if args.steps is None else args.steps
     warmup = 5 if args.warmup is None else args.warmup
     init = gol_init(W, H)
-    sim = GolSim(W, H, init)
+    sim = GolSim(W, H, init, fused=args.gol_form == "fused")
     for _ in range(warmup):
         sim.step(1)
     sim.heap.sync()
@@ -1400,7 +1402,8 @@ def bench_gol(args, torch):
     alive_after = sim.heap.stats().live_objects[cls_a]
     updates = steps * (2 * W * H + 0.5 * (alive_before + alive_after))
     res = {"value": updates / (ms * 1e-3), "unit": "updates/s", "ms_per_step": ms / steps, "dtype": "u8/i32",
-           "config": {"workload": "Game of Life in SMMO form, 256x256 torus, 25% initial density"},
+           "config": {"workload": "Game of Life in SMMO form, 256x256 torus, 25% initial density",
+                      "form": "gol.generation" if args.gol_form == "fused" else "three do-alls"},
            "roofline": None}
 
     def cpu_leg():
