@@ -277,6 +277,9 @@ smmo_status run_gol_generation(smmo_heap *h, uint32_t cls, const void *args, hip
 {
     smmo_gol_args a;
     memcpy(&a, args, sizeof a);
+    // the generation deletes Alive objects and (on the fused path) rewrites
+    // their iteration bitmaps: a snapshot of the class taken before is gone
+    if (a.alive_class < h->schema->nclasses) h->snap_pending &= ~(1u << a.alive_class);
     if (h->v.M > kDirectMaxBlocks) {
         smmo_status s = launch_gol<0>(h, cls, args, st);
         if (!s) s = launch_gol<1>(h, a.alive_class, args, st);
@@ -288,7 +291,6 @@ smmo_status run_gol_generation(smmo_heap *h, uint32_t cls, const void *args, hip
                                 [&] { return bind_gol(h, a, k); });
     if (s) return s;
     if (cls != a.cell_class) return fail(SMMO_EINVAL, "gol: method runs on a different class");
-    h->snap_pending &= ~(1u << a.alive_class);   // the count pass rewrites the Alive iteration bitmaps
     const LaunchShape lc = method_shape(h, cls, kGolCountGroup);
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     k.wpg = lc.block.x / 64;
