@@ -796,12 +796,18 @@ def measure_gol_large(torch):
     h, c, a = heap.h, heap.cls["Cell"], heap.cls["Alive"]
     sim.step(2)
     heap.sync()
-    st0 = heap.stats()
     n = 5
     tot = [0.0, 0.0, 0.0]
     alive_sum = 0.0
+    news = dels = 0
+    fused = []
+    # the two forms take turns, one generation each (the population changes
+    # from generation to generation): three do-alls with events around
+    # each, then gol.generation (an enumeration of Alive with its snapshot,
+    # the count, death and birth in one launch) with one pair of events
     for _ in range(n):
-        alive_sum += heap.stats().live_objects[a]
+        sb = heap.stats()
+        alive_sum += sb.live_objects[a]
         ev = events(torch, 4)
         ev[0].record()
         smmo.smmo_parallel_do(h, c, sim.m_count, sim.args)
@@ -813,6 +819,15 @@ def measure_gol_large(torch):
         torch.cuda.synchronize()
         for i in range(3):
             tot[i] += ev[i].elapsed_time(ev[i + 1]) * 1e3
+        sm = heap.stats()
+        news += sm.device_news - sb.device_news
+        dels += sm.device_deletes - sb.device_deletes
+        ev = events(torch, 2)
+        ev[0].record()
+        smmo.smmo_parallel_do(h, c, sim.m_gen, sim.args)
+        ev[1].record()
+        torch.cuda.synchronize()
+        fused.append(ev[0].elapsed_time(ev[1]) * 1e3)
     st1 = heap.stats()
     cells = W * H
     alive = alive_sum / n
@@ -827,9 +842,11 @@ def measure_gol_large(torch):
            "count_gbs": 13.0 * cells / (us[0] * 1e-6) / 1e9,
            "birth_gbs": 5.0 * cells / (us[2] * 1e-6) / 1e9,
            "death_gbs": 12.0 * alive / (us[1] * 1e-6) / 1e9,
-           "births_per_s": (st1.device_news - st0.device_news) / (gen_us * n * 1e-6),
-           "deaths_per_s": (st1.device_deletes - st0.device_deletes) / (gen_us * n * 1e-6),
-           "device_error": st1.device_error}
+           "births_per_s": news / (gen_us * n * 1e-6),
+           "deaths_per_s": dels / (gen_us * n * 1e-6),
+           "device_error": st1.device_error,
+           "fused": {"method": "gol.generation, on the generations between the timed three-do-all ones",
+                     "us_per_generation": sum(fused) / n}}
     heap.close()
     return res
 

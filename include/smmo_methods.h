@@ -26,14 +26,15 @@ extern "C" {
  * "gol.cell_birth"  on Cell : if dead and count == 3, set alive and create an
  *                             Alive object for the cell
  * "gol.generation"  on Cell : one whole generation, with the result of the
- *                             three do-alls above in that order.  On a heap
- *                             of at most 8,192 blocks it takes two launches:
- *                             the count, which also takes the Alive class's
- *                             iteration snapshot of every block, then death
- *                             and birth in one launch (they decide on
- *                             disjoint cells; the snapshot keeps the new
- *                             Alive objects out of the death walk).  On a
- *                             larger heap it runs the three do-alls.
+ *                             three do-alls above in that order: the count,
+ *                             then death and birth in one launch (they
+ *                             decide on disjoint cells), after the Alive
+ *                             class's iteration snapshot, which keeps the
+ *                             new Alive objects out of the death walk.  On a
+ *                             heap of at most 8,192 blocks the count takes
+ *                             the snapshot of every block; on a larger one
+ *                             an enumeration of the Alive class with its
+ *                             snapshot comes first (three launches).
  * cells[i] is the handle of the Cell with cell_id i (the thesis keeps Cell
  * pointers in a global array); the grid is width x height, index y*width+x. */
 typedef struct {

@@ -200,9 +200,10 @@ __global__ __launch_bounds__(1024) void k_gol_birth(HeapView h, GolK p)
 }
 
 // A whole generation's Alive::death and Cell::birth in one launch: the first
-// p.death_groups work-groups walk every block of the heap for Alive objects
-// (a direct walk of the iteration bitmaps that Cell::count's snapshot wrote),
-// the others walk the Cell blocks.  The two decide on disjoint cells (death
+// p.death_groups work-groups walk the Alive objects of the class's snapshot
+// (every block of a small heap, with the iteration bitmaps that
+// Cell::count's snapshot wrote, or the list and bitmaps of an enumeration
+// with snapshot), the others walk the Cell blocks.  The two decide on disjoint cells (death
 // on live cells whose count is not 2 or 3, birth on dead cells with count 3),
 // and the snapshot keeps the objects that births create out of the death
 // walk, so the result is that of the two do-alls in order.
@@ -269,46 +270,44 @@ smmo_status launch_gol(smmo_heap *h, uint32_t cls, const void *args, hipStream_t
     return SMMO_OK;
 }
 
-// gol.generation on Cell: Cell::count, Alive::death, Cell::birth.  On a heap
-// of at most kDirectMaxBlocks blocks two launches: the count, which also
-// takes the Alive snapshot of every block, then death and birth together
-// (k_gol_death_birth); on a larger heap the three do-alls one after another.
+// gol.generation on Cell: Cell::count, Alive::death, Cell::birth in two
+// launches after the Alive snapshot: the count, then death and birth
+// together (k_gol_death_birth).  On a heap of at most kDirectMaxBlocks
+// blocks the count itself takes the snapshot of every block and death walks
+// every block; on a larger one an enumeration of the Alive class with its
+// snapshot comes first and death walks that list.
 smmo_status run_gol_generation(smmo_heap *h, uint32_t cls, const void *args, hipStream_t st)
 {
     smmo_gol_args a;
     memcpy(&a, args, sizeof a);
-    // the generation deletes Alive objects and (on the fused path) rewrites
-    // their iteration bitmaps: a snapshot of the class taken before is gone
+    // the generation deletes Alive objects and rewrites their iteration
+    // bitmaps: a snapshot of the class taken before is gone
     if (a.alive_class < h->schema->nclasses) h->snap_pending &= ~(1u << a.alive_class);
-    if (h->v.M > kDirectMaxBlocks) {
-        smmo_status s = launch_gol<0>(h, cls, args, st);
-        if (!s) s = launch_gol<1>(h, a.alive_class, args, st);
-        if (!s) s = launch_gol<2>(h, cls, args, st);
-        return s;
-    }
     GolK k{};
     smmo_status s = cached_bind(h, (const void *)&run_gol_generation, cls, a, k,
                                 [&] { return bind_gol(h, a, k); });
     if (s) return s;
     if (cls != a.cell_class) return fail(SMMO_EINVAL, "gol: method runs on a different class");
+    const bool direct = h->v.M <= kDirectMaxBlocks;
+    if (!direct && (s = ensure_enumerated(h, a.alive_class, true, st, false, false))) return s;
     const LaunchShape lc = method_shape(h, cls, kGolCountGroup);
     if ((s = ensure_enumerated(h, cls, false, st))) return s;
     k.wpg = lc.block.x / 64;
-    k.snap = 1;
+    k.snap = direct ? 1u : 0u;
     k.death_groups = 0;
     if (lc.group == 4) hipLaunchKernelGGL(k_gol_count<4>, lc.grid, lc.block, 0, st, h->v, k);
     else if (lc.group == 2) hipLaunchKernelGGL(k_gol_count<2>, lc.grid, lc.block, 0, st, h->v, k);
     else hipLaunchKernelGGL(k_gol_count<1>, lc.grid, lc.block, 0, st, h->v, k);
     if ((s = launched("gol kernel"))) return s;
-    // death walks every block (a direct list) through the snapshot's
-    // bitmaps; its work-groups come first, a multiple of eight of them so
-    // that the birth work-groups keep their XCD numbering
+    // death's work-groups come first, a multiple of eight of them so that
+    // the birth work-groups keep their XCD numbering
     const LaunchShape lb = method_shape(h, cls, 0);
     const uint32_t wpg = lb.block.x / 64;
-    const uint64_t dwaves = std::min<uint64_t>(h->v.M, h->cfg.grid_waves ? h->cfg.grid_waves : 64ull * h->cu_count);
+    const uint64_t dblocks = direct ? h->v.M : std::max<uint64_t>(1, h->ub_blocks[a.alive_class]);
+    const uint64_t dwaves = std::min<uint64_t>(dblocks, h->cfg.grid_waves ? h->cfg.grid_waves : 64ull * h->cu_count);
     const uint32_t dgroups = (uint32_t)(((dwaves + wpg - 1) / wpg + 7) / 8 * 8);
     HeapView v = h->v;
-    v.direct |= 1u << a.alive_class;
+    if (direct) v.direct |= 1u << a.alive_class;
     v.snap |= 1u << a.alive_class;
     k.wpg = wpg;
     k.snap = 0;
