@@ -34,7 +34,9 @@ extern "C" {
  *                             heap of at most 8,192 blocks the count takes
  *                             the snapshot of every block; on a larger one
  *                             an enumeration of the Alive class with its
- *                             snapshot comes first (three launches).
+ *                             snapshot comes first (three launches).  A
+ *                             snapshot of the Alive class pending from
+ *                             smmo_snapshot is dropped.
  * cells[i] is the handle of the Cell with cell_id i (the thesis keeps Cell
  * pointers in a global array); the grid is width x height, index y*width+x. */
 typedef struct {
